@@ -1,0 +1,164 @@
+"""PP-GMRES(m): the oracle's version.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Algorithm 4 step 2 of Loe & Morgan: restarted GMRES on phi(A) y = b with
+right preconditioning and x = p(A) y, x_0 = 0. Readings (the paper does not
+spell these out):
+
+* Each cycle starts from the true residual r = b - A x. The cycle stops
+  early when the shortcut residual ||beta e_1 - Hbar z|| (section 3.2,
+  Example 3) reaches tol * ||b||, or after m steps.
+* The correction is x <- x + p(A)(V_k z); the paper's literal form (one
+  y accumulated over cycles, residual b - phi(A) y, a single x = p(A)y at
+  the end) is available as ``literal=True``; the two agree to rounding.
+* Outer stop: ||b - A x|| <= tol ||b||. NOCONV after max_cycles, or when
+  five consecutive cycles together reduce ||r|| by less than 1% (stall).
+* The small least-squares problem is solved by numpy's lstsq on Hbar.
+
+Counters follow section 3.1: mvps are sparse products (setup included),
+dots are inner products and norms, vops are all length-n vector operations
+(dots, norms, axpys and scalings).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .chains import apply_p, apply_phi, spmv_count_p, spmv_count_phi
+from .roots import BREAKDOWN_TOL, REAL
+
+OK, NOCONV = 0, 1
+
+
+@dataclass
+class Info:
+    status: int = OK
+    cycles: int = 0
+    iters: int = 0
+    mvps: int = 0
+    vops: int = 0
+    dots: int = 0
+    relres: float = float("nan")
+    relres_shortcut: float = float("nan")
+    history: list = field(default_factory=list)
+
+
+def _phi_vops(units) -> int:
+    # one axpy per real root, two per pair, one final subtraction
+    return sum(1 if k == REAL else 2 for (k, _, _) in units) + 1
+
+
+def _p_vops(units) -> int:
+    # 2r + 3c/2 - 1 axpys (section 3.1), r real and c complex roots
+    r = sum(1 for (k, _, _) in units if k == REAL)
+    c = 2 * sum(1 for (k, _, _) in units if k != REAL)
+    return 2 * r + (3 * c) // 2 - 1
+
+
+def pp_gmres(A, b: np.ndarray, units, m: int = 50, tol: float = 1e-8, max_cycles: int = 1000,
+             orth: str = "mgs", literal: bool = False, stall_cycles: int = 5,
+             setup_mvps: int = 0, x0=None):
+    """Solve A x = b by PP(d)-GMRES(m). Returns (x, Info)."""
+    b = np.asarray(b, dtype=np.float64)
+    n = b.shape[0]
+    bnorm = np.linalg.norm(b)
+    info = Info(mvps=setup_mvps)
+    phi = lambda v: apply_phi(A, units, v)  # noqa: E731
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    y = np.zeros(n)
+    if x0 is None:
+        r = b.copy()
+    else:
+        r = b - A @ x
+        info.mvps += 1
+    while True:
+        beta = np.linalg.norm(r)
+        info.dots += 1
+        info.vops += 1
+        info.relres = beta / bnorm
+        info.history.append(info.relres)
+        if info.relres <= tol:
+            info.status = OK
+            break
+        if info.cycles >= max_cycles:
+            info.status = NOCONV
+            break
+        h = info.history
+        if len(h) > stall_cycles and h[-1] > 0.99 * h[-1 - stall_cycles]:
+            info.status = NOCONV
+            break
+        info.cycles += 1
+        V = np.zeros((n, m + 1))
+        Hb = np.zeros((m + 1, m))
+        V[:, 0] = r / beta
+        info.vops += 1
+        k = 0
+        z = np.zeros(0)
+        for j in range(m):
+            w = phi(V[:, j])
+            info.mvps += spmv_count_phi(units)
+            info.vops += _phi_vops(units)
+            if orth == "mgs":
+                for i in range(j + 1):
+                    Hb[i, j] = V[:, i] @ w
+                    w = w - Hb[i, j] * V[:, i]
+                info.dots += j + 1
+                info.vops += 2 * (j + 1)
+            else:
+                h1 = V[:, : j + 1].T @ w
+                w = w - V[:, : j + 1] @ h1
+                h2 = V[:, : j + 1].T @ w
+                w = w - V[:, : j + 1] @ h2
+                Hb[: j + 1, j] = h1 + h2
+                info.dots += 2 * (j + 1)
+                info.vops += 4 * (j + 1)
+            Hb[j + 1, j] = np.linalg.norm(w)
+            info.dots += 1
+            info.vops += 2
+            info.iters += 1
+            k = j + 1
+            rhs = np.zeros(k + 1)
+            rhs[0] = beta
+            z, *_ = np.linalg.lstsq(Hb[: k + 1, :k], rhs, rcond=None)
+            short = np.linalg.norm(rhs - Hb[: k + 1, :k] @ z)
+            info.relres_shortcut = short / bnorm
+            lucky = Hb[j + 1, j] <= BREAKDOWN_TOL * np.linalg.norm(Hb[: k + 1, :k])
+            if lucky or short <= tol * bnorm:
+                break
+            V[:, j + 1] = w / Hb[j + 1, j]
+        dy = V[:, :k] @ z
+        info.vops += k
+        if literal:
+            y = y + dy
+            r = b - phi(y)
+            info.mvps += spmv_count_phi(units)
+            info.vops += _phi_vops(units) + 2
+            # x is formed once at the end; keep it current for the history
+        else:
+            x = x + apply_p(A, units, dy)
+            info.mvps += spmv_count_p(units)
+            info.vops += _p_vops(units) + 1
+            r = b - A @ x
+            info.mvps += 1
+            info.vops += 1
+    if literal:
+        x = apply_p(A, units, y)
+        info.mvps += spmv_count_p(units)
+        info.vops += _p_vops(units)
+        info.relres = np.linalg.norm(b - A @ x) / bnorm
+    return x, info
+
+
+def stability_check(A, units, b: np.ndarray) -> float:
+    """StCh = ||(b - A p(A) b) - pi(A) b|| (section 3.5).
+
+    r1 = b - A p(A)b uses Algorithm 3, r2 = b - phi(A)b = pi(A)b uses
+    Algorithm 1; their difference estimates the attainable residual.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    r1 = b - A @ apply_p(A, units, b)
+    r2 = b - apply_phi(A, units, b)
+    return float(np.linalg.norm(r1 - r2))

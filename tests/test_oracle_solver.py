@@ -1,0 +1,153 @@
+"""Pins of the oracle's PP-GMRES solver (Algorithm 4) and its variants."""
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as sla
+import torch
+
+from oracle import chains, roots, solver
+from oracle.mixed import apply_p_low, apply_phi_low, round_bf16
+from oracle.adjoint import grad_direct
+from workloads import convdiff2d, convdiff2d_parts, diagonal, rhs, start_vector
+from _golden import read_table
+
+
+def _cfg1():
+    A = convdiff2d(50, 1.0).to_scipy()
+    return A, rhs(A.shape[0], 1), start_vector(A.shape[0], 2)
+
+
+def test_cfg1_converges_to_tolerance_and_direct_solution():
+    A, b, v0 = _cfg1()
+    P = roots.setup(A, v0, 10)
+    x, info = solver.pp_gmres(A, b, P.units, m=50, tol=1e-8)
+    assert info.status == solver.OK
+    rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert rel <= 1e-8
+    xd = sla.spsolve(A.tocsc(), b)
+    # forward error bounded by cond(A) * residual; cond(A) < 2e3 here
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 2e3 * 1e-8
+
+
+def test_literal_form_agrees():
+    A, b, v0 = _cfg1()
+    P = roots.setup(A, v0, 10)
+    x1, i1 = solver.pp_gmres(A, b, P.units, m=20, tol=1e-10)
+    x2, i2 = solver.pp_gmres(A, b, P.units, m=20, tol=1e-10, literal=True)
+    assert i1.relres <= 1e-10 and i2.relres <= 1.5e-10
+    assert np.linalg.norm(x1 - x2) / np.linalg.norm(x1) < 1e-8
+
+
+@pytest.mark.parametrize("cycles", [1, 3])
+def test_degree1_is_textbook_gmres(cycles):
+    # PP(1)-GMRES(m): phi(A) = A/theta and p = 1/theta, so the iterates are
+    # those of GMRES(m) on A; compared against scipy's own GMRES.
+    A = convdiff2d(20, 3.0).to_scipy()
+    b = rhs(A.shape[0], 1)
+    P = roots.setup(A, start_vector(A.shape[0], 2), 1)
+    x, info = solver.pp_gmres(A, b, P.units, m=10, tol=1e-30, max_cycles=cycles)
+    xs, _ = sla.gmres(A, b, rtol=1e-30, atol=0.0, restart=10, maxiter=cycles)
+    assert info.cycles == cycles
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-12
+
+
+def test_example5_table3_6_loose():
+    # PP(50)-GMRES(50) matrix-vector products within 30% of Table 3.6
+    for (al, be, ga, _, pp_mvps) in read_table("table3_6_convdiff.txt")[:2]:
+        A = convdiff2d(200, al, be, ga).to_scipy()
+        n = A.shape[0]
+        P = roots.setup(A, start_vector(n, 2), 50)
+        x, info = solver.pp_gmres(A, rhs(n, 1), P.units, m=50, tol=1e-8, setup_mvps=P.d)
+        assert info.status == solver.OK
+        assert 0.7 * pp_mvps <= info.mvps <= 1.3 * pp_mvps
+
+
+def test_richardson_theorem_3_1():
+    # SPD A: adding a root theta_k >= lambda_max/2 does not increase ||pi(A) b||
+    A = convdiff2d(25).to_scipy()
+    n = A.shape[0]
+    b = rhs(n, 1)
+    P = roots.setup(A, start_vector(n, 2), 15, add_roots=False)
+    lam_max = 8.0  # 4 + 4 cos(pi h) < 8
+    pib = chains.apply_pi(A, P.units, b)
+    checked = 0
+    for (k, a, _) in P.units:
+        if k == 0 and a >= lam_max / 2:
+            ext = P.units + [(0, a, 0.0)]
+            assert np.linalg.norm(chains.apply_pi(A, ext, b)) <= np.linalg.norm(pib) * (1 + 1e-12)
+            checked += 1
+    assert checked >= 3
+
+
+def test_stability_check_small_for_stable_polynomial():
+    A, b, v0 = _cfg1()
+    P = roots.setup(A, v0, 10)
+    assert solver.stability_check(A, P.units, b) < 1e-12
+
+
+def test_noconv_after_max_cycles_returns_best_x():
+    A, b, v0 = _cfg1()
+    P = roots.setup(A, v0, 3)
+    x, info = solver.pp_gmres(A, b, P.units, m=5, tol=1e-12, max_cycles=2)
+    assert info.status == solver.NOCONV and info.cycles == 2
+    assert np.isclose(np.linalg.norm(b - A @ x) / np.linalg.norm(b), info.relres, rtol=1e-12)
+
+
+def test_breakdown_polynomial_solves_in_one_step():
+    # 3 distinct eigenvalues: degree drops to 3, phi(A) = I, one iteration
+    lam = np.repeat([1.0, 2.0, 5.0], 10)
+    A = diagonal(lam).to_scipy()
+    P = roots.setup(A, start_vector(30, 3), 10)
+    b = rhs(30, 1)
+    x, info = solver.pp_gmres(A, b, P.units, m=10, tol=1e-10)
+    assert info.status == solver.OK and info.iters == 1
+    assert np.allclose(x, b / lam, rtol=1e-9)
+
+
+def test_mixed_emulation_bound():
+    A, b, v0 = _cfg1()
+    P = roots.setup(A, v0, 10)
+    A32 = A.astype(np.float32)
+    p64 = chains.apply_p(A, P.units, b)
+    d32 = np.linalg.norm(apply_p_low(A32, P.units, b) - p64) / np.linalg.norm(p64)
+    d16 = np.linalg.norm(apply_p_low(A32, P.units, b, "bf16") - p64) / np.linalg.norm(p64)
+    f64 = chains.apply_phi(A, P.units, b)
+    e32 = np.linalg.norm(apply_phi_low(A32, P.units, b) - f64) / np.linalg.norm(f64)
+    assert 1e-9 < d32 < 1e-5 and 1e-9 < e32 < 1e-5
+    assert d32 < d16 < 1e-1
+
+
+def test_bf16_rounding_matches_torch():
+    # torch's float32 -> bfloat16 conversion rounds to nearest even
+    x = np.random.default_rng(0).standard_normal(10000).astype(np.float32) * 10.0
+    x[:4] = [1.0 + 2**-8, 1.0 + 3 * 2**-8, -(1.0 + 2**-8), 0.0]
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(round_bf16(x), ref)
+
+
+def test_adjoint_gradient_vs_finite_differences():
+    N = 12
+    A0, dval = convdiff2d_parts(N)
+    n = N * N
+    b = rhs(n, 1)
+    xt = np.random.default_rng(3).standard_normal(n)
+    alpha = 20.0
+
+    def loss(al):
+        A = A0.with_values(A0.val + al * dval).to_scipy()
+        x = sla.spsolve(A.tocsc(), b)
+        return 0.5 * np.sum((x - xt) ** 2)
+
+    A = A0.with_values(A0.val + alpha * dval).to_scipy()
+    x, lam, dv = grad_direct(A, b, lambda x: x - xt)
+    g = float(dv @ dval)
+    h = 1e-6
+    fd = (loss(alpha + h) - loss(alpha - h)) / (2 * h)
+    assert abs(g - fd) <= 1e-6 * abs(fd)
+    # dL/db = lambda: check one component by finite differences
+    e = np.zeros(n)
+    e[5] = 1.0
+    xp = sla.spsolve(A.tocsc(), b + h * e)
+    xm = sla.spsolve(A.tocsc(), b - h * e)
+    fdb = (0.5 * np.sum((xp - xt) ** 2) - 0.5 * np.sum((xm - xt) ** 2)) / (2 * h)
+    assert abs(lam[5] - fdb) <= 1e-6 * abs(fdb)

@@ -1,0 +1,218 @@
+"""Seeded synthetic workloads for polynomial-preconditioned GMRES.
+
+Matrices are returned in CSR form with int32 row pointers and column
+indices (sorted ascending within each row) and float64 values. All random
+draws use numpy's PCG64 ``default_rng(seed)``.
+
+Operators
+---------
+* Convection-diffusion, section 3.2 (Example 5) of Loe & Morgan: the PDE
+  -u_xx - u_yy + alpha u_x + beta u_y - gamma u on the unit square (and the
+  7-point 3-D analogue), zero Dirichlet boundary, uniform grid with N
+  interior points per side, h = 1/(N+1). Centred differences, every row
+  multiplied by h^2: diagonal 2*dim - gamma h^2, the lower x-neighbour
+  -1 - alpha h/2, the upper x-neighbour -1 + alpha h/2 (likewise for y and z).
+  Rows are ordered lexicographically with x fastest. Every stencil entry is
+  stored even when its coefficient is zero, so the sparsity pattern does
+  not depend on the coefficients.
+* Random nonsymmetric sparse: every row has 16 distinct off-diagonal
+  columns drawn uniformly without replacement, N(0,1) values, and the
+  diagonal 1.05 times the row's absolute off-diagonal sum.
+* Diagonal matrices of Examples 7 and 11/12 of the paper.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class CSR:
+    """A square sparse matrix in CSR form (host arrays)."""
+
+    n: int
+    rowptr: np.ndarray  # int32[n+1]
+    colind: np.ndarray  # int32[nnz]
+    val: np.ndarray  # float64[nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+
+        return sp.csr_matrix((self.val, self.colind, self.rowptr), shape=(self.n, self.n))
+
+    def with_values(self, val: np.ndarray) -> "CSR":
+        return CSR(self.n, self.rowptr, self.colind, np.ascontiguousarray(val, dtype=np.float64))
+
+
+def _csr_from_dense_slots(cols: np.ndarray, vals: np.ndarray, mask: np.ndarray) -> tuple:
+    """Pack an (n, k) slot table (columns ascending along axis 1) into CSR."""
+    counts = mask.sum(axis=1)
+    rowptr = np.zeros(cols.shape[0] + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    colind = cols[mask].astype(np.int32)
+    val = vals[mask].astype(np.float64)
+    assert rowptr[-1] < 2**31
+    return rowptr.astype(np.int32), colind, val
+
+
+def _stencil(N: int, dim: int, coef, gamma: float, with_parts: bool = False):
+    """Build the h^2-scaled centred-difference convection-diffusion matrix.
+
+    coef: convection coefficient per axis (x, y[, z]).
+    Returns (rowptr, colind, val) or, with with_parts, also the derivative of
+    the values with respect to the x-convection coefficient.
+    """
+    h = 1.0 / (N + 1)
+    half_h = 0.5 * h
+    n = N**dim
+    idx = np.arange(n, dtype=np.int64)
+    coords = [(idx // (N**a)) % N for a in range(dim)]  # x fastest
+    # slot order gives ascending columns: highest axis first (-), diag, then (+)
+    slots = []
+    for a in reversed(range(dim)):
+        slots.append((a, -1))
+    slots.append((None, 0))
+    for a in range(dim):
+        slots.append((a, +1))
+    k = len(slots)
+    cols = np.zeros((n, k), dtype=np.int64)
+    vals = np.zeros((n, k), dtype=np.float64)
+    dvals = np.zeros((n, k), dtype=np.float64)
+    mask = np.zeros((n, k), dtype=bool)
+    for s, (a, sgn) in enumerate(slots):
+        if a is None:
+            cols[:, s] = idx
+            vals[:, s] = 2.0 * dim - gamma * h * h
+            mask[:, s] = True
+            continue
+        stride = N**a
+        ok = coords[a] > 0 if sgn < 0 else coords[a] < N - 1
+        cols[:, s] = idx + sgn * stride
+        off = coef[a] * half_h
+        # lower neighbour: -1 - c h/2 ; upper neighbour: -1 + c h/2
+        vals[:, s] = -1.0 - off if sgn < 0 else -1.0 + off
+        if a == 0:
+            dvals[:, s] = -half_h if sgn < 0 else half_h
+        mask[:, s] = ok
+    rowptr, colind, val = _csr_from_dense_slots(cols, vals, mask)
+    if with_parts:
+        dval = dvals[mask].astype(np.float64)
+        return rowptr, colind, val, dval
+    return rowptr, colind, val
+
+
+def convdiff2d(N: int, alpha: float = 0.0, beta: float = 0.0, gamma: float = 0.0) -> CSR:
+    """2-D convection-diffusion on an N x N interior grid (n = N^2)."""
+    rowptr, colind, val = _stencil(N, 2, (float(alpha), float(beta)), float(gamma))
+    return CSR(N * N, rowptr, colind, val)
+
+
+def convdiff2d_parts(N: int, beta: float = 0.0, gamma: float = 0.0):
+    """2-D convection-diffusion split as values(alpha) = base + alpha * dval.
+
+    Returns (A0, dval): A0 is the matrix with no x-convection and dval the
+    derivative of the values with respect to the x-convection coefficient
+    alpha. base + alpha * dval is bit-identical to convdiff2d(N, alpha, ...)
+    because the x-neighbour entries are -1 -/+ alpha*(h/2) both ways.
+    """
+    rowptr, colind, val, dval = _stencil(N, 2, (0.0, float(beta)), float(gamma), with_parts=True)
+    return CSR(N * N, rowptr, colind, val), dval
+
+
+def convdiff3d(N: int, cx: float = 0.0, cy: float = 0.0, cz: float = 0.0, gamma: float = 0.0) -> CSR:
+    """3-D convection-diffusion, 7-point stencil on an N^3 interior grid."""
+    rowptr, colind, val = _stencil(N, 3, (float(cx), float(cy), float(cz)), float(gamma))
+    return CSR(N**3, rowptr, colind, val)
+
+
+def randsparse(n: int, k: int = 16, seed: int = 7, dominance: float = 1.05) -> CSR:
+    """Random nonsymmetric sparse matrix with k off-diagonals per row.
+
+    Columns: k distinct values in [0, n) excluding the row index, uniform
+    without replacement (rows with a repeated draw are redrawn). Values
+    N(0,1). Diagonal: dominance * sum_j |a_ij|.
+    """
+    rng = np.random.default_rng(seed)
+    rows = np.arange(n, dtype=np.int64)[:, None]
+    cols = rng.integers(0, n - 1, size=(n, k), dtype=np.int64)
+    cols += cols >= rows  # skip the diagonal
+    cols.sort(axis=1)
+    while True:
+        dup = np.any(cols[:, 1:] == cols[:, :-1], axis=1)
+        nd = int(dup.sum())
+        if nd == 0:
+            break
+        redo = rng.integers(0, n - 1, size=(nd, k), dtype=np.int64)
+        r = rows[dup]
+        redo += redo >= r
+        redo.sort(axis=1)
+        cols[dup] = redo
+    offv = rng.standard_normal((n, k))
+    diag = dominance * np.abs(offv).sum(axis=1)
+    allc = np.concatenate([cols, rows], axis=1)
+    allv = np.concatenate([offv, diag[:, None]], axis=1)
+    order = np.argsort(allc, axis=1, kind="stable")
+    allc = np.take_along_axis(allc, order, axis=1)
+    allv = np.take_along_axis(allv, order, axis=1)
+    rowptr = (np.arange(n + 1, dtype=np.int64) * (k + 1)).astype(np.int32)
+    return CSR(n, rowptr, allc.reshape(-1).astype(np.int32), allv.reshape(-1).astype(np.float64))
+
+
+def diagonal(values) -> CSR:
+    """Diagonal matrix with the given entries."""
+    v = np.asarray(values, dtype=np.float64)
+    n = v.size
+    return CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), v.copy())
+
+
+def diag_example7() -> CSR:
+    """Example 7: entries 0.01..0.1 (step 0.01), 30, 60, 100, 101, ..., 5087; n = 5000."""
+    small = np.arange(1, 11, dtype=np.float64) / 100.0
+    big = np.arange(100, 5088, dtype=np.float64)
+    return diagonal(np.concatenate([small, [30.0, 60.0], big]))
+
+
+def diag_squares(n: int) -> CSR:
+    """Examples 11 and 12: entries i^2/n for i = 1..n."""
+    i = np.arange(1, n + 1, dtype=np.float64)
+    return diagonal(i * i / n)
+
+
+def normal_vector(n: int, seed: int, count: int | None = None) -> np.ndarray:
+    """N(0,1) draws of length n (or shape (count, n))."""
+    rng = np.random.default_rng(seed)
+    if count is None:
+        return rng.standard_normal(n)
+    return rng.standard_normal((count, n))
+
+
+def rhs(n: int, seed: int = 1, count: int | None = None) -> np.ndarray:
+    """Right-hand side(s): N(0,1) draws, each normalised to unit 2-norm."""
+    b = normal_vector(n, seed, count)
+    if count is None:
+        return b / np.linalg.norm(b)
+    return b / np.linalg.norm(b, axis=1, keepdims=True)
+
+
+def start_vector(n: int, seed: int = 2) -> np.ndarray:
+    """Random start vector for the polynomial's GMRES(d) run (not normalised)."""
+    return normal_vector(n, seed)
+
+
+def batched_convdiff_specs(count: int = 256, seed: int = 11, side_lo: int = 64, side_hi: int = 512,
+                           coef_hi: float = 50.0):
+    """Sizes and convection coefficients of the batched 2-D workload.
+
+    Returns a list of (N, alpha, rhs_seed, start_seed) with N uniform in
+    [side_lo, side_hi] and alpha uniform in [0, coef_hi).
+    """
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(side_lo, side_hi + 1, size=count)
+    alphas = rng.uniform(0.0, coef_hi, size=count)
+    return [(int(sides[i]), float(alphas[i]), 1000 + i, 5000 + i) for i in range(count)]
