@@ -1,0 +1,225 @@
+"""Benchmark: time-to-solution of PP-GMRES and p(A)v bandwidth on one MI355X.
+
+Workload (the one the headline metric is quoted on): 3-D convection-diffusion
+-Lap u + 10 (u_x + u_y + u_z), 7-point finite differences on a 128^3 grid
+(n = 2,097,152, nnz = 14,581,760), b ~ N(0,1) normalised, polynomial of
+degree 40 from GMRES(40) on a seeded N(0,1) start vector with roots added
+for stability, PP-GMRES(50) to a true relative residual of 1e-8.
+
+One step = polynomial setup + solve (the whole hot path) with the p/phi
+chains and Krylov vectors in FP32 inside FP64 iterative refinement. The
+plain FP64 form is timed beside it. Inputs are resident in HBM before the
+timed region. Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solution @1e-8 rel. residual; p(A)v achieved HBM GB/s (FP32 vs FP64)"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def step_bytes(n, nnz, s_val, s_vec):
+    """Algorithmic bytes of one chain step: CSR read once, input read once, output written once."""
+    return nnz * (s_val + 4) + 4 * (n + 1) + 2 * n * s_vec
+
+
+def cpu_baseline(csr, b, v0, d, m, gpu_iters, gpu_cycles, d_eff):
+    """The oracle timed on the host on a bounded sample, extrapolated to the solve's op counts."""
+    import numpy as np
+
+    from oracle import chains, roots
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([1] + [i.get("num_threads", 1) for i in threadpool_info()])
+    except Exception:
+        threads = os.cpu_count() or 1
+    A = csr.to_scipy()
+    t0 = time.perf_counter()
+    P = roots.setup(A, v0, d)
+    t_setup = time.perf_counter() - t0
+    v = b / np.linalg.norm(b)
+    t0 = time.perf_counter()
+    chains.apply_phi(A, P.units, v)
+    t_phi = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    chains.apply_p(A, P.units, v)
+    t_p = time.perf_counter() - t0
+    w = v.copy()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        h = w @ v
+        w = w - h * v
+    t_da = (time.perf_counter() - t0) / 10
+    t0 = time.perf_counter()
+    _ = b - A @ v
+    t_res = time.perf_counter() - t0
+    sample = t_setup + t_phi + t_p + 10 * t_da + t_res
+    # extrapolate: per Arnoldi step j one phi(A)v and (j+1) dot+axpy pairs (MGS);
+    # per cycle one p(A)v and one residual
+    per_cycle = max(1, int(round(gpu_iters / max(gpu_cycles, 1))))
+    est = t_setup
+    left = gpu_iters
+    for _ in range(gpu_cycles):
+        k = min(per_cycle, left)
+        left -= k
+        est += sum(t_phi + (j + 1) * t_da for j in range(k)) + t_p + t_res
+    return {
+        "value": est,
+        "unit": "s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"FP64 numpy/scipy oracle: full setup (GMRES({d}) MGS, Leja, added roots: {t_setup:.2f} s), "
+                   f"one phi(A)v ({t_phi:.2f} s), one p(A)v ({t_p:.2f} s), dot+axpy ({t_da * 1e3:.1f} ms), "
+                   f"one residual; extrapolated to the GPU run's {gpu_iters} Arnoldi steps in {gpu_cycles} "
+                   f"cycles; sample took {sample:.1f} s"),
+        "oracle_d_eff": P.d_eff,
+        "gpu_d_eff": d_eff,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--degree", type=int, default=40)
+    ap.add_argument("--m", type=int, default=50)
+    ap.add_argument("--pav-reps", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the build has no multi-GPU path; "
+              "see DESIGN.md for how the solver would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1911_07065_amd.api as pp
+    from workloads import convdiff3d, rhs, start_vector
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    N, d, m, tol = args.grid, args.degree, args.m, 1e-8
+    log("generating workload", N)
+    csr = convdiff3d(N, 10.0, 10.0, 10.0)
+    n, nnz = csr.n, csr.nnz
+    b = rhs(n, 1)
+    v0 = start_vector(n, 2)
+    M = pp.Matrix.from_csr(csr)
+    bd = torch.as_tensor(b, device="cuda")
+    v0d = torch.as_tensor(v0, device="cuda")
+    torch.cuda.synchronize()
+
+    def step(inner):
+        poly = pp.setup(M, v0d, d)
+        x, info = pp.solve(poly, M, bd, tol=tol, m=m, inner=inner)
+        return poly, x, info
+
+    res = {}
+    for inner in ("fp32", "fp64"):
+        for _ in range(args.warmup):
+            step(inner)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            poly, x, info = step(inner)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        A = csr.to_scipy()
+        rel = float(np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b))
+        res[inner] = dict(t=t, info=info, poly=poly, relres=rel)
+        log(inner, f"time-to-solution {t * 1e3:.1f} ms", info, "true relres", rel)
+
+    # p(A)v bandwidth (algorithmic bytes / event time), FP32 and FP64
+    poly = res["fp32"]["poly"]
+    nl = poly.d_eff - 1  # launches of the p chain
+    stream = torch.cuda.current_stream()
+    pav = {}
+    for prec, dt, sv, sx in (("fp32", torch.float32, 4, 4), ("fp64", torch.float64, 8, 8)):
+        v = bd.to(dt)
+        y = torch.empty_like(v)
+        for _ in range(3):
+            pp.apply(poly, M, v, "p", out=y)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.pav_reps):
+            pp.apply(poly, M, v, "p", out=y)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / args.pav_reps
+        by = nl * step_bytes(n, nnz, sv, sx) + 2 * n * sx
+        pav[prec] = dict(ms=ms, GBps=by / (ms * 1e-3) / 1e9, bytes=by, launches=nl,
+                         launch_us=ms * 1e3 / nl, step_bytes=step_bytes(n, nnz, sv, sx))
+        log("p(A)v", prec, f"{ms:.3f} ms", f"{pav[prec]['GBps']:.0f} GB/s", f"{pav[prec]['launch_us']:.1f} us/launch")
+
+    k32 = pav["fp32"]
+    achieved = k32["step_bytes"] / (k32["launch_us"] * 1e-6) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": "k_chain<float,float> (fused CSR SpMV + chain update, one root factor)",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBPS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBPS, 4),
+        "traffic": None,
+        "bytes_per_launch": k32["step_bytes"],
+        "avg_launch_us": round(k32["launch_us"], 3),
+    }
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the oracle on the host (bounded sample)")
+        i32 = res["fp32"]["info"]
+        cpu = cpu_baseline(csr, b, v0, d, m, i32["iters"], i32["cycles"], poly.d_eff)
+
+    r32, r64 = res["fp32"], res["fp64"]
+    out = {
+        "metric": METRIC,
+        "value": round(r32["t"], 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["t"] * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"3-D convection-diffusion {N}^3 (n={n}, nnz={nnz}), PP({d}+{poly.n_added})-GMRES({m}) "
+                         f"to 1e-8, FP32 chains + FP64 refinement; setup included"),
+            "n": n, "nnz": nnz, "d": d, "d_eff": poly.d_eff, "m": m, "tol": tol,
+        },
+        "relres": r32["relres"],
+        "iters": r32["info"]["iters"],
+        "cycles": r32["info"]["cycles"],
+        "fp64_time_to_solution_s": round(r64["t"], 6),
+        "fp64_relres": r64["relres"],
+        "fp64_iters": r64["info"]["iters"],
+        "mixed_speedup_vs_fp64": round(r64["t"] / r32["t"], 3),
+        "pAv_GBps": {"fp32": round(pav["fp32"]["GBps"], 1), "fp64": round(pav["fp64"]["GBps"], 1)},
+        "pAv_ms": {"fp32": round(pav["fp32"]["ms"], 4), "fp64": round(pav["fp64"]["ms"], 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

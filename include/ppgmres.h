@@ -1,0 +1,240 @@
+/*
+ * ppgmres.h - C ABI of the MI355X (gfx950) polynomial-preconditioned GMRES
+ * library (Loe & Morgan, "Toward Efficient Polynomial Preconditioning for
+ * GMRES", arXiv 1911.07065).
+ *
+ * Conventions for every entry point:
+ *  - Plain C types only. "device" pointers are HIP device memory owned by the
+ *    caller; "host" pointers are ordinary CPU memory owned by the caller.
+ *    The library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls are ordered on that stream; results written to device memory are
+ *    valid after the stream is synchronised. Entry points that return host
+ *    results (info structs, roots) synchronise the stream themselves.
+ *  - Indices are int32, values are IEEE binary64 unless stated otherwise.
+ *  - Negative status = error: outputs are left unspecified, pp_last_error()
+ *    returns a message (thread-local). Positive status = warning with valid
+ *    outputs. No C++ exception crosses the boundary.
+ *  - Handles (pp_matrix, pp_poly) are library-owned; a pp_poly is immutable
+ *    after creation and may be shared between streams; a pp_matrix holds
+ *    scratch memory and must not be used by two streams at once.
+ */
+#ifndef PPGMRES_H
+#define PPGMRES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PP_OK = 0,
+    PP_NOCONV = 1,     /* tolerance not reached (max cycles or stall); best x returned */
+    PP_BREAKDOWN = 2,  /* setup Krylov space invariant at k < d: degree lowered to k */
+    PP_UNSTABLE = 3,   /* stability check above its threshold */
+    PP_EINVAL = -1,    /* bad argument */
+    PP_ENOMEM = -2,    /* device or host allocation failed */
+    PP_EDEVICE = -3,   /* HIP runtime error */
+    PP_ESINGULAR = -4  /* H_dd singular or a zero harmonic Ritz value */
+} pp_status;
+
+/* Arithmetic of a chain / Krylov vectors. */
+typedef enum {
+    PP_F64 = 0,   /* binary64 storage and arithmetic */
+    PP_F32 = 1,   /* binary32 storage and arithmetic */
+    PP_BF16S = 2  /* bfloat16 vector storage, binary32 arithmetic, binary32 matrix values */
+} pp_prec;
+
+/* Which polynomial pp_apply evaluates. */
+typedef enum {
+    PP_APPLY_P = 0,   /* y = p(A) v      (Algorithm 3; eq. 3.1) */
+    PP_APPLY_PHI = 1, /* y = phi(A) v = v - pi(A) v  (Algorithm 1) */
+    PP_APPLY_PI = 2   /* y = pi(A) v     (eqs. 2.1, 2.2) */
+} pp_apply_kind;
+
+typedef struct pp_matrix_s *pp_matrix;
+typedef struct pp_poly_s *pp_poly;
+
+/* Result of pp_gmres_setup. */
+typedef struct {
+    int d;           /* degree reached (number of harmonic Ritz values) */
+    int d_eff;       /* roots after Algorithm 2 (d + n_added) */
+    int n_added;     /* roots added for stability */
+    int breakdown;   /* 1 if the setup Krylov space became invariant */
+    int64_t mvps;    /* sparse products used by the setup cycle */
+    int64_t dots;    /* inner products and norms used by the setup cycle */
+    double t_setup_s;
+} pp_setup_info;
+
+/* Options of pp_solve. */
+typedef struct {
+    int m;            /* GMRES restart length (Krylov dimension per cycle) */
+    int max_cycles;   /* cycle limit */
+    double tol;       /* stop when ||b - A x|| <= tol ||b|| */
+    pp_prec inner;    /* precision of the phi/p chains and the Krylov basis */
+    int stall_cycles; /* NOCONV if this many cycles cut ||r|| by < 1% (0: off) */
+} pp_solve_opts;
+
+/* Result of pp_solve. */
+typedef struct {
+    int status;            /* pp_status of the solve */
+    int cycles;            /* restarts + 1 */
+    int iters;             /* outer Arnoldi steps in total */
+    int fp64_cycles;       /* cycles run with FP64 inner arithmetic */
+    int64_t mvps;          /* sparse products (solve only) */
+    int64_t vops;          /* length-n vector operations */
+    int64_t dots;          /* inner products and norms */
+    double relres;         /* true ||b - A x|| / ||b|| in FP64 */
+    double relres_shortcut;/* last cycle's ||beta e1 - Hbar z|| / ||b|| */
+    double t_solve_s;
+} pp_info;
+
+/* ------------------------------------------------------------------ */
+/* Matrix handle                                                        */
+/* ------------------------------------------------------------------ */
+
+/* Wrap a square CSR matrix that lives in device memory (section 1: A is
+ * large, sparse, real and nonsymmetric).
+ *   n, nnz   : size and number of stored entries (nnz < 2^31).
+ *   rowptr   : device int32[n+1], rowptr[0] = 0, non-decreasing.
+ *   colind   : device int32[nnz], column indices in [0, n).
+ *   val      : device double[nnz].
+ * The arrays are borrowed, not copied: they must stay valid and unchanged
+ * (except through pp_matrix_set_values) while the handle lives. The library
+ * allocates a float32 copy of the values and a row-tile plan.
+ * Errors: PP_EINVAL on bad sizes or a malformed rowptr, PP_ENOMEM, PP_EDEVICE. */
+pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colind,
+                           const double *val, void *stream, pp_matrix *out);
+
+/* Point the handle at new values (same pattern), e.g. after a parameter
+ * update; refreshes the float32 copy. val: device double[nnz]. */
+pp_status pp_matrix_set_values(pp_matrix A, const double *val, void *stream);
+
+/* Release the handle and its scratch memory (not the caller's arrays). */
+void pp_matrix_destroy(pp_matrix A);
+
+/* Transposed pattern of A for the adjoint solve (p(A)^T = p(A^T)).
+ * Outputs (device, caller-allocated): rowptr_t int32[n+1], colind_t
+ * int32[nnz], perm int32[nnz] with val_t[k] = val[perm[k]]. Entries of a
+ * row of A^T are in ascending column order (stable counting sort). */
+pp_status pp_matrix_transpose(pp_matrix A, int32_t *rowptr_t, int32_t *colind_t, int32_t *perm,
+                              void *stream);
+
+/* out[k] = in[perm[k]] for k < nnz (device double arrays). */
+pp_status pp_gather(int64_t nnz, const double *in, const int32_t *perm, double *out, void *stream);
+
+/* Gradient of a loss through A x = b with respect to the stored values:
+ * dval[k] = -lam[row(k)] * x[col(k)]  (lam solves A^T lam = dL/dx).
+ * lam, x: device double[n]; dval: device double[nnz]. */
+pp_status pp_adjoint_values(pp_matrix A, const double *lam, const double *x, double *dval,
+                            void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Polynomial                                                           */
+/* ------------------------------------------------------------------ */
+
+/* Build the preconditioning polynomial (Algorithm 4 step 1): one GMRES(d)
+ * cycle on A from v0 (FP64 Arnoldi with classical Gram-Schmidt applied
+ * twice, on the device), harmonic Ritz values from the Hessenberg matrix
+ * (host), modified Leja ordering and, if add_roots, Algorithm 2's added
+ * roots (host).
+ *   v0: device double[n], the random start vector (section 3.6 advises a
+ *       random vector, not the right-hand side); not modified.
+ *   d : requested degree, 1 <= d <= n and d <= 4096.
+ * Returns PP_BREAKDOWN (with a valid polynomial of lower degree) if the
+ * Krylov space became invariant, PP_ESINGULAR if H_dd is singular or a root
+ * is zero. info may be NULL. */
+pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, void *stream,
+                         pp_poly *out, pp_setup_info *info);
+
+/* Flags of pp_poly_from_roots. */
+#define PP_ROOTS_ADD 1        /* add roots for stability (Algorithm 2) */
+#define PP_ROOTS_KEEP_ORDER 2 /* use the list as given: no Leja ordering, no added
+                                 roots; pairs must be adjacent (a+bi, a-bi) */
+
+/* Build a polynomial from given roots (host arrays, conjugate pairs
+ * present as exact conjugates): modified Leja ordering and, with
+ * PP_ROOTS_ADD, added roots as in pp_gmres_setup; with PP_ROOTS_KEEP_ORDER
+ * the list is applied in the given order. */
+pp_status pp_poly_from_roots(int d, const double *re, const double *im, int flags, pp_poly *out);
+
+/* Which root list pp_poly_roots copies. */
+#define PP_ROOTS_FINAL 0  /* ordered list with added roots (what the chains apply) */
+#define PP_ROOTS_THETA 1  /* harmonic Ritz values as the eigensolver returned them */
+#define PP_ROOTS_LEJA 2   /* original roots in modified Leja order */
+
+/* Copy a root list (host). cap: capacity of re/im (re/im may be NULL to
+ * query sizes); len receives the list length (PP_EINVAL if cap < len).
+ * d_orig / n_added may be NULL. */
+pp_status pp_poly_roots(pp_poly p, int which, int cap, double *re, double *im, int *len, int *d_orig,
+                        int *n_added);
+
+void pp_poly_destroy(pp_poly p);
+
+/* ------------------------------------------------------------------ */
+/* Hot path                                                             */
+/* ------------------------------------------------------------------ */
+
+/* y = p(A) v, phi(A) v or pi(A) v by the root-product chain (Algorithms 1
+ * and 3), every sparse product fused with its vector updates.
+ *   v, y : device vectors of n elements of type prec (double, float or
+ *          bfloat16 bits as uint16); v is not modified; y must not alias v.
+ * Chains of float32/bfloat16 use the float32 copy of the values. */
+pp_status pp_apply(pp_poly p, pp_matrix A, int kind, int prec, const void *v, void *y,
+                   void *stream);
+
+/* Solve A x = b by PP(d)-GMRES(m) (Algorithm 4 step 2), x_0 = 0.
+ * Each cycle starts from the true residual r = b - A x computed in FP64;
+ * the cycle runs GMRES(m) on phi(A) in opts->inner precision and adds
+ * ||r|| * p(A)(V z) to x in FP64 (iterative refinement when inner is not
+ * FP64). A mixed cycle that fails to halve ||r|| is followed by an FP64 one.
+ *   b, x : device double[n]; x is overwritten.
+ * Returns PP_OK or PP_NOCONV (x is then the last iterate); info may be NULL. */
+pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_solve_opts *opts,
+                   void *stream, pp_info *info);
+
+/* Stability check of section 3.5: StCh = ||(b - A p(A) b) - pi(A) b|| in
+ * FP64. b: device double[n]; result to *stch (host). */
+pp_status pp_stability_check(pp_poly p, pp_matrix A, const double *b, void *stream, double *stch);
+
+/* ------------------------------------------------------------------ */
+/* Host-only building blocks (deterministic; no device work)            */
+/* ------------------------------------------------------------------ */
+
+/* Harmonic Ritz values from the (k+1) x k upper Hessenberg matrix Hbar
+ * (column-major, leading dimension k+1): eigenvalues of H_kk + h^2 f e_k^T
+ * with H_kk^T f = e_k (Algorithm 4 step 1b); if breakdown != 0 the last row
+ * is ignored and the eigenvalues of H_kk are returned. re/im: host double[k];
+ * a conjugate pair is returned as exact conjugates, +imag first. */
+pp_status pp_harmonic_ritz(int k, const double *hbar, int breakdown, double *re, double *im);
+
+/* Eigenvalues of a real upper Hessenberg matrix (column-major, ld >= k) by
+ * the Francis double-shift QR iteration. */
+pp_status pp_hessenberg_eig(int k, const double *h, int ld, double *re, double *im);
+
+/* Modified Leja permutation (section 2, Algorithm 2 step 1): the ordered
+ * roots are re[perm[i]] + i im[perm[i]]; conjugate pairs adjacent, +imag
+ * first. Exact ties go to the lowest (real, imag)-sorted index. */
+pp_status pp_leja_order(int d, const double *re, const double *im, int *perm);
+
+/* Algorithm 2 steps 2-3 on Leja-ordered roots: pof per unit (mantissa in
+ * [0.5,1) and binary exponent, one entry per root position: the +imag
+ * member of a pair holds the pair's value, the -imag member a copy),
+ * copies per unit n_add (same layout) and the final root list with the
+ * copies inserted (re_out/im_out, capacity cap, length *d_eff). With
+ * add == 0 no copies are inserted (pof and n_add are still reported). */
+pp_status pp_add_roots(int d, const double *re, const double *im, int add, int cap, double *re_out,
+                       double *im_out, int *d_eff, int *n_add, double *pof_mant, int *pof_exp);
+
+/* Message of the last error on this thread. */
+const char *pp_last_error(void);
+
+/* Library version string. */
+const char *pp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPGMRES_H */

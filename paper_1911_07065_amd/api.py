@@ -1,0 +1,336 @@
+"""Python front of libppgmres: argument marshalling between torch tensors and the C ABI.
+
+Every numerical step runs in the library (HIP kernels on the GPU, C++ for
+the small host-side problems). Tensors passed to the device entry points
+must live on a ROCm device; nothing here computes a result on the CPU.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from ._lib import SetupInfo, SolveInfo, SolveOpts, check, lib, PP_BREAKDOWN, PP_NOCONV, STATUS_NAMES
+
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+DTYPE_OF_PREC = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}
+PREC_OF_DTYPE = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2}
+KIND = {"p": 0, "phi": 1, "pi": 2}
+
+
+def version() -> str:
+    return lib.pp_version().decode()
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_tensor(x, dtype, device):
+    t = torch.as_tensor(x, dtype=dtype, device=device)
+    if t.device.type != "cuda":
+        raise ValueError("device tensors are required")
+    return t.contiguous()
+
+
+class Matrix:
+    """A square CSR matrix on the GPU (int32 indices, float64 values).
+
+    The tensors are kept alive by this object; the library borrows them.
+    """
+
+    def __init__(self, rowptr, colind, val, device="cuda"):
+        self.rowptr = _dev_tensor(rowptr, torch.int32, device)
+        self.colind = _dev_tensor(colind, torch.int32, device)
+        self.val = _dev_tensor(val, torch.float64, device)
+        self.n = int(self.rowptr.numel() - 1)
+        self.nnz = int(self.colind.numel())
+        self.device = self.val.device
+        h = ctypes.c_void_p()
+        check(lib.pp_matrix_create(self.n, self.nnz, _ptr(self.rowptr), _ptr(self.colind), _ptr(self.val),
+                                   _stream(self.device), ctypes.byref(h)), "pp_matrix_create")
+        self.handle = h
+        self._t = None
+
+    @classmethod
+    def from_csr(cls, csr, device="cuda"):
+        """From any object with rowptr/colind/val host arrays (e.g. workloads.CSR)."""
+        return cls(csr.rowptr, csr.colind, csr.val, device=device)
+
+    def set_values(self, val):
+        val = _dev_tensor(val, torch.float64, self.device)
+        if val.numel() != self.nnz:
+            raise ValueError("value count does not match the pattern")
+        check(lib.pp_matrix_set_values(self.handle, _ptr(val), _stream(self.device)), "pp_matrix_set_values")
+        self.val = val
+        self._t = None
+
+    def transpose_pattern(self):
+        """(rowptr_t, colind_t, perm) of A^T with val_t = val[perm]."""
+        rp = torch.empty(self.n + 1, dtype=torch.int32, device=self.device)
+        ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
+        pm = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
+        check(lib.pp_matrix_transpose(self.handle, _ptr(rp), _ptr(ci), _ptr(pm), _stream(self.device)),
+              "pp_matrix_transpose")
+        return rp, ci[: self.nnz], pm[: self.nnz]
+
+    def transpose(self) -> "Matrix":
+        """A^T as a new Matrix (pattern built once, values gathered on the GPU)."""
+        rp, ci, pm = self.transpose_pattern()
+        vt = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
+        check(lib.pp_gather(self.nnz, _ptr(self.val), _ptr(pm), _ptr(vt), _stream(self.device)), "pp_gather")
+        At = Matrix(rp, ci, vt, device=self.device)
+        At.perm = pm
+        return At
+
+    def adjoint_values(self, lam: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+        """dval[k] = -lam[row k] * x[col k]."""
+        out = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
+        check(lib.pp_adjoint_values(self.handle, _ptr(lam.contiguous()), _ptr(x.contiguous()), _ptr(out),
+                                    _stream(self.device)), "pp_adjoint_values")
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            lib.pp_matrix_destroy(h)
+            self.handle = None
+
+
+@dataclass
+class Poly:
+    """Handle of a preconditioning polynomial (library-owned root list)."""
+
+    handle: ctypes.c_void_p
+    d: int
+    d_eff: int
+    n_added: int
+    breakdown: bool = False
+    setup_info: dict | None = None
+
+    def roots(self, which: str = "final") -> np.ndarray:
+        """Root list: "final" (applied order, with added roots), "theta" (raw
+        harmonic Ritz values) or "leja" (original roots in Leja order)."""
+        w = {"final": 0, "theta": 1, "leja": 2}[which]
+        ln = ctypes.c_int()
+        check(lib.pp_poly_roots(self.handle, w, 0, None, None, ctypes.byref(ln), None, None), "pp_poly_roots")
+        re = np.zeros(ln.value)
+        im = np.zeros(ln.value)
+        check(lib.pp_poly_roots(self.handle, w, ln.value, re.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                im.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(ln), None, None),
+              "pp_poly_roots")
+        return re + 1j * im
+
+    def units(self):
+        """(kind, re, im) units of the final root list (kind 1 = conjugate pair)."""
+        r = self.roots()
+        out, i = [], 0
+        while i < r.size:
+            if r[i].imag == 0:
+                out.append((0, float(r[i].real), 0.0))
+                i += 1
+            else:
+                out.append((1, float(r[i].real), float(r[i].imag)))
+                i += 2
+        return out
+
+    def __del__(self):
+        if self.handle is not None and self.handle.value:
+            lib.pp_poly_destroy(self.handle)
+            self.handle = None
+
+
+def _poly_from_handle(h, setup_info=None, breakdown=False) -> Poly:
+    de, do, na = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(lib.pp_poly_roots(h, 0, 0, None, None, ctypes.byref(de), ctypes.byref(do), ctypes.byref(na)),
+          "pp_poly_roots")
+    return Poly(h, do.value, de.value, na.value, breakdown, setup_info)
+
+
+def setup(A: Matrix, v0, d: int, add_roots: bool = True) -> Poly:
+    """Polynomial of degree d from one GMRES(d) cycle on A started at v0 (Algorithm 4 step 1)."""
+    v0 = _dev_tensor(v0, torch.float64, A.device)
+    if v0.numel() != A.n:
+        raise ValueError("start vector length")
+    h = ctypes.c_void_p()
+    info = SetupInfo()
+    st = check(lib.pp_gmres_setup(A.handle, _ptr(v0), int(d), int(bool(add_roots)), _stream(A.device),
+                                  ctypes.byref(h), ctypes.byref(info)), "pp_gmres_setup")
+    si = {k: getattr(info, k) for k, _ in SetupInfo._fields_}
+    return _poly_from_handle(h, si, breakdown=(st == PP_BREAKDOWN) or bool(info.breakdown))
+
+
+def poly_from_roots(roots, add_roots: bool = False, keep_order: bool = False) -> Poly:
+    """Polynomial with given roots: Leja-ordered (optionally with added roots),
+    or applied exactly in the given order with keep_order=True."""
+    r = np.asarray(roots, dtype=np.complex128)
+    re = np.ascontiguousarray(r.real)
+    im = np.ascontiguousarray(r.imag)
+    flags = (1 if add_roots else 0) | (2 if keep_order else 0)
+    h = ctypes.c_void_p()
+    check(lib.pp_poly_from_roots(r.size, re.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 im.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), flags,
+                                 ctypes.byref(h)), "pp_poly_from_roots")
+    return _poly_from_handle(h)
+
+
+def apply(poly: Poly, A: Matrix, v: torch.Tensor, kind: str = "p", out: torch.Tensor | None = None) -> torch.Tensor:
+    """p(A)v, phi(A)v or pi(A)v; the precision follows v's dtype (float64, float32 or bfloat16)."""
+    if v.dtype not in PREC_OF_DTYPE:
+        raise TypeError("v must be float64, float32 or bfloat16")
+    v = v.contiguous()
+    if v.numel() != A.n or v.device != A.device:
+        raise ValueError("v must be a length-n tensor on the matrix's device")
+    if out is None:
+        out = torch.empty_like(v)
+    check(lib.pp_apply(poly.handle, A.handle, KIND[kind], PREC_OF_DTYPE[v.dtype], _ptr(v), _ptr(out),
+                       _stream(A.device)), "pp_apply")
+    return out
+
+
+def solve(poly: Poly, A: Matrix, b, tol: float = 1e-8, m: int = 50, max_cycles: int = 1000,
+          inner: str = "fp32", stall_cycles: int = 5, x: torch.Tensor | None = None):
+    """x solving A x = b by PP-GMRES(m) with FP64 refinement. Returns (x, info dict)."""
+    b = _dev_tensor(b, torch.float64, A.device)
+    if b.numel() != A.n:
+        raise ValueError("right-hand side length")
+    if x is None:
+        x = torch.empty_like(b)
+    opts = SolveOpts(int(m), int(max_cycles), float(tol), PREC[inner], int(stall_cycles))
+    info = SolveInfo()
+    st = check(lib.pp_solve(poly.handle, A.handle, _ptr(b), _ptr(x), ctypes.byref(opts), _stream(A.device),
+                            ctypes.byref(info)), "pp_solve")
+    out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+    out["status_name"] = STATUS_NAMES.get(st, str(st))
+    out["converged"] = st != PP_NOCONV
+    return x, out
+
+
+def stability_check(poly: Poly, A: Matrix, b) -> float:
+    """StCh = ||(b - A p(A) b) - pi(A) b|| (section 3.5), FP64 on the GPU."""
+    b = _dev_tensor(b, torch.float64, A.device)
+    out = ctypes.c_double()
+    check(lib.pp_stability_check(poly.handle, A.handle, _ptr(b), _stream(A.device), ctypes.byref(out)),
+          "pp_stability_check")
+    return out.value
+
+
+# ---------------------------------------------------------------------------
+# differentiation: x = A(vals)^{-1} b with the adjoint solved by the same roots
+# ---------------------------------------------------------------------------
+
+class PPSolve(torch.autograd.Function):
+    """x = A^{-1} b with A's stored values as a differentiable input.
+
+    forward(vals, b, A, poly, opts): A is a Matrix whose pattern is used
+    (its values are replaced by vals), poly the polynomial (for A; its
+    roots serve A^T too since p(A)^T = p(A^T)), opts a dict of solve
+    options. backward solves A^T lam = dL/dx with the same roots on the
+    transposed pattern and returns dL/dvals[k] = -lam[row k] x[col k] and
+    dL/db = lam.
+    """
+
+    @staticmethod
+    def forward(ctx, vals, b, A, poly, opts):
+        A.set_values(vals.detach())
+        x, info = solve(poly, A, b.detach(), **opts)
+        if not info["converged"]:
+            raise RuntimeError(f"PP-GMRES did not converge in forward: {info}")
+        ctx.A, ctx.poly, ctx.opts = A, poly, opts
+        ctx.save_for_backward(vals.detach(), x)
+        ctx.info = info
+        return x
+
+    @staticmethod
+    def backward(ctx, g):
+        vals, x = ctx.saved_tensors
+        A = ctx.A
+        At = getattr(A, "_t", None)
+        if At is None:
+            At = A.transpose()
+            A._t = At
+        else:
+            vt = torch.empty_like(vals)
+            check(lib.pp_gather(A.nnz, _ptr(vals.contiguous()), _ptr(At.perm), _ptr(vt), _stream(A.device)),
+                  "pp_gather")
+            At.set_values(vt)
+        lam, info = solve(ctx.poly, At, g.contiguous(), **ctx.opts)
+        if not info["converged"]:
+            raise RuntimeError(f"PP-GMRES did not converge in backward: {info}")
+        dvals = A.adjoint_values(lam, x)
+        return dvals, lam, None, None, None
+
+
+def pp_solve_fn(vals, b, A: Matrix, poly: Poly, **opts):
+    """Differentiable x = A(vals)^{-1} b (see PPSolve)."""
+    return PPSolve.apply(vals, b, A, poly, opts)
+
+
+# ---------------------------------------------------------------------------
+# host-only building blocks (no device work; deterministic)
+# ---------------------------------------------------------------------------
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def leja_order(re, im) -> np.ndarray:
+    re = np.ascontiguousarray(re, dtype=np.float64)
+    im = np.ascontiguousarray(im, dtype=np.float64)
+    perm = np.zeros(re.size, dtype=np.int32)
+    check(lib.pp_leja_order(re.size, _dp(re), _dp(im), _ip(perm)), "pp_leja_order")
+    return perm.astype(np.int64)
+
+
+def add_roots(re, im, add: bool = True):
+    """Algorithm 2 steps 2-3 on Leja-ordered roots: dict of pof (mantissa, exponent), n_add, roots."""
+    re = np.ascontiguousarray(re, dtype=np.float64)
+    im = np.ascontiguousarray(im, dtype=np.float64)
+    d = re.size
+    n_add = np.zeros(d, dtype=np.int32)
+    mant = np.zeros(d)
+    expo = np.zeros(d, dtype=np.int32)
+    de = ctypes.c_int()
+    check(lib.pp_add_roots(d, _dp(re), _dp(im), int(add), 0, None, None, ctypes.byref(de), _ip(n_add), _dp(mant),
+                           _ip(expo)), "pp_add_roots")
+    ro = np.zeros(de.value)
+    io = np.zeros(de.value)
+    check(lib.pp_add_roots(d, _dp(re), _dp(im), int(add), de.value, _dp(ro), _dp(io), ctypes.byref(de), None, None,
+                           None), "pp_add_roots")
+    return {"n_add": n_add, "pof_mant": mant, "pof_exp": expo, "roots": ro + 1j * io, "d_eff": de.value}
+
+
+def harmonic_ritz(hbar: np.ndarray, breakdown: bool = False) -> np.ndarray:
+    hbar = np.asarray(hbar, dtype=np.float64)
+    k = hbar.shape[1]
+    h = np.asfortranarray(hbar)
+    re = np.zeros(k)
+    im = np.zeros(k)
+    check(lib.pp_harmonic_ritz(k, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(breakdown), _dp(re), _dp(im)),
+          "pp_harmonic_ritz")
+    return re + 1j * im
+
+
+def hessenberg_eig(h: np.ndarray) -> np.ndarray:
+    h = np.asfortranarray(np.asarray(h, dtype=np.float64))
+    k = h.shape[0]
+    re = np.zeros(k)
+    im = np.zeros(k)
+    check(lib.pp_hessenberg_eig(k, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), k, _dp(re), _dp(im)),
+          "pp_hessenberg_eig")
+    return re + 1j * im

@@ -1,0 +1,150 @@
+"""GPU parity of the root-product chains (Algorithms 1 and 3) against the oracle."""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from oracle import chains, roots as oroots
+from oracle.mixed import apply_p_low, apply_phi_low
+from workloads import CSR, convdiff2d, convdiff3d, randsparse, start_vector, rhs
+from gpu_util import say, dev, host, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pp():
+    import paper_1911_07065_amd.api as api
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return api
+
+
+def _ragged_csr(n=5000, seed=3):
+    """Rows of length 0..40, a few long rows (> one tile), an empty row."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, 41, size=n)
+    lens[17] = 0
+    lens[100] = 5000  # longer than a 2048-entry tile
+    lens[101] = 2048
+    lens[4000] = 2049
+    lens = np.minimum(lens, n)
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        c = np.sort(rng.choice(n, size=lens[i], replace=False))
+        rows.append(np.full(lens[i], i))
+        cols.append(c)
+        vals.append(rng.standard_normal(lens[i]) / np.sqrt(max(lens[i], 1)))
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    A = A + sp.eye(n) * 3.0
+    A = A.tocsr()
+    A.sort_indices()
+    return CSR(n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
+
+
+def _cases():
+    return {
+        "cfg1_convdiff2d_50": (convdiff2d(50, 1.0), 10),
+        "convdiff3d_20": (convdiff3d(20, 10, 10, 10), 12),
+        "randsparse_20000": (randsparse(20000, 16, seed=7), 15),
+        "ragged_5000": (_ragged_csr(), 8),
+    }
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_chains_fp64_match_oracle(pp, name):
+    csr, d = _cases()[name]
+    A = csr.to_scipy()
+    P = oroots.setup(A, start_vector(csr.n, 2), d)
+    say("chains fp64", name, "n", csr.n, "nnz", csr.nnz, "d_eff", P.d_eff)
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.poly_from_roots(P.roots(), keep_order=True)
+    assert poly.d_eff == P.d_eff
+    v = rhs(csr.n, 5)
+    vd = dev(v)
+    for kind, fn in [("p", chains.apply_p), ("phi", chains.apply_phi), ("pi", chains.apply_pi)]:
+        got = host(pp.apply(poly, M, vd, kind))
+        ref = fn(A, P.units, v)
+        assert relerr(got, ref) <= 1e-12, (kind, relerr(got, ref))
+
+
+def test_chain_with_complex_pairs_and_added_roots(pp):
+    # a polynomial whose list has pairs, copies and a real last unit
+    csr = convdiff2d(40, 30.0)
+    A = csr.to_scipy()
+    th = np.array([7.5, 0.2, 3 + 1j, 3 - 1j, 5 + 0.5j, 5 - 0.5j, 1.0, 0.05])
+    P = oroots.poly_from_roots(th, add_roots=True)
+    assert P.n_added > 0
+    say("chains pairs+added", "d_eff", P.d_eff)
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.poly_from_roots(th, add_roots=True)
+    assert np.array_equal(poly.roots(), P.roots())
+    v = rhs(csr.n, 6)
+    for kind, fn in [("p", chains.apply_p), ("phi", chains.apply_phi)]:
+        got = host(pp.apply(poly, M, dev(v), kind))
+        assert relerr(got, fn(A, P.units, v)) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["cfg1_convdiff2d_50", "convdiff3d_20", "randsparse_20000"])
+def test_chains_fp32_bf16_within_emulated_bound(pp, name):
+    csr, d = _cases()[name]
+    A = csr.to_scipy()
+    A32 = A.astype(np.float32)
+    P = oroots.setup(A, start_vector(csr.n, 2), d)
+    say("chains fp32/bf16", name)
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.poly_from_roots(P.roots(), keep_order=True)
+    v = rhs(csr.n, 5)
+    for kind, f64, flow in [("p", chains.apply_p, apply_p_low), ("phi", chains.apply_phi, apply_phi_low)]:
+        ref = f64(A, P.units, v)
+        for prec, dt in [("fp32", torch.float32), ("bf16", torch.bfloat16)]:
+            vin = dev(v, dt)
+            got = host(pp.apply(poly, M, vin, kind))
+            vq = host(vin)  # the stored input
+            delta = relerr(flow(A32, P.units, vq, prec), ref)
+            err = relerr(got, ref)
+            # same magnitude as the emulated chain (different summation order)
+            assert err <= 10 * delta + 1e-6, (kind, prec, err, delta)
+
+
+def test_chain_deterministic(pp):
+    csr = convdiff3d(24, 10, 10, 10)
+    P = oroots.setup(csr.to_scipy(), start_vector(csr.n, 2), 10)
+    say("determinism")
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.poly_from_roots(P.roots(), keep_order=True)
+    v = dev(rhs(csr.n, 1), torch.float32)
+    a = pp.apply(poly, M, v, "p").clone()
+    b = pp.apply(poly, M, v, "p").clone()
+    assert torch.equal(a, b)
+
+
+def test_cfg2_full_size_p_chain(pp):
+    # the benchmark workload at its real size: 128^3 grid, n = 2,097,152
+    csr = convdiff3d(128, 10, 10, 10)
+    A = csr.to_scipy()
+    th = np.array([11.5, 0.3, 6 + 2j, 6 - 2j, 2.0, 9.0, 4.0 + 0.5j, 4.0 - 0.5j, 0.9, 7.2])
+    P = oroots.poly_from_roots(th)
+    say("cfg2 full size p chain", csr.n, csr.nnz)
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.poly_from_roots(P.roots(), keep_order=True)
+    v = rhs(csr.n, 1)
+    ref = chains.apply_p(A, P.units, v)
+    got64 = host(pp.apply(poly, M, dev(v), "p"))
+    assert relerr(got64, ref) <= 1e-12
+    got32 = host(pp.apply(poly, M, dev(v, torch.float32), "p"))
+    assert relerr(got32, ref) <= 1e-5
+
+
+def test_bad_arguments_rejected(pp):
+    csr = convdiff2d(10)
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.poly_from_roots([2.0, 5.0])
+    v = dev(np.ones(csr.n))
+    with pytest.raises(Exception):
+        pp.apply(poly, M, v, "p", out=v)  # aliasing
+    with pytest.raises(Exception):
+        pp.Matrix(np.array([0, 1, 2], dtype=np.int32), np.array([0, 5], dtype=np.int32), np.ones(2))  # col >= n
+    with pytest.raises(Exception):
+        pp.Matrix(np.array([0, 2, 1], dtype=np.int32), np.array([0, 1], dtype=np.int32), np.ones(2))  # rowptr
