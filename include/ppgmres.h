@@ -188,7 +188,7 @@ pp_status pp_apply(pp_poly p, pp_matrix A, int kind, int prec, const void *v, vo
 /* Solve A x = b by PP(d)-GMRES(m) (Algorithm 4 step 2), x_0 = 0.
  * Each cycle starts from the true residual r = b - A x computed in FP64;
  * the cycle runs GMRES(m) on phi(A) in opts->inner precision and adds
- * ||r|| * p(A)(V z) to x in FP64 (iterative refinement when inner is not
+ * p(A)(V z) to x in FP64 (z minimises ||r|| e_1 - Hbar z) (iterative refinement when inner is not
  * FP64). A mixed cycle that fails to halve ||r|| is followed by an FP64 one.
  *   b, x : device double[n]; x is overwritten.
  * Returns PP_OK or PP_NOCONV (x is then the last iterate); info may be NULL. */

@@ -99,13 +99,14 @@ class Matrix:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            try:
-                torch.cuda.synchronize(self.device)
-            except Exception:
-                pass
+        if h is None or not h.value or lib is None:
+            return
+        try:
+            torch.cuda.synchronize(self.device)
             lib.pp_matrix_destroy(h)
-            self.handle = None
+        except Exception:  # interpreter shutdown
+            pass
+        self.handle = None
 
 
 @dataclass
@@ -146,9 +147,13 @@ class Poly:
         return out
 
     def __del__(self):
-        if self.handle is not None and self.handle.value:
+        if self.handle is None or not self.handle.value or lib is None:
+            return
+        try:
             lib.pp_poly_destroy(self.handle)
-            self.handle = None
+        except Exception:  # interpreter shutdown
+            pass
+        self.handle = None
 
 
 def _poly_from_handle(h, setup_info=None, breakdown=False) -> Poly:

@@ -636,10 +636,11 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
             // stage through pinned memory (the stream is idle here: cgs2_step synchronised)
             std::memcpy(A->hpin + A->ldp, zh.data(), sizeof(double) * k);
             HIP_TRY(hipMemcpyAsync(A->z(), A->hpin + A->ldp, sizeof(double) * k, hipMemcpyHostToDevice, st));
-            // dy = V_k z ; dx = p(A) dy ; x += beta dx
+            // dy = V_k z (z solves min ||beta e1 - Hbar z||, so it carries beta);
+            // dx = p(A) dy ; x += dx in FP64
             HIP_TRY(launch_combine(prec, n, ws.V, ws.ldv, k, A->z(), ws.D, st));
             PP_TRY(run_program(A, p->prog_p, prec, ws.D, ws.ACC, st));
-            HIP_TRY(launch_axpy_x(prec, n, beta, ws.ACC, x, st));
+            HIP_TRY(launch_axpy_x(prec, n, 1.0, ws.ACC, x, st));
             inf.mvps += mv_p;
             inf.vops += k + (int64_t)p->prog_p.size() * 2 + 1;
         }
