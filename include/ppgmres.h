@@ -115,6 +115,22 @@ pp_status pp_matrix_set_values(pp_matrix A, const double *val, void *stream);
 /* Release the handle and its scratch memory (not the caller's arrays). */
 void pp_matrix_destroy(pp_matrix A);
 
+/* Autotune the chain-step kernel for this matrix and precision: every
+ * variant (row tiles with LDS row sums, or LPR lanes per row with U rows in
+ * flight, each with and without the XCD-aware workgroup order) is timed on
+ * one sparse product and the fastest is kept in the handle. Runs by itself
+ * before a precision's first chain; variant/remap/us_per_launch (host, may
+ * be NULL) receive the choice and its time per launch in microseconds. */
+pp_status pp_matrix_tune(pp_matrix A, int prec, void *stream, int *variant, int *remap,
+                         double *us_per_launch);
+
+/* Force a chain-step variant (0 <= variant < 20, remap 0/1; 15 = persistent) for a precision
+ * instead of tuning, e.g. to test every variant. */
+pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap);
+
+/* Name of a chain-step variant ("tile8x1", "vec8x4", ...). */
+const char *pp_chain_variant_name(int variant);
+
 /* Transposed pattern of A for the adjoint solve (p(A)^T = p(A^T)).
  * Outputs (device, caller-allocated): rowptr_t int32[n+1], colind_t
  * int32[nnz], perm int32[nnz] with val_t[k] = val[perm[k]]. Entries of a

@@ -25,6 +25,13 @@ def version() -> str:
     return lib.pp_version().decode()
 
 
+N_CHAIN_VARIANTS = 20
+
+
+def chain_variant_name(v: int) -> str:
+    return lib.pp_chain_variant_name(int(v)).decode()
+
+
 def _stream(device=None):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -71,6 +78,17 @@ class Matrix:
         check(lib.pp_matrix_set_values(self.handle, _ptr(val), _stream(self.device)), "pp_matrix_set_values")
         self.val = val
         self._t = None
+
+    def tune(self, prec: str = "fp32"):
+        """Autotune the chain kernel for one precision; returns (variant name, remap, us per launch)."""
+        v, r, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        check(lib.pp_matrix_tune(self.handle, PREC[prec], _stream(self.device), ctypes.byref(v), ctypes.byref(r),
+                                 ctypes.byref(us)), "pp_matrix_tune")
+        return lib.pp_chain_variant_name(v.value).decode(), r.value, us.value
+
+    def set_variant(self, prec: str, variant: int, remap: int = 1):
+        """Force chain variant `variant` (0..19; 15 = persistent cooperative kernel) for a precision."""
+        check(lib.pp_matrix_set_variant(self.handle, PREC[prec], int(variant), int(remap)), "pp_matrix_set_variant")
 
     def transpose_pattern(self):
         """(rowptr_t, colind_t, perm) of A^T with val_t = val[perm]."""

@@ -8,8 +8,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/ppgmres.h"
@@ -82,19 +84,41 @@ struct pp_matrix_s {
     const int32_t *rowptr = nullptr, *colind = nullptr;
     const double *val = nullptr;
     float *val32 = nullptr;
-    int32_t *tiles = nullptr;
-    int ntiles = 0;
-    int xcd_remap = 1;
+    int4 *tile8 = nullptr, *tile16 = nullptr, *tileP = nullptr;
+    int ntile8 = 0, ntile16 = 0, ntileP = 0;
+    int4 *tileB8[3] = {nullptr, nullptr, nullptr}, *tileB16[3] = {nullptr, nullptr, nullptr};
+    // sliced-ELL copy
+    int32_t *sptr = nullptr, *scol = nullptr, *sperm = nullptr;
+    double *sval64 = nullptr;
+    float *sval32 = nullptr;
+    int nslices = 0;
+    long npad = 0;
+    int ntileB8[3] = {0, 0, 0}, ntileB16[3] = {0, 0, 0};
+    int variant[3] = {CV_TILE8, CV_TILE8, CV_TILE8};  // single-launch variant
+    int remap[3] = {1, 1, 1};
+    int persist[3] = {0, 0, 0};     // chains of >= 2 steps in one cooperative launch
+    int premap[3] = {1, 1, 1};
+    int tuned[3] = {0, 0, 0};
+    double tuned_us[3] = {0, 0, 0};
+    // persistent kernel state
+    int pgrid = 0;
+    int tune_persist = 0;
+    unsigned long long *bar = nullptr;  // barrier counter (device)
+    unsigned long long bar_host = 0;    // its value after the last launch
+    int *err = nullptr;                 // barrier timeout flag (device)
+    int *errpin = nullptr;              // pinned mirror
+    PStep *tune_steps = nullptr;        // 8 alternating sparse products
+    std::map<std::pair<unsigned long long, int>, PStep *> progs;  // (poly id, kind) -> device table
     std::vector<int32_t> h_rowptr;
     Workspace ws[3];
     // reductions and FP64 vectors
     int ldp = 0;
-    double *partial = nullptr;  // dot_blocks(n) x ldp
+    double *partial = nullptr;  // max(dot_blocks, update_dots_blocks) x ldp
     double *npart = nullptr;    // ceil(n/256)
     double *small = nullptr;    // h1 | h2 | H | inv | z   (5 * ldp)
     double *hpin = nullptr;     // pinned host mirror (2 * ldp)
     double *r64 = nullptr, *t64 = nullptr;
-    int nblk_dot = 0, nblk_upd = 0;
+    int nblk_dot = 0, nblk_upd = 0, nblk_ud = 0;
 
     DevCSR dev() const {
         DevCSR d;
@@ -104,9 +128,27 @@ struct pp_matrix_s {
         d.colind = colind;
         d.val64 = val;
         d.val32 = val32;
-        d.tiles = tiles;
-        d.ntiles = ntiles;
-        d.xcd_remap = xcd_remap;
+        d.tile8 = tile8;
+        d.ntile8 = ntile8;
+        d.tile16 = tile16;
+        d.ntile16 = ntile16;
+        d.tileP = tileP;
+        d.ntileP = ntileP;
+        d.sptr = sptr;
+        d.scol = scol;
+        d.sval64 = sval64;
+        d.sval32 = sval32;
+        d.nslices = nslices;
+        for (int p = 0; p < 3; ++p) {
+            d.tileB8[p] = tileB8[p];
+            d.ntileB8[p] = ntileB8[p];
+            d.tileB16[p] = tileB16[p];
+            d.ntileB16[p] = ntileB16[p];
+        }
+        for (int p = 0; p < 3; ++p) {
+            d.variant[p] = variant[p];
+            d.remap[p] = remap[p];
+        }
         return d;
     }
     double *h1() { return small; }
@@ -131,7 +173,7 @@ struct pp_matrix_s {
         if (hpin) (void)hipHostFree(hpin);
         hpin = nullptr;
         ldp = 0;
-        PP_TRY(dev_alloc(&partial, (size_t)nblk_dot * want));
+        PP_TRY(dev_alloc(&partial, (size_t)std::max(nblk_dot, nblk_ud) * want));
         PP_TRY(dev_alloc(&small, (size_t)5 * want));
         if (hipHostMalloc((void **)&hpin, sizeof(double) * 2 * want, hipHostMallocDefault) != hipSuccess) {
             hpin = nullptr;
@@ -167,7 +209,23 @@ struct pp_matrix_s {
     ~pp_matrix_s() {
         for (auto &w : ws) release_ws(w);
         dev_free(val32);
-        dev_free(tiles);
+        dev_free(tile8);
+        dev_free(tile16);
+        dev_free(tileP);
+        dev_free(sptr);
+        dev_free(scol);
+        dev_free(sperm);
+        dev_free(sval64);
+        dev_free(sval32);
+        for (int p = 0; p < 3; ++p) {
+            dev_free(tileB8[p]);
+            dev_free(tileB16[p]);
+        }
+        dev_free(bar);
+        dev_free(err);
+        dev_free(tune_steps);
+        for (auto &kv : progs) dev_free(kv.second);
+        if (errpin) (void)hipHostFree(errpin);
         dev_free(partial);
         dev_free(npart);
         dev_free(small);
@@ -197,8 +255,183 @@ void *buf_ptr(int b, const void *in, void *out, const Workspace &w) {
     }
 }
 
-pp_status run_program(pp_matrix A, const std::vector<Step> &prog, int prec, const void *in, void *out,
-                      hipStream_t st) {
+pp_status check_barrier_flag(pp_matrix A) {
+    if (A->errpin && *A->errpin) {
+        set_error("persistent chain: grid barrier timed out");
+        return PP_EDEVICE;
+    }
+    return PP_OK;
+}
+
+PStep to_pstep(const Step &s) {
+    PStep p;
+    p.spmv = s.spmv;
+    p.in = s.in;
+    p.aux = s.aux;
+    p.out = s.out;
+    p.acc = s.acc;
+    p.acc_init = s.acc_init;
+    p.fin = s.fin;
+    p.pad = 0;
+    p.a0 = s.a0;
+    p.a1 = s.a1;
+    p.a2 = s.a2;
+    p.b0 = s.b0;
+    p.b1 = s.b1;
+    return p;
+}
+
+pp_status upload_steps(const std::vector<PStep> &h, PStep **out, hipStream_t st) {
+    PP_TRY(dev_alloc(out, h.size()));
+    HIP_TRY(hipMemcpyAsync(*out, h.data(), sizeof(PStep) * h.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return PP_OK;
+}
+
+pp_status launch_persist(pp_matrix A, int prec, const PStep *steps, int nsteps, const void *in, void *out, int remap,
+                         hipStream_t st) {
+    const Workspace &w = A->ws[prec];
+    void *bufs[5] = {(void *)in, out, w.P0, w.P1, w.T};
+    HIP_TRY(launch_chain_persist(A->dev(), prec, bufs, steps, nsteps, A->bar, A->bar_host, A->err, A->pgrid, remap,
+                                 st));
+    A->bar_host += (unsigned long long)(nsteps - 1) * (unsigned long long)A->pgrid;
+    return PP_OK;
+}
+
+// Autotuner: per sparse product, time every single-launch chain variant
+// (with and without the XCD-aware workgroup order) on 5 back-to-back
+// launches, and the persistent kernel on an 8-step program; keep the
+// fastest single-launch variant and use the persistent kernel for chains
+// if it beats it.
+// Tile plan with a whole number of occupancy rounds of equal tiles: every
+// co-resident workgroup slot gets the same number of tiles of the same
+// size, so the last round is not a partial one.
+pp_status build_round_plan(pp_matrix A, int prec, int ept, int4 **dst, int *ndst, hipStream_t st) {
+    if (*dst) return PP_OK;
+    int slots = 0;
+    HIP_TRY(tile_slots(prec, ept, &slots));
+    if (slots <= 0) return PP_OK;
+    const long cap_max = 256L * ept - 4, rows_max = 256L * (ept / 8);
+    const long rounds = std::max<long>(1, ((long)A->nnz + slots * cap_max - 1) / (slots * cap_max));
+    const long cap = std::max<long>(1, ((long)A->nnz + slots * rounds - 1) / (slots * rounds));
+    std::vector<int4> t;
+    build_tiles(A->h_rowptr.data(), A->n, (int)rows_max, (int)std::min(cap, cap_max), t);
+    PP_TRY(dev_alloc(dst, t.size()));
+    HIP_TRY(hipMemcpyAsync(*dst, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *ndst = (int)t.size();
+    return PP_OK;
+}
+
+pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
+    PP_TRY(A->ensure_ws(prec, 0));
+    PP_TRY(build_round_plan(A, prec, 8, &A->tileB8[prec], &A->ntileB8[prec], st));
+    PP_TRY(build_round_plan(A, prec, 16, &A->tileB16[prec], &A->ntileB16[prec], st));
+    const Workspace &w = A->ws[prec];
+    HIP_TRY(hipMemsetAsync(w.P0, 0, (size_t)w.ldv * elem_size(prec), st));
+    HIP_TRY(hipMemsetAsync(w.P1, 0, (size_t)w.ldv * elem_size(prec), st));
+    StepPtrs p;
+    std::memset(&p, 0, sizeof(p));
+    p.in = w.P0;
+    p.out = w.P1;
+    p.spmv = 1;
+    p.a0 = 1.0;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    double best = 1e30;
+    int bv = CV_TILE8, br = 1;
+    const int reps = 5;
+    for (int v = 0; v < CV_COUNT; ++v) {
+        if (v == CV_PERSIST || ((v == CV_SELL || v == CV_SELLT) && A->nslices == 0) || (v == CV_TILEB8 && A->ntileB8[prec] == 0) ||
+            (v == CV_TILEB16 && A->ntileB16[prec] == 0))
+            continue;
+        for (int r = 0; r < 2; ++r) {
+            A->variant[prec] = v;
+            A->remap[prec] = r;
+            const DevCSR d = A->dev();
+            for (int i = 0; i < 2; ++i) HIP_TRY(launch_chain_step(d, prec, p, st));
+            HIP_TRY(hipEventRecord(e0, st));
+            for (int i = 0; i < reps; ++i) HIP_TRY(launch_chain_step(d, prec, p, st));
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1e3 * ms / reps;
+            if (us < best) {
+                best = us;
+                bv = v;
+                br = r;
+            }
+        }
+    }
+    A->variant[prec] = bv;
+    A->remap[prec] = br;
+    A->persist[prec] = 0;
+    double best_all = best;
+    // The persistent kernel is only timed on request: its grid barrier must
+    // write back and invalidate the per-XCD L2 caches, which costs far more
+    // than a kernel boundary on this GPU.
+    if (A->pgrid > 0 && A->tune_persist) {
+        for (int r = 0; r < 2; ++r) {
+            PP_TRY(launch_persist(A, prec, A->tune_steps, 8, w.P0, w.P1, r, st));
+            HIP_TRY(hipEventRecord(e0, st));
+            for (int i = 0; i < 2; ++i) PP_TRY(launch_persist(A, prec, A->tune_steps, 8, w.P0, w.P1, r, st));
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            HIP_TRY(hipMemcpyAsync(A->errpin, A->err, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            PP_TRY(check_barrier_flag(A));
+            const double us = 1e3 * ms / (2 * 8);
+            if (us < best_all) {
+                best_all = us;
+                A->persist[prec] = 1;
+                A->premap[prec] = r;
+            }
+        }
+    }
+    A->tuned[prec] = 1;
+    A->tuned_us[prec] = best_all;
+    return PP_OK;
+}
+
+pp_status ensure_tuned(pp_matrix A, int prec, hipStream_t st) {
+    if (A->tuned[prec]) return PP_OK;
+    return tune_chain(A, prec, st);
+}
+
+const std::vector<Step> &prog_of(pp_poly p, int kind) {
+    return kind == PP_APPLY_P ? p->prog_p : (kind == PP_APPLY_PHI ? p->prog_phi : p->prog_pi);
+}
+
+// Evaluate a chain program: one cooperative launch (persistent kernel) or
+// one launch per step, as tuned for this matrix and precision.
+pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void *in, void *out, hipStream_t st) {
+    PP_TRY(ensure_tuned(A, prec, st));
+    const std::vector<Step> &prog = prog_of(poly, kind);
+    if (A->persist[prec] && prog.size() >= 2) {
+        const auto key = std::make_pair((unsigned long long)poly->id, kind);
+        auto it = A->progs.find(key);
+        PStep *table = nullptr;
+        if (it == A->progs.end()) {
+            std::vector<PStep> h;
+            for (const Step &s : prog) h.push_back(to_pstep(s));
+            PP_TRY(upload_steps(h, &table, st));
+            A->progs[key] = table;
+        } else {
+            table = it->second;
+        }
+        return launch_persist(A, prec, table, (int)prog.size(), in, out, A->premap[prec], st);
+    }
     const Workspace &w = A->ws[prec];
     const DevCSR d = A->dev();
     for (const Step &s : prog) {
@@ -223,6 +456,7 @@ pp_status run_program(pp_matrix A, const std::vector<Step> &prog, int prec, cons
 // One step of the SpMV alone: out = a0 * A in + a2 * aux
 pp_status spmv_axpby(pp_matrix A, int prec, const void *in, double a0, const void *aux, double a2, void *out,
                      hipStream_t st) {
+    PP_TRY(ensure_tuned(A, prec, st));
     StepPtrs p;
     p.in = in;
     p.aux = aux;
@@ -246,17 +480,26 @@ pp_status cgs2_step(pp_matrix A, int prec, const Workspace &ws, int j, hipStream
     const int n = A->n;
     const int ncols = j + 1;
     void *w = vcol(ws, prec, j + 1);
+    // pass 1: h1 = V^T w
     HIP_TRY(launch_dots(prec, n, ws.V, ws.ldv, ncols, w, A->partial, A->ldp, st));
     HIP_TRY(launch_reduce(A->nblk_dot, A->partial, A->ldp, ncols, A->h1(), A->H(), 1, st));
-    HIP_TRY(launch_update(prec, n, ws.V, ws.ldv, ncols, A->h1(), w, nullptr, st));
-    HIP_TRY(launch_dots(prec, n, ws.V, ws.ldv, ncols, w, A->partial, A->ldp, st));
-    HIP_TRY(launch_reduce(A->nblk_dot, A->partial, A->ldp, ncols, A->h2(), A->H(), 2, st));
+    // w -= V h1 ; h2 = V^T w  (fused into one read of V when the row fits in registers)
+    if (ncols <= update_dots_max_cols(prec)) {
+        HIP_TRY(launch_update_dots(prec, n, ws.V, ws.ldv, ncols, A->h1(), w, A->partial, A->ldp, st));
+        HIP_TRY(launch_reduce(A->nblk_ud, A->partial, A->ldp, ncols, A->h2(), A->H(), 2, st));
+    } else {
+        HIP_TRY(launch_update(prec, n, ws.V, ws.ldv, ncols, A->h1(), w, nullptr, st));
+        HIP_TRY(launch_dots(prec, n, ws.V, ws.ldv, ncols, w, A->partial, A->ldp, st));
+        HIP_TRY(launch_reduce(A->nblk_dot, A->partial, A->ldp, ncols, A->h2(), A->H(), 2, st));
+    }
+    // w -= V h2 ; ||w||
     HIP_TRY(launch_update(prec, n, ws.V, ws.ldv, ncols, A->h2(), w, A->npart, st));
     HIP_TRY(launch_reduce_norm(A->nblk_upd, A->npart, A->H() + ncols, A->inv(), st));
     HIP_TRY(launch_scale_cast(prec, prec, n, w, A->inv(), 0.0, w, st));
     HIP_TRY(hipMemcpyAsync(A->hpin, A->H(), sizeof(double) * (ncols + 1), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(A->errpin, A->err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    return PP_OK;
+    return check_barrier_flag(A);
 }
 
 // ||x|| of a device vector (synchronises); x is not modified.
@@ -264,9 +507,10 @@ pp_status dev_norm(pp_matrix A, int prec, const void *x, double *out, hipStream_
     HIP_TRY(launch_dots(prec, A->n, x, 0, 1, x, A->partial, A->ldp, st));
     HIP_TRY(launch_reduce(A->nblk_dot, A->partial, A->ldp, 1, A->h1(), nullptr, 0, st));
     HIP_TRY(hipMemcpyAsync(A->hpin, A->h1(), sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(A->errpin, A->err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     *out = std::sqrt(A->hpin[0]);
-    return PP_OK;
+    return check_barrier_flag(A);
 }
 
 bool valid_prec(int p) { return p >= 0 && p <= 2; }
@@ -310,8 +554,8 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
             set_error("pp_matrix_create: rowptr not non-decreasing");
             return fail(PP_EINVAL);
         }
+    std::vector<int32_t> ci(nnz);
     if (nnz > 0) {
-        std::vector<int32_t> ci(nnz);
         if (hipMemcpyAsync(ci.data(), colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
             set_error("pp_matrix_create: cannot read colind");
@@ -323,37 +567,122 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
                 return fail(PP_EINVAL);
             }
     }
-    // row tiles: <= kTileNnz stored entries and <= kTileRowsMax rows, or one long row
-    std::vector<int32_t> tiles;
-    tiles.push_back(0);
-    int r = 0;
-    while (r < n) {
-        const int start = r;
-        long nz = 0;
-        while (r < n && r - start < kTileRowsMax) {
-            const long rn = rp[r + 1] - rp[r];
-            if (r > start && nz + rn > kTileNnz) break;
-            nz += rn;
-            ++r;
-            if (rn > kTileNnz) break;
+    // row-tile plans of the two tile variants
+    std::vector<int4> t8, t16;
+    // capacities leave room for the 16-byte alignment of the vector-load variants
+    build_tiles(rp.data(), (int)n, 256, 256 * 8 - 4, t8);
+    build_tiles(rp.data(), (int)n, 512, 256 * 16 - 4, t16);
+    A->ntile8 = (int)t8.size();
+    A->ntile16 = (int)t16.size();
+    // persistent kernel: the largest co-resident grid over the three
+    // precisions, and a tile plan balanced so that every workgroup owns about
+    // the same number of stored entries
+    {
+        int g0 = 0, g1 = 0, g2 = 0;
+        if (persist_max_grid(0, &g0) != hipSuccess || persist_max_grid(1, &g1) != hipSuccess ||
+            persist_max_grid(2, &g2) != hipSuccess) {
+            set_error("pp_matrix_create: occupancy query failed");
+            return fail(PP_EDEVICE);
         }
-        tiles.push_back(r);
+        A->pgrid = std::max(0, std::min(g0, std::min(g1, g2)));
     }
-    A->ntiles = (int)tiles.size() - 1;
+    std::vector<int4> tP;
+    if (A->pgrid > 0) {
+        const long G = A->pgrid;
+        const long per_wg = std::max<long>(1, (nnz + G - 1) / G);
+        const long k = std::max<long>(1, (per_wg + (256 * 8 - 4) - 1) / (256 * 8 - 4));
+        const long cap = std::max<long>(1, (per_wg + k - 1) / k);
+        build_tiles(rp.data(), (int)n, 256, (int)std::min<long>(cap, 256 * 8 - 4), tP);
+    }
+    A->ntileP = (int)tP.size();
     A->nblk_dot = dot_blocks(A->n);
     A->nblk_upd = (A->n + 255) / 256;
+    A->nblk_ud = update_dots_blocks(A->n);
     pp_status s;
-    if ((s = dev_alloc(&A->tiles, tiles.size())) != PP_OK) return fail(s);
+    if ((s = dev_alloc(&A->tile8, t8.size())) != PP_OK) return fail(s);
+    if ((s = dev_alloc(&A->tile16, t16.size())) != PP_OK) return fail(s);
+    if (!tP.empty() && (s = dev_alloc(&A->tileP, tP.size())) != PP_OK) return fail(s);
+    if ((s = dev_alloc(&A->bar, 1)) != PP_OK) return fail(s);
+    if ((s = dev_alloc(&A->err, 1)) != PP_OK) return fail(s);
+    if (hipHostMalloc((void **)&A->errpin, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        A->errpin = nullptr;
+        set_error("hipHostMalloc failed");
+        return fail(PP_ENOMEM);
+    }
+    *A->errpin = 0;
     if ((s = dev_alloc(&A->val32, (size_t)std::max<int64_t>(nnz, 1))) != PP_OK) return fail(s);
     if ((s = dev_alloc(&A->npart, (size_t)A->nblk_upd)) != PP_OK) return fail(s);
     if ((s = dev_alloc(&A->r64, (size_t)2 * A->n)) != PP_OK) return fail(s);
     A->t64 = A->r64 + A->n;
     if ((s = A->ensure_red(64)) != PP_OK) return fail(s);
-    if (hipMemcpyAsync(A->tiles, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice, st) !=
-            hipSuccess ||
+    if (hipMemcpyAsync(A->tile8, t8.data(), sizeof(int4) * t8.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(A->tile16, t16.data(), sizeof(int4) * t16.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        (!tP.empty() &&
+         hipMemcpyAsync(A->tileP, tP.data(), sizeof(int4) * tP.size(), hipMemcpyHostToDevice, st) != hipSuccess) ||
+        hipMemsetAsync(A->bar, 0, sizeof(unsigned long long), st) != hipSuccess ||
+        hipMemsetAsync(A->err, 0, sizeof(int), st) != hipSuccess ||
         launch_val_to_f32((int)nnz, val, A->val32, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
         set_error("pp_matrix_create: device upload failed");
         return fail(PP_EDEVICE);
+    }
+    // Sliced-ELL copy (64-row slices, entries of a slice stored column by
+    // column) when the padding stays below a quarter of the entries.
+    {
+        const int ns = (int)((n + 63) / 64);
+        std::vector<int32_t> sp(ns + 1, 0);
+        long tot = 0;
+        for (int w = 0; w < ns; ++w) {
+            int width = 0;
+            for (int r = w * 64; r < std::min<int64_t>((int64_t)w * 64 + 64, n); ++r) width = std::max(width, rp[r + 1] - rp[r]);
+            tot += 64L * width;
+            sp[w + 1] = (int32_t)std::min<long>(tot, (1L << 31) - 1);
+        }
+        if (nnz > 0 && tot <= nnz + nnz / 4 + 64L * 8 && tot < (1L << 31)) {
+            std::vector<int32_t> scol(tot, 0), sperm(tot, -1);
+            for (int w = 0; w < ns; ++w) {
+                const int width = (sp[w + 1] - sp[w]) / 64;
+                for (int j = 0; j < 64; ++j) {
+                    const long r = (long)w * 64 + j;
+                    const int len = r < n ? rp[r + 1] - rp[r] : 0;
+                    for (int k = 0; k < width; ++k) {
+                        const long o = sp[w] + (long)k * 64 + j;
+                        if (k < len) {
+                            scol[o] = ci[rp[r] + k];
+                            sperm[o] = rp[r] + k;
+                        } else {
+                            scol[o] = r < n ? (int32_t)r : 0;  // padding: a valid index with value 0
+                        }
+                    }
+                }
+            }
+            if ((s = dev_alloc(&A->sptr, sp.size())) != PP_OK || (s = dev_alloc(&A->scol, (size_t)tot)) != PP_OK ||
+                (s = dev_alloc(&A->sperm, (size_t)tot)) != PP_OK || (s = dev_alloc(&A->sval64, (size_t)tot)) != PP_OK ||
+                (s = dev_alloc(&A->sval32, (size_t)tot)) != PP_OK)
+                return fail(s);
+            if (hipMemcpyAsync(A->sptr, sp.data(), sizeof(int32_t) * sp.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(A->scol, scol.data(), sizeof(int32_t) * tot, hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(A->sperm, sperm.data(), sizeof(int32_t) * tot, hipMemcpyHostToDevice, st) != hipSuccess ||
+                launch_sell_values(tot, A->sperm, val, A->sval64, A->sval32, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                set_error("pp_matrix_create: sliced-ELL upload failed");
+                return fail(PP_EDEVICE);
+            }
+            A->nslices = ns;
+            A->npad = tot;
+        }
+    }
+    {
+        // tuning program of the persistent kernel: 8 sparse products P0 -> P1 -> P0 ...
+        std::vector<PStep> h(8);
+        for (int i = 0; i < 8; ++i) {
+            std::memset(&h[i], 0, sizeof(PStep));
+            h[i].spmv = 1;
+            h[i].in = (i % 2 == 0) ? B_P0 : B_P1;
+            h[i].out = (i % 2 == 0) ? B_P1 : B_P0;
+            h[i].aux = h[i].acc = -1;
+            h[i].a0 = 1.0;
+        }
+        if ((s = upload_steps(h, &A->tune_steps, st)) != PP_OK) return fail(s);
     }
     *out = A;
     return PP_OK;
@@ -366,10 +695,52 @@ pp_status pp_matrix_set_values(pp_matrix A, const double *val, void *stream) {
     }
     A->val = val;
     HIP_TRY(launch_val_to_f32(A->nnz, val, A->val32, S(stream)));
+    if (A->nslices > 0) HIP_TRY(launch_sell_values(A->npad, A->sperm, val, A->sval64, A->sval32, S(stream)));
     return PP_OK;
 }
 
 void pp_matrix_destroy(pp_matrix A) { delete A; }
+
+pp_status pp_matrix_tune(pp_matrix A, int prec, void *stream, int *variant, int *remap, double *us_per_launch) {
+    if (!A || !valid_prec(prec)) {
+        set_error("pp_matrix_tune: bad argument");
+        return PP_EINVAL;
+    }
+    PP_TRY(tune_chain(A, prec, S(stream)));
+    if (variant) *variant = A->persist[prec] ? (int)CV_PERSIST : A->variant[prec];
+    if (remap) *remap = A->persist[prec] ? A->premap[prec] : A->remap[prec];
+    if (us_per_launch) *us_per_launch = A->tuned_us[prec];
+    return PP_OK;
+}
+
+pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
+    if (!A || !valid_prec(prec) || variant < 0 || variant >= CV_COUNT || (remap != 0 && remap != 1)) {
+        set_error("pp_matrix_set_variant: bad argument");
+        return PP_EINVAL;
+    }
+    if (variant == CV_PERSIST) {
+        if (A->pgrid <= 0) {
+            set_error("pp_matrix_set_variant: persistent kernel unavailable");
+            return PP_EINVAL;
+        }
+        A->persist[prec] = 1;
+        A->premap[prec] = remap;
+    } else {
+        if ((variant == CV_SELL || variant == CV_SELLT) && A->nslices == 0) {
+            set_error("pp_matrix_set_variant: no sliced-ELL copy for this matrix (too much padding)");
+            return PP_EINVAL;
+        }
+        if (variant == CV_TILEB8) PP_TRY(build_round_plan(A, prec, 8, &A->tileB8[prec], &A->ntileB8[prec], 0));
+        if (variant == CV_TILEB16) PP_TRY(build_round_plan(A, prec, 16, &A->tileB16[prec], &A->ntileB16[prec], 0));
+        A->persist[prec] = 0;
+        A->variant[prec] = variant;
+        A->remap[prec] = remap;
+    }
+    A->tuned[prec] = 1;
+    return PP_OK;
+}
+
+const char *pp_chain_variant_name(int variant) { return chain_variant_name(variant); }
 
 pp_status pp_matrix_transpose(pp_matrix A, int32_t *rowptr_t, int32_t *colind_t, int32_t *perm, void *stream) {
     if (!A || !rowptr_t || (A->nnz > 0 && (!colind_t || !perm))) {
@@ -507,8 +878,7 @@ pp_status pp_apply(pp_poly p, pp_matrix A, int kind, int prec, const void *v, vo
         return PP_EINVAL;
     }
     PP_TRY(A->ensure_ws(prec, 0));
-    const auto &prog = kind == PP_APPLY_P ? p->prog_p : (kind == PP_APPLY_PHI ? p->prog_phi : p->prog_pi);
-    return run_program(A, prog, prec, v, y, S(stream));
+    return run_program(A, p, kind, prec, v, y, S(stream));
 }
 
 pp_status pp_stability_check(pp_poly p, pp_matrix A, const double *b, void *stream, double *stch) {
@@ -520,9 +890,9 @@ pp_status pp_stability_check(pp_poly p, pp_matrix A, const double *b, void *stre
     PP_TRY(A->ensure_ws(0, 0));
     const Workspace &ws = A->ws[0];
     // r1 = b - A p(A) b  (into ws.ACC); r2 = pi(A) b (into r64); ||r1 - r2||
-    PP_TRY(run_program(A, p->prog_p, 0, b, ws.D, st));
+    PP_TRY(run_program(A, p, PP_APPLY_P, 0, b, ws.D, st));
     PP_TRY(spmv_axpby(A, 0, ws.D, -1.0, b, 1.0, ws.ACC, st));
-    PP_TRY(run_program(A, p->prog_pi, 0, b, A->r64, st));
+    PP_TRY(run_program(A, p, PP_APPLY_PI, 0, b, A->r64, st));
     HIP_TRY(hipStreamSynchronize(st));
     A->hpin[A->ldp] = 1.0;
     HIP_TRY(hipMemcpyAsync(A->h1(), A->hpin + A->ldp, sizeof(double), hipMemcpyHostToDevice, st));
@@ -609,7 +979,7 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
         double fro2 = 0.0;
         int k = 0;
         for (int j = 0; j < m; ++j) {
-            PP_TRY(run_program(A, p->prog_phi, prec, vcol(ws, prec, j), vcol(ws, prec, j + 1), st));
+            PP_TRY(run_program(A, p, PP_APPLY_PHI, prec, vcol(ws, prec, j), vcol(ws, prec, j + 1), st));
             PP_TRY(cgs2_step(A, prec, ws, j, st));
             inf.mvps += mv_phi;
             inf.dots += 2 * (j + 1) + 1;
@@ -639,7 +1009,7 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
             // dy = V_k z (z solves min ||beta e1 - Hbar z||, so it carries beta);
             // dx = p(A) dy ; x += dx in FP64
             HIP_TRY(launch_combine(prec, n, ws.V, ws.ldv, k, A->z(), ws.D, st));
-            PP_TRY(run_program(A, p->prog_p, prec, ws.D, ws.ACC, st));
+            PP_TRY(run_program(A, p, PP_APPLY_P, prec, ws.D, ws.ACC, st));
             HIP_TRY(launch_axpy_x(prec, n, 1.0, ws.ACC, x, st));
             inf.mvps += mv_p;
             inf.vops += k + (int64_t)p->prog_p.size() * 2 + 1;

@@ -8,13 +8,42 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace ppg {
 
-constexpr int kChainBlock = 256;     // threads per chain-step workgroup
-constexpr int kChainEpt = 8;         // stored entries per thread and tile
-constexpr int kTileNnz = kChainBlock * kChainEpt;
-constexpr int kTileRowsMax = 4 * kChainBlock;
+// chain-step kernel variants (the autotuner picks one per matrix and precision)
+enum ChainVariant : int {
+    CV_TILE8 = 0,   // tiles of <= 256 rows / 2048 entries, LDS row sums
+    CV_TILE16 = 1,  // tiles of <= 512 rows / 4096 entries
+    CV_VEC1x4 = 2,  // one lane per row, 4 rows per lane
+    CV_VEC4x4 = 3,  // 4 lanes per row, 4 rows in flight per lane group
+    CV_VEC8x2 = 4,
+    CV_VEC8x4 = 5,
+    CV_VEC16x2 = 6,
+    CV_VEC16x4 = 7,
+    CV_VEC32x2 = 8,
+    CV_TILEV8 = 9,    // tile8 plan, 16-byte non-temporal loads of the entry stream
+    CV_TILEV16 = 10,  // tile16 plan, same loads
+    CV_VK2x4x4 = 11,  // 2 lanes per row, 4 rows per group, 4 entries per lane per batch
+    CV_VK4x4x2 = 12,
+    CV_VK8x4x1 = 13,
+    CV_VK16x2x2 = 14,
+    CV_PERSIST = 15,  // one cooperative launch per chain, grid barrier between steps (opt-in)
+    CV_TILEB8 = 16,   // tile8 kernel on a plan of whole occupancy rounds of equal tiles
+    CV_TILEB16 = 17,  // tile16 kernel, same
+    CV_SELL = 18,     // sliced-ELL copy (64-row slices): one lane per row, coalesced gathers
+    CV_SELLT = 19,    // same with ordinary (cache-allocating) loads of the entry stream
+    CV_COUNT = 20
+};
+
+// A chain step as the persistent kernel reads it from device memory.
+// Buffers: 0 = input, 1 = output, 2/3 = ping-pong, 4 = temporary, -1 = none.
+struct PStep {
+    int spmv, in, aux, out, acc, acc_init, fin, pad;
+    double a0, a1, a2, b0, b1;
+};
+const char *chain_variant_name(int v);
 constexpr int kRedBlock = 256;       // threads per reduction workgroup
 constexpr int kDotRows = 2048;       // rows per dot-product workgroup
 constexpr int kDotCols = 8;          // Krylov columns per dot-product pass
@@ -39,10 +68,46 @@ struct DevCSR {
     const int32_t *colind;
     const double *val64;
     const float *val32;
-    const int32_t *tiles;  // row tile starts, ntiles + 1 entries
-    int ntiles;
-    int xcd_remap;         // 1: keep neighbouring tiles on one XCD
+    const int4 *tile8;   // {r0, r1, e0, e1} per tile of the CV_TILE8 plan
+    int ntile8;
+    const int4 *tile16;  // same for CV_TILE16
+    int ntile16;
+    const int4 *tileP;   // balanced plan of the persistent kernel
+    int ntileP;
+    const int4 *tileB8[3];  // per precision: plans of whole occupancy rounds
+    int ntileB8[3];
+    const int4 *tileB16[3];
+    int ntileB16[3];
+    // sliced-ELL copy (absent if nslices == 0): slice s holds rows
+    // [64 s, 64 s + 64) as width_s columns of 64 entries, offsets sptr[s]
+    const int32_t *sptr;
+    const int32_t *scol;
+    const double *sval64;
+    const float *sval32;
+    int nslices;
+    int variant[3];      // chain variant per precision
+    int remap[3];        // 1: keep neighbouring workgroups on one XCD
 };
+
+// All steps of a chain program in one cooperative launch of `grid`
+// workgroups (grid <= persist_max_grid). bar: monotonically growing barrier
+// counter whose value before the launch is bar_base; it grows by
+// (nsteps - 1) * grid. err: set to 1 if a barrier timed out.
+hipError_t launch_chain_persist(const DevCSR &A, int prec, void *const bufs[5], const PStep *steps, int nsteps,
+                                unsigned long long *bar, unsigned long long bar_base, int *err, int grid, int remap,
+                                hipStream_t st);
+// Largest co-resident grid of the persistent kernel.
+hipError_t persist_max_grid(int prec, int *grid);
+// Co-resident workgroups (whole GPU) of the tile kernels with EPT 8 or 16.
+hipError_t tile_slots(int prec, int ept, int *slots);
+
+// Sliced-ELL values from CSR values: sval[k] = sperm[k] >= 0 ? val[sperm[k]] : 0.
+hipError_t launch_sell_values(long npad, const int32_t *sperm, const double *val, double *sval64, float *sval32,
+                              hipStream_t st);
+
+// Tile plan on the host: tiles of <= row_cap rows and <= nnz_cap entries
+// (a longer row gets a tile of its own). Returns {r0, r1, e0, e1} per tile.
+void build_tiles(const int32_t *rowptr, int n, int row_cap, int nnz_cap, std::vector<int4> &out);
 
 size_t elem_size(int prec);
 
@@ -58,6 +123,12 @@ hipError_t launch_reduce(int nblk, const double *partial, int ldp, int ncols, do
 // w[i] -= sum_k V[i,k] h[k]; with norm_partial, also per-block sums of w^2.
 hipError_t launch_update(int prec, int n, const void *V, long ldv, int ncols, const double *h, void *w,
                          double *norm_partial, hipStream_t st);
+// Fused w -= V h and partial[b*ldp + k] = sum over block b of V[i,k] w[i]
+// (one read of V). Only for ncols <= update_dots_max_cols(prec).
+int update_dots_blocks(int n);
+int update_dots_max_cols(int prec);
+hipError_t launch_update_dots(int prec, int n, const void *V, long ldv, int ncols, const double *h, void *w,
+                              double *partial, int ldp, hipStream_t st);
 // norm = sqrt(sum_b partial[b]); writes H[0] = norm, inv[0] = 1/norm (0 if norm == 0).
 hipError_t launch_reduce_norm(int nblk, const double *partial, double *H, double *inv, hipStream_t st);
 // out[i] = (T_out)(in[i] * s) with s = scale[0] (device) or, if scale is null,

@@ -93,6 +93,20 @@ __device__ __forceinline__ int remap_tile(int b, int ntiles, int remap) {
 
 // ---------------------------------------------------------------------------
 // fused chain step
+//
+// Every launch computes, for each row r,
+//     w = a0 (A in)_r + a1 in_r + a2 aux_r
+//     acc_r = (acc_init ? 0 : acc_r) + b0 in_r + b1 w      (if acc)
+//     out_r = fin ? vfin_r - w : w                          (if out)
+// which covers one factor of Algorithm 1 or 3 (see poly.cpp). Two kernel
+// families compute (A in)_r; the autotuner picks one per matrix and
+// precision:
+//  * tile: a workgroup owns a tile of <= 256*RPT rows holding <= 256*EPT
+//    stored entries; the entries are streamed with coalesced loads, the
+//    products staged in LDS and summed per row. Row data of the epilogue is
+//    prefetched before the stream so that it overlaps it.
+//  * vec: LPR lanes per row, U rows in flight per lane group, sums reduced
+//    with cross-lane shuffles; no LDS and no barrier.
 // ---------------------------------------------------------------------------
 
 template <typename VT, typename XT>
@@ -100,9 +114,6 @@ struct ChainArgs {
     const int32_t *rowptr;
     const int32_t *colind;
     const VT *val;
-    const int32_t *tiles;
-    int ntiles;
-    int xcd_remap;
     const XT *in;
     const XT *aux;
     const XT *vfin;
@@ -110,41 +121,75 @@ struct ChainArgs {
     XT *acc;
     typename Arith<XT>::T a0, a1, a2, b0, b1;
     int acc_init;
-    int spmv;
+    int n;
+};
+
+template <typename AT>
+struct RowPre {
+    AT xin, aux, vf, acc;
 };
 
 template <typename VT, typename XT>
-__device__ __forceinline__ void chain_epilogue(const ChainArgs<VT, XT> &a, int r, typename Arith<XT>::T s) {
+__device__ __forceinline__ RowPre<typename Arith<XT>::T> row_prefetch(const ChainArgs<VT, XT> &a, int r) {
     using AT = typename Arith<XT>::T;
-    const AT xin = ldx(a.in, r);
-    AT w = a.a0 * s + a.a1 * xin;
-    if (a.aux) w += a.a2 * ldx(a.aux, r);
-    if (a.acc) {
-        const AT old = a.acc_init ? AT(0) : ldx(a.acc, r);
-        stx(a.acc, r, old + a.b0 * xin + a.b1 * w);
-    }
-    if (a.out) stx(a.out, r, a.vfin ? ldx(a.vfin, r) - w : w);
+    RowPre<AT> p;
+    p.xin = ldx(a.in, r);
+    p.aux = a.aux ? (AT)ldx(a.aux, r) : AT(0);
+    p.vf = a.vfin ? (AT)ldx(a.vfin, r) : AT(0);
+    p.acc = (a.acc && !a.acc_init) ? (AT)ldx(a.acc, r) : AT(0);
+    return p;
 }
 
 template <typename VT, typename XT>
-__global__ __launch_bounds__(kChainBlock) void k_chain(ChainArgs<VT, XT> a) {
+__device__ __forceinline__ void row_finish(const ChainArgs<VT, XT> &a, int r, typename Arith<XT>::T s,
+                                           const RowPre<typename Arith<XT>::T> &p) {
     using AT = typename Arith<XT>::T;
-    __shared__ AT buf[kTileNnz];
-    __shared__ AT red[4];
-    const int t = remap_tile(blockIdx.x, a.ntiles, a.xcd_remap);
-    const int r0 = a.tiles[t], r1 = a.tiles[t + 1];
+    AT w = a.a0 * s + a.a1 * p.xin;
+    if (a.aux) w += a.a2 * p.aux;
+    if (a.acc) stx(a.acc, r, p.acc + a.b0 * p.xin + a.b1 * w);
+    if (a.out) stx(a.out, r, a.vfin ? p.vf - w : w);
+}
+
+// steps without a sparse product (a0 unused)
+template <typename VT, typename XT>
+__global__ __launch_bounds__(256) void k_chain_elem(ChainArgs<VT, XT> a) {
+    using AT = typename Arith<XT>::T;
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < a.n) row_finish(a, r, AT(0), row_prefetch(a, r));
+}
+
+// One row tile of a chain step (r0, r1, e0, e1 in ti); buf: LDS of 256*EPT
+// entries, red: LDS of 4. With spmv == 0 only the epilogue runs.
+template <typename VT, typename XT, int EPT, int RPT>
+__device__ __forceinline__ void tile_body(const ChainArgs<VT, XT> &a, const int4 ti, int spmv,
+                                          typename Arith<XT>::T *buf, typename Arith<XT>::T *red) {
+    using AT = typename Arith<XT>::T;
+    constexpr int TILE = 256 * EPT;
+    const int r0 = ti.x, r1 = ti.y, e0 = ti.z, e1 = ti.w;
     const int tid = threadIdx.x;
-    if (!a.spmv) {
-        for (int r = r0 + tid; r < r1; r += kChainBlock) chain_epilogue(a, r, AT(0));
+    if (!spmv) {
+        for (int r = r0 + tid; r < r1; r += 256) row_finish(a, r, AT(0), row_prefetch(a, r));
         return;
     }
-    const int e0 = a.rowptr[r0], e1 = a.rowptr[r1];
-    if (e1 - e0 <= kTileNnz) {
-        int col[kChainEpt];
-        VT v[kChainEpt];
+    if (e1 - e0 <= TILE) {
+        int rs[RPT], rl[RPT];
+        RowPre<AT> pre[RPT];
 #pragma unroll
-        for (int k = 0; k < kChainEpt; ++k) {
-            const int e = e0 + k * kChainBlock + tid;
+        for (int q = 0; q < RPT; ++q) {
+            const int r = r0 + tid + q * 256;
+            rs[q] = 0;
+            rl[q] = 0;
+            if (r < r1) {
+                rs[q] = a.rowptr[r] - e0;
+                rl[q] = a.rowptr[r + 1] - e0;
+                pre[q] = row_prefetch(a, r);
+            }
+        }
+        int col[EPT];
+        VT v[EPT];
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int e = e0 + k * 256 + tid;
             col[k] = 0;
             v[k] = VT(0);
             if (e < e1) {
@@ -153,36 +198,414 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(ChainArgs<VT, XT> a) {
             }
         }
 #pragma unroll
-        for (int k = 0; k < kChainEpt; ++k) {
-            const int e = e0 + k * kChainBlock + tid;
-            if (e < e1) buf[k * kChainBlock + tid] = (AT)v[k] * ldx(a.in, col[k]);
+        for (int k = 0; k < EPT; ++k) {
+            const int e = e0 + k * 256 + tid;
+            if (e < e1) buf[k * 256 + tid] = (AT)v[k] * ldx(a.in, col[k]);
         }
         __syncthreads();
-        for (int r = r0 + tid; r < r1; r += kChainBlock) {
-            const int s0 = a.rowptr[r] - e0, s1 = a.rowptr[r + 1] - e0;
-            AT s = AT(0);
-            for (int q = s0; q < s1; ++q) s += buf[q];
-            chain_epilogue(a, r, s);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = r0 + tid + q * 256;
+            if (r < r1) {
+                AT s = AT(0);
+                for (int k = rs[q]; k < rl[q]; ++k) s += buf[k];
+                row_finish(a, r, s, pre[q]);
+            }
         }
     } else {
-        // a tile with a single long row
+        // a tile holding one row longer than the tile capacity
         AT s = AT(0);
-        for (int e = e0 + tid; e < e1; e += kChainBlock) s += (AT)a.val[e] * ldx(a.in, a.colind[e]);
+        for (int e = e0 + tid; e < e1; e += 256) s += (AT)a.val[e] * ldx(a.in, a.colind[e]);
         s = block_sum256(s, red);
-        if (tid == 0) chain_epilogue(a, r0, s);
+        if (tid == 0) row_finish(a, r0, s, row_prefetch(a, r0));
     }
 }
 
+template <typename VT, typename XT, int EPT, int RPT>
+__global__ __launch_bounds__(256) void k_chain_tile(ChainArgs<VT, XT> a, const int4 *__restrict__ tinfo, int ntiles,
+                                                    int remap) {
+    using AT = typename Arith<XT>::T;
+    __shared__ AT buf[256 * EPT];
+    __shared__ AT red[4];
+    const int t = remap_tile(blockIdx.x, ntiles, remap);
+    tile_body<VT, XT, EPT, RPT>(a, tinfo[t], 1, buf, red);
+}
+
+// ---------------------------------------------------------------------------
+// persistent chain: all steps of a program in one cooperative launch
+//
+// Every workgroup owns a fixed contiguous range of row tiles (balanced in
+// stored entries) and runs each step of the program over it; consecutive
+// steps are separated by a grid-wide barrier (the next step gathers rows
+// written by other workgroups). The barrier counter only grows: the host
+// passes the value it had before the launch. A barrier that does not
+// complete within a bounded number of polls sets *err and lets the kernel
+// run to its end, so every wave exits.
+// ---------------------------------------------------------------------------
+
 template <typename VT, typename XT>
-hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, hipStream_t st) {
+struct PArgs {
+    const int32_t *rowptr;
+    const int32_t *colind;
+    const VT *val;
+    const int4 *tiles;
+    int ntiles;
+    int n;
+    XT *bufs[5];
+    const PStep *steps;
+    int nsteps;
+    int remap;
+    unsigned long long *bar;
+    unsigned long long bar_base;
+    int *err;
+};
+
+__device__ __forceinline__ void grid_barrier(unsigned long long *bar, unsigned long long target, int *err) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            // bounded wait (~0.2 s); after a timeout every later barrier of
+            // the launch returns at once
+            if (++spins > (1u << 23) || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <typename VT, typename XT, int EPT>
+__global__ __launch_bounds__(256) void k_chain_persist(PArgs<VT, XT> p) {
+    using AT = typename Arith<XT>::T;
+    __shared__ AT buf[256 * EPT];
+    __shared__ AT red[4];
+    const int G = gridDim.x;
+    const int w = remap_tile(blockIdx.x, G, p.remap);
+    const int t0 = (int)((long)w * p.ntiles / G), t1 = (int)((long)(w + 1) * p.ntiles / G);
+    for (int s = 0; s < p.nsteps; ++s) {
+        const PStep st = p.steps[s];
+        ChainArgs<VT, XT> a;
+        a.rowptr = p.rowptr;
+        a.colind = p.colind;
+        a.val = p.val;
+        a.in = p.bufs[st.in];
+        a.aux = st.aux >= 0 ? p.bufs[st.aux] : nullptr;
+        a.vfin = st.fin ? p.bufs[0] : nullptr;
+        a.out = st.out >= 0 ? p.bufs[st.out] : nullptr;
+        a.acc = st.acc >= 0 ? p.bufs[st.acc] : nullptr;
+        a.a0 = (AT)st.a0;
+        a.a1 = (AT)st.a1;
+        a.a2 = (AT)st.a2;
+        a.b0 = (AT)st.b0;
+        a.b1 = (AT)st.b1;
+        a.acc_init = st.acc_init;
+        a.n = p.n;
+        for (int t = t0; t < t1; ++t) {
+            tile_body<VT, XT, EPT, 1>(a, p.tiles[t], st.spmv, buf, red);
+            __syncthreads();
+        }
+        if (s + 1 < p.nsteps) grid_barrier(p.bar, p.bar_base + (unsigned long long)(s + 1) * G, p.err);
+    }
+}
+
+// 16-byte non-temporal loads of 4 consecutive stored entries (streamed once
+// per launch: kept out of the way of the gathered input vector in L2)
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void load4(const int32_t *p, int *c) {
+    const v4i q = __builtin_nontemporal_load((const v4i *)p);
+    c[0] = q.x;
+    c[1] = q.y;
+    c[2] = q.z;
+    c[3] = q.w;
+}
+__device__ __forceinline__ void load4(const float *p, float *v) {
+    const v4f q = __builtin_nontemporal_load((const v4f *)p);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+}
+__device__ __forceinline__ void load4(const double *p, double *v) {
+    const v2d a = __builtin_nontemporal_load((const v2d *)p);
+    const v2d b = __builtin_nontemporal_load((const v2d *)p + 1);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+}
+
+// Tile kernel with 16-byte streaming loads: the tile's entries are read in
+// aligned chunks of 4 from e0 rounded down to a multiple of 4 (entries of
+// the neighbouring tiles in the first/last chunk are masked out). A chunk
+// that would cross the end of the arrays is read element by element.
+template <typename VT, typename XT, int EPT, int RPT>
+__global__ __launch_bounds__(256) void k_chain_tilev(ChainArgs<VT, XT> a, const int4 *__restrict__ tinfo, int ntiles,
+                                                     int remap, int nnz) {
+    using AT = typename Arith<XT>::T;
+    constexpr int TILE = 256 * EPT;
+    constexpr int CH = EPT / 4;  // chunks of 4 per thread
+    __shared__ AT buf[TILE];
+    __shared__ AT red[4];
+    const int t = remap_tile(blockIdx.x, ntiles, remap);
+    const int4 ti = tinfo[t];
+    const int r0 = ti.x, r1 = ti.y, e0 = ti.z, e1 = ti.w;
+    const int ea = e0 & ~3;
+    const int tid = threadIdx.x;
+    if (e1 - ea <= TILE) {
+        int rs[RPT], rl[RPT];
+        RowPre<AT> pre[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = r0 + tid + q * 256;
+            rs[q] = 0;
+            rl[q] = 0;
+            if (r < r1) {
+                rs[q] = a.rowptr[r] - ea;
+                rl[q] = a.rowptr[r + 1] - ea;
+                pre[q] = row_prefetch(a, r);
+            }
+        }
+        int col[CH][4];
+        VT v[CH][4];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int c = ea + (k * 256 + tid) * 4;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                col[k][j] = 0;
+                v[k][j] = VT(0);
+            }
+            if (c < e1) {
+                if (c + 4 <= nnz) {
+                    load4(a.colind + c, col[k]);
+                    load4(a.val + c, v[k]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (c + j < nnz) {
+                            col[k][j] = a.colind[c + j];
+                            v[k][j] = a.val[c + j];
+                        }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int c = ea + (k * 256 + tid) * 4;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = c + j;
+                if (e >= e0 && e < e1) buf[e - ea] = (AT)v[k][j] * ldx(a.in, col[k][j]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = r0 + tid + q * 256;
+            if (r < r1) {
+                AT s = AT(0);
+                for (int k = rs[q]; k < rl[q]; ++k) s += buf[k];
+                row_finish(a, r, s, pre[q]);
+            }
+        }
+    } else {
+        AT s = AT(0);
+        for (int e = e0 + tid; e < e1; e += 256) s += (AT)a.val[e] * ldx(a.in, a.colind[e]);
+        s = block_sum256(s, red);
+        if (tid == 0) row_finish(a, r0, s, row_prefetch(a, r0));
+    }
+}
+
+// LPR lanes per row, U rows per lane group, K entries per lane loaded in
+// one batch (rows longer than LPR*K finish in a loop).
+template <typename VT, typename XT, int LPR, int U, int K>
+__global__ __launch_bounds__(256) void k_chain_vk(ChainArgs<VT, XT> a, int nblocks, int remap) {
+    using AT = typename Arith<XT>::T;
+    constexpr int GPW = 64 / LPR;
+    constexpr int RPW = GPW * U;
+    const int blk = remap_tile(blockIdx.x, nblocks, remap);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane / LPR, l = lane % LPR;
+    const int base = (blk * 4 + wave) * RPW + g;
+    int e0[U], e1[U];
+    RowPre<AT> pre[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = base + u * GPW;
+        e0[u] = 0;
+        e1[u] = 0;
+        if (r < a.n) {
+            e0[u] = a.rowptr[r];
+            e1[u] = a.rowptr[r + 1];
+            if (l == 0) pre[u] = row_prefetch(a, r);
+        }
+    }
+    int col[U][K];
+    VT v[U][K];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = e0[u] + l + k * LPR;
+            col[u][k] = 0;
+            v[u][k] = VT(0);
+            if (e < e1[u]) {
+                col[u][k] = __builtin_nontemporal_load(a.colind + e);
+                v[u][k] = __builtin_nontemporal_load(a.val + e);
+            }
+        }
+    AT s[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        s[u] = AT(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (e0[u] + l + k * LPR < e1[u]) s[u] += (AT)v[u][k] * ldx(a.in, col[u][k]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        for (int e = e0[u] + l + K * LPR; e < e1[u]; e += LPR) s[u] += (AT)a.val[e] * ldx(a.in, a.colind[e]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int off = LPR / 2; off > 0; off >>= 1) s[u] += __shfl_xor(s[u], off, 64);
+    }
+    if (l == 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = base + u * GPW;
+            if (r < a.n) row_finish(a, r, s[u], pre[u]);
+        }
+    }
+}
+
+template <typename VT, typename XT, int LPR, int U>
+__global__ __launch_bounds__(256) void k_chain_vec(ChainArgs<VT, XT> a, int nblocks, int remap) {
+    using AT = typename Arith<XT>::T;
+    constexpr int GPW = 64 / LPR;  // row groups per wave
+    constexpr int RPW = GPW * U;   // rows per wave
+    const int blk = remap_tile(blockIdx.x, nblocks, remap);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane / LPR, l = lane % LPR;
+    const int base = (blk * 4 + wave) * RPW + g;
+    int e0[U], e1[U];
+    RowPre<AT> pre[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = base + u * GPW;
+        e0[u] = 0;
+        e1[u] = 0;
+        if (r < a.n) {
+            e0[u] = a.rowptr[r];
+            e1[u] = a.rowptr[r + 1];
+            if (l == 0) pre[u] = row_prefetch(a, r);
+        }
+    }
+    int col[U];
+    VT v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = e0[u] + l;
+        col[u] = 0;
+        v[u] = VT(0);
+        if (e < e1[u]) {
+            col[u] = a.colind[e];
+            v[u] = a.val[e];
+        }
+    }
+    AT s[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s[u] = (e0[u] + l < e1[u]) ? (AT)v[u] * ldx(a.in, col[u]) : AT(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        for (int e = e0[u] + l + LPR; e < e1[u]; e += LPR) s[u] += (AT)a.val[e] * ldx(a.in, a.colind[e]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int off = LPR / 2; off > 0; off >>= 1) s[u] += __shfl_xor(s[u], off, 64);
+    }
+    if (l == 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = base + u * GPW;
+            if (r < a.n) row_finish(a, r, s[u], pre[u]);
+        }
+    }
+}
+
+// Sliced ELL: wave w handles slice w (64 rows, lane j -> row 64 w + j). The
+// k-th entries of the slice's rows are contiguous, so the index and value
+// loads are coalesced and, for stencil-like matrices, so is the gather of
+// the input (neighbouring rows have neighbouring columns). Entries are
+// consumed 8 at a time (loads issued together).
+template <typename T>
+__device__ __forceinline__ T stream_load(const T *p, bool nt) {
+    return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+template <typename VT, typename XT, bool NT>
+__global__ __launch_bounds__(256) void k_chain_sell(ChainArgs<VT, XT> a, const int32_t *__restrict__ sptr,
+                                                    const int32_t *__restrict__ scol, const VT *__restrict__ sval,
+                                                    int nslices, int nblocks, int remap) {
+    using AT = typename Arith<XT>::T;
+    constexpr int U = 8;
+    const int blk = remap_tile(blockIdx.x, nblocks, remap);
+    const int w = blk * 4 + (threadIdx.x >> 6);
+    if (w >= nslices) return;
+    const int lane = threadIdx.x & 63;
+    const int r = w * 64 + lane;
+    const int o0 = sptr[w];
+    const int width = (sptr[w + 1] - o0) >> 6;
+    RowPre<AT> pre;
+    if (r < a.n) pre = row_prefetch(a, r);
+    AT s = AT(0);
+    for (int k0 = 0; k0 < width; k0 += U) {
+        int c[U];
+        VT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = 0;
+            v[u] = VT(0);
+            if (k0 + u < width) {
+                const int o = o0 + (k0 + u) * 64 + lane;
+                c[u] = stream_load(scol + o, NT);
+                v[u] = stream_load(sval + o, NT);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < width) s += (AT)v[u] * ldx(a.in, c[u]);
+    }
+    if (r < a.n) row_finish(a, r, s, pre);
+}
+
+template <typename VT>
+const VT *sell_vals(const DevCSR &A);
+template <>
+const double *sell_vals<double>(const DevCSR &A) {
+    return A.sval64;
+}
+template <>
+const float *sell_vals<float>(const DevCSR &A) {
+    return A.sval32;
+}
+
+template <typename VT, typename XT>
+ChainArgs<VT, XT> chain_args(const DevCSR &A, const VT *val, const StepPtrs &s) {
     using AT = typename Arith<XT>::T;
     ChainArgs<VT, XT> a;
     a.rowptr = A.rowptr;
     a.colind = A.colind;
     a.val = val;
-    a.tiles = A.tiles;
-    a.ntiles = A.ntiles;
-    a.xcd_remap = A.xcd_remap;
     a.in = (const XT *)s.in;
     a.aux = (const XT *)s.aux;
     a.vfin = (const XT *)s.vfin;
@@ -194,10 +617,108 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, hipSt
     a.b0 = (AT)s.b0;
     a.b1 = (AT)s.b1;
     a.acc_init = s.acc_init;
-    a.spmv = s.spmv;
-    if (A.ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_chain<VT, XT>), dim3(A.ntiles), dim3(kChainBlock), 0, st, a);
+    a.n = A.n;
+    return a;
+}
+
+template <typename VT, typename XT, int LPR, int U>
+hipError_t vec_launch(const ChainArgs<VT, XT> &a, int remap, hipStream_t st) {
+    constexpr int RPB = 4 * (64 / LPR) * U;
+    const int nb = (a.n + RPB - 1) / RPB;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_chain_vec<VT, XT, LPR, U>), dim3(nb), dim3(256), 0, st, a, nb, remap);
     return hipGetLastError();
+}
+
+template <typename XT>
+constexpr int prec_of() {
+    return sizeof(XT) == 8 ? 0 : (sizeof(XT) == 4 ? 1 : 2);
+}
+
+template <typename VT, typename XT, int LPR, int U, int K>
+hipError_t vk_launch(const ChainArgs<VT, XT> &a, int remap, hipStream_t st) {
+    constexpr int RPB = 4 * (64 / LPR) * U;
+    const int nb = (a.n + RPB - 1) / RPB;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_chain_vk<VT, XT, LPR, U, K>), dim3(nb), dim3(256), 0, st, a, nb, remap);
+    return hipGetLastError();
+}
+
+template <typename VT, typename XT>
+hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int variant, int remap, hipStream_t st) {
+    const ChainArgs<VT, XT> a = chain_args<VT, XT>(A, val, s);
+    if (A.n == 0) return hipSuccess;
+    if (!s.spmv) {
+        hipLaunchKernelGGL((k_chain_elem<VT, XT>), dim3((A.n + 255) / 256), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
+    switch (variant) {
+        case CV_TILE8:
+            hipLaunchKernelGGL((k_chain_tile<VT, XT, 8, 1>), dim3(A.ntile8), dim3(256), 0, st, a, A.tile8, A.ntile8,
+                               remap);
+            return hipGetLastError();
+        case CV_TILE16:
+            hipLaunchKernelGGL((k_chain_tile<VT, XT, 16, 2>), dim3(A.ntile16), dim3(256), 0, st, a, A.tile16,
+                               A.ntile16, remap);
+            return hipGetLastError();
+        case CV_VEC1x4:
+            return vec_launch<VT, XT, 1, 4>(a, remap, st);
+        case CV_VEC4x4:
+            return vec_launch<VT, XT, 4, 4>(a, remap, st);
+        case CV_VEC8x2:
+            return vec_launch<VT, XT, 8, 2>(a, remap, st);
+        case CV_VEC8x4:
+            return vec_launch<VT, XT, 8, 4>(a, remap, st);
+        case CV_VEC16x2:
+            return vec_launch<VT, XT, 16, 2>(a, remap, st);
+        case CV_VEC16x4:
+            return vec_launch<VT, XT, 16, 4>(a, remap, st);
+        case CV_VEC32x2:
+            return vec_launch<VT, XT, 32, 2>(a, remap, st);
+        case CV_TILEV8:
+            hipLaunchKernelGGL((k_chain_tilev<VT, XT, 8, 1>), dim3(A.ntile8), dim3(256), 0, st, a, A.tile8, A.ntile8,
+                               remap, A.nnz);
+            return hipGetLastError();
+        case CV_TILEV16:
+            hipLaunchKernelGGL((k_chain_tilev<VT, XT, 16, 2>), dim3(A.ntile16), dim3(256), 0, st, a, A.tile16,
+                               A.ntile16, remap, A.nnz);
+            return hipGetLastError();
+        case CV_VK2x4x4:
+            return vk_launch<VT, XT, 2, 4, 4>(a, remap, st);
+        case CV_VK4x4x2:
+            return vk_launch<VT, XT, 4, 4, 2>(a, remap, st);
+        case CV_VK8x4x1:
+            return vk_launch<VT, XT, 8, 4, 1>(a, remap, st);
+        case CV_VK16x2x2:
+            return vk_launch<VT, XT, 16, 2, 2>(a, remap, st);
+        case CV_SELL:
+        case CV_SELLT: {
+            if (A.nslices == 0) return hipErrorInvalidValue;
+            const int nb = (A.nslices + 3) / 4;
+            if (variant == CV_SELL)
+                hipLaunchKernelGGL((k_chain_sell<VT, XT, true>), dim3(nb), dim3(256), 0, st, a, A.sptr, A.scol,
+                                   sell_vals<VT>(A), A.nslices, nb, remap);
+            else
+                hipLaunchKernelGGL((k_chain_sell<VT, XT, false>), dim3(nb), dim3(256), 0, st, a, A.sptr, A.scol,
+                                   sell_vals<VT>(A), A.nslices, nb, remap);
+            return hipGetLastError();
+        }
+        case CV_TILEB8: {
+            const int p = prec_of<XT>();
+            if (A.ntileB8[p] == 0) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_chain_tile<VT, XT, 8, 1>), dim3(A.ntileB8[p]), dim3(256), 0, st, a, A.tileB8[p],
+                               A.ntileB8[p], remap);
+            return hipGetLastError();
+        }
+        case CV_TILEB16: {
+            const int p = prec_of<XT>();
+            if (A.ntileB16[p] == 0) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_chain_tile<VT, XT, 16, 2>), dim3(A.ntileB16[p]), dim3(256), 0, st, a, A.tileB16[p],
+                               A.ntileB16[p], remap);
+            return hipGetLastError();
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -286,6 +807,47 @@ __global__ __launch_bounds__(256) void k_update(int n, const XT *V, long ldv, in
     }
 }
 
+// w <- w - V h and partial[b * ldp + k] = sum over the block's rows of
+// V[i,k] * w_new[i]: the update of one Gram-Schmidt pass fused with the
+// projection of the next, so V is read once. A row of V (ncols <= KMAX
+// values) stays in registers between the two uses.
+template <typename XT, int KMAX, int RPT>
+__global__ __launch_bounds__(256) void k_update_dots(int n, const XT *V, long ldv, int ncols, const double *h, XT *w,
+                                                     double *partial, int ldp) {
+    using AT = typename Arith<XT>::T;
+    __shared__ double hs[KMAX];
+    __shared__ double sm[4][KMAX];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < KMAX) hs[tid] = tid < ncols ? h[tid] : 0.0;
+    __syncthreads();
+    AT acc[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) acc[k] = AT(0);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const long i = ((long)blockIdx.x * RPT + q) * 256 + tid;
+        if (i < n) {
+            AT vr[KMAX];
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) vr[k] = k < ncols ? (AT)ldx(V, i + (long)k * ldv) : AT(0);
+            double wi = (double)ldx(w, i);
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) wi -= (double)vr[k] * hs[k];
+            stx(w, i, (AT)wi);
+            const AT ws = (AT)stored_value(w, wi);
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) acc[k] += vr[k] * ws;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const double t = wave_sum((double)acc[k]);
+        if (lane == 0) sm[wave][k] = t;
+    }
+    __syncthreads();
+    if (tid < ncols) partial[(long)blockIdx.x * ldp + tid] = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
+}
+
 __global__ __launch_bounds__(kRedBlock) void k_reduce_norm(int nblk, const double *partial, double *H,
                                                            double *inv) {
     __shared__ double red[4];
@@ -345,6 +907,17 @@ __global__ __launch_bounds__(256) void k_val_to_f32(int nnz, const double *v, fl
     if (i < nnz) o[i] = (float)v[i];
 }
 
+__global__ __launch_bounds__(256) void k_sell_values(long npad, const int32_t *sperm, const double *val, double *s64,
+                                                     float *s32) {
+    const long k = (long)blockIdx.x * 256 + threadIdx.x;
+    if (k < npad) {
+        const int p = sperm[k];
+        const double v = p >= 0 ? val[p] : 0.0;
+        s64[k] = v;
+        s32[k] = (float)v;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_gather(int nnz, const double *in, const int32_t *perm, double *out) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i < nnz) out[i] = in[perm[i]];
@@ -365,13 +938,14 @@ inline unsigned blocks_for(long n, int per) { return (unsigned)((n + per - 1) / 
 size_t elem_size(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 
 hipError_t launch_chain_step(const DevCSR &A, int prec, const StepPtrs &s, hipStream_t st) {
+    const int v = A.variant[prec], r = A.remap[prec];
     switch (prec) {
         case 0:
-            return chain_launch<double, double>(A, A.val64, s, st);
+            return chain_launch<double, double>(A, A.val64, s, v, r, st);
         case 1:
-            return chain_launch<float, float>(A, A.val32, s, st);
+            return chain_launch<float, float>(A, A.val32, s, v, r, st);
         case 2:
-            return chain_launch<float, uint16_t>(A, A.val32, s, st);
+            return chain_launch<float, uint16_t>(A, A.val32, s, v, r, st);
     }
     return hipErrorInvalidValue;
 }
@@ -559,6 +1133,14 @@ hipError_t launch_val_to_f32(int nnz, const double *val64, float *val32, hipStre
     return hipGetLastError();
 }
 
+hipError_t launch_sell_values(long npad, const int32_t *sperm, const double *val, double *sval64, float *sval32,
+                              hipStream_t st) {
+    const unsigned g = blocks_for(npad, 256);
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sell_values, dim3(g), dim3(256), 0, st, npad, sperm, val, sval64, sval32);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather(int nnz, const double *in, const int32_t *perm, double *out, hipStream_t st) {
     const unsigned g = blocks_for(nnz, 256);
     if (g == 0) return hipSuccess;
@@ -571,6 +1153,154 @@ hipError_t launch_adjoint_values(const DevCSR &A, const double *lam, const doubl
     if (g == 0) return hipSuccess;
     hipLaunchKernelGGL(k_adjoint_values, dim3(g), dim3(256), 0, st, A.n, A.rowptr, A.colind, lam, x, dval);
     return hipGetLastError();
+}
+
+constexpr int kUdRows = 4;  // rows per thread of k_update_dots
+
+int update_dots_blocks(int n) { return (int)blocks_for(n, 256 * kUdRows); }
+
+int update_dots_max_cols(int prec) { return prec == 0 ? 32 : 64; }
+
+template <typename XT>
+static hipError_t ud_launch(int n, const XT *V, long ldv, int ncols, const double *h, XT *w, double *partial, int ldp,
+                            hipStream_t st, int prec) {
+    const unsigned g = blocks_for(n, 256 * kUdRows);
+    if (g == 0 || ncols == 0) return hipSuccess;
+    if (ncols <= 16)
+        hipLaunchKernelGGL((k_update_dots<XT, 16, kUdRows>), dim3(g), dim3(256), 0, st, n, V, ldv, ncols, h, w,
+                           partial, ldp);
+    else if (ncols <= 32)
+        hipLaunchKernelGGL((k_update_dots<XT, 32, kUdRows>), dim3(g), dim3(256), 0, st, n, V, ldv, ncols, h, w,
+                           partial, ldp);
+    else if (prec != 0 && ncols <= 64)
+        hipLaunchKernelGGL((k_update_dots<XT, 64, kUdRows>), dim3(g), dim3(256), 0, st, n, V, ldv, ncols, h, w,
+                           partial, ldp);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_update_dots(int prec, int n, const void *V, long ldv, int ncols, const double *h, void *w,
+                              double *partial, int ldp, hipStream_t st) {
+    switch (prec) {
+        case 0:
+            return ud_launch<double>(n, (const double *)V, ldv, ncols, h, (double *)w, partial, ldp, st, prec);
+        case 1:
+            return ud_launch<float>(n, (const float *)V, ldv, ncols, h, (float *)w, partial, ldp, st, prec);
+        case 2:
+            return ud_launch<uint16_t>(n, (const uint16_t *)V, ldv, ncols, h, (uint16_t *)w, partial, ldp, st, prec);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename VT, typename XT>
+static hipError_t persist_launch(const DevCSR &A, const VT *val, void *const bufs[5], const PStep *steps, int nsteps,
+                                 unsigned long long *bar, unsigned long long bar_base, int *err, int grid, int remap,
+                                 hipStream_t st) {
+    PArgs<VT, XT> p;
+    p.rowptr = A.rowptr;
+    p.colind = A.colind;
+    p.val = val;
+    p.tiles = A.tileP;
+    p.ntiles = A.ntileP;
+    p.n = A.n;
+    for (int i = 0; i < 5; ++i) p.bufs[i] = (XT *)bufs[i];
+    p.steps = steps;
+    p.nsteps = nsteps;
+    p.remap = remap;
+    p.bar = bar;
+    p.bar_base = bar_base;
+    p.err = err;
+    void *args[] = {&p};
+    return hipLaunchCooperativeKernel((const void *)k_chain_persist<VT, XT, 8>, dim3(grid), dim3(256), args, 0, st);
+}
+
+hipError_t launch_chain_persist(const DevCSR &A, int prec, void *const bufs[5], const PStep *steps, int nsteps,
+                                unsigned long long *bar, unsigned long long bar_base, int *err, int grid, int remap,
+                                hipStream_t st) {
+    if (nsteps <= 0) return hipSuccess;
+    switch (prec) {
+        case 0:
+            return persist_launch<double, double>(A, A.val64, bufs, steps, nsteps, bar, bar_base, err, grid, remap, st);
+        case 1:
+            return persist_launch<float, float>(A, A.val32, bufs, steps, nsteps, bar, bar_base, err, grid, remap, st);
+        case 2:
+            return persist_launch<float, uint16_t>(A, A.val32, bufs, steps, nsteps, bar, bar_base, err, grid, remap,
+                                                   st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename VT, typename XT>
+static hipError_t tile_occ(int ept, int *per) {
+    if (ept == 8) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, (const void *)k_chain_tile<VT, XT, 8, 1>, 256, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, (const void *)k_chain_tile<VT, XT, 16, 2>, 256, 0);
+}
+
+hipError_t tile_slots(int prec, int ept, int *slots) {
+    int dev = 0, ncu = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    if (prec == 0)
+        e = tile_occ<double, double>(ept, &per);
+    else if (prec == 1)
+        e = tile_occ<float, float>(ept, &per);
+    else
+        e = tile_occ<float, uint16_t>(ept, &per);
+    if (e != hipSuccess) return e;
+    *slots = per * ncu;
+    return hipSuccess;
+}
+
+hipError_t persist_max_grid(int prec, int *grid) {
+    int dev = 0, ncu = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    switch (prec) {
+        case 0:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain_persist<double, double, 8>, 256,
+                                                             0);
+            break;
+        case 1:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain_persist<float, float, 8>, 256,
+                                                             0);
+            break;
+        default:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain_persist<float, uint16_t, 8>,
+                                                             256, 0);
+    }
+    if (e != hipSuccess) return e;
+    *grid = per * ncu;
+    return hipSuccess;
+}
+
+void build_tiles(const int32_t *rp, int n, int row_cap, int nnz_cap, std::vector<int4> &out) {
+    out.clear();
+    int r = 0;
+    while (r < n) {
+        const int start = r;
+        long nz = 0;
+        while (r < n && r - start < row_cap) {
+            const long rn = (long)rp[r + 1] - rp[r];
+            if (r > start && nz + rn > nnz_cap) break;
+            nz += rn;
+            ++r;
+            if (rn > nnz_cap) break;  // a long row stays alone
+        }
+        out.push_back(make_int4(start, r, rp[start], rp[r]));
+    }
+}
+
+const char *chain_variant_name(int v) {
+    static const char *names[CV_COUNT] = {"tile8x1", "tile16x2", "vec1x4",  "vec4x4",    "vec8x2",
+                                          "vec8x4",  "vec16x2",  "vec16x4", "vec32x2",   "tilev8x1",
+                                          "tilev16x2", "vk2x4x4", "vk4x4x2", "vk8x4x1", "vk16x2x2", "persist8",
+                                          "tileb8x1", "tileb16x2", "sell64", "sell64t"};
+    return (v >= 0 && v < CV_COUNT) ? names[v] : "?";
 }
 
 }  // namespace ppg

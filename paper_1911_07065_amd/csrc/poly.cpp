@@ -2,7 +2,14 @@
 // pi(A)v (Algorithm 1) or p(A)v (Algorithm 3) for an ordered root list.
 #include "poly.h"
 
+#include <atomic>
+
 namespace ppg {
+
+unsigned long long next_poly_id() {
+    static std::atomic<unsigned long long> counter{0};
+    return ++counter;
+}
 
 namespace {
 

@@ -23,6 +23,8 @@ struct Step {
     double a0, a1, a2, b0, b1;
 };
 
+unsigned long long next_poly_id();
+
 // phi(A)v by Algorithm 1 (or pi(A)v when want_pi): d_eff sparse products.
 std::vector<Step> program_phi(const std::vector<Unit> &units, bool want_pi);
 // p(A)v by Algorithm 3: d_eff - 1 sparse products; the last real unit's
@@ -32,11 +34,13 @@ std::vector<Step> program_p(const std::vector<Unit> &units);
 }  // namespace ppg
 
 struct pp_poly_s {
+    unsigned long long id = 0;  // unique per polynomial (keys device-side caches)
     ppg::RootPlan plan;
     std::vector<double> theta_re, theta_im;  // raw harmonic Ritz values
     int breakdown = 0;
     std::vector<ppg::Step> prog_p, prog_phi, prog_pi;
     void finalize() {
+        id = ppg::next_poly_id();
         prog_p = ppg::program_p(plan.units);
         prog_phi = ppg::program_phi(plan.units, false);
         prog_pi = ppg::program_phi(plan.units, true);

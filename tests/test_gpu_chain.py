@@ -148,3 +148,41 @@ def test_bad_arguments_rejected(pp):
         pp.Matrix(np.array([0, 1, 2], dtype=np.int32), np.array([0, 5], dtype=np.int32), np.ones(2))  # col >= n
     with pytest.raises(Exception):
         pp.Matrix(np.array([0, 2, 1], dtype=np.int32), np.array([0, 1], dtype=np.int32), np.ones(2))  # rowptr
+
+
+@pytest.mark.parametrize("variant", range(20))
+def test_every_chain_variant_matches_oracle(pp, variant):
+    # each kernel variant the autotuner may pick, with and without the XCD order
+    for name in ["ragged_5000", "randsparse_20000", "convdiff3d_20"]:
+        csr, d = _cases()[name]
+        A = csr.to_scipy()
+        A32 = A.astype(np.float32)
+        P = oroots.setup(A, start_vector(csr.n, 2), d)
+        M = pp.Matrix.from_csr(csr)
+        poly = pp.poly_from_roots(P.roots(), keep_order=True)
+        v = rhs(csr.n, 5)
+        ref_p = chains.apply_p(A, P.units, v)
+        ref_phi = chains.apply_phi(A, P.units, v)
+        for remap in (0, 1):
+            say("variant", pp.chain_variant_name(variant), "remap", remap, name)
+            try:
+                M.set_variant("fp64", variant, remap)
+                M.set_variant("fp32", variant, remap)
+            except Exception as exc:
+                # the sliced-ELL copy is only built when its padding is small
+                assert "sliced-ELL" in str(exc) and name == "ragged_5000", exc
+                continue
+            assert relerr(host(pp.apply(poly, M, dev(v), "p")), ref_p) <= 1e-12
+            assert relerr(host(pp.apply(poly, M, dev(v), "phi")), ref_phi) <= 1e-12
+            got32 = host(pp.apply(poly, M, dev(v, torch.float32), "p"))
+            delta = relerr(apply_p_low(A32, P.units, v.astype(np.float32)), ref_p)
+            assert relerr(got32, ref_p) <= 10 * delta + 1e-6
+
+
+def test_autotuner_picks_a_valid_variant(pp):
+    csr = convdiff3d(48, 10, 10, 10)
+    M = pp.Matrix.from_csr(csr)
+    say("autotune")
+    for prec in ("fp64", "fp32", "bf16"):
+        name, remap, us = M.tune(prec)
+        assert name in [pp.chain_variant_name(v) for v in range(20)] and remap in (0, 1) and us > 0
