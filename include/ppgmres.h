@@ -75,6 +75,12 @@ typedef struct {
     double tol;       /* stop when ||b - A x|| <= tol ||b|| */
     pp_prec inner;    /* precision of the phi/p chains and the Krylov basis */
     int stall_cycles; /* NOCONV if this many cycles cut ||r|| by < 1% (0: off) */
+    double inner_eta; /* a reduced-precision cycle stops once its shortcut residual is
+                         <= max(tol ||b||, inner_eta ||r||); 0 = default (1e-5 FP32,
+                         1e-2 BF16); ignored for FP64 cycles */
+    double *history;  /* optional host array: true relative residual before each cycle
+                         and at the end (history_cap entries at most) */
+    int history_cap;
 } pp_solve_opts;
 
 /* Result of pp_solve. */

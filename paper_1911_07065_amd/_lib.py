@@ -28,7 +28,7 @@ class SetupInfo(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("m", c_int), ("max_cycles", c_int), ("tol", c_double), ("inner", c_int),
-                ("stall_cycles", c_int)]
+                ("stall_cycles", c_int), ("inner_eta", c_double), ("history", P_double), ("history_cap", c_int)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -42,7 +42,7 @@ constexpr double kBreakdownTol = 1e-14;
 constexpr int kMaxDegree = 4096;
 // relative inner-cycle target of a reduced-precision cycle (the FP64 outer
 // refinement recomputes the true residual after every cycle)
-constexpr double kInnerEta[3] = {0.0, 1e-6, 1e-2};
+constexpr double kInnerEta[3] = {0.0, 1e-5, 1e-2};
 
 template <typename T>
 pp_status dev_alloc(T **p, size_t count) {
@@ -476,27 +476,34 @@ pp_status spmv_axpby(pp_matrix A, int prec, const void *in, double a0, const voi
 // Orthogonalise w = V[:, j+1] against V[:, 0..j] by classical Gram-Schmidt
 // applied twice, normalise it, and leave the Hessenberg column
 // (j+2 values) in A->hpin (host) after a stream synchronisation.
-pp_status cgs2_step(pp_matrix A, int prec, const Workspace &ws, int j, hipStream_t st) {
+pp_status cgs2_step(pp_matrix A, int prec, const Workspace &ws, int j, hipStream_t st, double *Hcol = nullptr,
+                    bool to_host = true) {
+    if (!Hcol) Hcol = A->H();
     const int n = A->n;
     const int ncols = j + 1;
     void *w = vcol(ws, prec, j + 1);
     // pass 1: h1 = V^T w
     HIP_TRY(launch_dots(prec, n, ws.V, ws.ldv, ncols, w, A->partial, A->ldp, st));
-    HIP_TRY(launch_reduce(A->nblk_dot, A->partial, A->ldp, ncols, A->h1(), A->H(), 1, st));
-    // w -= V h1 ; h2 = V^T w  (fused into one read of V when the row fits in registers)
+    HIP_TRY(launch_reduce(A->nblk_dot, A->partial, A->ldp, ncols, A->h1(), Hcol, 1, st));
+    // w -= V h1 ; h2 = V^T w and ||w||^2 (one read of V when the row fits in
+    // registers); then w = (w - V h2) / ||w - V h2|| in one more pass, the
+    // norm following from ||w||^2 - ||h2||^2
     if (ncols <= update_dots_max_cols(prec)) {
         HIP_TRY(launch_update_dots(prec, n, ws.V, ws.ldv, ncols, A->h1(), w, A->partial, A->ldp, st));
-        HIP_TRY(launch_reduce(A->nblk_ud, A->partial, A->ldp, ncols, A->h2(), A->H(), 2, st));
+        HIP_TRY(launch_reduce(A->nblk_ud, A->partial, A->ldp, ncols + 1, A->h2(), nullptr, 0, st));
+        HIP_TRY(launch_finish_col(ncols, A->h2(), Hcol, A->inv(), st));
+        HIP_TRY(launch_update_scale(prec, n, ws.V, ws.ldv, ncols, A->h2(), w, A->inv(), st));
     } else {
         HIP_TRY(launch_update(prec, n, ws.V, ws.ldv, ncols, A->h1(), w, nullptr, st));
         HIP_TRY(launch_dots(prec, n, ws.V, ws.ldv, ncols, w, A->partial, A->ldp, st));
-        HIP_TRY(launch_reduce(A->nblk_dot, A->partial, A->ldp, ncols, A->h2(), A->H(), 2, st));
+        HIP_TRY(launch_reduce(A->nblk_dot, A->partial, A->ldp, ncols, A->h2(), Hcol, 2, st));
+        // w -= V h2 ; ||w|| ; w /= ||w||
+        HIP_TRY(launch_update(prec, n, ws.V, ws.ldv, ncols, A->h2(), w, A->npart, st));
+        HIP_TRY(launch_reduce_norm(A->nblk_upd, A->npart, Hcol + ncols, A->inv(), st));
+        HIP_TRY(launch_scale_cast(prec, prec, n, w, A->inv(), 0.0, w, st));
     }
-    // w -= V h2 ; ||w||
-    HIP_TRY(launch_update(prec, n, ws.V, ws.ldv, ncols, A->h2(), w, A->npart, st));
-    HIP_TRY(launch_reduce_norm(A->nblk_upd, A->npart, A->H() + ncols, A->inv(), st));
-    HIP_TRY(launch_scale_cast(prec, prec, n, w, A->inv(), 0.0, w, st));
-    HIP_TRY(hipMemcpyAsync(A->hpin, A->H(), sizeof(double) * (ncols + 1), hipMemcpyDeviceToHost, st));
+    if (!to_host) return PP_OK;
+    HIP_TRY(hipMemcpyAsync(A->hpin, Hcol, sizeof(double) * (ncols + 1), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(A->errpin, A->err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return check_barrier_flag(A);
@@ -813,23 +820,38 @@ pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, vo
         set_error("pp_gmres_setup: start vector is zero or not finite");
         return PP_EINVAL;
     }
-    std::vector<double> Hbar((size_t)(d + 1) * d, 0.0);
+    // All d Arnoldi steps are queued without a host round trip: the
+    // Hessenberg columns stay in device memory and the host looks for a
+    // breakdown once at the end (steps after a breakdown are discarded).
     const int ld = d + 1;
+    double *Hdev = nullptr;
+    PP_TRY(dev_alloc(&Hdev, (size_t)ld * d));
+    struct Free {
+        double *p;
+        ~Free() { dev_free(p); }
+    } free_h{Hdev};
+    HIP_TRY(hipMemsetAsync(Hdev, 0, sizeof(double) * ld * d, st));
+    for (int j = 0; j < d; ++j) {
+        PP_TRY(spmv_axpby(A, 0, vcol(ws, 0, j), 1.0, nullptr, 0.0, vcol(ws, 0, j + 1), st));
+        PP_TRY(cgs2_step(A, 0, ws, j, st, Hdev + (size_t)j * ld, false));
+    }
+    std::vector<double> Hbar((size_t)ld * d, 0.0);
+    HIP_TRY(hipMemcpyAsync(Hbar.data(), Hdev, sizeof(double) * ld * d, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(A->errpin, A->err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    PP_TRY(check_barrier_flag(A));
     int k = d;
     bool brk = false;
     double fro2 = 0.0;
     int64_t dots = 1;
     for (int j = 0; j < d; ++j) {
-        PP_TRY(spmv_axpby(A, 0, vcol(ws, 0, j), 1.0, nullptr, 0.0, vcol(ws, 0, j + 1), st));
-        PP_TRY(cgs2_step(A, 0, ws, j, st));
         dots += 2 * (j + 1) + 1;
         for (int i = 0; i <= j + 1; ++i) {
-            const double h = A->hpin[i];
+            const double h = Hbar[(size_t)i + (size_t)j * ld];
             if (!std::isfinite(h)) {
                 set_error("pp_gmres_setup: non-finite Hessenberg entry");
                 return PP_EINVAL;
             }
-            Hbar[(size_t)i + (size_t)j * ld] = h;
             fro2 += h * h;
         }
         if (Hbar[(size_t)(j + 1) + (size_t)j * ld] <= kBreakdownTol * std::sqrt(fro2)) {
@@ -949,6 +971,7 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
     pp_status status = PP_OK;
     for (;;) {
         const double relres = beta / bnorm;
+        if (opts->history && (int)hist.size() < opts->history_cap) opts->history[hist.size()] = relres;
         hist.push_back(relres);
         inf.relres = relres;
         if (relres <= opts->tol) {
@@ -975,7 +998,8 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
         // V[:,0] = r / beta in the cycle's precision
         HIP_TRY(launch_scale_cast(0, prec, n, A->r64, nullptr, 1.0 / beta, vcol(ws, prec, 0), st));
         ls.reset(m, beta);
-        const double target = std::max(opts->tol * bnorm, kInnerEta[prec] * beta);
+        const double eta = (prec != PP_F64 && opts->inner_eta > 0.0) ? opts->inner_eta : kInnerEta[prec];
+        const double target = std::max(opts->tol * bnorm, eta * beta);
         double fro2 = 0.0;
         int k = 0;
         for (int j = 0; j < m; ++j) {

@@ -45,8 +45,8 @@ struct PStep {
 };
 const char *chain_variant_name(int v);
 constexpr int kRedBlock = 256;       // threads per reduction workgroup
-constexpr int kDotRows = 2048;       // rows per dot-product workgroup
-constexpr int kDotCols = 8;          // Krylov columns per dot-product pass
+constexpr int kDotRows = 1024;       // rows per dot-product workgroup
+constexpr int kDotCols = 16;         // Krylov columns per dot-product pass
 
 // Pointers of one fused chain step (see Step in poly.h).
 struct StepPtrs {
@@ -129,6 +129,12 @@ int update_dots_blocks(int n);
 int update_dots_max_cols(int prec);
 hipError_t launch_update_dots(int prec, int n, const void *V, long ldv, int ncols, const double *h, void *w,
                               double *partial, int ldp, hipStream_t st);
+// (partial column ncols of launch_update_dots holds the block's ||w_new||^2)
+// H[k] += h2[k]; H[ncols] = sqrt(h2[ncols] - ||h2||^2); inv[0] = 1/H[ncols] (0 if 0).
+hipError_t launch_finish_col(int ncols, const double *h2, double *H, double *inv, hipStream_t st);
+// w = (w - V h) * inv[0]
+hipError_t launch_update_scale(int prec, int n, const void *V, long ldv, int ncols, const double *h, void *w,
+                               const double *inv, hipStream_t st);
 // norm = sqrt(sum_b partial[b]); writes H[0] = norm, inv[0] = 1/norm (0 if norm == 0).
 hipError_t launch_reduce_norm(int nblk, const double *partial, double *H, double *inv, hipStream_t st);
 // out[i] = (T_out)(in[i] * s) with s = scale[0] (device) or, if scale is null,

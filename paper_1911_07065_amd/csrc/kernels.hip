@@ -817,12 +817,14 @@ __global__ __launch_bounds__(256) void k_update_dots(int n, const XT *V, long ld
     using AT = typename Arith<XT>::T;
     __shared__ double hs[KMAX];
     __shared__ double sm[4][KMAX];
+    __shared__ double sm2[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid < KMAX) hs[tid] = tid < ncols ? h[tid] : 0.0;
     __syncthreads();
     AT acc[KMAX];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) acc[k] = AT(0);
+    double sq = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const long i = ((long)blockIdx.x * RPT + q) * 256 + tid;
@@ -834,7 +836,9 @@ __global__ __launch_bounds__(256) void k_update_dots(int n, const XT *V, long ld
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) wi -= (double)vr[k] * hs[k];
             stx(w, i, (AT)wi);
-            const AT ws = (AT)stored_value(w, wi);
+            const double wst = stored_value(w, wi);
+            sq += wst * wst;
+            const AT ws = (AT)wst;
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) acc[k] += vr[k] * ws;
         }
@@ -844,8 +848,50 @@ __global__ __launch_bounds__(256) void k_update_dots(int n, const XT *V, long ld
         const double t = wave_sum((double)acc[k]);
         if (lane == 0) sm[wave][k] = t;
     }
+    sq = wave_sum(sq);
+    if (lane == 0) sm2[wave] = sq;
     __syncthreads();
     if (tid < ncols) partial[(long)blockIdx.x * ldp + tid] = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
+    if (tid == 0) partial[(long)blockIdx.x * ldp + ncols] = ((sm2[0] + sm2[1]) + sm2[2]) + sm2[3];
+}
+
+// After the fused pass: H[k] += h2[k] (k < ncols), and the norm of the final
+// vector w'' = w' - V h2 from ||w''||^2 = ||w'||^2 - ||h2||^2 (h2[ncols] holds
+// ||w'||^2; h2 is the small reorthogonalisation correction, so there is no
+// cancellation). Writes H[ncols] = ||w''||, inv[0] = 1/||w''|| (0 if zero).
+__global__ __launch_bounds__(256) void k_finish_col(int ncols, const double *h2, double *H, double *inv) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < ncols; k += 256) {
+        s += h2[k] * h2[k];
+        H[k] += h2[k];
+    }
+    s = block_sum256(s, red);
+    if (threadIdx.x == 0) {
+        const double nrm = sqrt(fmax(h2[ncols] - s, 0.0));
+        H[ncols] = nrm;
+        inv[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    }
+}
+
+// w <- (w - V h) * inv[0]: the last update of Gram-Schmidt fused with the
+// normalisation.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_update_scale(int n, const XT *V, long ldv, int ncols, const double *h, XT *w,
+                                                      const double *inv) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int k = 0;
+    for (; k + 4 <= ncols; k += 4) {
+        acc0 += (double)ldx(V, i + (long)k * ldv) * h[k];
+        acc1 += (double)ldx(V, i + (long)(k + 1) * ldv) * h[k + 1];
+        acc2 += (double)ldx(V, i + (long)(k + 2) * ldv) * h[k + 2];
+        acc3 += (double)ldx(V, i + (long)(k + 3) * ldv) * h[k + 3];
+    }
+    for (; k < ncols; ++k) acc0 += (double)ldx(V, i + (long)k * ldv) * h[k];
+    const double wn = ((double)ldx(w, i) - ((acc0 + acc1) + (acc2 + acc3))) * inv[0];
+    stx(w, i, (typename Arith<XT>::T)wn);
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_reduce_norm(int nblk, const double *partial, double *H,
@@ -1276,6 +1322,34 @@ hipError_t persist_max_grid(int prec, int *grid) {
     if (e != hipSuccess) return e;
     *grid = per * ncu;
     return hipSuccess;
+}
+
+hipError_t launch_finish_col(int ncols, const double *h2, double *H, double *inv, hipStream_t st) {
+    hipLaunchKernelGGL(k_finish_col, dim3(1), dim3(256), 0, st, ncols, h2, H, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_scale(int prec, int n, const void *V, long ldv, int ncols, const double *h, void *w,
+                               const double *inv, hipStream_t st) {
+    const unsigned g = blocks_for(n, 256);
+    if (g == 0) return hipSuccess;
+    switch (prec) {
+        case 0:
+            hipLaunchKernelGGL(k_update_scale<double>, dim3(g), dim3(256), 0, st, n, (const double *)V, ldv, ncols, h,
+                               (double *)w, inv);
+            break;
+        case 1:
+            hipLaunchKernelGGL(k_update_scale<float>, dim3(g), dim3(256), 0, st, n, (const float *)V, ldv, ncols, h,
+                               (float *)w, inv);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_update_scale<uint16_t>, dim3(g), dim3(256), 0, st, n, (const uint16_t *)V, ldv, ncols,
+                               h, (uint16_t *)w, inv);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 void build_tiles(const int32_t *rp, int n, int row_cap, int nnz_cap, std::vector<int4> &out) {
