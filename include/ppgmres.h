@@ -222,6 +222,49 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
 pp_status pp_stability_check(pp_poly p, pp_matrix A, const double *b, void *stream, double *stch);
 
 /* ------------------------------------------------------------------ */
+/* Batched systems                                                      */
+/* ------------------------------------------------------------------ */
+
+typedef struct pp_batch_s *pp_batch;
+
+/* Wrap many independent square systems given as one block-diagonal CSR
+ * matrix in device memory: system s owns rows and columns
+ * [row_off[s], row_off[s+1]) (row_off: host int64[nsys+1], row_off[0] = 0),
+ * and every stored entry of a row lies in its system's diagonal block
+ * (checked; PP_EINVAL otherwise). rowptr: device int32[n+1], colind: device
+ * int32[nnz] (global column indices), val: device double[nnz]; copied into a
+ * sliced-ELL form (64-row slices inside each system), so the arrays may be
+ * freed after the call. */
+pp_status pp_batch_create(int nsys, const int64_t *row_off, int64_t nnz, const int32_t *rowptr,
+                          const int32_t *colind, const double *val, void *stream, pp_batch *out);
+
+/* New values for the same pattern (device double[nnz]). */
+pp_status pp_batch_set_values(pp_batch B, const double *val, void *stream);
+
+void pp_batch_destroy(pp_batch B);
+
+/* One polynomial per system (Algorithm 4 step 1 for every system at once):
+ * GMRES(d) on each diagonal block from the matching slice of v0 (device
+ * double[n]), all systems advanced in lockstep; harmonic Ritz values, Leja
+ * order and added roots per system on the host. polys: host array of nsys
+ * handles to receive the polynomials (each freed with pp_poly_destroy);
+ * infos: host array of nsys or NULL. PP_BREAKDOWN if some system's Krylov
+ * space became invariant (its degree is lowered). */
+pp_status pp_batch_setup(pp_batch B, const double *v0, int d, int add_roots, void *stream, pp_poly *polys,
+                         pp_setup_info *infos);
+
+/* Solve every system for nrhs (1, 2 or 4) right-hand sides by PP-GMRES,
+ * all (system, right-hand side) pairs in lockstep: each pair has its own
+ * Krylov basis, Hessenberg matrix and stopping test, each system its own
+ * polynomial (polys: host array of nsys). b, x: device double[n * nrhs],
+ * interleaved (entry (row i, rhs r) at i*nrhs + r); x is overwritten.
+ * opts as for pp_solve (opts->history receives pair 0's residuals). infos:
+ * host array of nsys*nrhs (pair s*nrhs + r) or NULL. PP_NOCONV if some pair
+ * did not converge. */
+pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const double *b, double *x,
+                         const pp_solve_opts *opts, void *stream, pp_info *infos);
+
+/* ------------------------------------------------------------------ */
 /* Host-only building blocks (deterministic; no device work)            */
 /* ------------------------------------------------------------------ */
 

@@ -57,6 +57,14 @@ SIGNATURES = {
     "pp_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts), c_void_p,
                          ctypes.POINTER(SolveInfo)]),
     "pp_stability_check": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, P_double]),
+    "pp_batch_create": (c_int, [c_int, ctypes.POINTER(c_int64), c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                ctypes.POINTER(c_void_p)]),
+    "pp_batch_set_values": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "pp_batch_destroy": (None, [c_void_p]),
+    "pp_batch_setup": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p),
+                               ctypes.POINTER(SetupInfo)]),
+    "pp_batch_solve": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_int, c_void_p, c_void_p,
+                               ctypes.POINTER(SolveOpts), c_void_p, ctypes.POINTER(SolveInfo)]),
     "pp_harmonic_ritz": (c_int, [c_int, P_double, c_int, P_double, P_double]),
     "pp_hessenberg_eig": (c_int, [c_int, P_double, c_int, P_double, P_double]),
     "pp_leja_order": (c_int, [c_int, P_double, P_double, P_int]),

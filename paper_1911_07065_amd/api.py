@@ -361,3 +361,105 @@ def hessenberg_eig(h: np.ndarray) -> np.ndarray:
     check(lib.pp_hessenberg_eig(k, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), k, _dp(re), _dp(im)),
           "pp_hessenberg_eig")
     return re + 1j * im
+
+
+# ---------------------------------------------------------------------------
+# batched systems
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """Many independent systems solved in lockstep (block-diagonal CSR on the GPU).
+
+    csrs: list of host CSR objects (rowptr/colind/val arrays, e.g. workloads.CSR).
+    Vectors of the batch are concatenated over systems; with R right-hand
+    sides they are interleaved (see interleave / deinterleave).
+    """
+
+    def __init__(self, csrs, device="cuda"):
+        sizes = np.array([c.n for c in csrs], dtype=np.int64)
+        self.row_off = np.zeros(len(csrs) + 1, dtype=np.int64)
+        np.cumsum(sizes, out=self.row_off[1:])
+        nnzs = np.array([int(c.rowptr[-1]) for c in csrs], dtype=np.int64)
+        nnz_off = np.zeros(len(csrs) + 1, dtype=np.int64)
+        np.cumsum(nnzs, out=nnz_off[1:])
+        rp = np.empty(int(self.row_off[-1]) + 1, dtype=np.int64)
+        rp[0] = 0
+        cols, vals = [], []
+        for s, c in enumerate(csrs):
+            r0 = int(self.row_off[s])
+            rp[r0 + 1: r0 + 1 + c.n] = np.asarray(c.rowptr[1:], dtype=np.int64) + nnz_off[s]
+            cols.append(np.asarray(c.colind, dtype=np.int64) + r0)
+            vals.append(np.asarray(c.val, dtype=np.float64))
+        self.nsys = len(csrs)
+        self.n = int(self.row_off[-1])
+        self.nnz = int(nnz_off[-1])
+        rowptr = _dev_tensor(rp.astype(np.int32), torch.int32, device)
+        colind = _dev_tensor(np.concatenate(cols).astype(np.int32), torch.int32, device)
+        val = _dev_tensor(np.concatenate(vals), torch.float64, device)
+        self.device = val.device
+        h = ctypes.c_void_p()
+        ro = np.ascontiguousarray(self.row_off)
+        check(lib.pp_batch_create(self.nsys, ro.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), self.nnz,
+                                  _ptr(rowptr), _ptr(colind), _ptr(val), _stream(self.device), ctypes.byref(h)),
+              "pp_batch_create")
+        torch.cuda.synchronize(self.device)
+        self.handle = h
+
+    def interleave(self, vecs):
+        """(R, n) host/device rows -> device vector of n*R values, entry (i, r) at i*R + r."""
+        t = torch.as_tensor(vecs, dtype=torch.float64, device=self.device)
+        if t.dim() == 1:
+            t = t[None, :]
+        return t.t().contiguous().reshape(-1)
+
+    @staticmethod
+    def deinterleave(x, R):
+        return x.reshape(-1, R).t()
+
+    def setup(self, v0, d: int, add_roots: bool = True):
+        """One polynomial per system from GMRES(d) on each block (lockstep)."""
+        v0 = _dev_tensor(v0, torch.float64, self.device)
+        if v0.numel() != self.n:
+            raise ValueError("start vector length")
+        hs = (ctypes.c_void_p * self.nsys)()
+        infos = (SetupInfo * self.nsys)()
+        st = check(lib.pp_batch_setup(self.handle, _ptr(v0), int(d), int(bool(add_roots)), _stream(self.device), hs,
+                                      infos), "pp_batch_setup")
+        out = []
+        for s in range(self.nsys):
+            si = {k: getattr(infos[s], k) for k, _ in SetupInfo._fields_}
+            out.append(_poly_from_handle(ctypes.c_void_p(hs[s]), si, breakdown=bool(infos[s].breakdown)))
+        return out
+
+    def solve(self, polys, b, R: int, tol: float = 1e-8, m: int = 50, max_cycles: int = 1000, inner: str = "fp32",
+              stall_cycles: int = 5, inner_eta: float = 0.0):
+        """x for every (system, rhs) pair; b interleaved (n*R). Returns (x, list of info dicts per pair)."""
+        b = _dev_tensor(b, torch.float64, self.device)
+        if b.numel() != self.n * R:
+            raise ValueError("right-hand side length")
+        x = torch.empty_like(b)
+        hs = (ctypes.c_void_p * self.nsys)(*[p.handle.value for p in polys])
+        hist = np.zeros(max(int(max_cycles), 0) + 2)
+        opts = SolveOpts(int(m), int(max_cycles), float(tol), PREC[inner], int(stall_cycles), float(inner_eta),
+                         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hist.size)
+        P = self.nsys * R
+        infos = (SolveInfo * P)()
+        check(lib.pp_batch_solve(self.handle, hs, int(R), _ptr(b), _ptr(x), ctypes.byref(opts), _stream(self.device),
+                                 infos), "pp_batch_solve")
+        out = []
+        for p in range(P):
+            d = {k: getattr(infos[p], k) for k, _ in SolveInfo._fields_}
+            d["converged"] = d["status"] != PP_NOCONV
+            out.append(d)
+        return x, out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is None or not h.value or lib is None:
+            return
+        try:
+            torch.cuda.synchronize(self.device)
+            lib.pp_batch_destroy(h)
+        except Exception:
+            pass
+        self.handle = None

@@ -16,7 +16,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["kernels.hip", "driver.hip"]
+HIP_SOURCES = ["kernels.hip", "driver.hip", "batched.hip", "batch_driver.hip"]
 HOST_SOURCES = ["host_core.cpp", "poly.cpp"]
 
 HIP_FLAGS = [

@@ -1,0 +1,705 @@
+// C ABI of the batched path: many independent systems (a block-diagonal
+// matrix) with R right-hand sides each, solved by PP-GMRES in lockstep. Each
+// system has its own polynomial (its own harmonic Ritz values), each
+// (system, right-hand side) pair its own Krylov process, Hessenberg matrix
+// and stopping test; every chain step and every Gram-Schmidt pass is one
+// launch for the whole batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ppgmres.h"
+#include "batched.h"
+#include "common.h"
+#include "host_core.h"
+#include "kernels.h"
+#include "poly.h"
+
+using namespace ppg;
+
+namespace {
+
+constexpr double kBreakdownTolB = 1e-14;
+constexpr double kInnerEtaB[3] = {0.0, 1e-5, 1e-2};
+constexpr int kBlockRows = 1024;  // rows per reduction block (system-aligned)
+
+struct BWork {
+    int m = -1, R = 0;
+    long ldv = 0;
+    void *V = nullptr;
+    void *buf = nullptr;  // P0 | P1 | T | D | ACC
+    long vec = 0;         // bytes per vector
+    void *P(int i) const { return (char *)buf + (size_t)i * vec; }
+};
+
+}  // namespace
+
+struct pp_batch_s {
+    int nsys = 0;
+    long n = 0, nnz = 0;
+    std::vector<long> row_off;
+    // sliced-ELL of the batch
+    int4 *slice = nullptr;
+    int32_t *sptr = nullptr, *scol = nullptr, *sperm = nullptr;
+    double *sval64 = nullptr;
+    float *sval32 = nullptr;
+    int nslices = 0;
+    long npad = 0;
+    // reduction blocks
+    int4 *block = nullptr;
+    int32_t *boff = nullptr;
+    int nblocks = 0;
+    // work
+    BWork ws[3];
+    int ldp = 0, ldh = 0;
+    double *partial = nullptr, *npart = nullptr, *h1 = nullptr, *h2 = nullptr, *inv = nullptr;
+    double *Hc = nullptr, *z = nullptr;      // pairs x ldh
+    double *hpin = nullptr, *zpin = nullptr;  // pinned mirrors
+    double *r64 = nullptr;                    // n*R (FP64)
+    long r64_len = 0;
+    int pairs_cap = 0;
+    PStep *desc_spmv = nullptr, *desc_res = nullptr;  // nsys x 1 uniform programs
+
+    int *act = nullptr;     // device: per-system active flags of the Arnoldi loop
+    int *actpin = nullptr;  // pinned mirror
+    int *kdev = nullptr;    // device: columns per pair of the last cycle
+    int *kpin = nullptr;
+    BatchSell sell(int, bool masked = false) const {
+        BatchSell s;
+        s.active = masked ? act : nullptr;
+        s.slice = slice;
+        s.sptr = sptr;
+        s.scol = scol;
+        s.sval64 = sval64;
+        s.sval32 = sval32;
+        s.nslices = nslices;
+        return s;
+    }
+    BatchBlocks blocks(bool masked = false) const {
+        BatchBlocks b;
+        b.active = masked ? act : nullptr;
+        b.block = block;
+        b.boff = boff;
+        b.nblocks = nblocks;
+        b.nsys = nsys;
+        return b;
+    }
+    void free_ws(BWork &w) {
+        dev_free(w.V);
+        dev_free(w.buf);
+        w.m = -1;
+        w.R = 0;
+    }
+    pp_status ensure(int prec, int m, int R) {
+        BWork &w = ws[prec];
+        if (w.m >= m && w.R == R && w.V) return PP_OK;
+        free_ws(w);
+        const size_t es = elem_size(prec);
+        w.ldv = (n * R + 63) / 64 * 64;
+        w.vec = (long)(w.ldv * es);
+        char *p = nullptr;
+        PP_TRY(dev_alloc(&p, (size_t)w.vec * (m + 1)));
+        w.V = p;
+        char *q = nullptr;
+        PP_TRY(dev_alloc(&q, (size_t)w.vec * 5));
+        w.buf = q;
+        w.m = m;
+        w.R = R;
+        return PP_OK;
+    }
+    // reduction buffers for `cols` Krylov columns and R right-hand sides
+    pp_status ensure_red(int cols, int R) {
+        const int want_p = (cols + 2) * R;
+        const int pairs = nsys * R;
+        if (want_p <= ldp && cols + 2 <= ldh && pairs <= pairs_cap && (long)n * R <= r64_len) return PP_OK;
+        dev_free(partial);
+        dev_free(npart);
+        dev_free(h1);
+        dev_free(h2);
+        dev_free(inv);
+        dev_free(Hc);
+        dev_free(z);
+        dev_free(r64);
+        dev_free(kdev);
+        if (hpin) (void)hipHostFree(hpin);
+        if (zpin) (void)hipHostFree(zpin);
+        if (kpin) (void)hipHostFree(kpin);
+        hpin = zpin = nullptr;
+        kpin = nullptr;
+        ldp = std::max(want_p, 64);
+        ldh = std::max(cols + 2, 64);
+        pairs_cap = pairs;
+        r64_len = (long)n * R;
+        PP_TRY(dev_alloc(&partial, (size_t)nblocks * ldp));
+        PP_TRY(dev_alloc(&npart, (size_t)nblocks * R));
+        PP_TRY(dev_alloc(&h1, (size_t)nsys * ldp));
+        PP_TRY(dev_alloc(&h2, (size_t)nsys * ldp));
+        PP_TRY(dev_alloc(&inv, (size_t)pairs));
+        PP_TRY(dev_alloc(&Hc, (size_t)pairs * ldh));
+        PP_TRY(dev_alloc(&z, (size_t)pairs * ldh));
+        PP_TRY(dev_alloc(&r64, (size_t)n * R));
+        PP_TRY(dev_alloc(&kdev, (size_t)pairs));
+        if (hipHostMalloc((void **)&hpin, sizeof(double) * pairs * ldh, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&zpin, sizeof(double) * pairs * ldh, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&kpin, sizeof(int) * pairs, hipHostMallocDefault) != hipSuccess) {
+            set_error("hipHostMalloc failed");
+            return PP_ENOMEM;
+        }
+        return PP_OK;
+    }
+    ~pp_batch_s() {
+        for (auto &w : ws) free_ws(w);
+        dev_free(slice);
+        dev_free(sptr);
+        dev_free(scol);
+        dev_free(sperm);
+        dev_free(sval64);
+        dev_free(sval32);
+        dev_free(block);
+        dev_free(boff);
+        dev_free(partial);
+        dev_free(npart);
+        dev_free(h1);
+        dev_free(h2);
+        dev_free(inv);
+        dev_free(Hc);
+        dev_free(z);
+        dev_free(r64);
+        dev_free(desc_spmv);
+        dev_free(desc_res);
+        dev_free(act);
+        dev_free(kdev);
+        if (actpin) (void)hipHostFree(actpin);
+        if (kpin) (void)hipHostFree(kpin);
+        if (hpin) (void)hipHostFree(hpin);
+        if (zpin) (void)hipHostFree(zpin);
+    }
+};
+
+namespace {
+
+PStep pstep_of(const Step &s) {
+    PStep p;
+    std::memset(&p, 0, sizeof(p));
+    p.spmv = s.spmv;
+    p.in = s.in;
+    p.aux = s.aux;
+    p.out = s.out;
+    p.acc = s.acc;
+    p.acc_init = s.acc_init;
+    p.fin = s.fin;
+    p.a0 = s.a0;
+    p.a1 = s.a1;
+    p.a2 = s.a2;
+    p.b0 = s.b0;
+    p.b1 = s.b1;
+    return p;
+}
+
+PStep skip_step() {
+    PStep p;
+    std::memset(&p, 0, sizeof(p));
+    p.spmv = -1;
+    p.in = 0;
+    p.aux = p.out = p.acc = -1;
+    return p;
+}
+
+pp_status upload(const std::vector<PStep> &h, PStep **dst, hipStream_t st) {
+    PP_TRY(dev_alloc(dst, h.size()));
+    HIP_TRY(hipMemcpyAsync(*dst, h.data(), sizeof(PStep) * h.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return PP_OK;
+}
+
+// Per-system programs padded to a common length with skipped steps.
+pp_status upload_programs(pp_batch B, const pp_poly *polys, int kind, PStep **dst, int *K, hipStream_t st) {
+    int kmax = 0;
+    for (int s = 0; s < B->nsys; ++s) {
+        const auto &prog = kind == PP_APPLY_P ? polys[s]->prog_p : polys[s]->prog_phi;
+        kmax = std::max(kmax, (int)prog.size());
+    }
+    std::vector<PStep> h((size_t)B->nsys * kmax, skip_step());
+    for (int s = 0; s < B->nsys; ++s) {
+        const auto &prog = kind == PP_APPLY_P ? polys[s]->prog_p : polys[s]->prog_phi;
+        for (size_t k = 0; k < prog.size(); ++k) h[(size_t)s * kmax + k] = pstep_of(prog[k]);
+    }
+    *K = kmax;
+    return upload(h, dst, st);
+}
+
+pp_status run_bprog(pp_batch B, int prec, int R, const PStep *desc, int K, const void *in, void *out,
+                    const BWork &w, hipStream_t st, bool masked = false) {
+    void *bufs[5] = {(void *)in, out, w.P(0), w.P(1), w.P(2)};
+    for (int k = 0; k < K; ++k) HIP_TRY(launch_bchain(B->sell(prec, masked), prec, R, desc, K, k, bufs, st));
+    return PP_OK;
+}
+
+void *bcol(const BWork &w, int prec, int j) { return (char *)w.V + (size_t)j * w.ldv * elem_size(prec); }
+
+// CGS2 of column j+1 against columns 0..j for every pair; H column base
+// Hbase (pair stride pstride): H[0..j] and H[j+1] = norm; w normalised.
+pp_status bcgs2(pp_batch B, int prec, int R, const BWork &w, int j, double *Hbase, long pstride, hipStream_t st,
+                bool masked = false) {
+    const BatchBlocks bl = B->blocks(masked);
+    const int ncols = j + 1;
+    void *wv = bcol(w, prec, j + 1);
+    HIP_TRY(launch_bdots(bl, prec, R, w.V, w.ldv, ncols, wv, B->partial, B->ldp, st));
+    HIP_TRY(launch_bred(bl, R, B->partial, B->ldp, ncols * R, B->h1, B->ldp, Hbase, pstride, 1, st));
+    HIP_TRY(launch_bupdate(bl, prec, R, w.V, w.ldv, ncols, B->h1, B->ldp, wv, nullptr, st));
+    HIP_TRY(launch_bdots(bl, prec, R, w.V, w.ldv, ncols, wv, B->partial, B->ldp, st));
+    HIP_TRY(launch_bred(bl, R, B->partial, B->ldp, ncols * R, B->h2, B->ldp, Hbase, pstride, 2, st));
+    HIP_TRY(launch_bupdate(bl, prec, R, w.V, w.ldv, ncols, B->h2, B->ldp, wv, B->npart, st));
+    HIP_TRY(launch_bnorm(bl, R, B->npart, Hbase + ncols, pstride, B->inv, st));
+    HIP_TRY(launch_bscale(bl, prec, prec, R, wv, B->inv, wv, st));
+    return PP_OK;
+}
+
+// ||v_p|| for every pair of an FP64 vector (synchronises; result in out[p])
+pp_status bnorms(pp_batch B, int R, const double *v, std::vector<double> &out, hipStream_t st) {
+    const BatchBlocks bl = B->blocks();
+    HIP_TRY(launch_bdots(bl, 0, R, v, 0, 1, v, B->partial, B->ldp, st));
+    HIP_TRY(launch_bred(bl, R, B->partial, B->ldp, R, B->h1, B->ldp, nullptr, 0, 0, st));
+    // h1[s*ldp + r] -> host
+    HIP_TRY(hipMemcpy2DAsync(B->hpin, sizeof(double) * R, B->h1, sizeof(double) * B->ldp, sizeof(double) * R, B->nsys,
+                             hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    out.resize((size_t)B->nsys * R);
+    for (size_t p = 0; p < out.size(); ++p) out[p] = std::sqrt(B->hpin[p]);
+    return PP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pp_status pp_batch_create(int nsys, const int64_t *row_off, int64_t nnz, const int32_t *rowptr, const int32_t *colind,
+                          const double *val, void *stream, pp_batch *out) {
+    if (nsys <= 0 || !row_off || !rowptr || !out || nnz < 0 || nnz >= (1LL << 31) || (nnz > 0 && (!colind || !val))) {
+        set_error("pp_batch_create: bad argument");
+        return PP_EINVAL;
+    }
+    const int64_t n = row_off[nsys];
+    if (row_off[0] != 0 || n <= 0 || n >= (1LL << 31)) {
+        set_error("pp_batch_create: row offsets must start at 0 and end below 2^31");
+        return PP_EINVAL;
+    }
+    for (int s = 0; s < nsys; ++s)
+        if (row_off[s + 1] <= row_off[s]) {
+            set_error("pp_batch_create: every system needs at least one row");
+            return PP_EINVAL;
+        }
+    hipStream_t st = S(stream);
+    auto *B = new (std::nothrow) pp_batch_s();
+    if (!B) return PP_ENOMEM;
+    auto fail = [&](pp_status s) {
+        delete B;
+        return s;
+    };
+    B->nsys = nsys;
+    B->n = n;
+    B->nnz = nnz;
+    B->row_off.assign(row_off, row_off + nsys + 1);
+    std::vector<int32_t> rp(n + 1), ci(nnz);
+    if (hipMemcpyAsync(rp.data(), rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        (nnz && hipMemcpyAsync(ci.data(), colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st) != hipSuccess) ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("pp_batch_create: cannot read the pattern");
+        return fail(PP_EDEVICE);
+    }
+    if (rp[0] != 0 || rp[n] != nnz) {
+        set_error("pp_batch_create: rowptr[0] must be 0 and rowptr[n] must be nnz");
+        return fail(PP_EINVAL);
+    }
+    // block-diagonal check: the columns of a row stay inside its system
+    for (int s = 0; s < nsys; ++s)
+        for (long r = row_off[s]; r < row_off[s + 1]; ++r) {
+            if (rp[r + 1] < rp[r]) {
+                set_error("pp_batch_create: rowptr not non-decreasing");
+                return fail(PP_EINVAL);
+            }
+            for (int e = rp[r]; e < rp[r + 1]; ++e)
+                if (ci[e] < row_off[s] || ci[e] >= row_off[s + 1]) {
+                    set_error("pp_batch_create: entry outside its system's diagonal block");
+                    return fail(PP_EINVAL);
+                }
+        }
+    // sliced-ELL: 64-row slices inside each system
+    std::vector<int4> sl;
+    std::vector<int32_t> sp(1, 0);
+    long tot = 0;
+    for (int s = 0; s < nsys; ++s)
+        for (long r0 = row_off[s]; r0 < row_off[s + 1]; r0 += 64) {
+            const int nr = (int)std::min<long>(64, row_off[s + 1] - r0);
+            int width = 0;
+            for (int j = 0; j < nr; ++j) width = std::max(width, rp[r0 + j + 1] - rp[r0 + j]);
+            sl.push_back(make_int4((int)r0, nr, s, 0));
+            tot += 64L * width;
+            if (tot >= (1L << 31)) {
+                set_error("pp_batch_create: padded batch too large");
+                return fail(PP_EINVAL);
+            }
+            sp.push_back((int32_t)tot);
+        }
+    std::vector<int32_t> scol(tot), sperm(tot, -1);
+    for (size_t k = 0; k < sl.size(); ++k) {
+        const int4 q = sl[k];
+        const int width = (sp[k + 1] - sp[k]) / 64;
+        for (int j = 0; j < 64; ++j) {
+            const long r = (long)q.x + j;
+            const int len = j < q.y ? rp[r + 1] - rp[r] : 0;
+            for (int c = 0; c < width; ++c) {
+                const long o = sp[k] + (long)c * 64 + j;
+                if (c < len) {
+                    scol[o] = ci[rp[r] + c];
+                    sperm[o] = rp[r] + c;
+                } else {
+                    scol[o] = j < q.y ? (int32_t)r : q.x;  // padding: a valid row of the slice, value 0
+                }
+            }
+        }
+    }
+    // reduction blocks
+    std::vector<int4> bl;
+    std::vector<int32_t> bo(1, 0);
+    for (int s = 0; s < nsys; ++s) {
+        for (long r0 = row_off[s]; r0 < row_off[s + 1]; r0 += kBlockRows)
+            bl.push_back(make_int4((int)r0, (int)std::min<long>(kBlockRows, row_off[s + 1] - r0), s, 0));
+        bo.push_back((int32_t)bl.size());
+    }
+    B->nslices = (int)sl.size();
+    B->npad = tot;
+    B->nblocks = (int)bl.size();
+    pp_status s;
+    if ((s = dev_alloc(&B->slice, sl.size())) != PP_OK || (s = dev_alloc(&B->sptr, sp.size())) != PP_OK ||
+        (s = dev_alloc(&B->scol, (size_t)std::max<long>(tot, 1))) != PP_OK ||
+        (s = dev_alloc(&B->sperm, (size_t)std::max<long>(tot, 1))) != PP_OK ||
+        (s = dev_alloc(&B->sval64, (size_t)std::max<long>(tot, 1))) != PP_OK ||
+        (s = dev_alloc(&B->sval32, (size_t)std::max<long>(tot, 1))) != PP_OK ||
+        (s = dev_alloc(&B->block, bl.size())) != PP_OK || (s = dev_alloc(&B->boff, bo.size())) != PP_OK)
+        return fail(s);
+    if (hipMemcpyAsync(B->slice, sl.data(), sizeof(int4) * sl.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(B->sptr, sp.data(), sizeof(int32_t) * sp.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        (tot && hipMemcpyAsync(B->scol, scol.data(), sizeof(int32_t) * tot, hipMemcpyHostToDevice, st) != hipSuccess) ||
+        (tot && hipMemcpyAsync(B->sperm, sperm.data(), sizeof(int32_t) * tot, hipMemcpyHostToDevice, st) != hipSuccess) ||
+        hipMemcpyAsync(B->block, bl.data(), sizeof(int4) * bl.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(B->boff, bo.data(), sizeof(int32_t) * bo.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        launch_sell_values(tot, B->sperm, val, B->sval64, B->sval32, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("pp_batch_create: device upload failed");
+        return fail(PP_EDEVICE);
+    }
+    // uniform programs: one plain sparse product, and the residual b - A x
+    std::vector<PStep> d1(nsys), dr(nsys);
+    for (int q = 0; q < nsys; ++q) {
+        std::memset(&d1[q], 0, sizeof(PStep));
+        d1[q].spmv = 1;
+        d1[q].in = B_IN;
+        d1[q].out = B_OUT;
+        d1[q].aux = d1[q].acc = -1;
+        d1[q].a0 = 1.0;
+        dr[q] = d1[q];
+        dr[q].aux = B_P0;  // b
+        dr[q].a0 = -1.0;
+        dr[q].a2 = 1.0;
+    }
+    if ((s = upload(d1, &B->desc_spmv, st)) != PP_OK || (s = upload(dr, &B->desc_res, st)) != PP_OK) return fail(s);
+    if ((s = dev_alloc(&B->act, (size_t)nsys)) != PP_OK) return fail(s);
+    if (hipHostMalloc((void **)&B->actpin, sizeof(int) * nsys, hipHostMallocDefault) != hipSuccess) {
+        B->actpin = nullptr;
+        set_error("hipHostMalloc failed");
+        return fail(PP_ENOMEM);
+    }
+    *out = B;
+    return PP_OK;
+}
+
+void pp_batch_destroy(pp_batch B) { delete B; }
+
+pp_status pp_batch_set_values(pp_batch B, const double *val, void *stream) {
+    if (!B || (!val && B->nnz > 0)) {
+        set_error("pp_batch_set_values: bad argument");
+        return PP_EINVAL;
+    }
+    HIP_TRY(launch_sell_values(B->npad, B->sperm, val, B->sval64, B->sval32, S(stream)));
+    return PP_OK;
+}
+
+pp_status pp_batch_setup(pp_batch B, const double *v0, int d, int add_roots, void *stream, pp_poly *polys,
+                         pp_setup_info *infos) {
+    if (!B || !v0 || !polys || d < 1 || d > 4096) {
+        set_error("pp_batch_setup: bad argument");
+        return PP_EINVAL;
+    }
+    for (int s = 0; s < B->nsys; ++s)
+        if (B->row_off[s + 1] - B->row_off[s] < d) {
+            set_error("pp_batch_setup: degree above a system's size");
+            return PP_EINVAL;
+        }
+    hipStream_t st = S(stream);
+    const double t0 = now_s();
+    const int R = 1, prec = 0;
+    PP_TRY(B->ensure(prec, d, R));
+    PP_TRY(B->ensure_red(d + 1, R));
+    const BWork &w = B->ws[prec];
+    const BatchBlocks bl = B->blocks();
+    // V0 = v0 / ||v0|| per system
+    void *v0c = bcol(w, prec, 0);
+    HIP_TRY(hipMemcpyAsync(v0c, v0, sizeof(double) * B->n, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(launch_bupdate(bl, prec, R, w.V, w.ldv, 0, B->h1, B->ldp, v0c, B->npart, st));
+    HIP_TRY(launch_bnorm(bl, R, B->npart, nullptr, 0, B->inv, st));
+    HIP_TRY(launch_bscale(bl, prec, prec, R, v0c, B->inv, v0c, st));
+    const int ld = d + 1;
+    const long pstride = (long)ld * d;
+    double *Hs = nullptr;
+    PP_TRY(dev_alloc(&Hs, (size_t)B->nsys * pstride));
+    struct Free {
+        double *p;
+        ~Free() { dev_free(p); }
+    } fh{Hs};
+    HIP_TRY(hipMemsetAsync(Hs, 0, sizeof(double) * B->nsys * pstride, st));
+    for (int j = 0; j < d; ++j) {
+        void *bufs[5] = {bcol(w, prec, j), bcol(w, prec, j + 1), w.P(0), w.P(1), w.P(2)};
+        HIP_TRY(launch_bchain(B->sell(prec), prec, R, B->desc_spmv, 1, 0, bufs, st));
+        PP_TRY(bcgs2(B, prec, R, w, j, Hs + (size_t)j * ld, pstride, st));
+    }
+    std::vector<double> H((size_t)B->nsys * pstride);
+    HIP_TRY(hipMemcpyAsync(H.data(), Hs, sizeof(double) * H.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<pp_poly> made;
+    pp_status worst = PP_OK;
+    for (int s = 0; s < B->nsys; ++s) {
+        const double *Hb = H.data() + (size_t)s * pstride;
+        int k = d;
+        bool brk = false;
+        double fro2 = 0.0;
+        for (int j = 0; j < d; ++j) {
+            for (int i = 0; i <= j + 1; ++i) fro2 += Hb[i + (size_t)j * ld] * Hb[i + (size_t)j * ld];
+            if (!std::isfinite(fro2)) {
+                for (auto p : made) delete p;
+                set_error("pp_batch_setup: non-finite Hessenberg entry");
+                return PP_EINVAL;
+            }
+            if (Hb[(j + 1) + (size_t)j * ld] <= kBreakdownTolB * std::sqrt(fro2)) {
+                k = j + 1;
+                brk = true;
+                break;
+            }
+        }
+        std::vector<double> hk((size_t)(k + 1) * k);
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i <= k; ++i) hk[i + (size_t)j * (k + 1)] = Hb[i + (size_t)j * ld];
+        std::vector<double> re(k), im(k);
+        int hs = harmonic_ritz(k, hk.data(), brk, re.data(), im.data());
+        auto *p = hs == PP_OK ? new (std::nothrow) pp_poly_s() : nullptr;
+        if (hs == PP_OK && !p) hs = PP_ENOMEM;
+        if (hs == PP_OK) hs = plan_roots(k, re.data(), im.data(), add_roots != 0, p->plan);
+        if (hs != PP_OK) {
+            delete p;
+            for (auto q : made) delete q;
+            set_error("pp_batch_setup: system " + std::to_string(s) + ": harmonic Ritz values failed");
+            return (pp_status)(hs < 0 ? hs : PP_ESINGULAR);
+        }
+        p->theta_re = re;
+        p->theta_im = im;
+        p->breakdown = brk ? 1 : 0;
+        p->finalize();
+        made.push_back(p);
+        if (brk && k < d) worst = PP_BREAKDOWN;
+        if (infos) {
+            infos[s].d = k;
+            infos[s].d_eff = p->plan.d_eff;
+            infos[s].n_added = p->plan.n_added;
+            infos[s].breakdown = brk ? 1 : 0;
+            infos[s].mvps = k;
+            infos[s].dots = (int64_t)k * (k + 2);
+            infos[s].t_setup_s = now_s() - t0;
+        }
+    }
+    for (int s = 0; s < B->nsys; ++s) polys[s] = made[s];
+    return worst;
+}
+
+pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const double *b, double *x,
+                         const pp_solve_opts *opts, void *stream, pp_info *infos) {
+    if (!B || !polys || !b || !x || !opts || !(nrhs == 1 || nrhs == 2 || nrhs == 4) || opts->m < 1 ||
+        opts->max_cycles < 0 || !(opts->tol > 0.0) || opts->inner < 0 || opts->inner > 2) {
+        set_error("pp_batch_solve: bad argument (nrhs must be 1, 2 or 4)");
+        return PP_EINVAL;
+    }
+    for (int s = 0; s < B->nsys; ++s)
+        if (!polys[s]) {
+            set_error("pp_batch_solve: null polynomial");
+            return PP_EINVAL;
+        }
+    hipStream_t st = S(stream);
+    const double t0 = now_s();
+    const int R = nrhs, m = opts->m;
+    const int P = B->nsys * R;
+    const long nR = B->n * R;
+    PP_TRY(B->ensure_red(m + 1, R));
+    PP_TRY(B->ensure(opts->inner, m, R));
+    const BatchBlocks bl = B->blocks();
+    PStep *dphi = nullptr, *dp = nullptr;
+    int Kphi = 0, Kp = 0;
+    PP_TRY(upload_programs(B, polys, PP_APPLY_PHI, &dphi, &Kphi, st));
+    struct Free2 {
+        PStep *a, *b;
+        ~Free2() {
+            dev_free(a);
+            dev_free(b);
+        }
+    } fp{dphi, nullptr};
+    PP_TRY(upload_programs(B, polys, PP_APPLY_P, &dp, &Kp, st));
+    fp.b = dp;
+    std::vector<pp_info> inf(P);
+    for (auto &i : inf) {
+        std::memset(&i, 0, sizeof(i));
+        i.relres_shortcut = NAN;
+    }
+    std::vector<double> bnorm, beta, beta_new;
+    PP_TRY(bnorms(B, R, b, bnorm, st));
+    HIP_TRY(launch_fill((int)nR, 0.0, x, st));
+    HIP_TRY(hipMemcpyAsync(B->r64, b, sizeof(double) * nR, hipMemcpyDeviceToDevice, st));
+    beta = bnorm;
+    std::vector<char> done(P, 0), noconv(P, 0);
+    std::vector<std::vector<double>> hist(P);
+    std::vector<GivensLS> ls(P);
+    std::vector<int> kp(P, 0);
+    int prec = opts->inner;
+    int cycles = 0;
+    for (;;) {
+        int active = 0;
+        for (int p = 0; p < P; ++p) {
+            if (done[p]) continue;
+            const double rel = bnorm[p] > 0 ? beta[p] / bnorm[p] : 0.0;
+            hist[p].push_back(rel);
+            inf[p].relres = rel;
+            const int sc = opts->stall_cycles;
+            if (rel <= opts->tol || !std::isfinite(rel)) {
+                done[p] = 1;
+                noconv[p] = !std::isfinite(rel);
+            } else if (cycles >= opts->max_cycles ||
+                       (sc > 0 && (int)hist[p].size() > sc && hist[p].back() > 0.99 * hist[p][hist[p].size() - 1 - sc])) {
+                done[p] = 1;
+                noconv[p] = 1;
+            } else {
+                ++active;
+            }
+        }
+        if (active == 0) break;
+        ++cycles;
+        if (prec == PP_F64) PP_TRY(B->ensure(0, m, R));
+        const BWork &w = B->ws[prec];
+        // V0 = r / beta for the pairs still running (0 for the others)
+        for (int p = 0; p < P; ++p) {
+            B->zpin[p] = done[p] ? 0.0 : 1.0 / beta[p];
+            inf[p].cycles += done[p] ? 0 : 1;
+            if (!done[p] && prec == PP_F64) inf[p].fp64_cycles++;
+        }
+        HIP_TRY(hipMemcpyAsync(B->inv, B->zpin, sizeof(double) * P, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_bscale(bl, 0, prec, R, B->r64, B->inv, bcol(w, prec, 0), st));
+        std::vector<char> run(P);
+        for (int p = 0; p < P; ++p) {
+            run[p] = !done[p];
+            kp[p] = 0;
+            if (run[p]) ls[p].reset(m, beta[p]);
+        }
+        const double eta = (prec != PP_F64 && opts->inner_eta > 0.0) ? opts->inner_eta : kInnerEtaB[prec];
+        std::vector<double> fro2(P, 0.0);
+        // systems with no running pair skip the Arnoldi work (their columns
+        // are never combined: z is zero beyond each pair's last step)
+        auto push_active = [&]() -> pp_status {
+            for (int q = 0; q < B->nsys; ++q) {
+                int a = 0;
+                for (int r = 0; r < R; ++r) a |= run[q * R + r];
+                B->actpin[q] = a;
+            }
+            HIP_TRY(hipMemcpyAsync(B->act, B->actpin, sizeof(int) * B->nsys, hipMemcpyHostToDevice, st));
+            return PP_OK;
+        };
+        PP_TRY(push_active());
+        for (int j = 0; j < m; ++j) {
+            PP_TRY(run_bprog(B, prec, R, dphi, Kphi, bcol(w, prec, j), bcol(w, prec, j + 1), w, st, true));
+            PP_TRY(bcgs2(B, prec, R, w, j, B->Hc, B->ldh, st, true));
+            HIP_TRY(hipMemcpyAsync(B->hpin, B->Hc, sizeof(double) * P * B->ldh, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            int still = 0;
+            for (int p = 0; p < P; ++p) {
+                if (!run[p]) continue;
+                const double *h = B->hpin + (size_t)p * B->ldh;
+                bool finite = true;
+                for (int i = 0; i <= j + 1; ++i) {
+                    finite = finite && std::isfinite(h[i]);
+                    fro2[p] += h[i] * h[i];
+                }
+                inf[p].iters++;
+                inf[p].mvps += polys[p / R]->plan.d_eff;
+                inf[p].dots += 2 * (j + 1) + 1;
+                if (!finite) {
+                    run[p] = 0;
+                    continue;
+                }
+                const double sc = ls[p].add_column(h);
+                kp[p] = j + 1;
+                inf[p].relres_shortcut = sc / bnorm[p];
+                const double target = std::max(opts->tol * bnorm[p], eta * beta[p]);
+                if (h[j + 1] <= kBreakdownTolB * std::sqrt(fro2[p]) || sc <= target)
+                    run[p] = 0;
+                else
+                    ++still;
+            }
+            if (still == 0) break;
+            PP_TRY(push_active());
+        }
+        // z per pair (zero for pairs that did not run)
+        int kmax = 0;
+        for (int p = 0; p < P; ++p) kmax = std::max(kmax, kp[p]);
+        std::vector<double> zp((size_t)P * B->ldh, 0.0);
+        for (int p = 0; p < P; ++p)
+            if (kp[p] > 0) ls[p].solve(zp.data() + (size_t)p * B->ldh);
+        std::memcpy(B->zpin, zp.data(), sizeof(double) * zp.size());
+        for (int p = 0; p < P; ++p) B->kpin[p] = kp[p];
+        HIP_TRY(hipMemcpyAsync(B->z, B->zpin, sizeof(double) * zp.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(B->kdev, B->kpin, sizeof(int) * P, hipMemcpyHostToDevice, st));
+        if (kmax > 0) {
+            HIP_TRY(launch_bcombine(bl, prec, R, w.V, w.ldv, B->kdev, B->z, B->ldh, w.P(3), st));
+            PP_TRY(run_bprog(B, prec, R, dp, Kp, w.P(3), w.P(4), w, st));
+            HIP_TRY(launch_axpy_x(prec, (int)nR, 1.0, w.P(4), x, st));
+        }
+        // true residual in FP64
+        {
+            const BWork &w64 = B->ws[0].V ? B->ws[0] : w;
+            void *bufs[5] = {x, B->r64, (void *)b, w64.P(0), w64.P(1)};
+            HIP_TRY(launch_bchain(B->sell(0), 0, R, B->desc_res, 1, 0, bufs, st));
+        }
+        PP_TRY(bnorms(B, R, B->r64, beta_new, st));
+        bool stalled = false;
+        for (int p = 0; p < P; ++p) {
+            if (done[p]) continue;
+            inf[p].mvps += polys[p / R]->plan.d_eff;  // p(A) (d_eff - 1) and the residual (1)
+            if (!(beta_new[p] <= 0.5 * beta[p])) stalled = true;
+            beta[p] = beta_new[p];
+        }
+        if (prec != PP_F64 && stalled) prec = PP_F64;
+    }
+    pp_status status = PP_OK;
+    const double t = now_s() - t0;
+    for (int p = 0; p < P; ++p) {
+        inf[p].status = noconv[p] ? PP_NOCONV : PP_OK;
+        inf[p].t_solve_s = t;
+        if (noconv[p]) status = PP_NOCONV;
+        if (opts->history && p == 0)
+            for (size_t i = 0; i < hist[p].size() && (int)i < opts->history_cap; ++i) opts->history[i] = hist[p][i];
+    }
+    if (infos)
+        for (int p = 0; p < P; ++p) infos[p] = inf[p];
+    return status;
+}
+
+}  // extern "C"

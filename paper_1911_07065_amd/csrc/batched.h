@@ -1,0 +1,66 @@
+// Launchers of the batched kernels (internal).
+//
+// A batch is a block-diagonal matrix: system s owns rows (and columns)
+// [row_off[s], row_off[s+1]). Vectors hold R right-hand sides interleaved:
+// element (row i, rhs r) sits at i*R + r. Every (system, rhs) pair runs its
+// own Krylov process; pair p = s*R + r.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace ppg {
+
+// Sliced-ELL of the whole batch: 64-row slices that never cross a system
+// boundary. slice[k] = {row0, nrows, sys, 0}; entries of slice k are
+// sptr[k] .. sptr[k+1] (width (sptr[k+1]-sptr[k])/64), columns global.
+struct BatchSell {
+    const int4 *slice;
+    const int32_t *sptr;
+    const int32_t *scol;
+    const double *sval64;
+    const float *sval32;
+    int nslices;
+    const int *active;  // per system: 0 = skip its slices (null: all run)
+};
+
+// System-aligned row blocks for reductions: block[b] = {row0, nrows, sys, 0};
+// the blocks of system s are boff[s] .. boff[s+1]-1.
+struct BatchBlocks {
+    const int4 *block;
+    const int32_t *boff;
+    int nblocks;
+    int nsys;
+    const int *active;  // per system: 0 = skip its blocks (null: all run)
+};
+
+// One chain step k of every system (desc: nsys x K step table; a step with
+// spmv == -1 is skipped for that system). bufs: input, output, ping, pong,
+// temporary (each n_total*R elements of the precision's type).
+hipError_t launch_bchain(const BatchSell &S, int prec, int R, const PStep *desc, int K, int k, void *const bufs[5],
+                         hipStream_t st);
+// partial[b*ldp + c*R + r] = sum over block b of V_c[i*R+r] * w[i*R+r], c < ncols
+hipError_t launch_bdots(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols, const void *w,
+                        double *partial, int ldp, hipStream_t st);
+// h[s*ldh + t] = sum over the blocks of s of partial[b*ldp + t] (t < nt, fixed
+// order); if H: H[p*pstride + t/R] (hmode 1: =, 2: +=) for pair p = s*R + t%R.
+hipError_t launch_bred(const BatchBlocks &B, int R, const double *partial, int ldp, int nt, double *h, int ldh,
+                       double *H, long pstride, int hmode, hipStream_t st);
+// w[i*R+r] -= sum_c V_c[i*R+r] h[s*ldh + c*R + r]; with npart, per-block sums
+// of the new w^2 in npart[b*R + r].
+hipError_t launch_bupdate(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols, const double *h,
+                          int ldh, void *w, double *npart, hipStream_t st);
+// per pair: norm = sqrt(sum_b npart[b*R + r]); H[p*pstride] = norm; inv[p] = 1/norm (0 if 0)
+hipError_t launch_bnorm(const BatchBlocks &B, int R, const double *npart, double *H, long pstride, double *inv,
+                        hipStream_t st);
+// out[i*R+r] = (T_out)(in[i*R+r] * scale[p])
+hipError_t launch_bscale(const BatchBlocks &B, int prec_in, int prec_out, int R, const void *in, const double *scale,
+                         void *out, hipStream_t st);
+// out[i*R+r] = sum_j V_j[i*R+r] z[p*ldz + j], j < k[p] (device int per pair)
+hipError_t launch_bcombine(const BatchBlocks &B, int prec, int R, const void *V, long ldv, const int *k,
+                           const double *z, int ldz, void *out, hipStream_t st);
+
+}  // namespace ppg

@@ -1,0 +1,451 @@
+// Batched kernels: many independent systems (a block-diagonal matrix) with
+// R right-hand sides each, advanced in lockstep so that every step of the
+// polynomial chain and of Gram-Schmidt is one launch for the whole batch.
+//
+// * The chain reads the batch's sliced-ELL copy once per step for all R
+//   right-hand sides (interleaved vectors: the gather of one entry fetches
+//   R consecutive values). Each slice belongs to one system and reads that
+//   system's step descriptor (its own polynomial).
+// * Gram-Schmidt works on system-aligned row blocks; per-block partial sums
+//   are reduced per system in a fixed order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "batched.h"
+#include "devutil.h"
+
+namespace ppg {
+namespace {
+
+template <typename VT, typename XT>
+struct BChainArgs {
+    const int4 *slice;
+    const int32_t *sptr;
+    const int32_t *scol;
+    const VT *sval;
+    int nslices;
+    const int *active;
+    const PStep *desc;
+    int K;
+    int k;
+    XT *bufs[5];
+};
+
+template <typename VT, typename XT, int R>
+__global__ __launch_bounds__(256) void k_bchain(BChainArgs<VT, XT> a) {
+    using AT = typename Arith<XT>::T;
+    constexpr int U = 8;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= a.nslices) return;
+    const int lane = threadIdx.x & 63;
+    const int4 si = a.slice[w];
+    if (a.active && !a.active[si.z]) return;
+    const PStep st = a.desc[(long)si.z * a.K + a.k];
+    if (st.spmv < 0) return;  // this system's program is shorter
+    const bool active = lane < si.y;
+    const long row = (long)si.x + lane;
+    const XT *in = a.bufs[st.in];
+    const XT *aux = st.aux >= 0 ? a.bufs[st.aux] : nullptr;
+    const XT *vfin = st.fin ? a.bufs[0] : nullptr;
+    XT *out = st.out >= 0 ? a.bufs[st.out] : nullptr;
+    XT *acc = st.acc >= 0 ? a.bufs[st.acc] : nullptr;
+    AT s[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) s[r] = AT(0);
+    if (st.spmv) {
+        const int o0 = a.sptr[w];
+        const int width = (a.sptr[w + 1] - o0) >> 6;
+        for (int k0 = 0; k0 < width; k0 += U) {
+            int c[U];
+            VT v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c[u] = 0;
+                v[u] = VT(0);
+                if (k0 + u < width) {
+                    const int o = o0 + (k0 + u) * 64 + lane;
+                    c[u] = __builtin_nontemporal_load(a.scol + o);
+                    v[u] = __builtin_nontemporal_load(a.sval + o);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (k0 + u < width) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) s[r] += (AT)v[u] * ldx(in, (long)c[u] * R + r);
+                }
+        }
+    }
+    if (!active) return;
+    const AT a0 = (AT)st.a0, a1 = (AT)st.a1, a2 = (AT)st.a2, b0 = (AT)st.b0, b1 = (AT)st.b1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const long idx = row * R + r;
+        const AT xin = ldx(in, idx);
+        AT wv = a0 * s[r] + a1 * xin;
+        if (aux) wv += a2 * (AT)ldx(aux, idx);
+        if (acc) {
+            const AT old = st.acc_init ? AT(0) : (AT)ldx(acc, idx);
+            stx(acc, idx, old + b0 * xin + b1 * wv);
+        }
+        if (out) stx(out, idx, vfin ? (AT)ldx(vfin, idx) - wv : wv);
+    }
+}
+
+// Gram-Schmidt projections, KC columns per pass.
+template <typename XT, int R>
+__global__ __launch_bounds__(256) void k_bdots(const int4 *block, const int *active, const XT *V, long ldv, int ncols,
+                                               const XT *w, double *partial, int ldp) {
+    constexpr int KC = 16 / R;
+    __shared__ double sm[4][KC * R];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int4 bi = block[blockIdx.x];
+    if (active && !active[bi.z]) return;
+    const long r0 = bi.x, r1 = (long)bi.x + bi.y;
+    for (int c0 = 0; c0 < ncols; c0 += KC) {
+        double acc[KC][R];
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[kc][r] = 0.0;
+        for (long i = r0 + tid; i < r1; i += 256) {
+            double wv[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) wv[r] = (double)ldx(w, i * R + r);
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc)
+                if (c0 + kc < ncols) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[kc][r] += (double)ldx(V, (long)(c0 + kc) * ldv + i * R + r) * wv[r];
+                }
+        }
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double t = wave_sum(acc[kc][r]);
+                if (lane == 0) sm[wave][kc * R + r] = t;
+            }
+        __syncthreads();
+        if (tid < KC * R && c0 + tid / R < ncols)
+            partial[(long)blockIdx.x * ldp + (long)c0 * R + tid] =
+                ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bred(const int32_t *boff, int R, const double *partial, int ldp, int nt,
+                                              double *h, int ldh, double *H, long pstride, int hmode) {
+    const int s = blockIdx.x;
+    const int b0 = boff[s], b1 = boff[s + 1];
+    for (int t = threadIdx.x; t < nt; t += 256) {
+        double acc = 0.0;
+        for (int b = b0; b < b1; ++b) acc += partial[(long)b * ldp + t];
+        if (h) h[(long)s * ldh + t] = acc;
+        if (H) {
+            double *dst = H + ((long)s * R + t % R) * pstride + t / R;
+            if (hmode == 1)
+                *dst = acc;
+            else if (hmode == 2)
+                *dst += acc;
+        }
+    }
+}
+
+template <typename XT, int R>
+__global__ __launch_bounds__(256) void k_bupdate(const int4 *block, const int *active, const XT *V, long ldv, int ncols,
+                                                 const double *h, int ldh, XT *w, double *npart) {
+    __shared__ double red[4][R];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int4 bi = block[blockIdx.x];
+    if (active && !active[bi.z]) return;
+    const long r0 = bi.x, r1 = (long)bi.x + bi.y;
+    const double *hs = h + (long)bi.z * ldh;
+    double sq[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) sq[r] = 0.0;
+    for (long i = r0 + tid; i < r1; i += 256) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double acc = 0.0;
+            for (int c = 0; c < ncols; ++c) acc += (double)ldx(V, (long)c * ldv + i * R + r) * hs[c * R + r];
+            const double wn = (double)ldx(w, i * R + r) - acc;
+            stx(w, i * R + r, (typename Arith<XT>::T)wn);
+            const double stv = stored_value(w, wn);
+            sq[r] += stv * stv;
+        }
+    }
+    if (!npart) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double t = wave_sum(sq[r]);
+        if (lane == 0) red[wave][r] = t;
+    }
+    __syncthreads();
+    if (tid < R) npart[(long)blockIdx.x * R + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+}
+
+__global__ __launch_bounds__(64) void k_bnorm(const int32_t *boff, int nsys, int R, const double *npart, double *H,
+                                              long pstride, double *inv) {
+    const int p = blockIdx.x * 64 + threadIdx.x;
+    if (p >= nsys * R) return;
+    const int s = p / R, r = p % R;
+    double acc = 0.0;
+    for (int b = boff[s]; b < boff[s + 1]; ++b) acc += npart[(long)b * R + r];
+    const double nrm = sqrt(acc);
+    if (H) H[(long)p * pstride] = nrm;
+    inv[p] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+}
+
+template <typename TI, typename TO, int R>
+__global__ __launch_bounds__(256) void k_bscale(const int4 *block, const int *active, const TI *in, const double *scale,
+                                                TO *out) {
+    const int4 bi = block[blockIdx.x];
+    if (active && !active[bi.z]) return;
+    const long r0 = bi.x, r1 = (long)bi.x + bi.y;
+    for (long i = r0 + threadIdx.x; i < r1; i += 256) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double v = (double)ldx(in, i * R + r) * scale[(long)bi.z * R + r];
+            stx(out, i * R + r, (typename Arith<TO>::T)v);
+        }
+    }
+}
+
+// out = V z per pair over that pair's own kp[p] columns (columns past a
+// pair's last step may hold stale values of other cycles and are not read)
+template <typename XT, int R>
+__global__ __launch_bounds__(256) void k_bcombine(const int4 *block, const XT *V, long ldv, const int *kp,
+                                                  const double *z, int ldz, XT *out) {
+    const int4 bi = block[blockIdx.x];
+    const long r0 = bi.x, r1 = (long)bi.x + bi.y;
+    for (long i = r0 + threadIdx.x; i < r1; i += 256) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const long p = (long)bi.z * R + r;
+            const double *zp = z + p * ldz;
+            const int k = kp[p];
+            double acc = 0.0;
+            for (int j = 0; j < k; ++j) acc += (double)ldx(V, (long)j * ldv + i * R + r) * zp[j];
+            stx(out, i * R + r, (typename Arith<XT>::T)acc);
+        }
+    }
+}
+
+// ---- dispatch helpers -----------------------------------------------------
+
+template <typename VT, typename XT>
+hipError_t bchain_t(const BatchSell &S, const VT *sval, int R, const PStep *desc, int K, int k, void *const bufs[5],
+                    hipStream_t st) {
+    BChainArgs<VT, XT> a;
+    a.slice = S.slice;
+    a.sptr = S.sptr;
+    a.scol = S.scol;
+    a.sval = sval;
+    a.nslices = S.nslices;
+    a.active = S.active;
+    a.desc = desc;
+    a.K = K;
+    a.k = k;
+    for (int i = 0; i < 5; ++i) a.bufs[i] = (XT *)bufs[i];
+    const unsigned g = (unsigned)((S.nslices + 3) / 4);
+    if (g == 0) return hipSuccess;
+    switch (R) {
+        case 1:
+            hipLaunchKernelGGL((k_bchain<VT, XT, 1>), dim3(g), dim3(256), 0, st, a);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_bchain<VT, XT, 2>), dim3(g), dim3(256), 0, st, a);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_bchain<VT, XT, 4>), dim3(g), dim3(256), 0, st, a);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename XT>
+hipError_t bdots_t(const BatchBlocks &B, int R, const XT *V, long ldv, int ncols, const XT *w, double *partial, int ldp,
+                   hipStream_t st) {
+    if (B.nblocks == 0 || ncols == 0) return hipSuccess;
+    switch (R) {
+        case 1:
+            hipLaunchKernelGGL((k_bdots<XT, 1>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, w, partial,
+                               ldp);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_bdots<XT, 2>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, w, partial,
+                               ldp);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_bdots<XT, 4>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, w, partial,
+                               ldp);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename XT>
+hipError_t bupdate_t(const BatchBlocks &B, int R, const XT *V, long ldv, int ncols, const double *h, int ldh, XT *w,
+                     double *npart, hipStream_t st) {
+    if (B.nblocks == 0) return hipSuccess;
+    switch (R) {
+        case 1:
+            hipLaunchKernelGGL((k_bupdate<XT, 1>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, h, ldh, w,
+                               npart);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_bupdate<XT, 2>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, h, ldh, w,
+                               npart);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_bupdate<XT, 4>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, h, ldh, w,
+                               npart);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+hipError_t bscale_t(const BatchBlocks &B, int R, const TI *in, const double *scale, TO *out, hipStream_t st) {
+    if (B.nblocks == 0) return hipSuccess;
+    switch (R) {
+        case 1:
+            hipLaunchKernelGGL((k_bscale<TI, TO, 1>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, in, scale, out);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_bscale<TI, TO, 2>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, in, scale, out);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_bscale<TI, TO, 4>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, in, scale, out);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TI>
+hipError_t bscale_in(const BatchBlocks &B, int prec_out, int R, const TI *in, const double *scale, void *out,
+                     hipStream_t st) {
+    switch (prec_out) {
+        case 0:
+            return bscale_t<TI, double>(B, R, in, scale, (double *)out, st);
+        case 1:
+            return bscale_t<TI, float>(B, R, in, scale, (float *)out, st);
+        case 2:
+            return bscale_t<TI, uint16_t>(B, R, in, scale, (uint16_t *)out, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename XT>
+hipError_t bcombine_t(const BatchBlocks &B, int R, const XT *V, long ldv, const int *k, const double *z, int ldz, XT *out,
+                      hipStream_t st) {
+    if (B.nblocks == 0) return hipSuccess;
+    switch (R) {
+        case 1:
+            hipLaunchKernelGGL((k_bcombine<XT, 1>), dim3(B.nblocks), dim3(256), 0, st, B.block, V, ldv, k, z, ldz, out);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_bcombine<XT, 2>), dim3(B.nblocks), dim3(256), 0, st, B.block, V, ldv, k, z, ldz, out);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_bcombine<XT, 4>), dim3(B.nblocks), dim3(256), 0, st, B.block, V, ldv, k, z, ldz, out);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_bchain(const BatchSell &S, int prec, int R, const PStep *desc, int K, int k, void *const bufs[5],
+                         hipStream_t st) {
+    switch (prec) {
+        case 0:
+            return bchain_t<double, double>(S, S.sval64, R, desc, K, k, bufs, st);
+        case 1:
+            return bchain_t<float, float>(S, S.sval32, R, desc, K, k, bufs, st);
+        case 2:
+            return bchain_t<float, uint16_t>(S, S.sval32, R, desc, K, k, bufs, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bdots(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols, const void *w,
+                        double *partial, int ldp, hipStream_t st) {
+    switch (prec) {
+        case 0:
+            return bdots_t<double>(B, R, (const double *)V, ldv, ncols, (const double *)w, partial, ldp, st);
+        case 1:
+            return bdots_t<float>(B, R, (const float *)V, ldv, ncols, (const float *)w, partial, ldp, st);
+        case 2:
+            return bdots_t<uint16_t>(B, R, (const uint16_t *)V, ldv, ncols, (const uint16_t *)w, partial, ldp, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bred(const BatchBlocks &B, int R, const double *partial, int ldp, int nt, double *h, int ldh,
+                       double *H, long pstride, int hmode, hipStream_t st) {
+    if (B.nsys == 0 || nt == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bred, dim3(B.nsys), dim3(256), 0, st, B.boff, R, partial, ldp, nt, h, ldh, H, pstride, hmode);
+    return hipGetLastError();
+}
+
+hipError_t launch_bupdate(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols, const double *h,
+                          int ldh, void *w, double *npart, hipStream_t st) {
+    switch (prec) {
+        case 0:
+            return bupdate_t<double>(B, R, (const double *)V, ldv, ncols, h, ldh, (double *)w, npart, st);
+        case 1:
+            return bupdate_t<float>(B, R, (const float *)V, ldv, ncols, h, ldh, (float *)w, npart, st);
+        case 2:
+            return bupdate_t<uint16_t>(B, R, (const uint16_t *)V, ldv, ncols, h, ldh, (uint16_t *)w, npart, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bnorm(const BatchBlocks &B, int R, const double *npart, double *H, long pstride, double *inv,
+                        hipStream_t st) {
+    const int np = B.nsys * R;
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bnorm, dim3((np + 63) / 64), dim3(64), 0, st, B.boff, B.nsys, R, npart, H, pstride, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_bscale(const BatchBlocks &B, int prec_in, int prec_out, int R, const void *in, const double *scale,
+                         void *out, hipStream_t st) {
+    switch (prec_in) {
+        case 0:
+            return bscale_in<double>(B, prec_out, R, (const double *)in, scale, out, st);
+        case 1:
+            return bscale_in<float>(B, prec_out, R, (const float *)in, scale, out, st);
+        case 2:
+            return bscale_in<uint16_t>(B, prec_out, R, (const uint16_t *)in, scale, out, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bcombine(const BatchBlocks &B, int prec, int R, const void *V, long ldv, const int *k,
+                           const double *z, int ldz, void *out, hipStream_t st) {
+    switch (prec) {
+        case 0:
+            return bcombine_t<double>(B, R, (const double *)V, ldv, k, z, ldz, (double *)out, st);
+        case 1:
+            return bcombine_t<float>(B, R, (const float *)V, ldv, k, z, ldz, (float *)out, st);
+        case 2:
+            return bcombine_t<uint16_t>(B, R, (const uint16_t *)V, ldv, k, z, ldz, (uint16_t *)out, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ppg

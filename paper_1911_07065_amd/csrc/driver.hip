@@ -18,23 +18,9 @@
 #include "host_core.h"
 #include "kernels.h"
 #include "poly.h"
+#include "common.h"
 
 using namespace ppg;
-
-#define HIP_TRY(expr)                                                                              \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) {                                                                    \
-            set_error(std::string("HIP error ") + hipGetErrorString(e_) + " in " + #expr);         \
-            return PP_EDEVICE;                                                                     \
-        }                                                                                          \
-    } while (0)
-
-#define PP_TRY(expr)                     \
-    do {                                 \
-        pp_status s_ = (expr);           \
-        if (s_ < 0) return s_;           \
-    } while (0)
 
 namespace {
 
@@ -43,31 +29,6 @@ constexpr int kMaxDegree = 4096;
 // relative inner-cycle target of a reduced-precision cycle (the FP64 outer
 // refinement recomputes the true residual after every cycle)
 constexpr double kInnerEta[3] = {0.0, 1e-5, 1e-2};
-
-template <typename T>
-pp_status dev_alloc(T **p, size_t count) {
-    *p = nullptr;
-    if (count == 0) return PP_OK;
-    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        set_error(std::string("hipMalloc failed: ") + hipGetErrorString(e));
-        return PP_ENOMEM;
-    }
-    return PP_OK;
-}
-
-template <typename T>
-void dev_free(T *&p) {
-    if (p) (void)hipFree((void *)p);
-    p = nullptr;
-}
-
-inline hipStream_t S(void *s) { return (hipStream_t)s; }
-
-double now_s() {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
 
 }  // namespace
 

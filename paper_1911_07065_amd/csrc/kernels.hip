@@ -15,81 +15,11 @@
 
 #include <cstdint>
 
+#include "devutil.h"
 #include "kernels.h"
 
 namespace ppg {
 namespace {
-
-// ---------------------------------------------------------------------------
-// element access: double, float, bfloat16 bits (uint16)
-// ---------------------------------------------------------------------------
-
-template <typename XT>
-struct Arith;
-template <>
-struct Arith<double> {
-    using T = double;
-};
-template <>
-struct Arith<float> {
-    using T = float;
-};
-template <>
-struct Arith<uint16_t> {
-    using T = float;
-};
-
-__device__ __forceinline__ double ldx(const double *p, long i) { return p[i]; }
-__device__ __forceinline__ float ldx(const float *p, long i) { return p[i]; }
-__device__ __forceinline__ float ldx(const uint16_t *p, long i) {
-    return __uint_as_float(((uint32_t)p[i]) << 16);
-}
-
-// float -> bfloat16, round to nearest even (NaN stays NaN)
-__device__ __forceinline__ uint16_t f32_to_bf16(float v) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ void stx(double *p, long i, double v) { p[i] = v; }
-__device__ __forceinline__ void stx(float *p, long i, float v) { p[i] = v; }
-__device__ __forceinline__ void stx(uint16_t *p, long i, float v) { p[i] = f32_to_bf16(v); }
-
-// the value a store of v into an array of the pointer's type keeps
-__device__ __forceinline__ double stored_value(const double *, double v) { return v; }
-__device__ __forceinline__ double stored_value(const float *, double v) { return (double)(float)v; }
-__device__ __forceinline__ double stored_value(const uint16_t *, double v) {
-    return (double)__uint_as_float(((uint32_t)f32_to_bf16((float)v)) << 16);
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Deterministic sum over a 256-thread block; result valid in thread 0.
-template <typename T>
-__device__ __forceinline__ T block_sum256(T v, T *sm /* [4] */) {
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) sm[wave] = v;
-    __syncthreads();
-    T r = T(0);
-    if (threadIdx.x == 0) r = ((sm[0] + sm[1]) + sm[2]) + sm[3];
-    __syncthreads();
-    return r;
-}
-
-__device__ __forceinline__ int remap_tile(int b, int ntiles, int remap) {
-    if (!remap) return b;
-    constexpr int nx = 8;  // XCDs; workgroups are dispatched round-robin over them
-    const int x = b % nx, q = ntiles / nx, rem = ntiles % nx;
-    return x * q + min(x, rem) + b / nx;
-}
 
 // ---------------------------------------------------------------------------
 // fused chain step

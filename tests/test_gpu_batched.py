@@ -1,0 +1,147 @@
+"""GPU parity of the batched solver: every (system, rhs) pair equals its own single solve."""
+
+import time
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from oracle import roots as oroots
+from workloads import batched_convdiff_specs, convdiff2d, normal_vector, rhs, start_vector
+from gpu_util import say, dev, host, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pp():
+    import paper_1911_07065_amd.api as api
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return api
+
+
+def _systems(specs):
+    return [convdiff2d(N, alpha) for (N, alpha, _, _) in specs]
+
+
+def _rhs_block(specs, R):
+    # R normalised N(0,1) right-hand sides per system, from the system's seed
+    return [rhs(N * N, seed, count=R) for (N, _, seed, _) in specs]
+
+
+def _v0(specs):
+    return np.concatenate([start_vector(N * N, seed) for (N, _, _, seed) in specs])
+
+
+def _blockdiag(csrs):
+    return sp.block_diag([c.to_scipy() for c in csrs]).tocsr()
+
+
+SMALL = [(16, 3.0, 1000, 5000), (23, 40.0, 1001, 5001), (31, 0.0, 1002, 5002), (40, 12.5, 1003, 5003),
+         (9, 7.0, 1004, 5004), (28, 25.0, 1005, 5005)]
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+@pytest.mark.parametrize("R", [1, 4])
+def test_small_batch_matches_single_solves(pp, inner, R):
+    csrs = _systems(SMALL)
+    say("batch small", inner, R)
+    Bt = pp.Batch(csrs)
+    polys = Bt.setup(dev(_v0(SMALL)), 8)
+    brs = _rhs_block(SMALL, R)
+    bmat = np.concatenate(brs, axis=1)  # (R, n_total)
+    x, infos = Bt.solve(polys, Bt.interleave(bmat), R, tol=1e-8, m=30, inner=inner)
+    X = host(Bt.deinterleave(x, R))
+    Abig = _blockdiag(csrs)
+    off = np.concatenate([[0], np.cumsum([c.n for c in csrs])])
+    for s, c in enumerate(csrs):
+        A = c.to_scipy()
+        # the batched polynomial equals the single-system setup's up to rounding
+        M = pp.Matrix.from_csr(c)
+        single = pp.setup(M, dev(start_vector(c.n, SMALL[s][3])), 8)
+        th_b = np.sort_complex(polys[s].roots("theta"))
+        th_s = np.sort_complex(single.roots("theta"))
+        assert np.max(np.abs(th_b - th_s) / np.abs(th_s)) < 1e-8
+        for r in range(R):
+            p = s * R + r
+            xs = X[r, off[s]:off[s + 1]]
+            rel = np.linalg.norm(brs[s][r] - A @ xs) / np.linalg.norm(brs[s][r])
+            assert infos[p]["converged"] and rel <= 1e-8, (s, r, infos[p], rel)
+            xo, io = pp.solve(single, M, dev(brs[s][r]), tol=1e-8, m=30, inner=inner)
+            assert relerr(xs, host(xo)) < 1e-5
+    # the whole block system
+    R_all = bmat - (Abig @ X.T).T
+    assert np.all(np.linalg.norm(R_all, axis=1) <= 1e-8 * np.linalg.norm(bmat, axis=1) * np.sqrt(len(csrs)))
+
+
+def test_batch_rejects_coupled_blocks(pp):
+    csrs = _systems(SMALL[:2])
+    Bt = pp.Batch(csrs)  # valid
+    import ctypes
+    from paper_1911_07065_amd._lib import lib
+
+    # a pattern whose row 0 reaches into the second system
+    n0, n1 = csrs[0].n, csrs[1].n
+    rp = np.arange(n0 + n1 + 1, dtype=np.int32)
+    ci = np.arange(n0 + n1, dtype=np.int32)
+    ci[0] = n0 + 3
+    ro = np.array([0, n0, n0 + n1], dtype=np.int64)
+    h = ctypes.c_void_p()
+    st = lib.pp_batch_create(2, ro.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n0 + n1,
+                             ctypes.c_void_p(dev(rp, torch.int32).data_ptr()),
+                             ctypes.c_void_p(dev(ci, torch.int32).data_ptr()),
+                             ctypes.c_void_p(dev(np.ones(n0 + n1)).data_ptr()), None, ctypes.byref(h))
+    assert st == -1
+
+
+def test_batched_config_full_size(pp):
+    # 256 2-D convection-diffusion systems, sides U{64..512}, alpha U[0,50),
+    # 4 right-hand sides each, degree 20, GMRES(50), FP32 inner / FP64 outer
+    specs = batched_convdiff_specs()
+    csrs = _systems(specs)
+    n_tot = sum(c.n for c in csrs)
+    say("batched full", len(csrs), "systems", n_tot, "rows")
+    Bt = pp.Batch(csrs)
+    v0 = dev(_v0(specs))
+    bmat = np.concatenate(_rhs_block(specs, 4), axis=1)
+    bd = Bt.interleave(bmat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    polys = Bt.setup(v0, 20)
+    x, infos = Bt.solve(polys, bd, 4, tol=1e-8, m=50, inner="fp32")
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    X = host(Bt.deinterleave(x, 4))
+    Abig = _blockdiag(csrs)
+    Rres = bmat - (Abig @ X.T).T
+    off = np.concatenate([[0], np.cumsum([c.n for c in csrs])])
+    worst = 0.0
+    for s in range(len(csrs)):
+        for r in range(4):
+            seg = slice(off[s], off[s + 1])
+            worst = max(worst, np.linalg.norm(Rres[r, seg]) / np.linalg.norm(bmat[r, seg]))
+    say("batched full: time", round(t_batch, 3), "s, worst relres", worst,
+        "max iters", max(i["iters"] for i in infos), "max cycles", max(i["cycles"] for i in infos))
+    assert all(i["converged"] for i in infos) and worst <= 1e-8
+    # the same work as a loop of single-system solves, timed on every 16th
+    # system and scaled to the whole batch
+    t_loop = 0.0
+    sub = list(range(0, len(csrs), 16))
+    brs = _rhs_block(specs, 4)
+    for s in sub:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        M = pp.Matrix.from_csr(csrs[s])
+        M.tune("fp32")
+        M.tune("fp64")
+        poly = pp.setup(M, dev(start_vector(csrs[s].n, specs[s][3])), 20)
+        for r in range(4):
+            xs, io = pp.solve(poly, M, dev(brs[s][r]), tol=1e-8, m=50, inner="fp32")
+            assert io["converged"]
+        torch.cuda.synchronize()
+        t_loop += time.perf_counter() - t1
+    t_loop *= len(csrs) / len(sub)
+    say("loop of single solves (scaled from", len(sub), "systems):", round(t_loop, 3), "s; batched", round(t_batch, 3),
+        "s; speed-up", round(t_loop / t_batch, 2))
