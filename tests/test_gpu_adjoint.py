@@ -83,3 +83,55 @@ def test_gradient_vs_oracle_and_finite_differences(pp, inner):
     h = 1e-6
     fd = (L(theta0 + h) - L(theta0 - h)) / (2 * h)
     assert abs(g_theta - fd) <= 1e-6 * abs(fd), (g_theta, fd)
+
+
+def test_differentiation_config_full_size(pp):
+    # 2-D convection-diffusion on a 1024 x 1024 grid (n = 1,048,576), convection
+    # coefficient theta = 20 as a leaf tensor, loss 0.5 ||x(theta, b) - x_t||^2,
+    # degree 50; adjoint through the same roots vs the direct-solve gradient
+    # and central finite differences with h = 1e-6 (direct solves).
+    import time
+
+    N, theta0 = 1024, 20.0
+    A0, dval = convdiff2d_parts(N)
+    n = N * N
+    b = rhs(n, 1)
+    xt = np.random.default_rng(3).standard_normal(n)
+    say("differentiation full size", n)
+    M = pp.Matrix.from_csr(A0)
+    base, dirv = dev(A0.val), dev(dval)
+    M.set_values(base + theta0 * dirv)
+    poly = pp.setup(M, dev(start_vector(n, 2)), 50)
+    th = torch.tensor(theta0, dtype=torch.float64, device="cuda", requires_grad=True)
+    bt = dev(b).requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = pp.pp_solve_fn(base + th * dirv, bt, M, poly, tol=1e-12, m=50, inner="fp64")
+    loss = 0.5 * torch.sum((x - dev(xt)) ** 2)
+    loss.backward()
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    g_theta = float(th.grad)
+    g_b = host(bt.grad)
+    lu_of = lambda t: sla.splu(A0.with_values(A0.val + t * dval).to_scipy().tocsc(), permc_spec="COLAMD")
+    lu = lu_of(theta0)
+    xo = lu.solve(b)
+    lam = lu.solve(xo - xt, trans="T")
+    A = A0.with_values(A0.val + theta0 * dval).to_scipy()
+    rows = np.repeat(np.arange(n), np.diff(A.indptr))
+    g_or = float(np.dot(-lam[rows] * xo[A.indices], dval))
+    # central difference (L(theta+h) - L(theta-h)) / 2h, h = 1e-6, evaluated
+    # without cancellation: with D = dA/dtheta, x+ - x- = -2h A(theta+h)^{-1} D x-
+    # exactly, and L+ - L- = (x+ - x-)^T (x+ + x- - 2 x_t) / 2 (L ~ 5e5 here,
+    # so subtracting the two losses would lose ~1e-6 to rounding)
+    h = 1e-6
+    D = A0.with_values(dval).to_scipy()
+    xm = lu_of(theta0 - h).solve(b)
+    dx = -2 * h * lu_of(theta0 + h).solve(D @ xm)
+    xp = xm + dx
+    fd = float(dx @ (xp + xm - 2 * xt)) / (4 * h)
+    say("dL/dtheta gpu", g_theta, "oracle", g_or, "fd", fd, "gpu fwd+bwd s", round(t_gpu, 3),
+        "rel x err", relerr(host(x), xo))
+    assert abs(g_theta - g_or) <= 1e-6 * abs(g_or)
+    assert abs(g_theta - fd) <= 1e-6 * abs(fd)
+    assert relerr(g_b, lam) <= 1e-6
