@@ -147,31 +147,41 @@ def main():
     # p(A)v bandwidth (algorithmic bytes / event time), FP32 and FP64
     poly = res["fp32"]["poly"]
     nl = poly.d_eff - 1  # launches of the p chain
-    stream = torch.cuda.current_stream()
-    pav = {}
+    stream = torch.cuda.current_stream()  # the stream the library launches on
+
+    def event_ms(fn, reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    pav, phi = {}, {}
     for prec, dt, sv, sx in (("fp32", torch.float32, 4, 4), ("fp64", torch.float64, 8, 8)):
         v = bd.to(dt)
         y = torch.empty_like(v)
         for _ in range(3):
             pp.apply(poly, M, v, "p", out=y)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.pav_reps):
-            pp.apply(poly, M, v, "p", out=y)
-        e1.record(stream)
-        e1.synchronize()
-        ms = e0.elapsed_time(e1) / args.pav_reps
+            pp.apply(poly, M, v, "phi", out=y)
+        ms = event_ms(lambda: pp.apply(poly, M, v, "p", out=y), args.pav_reps)
         by = nl * step_bytes(n, nnz, sv, sx) + 2 * n * sx
-        pav[prec] = dict(ms=ms, GBps=by / (ms * 1e-3) / 1e9, bytes=by, launches=nl,
-                         launch_us=ms * 1e3 / nl, step_bytes=step_bytes(n, nnz, sv, sx))
+        pav[prec] = dict(ms=ms, GBps=by / (ms * 1e-3) / 1e9, bytes=by, launches=nl, launch_us=ms * 1e3 / nl)
         log("p(A)v", prec, f"{ms:.3f} ms", f"{pav[prec]['GBps']:.0f} GB/s", f"{pav[prec]['launch_us']:.1f} us/launch")
+        # phi(A)v: d_eff launches of exactly one chain step each (the Arnoldi operator)
+        ms = event_ms(lambda: pp.apply(poly, M, v, "phi", out=y), args.pav_reps)
+        phi[prec] = dict(ms=ms, launch_us=ms * 1e3 / poly.d_eff, step_bytes=step_bytes(n, nnz, sv, sx),
+                         variant=M.variant(prec)[0])
+        log("phi(A)v", prec, f"{ms:.3f} ms", f"{phi[prec]['launch_us']:.2f} us/launch", phi[prec]["variant"])
 
-    k32 = pav["fp32"]
+    k32 = phi["fp32"]
     achieved = k32["step_bytes"] / (k32["launch_us"] * 1e-6) / 1e9
     roofline = {
         "bound": "hbm",
-        "kernel": "k_chain<float,float> (fused CSR SpMV + chain update, one root factor)",
+        "kernel": f"k_chain_sell<float,float> ({k32['variant']}: fused sliced-ELL SpMV + chain update, one root)"
+        if k32["variant"] and k32["variant"].startswith("sell") else f"chain step, variant {k32['variant']}",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
@@ -179,6 +189,8 @@ def main():
         "traffic": None,
         "bytes_per_launch": k32["step_bytes"],
         "avg_launch_us": round(k32["launch_us"], 3),
+        "fp64_avg_launch_us": round(phi["fp64"]["launch_us"], 3),
+        "fp64_variant": phi["fp64"]["variant"],
     }
 
     cpu = None

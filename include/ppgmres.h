@@ -130,9 +130,16 @@ void pp_matrix_destroy(pp_matrix A);
 pp_status pp_matrix_tune(pp_matrix A, int prec, void *stream, int *variant, int *remap,
                          double *us_per_launch);
 
-/* Force a chain-step variant (0 <= variant < 20, remap 0/1; 15 = persistent) for a precision
+/* Force a chain-step variant (0 <= variant < 24, remap 0/1; 15 = persistent) for a precision
  * instead of tuning, e.g. to test every variant. */
 pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap);
+
+/* The chain-step variant in use for a precision, without tuning: variant
+ * (host) receives -1 if the precision has not been tuned or set yet, 15 when
+ * the persistent kernel is in use; remap and us_per_launch (host, may be
+ * NULL) receive the XCD remap flag and the tuned time per launch in
+ * microseconds (0 if the variant was forced). */
+pp_status pp_matrix_variant(pp_matrix A, int prec, int *variant, int *remap, double *us_per_launch);
 
 /* Name of a chain-step variant ("tile8x1", "vec8x4", ...). */
 const char *pp_chain_variant_name(int variant);

@@ -25,7 +25,7 @@ def version() -> str:
     return lib.pp_version().decode()
 
 
-N_CHAIN_VARIANTS = 20
+N_CHAIN_VARIANTS = 24
 
 
 def chain_variant_name(v: int) -> str:
@@ -86,8 +86,16 @@ class Matrix:
                                  ctypes.byref(us)), "pp_matrix_tune")
         return lib.pp_chain_variant_name(v.value).decode(), r.value, us.value
 
+    def variant(self, prec: str = "fp32"):
+        """Chain variant in use for a precision without tuning: (name or None, remap, tuned us per launch)."""
+        v, r, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        check(lib.pp_matrix_variant(self.handle, PREC[prec], ctypes.byref(v), ctypes.byref(r), ctypes.byref(us)),
+              "pp_matrix_variant")
+        name = None if v.value < 0 else lib.pp_chain_variant_name(v.value).decode()
+        return name, r.value, us.value
+
     def set_variant(self, prec: str, variant: int, remap: int = 1):
-        """Force chain variant `variant` (0..19; 15 = persistent cooperative kernel) for a precision."""
+        """Force chain variant `variant` (0..23; 15 = persistent cooperative kernel) for a precision."""
         check(lib.pp_matrix_set_variant(self.handle, PREC[prec], int(variant), int(remap)), "pp_matrix_set_variant")
 
     def transpose_pattern(self):

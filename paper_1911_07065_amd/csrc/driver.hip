@@ -50,6 +50,7 @@ struct pp_matrix_s {
     int4 *tileB8[3] = {nullptr, nullptr, nullptr}, *tileB16[3] = {nullptr, nullptr, nullptr};
     // sliced-ELL copy
     int32_t *sptr = nullptr, *scol = nullptr, *sperm = nullptr;
+    int16_t *sdel = nullptr;
     double *sval64 = nullptr;
     float *sval32 = nullptr;
     int nslices = 0;
@@ -97,6 +98,7 @@ struct pp_matrix_s {
         d.ntileP = ntileP;
         d.sptr = sptr;
         d.scol = scol;
+        d.sdel = sdel;
         d.sval64 = sval64;
         d.sval32 = sval32;
         d.nslices = nslices;
@@ -176,6 +178,7 @@ struct pp_matrix_s {
         dev_free(sptr);
         dev_free(scol);
         dev_free(sperm);
+        dev_free(sdel);
         dev_free(sval64);
         dev_free(sval32);
         for (int p = 0; p < 3; ++p) {
@@ -311,7 +314,8 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
     int bv = CV_TILE8, br = 1;
     const int reps = 5;
     for (int v = 0; v < CV_COUNT; ++v) {
-        if (v == CV_PERSIST || ((v == CV_SELL || v == CV_SELLT) && A->nslices == 0) || (v == CV_TILEB8 && A->ntileB8[prec] == 0) ||
+        if (v == CV_PERSIST || ((v == CV_SELL || v == CV_SELLT || v == CV_SELL2 || v == CV_SELL4) && A->nslices == 0) ||
+            ((v == CV_SELLD || v == CV_SELLD4) && !A->sdel) || (v == CV_TILEB8 && A->ntileB8[prec] == 0) ||
             (v == CV_TILEB16 && A->ntileB16[prec] == 0))
             continue;
         for (int r = 0; r < 2; ++r) {
@@ -637,6 +641,29 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
             }
             A->nslices = ns;
             A->npad = tot;
+            // 16-bit column offsets when every entry is within 32767 of its row
+            bool fits = true;
+            std::vector<int16_t> sdel(tot);
+            for (int w = 0; w < ns && fits; ++w)
+                for (long o = sp[w]; o < sp[w + 1]; ++o) {
+                    const long row = (long)w * 64 + (o - sp[w]) % 64;
+                    // rows past n are padding (column 0, value 0): offset 0 from base 0
+                    const long dlt = row < n ? (long)scol[o] - row : 0;
+                    if (dlt < -32768 || dlt > 32767) {
+                        fits = false;
+                        break;
+                    }
+                    sdel[o] = (int16_t)dlt;
+                }
+            if (fits) {
+                if ((s = dev_alloc(&A->sdel, (size_t)tot)) != PP_OK) return fail(s);
+                if (hipMemcpyAsync(A->sdel, sdel.data(), sizeof(int16_t) * tot, hipMemcpyHostToDevice, st) !=
+                        hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess) {
+                    set_error("pp_matrix_create: offset upload failed");
+                    return fail(PP_EDEVICE);
+                }
+            }
         }
     }
     {
@@ -694,7 +721,8 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
         A->persist[prec] = 1;
         A->premap[prec] = remap;
     } else {
-        if ((variant == CV_SELL || variant == CV_SELLT) && A->nslices == 0) {
+        if (((variant == CV_SELL || variant == CV_SELLT || variant == CV_SELL2 || variant == CV_SELL4) && A->nslices == 0) ||
+            ((variant == CV_SELLD || variant == CV_SELLD4) && !A->sdel)) {
             set_error("pp_matrix_set_variant: no sliced-ELL copy for this matrix (too much padding)");
             return PP_EINVAL;
         }
@@ -705,6 +733,19 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
         A->remap[prec] = remap;
     }
     A->tuned[prec] = 1;
+    A->tuned_us[prec] = 0.0;
+    return PP_OK;
+}
+
+pp_status pp_matrix_variant(pp_matrix A, int prec, int *variant, int *remap, double *us_per_launch) {
+    if (!A || !valid_prec(prec) || !variant) {
+        set_error("pp_matrix_variant: bad argument");
+        return PP_EINVAL;
+    }
+    const bool per = A->tuned[prec] && A->persist[prec];
+    *variant = !A->tuned[prec] ? -1 : (per ? (int)CV_PERSIST : A->variant[prec]);
+    if (remap) *remap = per ? A->premap[prec] : A->remap[prec];
+    if (us_per_launch) *us_per_launch = A->tuned[prec] ? A->tuned_us[prec] : 0.0;
     return PP_OK;
 }
 

@@ -34,7 +34,11 @@ enum ChainVariant : int {
     CV_TILEB16 = 17,  // tile16 kernel, same
     CV_SELL = 18,     // sliced-ELL copy (64-row slices): one lane per row, coalesced gathers
     CV_SELLT = 19,    // same with ordinary (cache-allocating) loads of the entry stream
-    CV_COUNT = 20
+    CV_SELL2 = 20,    // sell64 with 2 slices per wave
+    CV_SELL4 = 21,    // sell64 with 4 slices per wave
+    CV_SELLD = 22,    // sell64 with 16-bit column offsets (banded matrices only)
+    CV_SELLD4 = 23,   // same, 4 slices per wave
+    CV_COUNT = 24
 };
 
 // A chain step as the persistent kernel reads it from device memory.
@@ -82,6 +86,7 @@ struct DevCSR {
     // [64 s, 64 s + 64) as width_s columns of 64 entries, offsets sptr[s]
     const int32_t *sptr;
     const int32_t *scol;
+    const int16_t *sdel;  // column - row per entry (null if some offset exceeds 16 bits)
     const double *sval64;
     const float *sval32;
     int nslices;

@@ -482,17 +482,20 @@ __device__ __forceinline__ T stream_load(const T *p, bool nt) {
     return nt ? __builtin_nontemporal_load(p) : *p;
 }
 
-template <typename VT, typename XT, bool NT>
-__global__ __launch_bounds__(256) void k_chain_sell(ChainArgs<VT, XT> a, const int32_t *__restrict__ sptr,
-                                                    const int32_t *__restrict__ scol, const VT *__restrict__ sval,
-                                                    int nslices, int nblocks, int remap) {
+// One 64-row slice of a sliced-ELL matrix; lane j owns row 64 w + j. Entries
+// are consumed 8 at a time: all 16 loads of a block are issued before the
+// first is used (positions past the slice width re-read its last column and
+// are dropped by a select, so no load sits behind a branch). IT = int32_t:
+// the index is the column; IT = int16_t: the index is column - row (rows
+// past n store 0 relative to row 0).
+template <typename VT, typename XT, bool NT, typename IT>
+__device__ __forceinline__ void sell_slice(const ChainArgs<VT, XT> &a, const int32_t *__restrict__ sptr,
+                                           const IT *__restrict__ sidx, const VT *__restrict__ sval, int w,
+                                           int lane) {
     using AT = typename Arith<XT>::T;
     constexpr int U = 8;
-    const int blk = remap_tile(blockIdx.x, nblocks, remap);
-    const int w = blk * 4 + (threadIdx.x >> 6);
-    if (w >= nslices) return;
-    const int lane = threadIdx.x & 63;
     const int r = w * 64 + lane;
+    const int base = (sizeof(IT) == 4 || r < a.n) ? r : 0;
     const int o0 = sptr[w];
     const int width = (sptr[w + 1] - o0) >> 6;
     RowPre<AT> pre;
@@ -503,19 +506,40 @@ __global__ __launch_bounds__(256) void k_chain_sell(ChainArgs<VT, XT> a, const i
         VT v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            c[u] = 0;
-            v[u] = VT(0);
-            if (k0 + u < width) {
-                const int o = o0 + (k0 + u) * 64 + lane;
-                c[u] = stream_load(scol + o, NT);
-                v[u] = stream_load(sval + o, NT);
-            }
+            const int o = o0 + min(k0 + u, width - 1) * 64 + lane;
+            const int id = (int)stream_load(sidx + o, NT);
+            c[u] = sizeof(IT) == 4 ? id : base + id;
+            v[u] = stream_load(sval + o, NT);
         }
+        AT xv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (k0 + u < width) s += (AT)v[u] * ldx(a.in, c[u]);
+        for (int u = 0; u < U; ++u) xv[u] = ldx(a.in, c[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const AT t = (AT)v[u] * xv[u];
+            s += (k0 + u < width) ? t : AT(0);
+        }
     }
     if (r < a.n) row_finish(a, r, s, pre);
+}
+
+// Sliced ELL: wave w handles SPW consecutive slices of 64 rows (lane j -> row
+// 64 w' + j). The k-th entries of the slice's rows are contiguous, so the
+// index and value loads are coalesced and, for stencil-like matrices, so is
+// the gather of the input (neighbouring rows have neighbouring columns).
+// With IT = int16_t the indices are 16-bit column offsets from the row, for
+// matrices whose entries all lie within 32767 of the diagonal (banded,
+// stencils): the entry stream shrinks from 4 + s_val to 2 + s_val bytes.
+template <typename VT, typename XT, bool NT, int SPW, typename IT>
+__global__ __launch_bounds__(256) void k_chain_sell(ChainArgs<VT, XT> a, const int32_t *__restrict__ sptr,
+                                                    const IT *__restrict__ sidx, const VT *__restrict__ sval,
+                                                    int nslices, int nblocks, int remap) {
+    const int blk = remap_tile(blockIdx.x, nblocks, remap);
+    const int lane = threadIdx.x & 63;
+    const int w0 = (blk * 4 + (threadIdx.x >> 6)) * SPW;
+#pragma unroll
+    for (int q = 0; q < SPW; ++q)
+        if (w0 + q < nslices) sell_slice<VT, XT, NT, IT>(a, sptr, sidx, sval, w0 + q, lane);
 }
 
 template <typename VT>
@@ -621,15 +645,37 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int v
             return vk_launch<VT, XT, 8, 4, 1>(a, remap, st);
         case CV_VK16x2x2:
             return vk_launch<VT, XT, 16, 2, 2>(a, remap, st);
+        case CV_SELLD:
+        case CV_SELLD4: {
+            if (A.nslices == 0 || !A.sdel) return hipErrorInvalidValue;
+            const int spw = variant == CV_SELLD4 ? 4 : 1;
+            const int nb = (A.nslices + 4 * spw - 1) / (4 * spw);
+            if (spw == 1)
+                hipLaunchKernelGGL((k_chain_sell<VT, XT, true, 1, int16_t>), dim3(nb), dim3(256), 0, st, a, A.sptr,
+                                   A.sdel, sell_vals<VT>(A), A.nslices, nb, remap);
+            else
+                hipLaunchKernelGGL((k_chain_sell<VT, XT, true, 4, int16_t>), dim3(nb), dim3(256), 0, st, a, A.sptr,
+                                   A.sdel, sell_vals<VT>(A), A.nslices, nb, remap);
+            return hipGetLastError();
+        }
         case CV_SELL:
-        case CV_SELLT: {
+        case CV_SELLT:
+        case CV_SELL2:
+        case CV_SELL4: {
             if (A.nslices == 0) return hipErrorInvalidValue;
-            const int nb = (A.nslices + 3) / 4;
+            const int spw = variant == CV_SELL2 ? 2 : (variant == CV_SELL4 ? 4 : 1);
+            const int nb = (A.nslices + 4 * spw - 1) / (4 * spw);
             if (variant == CV_SELL)
-                hipLaunchKernelGGL((k_chain_sell<VT, XT, true>), dim3(nb), dim3(256), 0, st, a, A.sptr, A.scol,
+                hipLaunchKernelGGL((k_chain_sell<VT, XT, true, 1, int32_t>), dim3(nb), dim3(256), 0, st, a, A.sptr, A.scol,
+                                   sell_vals<VT>(A), A.nslices, nb, remap);
+            else if (variant == CV_SELLT)
+                hipLaunchKernelGGL((k_chain_sell<VT, XT, false, 1, int32_t>), dim3(nb), dim3(256), 0, st, a, A.sptr, A.scol,
+                                   sell_vals<VT>(A), A.nslices, nb, remap);
+            else if (variant == CV_SELL2)
+                hipLaunchKernelGGL((k_chain_sell<VT, XT, true, 2, int32_t>), dim3(nb), dim3(256), 0, st, a, A.sptr, A.scol,
                                    sell_vals<VT>(A), A.nslices, nb, remap);
             else
-                hipLaunchKernelGGL((k_chain_sell<VT, XT, false>), dim3(nb), dim3(256), 0, st, a, A.sptr, A.scol,
+                hipLaunchKernelGGL((k_chain_sell<VT, XT, true, 4, int32_t>), dim3(nb), dim3(256), 0, st, a, A.sptr, A.scol,
                                    sell_vals<VT>(A), A.nslices, nb, remap);
             return hipGetLastError();
         }
@@ -655,43 +701,96 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int v
 // Gram-Schmidt pieces
 // ---------------------------------------------------------------------------
 
+// One chunk of KC Krylov columns for k_dots: all RPT * KC loads are issued
+// before the first is used, then each column is reduced over the block.
+template <typename XT, int KC>
+__device__ __forceinline__ void dots_chunk(const XT *__restrict__ V, long ldv, int c0, const long *ii, const double *wv,
+                                           double (*sm)[kDotCols], double *prow) {
+    constexpr int RPT = kDotRows / 256;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double x[RPT][KC];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s)
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) x[s][kc] = (double)ldx(V, ii[s] + (long)(c0 + kc) * ldv);
+    double acc[KC];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+        acc[kc] = 0.0;
+#pragma unroll
+        for (int s = 0; s < RPT; ++s) acc[kc] += x[s][kc] * wv[s];
+        acc[kc] = wave_sum(acc[kc]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) sm[wave][kc] = acc[kc];
+    }
+    __syncthreads();
+    if (tid < KC) prow[c0 + tid] = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
+    __syncthreads();
+}
+
+// partial[b * ldp + c] = sum over the kDotRows rows of block b of V[i,c] w[i]
+// (c < ncols). Columns go 8 at a time, then 4, 2, 1 for the remainder, so
+// no load waits behind a column-count test. Rows past n read row n-1 and
+// are weighted by zero.
 template <typename XT>
 __global__ __launch_bounds__(256) void k_dots(int n, const XT *V, long ldv, int ncols, const XT *w,
                                               double *partial, int ldp) {
     constexpr int RPT = kDotRows / 256;
     __shared__ double sm[4][kDotCols];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long base = (long)blockIdx.x * kDotRows;
+    long ii[RPT];
     double wv[RPT];
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
-        const long i = base + s * 256 + tid;
-        wv[s] = (i < n) ? (double)ldx(w, i) : 0.0;
+        const long i = base + s * 256 + threadIdx.x;
+        ii[s] = i < n ? i : (long)n - 1;
+        const double t = (double)ldx(w, ii[s]);
+        wv[s] = i < n ? t : 0.0;
     }
-    for (int c0 = 0; c0 < ncols; c0 += kDotCols) {
-        double acc[kDotCols];
-#pragma unroll
-        for (int kc = 0; kc < kDotCols; ++kc) acc[kc] = 0.0;
-#pragma unroll
-        for (int s = 0; s < RPT; ++s) {
-            const long i = base + s * 256 + tid;
-            if (i < n) {
-#pragma unroll
-                for (int kc = 0; kc < kDotCols; ++kc)
-                    if (c0 + kc < ncols) acc[kc] += (double)ldx(V, i + (long)(c0 + kc) * ldv) * wv[s];
-            }
-        }
-#pragma unroll
-        for (int kc = 0; kc < kDotCols; ++kc) acc[kc] = wave_sum(acc[kc]);
-        if (lane == 0) {
-#pragma unroll
-            for (int kc = 0; kc < kDotCols; ++kc) sm[wave][kc] = acc[kc];
-        }
-        __syncthreads();
-        if (tid < kDotCols && c0 + tid < ncols)
-            partial[(long)blockIdx.x * ldp + c0 + tid] = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
-        __syncthreads();
+    double *prow = partial + (long)blockIdx.x * ldp;
+    int c0 = 0;
+    for (; c0 + 8 <= ncols; c0 += 8) dots_chunk<XT, 8>(V, ldv, c0, ii, wv, sm, prow);
+    if (ncols - c0 >= 4) {
+        dots_chunk<XT, 4>(V, ldv, c0, ii, wv, sm, prow);
+        c0 += 4;
     }
+    if (ncols - c0 >= 2) {
+        dots_chunk<XT, 2>(V, ldv, c0, ii, wv, sm, prow);
+        c0 += 2;
+    }
+    if (ncols - c0 >= 1) dots_chunk<XT, 1>(V, ldv, c0, ii, wv, sm, prow);
+}
+
+// sum over k < ncols of V[i,k] h[k] for one row: columns 8 at a time (then
+// 4, 2, 1) with each chunk's loads issued together.
+template <typename XT, int KC>
+__device__ __forceinline__ void vh_chunk(const XT *__restrict__ V, long ldv, int k0, const double *__restrict__ h,
+                                         long i, double *a) {
+    double x[KC];
+#pragma unroll
+    for (int u = 0; u < KC; ++u) x[u] = (double)ldx(V, i + (long)(k0 + u) * ldv);
+#pragma unroll
+    for (int u = 0; u < KC; ++u) a[u] += x[u] * h[k0 + u];
+}
+
+template <typename XT>
+__device__ __forceinline__ double vh_row(const XT *__restrict__ V, long ldv, int ncols, const double *__restrict__ h,
+                                         long i) {
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int k0 = 0;
+    for (; k0 + 8 <= ncols; k0 += 8) vh_chunk<XT, 8>(V, ldv, k0, h, i, a);
+    if (ncols - k0 >= 4) {
+        vh_chunk<XT, 4>(V, ldv, k0, h, i, a);
+        k0 += 4;
+    }
+    if (ncols - k0 >= 2) {
+        vh_chunk<XT, 2>(V, ldv, k0, h, i, a);
+        k0 += 2;
+    }
+    if (ncols - k0 >= 1) vh_chunk<XT, 1>(V, ldv, k0, h, i, a);
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_reduce(int nblk, const double *partial, int ldp, double *h,
@@ -717,16 +816,8 @@ __global__ __launch_bounds__(256) void k_update(int n, const XT *V, long ldv, in
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     double sq = 0.0;
     if (i < n) {
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        int k = 0;
-        for (; k + 4 <= ncols; k += 4) {
-            acc0 += (double)ldx(V, i + (long)k * ldv) * h[k];
-            acc1 += (double)ldx(V, i + (long)(k + 1) * ldv) * h[k + 1];
-            acc2 += (double)ldx(V, i + (long)(k + 2) * ldv) * h[k + 2];
-            acc3 += (double)ldx(V, i + (long)(k + 3) * ldv) * h[k + 3];
-        }
-        for (; k < ncols; ++k) acc0 += (double)ldx(V, i + (long)k * ldv) * h[k];
-        const double wn = (double)ldx(w, i) - ((acc0 + acc1) + (acc2 + acc3));
+        const double vh = vh_row(V, ldv, ncols, h, i);
+        const double wn = (double)ldx(w, i) - vh;
         stx(w, i, (typename Arith<XT>::T)wn);
         const double stored = stored_value(w, wn);
         sq = stored * stored;
@@ -759,9 +850,11 @@ __global__ __launch_bounds__(256) void k_update_dots(int n, const XT *V, long ld
     for (int q = 0; q < RPT; ++q) {
         const long i = ((long)blockIdx.x * RPT + q) * 256 + tid;
         if (i < n) {
+            // columns past ncols re-read the last one (h is zero there and
+            // their sums are dropped), so no load waits behind a test
             AT vr[KMAX];
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) vr[k] = k < ncols ? (AT)ldx(V, i + (long)k * ldv) : AT(0);
+            for (int k = 0; k < KMAX; ++k) vr[k] = (AT)ldx(V, i + (long)(k < ncols ? k : ncols - 1) * ldv);
             double wi = (double)ldx(w, i);
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) wi -= (double)vr[k] * hs[k];
@@ -811,16 +904,8 @@ __global__ __launch_bounds__(256) void k_update_scale(int n, const XT *V, long l
                                                       const double *inv) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    int k = 0;
-    for (; k + 4 <= ncols; k += 4) {
-        acc0 += (double)ldx(V, i + (long)k * ldv) * h[k];
-        acc1 += (double)ldx(V, i + (long)(k + 1) * ldv) * h[k + 1];
-        acc2 += (double)ldx(V, i + (long)(k + 2) * ldv) * h[k + 2];
-        acc3 += (double)ldx(V, i + (long)(k + 3) * ldv) * h[k + 3];
-    }
-    for (; k < ncols; ++k) acc0 += (double)ldx(V, i + (long)k * ldv) * h[k];
-    const double wn = ((double)ldx(w, i) - ((acc0 + acc1) + (acc2 + acc3))) * inv[0];
+    const double vh = vh_row(V, ldv, ncols, h, i);
+    const double wn = ((double)ldx(w, i) - vh) * inv[0];
     stx(w, i, (typename Arith<XT>::T)wn);
 }
 
@@ -1135,22 +1220,33 @@ constexpr int kUdRows = 4;  // rows per thread of k_update_dots
 
 int update_dots_blocks(int n) { return (int)blocks_for(n, 256 * kUdRows); }
 
-int update_dots_max_cols(int prec) { return prec == 0 ? 32 : 64; }
+int update_dots_max_cols(int prec) { return prec == 0 ? 48 : 64; }
 
 template <typename XT>
 static hipError_t ud_launch(int n, const XT *V, long ldv, int ncols, const double *h, XT *w, double *partial, int ldp,
                             hipStream_t st, int prec) {
     const unsigned g = blocks_for(n, 256 * kUdRows);
     if (g == 0 || ncols == 0) return hipSuccess;
-    if (ncols <= 16)
-        hipLaunchKernelGGL((k_update_dots<XT, 16, kUdRows>), dim3(g), dim3(256), 0, st, n, V, ldv, ncols, h, w,
-                           partial, ldp);
+#define PP_UD(K)                                                                                             \
+    hipLaunchKernelGGL((k_update_dots<XT, K, kUdRows>), dim3(g), dim3(256), 0, st, n, V, ldv, ncols, h, w, partial, \
+                       ldp)
+    if (ncols <= 4)
+        PP_UD(4);
+    else if (ncols <= 8)
+        PP_UD(8);
+    else if (ncols <= 16)
+        PP_UD(16);
+    else if (ncols <= 24)
+        PP_UD(24);
     else if (ncols <= 32)
-        hipLaunchKernelGGL((k_update_dots<XT, 32, kUdRows>), dim3(g), dim3(256), 0, st, n, V, ldv, ncols, h, w,
-                           partial, ldp);
+        PP_UD(32);
+    else if (ncols <= 40)
+        PP_UD(40);
+    else if (ncols <= 48)
+        PP_UD(48);
     else if (prec != 0 && ncols <= 64)
-        hipLaunchKernelGGL((k_update_dots<XT, 64, kUdRows>), dim3(g), dim3(256), 0, st, n, V, ldv, ncols, h, w,
-                           partial, ldp);
+        PP_UD(64);
+#undef PP_UD
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1303,7 +1399,7 @@ const char *chain_variant_name(int v) {
     static const char *names[CV_COUNT] = {"tile8x1", "tile16x2", "vec1x4",  "vec4x4",    "vec8x2",
                                           "vec8x4",  "vec16x2",  "vec16x4", "vec32x2",   "tilev8x1",
                                           "tilev16x2", "vk2x4x4", "vk4x4x2", "vk8x4x1", "vk16x2x2", "persist8",
-                                          "tileb8x1", "tileb16x2", "sell64", "sell64t"};
+                                          "tileb8x1", "tileb16x2", "sell64", "sell64t", "sell64x2", "sell64x4", "sell64d16", "sell64d16x4"};
     return (v >= 0 && v < CV_COUNT) ? names[v] : "?";
 }
 

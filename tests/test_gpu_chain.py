@@ -150,7 +150,7 @@ def test_bad_arguments_rejected(pp):
         pp.Matrix(np.array([0, 2, 1], dtype=np.int32), np.array([0, 1], dtype=np.int32), np.ones(2))  # rowptr
 
 
-@pytest.mark.parametrize("variant", range(20))
+@pytest.mark.parametrize("variant", range(24))
 def test_every_chain_variant_matches_oracle(pp, variant):
     # each kernel variant the autotuner may pick, with and without the XCD order
     for name in ["ragged_5000", "randsparse_20000", "convdiff3d_20"]:
@@ -183,6 +183,10 @@ def test_autotuner_picks_a_valid_variant(pp):
     csr = convdiff3d(48, 10, 10, 10)
     M = pp.Matrix.from_csr(csr)
     say("autotune")
+    assert M.variant("fp32")[0] is None  # nothing tuned or set yet
     for prec in ("fp64", "fp32", "bf16"):
         name, remap, us = M.tune(prec)
-        assert name in [pp.chain_variant_name(v) for v in range(20)] and remap in (0, 1) and us > 0
+        assert name in [pp.chain_variant_name(v) for v in range(24)] and remap in (0, 1) and us > 0
+        assert M.variant(prec) == (name, remap, us)
+    M.set_variant("fp32", 3, 0)
+    assert M.variant("fp32") == (pp.chain_variant_name(3), 0, 0.0)
