@@ -34,6 +34,70 @@ def step_bytes(n, nnz, s_val, s_vec):
     return nnz * (s_val + 4) + 4 * (n + 1) + 2 * n * s_vec
 
 
+# HBM traffic of the chain kernel, from rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE)
+# runs of ``bench.py --traffic-probe``, kept with the command that made it.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_chain_step_convdiff3d_128.md")
+KERNEL_SOURCES = ("kernels.hip", "kernels.h", "devutil.h")
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written
+
+
+def kernel_source_hash():
+    """sha256 over the sources the chain kernels are compiled from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1911_07065_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(prec, variant, remap):
+    """Measured HBM bytes per launch for (prec, variant, remap), or None when
+    there is no record, it is for other kernel sources, or other variants."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            line = next(l for l in fh if l.startswith("TRAFFIC_RECORD "))
+        rec = json.loads(line[len("TRAFFIC_RECORD "):])
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    for e in rec.get("kernels", []):
+        if e["prec"] == prec and e["variant"] == variant and e["remap"] == remap:
+            return e
+    return None
+
+
+def traffic_probe(pp, torch, np, M, n):
+    """Launch sequence for the counter runs: a plain copy of COPY_BYTES (to
+    calibrate FETCH_SIZE and WRITE_SIZE), then for each sliced-ELL variant and
+    precision 4 phi applications of an 8-root real polynomial (32 launches of
+    exactly one chain step each: the input read and gathered, the output
+    written)."""
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    log("copy", COPY_BYTES, "bytes x3")
+    poly = pp.poly_from_roots(np.linspace(2.0, 11.0, 8), keep_order=True)
+    names = [pp.chain_variant_name(v) for v in range(pp.N_CHAIN_VARIANTS)]
+    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        v = torch.as_tensor(np.random.default_rng(5).standard_normal(n), device="cuda").to(dt)
+        out = torch.empty_like(v)
+        for vi, name in enumerate(names):
+            if not name.startswith("sell"):
+                continue
+            M.set_variant(prec, vi, 1)
+            for _ in range(4):
+                pp.apply(poly, M, v, "phi", out=out)
+            torch.cuda.synchronize()
+            log("probe", prec, name, "remap 1: 32 launches")
+    log("kernel sources sha256", kernel_source_hash())
+
+
 def cpu_baseline(csr, b, v0, d, m, gpu_iters, gpu_cycles, d_eff):
     """The oracle timed on the host on a bounded sample, extrapolated to the solve's op counts."""
     import numpy as np
@@ -100,6 +164,8 @@ def main():
     ap.add_argument("--m", type=int, default=50)
     ap.add_argument("--pav-reps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run the launch sequence the rocprofv3 counter runs read (no JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the build has no multi-GPU path; "
@@ -123,6 +189,9 @@ def main():
     bd = torch.as_tensor(b, device="cuda")
     v0d = torch.as_tensor(v0, device="cuda")
     torch.cuda.synchronize()
+    if args.traffic_probe:
+        traffic_probe(pp, torch, np, M, n)
+        return
 
     def step(inner):
         poly = pp.setup(M, v0d, d)
@@ -172,12 +241,15 @@ def main():
         log("p(A)v", prec, f"{ms:.3f} ms", f"{pav[prec]['GBps']:.0f} GB/s", f"{pav[prec]['launch_us']:.1f} us/launch")
         # phi(A)v: d_eff launches of exactly one chain step each (the Arnoldi operator)
         ms = event_ms(lambda: pp.apply(poly, M, v, "phi", out=y), args.pav_reps)
+        vname, vremap, _ = M.variant(prec)
         phi[prec] = dict(ms=ms, launch_us=ms * 1e3 / poly.d_eff, step_bytes=step_bytes(n, nnz, sv, sx),
-                         variant=M.variant(prec)[0])
+                         variant=vname, remap=vremap)
         log("phi(A)v", prec, f"{ms:.3f} ms", f"{phi[prec]['launch_us']:.2f} us/launch", phi[prec]["variant"])
 
     k32 = phi["fp32"]
     achieved = k32["step_bytes"] / (k32["launch_us"] * 1e-6) / 1e9
+    tr = recorded_traffic("fp32", k32["variant"], k32["remap"])
+    log("recorded traffic", tr)
     roofline = {
         "bound": "hbm",
         "kernel": f"k_chain_sell<float,float> ({k32['variant']}: fused sliced-ELL SpMV + chain update, one root)"
@@ -186,8 +258,14 @@ def main():
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBPS, 4),
-        "traffic": None,
+        "traffic": tr["traffic_bytes"] if tr else None,
         "bytes_per_launch": k32["step_bytes"],
+        # measured HBM-side bytes over the same launch time (sliced-ELL with
+        # 16-bit offsets moves fewer bytes than CSR; the 256 MB MALL serves
+        # part of the re-read matrix)
+        "traffic_GBps": round(tr["traffic_bytes"] / (k32["launch_us"] * 1e-6) / 1e9, 1) if tr else None,
+        "traffic_frac": round(tr["traffic_bytes"] / (k32["launch_us"] * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)
+        if tr else None,
         "avg_launch_us": round(k32["launch_us"], 3),
         "fp64_avg_launch_us": round(phi["fp64"]["launch_us"], 3),
         "fp64_variant": phi["fp64"]["variant"],
