@@ -264,7 +264,8 @@ pp_status pp_batch_setup(pp_batch B, const double *v0, int d, int add_roots, voi
  * all (system, right-hand side) pairs in lockstep: each pair has its own
  * Krylov basis, Hessenberg matrix and stopping test, each system its own
  * polynomial (polys: host array of nsys). b, x: device double[n * nrhs],
- * interleaved (entry (row i, rhs r) at i*nrhs + r); x is overwritten.
+ * interleaved (entry (row i, rhs r) at i*nrhs + r), each aligned to
+ * 8*nrhs bytes (PP_EINVAL otherwise; fresh allocations are); x is overwritten.
  * opts as for pp_solve (opts->history receives pair 0's residuals). infos:
  * host array of nsys*nrhs (pair s*nrhs + r) or NULL. PP_NOCONV if some pair
  * did not converge. */

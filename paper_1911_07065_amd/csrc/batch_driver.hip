@@ -26,7 +26,7 @@ namespace {
 
 constexpr double kBreakdownTolB = 1e-14;
 constexpr double kInnerEtaB[3] = {0.0, 1e-5, 1e-2};
-constexpr int kBlockRows = 1024;  // rows per reduction block (system-aligned)
+constexpr int kBlockRows = kBatchBlockRows;
 
 struct BWork {
     int m = -1, R = 0;
@@ -530,6 +530,12 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
     if (!B || !polys || !b || !x || !opts || !(nrhs == 1 || nrhs == 2 || nrhs == 4) || opts->m < 1 ||
         opts->max_cycles < 0 || !(opts->tol > 0.0) || opts->inner < 0 || opts->inner > 2) {
         set_error("pp_batch_solve: bad argument (nrhs must be 1, 2 or 4)");
+        return PP_EINVAL;
+    }
+    // the kernels move the nrhs values of a row as one vector access
+    const uintptr_t al = (uintptr_t)(8 * nrhs);
+    if ((uintptr_t)b % al != 0 || (uintptr_t)x % al != 0) {
+        set_error("pp_batch_solve: b and x must be aligned to nrhs doubles (8*nrhs bytes)");
         return PP_EINVAL;
     }
     for (int s = 0; s < B->nsys; ++s)

@@ -27,8 +27,12 @@ struct BatchSell {
     const int *active;  // per system: 0 = skip its slices (null: all run)
 };
 
-// System-aligned row blocks for reductions: block[b] = {row0, nrows, sys, 0};
-// the blocks of system s are boff[s] .. boff[s+1]-1.
+// Rows per reduction block; a block never crosses a system boundary.
+constexpr int kBatchBlockRows = 1024;
+
+// System-aligned row blocks for reductions: block[b] = {row0, nrows, sys, 0}
+// with nrows <= kBatchBlockRows; the blocks of system s are boff[s] ..
+// boff[s+1]-1.
 struct BatchBlocks {
     const int4 *block;
     const int32_t *boff;

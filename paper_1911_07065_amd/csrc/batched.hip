@@ -18,6 +18,42 @@
 namespace ppg {
 namespace {
 
+// The R interleaved values of row i (elements i*R .. i*R + R - 1) move as
+// one vector access; every buffer is aligned to R elements (workspace
+// columns are multiples of 64 elements apart and the caller's b and x are
+// checked on entry).
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ float widen(float v) { return v; }
+__device__ __forceinline__ float widen(uint16_t v) { return __uint_as_float(((uint32_t)v) << 16); }
+__device__ __forceinline__ double narrow(const double *, double v) { return v; }
+__device__ __forceinline__ float narrow(const float *, float v) { return v; }
+__device__ __forceinline__ uint16_t narrow(const uint16_t *, float v) { return f32_to_bf16(v); }
+
+template <typename XT, int R>
+__device__ __forceinline__ void ldr(const XT *__restrict__ p, long i, typename Arith<XT>::T *o) {
+    if constexpr (R == 1) {
+        o[0] = widen(p[i]);
+    } else {
+        typedef XT VecT __attribute__((ext_vector_type(R)));
+        const VecT t = *reinterpret_cast<const VecT *>(p + i * R);
+#pragma unroll
+        for (int r = 0; r < R; ++r) o[r] = widen(t[r]);
+    }
+}
+
+template <typename XT, int R>
+__device__ __forceinline__ void str(XT *__restrict__ p, long i, const typename Arith<XT>::T *v) {
+    if constexpr (R == 1) {
+        p[i] = narrow(p, v[0]);
+    } else {
+        typedef XT VecT __attribute__((ext_vector_type(R)));
+        VecT t;
+#pragma unroll
+        for (int r = 0; r < R; ++r) t[r] = narrow(p, v[r]);
+        *reinterpret_cast<VecT *>(p + i * R) = t;
+    }
+}
+
 template <typename VT, typename XT>
 struct BChainArgs {
     const int4 *slice;
@@ -56,82 +92,152 @@ __global__ __launch_bounds__(256) void k_bchain(BChainArgs<VT, XT> a) {
     if (st.spmv) {
         const int o0 = a.sptr[w];
         const int width = (a.sptr[w + 1] - o0) >> 6;
+        // positions past the slice width re-read its last entry and are
+        // dropped by a select, so every load of a block of U is issued
+        // before the first is used
         for (int k0 = 0; k0 < width; k0 += U) {
             int c[U];
             VT v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                c[u] = 0;
-                v[u] = VT(0);
-                if (k0 + u < width) {
-                    const int o = o0 + (k0 + u) * 64 + lane;
-                    c[u] = __builtin_nontemporal_load(a.scol + o);
-                    v[u] = __builtin_nontemporal_load(a.sval + o);
-                }
+                const int o = o0 + min(k0 + u, width - 1) * 64 + lane;
+                c[u] = __builtin_nontemporal_load(a.scol + o);
+                v[u] = __builtin_nontemporal_load(a.sval + o);
             }
+            AT xv[U][R];
+#pragma unroll
+            for (int u = 0; u < U; ++u) ldr<XT, R>(in, c[u], xv[u]);
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (k0 + u < width) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) s[r] += (AT)v[u] * ldx(in, (long)c[u] * R + r);
+                for (int r = 0; r < R; ++r) {
+                    const AT t = (AT)v[u] * xv[u][r];
+                    s[r] += (k0 + u < width) ? t : AT(0);
                 }
         }
     }
     if (!active) return;
     const AT a0 = (AT)st.a0, a1 = (AT)st.a1, a2 = (AT)st.a2, b0 = (AT)st.b0, b1 = (AT)st.b1;
+    AT xin[R], wv[R], t[R];
+    ldr<XT, R>(in, row, xin);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const long idx = row * R + r;
-        const AT xin = ldx(in, idx);
-        AT wv = a0 * s[r] + a1 * xin;
-        if (aux) wv += a2 * (AT)ldx(aux, idx);
-        if (acc) {
-            const AT old = st.acc_init ? AT(0) : (AT)ldx(acc, idx);
-            stx(acc, idx, old + b0 * xin + b1 * wv);
+    for (int r = 0; r < R; ++r) wv[r] = a0 * s[r] + a1 * xin[r];
+    if (aux) {
+        ldr<XT, R>(aux, row, t);
+#pragma unroll
+        for (int r = 0; r < R; ++r) wv[r] += a2 * t[r];
+    }
+    if (acc) {
+        if (st.acc_init) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) t[r] = AT(0);
+        } else {
+            ldr<XT, R>(acc, row, t);
         }
-        if (out) stx(out, idx, vfin ? (AT)ldx(vfin, idx) - wv : wv);
+#pragma unroll
+        for (int r = 0; r < R; ++r) t[r] = t[r] + b0 * xin[r] + b1 * wv[r];
+        str<XT, R>(acc, row, t);
+    }
+    if (out) {
+        if (vfin) {
+            ldr<XT, R>(vfin, row, t);
+#pragma unroll
+            for (int r = 0; r < R; ++r) t[r] = t[r] - wv[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) t[r] = wv[r];
+        }
+        str<XT, R>(out, row, t);
     }
 }
 
-// Gram-Schmidt projections, KC columns per pass.
+// One chunk of KC Krylov columns of k_bdots for R interleaved right-hand
+// sides: all loads of the chunk are issued before the first is used.
+template <typename XT, int R, int KC>
+__device__ __forceinline__ void bdots_chunk(const XT *__restrict__ V, long ldv, int c0, const long *ii,
+                                            const double (*wv)[R], double (*sm)[8], double *prow) {
+    constexpr int RPT = kBatchBlockRows / 256;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    typename Arith<XT>::T x[RPT][KC][R];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s)
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) ldr<XT, R>(V + (long)(c0 + kc) * ldv, ii[s], x[s][kc]);
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < RPT; ++s) acc += (double)x[s][kc][r] * wv[s][r];
+            acc = wave_sum(acc);
+            if (lane == 0) sm[wave][kc * R + r] = acc;
+        }
+    __syncthreads();
+    if (tid < KC * R) prow[(long)c0 * R + tid] = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
+    __syncthreads();
+}
+
+// Gram-Schmidt projections of one system-aligned block (<= kBatchBlockRows
+// rows, 4 per thread): partial[b*ldp + c*R + r] = sum over the block of
+// V_c[i*R+r] w[i*R+r]. Columns go 8/R at a time, then smaller chunks for the
+// remainder; rows past the block read its last row with weight zero.
 template <typename XT, int R>
 __global__ __launch_bounds__(256) void k_bdots(const int4 *block, const int *active, const XT *V, long ldv, int ncols,
                                                const XT *w, double *partial, int ldp) {
-    constexpr int KC = 16 / R;
-    __shared__ double sm[4][KC * R];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int RPT = kBatchBlockRows / 256;
+    constexpr int KC = 8 / R;
+    __shared__ double sm[4][8];
     const int4 bi = block[blockIdx.x];
     if (active && !active[bi.z]) return;
-    const long r0 = bi.x, r1 = (long)bi.x + bi.y;
-    for (int c0 = 0; c0 < ncols; c0 += KC) {
-        double acc[KC][R];
+    const long r1 = (long)bi.x + bi.y;
+    long ii[RPT];
+    double wv[RPT][R];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+        const long i = (long)bi.x + s * 256 + threadIdx.x;
+        ii[s] = i < r1 ? i : r1 - 1;
+        typename Arith<XT>::T t[R];
+        ldr<XT, R>(w, ii[s], t);
+#pragma unroll
+        for (int r = 0; r < R; ++r) wv[s][r] = i < r1 ? (double)t[r] : 0.0;
+    }
+    double *prow = partial + (long)blockIdx.x * ldp;
+    int c0 = 0;
+    for (; c0 + KC <= ncols; c0 += KC) bdots_chunk<XT, R, KC>(V, ldv, c0, ii, wv, sm, prow);
+    if (KC >= 8 && ncols - c0 >= 4) {
+        bdots_chunk<XT, R, (KC >= 8 ? 4 : 1)>(V, ldv, c0, ii, wv, sm, prow);
+        c0 += 4;
+    }
+    if (KC >= 4 && ncols - c0 >= 2) {
+        bdots_chunk<XT, R, (KC >= 4 ? 2 : 1)>(V, ldv, c0, ii, wv, sm, prow);
+        c0 += 2;
+    }
+    if (KC >= 2 && ncols - c0 >= 1) bdots_chunk<XT, R, 1>(V, ldv, c0, ii, wv, sm, prow);
+}
+
+// sum over c < ncols of V_c[i*R+r] h[c*R+r] for one row and every r, with
+// columns taken KC at a time (all loads of a chunk issued together); KC = 1
+// covers the remainder.
+template <typename XT, int R>
+__device__ __forceinline__ void bvh_row(const XT *__restrict__ V, long ldv, int ncols, const double *__restrict__ hs,
+                                        long i, double *acc) {
+    constexpr int KC = 16 / R;
+    int c0 = 0;
+    for (; c0 + KC <= ncols; c0 += KC) {
+        typename Arith<XT>::T x[KC][R];
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) ldr<XT, R>(V + (long)(c0 + kc) * ldv, i, x[kc]);
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[kc][r] = 0.0;
-        for (long i = r0 + tid; i < r1; i += 256) {
-            double wv[R];
+            for (int r = 0; r < R; ++r) acc[r] += (double)x[kc][r] * hs[(c0 + kc) * R + r];
+    }
+    for (; c0 < ncols; ++c0) {
+        typename Arith<XT>::T x[R];
+        ldr<XT, R>(V + (long)c0 * ldv, i, x);
 #pragma unroll
-            for (int r = 0; r < R; ++r) wv[r] = (double)ldx(w, i * R + r);
-#pragma unroll
-            for (int kc = 0; kc < KC; ++kc)
-                if (c0 + kc < ncols) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) acc[kc][r] += (double)ldx(V, (long)(c0 + kc) * ldv + i * R + r) * wv[r];
-                }
-        }
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const double t = wave_sum(acc[kc][r]);
-                if (lane == 0) sm[wave][kc * R + r] = t;
-            }
-        __syncthreads();
-        if (tid < KC * R && c0 + tid / R < ncols)
-            partial[(long)blockIdx.x * ldp + (long)c0 * R + tid] =
-                ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
-        __syncthreads();
+        for (int r = 0; r < R; ++r) acc[r] += (double)x[r] * hs[c0 * R + r];
     }
 }
 
@@ -166,15 +272,20 @@ __global__ __launch_bounds__(256) void k_bupdate(const int4 *block, const int *a
 #pragma unroll
     for (int r = 0; r < R; ++r) sq[r] = 0.0;
     for (long i = r0 + tid; i < r1; i += 256) {
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        bvh_row<XT, R>(V, ldv, ncols, hs, i, acc);
+        typename Arith<XT>::T wr[R];
+        ldr<XT, R>(w, i, wr);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            double acc = 0.0;
-            for (int c = 0; c < ncols; ++c) acc += (double)ldx(V, (long)c * ldv + i * R + r) * hs[c * R + r];
-            const double wn = (double)ldx(w, i * R + r) - acc;
-            stx(w, i * R + r, (typename Arith<XT>::T)wn);
+            const double wn = (double)wr[r] - acc[r];
+            wr[r] = (typename Arith<XT>::T)wn;
             const double stv = stored_value(w, wn);
             sq[r] += stv * stv;
         }
+        str<XT, R>(w, i, wr);
     }
     if (!npart) return;
 #pragma unroll
@@ -205,11 +316,12 @@ __global__ __launch_bounds__(256) void k_bscale(const int4 *block, const int *ac
     if (active && !active[bi.z]) return;
     const long r0 = bi.x, r1 = (long)bi.x + bi.y;
     for (long i = r0 + threadIdx.x; i < r1; i += 256) {
+        typename Arith<TI>::T v[R];
+        typename Arith<TO>::T o[R];
+        ldr<TI, R>(in, i, v);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double v = (double)ldx(in, i * R + r) * scale[(long)bi.z * R + r];
-            stx(out, i * R + r, (typename Arith<TO>::T)v);
-        }
+        for (int r = 0; r < R; ++r) o[r] = (typename Arith<TO>::T)((double)v[r] * scale[(long)bi.z * R + r]);
+        str<TO, R>(out, i, o);
     }
 }
 
@@ -220,16 +332,37 @@ __global__ __launch_bounds__(256) void k_bcombine(const int4 *block, const XT *V
                                                   const double *z, int ldz, XT *out) {
     const int4 bi = block[blockIdx.x];
     const long r0 = bi.x, r1 = (long)bi.x + bi.y;
-    for (long i = r0 + threadIdx.x; i < r1; i += 256) {
+    int kr[R], kmax = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const long p = (long)bi.z * R + r;
-            const double *zp = z + p * ldz;
-            const int k = kp[p];
-            double acc = 0.0;
-            for (int j = 0; j < k; ++j) acc += (double)ldx(V, (long)j * ldv + i * R + r) * zp[j];
-            stx(out, i * R + r, (typename Arith<XT>::T)acc);
+    for (int r = 0; r < R; ++r) {
+        kr[r] = kp[(long)bi.z * R + r];
+        kmax = kr[r] > kmax ? kr[r] : kmax;
+    }
+    const double *zs = z + (long)bi.z * R * ldz;
+    constexpr int KC = 16 / R;
+    for (long i = r0 + threadIdx.x; i < r1; i += 256) {
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        // columns j >= kr[r] of pair r are dropped by a select (they may hold
+        // stale values of other cycles), so a chunk's loads go out together
+        for (int j0 = 0; j0 < kmax; j0 += KC) {
+            typename Arith<XT>::T x[KC][R];
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) ldr<XT, R>(V + (long)min(j0 + kc, kmax - 1) * ldv, i, x[kc]);
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int j = j0 + kc;
+                    const double t = (double)x[kc][r] * zs[(long)r * ldz + min(j, kmax - 1)];
+                    acc[r] += j < kr[r] ? t : 0.0;
+                }
         }
+        typename Arith<XT>::T o[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) o[r] = (typename Arith<XT>::T)acc[r];
+        str<XT, R>(out, i, o);
     }
 }
 
