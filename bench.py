@@ -10,6 +10,11 @@ One step = polynomial setup + solve (the whole hot path) with the p/phi
 chains and Krylov vectors in FP32 inside FP64 iterative refinement. The
 plain FP64 form is timed beside it. Inputs are resident in HBM before the
 timed region. Prints one JSON line.
+
+Two more legs are reported beside the headline (skip with --no-extras):
+differentiation through the solve on a 1024^2 2-D system (forward +
+adjoint) and the batched solve of 256 systems x 4 right-hand sides against
+a loop of single solves.
 """
 
 import argparse
@@ -98,6 +103,92 @@ def traffic_probe(pp, torch, np, M, n):
     log("kernel sources sha256", kernel_source_hash())
 
 
+def adjoint_leg(pp, torch, np):
+    """Differentiation through the solve: loss 0.5 ||x(theta, b) - x_t||^2 on
+    the 2-D convection-diffusion 1024^2 system whose convection coefficient
+    theta = 20 is a leaf tensor; degree 50, GMRES(50), tol 1e-12, FP64.
+    Timed: polynomial setup, forward solve and adjoint solve (same roots on
+    the transposed pattern), after one untimed pass."""
+    from workloads import convdiff2d_parts, rhs, start_vector
+
+    N, theta0 = 1024, 20.0
+    A0, dval = convdiff2d_parts(N)
+    n = N * N
+    M = pp.Matrix.from_csr(A0)
+    base = torch.as_tensor(A0.val, device="cuda")
+    dirv = torch.as_tensor(dval, device="cuda")
+    bd = torch.as_tensor(rhs(n, 1), device="cuda")
+    xt = torch.as_tensor(np.random.default_rng(3).standard_normal(n), device="cuda")
+    v0 = torch.as_tensor(start_vector(n, 2), device="cuda")
+
+    def once():
+        M.set_values(base + theta0 * dirv)
+        poly = pp.setup(M, v0, 50)
+        th = torch.tensor(theta0, dtype=torch.float64, device="cuda", requires_grad=True)
+        bt = bd.clone().requires_grad_(True)
+        x = pp.pp_solve_fn(base + th * dirv, bt, M, poly, tol=1e-12, m=50, inner="fp64")
+        loss = 0.5 * torch.sum((x - xt) ** 2)
+        loss.backward()
+        return float(th.grad), float(torch.linalg.norm(bt.grad))
+
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, gb = once()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    log("adjoint", f"{t * 1e3:.1f} ms", "dL/dtheta", g)
+    return {"workload": f"2-D convection-diffusion {N}^2 (n={n}, nnz={A0.nnz}), theta=20 leaf, "
+                        "PP(50)-GMRES(50) to 1e-12 FP64, forward + adjoint",
+            "time_s": round(t, 6), "dL_dtheta": g, "norm_dL_db": gb}
+
+
+def batched_leg(pp, torch, np, loop_every=16):
+    """Batched solve: 256 2-D convection-diffusion systems (sides U{64..512},
+    coefficient U[0,50)), 4 right-hand sides each, degree 20, GMRES(50),
+    FP32 inner / FP64 outer, tol 1e-8 (setup + solve), against a loop of
+    single-system solves timed on every 16th system (matrix handle made and
+    tuned outside the timing) and scaled to the batch."""
+    from workloads import batched_convdiff_specs, convdiff2d, rhs, start_vector
+
+    specs = batched_convdiff_specs()
+    csrs = [convdiff2d(N, a) for (N, a, _, _) in specs]
+    B = pp.Batch(csrs)
+    v0 = torch.as_tensor(np.concatenate([start_vector(N * N, s2) for (N, _, _, s2) in specs]), device="cuda")
+    brs = [rhs(N * N, s1, count=4) for (N, _, s1, _) in specs]
+    bd = B.interleave(np.concatenate(brs, axis=1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    polys = B.setup(v0, 20)
+    x, infos = B.solve(polys, bd, 4, tol=1e-8, m=50, inner="fp32")
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    ok = all(i["converged"] for i in infos)
+    worst = max(i["relres"] for i in infos)
+    log("batched", f"{t_batch:.3f} s", "converged", ok, "worst relres", worst)
+    t_loop, sub = 0.0, list(range(0, len(csrs), loop_every))
+    for s in sub:
+        M = pp.Matrix.from_csr(csrs[s])
+        M.tune("fp32")
+        M.tune("fp64")
+        bs = [torch.as_tensor(brs[s][r], device="cuda") for r in range(4)]
+        v0s = torch.as_tensor(start_vector(csrs[s].n, specs[s][3]), device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        poly = pp.setup(M, v0s, 20)
+        for r in range(4):
+            pp.solve(poly, M, bs[r], tol=1e-8, m=50, inner="fp32")
+        torch.cuda.synchronize()
+        t_loop += time.perf_counter() - t1
+    t_loop *= len(csrs) / len(sub)
+    log("loop of single solves (scaled)", f"{t_loop:.3f} s")
+    return {"workload": f"256 x 2-D convection-diffusion (sum n={B.n}, nnz={B.nnz}), 4 RHS each, PP(20)-GMRES(50) "
+                        "to 1e-8, FP32 inner / FP64 outer, setup included",
+            "time_s": round(t_batch, 6), "all_converged": ok, "worst_relres": worst,
+            "loop_time_s": round(t_loop, 6), "loop_sample": f"every {loop_every}th system, scaled",
+            "speedup_vs_loop": round(t_loop / t_batch, 3)}
+
+
 def cpu_baseline(csr, b, v0, d, m, gpu_iters, gpu_cycles, d_eff):
     """The oracle timed on the host on a bounded sample, extrapolated to the solve's op counts."""
     import numpy as np
@@ -164,6 +255,8 @@ def main():
     ap.add_argument("--m", type=int, default=50)
     ap.add_argument("--pav-reps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the differentiation and batched legs")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the launch sequence the rocprofv3 counter runs read (no JSON line)")
     args = ap.parse_args()
@@ -271,6 +364,11 @@ def main():
         "fp64_variant": phi["fp64"]["variant"],
     }
 
+    extras = {}
+    if not args.no_extras:
+        extras["adjoint"] = adjoint_leg(pp, torch, np)
+        extras["batched"] = batched_leg(pp, torch, np)
+
     cpu = None
     if not args.no_cpu:
         log("timing the oracle on the host (bounded sample)")
@@ -308,6 +406,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
 
 
