@@ -178,6 +178,29 @@ pp_status pp_adjoint_values(pp_matrix A, const double *lam, const double *x, dou
 pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, void *stream,
                          pp_poly *out, pp_setup_info *info);
 
+/* Options of the stability check run by pp_gmres_setup_checked (section 3.5). */
+typedef struct {
+    const double *b; /* device double[n]: the problem right-hand side the check uses */
+    double tol;      /* instability is predicted when StCh > tol * ||b|| */
+    int d_step;      /* > 0: lower the degree by d_step while instability is predicted */
+    int d_min;       /* lowest degree tried when lowering (values < 1 mean 1) */
+} pp_stch_opts;
+
+/* pp_gmres_setup followed by the stability check of section 3.5, which is
+ * computed once the polynomial is known and lets the degree be lowered when
+ * it predicts instability. The GMRES(d) cycle runs once; the polynomial of
+ * degree k < d comes from the leading (k+1) x k block of its Hessenberg
+ * matrix (the first k Arnoldi steps from v0 are the GMRES(k) cycle), so
+ * lowering costs host eigenvalue work and one check per degree tried.
+ * Degrees d, d - d_step, ... (not below d_min) are tried in turn; the first
+ * with StCh <= tol ||b|| is returned with PP_OK (or PP_BREAKDOWN as for
+ * pp_gmres_setup). If none passes, the one with the smallest StCh (NaN
+ * counting as infinite) is returned with the warning PP_UNSTABLE: the
+ * polynomial is valid. stch (host, may be NULL) receives its StCh. info->d
+ * is the degree returned; info->mvps and info->dots include the checks. */
+pp_status pp_gmres_setup_checked(pp_matrix A, const double *v0, int d, int add_roots, const pp_stch_opts *opts,
+                                 void *stream, pp_poly *out, pp_setup_info *info, double *stch);
+
 /* Flags of pp_poly_from_roots. */
 #define PP_ROOTS_ADD 1        /* add roots for stability (Algorithm 2) */
 #define PP_ROOTS_KEEP_ORDER 2 /* use the list as given: no Leja ordering, no added

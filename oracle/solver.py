@@ -27,6 +27,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import roots as _roots
 from .chains import apply_p, apply_phi, spmv_count_p, spmv_count_phi
 from .roots import BREAKDOWN_TOL, REAL
 
@@ -162,3 +163,44 @@ def stability_check(A, units, b: np.ndarray) -> float:
     r1 = b - A @ apply_p(A, units, b)
     r2 = b - apply_phi(A, units, b)
     return float(np.linalg.norm(r1 - r2))
+
+
+def setup_checked(A, v0: np.ndarray, d: int, b: np.ndarray, tol: float, d_step: int = 0, d_min: int = 1,
+                  add_roots: bool = True, orth: str = "mgs"):
+    """Polynomial setup followed by the stability check (section 3.5), with
+    the degree lowered while the check predicts instability.
+
+    Section 3.5 computes StCh once the polynomial is known, before the
+    solve, and lowers the degree when StCh predicts instability. Readings:
+    instability is predicted when StCh > tol ||b||. One GMRES(d) cycle runs
+    from v0; the polynomial of degree k < d comes from the leading
+    (k+1) x k block of its Hessenberg matrix, because the first k Arnoldi
+    steps from the same v0 are the GMRES(k) cycle. Degrees d, d - d_step,
+    ... (not below d_min) are tried in turn and the first with
+    StCh <= tol ||b|| is kept; when none passes, the one with the smallest
+    StCh is returned and flagged unstable (NaN counts as infinite).
+
+    Returns (Poly, stch, unstable, tried) with tried = [(k, StCh), ...].
+    """
+    v0 = np.asarray(v0, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    _, Hbar, k, brk = _roots.arnoldi(lambda v: A @ v, v0, d, orth)
+    limit = tol * float(np.linalg.norm(b))
+    tried, best = [], None
+    kk = k
+    while True:
+        at_break = brk and kk == k
+        theta = _roots.harmonic_ritz(Hbar[: kk + 1, :kk], breakdown=at_break)
+        leja, pof, n_add, units = _roots.order_and_add(theta, add_roots)
+        P = _roots.Poly(d=kk, theta=theta, leja=leja, pof=pof, n_add=n_add, units=units, breakdown=at_break)
+        st = stability_check(A, P.units, b)
+        tried.append((kk, st))
+        if st <= limit:
+            return P, st, False, tried
+        key = st if np.isfinite(st) else np.inf
+        if best is None or key < best[2]:
+            best = (P, st, key)
+        if d_step <= 0 or kk - d_step < max(d_min, 1):
+            break
+        kk -= d_step
+    return best[0], best[1], True, tried

@@ -26,6 +26,10 @@ class SetupInfo(ctypes.Structure):
                 ("mvps", c_int64), ("dots", c_int64), ("t_setup_s", c_double)]
 
 
+class StchOpts(ctypes.Structure):
+    _fields_ = [("b", c_void_p), ("tol", c_double), ("d_step", c_int), ("d_min", c_int)]
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [("m", c_int), ("max_cycles", c_int), ("tol", c_double), ("inner", c_int),
                 ("stall_cycles", c_int), ("inner_eta", c_double), ("history", P_double), ("history_cap", c_int)]
@@ -51,6 +55,8 @@ SIGNATURES = {
     "pp_adjoint_values": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pp_gmres_setup": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p),
                                ctypes.POINTER(SetupInfo)]),
+    "pp_gmres_setup_checked": (c_int, [c_void_p, c_void_p, c_int, c_int, ctypes.POINTER(StchOpts), c_void_p,
+                                       ctypes.POINTER(c_void_p), ctypes.POINTER(SetupInfo), P_double]),
     "pp_poly_from_roots": (c_int, [c_int, P_double, P_double, c_int, ctypes.POINTER(c_void_p)]),
     "pp_poly_roots": (c_int, [c_void_p, c_int, c_int, P_double, P_double, P_int, P_int, P_int]),
     "pp_poly_destroy": (None, [c_void_p]),

@@ -13,7 +13,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from ._lib import SetupInfo, SolveInfo, SolveOpts, check, lib, PP_BREAKDOWN, PP_NOCONV, STATUS_NAMES
+from ._lib import SetupInfo, SolveInfo, SolveOpts, StchOpts, check, lib, PP_BREAKDOWN, PP_NOCONV, PP_UNSTABLE, STATUS_NAMES
 
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 DTYPE_OF_PREC = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}
@@ -145,6 +145,8 @@ class Poly:
     n_added: int
     breakdown: bool = False
     setup_info: dict | None = None
+    stch: float | None = None  # stability check value (setup_checked only)
+    unstable: bool = False     # setup_checked: no degree tried passed the check
 
     def roots(self, which: str = "final") -> np.ndarray:
         """Root list: "final" (applied order, with added roots), "theta" (raw
@@ -200,6 +202,30 @@ def setup(A: Matrix, v0, d: int, add_roots: bool = True) -> Poly:
                                   ctypes.byref(h), ctypes.byref(info)), "pp_gmres_setup")
     si = {k: getattr(info, k) for k, _ in SetupInfo._fields_}
     return _poly_from_handle(h, si, breakdown=(st == PP_BREAKDOWN) or bool(info.breakdown))
+
+
+def setup_checked(A: Matrix, v0, d: int, b, tol: float = 1e-8, d_step: int = 0, d_min: int = 1,
+                  add_roots: bool = True) -> Poly:
+    """Setup followed by the stability check of section 3.5, the degree lowered
+    by d_step (down to d_min) while StCh > tol ||b||. The returned Poly has
+    .stch and .unstable (True when no degree tried passed; it is then the one
+    with the smallest StCh)."""
+    v0 = _dev_tensor(v0, torch.float64, A.device)
+    b = _dev_tensor(b, torch.float64, A.device)
+    if v0.numel() != A.n or b.numel() != A.n:
+        raise ValueError("vector length")
+    h = ctypes.c_void_p()
+    info = SetupInfo()
+    opts = StchOpts(_ptr(b), float(tol), int(d_step), int(d_min))
+    sc = ctypes.c_double()
+    st = check(lib.pp_gmres_setup_checked(A.handle, _ptr(v0), int(d), int(bool(add_roots)), ctypes.byref(opts),
+                                          _stream(A.device), ctypes.byref(h), ctypes.byref(info), ctypes.byref(sc)),
+               "pp_gmres_setup_checked")
+    si = {k: getattr(info, k) for k, _ in SetupInfo._fields_}
+    poly = _poly_from_handle(h, si, breakdown=(st == PP_BREAKDOWN) or bool(info.breakdown))
+    poly.stch = sc.value
+    poly.unstable = st == PP_UNSTABLE
+    return poly
 
 
 def poly_from_roots(roots, add_roots: bool = False, keep_order: bool = False) -> Poly:

@@ -798,14 +798,16 @@ pp_status pp_adjoint_values(pp_matrix A, const double *lam, const double *x, dou
     return PP_OK;
 }
 
-pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, void *stream, pp_poly *out,
-                         pp_setup_info *info) {
-    if (!A || !v0 || !out || d < 1 || d > A->n || d > kMaxDegree) {
-        set_error("pp_gmres_setup: bad argument (need 1 <= d <= min(n, 4096))");
-        return PP_EINVAL;
-    }
-    hipStream_t st = S(stream);
-    const double t0 = now_s();
+}  // extern "C"
+
+namespace {
+
+// One GMRES(d) cycle on A from v0 in FP64 with CGS2 (Algorithm 4 step 1a).
+// Hbar receives the (d+1) x d Hessenberg matrix (column-major, leading
+// dimension d+1), k the Krylov dimension reached (k < d after a breakdown)
+// and dots the inner products and norms used.
+pp_status setup_arnoldi(pp_matrix A, const double *v0, int d, hipStream_t st, std::vector<double> &Hbar, int &k,
+                        bool &brk, int64_t &dots, const char *who) {
     PP_TRY(A->ensure_ws(0, d));
     PP_TRY(A->ensure_red(d + 1));
     const Workspace &ws = A->ws[0];
@@ -819,7 +821,7 @@ pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, vo
     HIP_TRY(hipMemcpyAsync(A->hpin, A->H(), sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (!(A->hpin[0] > 0.0) || !std::isfinite(A->hpin[0])) {
-        set_error("pp_gmres_setup: start vector is zero or not finite");
+        set_error(std::string(who) + ": start vector is zero or not finite");
         return PP_EINVAL;
     }
     // All d Arnoldi steps are queued without a host round trip: the
@@ -837,21 +839,21 @@ pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, vo
         PP_TRY(spmv_axpby(A, 0, vcol(ws, 0, j), 1.0, nullptr, 0.0, vcol(ws, 0, j + 1), st));
         PP_TRY(cgs2_step(A, 0, ws, j, st, Hdev + (size_t)j * ld, false));
     }
-    std::vector<double> Hbar((size_t)ld * d, 0.0);
+    Hbar.assign((size_t)ld * d, 0.0);
     HIP_TRY(hipMemcpyAsync(Hbar.data(), Hdev, sizeof(double) * ld * d, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(A->errpin, A->err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     PP_TRY(check_barrier_flag(A));
-    int k = d;
-    bool brk = false;
+    k = d;
+    brk = false;
     double fro2 = 0.0;
-    int64_t dots = 1;
+    dots = 1;
     for (int j = 0; j < d; ++j) {
         dots += 2 * (j + 1) + 1;
         for (int i = 0; i <= j + 1; ++i) {
             const double h = Hbar[(size_t)i + (size_t)j * ld];
             if (!std::isfinite(h)) {
-                set_error("pp_gmres_setup: non-finite Hessenberg entry");
+                set_error(std::string(who) + ": non-finite Hessenberg entry");
                 return PP_EINVAL;
             }
             fro2 += h * h;
@@ -862,27 +864,58 @@ pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, vo
             break;
         }
     }
-    // repack to (k+1) x k
-    std::vector<double> hk((size_t)(k + 1) * k);
-    for (int j = 0; j < k; ++j)
-        for (int i = 0; i <= k; ++i) hk[(size_t)i + (size_t)j * (k + 1)] = Hbar[(size_t)i + (size_t)j * ld];
-    std::vector<double> re(k), im(k);
-    int hs = harmonic_ritz(k, hk.data(), brk, re.data(), im.data());
+    return PP_OK;
+}
+
+// The polynomial of degree kk from the leading (kk+1) x kk block of Hbar
+// (Algorithm 4 step 1b, then Algorithm 2): the first kk Arnoldi steps from
+// the same start vector are the GMRES(kk) cycle. at_break: the block ends
+// at a breakdown (roots are then eig(H_kk)).
+pp_status poly_from_hbar(const std::vector<double> &Hbar, int ld, int kk, bool at_break, bool add_roots,
+                         const char *who, pp_poly *out) {
+    std::vector<double> hk((size_t)(kk + 1) * kk);
+    for (int j = 0; j < kk; ++j)
+        for (int i = 0; i <= kk; ++i) hk[(size_t)i + (size_t)j * (kk + 1)] = Hbar[(size_t)i + (size_t)j * ld];
+    std::vector<double> re(kk), im(kk);
+    int hs = harmonic_ritz(kk, hk.data(), at_break, re.data(), im.data());
     if (hs != PP_OK) {
-        if (hs == PP_ESINGULAR) set_error("pp_gmres_setup: singular H_dd or zero harmonic Ritz value");
+        if (hs == PP_ESINGULAR) set_error(std::string(who) + ": singular H_dd or zero harmonic Ritz value");
         return (pp_status)hs;
     }
     auto *p = new (std::nothrow) pp_poly_s();
     if (!p) return PP_ENOMEM;
-    int ps = plan_roots(k, re.data(), im.data(), add_roots != 0, p->plan);
+    int ps = plan_roots(kk, re.data(), im.data(), add_roots, p->plan);
     if (ps != PP_OK) {
         delete p;
         return (pp_status)ps;
     }
     p->theta_re = re;
     p->theta_im = im;
-    p->breakdown = brk ? 1 : 0;
+    p->breakdown = at_break ? 1 : 0;
     p->finalize();
+    *out = p;
+    return PP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, void *stream, pp_poly *out,
+                         pp_setup_info *info) {
+    if (!A || !v0 || !out || d < 1 || d > A->n || d > kMaxDegree) {
+        set_error("pp_gmres_setup: bad argument (need 1 <= d <= min(n, 4096))");
+        return PP_EINVAL;
+    }
+    hipStream_t st = S(stream);
+    const double t0 = now_s();
+    std::vector<double> Hbar;
+    int k = 0;
+    bool brk = false;
+    int64_t dots = 0;
+    PP_TRY(setup_arnoldi(A, v0, d, st, Hbar, k, brk, dots, "pp_gmres_setup"));
+    pp_poly p = nullptr;
+    PP_TRY(poly_from_hbar(Hbar, d + 1, k, brk, add_roots != 0, "pp_gmres_setup", &p));
     *out = p;
     if (info) {
         info->d = k;
@@ -894,6 +927,79 @@ pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, vo
         info->t_setup_s = now_s() - t0;
     }
     return (brk && k < d) ? PP_BREAKDOWN : PP_OK;
+}
+
+pp_status pp_gmres_setup_checked(pp_matrix A, const double *v0, int d, int add_roots, const pp_stch_opts *opts,
+                                 void *stream, pp_poly *out, pp_setup_info *info, double *stch) {
+    if (!A || !v0 || !out || !opts || !opts->b || d < 1 || d > A->n || d > kMaxDegree || !(opts->tol >= 0.0) ||
+        opts->d_step < 0) {
+        set_error("pp_gmres_setup_checked: bad argument (need 1 <= d <= min(n, 4096), b, tol >= 0, d_step >= 0)");
+        return PP_EINVAL;
+    }
+    hipStream_t st = S(stream);
+    const double t0 = now_s();
+    std::vector<double> Hbar;
+    int k = 0;
+    bool brk = false;
+    int64_t dots = 0;
+    PP_TRY(setup_arnoldi(A, v0, d, st, Hbar, k, brk, dots, "pp_gmres_setup_checked"));
+    double bn = 0.0;
+    PP_TRY(dev_norm(A, 0, opts->b, &bn, st));
+    const double limit = opts->tol * bn;
+    const int d_min = std::max(opts->d_min, 1);
+    int64_t mvps = k;
+    pp_poly best = nullptr;
+    double best_st = 0.0, best_key = 0.0;
+    bool stable = false;
+    for (int kk = k;;) {
+        const bool at_break = brk && kk == k;
+        pp_poly p = nullptr;
+        pp_status s = poly_from_hbar(Hbar, d + 1, kk, at_break, add_roots != 0, "pp_gmres_setup_checked", &p);
+        if (s != PP_OK) {
+            if (best) pp_poly_destroy(best);
+            return s;
+        }
+        double sc = 0.0;
+        s = pp_stability_check(p, A, opts->b, stream, &sc);
+        if (s != PP_OK) {
+            pp_poly_destroy(p);
+            if (best) pp_poly_destroy(best);
+            return s;
+        }
+        mvps += 2L * p->plan.d_eff;  // p(A)b (d_eff - 1), A p(A)b (1), phi(A)b (d_eff)
+        dots += 1;
+        const double key = std::isfinite(sc) ? sc : INFINITY;
+        if (sc <= limit) {
+            if (best) pp_poly_destroy(best);
+            best = p;
+            best_st = sc;
+            stable = true;
+            break;
+        }
+        if (!best || key < best_key) {
+            if (best) pp_poly_destroy(best);
+            best = p;
+            best_st = sc;
+            best_key = key;
+        } else {
+            pp_poly_destroy(p);
+        }
+        if (opts->d_step <= 0 || kk - opts->d_step < d_min) break;
+        kk -= opts->d_step;
+    }
+    *out = best;
+    if (stch) *stch = best_st;
+    if (info) {
+        info->d = best->plan.d;
+        info->d_eff = best->plan.d_eff;
+        info->n_added = best->plan.n_added;
+        info->breakdown = best->breakdown;
+        info->mvps = mvps;
+        info->dots = dots;
+        info->t_setup_s = now_s() - t0;
+    }
+    if (!stable) return PP_UNSTABLE;
+    return (best->breakdown && k < d) ? PP_BREAKDOWN : PP_OK;
 }
 
 pp_status pp_apply(pp_poly p, pp_matrix A, int kind, int prec, const void *v, void *y, void *stream) {

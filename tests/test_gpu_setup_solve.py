@@ -71,6 +71,48 @@ def test_setup_breakdown(pp):
     assert np.allclose(np.sort(poly.roots().real), [1, 2, 5], rtol=1e-10)
 
 
+@pytest.mark.parametrize("case", ["clusters_no_added_roots", "wide_added_roots", "clusters_all_unstable"])
+def test_setup_checked_matches_oracle(pp, case):
+    # stability check in the setup (section 3.5) with the degree lowered by
+    # 10 from 40: the degree kept, the unstable flag and the roots follow
+    # the oracle; the StCh values at the decisions are orders of magnitude
+    # from the threshold, so rounding cannot flip them
+    from workloads import diag_clusters, diag_wide
+
+    csr = diag_wide() if case.startswith("wide") else diag_clusters()
+    add = case == "wide_added_roots"
+    tol = 0.0 if case.endswith("all_unstable") else 1e-8
+    A = csr.to_scipy()
+    b, v0 = rhs(csr.n, 1), start_vector(csr.n, 2)
+    say("setup checked", case)
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.setup_checked(M, dev(v0), 40, dev(b), tol=tol, d_step=10, d_min=10, add_roots=add)
+    P, st, unstable, tried = osolver.setup_checked(A, v0, 40, b, tol, d_step=10, d_min=10, add_roots=add,
+                                                   orth="cgs2")
+    assert poly.d == P.d and poly.unstable == unstable
+    theta = poly.roots("theta")
+    assert _multiset_relerr(theta, P.theta) < 1e-8
+    leja, pof, n_add, units = oroots.order_and_add(theta, add)
+    assert np.array_equal(poly.roots("final"), oroots.Poly(poly.d, theta, leja, pof, n_add, units).roots())
+    # StCh of the kept polynomial: rounding-level on both sides
+    st_or = osolver.stability_check(A, units, b)
+    assert poly.stch <= 1e-12 and st_or <= 1e-12
+    assert poly.setup_info["mvps"] == 40 + sum(2 * (oroots.setup(A, v0, k, add_roots=add, orth="cgs2").d_eff)
+                                               for k, _ in tried)
+
+
+def test_setup_checked_errors(pp):
+    csr = convdiff2d(8)
+    M = pp.Matrix.from_csr(csr)
+    v0, b = dev(start_vector(csr.n, 2)), dev(rhs(csr.n, 1))
+    with pytest.raises(Exception):
+        pp.setup_checked(M, v0, 4, b, tol=-1.0)
+    with pytest.raises(Exception):
+        pp.setup_checked(M, v0, 4, b, d_step=-1)
+    poly = pp.setup_checked(M, v0, 4, b, tol=1.0)  # stable at once: no lowering
+    assert poly.d == 4 and not poly.unstable and poly.stch <= 1.0
+
+
 def test_setup_errors(pp):
     csr = convdiff2d(8)
     M = pp.Matrix.from_csr(csr)

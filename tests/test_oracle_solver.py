@@ -151,3 +151,63 @@ def test_adjoint_gradient_vs_finite_differences():
     xm = sla.spsolve(A.tocsc(), b - h * e)
     fdb = (0.5 * np.sum((xp - xt) ** 2) - 0.5 * np.sum((xm - xt) ** 2)) / (2 * h)
     assert abs(lam[5] - fdb) <= 1e-6 * abs(fdb)
+
+
+# ---------------------------------------------------------------------------
+# stability check inside the setup, degree lowering (section 3.5)
+# ---------------------------------------------------------------------------
+
+def _clusters_problem():
+    from workloads import diag_clusters
+
+    A = diag_clusters().to_scipy()
+    n = A.shape[0]
+    return A, rhs(n, 1), start_vector(n, 2)
+
+
+def test_leading_hessenberg_block_is_the_lower_degree_cycle():
+    # the reading behind degree lowering: the first k Arnoldi steps from v0
+    # are the GMRES(k) cycle, so the leading (k+1) x k block of one GMRES(30)
+    # run gives the roots of a separate GMRES(k) setup
+    A, b, v0 = _clusters_problem()
+    _, Hbar, k, brk = roots.arnoldi(lambda v: A @ v, v0, 30, "cgs2")
+    assert k == 30 and not brk
+    for kk in (5, 10, 20):
+        lead = np.sort_complex(roots.harmonic_ritz(Hbar[: kk + 1, :kk]))
+        fresh = np.sort_complex(roots.setup(A, v0, kk, add_roots=False, orth="cgs2").theta)
+        assert np.max(np.abs(lead - fresh)) <= 1e-12 * np.max(np.abs(fresh))
+
+
+@pytest.mark.parametrize("case", ["clusters_no_added_roots", "wide_added_roots"])
+def test_setup_checked_keeps_the_first_stable_degree(case):
+    # brute force: StCh of a fresh setup at every degree tried; the kept
+    # degree is the first whose StCh passes, every earlier one fails
+    from workloads import diag_wide
+
+    if case == "clusters_no_added_roots":
+        A, b, v0 = _clusters_problem()
+        add, want = False, 10
+    else:
+        A = diag_wide().to_scipy()
+        b, v0 = rhs(A.shape[0], 1), start_vector(A.shape[0], 2)
+        add, want = True, 20
+    P, st, unstable, tried = solver.setup_checked(A, v0, 40, b, 1e-8, d_step=10, d_min=10, add_roots=add,
+                                                  orth="cgs2")
+    assert not unstable and P.d == want and st <= 1e-8
+    assert [k for k, _ in tried] == list(range(40, want - 1, -10))
+    for k, _ in tried:
+        Pk = roots.setup(A, v0, k, add_roots=add, orth="cgs2")
+        sk = solver.stability_check(A, Pk.units, b)
+        assert (sk <= 1e-8) == (k == want), (k, sk)
+
+
+def test_setup_checked_flags_unstable_and_keeps_smallest_stch():
+    A, b, v0 = _clusters_problem()
+    P, st, unstable, tried = solver.setup_checked(A, v0, 40, b, 0.0, d_step=10, d_min=10, add_roots=False,
+                                                  orth="cgs2")
+    assert unstable
+    vals = {k: (s if np.isfinite(s) else np.inf) for k, s in tried}
+    assert P.d == min(vals, key=vals.get) == 10 and st == vals[10]
+    # no lowering: only d is tried
+    P1, st1, unstable1, tried1 = solver.setup_checked(A, v0, 20, b, 1e-8, d_step=0, add_roots=False, orth="cgs2")
+    assert [k for k, _ in tried1] == [20] and unstable1 and P1.d == 20 and st1 > 1.0

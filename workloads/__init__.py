@@ -14,6 +14,8 @@ from .generators import (  # noqa: F401
     diagonal,
     diag_example7,
     diag_squares,
+    diag_clusters,
+    diag_wide,
     normal_vector,
     rhs,
     start_vector,

@@ -184,6 +184,19 @@ def diag_squares(n: int) -> CSR:
     return diagonal(i * i / n)
 
 
+def diag_clusters() -> CSR:
+    """Eigenvalues in bunches well separated from the rest (the situation the
+    stability discussion of section 3 describes): 1000 values evenly in
+    [1, 2], then 300, 300.3, 300.6, 700, 701 and 1500; n = 1006."""
+    return diagonal(np.concatenate([np.linspace(1.0, 2.0, 1000), [300.0, 300.3, 300.6, 700.0, 701.0, 1500.0]]))
+
+
+def diag_wide() -> CSR:
+    """A wide positive spectrum: 1000 values evenly in [0.01, 1], then 20
+    values geometrically from 10 to 1e5; n = 1020."""
+    return diagonal(np.concatenate([np.linspace(0.01, 1.0, 1000), np.geomspace(10.0, 1e5, 20)]))
+
+
 def normal_vector(n: int, seed: int, count: int | None = None) -> np.ndarray:
     """N(0,1) draws of length n (or shape (count, n))."""
     rng = np.random.default_rng(seed)
