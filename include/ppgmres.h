@@ -141,6 +141,24 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap);
  * microseconds (0 if the variant was forced). */
 pp_status pp_matrix_variant(pp_matrix A, int prec, int *variant, int *remap, double *us_per_launch);
 
+/* Composition with a diagonal right preconditioner M^{-1} = diag(s)
+ * (eqs. (1.3)-(1.4), section 1): from now on the handle's operator is
+ * A diag(s). Its chains, pp_gmres_setup (the polynomial is built for
+ * A M^{-1}, section 3.1) and pp_apply use the scaled values, and pp_solve
+ * solves phi(A M^{-1}) y = b and returns x = diag(s) p(A M^{-1}) y (the
+ * solution of A x = b; residuals are those of A x = b).
+ *   s : device double[n] (copied), or NULL for Jacobi, s_i = 1 / a_ii of the
+ *       current values (recomputed by every pp_matrix_set_values).
+ * The handle then owns a scaled copy of the values; the caller's values
+ * stay borrowed and unchanged. Returns PP_ESINGULAR (Jacobi) if a row has no
+ * stored diagonal or a zero one; on any error the handle reverts to the
+ * unscaled matrix. */
+pp_status pp_matrix_right_scale(pp_matrix A, const double *s, void *stream);
+
+/* Copy the right scaling s of a scaled handle into s (device double[n]);
+ * PP_EINVAL if the handle has none. */
+pp_status pp_matrix_scale(pp_matrix A, double *s, void *stream);
+
 /* Name of a chain-step variant ("tile8x1", "vec8x4", ...). */
 const char *pp_chain_variant_name(int variant);
 

@@ -204,3 +204,27 @@ def setup_checked(A, v0: np.ndarray, d: int, b: np.ndarray, tol: float, d_step: 
             break
         kk -= d_step
     return best[0], best[1], True, tried
+
+
+def right_scaled(A, s=None):
+    """The operator A M^{-1} for a diagonal right preconditioner M^{-1} =
+    diag(s) (eqs. (1.3)-(1.4)); s=None is Jacobi, s_i = 1 / a_ii.
+
+    The polynomial is then built on A M^{-1} (section 3.1: use A M^{-1} for
+    the initial GMRES run and the harmonic Ritz values), GMRES solves
+    phi(A M^{-1}) y = b, and x = M^{-1} p(A M^{-1}) y = s * x~ where x~ solves
+    (A M^{-1}) x~ = b. Entry (i, j) of A M^{-1} is a_ij s_j, one rounding.
+    Returns (A M^{-1} as scipy CSR, s). Raises ValueError for Jacobi when a
+    diagonal entry is zero or missing.
+    """
+    import scipy.sparse as sp
+
+    A = sp.csr_matrix(A)
+    if s is None:
+        diag = A.diagonal()
+        if np.any(diag == 0.0):
+            raise ValueError("zero or missing diagonal entry")
+        s = 1.0 / diag
+    s = np.asarray(s, dtype=np.float64)
+    AS = sp.csr_matrix((A.data * s[A.indices], A.indices.copy(), A.indptr.copy()), shape=A.shape)
+    return AS, s

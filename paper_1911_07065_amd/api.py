@@ -13,7 +13,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from ._lib import SetupInfo, SolveInfo, SolveOpts, StchOpts, check, lib, PP_BREAKDOWN, PP_NOCONV, PP_UNSTABLE, STATUS_NAMES
+from ._lib import PPError, SetupInfo, SolveInfo, SolveOpts, StchOpts, check, lib, PP_BREAKDOWN, PP_NOCONV, PP_UNSTABLE, STATUS_NAMES
 
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 DTYPE_OF_PREC = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}
@@ -65,6 +65,7 @@ class Matrix:
                                    _stream(self.device), ctypes.byref(h)), "pp_matrix_create")
         self.handle = h
         self._t = None
+        self.scaling = None  # right scaling: None, "jacobi" or "custom"
 
     @classmethod
     def from_csr(cls, csr, device="cuda"):
@@ -75,9 +76,37 @@ class Matrix:
         val = _dev_tensor(val, torch.float64, self.device)
         if val.numel() != self.nnz:
             raise ValueError("value count does not match the pattern")
-        check(lib.pp_matrix_set_values(self.handle, _ptr(val), _stream(self.device)), "pp_matrix_set_values")
         self.val = val
         self._t = None
+        try:
+            check(lib.pp_matrix_set_values(self.handle, _ptr(val), _stream(self.device)), "pp_matrix_set_values")
+        except PPError:
+            self.scaling = None  # a failed Jacobi scaling leaves the handle unscaled
+            raise
+
+    def right_scale(self, s=None):
+        """Compose with the diagonal right preconditioner M^{-1} = diag(s) (eqs.
+        1.3-1.4): the operator becomes A diag(s), polynomials built on this
+        Matrix are polynomials in A M^{-1}, and solve() returns the solution of
+        A x = b. s=None is Jacobi (s_i = 1/a_ii, recomputed by set_values)."""
+        if s is not None:
+            s = _dev_tensor(s, torch.float64, self.device)
+            if s.numel() != self.n:
+                raise ValueError("scaling length")
+        self._t = None
+        try:
+            check(lib.pp_matrix_right_scale(self.handle, _ptr(s) if s is not None else None, _stream(self.device)),
+                  "pp_matrix_right_scale")
+        except PPError:
+            self.scaling = None  # the handle reverts to the unscaled matrix
+            raise
+        self.scaling = "jacobi" if s is None else "custom"
+
+    def scale(self) -> torch.Tensor:
+        """The right scaling s of a scaled Matrix."""
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        check(lib.pp_matrix_scale(self.handle, _ptr(out), _stream(self.device)), "pp_matrix_scale")
+        return out
 
     def tune(self, prec: str = "fp32"):
         """Autotune the chain kernel for one precision; returns (variant name, remap, us per launch)."""
@@ -114,6 +143,8 @@ class Matrix:
         check(lib.pp_gather(self.nnz, _ptr(self.val), _ptr(pm), _ptr(vt), _stream(self.device)), "pp_gather")
         At = Matrix(rp, ci, vt, device=self.device)
         At.perm = pm
+        if getattr(self, "scaling", None) == "jacobi":
+            At.right_scale(None)  # diag(A^T) = diag(A)
         return At
 
     def adjoint_values(self, lam: torch.Tensor, x: torch.Tensor) -> torch.Tensor:

@@ -51,6 +51,13 @@ struct pp_matrix_s {
     // sliced-ELL copy
     int32_t *sptr = nullptr, *scol = nullptr, *sperm = nullptr;
     int16_t *sdel = nullptr;
+    // right scaling A diag(s) (composition with a diagonal preconditioner):
+    // the chains, the setup and the residual use the scaled values val_own;
+    // pp_solve returns x = diag(s) x~
+    int scale_mode = 0;                // 0 none, 1 Jacobi (s = 1/diag of the values), 2 the caller's s
+    const double *user_val = nullptr;  // the caller's unscaled values
+    double *val_own = nullptr;         // scaled values (nnz)
+    double *scale = nullptr;           // s (n)
     double *sval64 = nullptr;
     float *sval32 = nullptr;
     int nslices = 0;
@@ -179,6 +186,8 @@ struct pp_matrix_s {
         dev_free(scol);
         dev_free(sperm);
         dev_free(sdel);
+        dev_free(val_own);
+        dev_free(scale);
         dev_free(sval64);
         dev_free(sval32);
         for (int p = 0; p < 3; ++p) {
@@ -683,14 +692,102 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
     return PP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Point the handle at new FP64 values and refresh the copies derived from them.
+pp_status refresh_values(pp_matrix A, const double *val, hipStream_t st) {
+    A->val = val;
+    HIP_TRY(launch_val_to_f32(A->nnz, val, A->val32, st));
+    if (A->nslices > 0) HIP_TRY(launch_sell_values(A->npad, A->sperm, val, A->sval64, A->sval32, st));
+    return PP_OK;
+}
+
+// Values of A diag(s) from the caller's values (Jacobi: s from their diagonal).
+pp_status apply_scaling(pp_matrix A, hipStream_t st, const char *who) {
+    if (A->scale_mode == 1) {
+        int *bad = nullptr;
+        PP_TRY(dev_alloc(&bad, 1));
+        struct Free {
+            int *p;
+            ~Free() { dev_free(p); }
+        } fb{bad};
+        int hbad = 0;
+        HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), st));
+        HIP_TRY(launch_jacobi(A->n, A->rowptr, A->colind, A->user_val, A->scale, bad, st));
+        HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (hbad) {
+            set_error(std::string(who) + ": a diagonal entry is missing or zero (Jacobi scaling)");
+            return PP_ESINGULAR;
+        }
+    }
+    HIP_TRY(launch_scale_cols(A->nnz, A->colind, A->user_val, A->scale, A->val_own, st));
+    return refresh_values(A, A->val_own, st);
+}
+
+// Back to the caller's unscaled values (after a failed scaling).
+void drop_scaling(pp_matrix A, hipStream_t st) {
+    A->scale_mode = 0;
+    (void)refresh_values(A, A->user_val, st);
+    (void)hipStreamSynchronize(st);
+    dev_free(A->val_own);
+    dev_free(A->scale);
+    A->val_own = nullptr;
+    A->scale = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
 pp_status pp_matrix_set_values(pp_matrix A, const double *val, void *stream) {
     if (!A || (!val && A->nnz > 0)) {
         set_error("pp_matrix_set_values: bad argument");
         return PP_EINVAL;
     }
-    A->val = val;
-    HIP_TRY(launch_val_to_f32(A->nnz, val, A->val32, S(stream)));
-    if (A->nslices > 0) HIP_TRY(launch_sell_values(A->npad, A->sperm, val, A->sval64, A->sval32, S(stream)));
+    if (A->scale_mode != 0) {
+        A->user_val = val;
+        const pp_status r = apply_scaling(A, S(stream), "pp_matrix_set_values");
+        if (r != PP_OK) drop_scaling(A, S(stream));
+        return r;
+    }
+    return refresh_values(A, val, S(stream));
+}
+
+pp_status pp_matrix_right_scale(pp_matrix A, const double *s, void *stream) {
+    if (!A || A->nnz == 0) {
+        set_error("pp_matrix_right_scale: bad argument");
+        return PP_EINVAL;
+    }
+    hipStream_t st = S(stream);
+    if (A->scale_mode == 0) {
+        A->user_val = A->val;
+        PP_TRY(dev_alloc(&A->val_own, (size_t)A->nnz));
+        PP_TRY(dev_alloc(&A->scale, (size_t)A->n));
+    }
+    if (s) {
+        HIP_TRY(hipMemcpyAsync(A->scale, s, sizeof(double) * A->n, hipMemcpyDeviceToDevice, st));
+        A->scale_mode = 2;
+    } else {
+        A->scale_mode = 1;
+    }
+    const pp_status r = apply_scaling(A, st, "pp_matrix_right_scale");
+    if (r != PP_OK) drop_scaling(A, st);
+    return r;
+}
+
+pp_status pp_matrix_scale(pp_matrix A, double *s, void *stream) {
+    if (!A || !s) {
+        set_error("pp_matrix_scale: bad argument");
+        return PP_EINVAL;
+    }
+    if (A->scale_mode == 0) {
+        set_error("pp_matrix_scale: the matrix has no right scaling");
+        return PP_EINVAL;
+    }
+    HIP_TRY(hipMemcpyAsync(s, A->scale, sizeof(double) * A->n, hipMemcpyDeviceToDevice, S(stream)));
     return PP_OK;
 }
 
@@ -1156,6 +1253,8 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
         if (prec != PP_F64 && !(beta_new <= 0.5 * beta)) prec = PP_F64;  // refinement stalls: finish in FP64
         beta = beta_new;
     }
+    // composition with a right preconditioner: x = diag(s) x~ (eq. (1.4))
+    if (A->scale_mode != 0) HIP_TRY(launch_vmul(n, x, A->scale, st));
     inf.status = status;
     inf.t_solve_s = now_s() - t0;
     if (info) *info = inf;

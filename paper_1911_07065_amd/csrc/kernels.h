@@ -153,6 +153,14 @@ hipError_t launch_combine(int prec, int n, const void *V, long ldv, int k, const
 hipError_t launch_axpy_x(int prec, int n, double beta, const void *d, double *x, hipStream_t st);
 // x[i] = value (double)
 hipError_t launch_fill(int n, double value, double *x, hipStream_t st);
+// s[i] = 1/a_ii (0 and *bad = 1 where the diagonal is missing or zero)
+hipError_t launch_jacobi(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double *s, int *bad,
+                         hipStream_t st);
+// out[k] = val[k] * s[colind[k]]
+hipError_t launch_scale_cols(int nnz, const int32_t *colind, const double *val, const double *s, double *out,
+                             hipStream_t st);
+// x[i] *= s[i]
+hipError_t launch_vmul(int n, double *x, const double *s, hipStream_t st);
 // copy with conversion
 hipError_t launch_convert(int prec_in, int prec_out, int n, const void *in, void *out, hipStream_t st);
 // val32[k] = (float) val64[k]

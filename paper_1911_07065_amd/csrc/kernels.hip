@@ -963,6 +963,32 @@ __global__ __launch_bounds__(256) void k_fill(int n, double value, double *x) {
     if (i < n) x[i] = value;
 }
 
+// s[i] = 1 / a_ii (right Jacobi scaling); a row without a stored diagonal
+// or with a_ii = 0 gets s[i] = 0 and sets *bad.
+__global__ __launch_bounds__(256) void k_jacobi(int n, const int32_t *rowptr, const int32_t *colind,
+                                                const double *val, double *s, int *bad) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double a = 0.0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e)
+        if (colind[e] == i) a = val[e];
+    s[i] = a != 0.0 ? 1.0 / a : 0.0;
+    if (a == 0.0) *bad = 1;
+}
+
+// out[k] = val[k] * s[colind[k]]: the values of A diag(s)
+__global__ __launch_bounds__(256) void k_scale_cols(int nnz, const int32_t *colind, const double *val,
+                                                    const double *s, double *out) {
+    const long k = (long)blockIdx.x * 256 + threadIdx.x;
+    if (k < nnz) out[k] = val[k] * s[colind[k]];
+}
+
+// x[i] *= s[i]
+__global__ __launch_bounds__(256) void k_vmul(int n, double *x, const double *s) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] *= s[i];
+}
+
 __global__ __launch_bounds__(256) void k_val_to_f32(int nnz, const double *v, float *o) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i < nnz) o[i] = (float)v[i];
@@ -1184,6 +1210,29 @@ hipError_t launch_fill(int n, double value, double *x, hipStream_t st) {
     const unsigned g = blocks_for(n, 256);
     if (g == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3(g), dim3(256), 0, st, n, value, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double *s, int *bad,
+                         hipStream_t st) {
+    const unsigned g = blocks_for(n, 256);
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(256), 0, st, n, rowptr, colind, val, s, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_cols(int nnz, const int32_t *colind, const double *val, const double *s, double *out,
+                             hipStream_t st) {
+    const unsigned g = blocks_for(nnz, 256);
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_cols, dim3(g), dim3(256), 0, st, nnz, colind, val, s, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_vmul(int n, double *x, const double *s, hipStream_t st) {
+    const unsigned g = blocks_for(n, 256);
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vmul, dim3(g), dim3(256), 0, st, n, x, s);
     return hipGetLastError();
 }
 

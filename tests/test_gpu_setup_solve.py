@@ -199,3 +199,105 @@ def test_cfg3_full_size_solve(pp, inner):
     rel = np.linalg.norm(b - A @ host(x)) / np.linalg.norm(b)
     say("cfg3 solve done", inner, info)
     assert info["status"] == 0 and rel <= 1e-8
+
+
+# ---------------------------------------------------------------------------
+# composition with a diagonal right preconditioner (eqs. 1.3-1.4)
+# ---------------------------------------------------------------------------
+
+def test_jacobi_operator_and_scale(pp):
+    from workloads import convdiff2d_colscaled
+
+    csr = convdiff2d_colscaled(40, 5.0, 3.0)
+    A = csr.to_scipy()
+    say("jacobi operator")
+    M = pp.Matrix.from_csr(csr)
+    M.right_scale()
+    AS, s = osolver.right_scaled(A)
+    assert np.array_equal(host(M.scale()), s)  # 1/a_ii, one rounding on both sides
+    v = rhs(csr.n, 7)
+    ident = pp.poly_from_roots([1.0])  # phi(z) = z: one product with the operator
+    y = host(pp.apply(ident, M, dev(v), "phi"))
+    assert relerr(y, AS @ v) <= 1e-14
+    # new values: the scaling follows their diagonal
+    M.set_values(dev(2.0 * csr.val))
+    assert np.array_equal(host(M.scale()), 1.0 / (2.0 * A.diagonal()))
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_jacobi_composed_solve_matches_oracle(pp, inner):
+    from workloads import convdiff2d_colscaled
+
+    csr = convdiff2d_colscaled(50, 1.0, 3.0)
+    A = csr.to_scipy()
+    b, v0 = rhs(csr.n, 1), start_vector(csr.n, 2)
+    say("jacobi solve", inner)
+    M = pp.Matrix.from_csr(csr)
+    M.right_scale()
+    poly = pp.setup(M, dev(v0), 10)
+    AS, s = osolver.right_scaled(A)
+    P = oroots.setup(AS, v0, 10, orth="cgs2")
+    theta = poly.roots("theta")
+    assert _multiset_relerr(theta, P.theta) < 1e-8
+    x, info = pp.solve(poly, M, dev(b), tol=1e-8, m=50, inner=inner)
+    xh = host(x)
+    assert info["converged"] and info["cycles"] <= 3
+    assert np.linalg.norm(b - A @ xh) <= 1e-8 * np.linalg.norm(b)
+    xt, _ = osolver.pp_gmres(AS, b, P.units, m=50, tol=1e-8)
+    assert relerr(xh, s * xt) <= 2e-5
+    # without the composition the same polynomial degree does not converge
+    M0 = pp.Matrix.from_csr(csr)
+    x0, info0 = pp.solve(pp.setup(M0, dev(v0), 10), M0, dev(b), tol=1e-8, m=50, max_cycles=30, inner=inner)
+    assert not info0["converged"]
+
+
+def test_custom_right_scaling_and_errors(pp):
+    csr = convdiff2d(20, 10.0)
+    A = csr.to_scipy()
+    b, v0 = rhs(csr.n, 1), start_vector(csr.n, 2)
+    s = 10.0 ** np.random.default_rng(4).uniform(-1, 1, csr.n)
+    say("custom right scaling")
+    M = pp.Matrix.from_csr(csr)
+    M.right_scale(dev(s))
+    assert np.array_equal(host(M.scale()), s)
+    x, info = pp.solve(pp.setup(M, dev(v0), 8), M, dev(b), tol=1e-10, m=50, inner="fp64")
+    assert info["converged"] and np.linalg.norm(b - A @ host(x)) <= 1e-10 * np.linalg.norm(b)
+    # a zero diagonal: Jacobi fails and the handle stays unscaled
+    vals = csr.val.copy()
+    rows = np.repeat(np.arange(csr.n), np.diff(csr.rowptr))
+    vals[np.flatnonzero(rows == csr.colind)[3]] = 0.0
+    Mz = pp.Matrix.from_csr(csr.with_values(vals))
+    with pytest.raises(Exception):
+        Mz.right_scale()
+    assert Mz.scaling is None
+    with pytest.raises(Exception):
+        Mz.scale()
+    ident = pp.poly_from_roots([1.0])
+    v = rhs(csr.n, 7)
+    assert relerr(host(pp.apply(ident, Mz, dev(v), "phi")), csr.with_values(vals).to_scipy() @ v) <= 1e-14
+
+
+def test_jacobi_composed_gradient(pp):
+    # the adjoint of a Jacobi-composed solve: the transposed handle gets the
+    # same diagonal scaling; the gradient is that of A x = b
+    from oracle.adjoint import grad_direct
+    from workloads import convdiff2d_parts
+
+    A0, dval = convdiff2d_parts(32)
+    theta0 = 15.0
+    n = A0.n
+    b = rhs(n, 1)
+    xt = np.random.default_rng(3).standard_normal(n)
+    say("jacobi gradient")
+    M = pp.Matrix.from_csr(A0)
+    base, dirv = dev(A0.val), dev(dval)
+    M.set_values(base + theta0 * dirv)
+    M.right_scale()
+    poly = pp.setup(M, dev(start_vector(n, 2)), 20)
+    th = torch.tensor(theta0, dtype=torch.float64, device="cuda", requires_grad=True)
+    x = pp.pp_solve_fn(base + th * dirv, dev(b), M, poly, tol=1e-12, m=50, inner="fp64")
+    (0.5 * torch.sum((x - dev(xt)) ** 2)).backward()
+    A = A0.with_values(A0.val + theta0 * dval).to_scipy()
+    _, _, dv = grad_direct(A, b, lambda z: z - xt)
+    g_or = float(dv @ dval)
+    assert abs(float(th.grad) - g_or) <= 1e-6 * abs(g_or)

@@ -211,3 +211,54 @@ def test_setup_checked_flags_unstable_and_keeps_smallest_stch():
     # no lowering: only d is tried
     P1, st1, unstable1, tried1 = solver.setup_checked(A, v0, 20, b, 1e-8, d_step=0, add_roots=False, orth="cgs2")
     assert [k for k, _ in tried1] == [20] and unstable1 and P1.d == 20 and st1 > 1.0
+
+
+# ---------------------------------------------------------------------------
+# composition with a diagonal right preconditioner (eqs. 1.3-1.4)
+# ---------------------------------------------------------------------------
+
+def test_jacobi_scaled_operator_closed_forms():
+    from workloads import convdiff2d_colscaled
+
+    A0 = convdiff2d(30, 5.0).to_scipy()
+    A = convdiff2d_colscaled(30, 5.0, 3.0).to_scipy()
+    AS, s = solver.right_scaled(A)
+    # unit diagonal, and the column scaling cancels: A0 S (D0 S)^{-1} = A0 D0^{-1}
+    assert np.max(np.abs(AS.diagonal() - 1.0)) <= 2.0 ** -52
+    AS0, _ = solver.right_scaled(A0)
+    d = (AS - AS0).tocsr()
+    assert np.max(np.abs(d.data)) <= 4 * np.finfo(float).eps * np.max(np.abs(AS0.data))
+    with pytest.raises(ValueError):
+        solver.right_scaled(diagonal(np.array([1.0, 0.0, 2.0])).to_scipy())
+
+
+def test_jacobi_composition_solves_badly_scaled_system():
+    # x = M^{-1} p(A M^{-1}) y solves A x = b; the composition removes the
+    # column scaling that stops the plain polynomial preconditioned solve
+    from workloads import convdiff2d_colscaled
+
+    A = convdiff2d_colscaled(50, 1.0, 3.0).to_scipy()
+    n = A.shape[0]
+    b, v0 = rhs(n, 1), start_vector(n, 2)
+    AS, s = solver.right_scaled(A)
+    PJ = roots.setup(AS, v0, 10, orth="cgs2")
+    xt, infj = solver.pp_gmres(AS, b, PJ.units, m=50, tol=1e-8, max_cycles=50)
+    x = s * xt
+    assert infj.status == solver.OK and infj.cycles <= 2
+    assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
+    assert np.linalg.norm(x - sla.spsolve(A.tocsc(), b)) <= 1e-5 * np.linalg.norm(x)
+    P = roots.setup(A, v0, 10, orth="cgs2")
+    _, inf = solver.pp_gmres(A, b, P.units, m=50, tol=1e-8, max_cycles=30)
+    assert inf.status == solver.NOCONV
+
+
+def test_custom_right_scaling_solves():
+    A = convdiff2d(20, 10.0).to_scipy()
+    n = A.shape[0]
+    b, v0 = rhs(n, 1), start_vector(n, 2)
+    s = 10.0 ** np.random.default_rng(4).uniform(-1, 1, n)
+    AS, s2 = solver.right_scaled(A, s)
+    assert np.array_equal(s2, s)
+    P = roots.setup(AS, v0, 8, orth="cgs2")
+    xt, inf = solver.pp_gmres(AS, b, P.units, m=50, tol=1e-10, max_cycles=50)
+    assert np.linalg.norm(b - A @ (s * xt)) <= 1e-10 * np.linalg.norm(b)

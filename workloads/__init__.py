@@ -9,6 +9,7 @@ from .generators import (  # noqa: F401
     CSR,
     convdiff2d,
     convdiff2d_parts,
+    convdiff2d_colscaled,
     convdiff3d,
     randsparse,
     diagonal,

@@ -125,6 +125,16 @@ def convdiff2d_parts(N: int, beta: float = 0.0, gamma: float = 0.0):
     return CSR(N * N, rowptr, colind, val), dval
 
 
+def convdiff2d_colscaled(N: int, alpha: float = 0.0, decades: float = 3.0, seed: int = 9) -> CSR:
+    """The 2-D convection-diffusion matrix with its columns scaled by
+    10^u, u ~ U(-decades, decades) from the seed: a badly scaled system (unit
+    variation of the diagonal over 2*decades orders of magnitude) for the
+    composition with a diagonal preconditioner."""
+    base = convdiff2d(N, alpha)
+    s = 10.0 ** np.random.default_rng(seed).uniform(-decades, decades, size=base.n)
+    return base.with_values(base.val * s[base.colind])
+
+
 def convdiff3d(N: int, cx: float = 0.0, cy: float = 0.0, cz: float = 0.0, gamma: float = 0.0) -> CSR:
     """3-D convection-diffusion, 7-point stencil on an N^3 interior grid."""
     rowptr, colind, val = _stencil(N, 3, (float(cx), float(cy), float(cz)), float(gamma))
