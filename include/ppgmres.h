@@ -81,6 +81,11 @@ typedef struct {
     double *history;  /* optional host array: true relative residual before each cycle
                          and at the end (history_cap entries at most) */
     int history_cap;
+    int new_poly_degree; /* > 0: the variant of section 5.2 (ChPoly): every cycle first builds
+                            a new polynomial of this degree from one GMRES(d) cycle started at
+                            the current residual, and uses it for that cycle's phi and p; the
+                            polynomial argument of pp_solve may then be NULL. 0: off */
+    int new_poly_add;    /* ChPoly: add roots for stability (Algorithm 2) */
 } pp_solve_opts;
 
 /* Result of pp_solve. */
@@ -261,6 +266,8 @@ pp_status pp_apply(pp_poly p, pp_matrix A, int kind, int prec, const void *v, vo
  * p(A)(V z) to x in FP64 (z minimises ||r|| e_1 - Hbar z) (iterative refinement when inner is not
  * FP64). A mixed cycle that fails to halve ||r|| is followed by an FP64 one.
  *   b, x : device double[n]; x is overwritten.
+ * With opts->new_poly_degree > 0 each cycle uses its own polynomial (see
+ * pp_solve_opts); info->mvps and info->dots then include those setups.
  * Returns PP_OK or PP_NOCONV (x is then the last iterate); info may be NULL. */
 pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_solve_opts *opts,
                    void *stream, pp_info *info);
@@ -307,7 +314,8 @@ pp_status pp_batch_setup(pp_batch B, const double *v0, int d, int add_roots, voi
  * polynomial (polys: host array of nsys). b, x: device double[n * nrhs],
  * interleaved (entry (row i, rhs r) at i*nrhs + r), each aligned to
  * 8*nrhs bytes (PP_EINVAL otherwise; fresh allocations are); x is overwritten.
- * opts as for pp_solve (opts->history receives pair 0's residuals). infos:
+ * opts as for pp_solve (opts->history receives pair 0's residuals;
+ * opts->new_poly_degree must be 0). infos:
  * host array of nsys*nrhs (pair s*nrhs + r) or NULL. PP_NOCONV if some pair
  * did not converge. */
 pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const double *b, double *x,

@@ -13,7 +13,8 @@ spell these out):
   y accumulated over cycles, residual b - phi(A) y, a single x = p(A)y at
   the end) is available as ``literal=True``; the two agree to rounding.
 * Outer stop: ||b - A x|| <= tol ||b||. NOCONV after max_cycles, or when
-  five consecutive cycles together reduce ||r|| by less than 1% (stall).
+  five consecutive cycles together reduce ||r|| by less than 1% (stall;
+  stall_cycles = 0 turns this test off).
 * The small least-squares problem is solved by numpy's lstsq on Hbar.
 
 Counters follow section 3.1: mvps are sparse products (setup included),
@@ -61,8 +62,17 @@ def _p_vops(units) -> int:
 
 def pp_gmres(A, b: np.ndarray, units, m: int = 50, tol: float = 1e-8, max_cycles: int = 1000,
              orth: str = "mgs", literal: bool = False, stall_cycles: int = 5,
-             setup_mvps: int = 0, x0=None):
-    """Solve A x = b by PP(d)-GMRES(m). Returns (x, Info)."""
+             setup_mvps: int = 0, x0=None, new_poly_degree: int = 0, new_poly_add: bool = True):
+    """Solve A x = b by PP(d)-GMRES(m). Returns (x, Info).
+
+    new_poly_degree > 0 is the variant of section 5.2 (ChPoly): at the start
+    of every cycle a new polynomial of that degree is built from one GMRES(d)
+    cycle whose start vector is the current residual (roots added when
+    new_poly_add), and that cycle's phi and p use it; ``units`` is then
+    ignored. The setup products count in mvps and its inner products in dots.
+    """
+    if new_poly_degree > 0 and literal:
+        raise ValueError("the literal form keeps one polynomial")
     b = np.asarray(b, dtype=np.float64)
     n = b.shape[0]
     bnorm = np.linalg.norm(b)
@@ -88,10 +98,15 @@ def pp_gmres(A, b: np.ndarray, units, m: int = 50, tol: float = 1e-8, max_cycles
             info.status = NOCONV
             break
         h = info.history
-        if len(h) > stall_cycles and h[-1] > 0.99 * h[-1 - stall_cycles]:
+        if stall_cycles > 0 and len(h) > stall_cycles and h[-1] > 0.99 * h[-1 - stall_cycles]:
             info.status = NOCONV
             break
         info.cycles += 1
+        if new_poly_degree > 0:
+            P = _roots.setup(A, r, new_poly_degree, add_roots=new_poly_add, orth=orth)
+            units = P.units
+            info.mvps += P.d
+            info.dots += 1 + sum((2 if orth == "cgs2" else 1) * (j + 1) + 1 for j in range(P.d))
         V = np.zeros((n, m + 1))
         Hb = np.zeros((m + 1, m))
         V[:, 0] = r / beta

@@ -287,10 +287,13 @@ def apply(poly: Poly, A: Matrix, v: torch.Tensor, kind: str = "p", out: torch.Te
     return out
 
 
-def solve(poly: Poly, A: Matrix, b, tol: float = 1e-8, m: int = 50, max_cycles: int = 1000,
-          inner: str = "fp32", stall_cycles: int = 5, x: torch.Tensor | None = None, inner_eta: float = 0.0):
+def solve(poly: Poly | None, A: Matrix, b, tol: float = 1e-8, m: int = 50, max_cycles: int = 1000,
+          inner: str = "fp32", stall_cycles: int = 5, x: torch.Tensor | None = None, inner_eta: float = 0.0,
+          new_poly_degree: int = 0, new_poly_add: bool = True):
     """x solving A x = b by PP-GMRES(m) with FP64 refinement. Returns (x, info dict);
-    info["history"] holds the true relative residual before each cycle and at the end."""
+    info["history"] holds the true relative residual before each cycle and at the end.
+    new_poly_degree > 0: a new polynomial of that degree from the current residual
+    at every cycle (section 5.2, ChPoly); poly may then be None."""
     b = _dev_tensor(b, torch.float64, A.device)
     if b.numel() != A.n:
         raise ValueError("right-hand side length")
@@ -298,9 +301,10 @@ def solve(poly: Poly, A: Matrix, b, tol: float = 1e-8, m: int = 50, max_cycles: 
         x = torch.empty_like(b)
     hist = np.zeros(max(int(max_cycles), 0) + 2)
     opts = SolveOpts(int(m), int(max_cycles), float(tol), PREC[inner], int(stall_cycles), float(inner_eta),
-                     hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hist.size)
+                     hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hist.size, int(new_poly_degree),
+                     int(bool(new_poly_add)))
     info = SolveInfo()
-    st = check(lib.pp_solve(poly.handle, A.handle, _ptr(b), _ptr(x), ctypes.byref(opts), _stream(A.device),
+    st = check(lib.pp_solve(poly.handle if poly is not None else None, A.handle, _ptr(b), _ptr(x), ctypes.byref(opts), _stream(A.device),
                             ctypes.byref(info)), "pp_solve")
     out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
     out["status_name"] = STATUS_NAMES.get(st, str(st))

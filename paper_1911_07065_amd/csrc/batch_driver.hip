@@ -528,8 +528,9 @@ pp_status pp_batch_setup(pp_batch B, const double *v0, int d, int add_roots, voi
 pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const double *b, double *x,
                          const pp_solve_opts *opts, void *stream, pp_info *infos) {
     if (!B || !polys || !b || !x || !opts || !(nrhs == 1 || nrhs == 2 || nrhs == 4) || opts->m < 1 ||
-        opts->max_cycles < 0 || !(opts->tol > 0.0) || opts->inner < 0 || opts->inner > 2) {
-        set_error("pp_batch_solve: bad argument (nrhs must be 1, 2 or 4)");
+        opts->max_cycles < 0 || !(opts->tol > 0.0) || opts->inner < 0 || opts->inner > 2 ||
+        opts->new_poly_degree != 0) {
+        set_error("pp_batch_solve: bad argument (nrhs must be 1, 2 or 4; no new polynomial per cycle)");
         return PP_EINVAL;
     }
     // the kernels move the nrhs values of a row as one vector access

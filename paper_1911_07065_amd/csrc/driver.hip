@@ -1133,8 +1133,9 @@ pp_status pp_stability_check(pp_poly p, pp_matrix A, const double *b, void *stre
 
 pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_solve_opts *opts, void *stream,
                    pp_info *info) {
-    if (!p || !A || !b || !x || !opts || opts->m < 1 || opts->max_cycles < 0 || !(opts->tol > 0.0) ||
-        !valid_prec(opts->inner)) {
+    const int d_new = opts ? opts->new_poly_degree : 0;
+    if ((!p && d_new <= 0) || !A || !b || !x || !opts || opts->m < 1 || opts->max_cycles < 0 ||
+        !(opts->tol > 0.0) || !valid_prec(opts->inner) || d_new < 0 || d_new > std::min(A->n, kMaxDegree)) {
         set_error("pp_solve: bad argument");
         return PP_EINVAL;
     }
@@ -1142,9 +1143,16 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
     const double t0 = now_s();
     const int n = A->n;
     const int m = opts->m;
-    PP_TRY(A->ensure_ws(0, m));
+    PP_TRY(A->ensure_ws(0, std::max(m, d_new)));
     if (opts->inner != PP_F64) PP_TRY(A->ensure_ws(opts->inner, m));
-    PP_TRY(A->ensure_red(m + 1));
+    PP_TRY(A->ensure_red(std::max(m, d_new) + 1));
+    // ChPoly: the polynomial of the current cycle, owned here
+    struct Owned {
+        pp_poly q = nullptr;
+        ~Owned() {
+            if (q) pp_poly_destroy(q);
+        }
+    } owned;
     pp_info inf;
     std::memset(&inf, 0, sizeof(inf));
     inf.relres_shortcut = NAN;
@@ -1171,8 +1179,6 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
     std::vector<double> hist;
     GivensLS ls;
     std::vector<double> zh(m + 1);
-    const int dphi = p->plan.d_eff;
-    const int64_t mv_phi = dphi, mv_p = dphi - 1;
     pp_status status = PP_OK;
     for (;;) {
         const double relres = beta / bnorm;
@@ -1199,6 +1205,22 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
         }
         inf.cycles++;
         if (prec == PP_F64) inf.fp64_cycles++;
+        if (d_new > 0) {
+            // section 5.2: a new polynomial from GMRES(d) started at the current residual
+            std::vector<double> Hb;
+            int kk = 0;
+            bool brk = false;
+            int64_t sdots = 0;
+            PP_TRY(setup_arnoldi(A, A->r64, d_new, st, Hb, kk, brk, sdots, "pp_solve"));
+            pp_poly q = nullptr;
+            PP_TRY(poly_from_hbar(Hb, d_new + 1, kk, brk, opts->new_poly_add != 0, "pp_solve", &q));
+            if (owned.q) pp_poly_destroy(owned.q);
+            owned.q = q;
+            p = q;
+            inf.mvps += kk;
+            inf.dots += sdots;
+        }
+        const int64_t mv_phi = p->plan.d_eff, mv_p = p->plan.d_eff - 1;
         const Workspace &ws = A->ws[prec];
         // V[:,0] = r / beta in the cycle's precision
         HIP_TRY(launch_scale_cast(0, prec, n, A->r64, nullptr, 1.0 / beta, vcol(ws, prec, 0), st));

@@ -301,3 +301,62 @@ def test_jacobi_composed_gradient(pp):
     _, _, dv = grad_direct(A, b, lambda z: z - xt)
     g_or = float(dv @ dval)
     assert abs(float(th.grad) - g_or) <= 1e-6 * abs(g_or)
+
+
+# ---------------------------------------------------------------------------
+# polynomial changed at every cycle (section 5.2, ChPoly)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_chpoly_matches_oracle(pp, inner):
+    csr = convdiff2d(50, 1.0)
+    A = csr.to_scipy()
+    b = rhs(csr.n, 1)
+    say("chpoly cfg1", inner)
+    M = pp.Matrix.from_csr(csr)
+    x, info = pp.solve(None, M, dev(b), tol=1e-10, m=50, inner=inner, new_poly_degree=10)
+    xo, io = osolver.pp_gmres(A, b, None, m=50, tol=1e-10, orth="cgs2", new_poly_degree=10)
+    xh = host(x)
+    assert info["converged"] and np.linalg.norm(b - A @ xh) <= 1e-10 * np.linalg.norm(b)
+    assert relerr(xh, xo) <= 1e-6
+    if inner == "fp64":  # the same path up to the rounding of two Arnoldi runs
+        assert abs(info["cycles"] - io.cycles) <= 1 and abs(info["mvps"] - io.mvps) <= 0.05 * io.mvps
+
+
+def test_chpoly_example12_table5_1(pp, golden_dir):
+    # Example 12 at full size: diag(i^2/n), n = 10000, GMRES(50), tol 1e-10.
+    # mvps against Table 5.1 (loose: other random vectors, CGS2 instead of
+    # MGS), and the table's ordering at d = 10 and 25: ChPoly needs fewer
+    # products than the fixed polynomial
+    import os
+    import time
+
+    from workloads import diag_squares
+
+    rows = {int(r[0]): (r[1] * 1000, r[2] * 1000) for r in
+            np.loadtxt(os.path.join(golden_dir, "table5_1_chpoly.txt"), comments="#", ndmin=2)}
+    n = 10000
+    csr = diag_squares(n)
+    A = csr.to_scipy()
+    b, v0 = rhs(n, 1), start_vector(n, 2)
+    M = pp.Matrix.from_csr(csr)
+    for d in (10, 25):
+        say("example 12 chpoly", d)
+        t0 = time.perf_counter()
+        x, ich = pp.solve(None, M, dev(b), tol=1e-10, m=50, max_cycles=20000, inner="fp64", stall_cycles=0,
+                          new_poly_degree=d)
+        t_ch = time.perf_counter() - t0
+        assert ich["converged"] and np.linalg.norm(b - A @ host(x)) <= 1e-10 * np.linalg.norm(b)
+        say("example 12 fixed", d)
+        t0 = time.perf_counter()
+        poly = pp.setup(M, dev(v0), d)
+        x, ipp = pp.solve(poly, M, dev(b), tol=1e-10, m=50, max_cycles=20000, inner="fp64", stall_cycles=0)
+        t_pp = time.perf_counter() - t0
+        assert ipp["converged"]
+        ppg, chp = rows[d]
+        mv_pp = ipp["mvps"] + poly.d
+        say("d", d, "ChPoly mvps", ich["mvps"], "(paper", chp, ") s", round(t_ch, 2), "| PP-G mvps", mv_pp,
+            "(paper", ppg, ") s", round(t_pp, 2))
+        assert 0.5 * chp <= ich["mvps"] <= 1.5 * chp
+        assert 0.5 * ppg <= mv_pp <= 1.5 * ppg
+        assert ich["mvps"] < mv_pp

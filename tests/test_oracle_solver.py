@@ -262,3 +262,35 @@ def test_custom_right_scaling_solves():
     P = roots.setup(AS, v0, 8, orth="cgs2")
     xt, inf = solver.pp_gmres(AS, b, P.units, m=50, tol=1e-10, max_cycles=50)
     assert np.linalg.norm(b - A @ (s * xt)) <= 1e-10 * np.linalg.norm(b)
+
+
+# ---------------------------------------------------------------------------
+# polynomial changed at every cycle (section 5.2, ChPoly)
+# ---------------------------------------------------------------------------
+
+def test_chpoly_first_cycle_uses_the_polynomial_from_b():
+    # the first residual is b, so cycle 1 is PP-GMRES with GMRES(d) started at b
+    A = convdiff2d(30, 10.0).to_scipy()
+    b = rhs(A.shape[0], 1)
+    x1, i1 = solver.pp_gmres(A, b, None, m=20, tol=1e-12, max_cycles=1, orth="cgs2", new_poly_degree=8)
+    P = roots.setup(A, b, 8, orth="cgs2")
+    x2, i2 = solver.pp_gmres(A, b, P.units, m=20, tol=1e-12, max_cycles=1, orth="cgs2")
+    assert np.array_equal(x1, x2)
+    assert i1.mvps == i2.mvps + P.d and i1.cycles == i2.cycles == 1
+
+
+def test_chpoly_needs_fewer_mvps_at_low_degree():
+    # Table 5.1's trend at low degree, on Example 12's matrix scaled down to
+    # n = 2000: the changing polynomial needs far fewer products
+    from workloads import diag_squares
+
+    n = 2000
+    A = diag_squares(n).to_scipy()
+    b, v0 = rhs(n, 1), start_vector(n, 2)
+    x, ich = solver.pp_gmres(A, b, None, m=50, tol=1e-10, max_cycles=5000, orth="cgs2", new_poly_degree=10,
+                             stall_cycles=0)
+    assert ich.status == solver.OK and np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+    P = roots.setup(A, v0, 10, orth="cgs2")
+    _, ipp = solver.pp_gmres(A, b, P.units, m=50, tol=1e-10, max_cycles=5000, orth="cgs2", setup_mvps=P.d,
+                             stall_cycles=0)
+    assert ipp.status == solver.OK and ich.mvps < ipp.mvps / 2
