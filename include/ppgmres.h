@@ -224,6 +224,20 @@ typedef struct {
 pp_status pp_gmres_setup_checked(pp_matrix A, const double *v0, int d, int add_roots, const pp_stch_opts *opts,
                                  void *stream, pp_poly *out, pp_setup_info *info, double *stch);
 
+/* Double polynomial (section 6): one GMRES(d2) cycle with the operator
+ * phi1(A), started at v0, gives the roots of phi2 (Algorithm 4 step 1 and
+ * Algorithm 2 applied to phi1(A)). The result is the composite polynomial
+ * phi2(phi1(A)): pp_apply and pp_solve then use phi(A) = phi2(phi1(A)) and
+ * p(A) = p1(A) p2(phi1(A)), with phi1(a) = a p1(a) and phi2(a) = a p2(a)
+ * (so A p(A) = phi(A)); its degree is d_eff(phi1) * d_eff(phi2). The
+ * composite keeps its own copy of phi1 (p1 may be destroyed afterwards).
+ * pp_poly_roots gives phi2's roots (PP_ROOTS_FINAL/THETA/LEJA) and phi1's
+ * final roots (PP_ROOTS_INNER). info as for pp_gmres_setup, for phi2 (mvps
+ * counts the sparse products: d2 applications of phi1). Not accepted by
+ * pp_batch_solve. */
+pp_status pp_gmres_setup_double(pp_matrix A, pp_poly p1, const double *v0, int d2, int add_roots, void *stream,
+                                pp_poly *out, pp_setup_info *info);
+
 /* Flags of pp_poly_from_roots. */
 #define PP_ROOTS_ADD 1        /* add roots for stability (Algorithm 2) */
 #define PP_ROOTS_KEEP_ORDER 2 /* use the list as given: no Leja ordering, no added
@@ -239,6 +253,7 @@ pp_status pp_poly_from_roots(int d, const double *re, const double *im, int flag
 #define PP_ROOTS_FINAL 0  /* ordered list with added roots (what the chains apply) */
 #define PP_ROOTS_THETA 1  /* harmonic Ritz values as the eigensolver returned them */
 #define PP_ROOTS_LEJA 2   /* original roots in modified Leja order */
+#define PP_ROOTS_INNER 3  /* composite polynomial: the final roots of the inner phi1 */
 
 /* Copy a root list (host). cap: capacity of re/im (re/im may be NULL to
  * query sizes); len receives the list length (PP_EINVAL if cap < len).

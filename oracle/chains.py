@@ -72,3 +72,37 @@ def spmv_count_p(units) -> int:
         else:
             c += 1 if idx == last else 2
     return c
+
+
+# ---------------------------------------------------------------------------
+# double polynomial (section 6): phi2(phi1(A)) and p1(A) p2(phi1(A))
+# ---------------------------------------------------------------------------
+
+class PhiOperator:
+    """phi1(A) as an operator, ``op @ v = phi1(A) v`` (Algorithm 1): the
+    matrix of the second GMRES run of a double polynomial, and the variable
+    in which phi2's roots live."""
+
+    def __init__(self, A, units):
+        self.A = A
+        self.units = units
+        self.shape = A.shape
+
+    def __matmul__(self, v):
+        return apply_phi(self.A, self.units, v)
+
+
+def apply_phi_double(A, inner, outer, v: np.ndarray) -> np.ndarray:
+    """phi2(phi1(A)) v: Algorithm 1 for phi2 with phi1(A) as the matrix."""
+    return apply_phi(PhiOperator(A, inner), outer, v)
+
+
+def apply_pi_double(A, inner, outer, v: np.ndarray) -> np.ndarray:
+    """pi2(phi1(A)) v = v - phi2(phi1(A)) v."""
+    return apply_pi(PhiOperator(A, inner), outer, v)
+
+
+def apply_p_double(A, inner, outer, v: np.ndarray) -> np.ndarray:
+    """p(A) v with A p(A) = phi2(phi1(A)): since phi1(a) = a p1(a) and
+    phi2(a) = a p2(a), p(A) = p1(A) p2(phi1(A)) (section 6)."""
+    return apply_p(A, inner, apply_p(PhiOperator(A, inner), outer, v))

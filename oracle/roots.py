@@ -377,3 +377,13 @@ def poly_from_roots(theta, add_roots: bool = False) -> Poly:
     theta = np.asarray(theta, dtype=np.complex128)
     leja, pof, n_add, units = order_and_add(theta, add_roots)
     return Poly(d=theta.size, theta=theta, leja=leja, pof=pof, n_add=n_add, units=units)
+
+
+def setup_double(A, inner_units, v0: np.ndarray, d2: int, add_roots: bool = True, orth: str = "mgs") -> Poly:
+    """The outer polynomial phi2 of a double polynomial (section 6): one
+    GMRES(d2) cycle with the matrix phi1(A) (inner_units) from v0, then the
+    harmonic Ritz values, Leja order and added roots of Algorithm 4 step 1
+    and Algorithm 2, all in the variable of phi1(A)."""
+    from .chains import PhiOperator
+
+    return setup(PhiOperator(A, inner_units), v0, d2, add_roots, orth)

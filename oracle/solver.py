@@ -29,7 +29,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import roots as _roots
-from .chains import apply_p, apply_phi, spmv_count_p, spmv_count_phi
+from .chains import PhiOperator, apply_p, apply_phi, spmv_count_p, spmv_count_phi
 from .roots import BREAKDOWN_TOL, REAL
 
 OK, NOCONV = 0, 1
@@ -62,7 +62,8 @@ def _p_vops(units) -> int:
 
 def pp_gmres(A, b: np.ndarray, units, m: int = 50, tol: float = 1e-8, max_cycles: int = 1000,
              orth: str = "mgs", literal: bool = False, stall_cycles: int = 5,
-             setup_mvps: int = 0, x0=None, new_poly_degree: int = 0, new_poly_add: bool = True):
+             setup_mvps: int = 0, x0=None, new_poly_degree: int = 0, new_poly_add: bool = True,
+             inner_units=None):
     """Solve A x = b by PP(d)-GMRES(m). Returns (x, Info).
 
     new_poly_degree > 0 is the variant of section 5.2 (ChPoly): at the start
@@ -70,6 +71,10 @@ def pp_gmres(A, b: np.ndarray, units, m: int = 50, tol: float = 1e-8, max_cycles
     cycle whose start vector is the current residual (roots added when
     new_poly_add), and that cycle's phi and p use it; ``units`` is then
     ignored. The setup products count in mvps and its inner products in dots.
+
+    inner_units: a double polynomial (section 6): ``units`` are phi2's and
+    the solve uses phi2(phi1(A)) and p1(A) p2(phi1(A)); mvps count products
+    with A (each application of phi1(A) is d_eff(phi1) of them).
     """
     if new_poly_degree > 0 and literal:
         raise ValueError("the literal form keeps one polynomial")
@@ -77,7 +82,20 @@ def pp_gmres(A, b: np.ndarray, units, m: int = 50, tol: float = 1e-8, max_cycles
     n = b.shape[0]
     bnorm = np.linalg.norm(b)
     info = Info(mvps=setup_mvps)
-    phi = lambda v: apply_phi(A, units, v)  # noqa: E731
+    if inner_units is not None:
+        if new_poly_degree > 0 or literal:
+            raise ValueError("a double polynomial is fixed")
+        op = PhiOperator(A, inner_units)
+        n1 = spmv_count_phi(inner_units)
+        phi = lambda v: apply_phi(op, units, v)  # noqa: E731
+        p_of = lambda v: apply_p(A, inner_units, apply_p(op, units, v))  # noqa: E731
+        mv_phi = lambda: spmv_count_phi(units) * n1  # noqa: E731
+        mv_p = lambda: spmv_count_p(units) * n1 + spmv_count_p(inner_units)  # noqa: E731
+    else:
+        phi = lambda v: apply_phi(A, units, v)  # noqa: E731
+        p_of = lambda v: apply_p(A, units, v)  # noqa: E731
+        mv_phi = lambda: spmv_count_phi(units)  # noqa: E731
+        mv_p = lambda: spmv_count_p(units)  # noqa: E731
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     y = np.zeros(n)
     if x0 is None:
@@ -115,7 +133,7 @@ def pp_gmres(A, b: np.ndarray, units, m: int = 50, tol: float = 1e-8, max_cycles
         z = np.zeros(0)
         for j in range(m):
             w = phi(V[:, j])
-            info.mvps += spmv_count_phi(units)
+            info.mvps += mv_phi()
             info.vops += _phi_vops(units)
             if orth == "mgs":
                 for i in range(j + 1):
@@ -154,8 +172,8 @@ def pp_gmres(A, b: np.ndarray, units, m: int = 50, tol: float = 1e-8, max_cycles
             info.vops += _phi_vops(units) + 2
             # x is formed once at the end; keep it current for the history
         else:
-            x = x + apply_p(A, units, dy)
-            info.mvps += spmv_count_p(units)
+            x = x + p_of(dy)
+            info.mvps += mv_p()
             info.vops += _p_vops(units) + 1
             r = b - A @ x
             info.mvps += 1

@@ -12,7 +12,7 @@ add_roots, harmonic_ritz, hessenberg_eig.
 """
 
 __all__ = [
-    "Matrix", "Poly", "setup", "setup_checked", "poly_from_roots", "apply", "solve", "stability_check", "PPSolve",
+    "Matrix", "Poly", "setup", "setup_checked", "setup_double", "poly_from_roots", "apply", "solve", "stability_check", "PPSolve",
     "pp_solve_fn", "leja_order", "add_roots", "harmonic_ritz", "hessenberg_eig", "version", "Batch",
 ]
 

@@ -177,12 +177,14 @@ class Poly:
     breakdown: bool = False
     setup_info: dict | None = None
     stch: float | None = None  # stability check value (setup_checked only)
+    composite_degree: int | None = None  # double polynomials: degree of phi2(phi1(z))
     unstable: bool = False     # setup_checked: no degree tried passed the check
 
     def roots(self, which: str = "final") -> np.ndarray:
         """Root list: "final" (applied order, with added roots), "theta" (raw
-        harmonic Ritz values) or "leja" (original roots in Leja order)."""
-        w = {"final": 0, "theta": 1, "leja": 2}[which]
+        harmonic Ritz values), "leja" (original roots in Leja order) or, for a
+        double polynomial, "inner" (the final roots of phi1)."""
+        w = {"final": 0, "theta": 1, "leja": 2, "inner": 3}[which]
         ln = ctypes.c_int()
         check(lib.pp_poly_roots(self.handle, w, 0, None, None, ctypes.byref(ln), None, None), "pp_poly_roots")
         re = np.zeros(ln.value)
@@ -233,6 +235,26 @@ def setup(A: Matrix, v0, d: int, add_roots: bool = True) -> Poly:
                                   ctypes.byref(h), ctypes.byref(info)), "pp_gmres_setup")
     si = {k: getattr(info, k) for k, _ in SetupInfo._fields_}
     return _poly_from_handle(h, si, breakdown=(st == PP_BREAKDOWN) or bool(info.breakdown))
+
+
+def setup_double(A: Matrix, p1: Poly, v0, d2: int, add_roots: bool = True) -> Poly:
+    """Double polynomial (section 6): phi2 from GMRES(d2) with the operator
+    phi1(A) started at v0; the result is the composite phi2(phi1(A)) with
+    p(A) = p1(A) p2(phi1(A)). Its roots("final"/"theta"/"leja") are phi2's,
+    roots("inner") phi1's; .composite_degree = d_eff(phi1) * d_eff(phi2)."""
+    v0 = _dev_tensor(v0, torch.float64, A.device)
+    if v0.numel() != A.n:
+        raise ValueError("start vector length")
+    h = ctypes.c_void_p()
+    info = SetupInfo()
+    st = check(lib.pp_gmres_setup_double(A.handle, p1.handle, _ptr(v0), int(d2), int(bool(add_roots)),
+                                         _stream(A.device), ctypes.byref(h), ctypes.byref(info)),
+               "pp_gmres_setup_double")
+    si = {k: getattr(info, k) for k, _ in SetupInfo._fields_}
+    poly = _poly_from_handle(h, si, breakdown=(st == PP_BREAKDOWN) or bool(info.breakdown))
+    poly.composite_degree = p1.d_eff * poly.d_eff if p1.composite_degree is None else \
+        p1.composite_degree * poly.d_eff
+    return poly
 
 
 def setup_checked(A: Matrix, v0, d: int, b, tol: float = 1e-8, d_step: int = 0, d_min: int = 1,

@@ -540,8 +540,8 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
         return PP_EINVAL;
     }
     for (int s = 0; s < B->nsys; ++s)
-        if (!polys[s]) {
-            set_error("pp_batch_solve: null polynomial");
+        if (!polys[s] || polys[s]->inner) {
+            set_error("pp_batch_solve: null or composite polynomial");
             return PP_EINVAL;
         }
     hipStream_t st = S(stream);

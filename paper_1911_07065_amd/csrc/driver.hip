@@ -38,6 +38,7 @@ struct Workspace {
     long ldv = 0;
     void *V = nullptr;   // ldv x (m+1)
     void *P0 = nullptr, *P1 = nullptr, *T = nullptr, *D = nullptr, *ACC = nullptr;
+    void *X = nullptr;  // 5 more vectors for composite polynomials (allocated on first use)
 };
 
 struct pp_matrix_s {
@@ -130,8 +131,19 @@ struct pp_matrix_s {
     void release_ws(Workspace &w) {
         dev_free(w.V);
         dev_free(w.P0);  // P1, T, D and ACC live in P0's allocation
+        dev_free(w.X);
         w.P1 = w.T = w.D = w.ACC = nullptr;
         w.m = -1;
+    }
+
+    // The 5 extra vectors of a precision (after ensure_ws).
+    pp_status ensure_extra(int prec) {
+        Workspace &w = ws[prec];
+        if (w.X) return PP_OK;
+        char *q = nullptr;
+        PP_TRY(dev_alloc(&q, (size_t)w.ldv * elem_size(prec) * 5));
+        w.X = q;
+        return PP_OK;
     }
 
     // Reduction buffers for up to `cols` Krylov columns.
@@ -389,7 +401,10 @@ const std::vector<Step> &prog_of(pp_poly p, int kind) {
 
 // Evaluate a chain program: one cooperative launch (persistent kernel) or
 // one launch per step, as tuned for this matrix and precision.
+pp_status run_composite(pp_matrix A, pp_poly poly, int kind, int prec, const void *in, void *out, hipStream_t st);
+
 pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void *in, void *out, hipStream_t st) {
+    if (poly->inner) return run_composite(A, poly, kind, prec, in, out, st);
     PP_TRY(ensure_tuned(A, prec, st));
     const std::vector<Step> &prog = prog_of(poly, kind);
     if (A->persist[prec] && prog.size() >= 2) {
@@ -425,6 +440,80 @@ pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void 
         HIP_TRY(launch_chain_step(d, prec, p, st));
     }
     return PP_OK;
+}
+
+// A composite polynomial phi2(phi1(A)) (section 6). The outer program is
+// phi2's with every sparse product replaced by phi1(A): the inner chain
+// writes phi1(A) in into Q, then one elementwise launch applies the outer
+// step's update with Q as its product term. kind P: p1(A) p2(phi1(A)) v,
+// the outer p2 program into E, then the inner p1 program from E.
+pp_status run_composite(pp_matrix A, pp_poly poly, int kind, int prec, const void *in, void *out, hipStream_t st) {
+    PP_TRY(ensure_tuned(A, prec, st));
+    PP_TRY(A->ensure_extra(prec));
+    const Workspace &w = A->ws[prec];
+    const size_t vec = (size_t)w.ldv * elem_size(prec);
+    char *X = (char *)w.X;
+    void *Q = X, *O0 = X + vec, *O1 = X + 2 * vec, *OT = X + 3 * vec, *E = X + 4 * vec;
+    pp_poly inner = const_cast<pp_poly>(poly->inner.get());
+    void *dst = kind == PP_APPLY_P ? E : out;
+    auto bp = [&](int b) -> void * {
+        switch (b) {
+            case B_IN:
+                return (void *)in;
+            case B_OUT:
+                return dst;
+            case B_P0:
+                return O0;
+            case B_P1:
+                return O1;
+            case B_T:
+                return OT;
+            default:
+                return nullptr;
+        }
+    };
+    for (const Step &s : prog_of(poly, kind)) {
+        StepPtrs p;
+        p.in = bp(s.in);
+        p.aux = bp(s.aux);
+        p.vfin = s.fin ? in : nullptr;
+        p.out = bp(s.out);
+        p.acc = bp(s.acc);
+        p.acc_init = s.acc_init;
+        p.spmv = 0;
+        p.a0 = s.a0;
+        p.a1 = s.a1;
+        p.a2 = s.a2;
+        p.b0 = s.b0;
+        p.b1 = s.b1;
+        p.prod = nullptr;
+        if (s.spmv) {
+            PP_TRY(run_program(A, inner, PP_APPLY_PHI, prec, p.in, Q, st));
+            p.prod = Q;
+        }
+        HIP_TRY(launch_chain_step(A->dev(), prec, p, st));
+    }
+    if (kind == PP_APPLY_P) PP_TRY(run_program(A, inner, PP_APPLY_P, prec, E, out, st));
+    return PP_OK;
+}
+
+// Sparse products of one application of a polynomial (kind PHI/PI or P).
+int64_t chain_mvps(pp_poly p, int kind) {
+    if (!p->inner) return kind == PP_APPLY_P ? p->plan.d_eff - 1 : p->plan.d_eff;
+    const int64_t inner_phi = chain_mvps(const_cast<pp_poly>(p->inner.get()), PP_APPLY_PHI);
+    const int64_t outer = kind == PP_APPLY_P ? p->plan.d_eff - 1 : p->plan.d_eff;
+    return outer * inner_phi +
+           (kind == PP_APPLY_P ? chain_mvps(const_cast<pp_poly>(p->inner.get()), PP_APPLY_P) : 0);
+}
+
+// Launches of one application (for the vector-operation counter).
+int64_t chain_launches(pp_poly p, int kind) {
+    const std::vector<Step> &prog = prog_of(p, kind);
+    if (!p->inner) return (int64_t)prog.size();
+    const pp_poly in = const_cast<pp_poly>(p->inner.get());
+    int64_t n = 0;
+    for (const Step &s : prog) n += 1 + (s.spmv ? chain_launches(in, PP_APPLY_PHI) : 0);
+    return n + (kind == PP_APPLY_P ? chain_launches(in, PP_APPLY_P) : 0);
 }
 
 // One step of the SpMV alone: out = a0 * A in + a2 * aux
@@ -904,7 +993,7 @@ namespace {
 // dimension d+1), k the Krylov dimension reached (k < d after a breakdown)
 // and dots the inner products and norms used.
 pp_status setup_arnoldi(pp_matrix A, const double *v0, int d, hipStream_t st, std::vector<double> &Hbar, int &k,
-                        bool &brk, int64_t &dots, const char *who) {
+                        bool &brk, int64_t &dots, const char *who, pp_poly op = nullptr) {
     PP_TRY(A->ensure_ws(0, d));
     PP_TRY(A->ensure_red(d + 1));
     const Workspace &ws = A->ws[0];
@@ -933,7 +1022,11 @@ pp_status setup_arnoldi(pp_matrix A, const double *v0, int d, hipStream_t st, st
     } free_h{Hdev};
     HIP_TRY(hipMemsetAsync(Hdev, 0, sizeof(double) * ld * d, st));
     for (int j = 0; j < d; ++j) {
-        PP_TRY(spmv_axpby(A, 0, vcol(ws, 0, j), 1.0, nullptr, 0.0, vcol(ws, 0, j + 1), st));
+        // the operator: A, or phi1(A) for the second polynomial of a double one
+        if (op)
+            PP_TRY(run_program(A, op, PP_APPLY_PHI, 0, vcol(ws, 0, j), vcol(ws, 0, j + 1), st));
+        else
+            PP_TRY(spmv_axpby(A, 0, vcol(ws, 0, j), 1.0, nullptr, 0.0, vcol(ws, 0, j + 1), st));
         PP_TRY(cgs2_step(A, 0, ws, j, st, Hdev + (size_t)j * ld, false));
     }
     Hbar.assign((size_t)ld * d, 0.0);
@@ -1026,6 +1119,35 @@ pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, vo
     return (brk && k < d) ? PP_BREAKDOWN : PP_OK;
 }
 
+pp_status pp_gmres_setup_double(pp_matrix A, pp_poly p1, const double *v0, int d2, int add_roots, void *stream,
+                                pp_poly *out, pp_setup_info *info) {
+    if (!A || !p1 || !v0 || !out || d2 < 1 || d2 > A->n || d2 > kMaxDegree) {
+        set_error("pp_gmres_setup_double: bad argument (need p1 and 1 <= d2 <= min(n, 4096))");
+        return PP_EINVAL;
+    }
+    hipStream_t st = S(stream);
+    const double t0 = now_s();
+    std::vector<double> Hbar;
+    int k = 0;
+    bool brk = false;
+    int64_t dots = 0;
+    PP_TRY(setup_arnoldi(A, v0, d2, st, Hbar, k, brk, dots, "pp_gmres_setup_double", p1));
+    pp_poly q = nullptr;
+    PP_TRY(poly_from_hbar(Hbar, d2 + 1, k, brk, add_roots != 0, "pp_gmres_setup_double", &q));
+    q->inner = std::make_shared<const pp_poly_s>(*p1);
+    *out = q;
+    if (info) {
+        info->d = k;
+        info->d_eff = q->plan.d_eff;
+        info->n_added = q->plan.n_added;
+        info->breakdown = brk ? 1 : 0;
+        info->mvps = (int64_t)k * chain_mvps(p1, PP_APPLY_PHI);
+        info->dots = dots;
+        info->t_setup_s = now_s() - t0;
+    }
+    return (brk && k < d2) ? PP_BREAKDOWN : PP_OK;
+}
+
 pp_status pp_gmres_setup_checked(pp_matrix A, const double *v0, int d, int add_roots, const pp_stch_opts *opts,
                                  void *stream, pp_poly *out, pp_setup_info *info, double *stch) {
     if (!A || !v0 || !out || !opts || !opts->b || d < 1 || d > A->n || d > kMaxDegree || !(opts->tol >= 0.0) ||
@@ -1063,7 +1185,7 @@ pp_status pp_gmres_setup_checked(pp_matrix A, const double *v0, int d, int add_r
             if (best) pp_poly_destroy(best);
             return s;
         }
-        mvps += 2L * p->plan.d_eff;  // p(A)b (d_eff - 1), A p(A)b (1), phi(A)b (d_eff)
+        mvps += chain_mvps(p, PP_APPLY_P) + 1 + chain_mvps(p, PP_APPLY_PHI);  // p(A)b, A p(A)b, phi(A)b
         dots += 1;
         const double key = std::isfinite(sc) ? sc : INFINITY;
         if (sc <= limit) {
@@ -1220,7 +1342,7 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
             inf.mvps += kk;
             inf.dots += sdots;
         }
-        const int64_t mv_phi = p->plan.d_eff, mv_p = p->plan.d_eff - 1;
+        const int64_t mv_phi = chain_mvps(p, PP_APPLY_PHI), mv_p = chain_mvps(p, PP_APPLY_P);
         const Workspace &ws = A->ws[prec];
         // V[:,0] = r / beta in the cycle's precision
         HIP_TRY(launch_scale_cast(0, prec, n, A->r64, nullptr, 1.0 / beta, vcol(ws, prec, 0), st));
@@ -1234,7 +1356,7 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
             PP_TRY(cgs2_step(A, prec, ws, j, st));
             inf.mvps += mv_phi;
             inf.dots += 2 * (j + 1) + 1;
-            inf.vops += 4 * (j + 1) + 2 + (int64_t)p->prog_phi.size();
+            inf.vops += 4 * (j + 1) + 2 + chain_launches(p, PP_APPLY_PHI);
             inf.iters++;
             bool finite = true;
             for (int i = 0; i <= j + 1; ++i) {
@@ -1263,7 +1385,7 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
             PP_TRY(run_program(A, p, PP_APPLY_P, prec, ws.D, ws.ACC, st));
             HIP_TRY(launch_axpy_x(prec, n, 1.0, ws.ACC, x, st));
             inf.mvps += mv_p;
-            inf.vops += k + (int64_t)p->prog_p.size() * 2 + 1;
+            inf.vops += k + chain_launches(p, PP_APPLY_P) * 2 + 1;
         }
         // true residual in FP64: r = b - A x
         PP_TRY(spmv_axpby(A, 0, x, -1.0, b, 1.0, A->r64, st));

@@ -638,15 +638,16 @@ pp_status pp_poly_from_roots(int d, const double *re, const double *im, int flag
 
 pp_status pp_poly_roots(pp_poly p, int which, int cap, double *re, double *im, int *len, int *d_orig,
                         int *n_added) {
-    if (!p || which < 0 || which > 2) {
-        set_error("pp_poly_roots: bad argument");
+    if (!p || which < 0 || which > 3 || (which == PP_ROOTS_INNER && !p->inner)) {
+        set_error("pp_poly_roots: bad argument (PP_ROOTS_INNER needs a composite polynomial)");
         return PP_EINVAL;
     }
     if (d_orig) *d_orig = p->plan.d;
     if (n_added) *n_added = p->plan.n_added;
     std::vector<double> r, i;
-    if (which == PP_ROOTS_FINAL) {
-        for (auto &u : p->plan.units) {
+    if (which == PP_ROOTS_FINAL || which == PP_ROOTS_INNER) {
+        const pp_poly_s *q = which == PP_ROOTS_INNER ? p->inner.get() : p;
+        for (auto &u : q->plan.units) {
             r.push_back(u.re);
             i.push_back(u.im);
             if (u.kind == UNIT_PAIR) {

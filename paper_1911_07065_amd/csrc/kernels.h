@@ -62,6 +62,8 @@ struct StepPtrs {
     int acc_init;
     int spmv;
     double a0, a1, a2, b0, b1;
+    // spmv == 0: the product term a0 * prod[r] comes from this vector (null: none)
+    const void *prod = nullptr;
 };
 
 // CSR in the form the kernels read.

@@ -80,12 +80,14 @@ __device__ __forceinline__ void row_finish(const ChainArgs<VT, XT> &a, int r, ty
     if (a.out) stx(a.out, r, a.vfin ? p.vf - w : w);
 }
 
-// steps without a sparse product (a0 unused)
+// steps without a sparse product: the product term is a0 * prod[r] when a
+// product vector is given (a composite polynomial's outer step, whose
+// operator was applied by another chain), else zero
 template <typename VT, typename XT>
-__global__ __launch_bounds__(256) void k_chain_elem(ChainArgs<VT, XT> a) {
+__global__ __launch_bounds__(256) void k_chain_elem(ChainArgs<VT, XT> a, const XT *prod) {
     using AT = typename Arith<XT>::T;
     const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r < a.n) row_finish(a, r, AT(0), row_prefetch(a, r));
+    if (r < a.n) row_finish(a, r, prod ? (AT)ldx(prod, r) : AT(0), row_prefetch(a, r));
 }
 
 // One row tile of a chain step (r0, r1, e0, e1 in ti); buf: LDS of 256*EPT
@@ -603,7 +605,8 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int v
     const ChainArgs<VT, XT> a = chain_args<VT, XT>(A, val, s);
     if (A.n == 0) return hipSuccess;
     if (!s.spmv) {
-        hipLaunchKernelGGL((k_chain_elem<VT, XT>), dim3((A.n + 255) / 256), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_chain_elem<VT, XT>), dim3((A.n + 255) / 256), dim3(256), 0, st, a,
+                           (const XT *)s.prod);
         return hipGetLastError();
     }
     switch (variant) {

@@ -2,6 +2,7 @@
 // programs derived from its root list (internal).
 #pragma once
 
+#include <memory>
 #include <vector>
 
 #include "host_core.h"
@@ -39,6 +40,9 @@ struct pp_poly_s {
     std::vector<double> theta_re, theta_im;  // raw harmonic Ritz values
     int breakdown = 0;
     std::vector<ppg::Step> prog_p, prog_phi, prog_pi;
+    // Composite (double) polynomial phi2(phi1(A)): this object holds phi2's
+    // roots (in the variable of phi1(A)) and inner is phi1 (section 6).
+    std::shared_ptr<const pp_poly_s> inner;
     void finalize() {
         id = ppg::next_poly_id();
         prog_p = ppg::program_p(plan.units);

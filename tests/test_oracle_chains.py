@@ -7,7 +7,7 @@ import scipy.sparse as sp
 
 from oracle import chains, roots
 from oracle.chains import spmv_count_p, spmv_count_phi
-from workloads import convdiff2d, start_vector
+from workloads import convdiff2d, diagonal, start_vector
 
 
 def _units_from(theta):
@@ -128,3 +128,60 @@ def test_pair_factor_identity():
         A = sp.csr_matrix(np.array([[z]]))
         pi = chains.apply_pi(A, [(1, a, b)], np.array([1.0]))
         assert abs(pi[0] - rhs) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# double polynomial (section 6)
+# ---------------------------------------------------------------------------
+
+def test_double_polynomial_diagonal_closed_form():
+    # on a diagonal matrix phi2(phi1(A)) v and p(A) v = p1(A) p2(phi1(A)) v act
+    # per eigenvalue: phi(l) = 1 - prod(1 - phi1(l)/t2) with
+    # phi1(l) = 1 - prod(1 - l/t1), and p(l) = phi(l) / l; evaluated in mpmath
+    import mpmath as mp
+
+    from oracle.chains import apply_p_double, apply_phi_double, apply_pi_double
+
+    mp.mp.dps = 40
+    lam = np.linspace(1.0, 10.0, 40)
+    A = diagonal(lam).to_scipy()
+    inner = [(chains.REAL, 9.0, 0.0), (chains.PAIR, 5.0, 2.0), (chains.REAL, 1.5, 0.0)]
+    outer = [(chains.REAL, 0.9, 0.0), (chains.PAIR, 0.6, 0.3), (chains.REAL, 0.2, 0.0)]
+
+    def pi_of(units, z):
+        out = mp.mpf(1)
+        for k, a, b in units:
+            if k == chains.REAL:
+                out *= 1 - z / a
+            else:
+                out *= (1 - z / mp.mpc(a, b)) * (1 - z / mp.mpc(a, -b))
+        return out
+
+    v = np.ones(lam.size)
+    phi_ref, p_ref = [], []
+    for l in lam:
+        mu = 1 - pi_of(inner, mp.mpf(l))
+        ph = 1 - pi_of(outer, mu)
+        phi_ref.append(float(mp.re(ph)))
+        p_ref.append(float(mp.re(ph / l)))
+    phi_ref, p_ref = np.array(phi_ref), np.array(p_ref)
+    assert np.max(np.abs(apply_phi_double(A, inner, outer, v) - phi_ref)) <= 1e-13 * np.max(np.abs(phi_ref))
+    assert np.max(np.abs(apply_pi_double(A, inner, outer, v) - (1 - phi_ref))) <= 1e-13
+    assert np.max(np.abs(apply_p_double(A, inner, outer, v) - p_ref)) <= 1e-13 * np.max(np.abs(p_ref))
+
+
+def test_double_setup_outer_roots_are_eigenvalues_of_phi1():
+    # with d2 = n the Krylov space of phi1(A) is complete: the outer roots are
+    # the eigenvalues phi1(l_i) of phi1(A) (closed form on a diagonal matrix)
+    lam = np.array([1.0, 1.7, 2.2, 3.1, 4.0, 4.6, 5.5, 6.3, 7.0, 8.2, 9.1, 10.0])
+    A = diagonal(lam).to_scipy()
+    v0 = start_vector(lam.size, 2)
+    P1 = roots.setup(A, v0, 4, orth="cgs2")
+    P2 = roots.setup_double(A, P1.units, v0, lam.size, add_roots=False, orth="cgs2")
+    pi1 = np.ones(lam.size, dtype=complex)
+    for z in P1.roots():
+        pi1 *= 1 - lam / z
+    want = np.sort((1 - pi1).real)
+    got = np.sort(P2.theta.real)
+    assert P2.breakdown and np.max(np.abs(P2.theta.imag)) <= 1e-10
+    assert np.max(np.abs(got - want)) <= 1e-8 * np.max(np.abs(want))

@@ -294,3 +294,40 @@ def test_chpoly_needs_fewer_mvps_at_low_degree():
     _, ipp = solver.pp_gmres(A, b, P.units, m=50, tol=1e-10, max_cycles=5000, orth="cgs2", setup_mvps=P.d,
                              stall_cycles=0)
     assert ipp.status == solver.OK and ich.mvps < ipp.mvps / 2
+
+
+def test_biharmonic_condition_number_example3(golden_dir):
+    # Example 3: the 13-point reading of the operator gives the printed
+    # condition number 8.2e7 (the 9-point reading without u_xxyy gives 5.3e7)
+    import os
+
+    from workloads import biharmonic2d
+
+    with open(os.path.join(golden_dir, "example3_biharmonic.txt")) as fh:
+        cond_paper = float(next(l for l in fh if "condition_number" in l).split()[-1])
+    A = biharmonic2d(200).to_scipy()
+    assert A.shape[0] == 40000 and np.median(np.diff(A.indptr)) == 13
+    smax = sla.svds(A, k=1, which="LM", return_singular_vectors=False)[0]
+    lu = sla.splu(A.tocsc())
+    x = np.random.default_rng(0).standard_normal(A.shape[0])
+    for _ in range(60):  # inverse iteration on A^T A for the smallest singular value
+        z = lu.solve(lu.solve(x), trans="T")
+        nz = np.linalg.norm(z)
+        x = z / nz
+    cond = smax * np.sqrt(nz)
+    assert abs(cond - cond_paper) <= 0.02 * cond_paper, cond
+
+
+def test_double_polynomial_solve_small():
+    # PP-GMRES with phi2(phi1(A)) solves A x = b (x = p1(A) p2(phi1(A)) z)
+    from workloads import biharmonic2d
+
+    A = biharmonic2d(30).to_scipy()
+    n = A.shape[0]
+    b, v0 = rhs(n, 1), start_vector(n, 2)
+    P1 = roots.setup(A, v0, 6, orth="cgs2")
+    P2 = roots.setup_double(A, P1.units, v0, 6, orth="cgs2")
+    x, info = solver.pp_gmres(A, b, P2.units, m=50, tol=1e-10, orth="cgs2", inner_units=P1.units)
+    assert info.status == solver.OK
+    assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - sla.spsolve(A.tocsc(), b)) <= 1e-4 * np.linalg.norm(x)

@@ -12,6 +12,7 @@ from .generators import (  # noqa: F401
     convdiff2d_colscaled,
     convdiff3d,
     randsparse,
+    biharmonic2d,
     diagonal,
     diag_example7,
     diag_squares,

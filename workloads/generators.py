@@ -141,6 +141,29 @@ def convdiff3d(N: int, cx: float = 0.0, cy: float = 0.0, cz: float = 0.0, gamma:
     return CSR(N**3, rowptr, colind, val)
 
 
+def biharmonic2d(N: int = 200) -> CSR:
+    """Example 3's matrix: -(u_xxxx + 2 u_xxyy + u_yyyy) + u_xxx on the unit
+    square, N x N interior grid, h = 1/(N+1), u = 0 outside the grid (the
+    stencil is cut at the boundary), scaled by h^4, rows lexicographic with
+    x fastest. Centred differences: the 13-point biharmonic stencil and
+    (-u_{i-2} + 2u_{i-1} - 2u_{i+1} + u_{i+2}) / (2h^3) for u_xxx.
+    The mixed term is the reading that gives the paper's 13 nonzeros per row
+    and its condition number 8.2e7 at N = 200 (the printed equation shows
+    only u_xxxx and u_yyyy)."""
+    import scipy.sparse as sp
+
+    h = 1.0 / (N + 1)
+    e = np.ones(N)
+    I = sp.identity(N, format="csr")
+    D4 = sp.diags([e[2:], -4 * e[1:], 6 * e, -4 * e[1:], e[2:]], [-2, -1, 0, 1, 2], format="csr")
+    D2 = sp.diags([e[1:], -2 * e, e[1:]], [-1, 0, 1], format="csr")
+    D3 = sp.diags([-e[2:], 2 * e[1:], -2 * e[1:], e[2:]], [-2, -1, 1, 2], format="csr") * 0.5
+    A = (-(sp.kron(I, D4) + sp.kron(D4, I) + 2.0 * sp.kron(D2, D2)) + h * sp.kron(I, D3)).tocsr()
+    A.sort_indices()
+    return CSR(n=N * N, rowptr=A.indptr.astype(np.int32), colind=A.indices.astype(np.int32),
+               val=A.data.astype(np.float64))
+
+
 def randsparse(n: int, k: int = 16, seed: int = 7, dominance: float = 1.05) -> CSR:
     """Random nonsymmetric sparse matrix with k off-diagonals per row.
 
