@@ -52,6 +52,12 @@ struct pp_matrix_s {
     // sliced-ELL copy
     int32_t *sptr = nullptr, *scol = nullptr, *sperm = nullptr;
     int16_t *sdel = nullptr;
+    // diagonal-format copy (few diagonals only): values diagonal-major, and
+    // for each slot the CSR entry it holds (-1: zero padding)
+    std::vector<int> h_doff;
+    double *dval64 = nullptr;
+    float *dval32 = nullptr;
+    int32_t *dperm = nullptr;
     // right scaling A diag(s) (composition with a diagonal preconditioner):
     // the chains, the setup and the residual use the scaled values val_own;
     // pp_solve returns x = diag(s) x~
@@ -110,6 +116,10 @@ struct pp_matrix_s {
         d.sval64 = sval64;
         d.sval32 = sval32;
         d.nslices = nslices;
+        d.doff.nd = (int)h_doff.size();
+        for (int k = 0; k < kMaxDiag; ++k) d.doff.off[k] = k < d.doff.nd ? h_doff[k] : 0;
+        d.dval64 = dval64;
+        d.dval32 = dval32;
         for (int p = 0; p < 3; ++p) {
             d.tileB8[p] = tileB8[p];
             d.ntileB8[p] = ntileB8[p];
@@ -198,6 +208,9 @@ struct pp_matrix_s {
         dev_free(scol);
         dev_free(sperm);
         dev_free(sdel);
+        dev_free(dval64);
+        dev_free(dval32);
+        dev_free(dperm);
         dev_free(val_own);
         dev_free(scale);
         dev_free(sval64);
@@ -333,10 +346,14 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
     } guard{e0, e1};
     double best = 1e30;
     int bv = CV_TILE8, br = 1;
-    const int reps = 5;
+    // every (variant, remap) is timed over `reps` launches in two rounds and
+    // keeps its faster round, so one noisy trial does not decide the pick
+    const int reps = 10;
+    for (int round = 0; round < 2; ++round)
     for (int v = 0; v < CV_COUNT; ++v) {
         if (v == CV_PERSIST || ((v == CV_SELL || v == CV_SELLT || v == CV_SELL2 || v == CV_SELL4) && A->nslices == 0) ||
-            ((v == CV_SELLD || v == CV_SELLD4) && !A->sdel) || (v == CV_TILEB8 && A->ntileB8[prec] == 0) ||
+            ((v == CV_SELLD || v == CV_SELLD4) && !A->sdel) || ((v == CV_DIA || v == CV_DIA4) && A->h_doff.empty()) ||
+            (v == CV_TILEB8 && A->ntileB8[prec] == 0) ||
             (v == CV_TILEB16 && A->ntileB16[prec] == 0))
             continue;
         for (int r = 0; r < 2; ++r) {
@@ -764,6 +781,51 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
             }
         }
     }
+    // diagonal format when the entries lie on at most kMaxDiag diagonals and
+    // the padding stays under a quarter of nnz
+    if (nnz > 0) {
+        std::vector<int> offs;
+        bool few = true;
+        for (int64_t r = 0; r < n && few; ++r)
+            for (int k = rp[r]; k < rp[r + 1]; ++k) {
+                const int off = ci[k] - (int)r;
+                if (std::find(offs.begin(), offs.end(), off) == offs.end()) {
+                    offs.push_back(off);
+                    if ((int)offs.size() > kMaxDiag) {
+                        few = false;
+                        break;
+                    }
+                }
+            }
+        const long nblk = ((long)n + 255) / 256;
+        const long slots = (long)offs.size() * nblk * 256;
+        if (few && slots <= (long)nnz + nnz / 4 + 64 && slots < (1L << 31)) {
+            std::sort(offs.begin(), offs.end());
+            std::vector<int32_t> dp(slots, -1);
+            for (int64_t r = 0; r < n; ++r)
+                for (int k = rp[r]; k < rp[r + 1]; ++k) {
+                    const int d = (int)(std::lower_bound(offs.begin(), offs.end(), ci[k] - (int)r) - offs.begin());
+                    dp[((r >> 8) * (long)offs.size() + d) * 256 + (r & 255)] = k;  // a repeat keeps its last entry
+                }
+            // repeated entries of one (row, column) cannot share a slot: no diagonal format then
+            long used = 0;
+            for (long q = 0; q < slots; ++q) used += dp[q] >= 0;
+            if (used == nnz) {
+                if ((s = dev_alloc(&A->dval64, (size_t)slots)) != PP_OK ||
+                    (s = dev_alloc(&A->dval32, (size_t)slots)) != PP_OK ||
+                    (s = dev_alloc(&A->dperm, (size_t)slots)) != PP_OK)
+                    return fail(s);
+                if (hipMemcpyAsync(A->dperm, dp.data(), sizeof(int32_t) * slots, hipMemcpyHostToDevice, st) !=
+                        hipSuccess ||
+                    launch_sell_values(slots, A->dperm, val, A->dval64, A->dval32, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess) {
+                    set_error("pp_matrix_create: diagonal-format upload failed");
+                    return fail(PP_EDEVICE);
+                }
+                A->h_doff = offs;
+            }
+        }
+    }
     {
         // tuning program of the persistent kernel: 8 sparse products P0 -> P1 -> P0 ...
         std::vector<PStep> h(8);
@@ -790,6 +852,9 @@ pp_status refresh_values(pp_matrix A, const double *val, hipStream_t st) {
     A->val = val;
     HIP_TRY(launch_val_to_f32(A->nnz, val, A->val32, st));
     if (A->nslices > 0) HIP_TRY(launch_sell_values(A->npad, A->sperm, val, A->sval64, A->sval32, st));
+    if (!A->h_doff.empty())
+        HIP_TRY(launch_sell_values((long)A->h_doff.size() * (((long)A->n + 255) / 256) * 256, A->dperm, val,
+                                   A->dval64, A->dval32, st));
     return PP_OK;
 }
 
@@ -910,6 +975,10 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
         if (((variant == CV_SELL || variant == CV_SELLT || variant == CV_SELL2 || variant == CV_SELL4) && A->nslices == 0) ||
             ((variant == CV_SELLD || variant == CV_SELLD4) && !A->sdel)) {
             set_error("pp_matrix_set_variant: no sliced-ELL copy for this matrix (too much padding)");
+            return PP_EINVAL;
+        }
+        if ((variant == CV_DIA || variant == CV_DIA4) && A->h_doff.empty()) {
+            set_error("pp_matrix_set_variant: no diagonal-format copy for this matrix (too many diagonals)");
             return PP_EINVAL;
         }
         if (variant == CV_TILEB8) PP_TRY(build_round_plan(A, prec, 8, &A->tileB8[prec], &A->ntileB8[prec], 0));

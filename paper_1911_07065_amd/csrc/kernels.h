@@ -38,7 +38,9 @@ enum ChainVariant : int {
     CV_SELL4 = 21,    // sell64 with 4 slices per wave
     CV_SELLD = 22,    // sell64 with 16-bit column offsets (banded matrices only)
     CV_SELLD4 = 23,   // same, 4 slices per wave
-    CV_COUNT = 24
+    CV_DIA = 24,      // diagonal format (matrices on few diagonals): 2 rows per lane
+    CV_DIA4 = 25,     // same, 1 row per lane
+    CV_COUNT = 26
 };
 
 // A chain step as the persistent kernel reads it from device memory.
@@ -64,6 +66,13 @@ struct StepPtrs {
     double a0, a1, a2, b0, b1;
     // spmv == 0: the product term a0 * prod[r] comes from this vector (null: none)
     const void *prod = nullptr;
+};
+
+// Diagonals of the diagonal format, passed by value (uniform per launch).
+constexpr int kMaxDiag = 32;
+struct DiaOffsets {
+    int nd;               // number of diagonals (0: no diagonal-format copy)
+    int off[kMaxDiag];    // column - row of each diagonal, ascending
 };
 
 // CSR in the form the kernels read.
@@ -92,6 +101,13 @@ struct DevCSR {
     const double *sval64;
     const float *sval32;
     int nslices;
+    // diagonal-format copy (absent if doff.nd == 0): the entry of row i on
+    // diagonal d is dval[((i / 256) nd + d) 256 + i % 256] (0 where the
+    // diagonal leaves the matrix or holds no stored entry), its column
+    // i + doff.off[d]; ceil(n / 256) blocks
+    DiaOffsets doff;
+    const double *dval64;
+    const float *dval32;
     int variant[3];      // chain variant per precision
     int remap[3];        // 1: keep neighbouring workgroups on one XCD
 };

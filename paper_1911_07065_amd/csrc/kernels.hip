@@ -544,6 +544,100 @@ __global__ __launch_bounds__(256) void k_chain_sell(ChainArgs<VT, XT> a, const i
         if (w0 + q < nslices) sell_slice<VT, XT, NT, IT>(a, sptr, sidx, sval, w0 + q, lane);
 }
 
+// Diagonal format: each lane owns RPT rows (256 apart); the diagonals are
+// consumed DU at a time with every load of a block issued before the first
+// is used. Diagonal positions past nd re-read the last diagonal and columns
+// outside [0, n) read a clamped column; both carry a zero value or are
+// dropped by a select. Values are stored per 256-row block, diagonal after
+// diagonal (entry of row r on diagonal d at ((r/256) nd + d) 256 + r%256),
+// so a workgroup streams contiguous memory; the gather is coalesced too:
+// lane i reads x[i + off].
+template <typename VT, typename XT, int RPT, int DU>
+__global__ __launch_bounds__(256) void k_chain_dia(ChainArgs<VT, XT> a, const VT *__restrict__ dval, DiaOffsets doff,
+                                                   int nblocks, int remap) {
+    using AT = typename Arith<XT>::T;
+    const int blk = remap_tile(blockIdx.x, nblocks, remap);
+    const int base = blk * 256 * RPT + (int)threadIdx.x;
+    const int n = a.n, nd = doff.nd;
+    // 32-bit index math: n and the number of stored slots are below 2^31
+    int rr[RPT], vb[RPT];
+    AT s[RPT];
+    RowPre<AT> pre[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = base + q * 256;
+        rr[q] = r < n ? r : n - 1;
+        vb[q] = (rr[q] >> 8) * nd * 256 + (rr[q] & 255);
+        s[q] = AT(0);
+        if (r < n) pre[q] = row_prefetch(a, r);
+    }
+    for (int d0 = 0; d0 < nd; d0 += DU) {
+        VT v[DU][RPT];
+        AT x[DU][RPT];
+#pragma unroll
+        for (int u = 0; u < DU; ++u) {
+            const int d = min(d0 + u, nd - 1);
+            const int off = doff.off[d];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int c = min(max(rr[q] + off, 0), n - 1);
+                v[u][q] = __builtin_nontemporal_load(dval + vb[q] + d * 256);
+                x[u][q] = ldx(a.in, c);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < DU; ++u)
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const AT t = (AT)v[u][q] * x[u][q];
+                s[q] += (d0 + u < nd) ? t : AT(0);
+            }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = base + q * 256;
+        if (r < n) row_finish(a, r, s[q], pre[q]);
+    }
+}
+
+// Diagonal format with the diagonal count ND known at compile time (common
+// stencils: 3, 5, 7, 9, 13, 19, 27): one row per lane, all 2 ND loads issued
+// together, no clamp of the diagonal index and no select.
+template <typename VT, typename XT, int ND>
+__global__ __launch_bounds__(256) void k_chain_dia_nd(ChainArgs<VT, XT> a, const VT *__restrict__ dval, DiaOffsets doff,
+                                                      int nblocks, int remap) {
+    using AT = typename Arith<XT>::T;
+    const int blk = remap_tile(blockIdx.x, nblocks, remap);
+    const int r = blk * 256 + (int)threadIdx.x;
+    const int n = a.n;
+    const int rr = r < n ? r : n - 1;
+    const int vb = (rr >> 8) * ND * 256 + (rr & 255);
+    RowPre<AT> pre;
+    if (r < n) pre = row_prefetch(a, r);
+    VT v[ND];
+    AT x[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        v[d] = __builtin_nontemporal_load(dval + vb + d * 256);
+        x[d] = ldx(a.in, min(max(rr + doff.off[d], 0), n - 1));
+    }
+    AT s = AT(0);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) s += (AT)v[d] * x[d];
+    if (r < n) row_finish(a, r, s, pre);
+}
+
+template <typename VT>
+const VT *dia_vals(const DevCSR &A);
+template <>
+const double *dia_vals<double>(const DevCSR &A) {
+    return A.dval64;
+}
+template <>
+const float *dia_vals<float>(const DevCSR &A) {
+    return A.dval32;
+}
+
 template <typename VT>
 const VT *sell_vals(const DevCSR &A);
 template <>
@@ -648,6 +742,36 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int v
             return vk_launch<VT, XT, 8, 4, 1>(a, remap, st);
         case CV_VK16x2x2:
             return vk_launch<VT, XT, 16, 2, 2>(a, remap, st);
+        case CV_DIA:
+        case CV_DIA4: {
+            if (A.doff.nd <= 0) return hipErrorInvalidValue;
+            const int rpt = variant == CV_DIA ? 2 : 1;
+            const int nb = (int)((A.n + 256L * rpt - 1) / (256L * rpt));
+            if (rpt == 2) {
+                hipLaunchKernelGGL((k_chain_dia<VT, XT, 2, 8>), dim3(nb), dim3(256), 0, st, a, dia_vals<VT>(A), A.doff,
+                                   nb, remap);
+                return hipGetLastError();
+            }
+#define PP_DIA_ND(K)                                                                                              \
+    case K:                                                                                                       \
+        hipLaunchKernelGGL((k_chain_dia_nd<VT, XT, K>), dim3(nb), dim3(256), 0, st, a, dia_vals<VT>(A), A.doff, nb, \
+                           remap);                                                                                \
+        break;
+            switch (A.doff.nd) {
+                PP_DIA_ND(3)
+                PP_DIA_ND(5)
+                PP_DIA_ND(7)
+                PP_DIA_ND(9)
+                PP_DIA_ND(13)
+                PP_DIA_ND(19)
+                PP_DIA_ND(27)
+                default:
+                    hipLaunchKernelGGL((k_chain_dia<VT, XT, 1, 8>), dim3(nb), dim3(256), 0, st, a, dia_vals<VT>(A),
+                                       A.doff, nb, remap);
+            }
+#undef PP_DIA_ND
+            return hipGetLastError();
+        }
         case CV_SELLD:
         case CV_SELLD4: {
             if (A.nslices == 0 || !A.sdel) return hipErrorInvalidValue;
@@ -1451,7 +1575,8 @@ const char *chain_variant_name(int v) {
     static const char *names[CV_COUNT] = {"tile8x1", "tile16x2", "vec1x4",  "vec4x4",    "vec8x2",
                                           "vec8x4",  "vec16x2",  "vec16x4", "vec32x2",   "tilev8x1",
                                           "tilev16x2", "vk2x4x4", "vk4x4x2", "vk8x4x1", "vk16x2x2", "persist8",
-                                          "tileb8x1", "tileb16x2", "sell64", "sell64t", "sell64x2", "sell64x4", "sell64d16", "sell64d16x4"};
+                                          "tileb8x1", "tileb16x2", "sell64", "sell64t", "sell64x2", "sell64x4", "sell64d16", "sell64d16x4",
+                                              "dia2",   "dia1"};
     return (v >= 0 && v < CV_COUNT) ? names[v] : "?";
 }
 

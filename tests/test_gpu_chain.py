@@ -7,7 +7,7 @@ import torch
 
 from oracle import chains, roots as oroots
 from oracle.mixed import apply_p_low, apply_phi_low
-from workloads import CSR, convdiff2d, convdiff3d, randsparse, start_vector, rhs
+from workloads import CSR, convdiff2d, convdiff3d, diagonal, randsparse, start_vector, rhs
 from gpu_util import say, dev, host, relerr
 
 pytestmark = pytest.mark.gpu
@@ -150,7 +150,7 @@ def test_bad_arguments_rejected(pp):
         pp.Matrix(np.array([0, 2, 1], dtype=np.int32), np.array([0, 1], dtype=np.int32), np.ones(2))  # rowptr
 
 
-@pytest.mark.parametrize("variant", range(24))
+@pytest.mark.parametrize("variant", range(26))
 def test_every_chain_variant_matches_oracle(pp, variant):
     # each kernel variant the autotuner may pick, with and without the XCD order
     for name in ["ragged_5000", "randsparse_20000", "convdiff3d_20"]:
@@ -169,14 +169,47 @@ def test_every_chain_variant_matches_oracle(pp, variant):
                 M.set_variant("fp64", variant, remap)
                 M.set_variant("fp32", variant, remap)
             except Exception as exc:
-                # the sliced-ELL copy is only built when its padding is small
-                assert "sliced-ELL" in str(exc) and name == "ragged_5000", exc
+                # the sliced-ELL copy is only built when its padding is small,
+                # the diagonal format only for matrices on few diagonals
+                assert ("sliced-ELL" in str(exc) and name == "ragged_5000") or \
+                    ("diagonal-format" in str(exc) and name != "convdiff3d_20"), exc
                 continue
             assert relerr(host(pp.apply(poly, M, dev(v), "p")), ref_p) <= 1e-12
             assert relerr(host(pp.apply(poly, M, dev(v), "phi")), ref_phi) <= 1e-12
             got32 = host(pp.apply(poly, M, dev(v, torch.float32), "p"))
             delta = relerr(apply_p_low(A32, P.units, v.astype(np.float32)), ref_p)
             assert relerr(got32, ref_p) <= 10 * delta + 1e-6
+
+
+@pytest.mark.parametrize("case", ["diagonal_1000", "tridiag_1000", "convdiff2d_37", "convdiff3d_9"])
+def test_diagonal_format_edge_cases(pp, case):
+    # one diagonal, a ragged tail of rows, zero padding where diagonals
+    # leave the grid: both diagonal-format variants against the oracle
+    import scipy.sparse as sp
+
+    from workloads.generators import CSR
+
+    if case == "diagonal_1000":
+        csr = diagonal(np.linspace(1.0, 3.0, 1000))
+    elif case == "tridiag_1000":
+        T = sp.diags([np.full(999, -1.0), np.full(1000, 2.5), np.full(999, -1.2)], [-1, 0, 1], format="csr")
+        csr = CSR(n=1000, rowptr=T.indptr.astype(np.int32), colind=T.indices.astype(np.int32),
+                  val=T.data.astype(np.float64))
+    elif case == "convdiff2d_37":
+        csr = convdiff2d(37, 3.0)
+    else:
+        csr = convdiff3d(9, 1.0, 2.0, 3.0)
+    A = csr.to_scipy()
+    P = oroots.setup(A, start_vector(csr.n, 2), 6)
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.poly_from_roots(P.roots(), keep_order=True)
+    v = rhs(csr.n, 5)
+    for variant in (24, 25):
+        for remap in (0, 1):
+            say("diagonal format", case, pp.chain_variant_name(variant), remap)
+            M.set_variant("fp64", variant, remap)
+            assert relerr(host(pp.apply(poly, M, dev(v), "p")), chains.apply_p(A, P.units, v)) <= 1e-12
+            assert relerr(host(pp.apply(poly, M, dev(v), "phi")), chains.apply_phi(A, P.units, v)) <= 1e-12
 
 
 def test_autotuner_picks_a_valid_variant(pp):
@@ -186,7 +219,7 @@ def test_autotuner_picks_a_valid_variant(pp):
     assert M.variant("fp32")[0] is None  # nothing tuned or set yet
     for prec in ("fp64", "fp32", "bf16"):
         name, remap, us = M.tune(prec)
-        assert name in [pp.chain_variant_name(v) for v in range(24)] and remap in (0, 1) and us > 0
+        assert name in [pp.chain_variant_name(v) for v in range(26)] and remap in (0, 1) and us > 0
         assert M.variant(prec) == (name, remap, us)
     M.set_variant("fp32", 3, 0)
     assert M.variant("fp32") == (pp.chain_variant_name(3), 0, 0.0)
