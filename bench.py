@@ -11,10 +11,11 @@ chains and Krylov vectors in FP32 inside FP64 iterative refinement. The
 plain FP64 form is timed beside it. Inputs are resident in HBM before the
 timed region. Prints one JSON line.
 
-Two more legs are reported beside the headline (skip with --no-extras):
-differentiation through the solve on a 1024^2 2-D system (forward +
-adjoint) and the batched solve of 256 systems x 4 right-hand sides against
-a loop of single solves.
+More legs are reported beside the headline (skip with --no-extras): the
+random sparse workload (n = 1e6) in FP64/FP32/BF16, differentiation
+through the solve on a 1024^2 2-D system (forward + adjoint), the batched
+solve of 256 systems x 4 right-hand sides against loops of single solves,
+and the paper's own synthetic rows run beside its printed figures.
 """
 
 import argparse
@@ -157,6 +158,109 @@ def adjoint_leg(pp, torch, np):
             "time_s": round(t, 6), "dL_dtheta": g, "norm_dL_db": gb}
 
 
+def random_sparse_leg(pp, torch, np, reps=5):
+    """Random sparse workload: n = 1e6, 16 distinct off-diagonal columns per
+    row plus the diagonal, diagonally dominant, degree 100 with added roots,
+    GMRES(30), tol 1e-8. Time-to-solution (setup included) in FP64, FP32 and
+    BF16 storage, and p(A)v per chain launch with its CSR algorithmic rate."""
+    from workloads import randsparse, rhs, start_vector
+
+    csr = randsparse(1_000_000, 16, seed=7)
+    n, nnz = csr.n, csr.nnz
+    A = csr.to_scipy()
+    b = rhs(n, 1)
+    M = pp.Matrix.from_csr(csr)
+    bd = torch.as_tensor(b, device="cuda")
+    v0 = torch.as_tensor(start_vector(n, 2), device="cuda")
+    out = {"workload": f"random sparse n={n}, nnz={nnz} (16 random columns + diagonal, dominance 1.05), "
+                       "PP(100+added)-GMRES(30) to 1e-8, setup included"}
+    stream = torch.cuda.current_stream()
+    poly = None
+    for inner in ("fp64", "fp32", "bf16"):
+        poly = pp.setup(M, v0, 100)
+        pp.solve(poly, M, bd, tol=1e-8, m=30, inner=inner)  # warm-up (tuning)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        poly = pp.setup(M, v0, 100)
+        x, info = pp.solve(poly, M, bd, tol=1e-8, m=30, inner=inner)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rel = float(np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b))
+        out[f"time_to_solution_s_{inner}"] = round(t, 6)
+        out[f"relres_{inner}"] = rel
+        out[f"cycles_{inner}"] = info["cycles"]
+        log("random sparse", inner, f"{t * 1e3:.1f} ms", "relres", rel, "cycles", info["cycles"])
+    out["d_eff"] = poly.d_eff
+    for prec, dt, sv, sx in (("fp32", torch.float32, 4, 4), ("fp64", torch.float64, 8, 8),
+                             ("bf16", torch.bfloat16, 4, 2)):
+        v = bd.to(dt)
+        y = torch.empty_like(v)
+        for _ in range(2):
+            pp.apply(poly, M, v, "phi", out=y)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            pp.apply(poly, M, v, "phi", out=y)
+        e1.record(stream)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps / poly.d_eff
+        by = step_bytes(n, nnz, sv, sx)
+        out[f"chain_step_us_{prec}"] = round(us, 3)
+        out[f"chain_step_GBps_{prec}"] = round(by / (us * 1e-6) / 1e9, 1)
+        out[f"chain_step_frac_{prec}"] = round(by / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)
+        out[f"chain_variant_{prec}"] = M.variant(prec)[0]
+        log("random sparse phi step", prec, f"{us:.2f} us", out[f"chain_step_GBps_{prec}"], "GB/s")
+    return out
+
+
+def paper_context_leg(pp, torch, np):
+    """The paper's synthetic rows run on the GPU beside its printed counts and
+    times (MATLAB on an Intel i7-6700, FP64, MGS): Table 3.6 (2-D
+    convection-diffusion, n = 40000, PP(50)-GMRES(50), alpha = beta = gamma = 0),
+    Table 4.1 (diag(i^2/n), n = 20000, d = 256, GMRES(50), tol 1e-10) and
+    Table 3.4 / Example 13 (biharmonic, n = 40000, d = 200 and the 40 x 40
+    double polynomial; true residual 2e-10 for the paper's shortcut 1e-10).
+    FP64 throughout."""
+    from workloads import biharmonic2d, convdiff2d, diag_squares, rhs, start_vector
+
+    rows = []
+
+    def run(name, csr, d, tol, paper, double=None):
+        M = pp.Matrix.from_csr(csr)
+        bd = torch.as_tensor(rhs(csr.n, 1), device="cuda")
+        v0 = torch.as_tensor(start_vector(csr.n, 2), device="cuda")
+        for timed in (False, True):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = pp.setup(M, v0, d)
+            setup_mv, setup_dots = p.setup_info["mvps"], p.setup_info["dots"]
+            if double:
+                p2 = pp.setup_double(M, p, v0, double)
+                setup_mv += p2.setup_info["mvps"]
+                setup_dots += p2.setup_info["dots"]
+                p = p2
+            x, info = pp.solve(p, M, bd, tol=tol, m=50, max_cycles=20000, inner="fp64", stall_cycles=0)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+        rows.append({"case": name, "cycles": info["cycles"], "mvps": info["mvps"] + setup_mv,
+                     "dots": info["dots"] + setup_dots, "time_s": round(t, 4), "converged": info["converged"],
+                     "paper": paper})
+        log("paper context", rows[-1])
+
+    run("Table 3.6 row 1: 2-D conv.-diff. n=40000, PP(50)-GMRES(50), tol 1e-8", convdiff2d(200, 0.0), 50, 1e-8,
+        {"mvps": 1051, "time_s": 0.95})
+    run("Table 4.1: diag(i^2/n) n=20000, PP(256)-GMRES(50), tol 1e-10", diag_squares(20000), 256, 1e-10,
+        {"cycles": 43, "mvps": 542000, "dots": 89000, "time_s": 40.9})
+    bh = biharmonic2d(200)
+    run("Table 3.4: biharmonic n=40000, PP(200)-GMRES(50), true residual 2e-10", bh, 200, 2e-10,
+        {"cycles": 11, "mvps": 105000, "dots": 33900, "time_s": 54.9})
+    run("Table 6.1: biharmonic n=40000, double 40x40, GMRES(50), true residual 2e-10", bh, 40, 2e-10,
+        {"cycles": 1, "mvps": 75300, "dots": 2760, "time_s": 35.8}, double=40)
+    return {"hardware_of_paper": "MATLAB, Dell Optiplex, Intel i7-6700, FP64, modified Gram-Schmidt",
+            "ours": "one MI355X, FP64, CGS2 (dots count both passes)", "rows": rows}
+
+
 def batched_leg(pp, torch, np, loop_every=16):
     """Batched solve: 256 2-D convection-diffusion systems (sides U{64..512},
     coefficient U[0,50)), 4 right-hand sides each, degree 20, GMRES(50),
@@ -180,27 +284,33 @@ def batched_leg(pp, torch, np, loop_every=16):
     ok = all(i["converged"] for i in infos)
     worst = max(i["relres"] for i in infos)
     log("batched", f"{t_batch:.3f} s", "converged", ok, "worst relres", worst)
-    t_loop, sub = 0.0, list(range(0, len(csrs), loop_every))
+    t_loop, t_loop64, sub = 0.0, 0.0, list(range(0, len(csrs), loop_every))
     for s in sub:
         M = pp.Matrix.from_csr(csrs[s])
         M.tune("fp32")
         M.tune("fp64")
         bs = [torch.as_tensor(brs[s][r], device="cuda") for r in range(4)]
         v0s = torch.as_tensor(start_vector(csrs[s].n, specs[s][3]), device="cuda")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        poly = pp.setup(M, v0s, 20)
-        for r in range(4):
-            pp.solve(poly, M, bs[r], tol=1e-8, m=50, inner="fp32")
-        torch.cuda.synchronize()
-        t_loop += time.perf_counter() - t1
+        for inner in ("fp32", "fp64"):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            poly = pp.setup(M, v0s, 20)
+            for r in range(4):
+                pp.solve(poly, M, bs[r], tol=1e-8, m=50, inner=inner)
+            torch.cuda.synchronize()
+            if inner == "fp32":
+                t_loop += time.perf_counter() - t1
+            else:
+                t_loop64 += time.perf_counter() - t1
     t_loop *= len(csrs) / len(sub)
-    log("loop of single solves (scaled)", f"{t_loop:.3f} s")
+    t_loop64 *= len(csrs) / len(sub)
+    log("loop of single solves (scaled)", f"{t_loop:.3f} s", "plain FP64", f"{t_loop64:.3f} s")
     return {"workload": f"256 x 2-D convection-diffusion (sum n={B.n}, nnz={B.nnz}), 4 RHS each, PP(20)-GMRES(50) "
                         "to 1e-8, FP32 inner / FP64 outer, setup included",
             "time_s": round(t_batch, 6), "all_converged": ok, "worst_relres": worst,
-            "loop_time_s": round(t_loop, 6), "loop_sample": f"every {loop_every}th system, scaled",
-            "speedup_vs_loop": round(t_loop / t_batch, 3)}
+            "loop_time_s": round(t_loop, 6), "loop_fp64_time_s": round(t_loop64, 6),
+            "loop_sample": f"every {loop_every}th system, scaled, handles made and tuned outside the timing",
+            "speedup_vs_loop": round(t_loop / t_batch, 3), "speedup_vs_fp64_loop": round(t_loop64 / t_batch, 3)}
 
 
 def cpu_baseline(csr, b, v0, d, m, gpu_iters, gpu_cycles, d_eff):
@@ -382,8 +492,10 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        extras["random_sparse"] = random_sparse_leg(pp, torch, np)
         extras["adjoint"] = adjoint_leg(pp, torch, np)
         extras["batched"] = batched_leg(pp, torch, np)
+        extras["paper_context"] = paper_context_leg(pp, torch, np)
 
     cpu = None
     if not args.no_cpu:

@@ -86,6 +86,10 @@ typedef struct {
                             the current residual, and uses it for that cycle's phi and p; the
                             polynomial argument of pp_solve may then be NULL. 0: off */
     int new_poly_add;    /* ChPoly: add roots for stability (Algorithm 2) */
+    int graphs;          /* pp_batch_solve: 1 = capture each Arnoldi step's device work (chain,
+                            Gram-Schmidt, flag and Hessenberg copies) once per step index and
+                            precision into a HIP graph and replay it in later cycles; 0 = launch
+                            eagerly. Same results either way. Ignored by pp_solve. */
 } pp_solve_opts;
 
 /* Result of pp_solve. */

@@ -33,7 +33,7 @@ class StchOpts(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("m", c_int), ("max_cycles", c_int), ("tol", c_double), ("inner", c_int),
                 ("stall_cycles", c_int), ("inner_eta", c_double), ("history", P_double), ("history_cap", c_int),
-                ("new_poly_degree", c_int), ("new_poly_add", c_int)]
+                ("new_poly_degree", c_int), ("new_poly_add", c_int), ("graphs", c_int)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -523,8 +523,9 @@ class Batch:
         return out
 
     def solve(self, polys, b, R: int, tol: float = 1e-8, m: int = 50, max_cycles: int = 1000, inner: str = "fp32",
-              stall_cycles: int = 5, inner_eta: float = 0.0):
-        """x for every (system, rhs) pair; b interleaved (n*R). Returns (x, list of info dicts per pair)."""
+              stall_cycles: int = 5, inner_eta: float = 0.0, graphs: bool = True):
+        """x for every (system, rhs) pair; b interleaved (n*R). Returns (x, list of info dicts per pair).
+        graphs: capture each Arnoldi step into a HIP graph once and replay it in later cycles."""
         b = _dev_tensor(b, torch.float64, self.device)
         if b.numel() != self.n * R:
             raise ValueError("right-hand side length")
@@ -532,7 +533,7 @@ class Batch:
         hs = (ctypes.c_void_p * self.nsys)(*[p.handle.value for p in polys])
         hist = np.zeros(max(int(max_cycles), 0) + 2)
         opts = SolveOpts(int(m), int(max_cycles), float(tol), PREC[inner], int(stall_cycles), float(inner_eta),
-                         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hist.size)
+                         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hist.size, 0, 1, int(bool(graphs)))
         P = self.nsys * R
         infos = (SolveInfo * P)()
         check(lib.pp_batch_solve(self.handle, hs, int(R), _ptr(b), _ptr(x), ctypes.byref(opts), _stream(self.device),

@@ -40,6 +40,11 @@ struct BWork {
 }  // namespace
 
 struct pp_batch_s {
+    // stream of graph-mode solves: the caller's stream may be the legacy
+    // default stream, which cannot be captured (created on first use,
+    // default priority, non-blocking)
+    hipStream_t gstream = nullptr;
+    hipEvent_t gevent = nullptr;
     int nsys = 0;
     long n = 0, nnz = 0;
     std::vector<long> row_off;
@@ -153,6 +158,11 @@ struct pp_batch_s {
         return PP_OK;
     }
     ~pp_batch_s() {
+        if (gstream) {
+            (void)hipStreamSynchronize(gstream);
+            (void)hipStreamDestroy(gstream);
+        }
+        if (gevent) (void)hipEventDestroy(gevent);
         for (auto &w : ws) free_ws(w);
         dev_free(slice);
         dev_free(sptr);
@@ -545,6 +555,24 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
             return PP_EINVAL;
         }
     hipStream_t st = S(stream);
+    if (opts->graphs) {
+        // the solve runs on the batch's own stream, after the caller's work
+        if (!B->gstream) {
+            HIP_TRY(hipStreamCreateWithFlags(&B->gstream, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&B->gevent, hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventRecord(B->gevent, st));
+        HIP_TRY(hipStreamWaitEvent(B->gstream, B->gevent, 0));
+        st = B->gstream;
+    }
+    // whatever the exit, the solve's stream is drained before returning
+    struct Drain {
+        hipStream_t s;
+        bool own;
+        ~Drain() {
+            if (own) (void)hipStreamSynchronize(s);
+        }
+    } drain{st, opts->graphs != 0};
     const double t0 = now_s();
     const int R = nrhs, m = opts->m;
     const int P = B->nsys * R;
@@ -580,6 +608,17 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
     std::vector<int> kp(P, 0);
     int prec = opts->inner;
     int cycles = 0;
+    // captured Arnoldi steps, per precision and step index (this solve only)
+    struct StepGraphs {
+        int m;
+        std::vector<hipGraphExec_t> ex;
+        explicit StepGraphs(int m_) : m(m_), ex((size_t)3 * m_, nullptr) {}
+        hipGraphExec_t &at(int p, int j) { return ex[(size_t)p * m + j]; }
+        ~StepGraphs() {
+            for (auto e : ex)
+                if (e) (void)hipGraphExecDestroy(e);
+        }
+    } graphs(m);
     for (;;) {
         int active = 0;
         for (int p = 0; p < P; ++p) {
@@ -621,20 +660,50 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
         std::vector<double> fro2(P, 0.0);
         // systems with no running pair skip the Arnoldi work (their columns
         // are never combined: z is zero beyond each pair's last step)
-        auto push_active = [&]() -> pp_status {
+        // the host fills the pinned activity flags; each step copies them to
+        // the device first (read when the copy runs, after the previous
+        // step's synchronisation)
+        auto push_active = [&]() {
             for (int q = 0; q < B->nsys; ++q) {
                 int a = 0;
                 for (int r = 0; r < R; ++r) a |= run[q * R + r];
                 B->actpin[q] = a;
             }
-            HIP_TRY(hipMemcpyAsync(B->act, B->actpin, sizeof(int) * B->nsys, hipMemcpyHostToDevice, st));
-            return PP_OK;
         };
-        PP_TRY(push_active());
-        for (int j = 0; j < m; ++j) {
+        // Device work of Arnoldi step j: flags in, the phi chain, CGS2, the
+        // Hessenberg columns out. With opts->graphs it is captured once per
+        // (precision, j) into a HIP graph and replayed in later cycles; the
+        // work has no synchronisation and no memset, and its arguments
+        // (buffers, programs, column count) are fixed for the solve.
+        auto step_work = [&](int j) -> pp_status {
+            HIP_TRY(hipMemcpyAsync(B->act, B->actpin, sizeof(int) * B->nsys, hipMemcpyHostToDevice, st));
             PP_TRY(run_bprog(B, prec, R, dphi, Kphi, bcol(w, prec, j), bcol(w, prec, j + 1), w, st, true));
             PP_TRY(bcgs2(B, prec, R, w, j, B->Hc, B->ldh, st, true));
             HIP_TRY(hipMemcpyAsync(B->hpin, B->Hc, sizeof(double) * P * B->ldh, hipMemcpyDeviceToHost, st));
+            return PP_OK;
+        };
+        push_active();
+        for (int j = 0; j < m; ++j) {
+            if (opts->graphs) {
+                hipGraphExec_t &ex = graphs.at(prec, j);
+                if (!ex) {
+                    hipGraph_t g = nullptr;
+                    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                    const pp_status sw = step_work(j);
+                    const hipError_t ec = hipStreamEndCapture(st, &g);
+                    if (sw != PP_OK) {
+                        if (ec == hipSuccess && g) (void)hipGraphDestroy(g);
+                        return sw;
+                    }
+                    HIP_TRY(ec);
+                    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    HIP_TRY(ei);
+                }
+                HIP_TRY(hipGraphLaunch(ex, st));
+            } else {
+                PP_TRY(step_work(j));
+            }
             HIP_TRY(hipStreamSynchronize(st));
             int still = 0;
             for (int p = 0; p < P; ++p) {
@@ -662,7 +731,7 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
                     ++still;
             }
             if (still == 0) break;
-            PP_TRY(push_active());
+            push_active();
         }
         // z per pair (zero for pairs that did not run)
         int kmax = 0;

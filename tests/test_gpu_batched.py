@@ -145,3 +145,28 @@ def test_batched_config_full_size(pp):
     t_loop *= len(csrs) / len(sub)
     say("loop of single solves (scaled from", len(sub), "systems):", round(t_loop, 3), "s; batched", round(t_batch, 3),
         "s; speed-up", round(t_loop / t_batch, 2))
+
+
+@pytest.mark.parametrize("R", [1, 4])
+def test_batched_graph_replays_equal_eager(pp, R):
+    # Arnoldi steps captured into HIP graphs and replayed over several cycles
+    # (with eager launches, host work and synchronisations between replays)
+    # give the eager result bit for bit: x, every pair's counters and the
+    # residual history of every cycle
+    specs = SMALL
+    csrs = _systems(specs)
+    say("batched graphs", R)
+    Bt = pp.Batch(csrs)
+    bd = Bt.interleave(np.concatenate(_rhs_block(specs, R), axis=1))
+    polys = Bt.setup(dev(_v0(specs)), 6)
+    xe, ie = Bt.solve(polys, bd, R, tol=1e-11, m=8, inner="fp32", graphs=False)
+    assert max(i["cycles"] for i in ie) >= 3 and all(i["converged"] for i in ie)
+    for _ in range(2):
+        xg, ig = Bt.solve(polys, bd, R, tol=1e-11, m=8, inner="fp32", graphs=True)
+        assert torch.equal(xg, xe)
+        for a, b in zip(ig, ie):
+            for k in ("iters", "cycles", "mvps", "dots", "fp64_cycles"):
+                assert a[k] == b[k], k
+            assert a["relres"] == b["relres"]
+        xe2, _ = Bt.solve(polys, bd, R, tol=1e-11, m=8, inner="fp32", graphs=False)
+        assert torch.equal(xe2, xe)
