@@ -99,6 +99,8 @@ def test_double_solve_matches_oracle(pp, cfg1, inner_prec):
     assert info["converged"] and np.linalg.norm(b - A @ xh) <= 1e-10 * np.linalg.norm(b)
     inner, outer = _units(p2.roots("inner")), _units(p2.roots("final"))
     xo, io = osolver.pp_gmres(A, b, outer, m=50, tol=1e-10, orth="cgs2", inner_units=inner)
+    say("result double", inner_prec, "relres", np.linalg.norm(b - A @ xh) / np.linalg.norm(b), "x_err_vs_oracle",
+        relerr(xh, xo))
     assert relerr(xh, xo) <= 1e-6
     if inner_prec == "fp64":
         assert abs(info["mvps"] - io.mvps) <= 0.05 * io.mvps
