@@ -65,6 +65,9 @@ def chain_kernel_name(variant):
         return f"k_chain_sell<float,float,...,short> ({v}: sliced-ELL, 16-bit column offsets, fused chain update)"
     if v.startswith("sell"):
         return f"k_chain_sell<float,float,...,int> ({v}: sliced-ELL SpMV fused with the chain update)"
+    if v.startswith("diac"):
+        return (f"k_chain_diac<float,float,nd,rows> ({v}: diagonal format with 1-byte codes into the matrix's "
+                "distinct values, fused chain update)")
     if v == "dia1":
         return "k_chain_dia_nd<float,float,nd> (dia1: diagonal format, one row per lane, fused chain update)"
     if v.startswith("dia"):
@@ -92,9 +95,9 @@ def recorded_traffic(prec, variant, remap):
 def traffic_probe(pp, torch, np, M, n):
     """Launch sequence for the counter runs: a plain copy of COPY_BYTES (to
     calibrate FETCH_SIZE and WRITE_SIZE), then for each sliced-ELL and
-    diagonal-format variant and precision 4 phi applications of an 8-root real polynomial (32 launches of
-    exactly one chain step each: the input read and gathered, the output
-    written)."""
+    diagonal-format variant, precision and XCD order (remap 1, then 0) 4
+    phi applications of an 8-root real polynomial (32 launches of exactly one
+    chain step each: the input read and gathered, the output written)."""
     x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     for _ in range(3):
@@ -110,11 +113,12 @@ def traffic_probe(pp, torch, np, M, n):
         for vi, name in enumerate(names):
             if not (name.startswith("sell") or name.startswith("dia")):
                 continue
-            M.set_variant(prec, vi, 1)
-            for _ in range(4):
-                pp.apply(poly, M, v, "phi", out=out)
-            torch.cuda.synchronize()
-            log("probe", prec, name, "remap 1: 32 launches")
+            for remap in (1, 0):  # the counter summary splits each kernel's dispatches in this order
+                M.set_variant(prec, vi, remap)
+                for _ in range(4):
+                    pp.apply(poly, M, v, "phi", out=out)
+                torch.cuda.synchronize()
+                log("probe", prec, name, f"remap {remap}: 32 launches")
     log("kernel sources sha256", kernel_source_hash())
 
 
@@ -379,6 +383,9 @@ def main():
     ap.add_argument("--m", type=int, default=50)
     ap.add_argument("--pav-reps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--chain-variant", default=None,
+                    help="pin the chain kernel (e.g. diac) for both precisions instead of autotuning, remap on; "
+                         "used to profile the kernel an unprofiled run picks")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the differentiation and batched legs")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -403,6 +410,11 @@ def main():
     b = rhs(n, 1)
     v0 = start_vector(n, 2)
     M = pp.Matrix.from_csr(csr)
+    if args.chain_variant:
+        vi = [pp.chain_variant_name(k) for k in range(pp.N_CHAIN_VARIANTS)].index(args.chain_variant)
+        for prec in ("fp32", "fp64"):
+            M.set_variant(prec, vi, 1)
+        log("chain variant pinned:", args.chain_variant)
     bd = torch.as_tensor(b, device="cuda")
     v0d = torch.as_tensor(v0, device="cuda")
     torch.cuda.synchronize()
@@ -482,9 +494,9 @@ def main():
         "traffic_GBps": round(tr["traffic_bytes"] / (k32["launch_us"] * 1e-6) / 1e9, 1) if tr else None,
         "traffic_frac": round(tr["traffic_bytes"] / (k32["launch_us"] * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)
         if tr else None,
-        "note": ("achieved uses the CSR algorithmic bytes (int32 indices); formats without column indices "
-                 "(diagonal) or with 16-bit offsets move fewer bytes, so frac can pass 1; traffic_GBps is the "
-                 "measured HBM-side rate"),
+        "note": ("achieved uses the CSR algorithmic bytes (int32 indices and 4-byte values); formats without "
+                 "column indices (diagonal), with 16-bit offsets or with 1-byte value codes move fewer bytes, so "
+                 "frac can pass 1; traffic_GBps is the measured HBM-side rate"),
         "avg_launch_us": round(k32["launch_us"], 3),
         "fp64_avg_launch_us": round(phi["fp64"]["launch_us"], 3),
         "fp64_variant": phi["fp64"]["variant"],

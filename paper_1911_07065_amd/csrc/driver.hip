@@ -11,6 +11,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -58,6 +59,11 @@ struct pp_matrix_s {
     double *dval64 = nullptr;
     float *dval32 = nullptr;
     int32_t *dperm = nullptr;
+    // value-coded diagonal copy (few distinct values; dropped when the values change)
+    uint8_t *dcode = nullptr;
+    double *dtab64 = nullptr;
+    float *dtab32 = nullptr;
+    int ntab = 0;
     // right scaling A diag(s) (composition with a diagonal preconditioner):
     // the chains, the setup and the residual use the scaled values val_own;
     // pp_solve returns x = diag(s) x~
@@ -120,6 +126,10 @@ struct pp_matrix_s {
         for (int k = 0; k < kMaxDiag; ++k) d.doff.off[k] = k < d.doff.nd ? h_doff[k] : 0;
         d.dval64 = dval64;
         d.dval32 = dval32;
+        d.dcode = dcode;
+        d.dtab64 = dtab64;
+        d.dtab32 = dtab32;
+        d.ntab = ntab;
         for (int p = 0; p < 3; ++p) {
             d.tileB8[p] = tileB8[p];
             d.ntileB8[p] = ntileB8[p];
@@ -211,6 +221,9 @@ struct pp_matrix_s {
         dev_free(dval64);
         dev_free(dval32);
         dev_free(dperm);
+        dev_free(dcode);
+        dev_free(dtab64);
+        dev_free(dtab32);
         dev_free(val_own);
         dev_free(scale);
         dev_free(sval64);
@@ -353,6 +366,7 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
     for (int v = 0; v < CV_COUNT; ++v) {
         if (v == CV_PERSIST || ((v == CV_SELL || v == CV_SELLT || v == CV_SELL2 || v == CV_SELL4) && A->nslices == 0) ||
             ((v == CV_SELLD || v == CV_SELLD4) && !A->sdel) || ((v == CV_DIA || v == CV_DIA4) && A->h_doff.empty()) ||
+            (v == CV_DIAC && !A->dcode) ||
             (v == CV_TILEB8 && A->ntileB8[prec] == 0) ||
             (v == CV_TILEB16 && A->ntileB16[prec] == 0))
             continue;
@@ -823,6 +837,60 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
                     return fail(PP_EDEVICE);
                 }
                 A->h_doff = offs;
+                // value-coded copy: at most 255 distinct nonzero values (code 0 is
+                // zero) and a diagonal count the kernel is compiled for
+                const int nd = (int)offs.size();
+                const bool nd_ok = nd <= 9 || nd == 13 || nd == 19 || nd == 27;
+                std::vector<double> hv(nnz);
+                if (nd_ok && hipMemcpyAsync(hv.data(), val, sizeof(double) * nnz, hipMemcpyDeviceToHost, st) ==
+                                 hipSuccess &&
+                    hipStreamSynchronize(st) == hipSuccess) {
+                    std::unordered_map<uint64_t, int> code_of;
+                    std::vector<double> tab(1, 0.0);
+                    code_of[0] = 0;
+                    bool few_values = true;
+                    for (int64_t q = 0; q < nnz && few_values; ++q) {
+                        uint64_t bits;
+                        std::memcpy(&bits, &hv[q], sizeof bits);
+                        if (code_of.find(bits) == code_of.end()) {
+                            if (tab.size() >= 256) {
+                                few_values = false;
+                                break;
+                            }
+                            code_of[bits] = (int)tab.size();
+                            tab.push_back(hv[q]);
+                        }
+                    }
+                    if (few_values) {
+                        const int G = (nd + 7) / 8;
+                        std::vector<uint8_t> codes((size_t)n * G * 8, 0);
+                        for (int64_t r = 0; r < n; ++r)
+                            for (int dd = 0; dd < nd; ++dd) {
+                                const int kk = dp[((r >> 8) * (long)nd + dd) * 256 + (r & 255)];
+                                if (kk < 0) continue;
+                                uint64_t bits;
+                                std::memcpy(&bits, &hv[kk], sizeof bits);
+                                codes[((size_t)r * G + dd / 8) * 8 + dd % 8] = (uint8_t)code_of[bits];
+                            }
+                        std::vector<float> tab32(tab.size());
+                        for (size_t q = 0; q < tab.size(); ++q) tab32[q] = (float)tab[q];
+                        if ((s = dev_alloc(&A->dcode, codes.size())) != PP_OK ||
+                            (s = dev_alloc(&A->dtab64, tab.size())) != PP_OK ||
+                            (s = dev_alloc(&A->dtab32, tab.size())) != PP_OK)
+                            return fail(s);
+                        if (hipMemcpyAsync(A->dcode, codes.data(), codes.size(), hipMemcpyHostToDevice, st) !=
+                                hipSuccess ||
+                            hipMemcpyAsync(A->dtab64, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice,
+                                           st) != hipSuccess ||
+                            hipMemcpyAsync(A->dtab32, tab32.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice,
+                                           st) != hipSuccess ||
+                            hipStreamSynchronize(st) != hipSuccess) {
+                            set_error("pp_matrix_create: value-coded upload failed");
+                            return fail(PP_EDEVICE);
+                        }
+                        A->ntab = (int)tab.size();
+                    }
+                }
             }
         }
     }
@@ -849,6 +917,19 @@ namespace {
 
 // Point the handle at new FP64 values and refresh the copies derived from them.
 pp_status refresh_values(pp_matrix A, const double *val, hipStream_t st) {
+    if (A->dcode) {
+        // the codes describe the old values: drop them (and a tuned pick of them)
+        (void)hipStreamSynchronize(st);
+        dev_free(A->dcode);
+        dev_free(A->dtab64);
+        dev_free(A->dtab32);
+        A->ntab = 0;
+        for (int p = 0; p < 3; ++p)
+            if (A->variant[p] == CV_DIAC) {
+                A->variant[p] = CV_TILE8;
+                A->tuned[p] = 0;
+            }
+    }
     A->val = val;
     HIP_TRY(launch_val_to_f32(A->nnz, val, A->val32, st));
     if (A->nslices > 0) HIP_TRY(launch_sell_values(A->npad, A->sperm, val, A->sval64, A->sval32, st));
@@ -981,6 +1062,11 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
             set_error("pp_matrix_set_variant: no diagonal-format copy for this matrix (too many diagonals)");
             return PP_EINVAL;
         }
+        if (variant == CV_DIAC && !A->dcode) {
+            set_error("pp_matrix_set_variant: no value-coded diagonal copy (too many diagonals or distinct values, "
+                      "or the values changed)");
+            return PP_EINVAL;
+        }
         if (variant == CV_TILEB8) PP_TRY(build_round_plan(A, prec, 8, &A->tileB8[prec], &A->ntileB8[prec], 0));
         if (variant == CV_TILEB16) PP_TRY(build_round_plan(A, prec, 16, &A->tileB16[prec], &A->ntileB16[prec], 0));
         A->persist[prec] = 0;
@@ -1057,31 +1143,36 @@ pp_status pp_adjoint_values(pp_matrix A, const double *lam, const double *x, dou
 
 namespace {
 
-// One GMRES(d) cycle on A from v0 in FP64 with CGS2 (Algorithm 4 step 1a).
-// Hbar receives the (d+1) x d Hessenberg matrix (column-major, leading
-// dimension d+1), k the Krylov dimension reached (k < d after a breakdown)
-// and dots the inner products and norms used.
+// One GMRES(d) cycle on A from v0 in FP64 (Algorithm 4 step 1a). Hbar
+// receives the (d+1) x d Hessenberg matrix (column-major, leading dimension
+// d+1), k the Krylov dimension reached (k < d after a breakdown) and dots
+// the inner products used.
+//
+// The orthogonalisation is classical Gram-Schmidt with the second pass and
+// the normalisation delayed by one step. The pending vector u (projected
+// once against v_0..v_{j-1}) goes into the product w = op(u) before it is
+// final. Then one pass of dot products ([V_j u w]^T [u w]), one workgroup of
+// coefficient algebra, and one update pass finish v_j = (u - V_j a)/rho and
+// form the next pending vector from w through the Arnoldi relation
+// A V_j = V_{j+1} Hbar: two sweeps over the basis per step instead of
+// three. A last dot pass finishes column d-1.
 pp_status setup_arnoldi(pp_matrix A, const double *v0, int d, hipStream_t st, std::vector<double> &Hbar, int &k,
                         bool &brk, int64_t &dots, const char *who, pp_poly op = nullptr) {
     PP_TRY(A->ensure_ws(0, d));
-    PP_TRY(A->ensure_red(d + 1));
+    PP_TRY(A->ensure_red(2 * d + 4));
     const Workspace &ws = A->ws[0];
     const int n = A->n;
-    // V[:,0] = v0 / ||v0||
-    void *v0c = vcol(ws, 0, 0);
-    HIP_TRY(hipMemcpyAsync(v0c, v0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(launch_update(0, n, ws.V, ws.ldv, 0, A->h1(), v0c, A->npart, st));
-    HIP_TRY(launch_reduce_norm(A->nblk_upd, A->npart, A->H(), A->inv(), st));
-    HIP_TRY(launch_scale_cast(0, 0, n, v0c, A->inv(), 0.0, v0c, st));
-    HIP_TRY(hipMemcpyAsync(A->hpin, A->H(), sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (!(A->hpin[0] > 0.0) || !std::isfinite(A->hpin[0])) {
+    double *u = (double *)ws.D, *w = (double *)ws.ACC;
+    double v0n = 0.0;
+    PP_TRY(dev_norm(A, 0, v0, &v0n, st));
+    if (!(v0n > 0.0) || !std::isfinite(v0n)) {
         set_error(std::string(who) + ": start vector is zero or not finite");
         return PP_EINVAL;
     }
-    // All d Arnoldi steps are queued without a host round trip: the
-    // Hessenberg columns stay in device memory and the host looks for a
-    // breakdown once at the end (steps after a breakdown are discarded).
+    HIP_TRY(hipMemcpyAsync(u, v0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    // All steps are queued without a host round trip: the Hessenberg columns
+    // stay in device memory and the host looks for a breakdown once at the
+    // end (columns after a breakdown are discarded).
     const int ld = d + 1;
     double *Hdev = nullptr;
     PP_TRY(dev_alloc(&Hdev, (size_t)ld * d));
@@ -1090,13 +1181,24 @@ pp_status setup_arnoldi(pp_matrix A, const double *v0, int d, hipStream_t st, st
         ~Free() { dev_free(p); }
     } free_h{Hdev};
     HIP_TRY(hipMemsetAsync(Hdev, 0, sizeof(double) * ld * d, st));
-    for (int j = 0; j < d; ++j) {
-        // the operator: A, or phi1(A) for the second polynomial of a double one
-        if (op)
-            PP_TRY(run_program(A, op, PP_APPLY_PHI, 0, vcol(ws, 0, j), vcol(ws, 0, j + 1), st));
-        else
-            PP_TRY(spmv_axpby(A, 0, vcol(ws, 0, j), 1.0, nullptr, 0.0, vcol(ws, 0, j + 1), st));
-        PP_TRY(cgs2_step(A, 0, ws, j, st, Hdev + (size_t)j * ld, false));
+    double *dd = A->h1();    // reduced dots, then g (3 d + 6 values over h1, h2, H)
+    double *pend = A->z();   // first-pass coefficients of the pending column
+    double *coef = A->inv(); // {1/rho, g_j}
+    for (int j = 0; j <= d; ++j) {
+        const bool last = j == d;
+        if (!last) {
+            // the operator: A, or phi1(A) for the second polynomial of a double one
+            if (op)
+                PP_TRY(run_program(A, op, PP_APPLY_PHI, 0, u, w, st));
+            else
+                PP_TRY(spmv_axpby(A, 0, u, 1.0, nullptr, 0.0, w, st));
+        }
+        HIP_TRY(launch_dots_pair(n, (const double *)ws.V, ws.ldv, j, u, last ? u : w, A->partial, A->ldp, st));
+        HIP_TRY(launch_reduce(A->nblk_dot, A->partial, A->ldp, 2 * j + 2, dd, nullptr, 0, st));
+        HIP_TRY(launch_dcgs_step(j, dd, Hdev, ld, pend, coef, last ? 1 : 0, st));
+        if (!last)
+            HIP_TRY(launch_update_pair(n, (const double *)ws.V, ws.ldv, j, dd, dd + 2 * j + 2, coef, u, w,
+                                       (double *)vcol(ws, 0, j), st));
     }
     Hbar.assign((size_t)ld * d, 0.0);
     HIP_TRY(hipMemcpyAsync(Hbar.data(), Hdev, sizeof(double) * ld * d, hipMemcpyDeviceToHost, st));
@@ -1108,7 +1210,7 @@ pp_status setup_arnoldi(pp_matrix A, const double *v0, int d, hipStream_t st, st
     double fro2 = 0.0;
     dots = 1;
     for (int j = 0; j < d; ++j) {
-        dots += 2 * (j + 1) + 1;
+        dots += 2 * (j + 1) + 2;
         for (int i = 0; i <= j + 1; ++i) {
             const double h = Hbar[(size_t)i + (size_t)j * ld];
             if (!std::isfinite(h)) {

@@ -40,7 +40,8 @@ enum ChainVariant : int {
     CV_SELLD4 = 23,   // same, 4 slices per wave
     CV_DIA = 24,      // diagonal format (matrices on few diagonals): 2 rows per lane
     CV_DIA4 = 25,     // same, 1 row per lane
-    CV_COUNT = 26
+    CV_DIAC = 26,     // diagonal format with 1-byte codes into a table of the matrix's distinct values, 4 rows per lane
+    CV_COUNT = 27
 };
 
 // A chain step as the persistent kernel reads it from device memory.
@@ -108,6 +109,13 @@ struct DevCSR {
     DiaOffsets doff;
     const double *dval64;
     const float *dval32;
+    // value-coded diagonal format (absent if dcode is null): row i's codes
+    // for diagonals 8g .. 8g+7 are the 8 bytes dcode[(i * G + g) * 8 ..],
+    // G = ceil(nd / 8); code c stands for the value dtab[c] (code 0: zero)
+    const uint8_t *dcode;
+    const double *dtab64;
+    const float *dtab32;
+    int ntab;
     int variant[3];      // chain variant per precision
     int remap[3];        // 1: keep neighbouring workgroups on one XCD
 };
@@ -171,6 +179,17 @@ hipError_t launch_combine(int prec, int n, const void *V, long ldv, int k, const
 hipError_t launch_axpy_x(int prec, int n, double beta, const void *d, double *x, hipStream_t st);
 // x[i] = value (double)
 hipError_t launch_fill(int n, double value, double *x, hipStream_t st);
+// Delayed Gram-Schmidt of the setup cycle (FP64): the dot pass
+// (partial[b*ldp + 0..ncols) = V^T u, [ncols..2 ncols) = V^T w, then u^T u,
+// u^T w), the one-workgroup coefficient step (dd after reduction, H column
+// j-1, pending coefficients, coef = {1/rho, g_j}, g into dd[2j+2..]) and the
+// update pass (v_j into vout, the next pending vector into u).
+hipError_t launch_dots_pair(int n, const double *V, long ldv, int ncols, const double *u, const double *w,
+                            double *partial, int ldp, hipStream_t st);
+hipError_t launch_dcgs_step(int j, double *dd, double *H, int ldh, double *pend, double *coef, int final_step,
+                            hipStream_t st);
+hipError_t launch_update_pair(int n, const double *V, long ldv, int ncols, const double *a, const double *g,
+                              const double *coef, double *u, const double *w, double *vout, hipStream_t st);
 // s[i] = 1/a_ii (0 and *bad = 1 where the diagonal is missing or zero)
 hipError_t launch_jacobi(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double *s, int *bad,
                          hipStream_t st);

@@ -627,6 +627,64 @@ __global__ __launch_bounds__(256) void k_chain_dia_nd(ChainArgs<VT, XT> a, const
     if (r < n) row_finish(a, r, s, pre);
 }
 
+// Value-coded diagonal format: as k_chain_dia_nd, but the entry of row r on
+// diagonal d is the byte code dcode[(r G + d/8) 8 + d%8] into a table of the
+// matrix's distinct values (staged in LDS), so a row's entries cost 8 bytes
+// per 8 diagonals. Rows past n read row n - 1 and are not written.
+template <typename VT, typename XT, int ND, int RPT>
+__global__ __launch_bounds__(256) void k_chain_diac(ChainArgs<VT, XT> a, const uint8_t *__restrict__ dcode,
+                                                    const VT *__restrict__ dtab, int ntab, DiaOffsets doff,
+                                                    int nblocks, int remap) {
+    using AT = typename Arith<XT>::T;
+    constexpr int G = (ND + 7) / 8;
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __shared__ AT tab[256];
+    const int blk = remap_tile(blockIdx.x, nblocks, remap);
+    const int base = blk * 256 * RPT + (int)threadIdx.x;
+    const int n = a.n;
+    // the block's loads go out before the table is staged (it waits once)
+    int rr[RPT];
+    u32x2 cw[RPT][G];
+    AT x[RPT][ND];
+    RowPre<AT> pre[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = base + q * 256;
+        rr[q] = r < n ? r : n - 1;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            cw[q][g] = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(dcode) + (long)rr[q] * G + g);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) x[q][d] = ldx(a.in, min(max(rr[q] + doff.off[d], 0), n - 1));
+        if (r < n) pre[q] = row_prefetch(a, r);
+    }
+    if ((int)threadIdx.x < ntab) tab[threadIdx.x] = (AT)dtab[threadIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        AT s = AT(0);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const unsigned word = (d & 7) < 4 ? cw[q][d >> 3].x : cw[q][d >> 3].y;
+            const unsigned code = (word >> (8 * (d & 3))) & 0xffu;
+            s += tab[code] * x[q][d];
+        }
+        const int r = base + q * 256;
+        if (r < n) row_finish(a, r, s, pre[q]);
+    }
+}
+
+template <typename VT>
+const VT *diac_tab(const DevCSR &A);
+template <>
+const double *diac_tab<double>(const DevCSR &A) {
+    return A.dtab64;
+}
+template <>
+const float *diac_tab<float>(const DevCSR &A) {
+    return A.dtab32;
+}
+
 template <typename VT>
 const VT *dia_vals(const DevCSR &A);
 template <>
@@ -770,6 +828,34 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int v
                                        A.doff, nb, remap);
             }
 #undef PP_DIA_ND
+            return hipGetLastError();
+        }
+        case CV_DIAC: {
+            // 4 rows per lane (2 and 8 measured the same on the 128^3 stencil)
+            if (A.doff.nd <= 0 || !A.dcode) return hipErrorInvalidValue;
+            const int nb = (int)((A.n + 1023L) / 1024L);
+#define PP_DIAC_ND(K)                                                                                              \
+    case K:                                                                                                        \
+        hipLaunchKernelGGL((k_chain_diac<VT, XT, K, 4>), dim3(nb), dim3(256), 0, st, a, A.dcode, diac_tab<VT>(A),    \
+                           A.ntab, A.doff, nb, remap);                                                             \
+        break;
+            switch (A.doff.nd) {
+                PP_DIAC_ND(1)
+                PP_DIAC_ND(2)
+                PP_DIAC_ND(3)
+                PP_DIAC_ND(4)
+                PP_DIAC_ND(5)
+                PP_DIAC_ND(6)
+                PP_DIAC_ND(7)
+                PP_DIAC_ND(8)
+                PP_DIAC_ND(9)
+                PP_DIAC_ND(13)
+                PP_DIAC_ND(19)
+                PP_DIAC_ND(27)
+                default:
+                    return hipErrorInvalidValue;  // the coded copy is only built for these counts
+            }
+#undef PP_DIAC_ND
             return hipGetLastError();
         }
         case CV_SELLD:
@@ -918,6 +1004,196 @@ __device__ __forceinline__ double vh_row(const XT *__restrict__ V, long ldv, int
     }
     if (ncols - k0 >= 1) vh_chunk<XT, 1>(V, ldv, k0, h, i, a);
     return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// ---------------------------------------------------------------------------
+// Delayed Gram-Schmidt of the setup cycle: per Arnoldi step one pass of dot
+// products (with the pending vector u and w = A u together) and one update
+// pass (finishing v_j and forming the next pending vector), with the small
+// coefficient algebra in one workgroup between them.
+// ---------------------------------------------------------------------------
+
+// s1 = sum_k V[i,k] a_k and s2 = sum_k V[i,k] g_k (k < ncols) from one
+// read of the row: columns 8 at a time (then 4, 2, 1), loads issued together.
+template <typename XT, int KC>
+__device__ __forceinline__ void vh2_chunk(const XT *__restrict__ V, long ldv, int k0, const double *__restrict__ a,
+                                          const double *__restrict__ g, long i, double *s1, double *s2) {
+    double x[KC];
+#pragma unroll
+    for (int u = 0; u < KC; ++u) x[u] = (double)ldx(V, i + (long)(k0 + u) * ldv);
+#pragma unroll
+    for (int u = 0; u < KC; ++u) {
+        s1[u] += x[u] * a[k0 + u];
+        s2[u] += x[u] * g[k0 + u];
+    }
+}
+
+template <typename XT>
+__device__ __forceinline__ void vh2_row(const XT *__restrict__ V, long ldv, int ncols, const double *__restrict__ a,
+                                        const double *__restrict__ g, long i, double &o1, double &o2) {
+    double s1[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, s2[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int k0 = 0;
+    for (; k0 + 8 <= ncols; k0 += 8) vh2_chunk<XT, 8>(V, ldv, k0, a, g, i, s1, s2);
+    if (ncols - k0 >= 4) {
+        vh2_chunk<XT, 4>(V, ldv, k0, a, g, i, s1, s2);
+        k0 += 4;
+    }
+    if (ncols - k0 >= 2) {
+        vh2_chunk<XT, 2>(V, ldv, k0, a, g, i, s1, s2);
+        k0 += 2;
+    }
+    if (ncols - k0 >= 1) vh2_chunk<XT, 1>(V, ldv, k0, a, g, i, s1, s2);
+    o1 = ((s1[0] + s1[1]) + (s1[2] + s1[3])) + ((s1[4] + s1[5]) + (s1[6] + s1[7]));
+    o2 = ((s2[0] + s2[1]) + (s2[2] + s2[3])) + ((s2[4] + s2[5]) + (s2[6] + s2[7]));
+}
+
+// One chunk of KC columns of k_dots_pair: sums V_c u and V_c w.
+template <typename XT, int KC>
+__device__ __forceinline__ void dots2_chunk(const XT *__restrict__ V, long ldv, int c0, int ncols, const long *ii,
+                                            const double *uv, const double *wv, double (*sm)[2 * kDotCols],
+                                            double *prow) {
+    constexpr int RPT = kDotRows / 256;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double x[RPT][KC];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s)
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) x[s][kc] = (double)ldx(V, ii[s] + (long)(c0 + kc) * ldv);
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+        double au = 0.0, aw = 0.0;
+#pragma unroll
+        for (int s = 0; s < RPT; ++s) {
+            au += x[s][kc] * uv[s];
+            aw += x[s][kc] * wv[s];
+        }
+        au = wave_sum(au);
+        aw = wave_sum(aw);
+        if (lane == 0) {
+            sm[wave][kc] = au;
+            sm[wave][KC + kc] = aw;
+        }
+    }
+    __syncthreads();
+    if (tid < 2 * KC) {
+        const double t = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
+        prow[tid < KC ? c0 + tid : ncols + c0 + (tid - KC)] = t;
+    }
+    __syncthreads();
+}
+
+// partial[b*ldp + c] = sum over block b of V_c u, partial[b*ldp + ncols + c]
+// = sum of V_c w (c < ncols), partial[b*ldp + 2 ncols] = sum u u and
+// [2 ncols + 1] = sum u w; kDotRows rows per block, columns 8 at a time.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_dots_pair(int n, const XT *V, long ldv, int ncols, const XT *u, const XT *w,
+                                                   double *partial, int ldp) {
+    constexpr int RPT = kDotRows / 256;
+    __shared__ double sm[4][2 * kDotCols];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long base = (long)blockIdx.x * kDotRows;
+    long ii[RPT];
+    double uv[RPT], wv[RPT];
+    double suu = 0.0, suw = 0.0;
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+        const long i = base + s * 256 + tid;
+        ii[s] = i < n ? i : (long)n - 1;
+        const double a = (double)ldx(u, ii[s]), b = (double)ldx(w, ii[s]);
+        uv[s] = i < n ? a : 0.0;
+        wv[s] = i < n ? b : 0.0;
+        suu += uv[s] * uv[s];
+        suw += uv[s] * wv[s];
+    }
+    double *prow = partial + (long)blockIdx.x * ldp;
+    int c0 = 0;
+    for (; c0 + 8 <= ncols; c0 += 8) dots2_chunk<XT, 8>(V, ldv, c0, ncols, ii, uv, wv, sm, prow);
+    if (ncols - c0 >= 4) {
+        dots2_chunk<XT, 4>(V, ldv, c0, ncols, ii, uv, wv, sm, prow);
+        c0 += 4;
+    }
+    if (ncols - c0 >= 2) {
+        dots2_chunk<XT, 2>(V, ldv, c0, ncols, ii, uv, wv, sm, prow);
+        c0 += 2;
+    }
+    if (ncols - c0 >= 1) dots2_chunk<XT, 1>(V, ldv, c0, ncols, ii, uv, wv, sm, prow);
+    suu = wave_sum(suu);
+    suw = wave_sum(suw);
+    if (lane == 0) {
+        sm[wave][0] = suu;
+        sm[wave][1] = suw;
+    }
+    __syncthreads();
+    if (tid < 2) prow[2 * ncols + tid] = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
+}
+
+// The coefficient algebra of delayed step j (one workgroup). dd holds, after
+// the reduction: a = V_j^T u (j values), b = V_j^T w (j), alpha = u^T u,
+// beta = u^T w. pend holds the first-pass coefficients of H column j-1.
+//   rho = sqrt(alpha - a^T a);  v_j = (u - V_j a) / rho
+//   H[0:j, j-1] = pend + a,  H[j, j-1] = rho
+// and, unless final, with y = Hbar_{(j+1) x j} a and A v_j = (w - V_{j+1} y)/rho:
+//   c_k = (b_k - y_k)/rho (k < j),  c_j = ((beta - a^T b)/rho - y_j)/rho
+//   g = y/rho + c, the next pending vector u' = w/rho - V_{j+1} g,
+//   pend <- c (first-pass coefficients of column j), coef = {1/rho, g_j}.
+// g is written to dd[2j+2 ...]. Sums run in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_dcgs_step(int j, double *dd, double *H, int ldh, double *pend, double *coef,
+                                                   int final_step) {
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    const double *a = dd, *b = dd + j;
+    const double alpha = dd[2 * j], beta = dd[2 * j + 1];
+    double saa = 0.0, sab = 0.0;
+    for (int k = tid; k < j; k += 256) {
+        saa += a[k] * a[k];
+        sab += a[k] * b[k];
+    }
+    saa = block_sum256(saa, red);
+    sab = block_sum256(sab, red);
+    __shared__ double sh[2];
+    if (tid == 0) {
+        const double rho = sqrt(fmax(alpha - saa, 0.0));
+        sh[0] = rho;
+        sh[1] = rho > 0.0 ? 1.0 / rho : 0.0;
+        if (j >= 1) H[j + (long)(j - 1) * ldh] = rho;
+    }
+    if (j >= 1)
+        for (int k = tid; k < j; k += 256) H[k + (long)(j - 1) * ldh] = pend[k] + a[k];
+    __syncthreads();
+    if (final_step) return;
+    const double inv = sh[1];
+    double *g = dd + 2 * j + 2;
+    // y_i = sum_k H[i,k] a_k over k < j (H upper Hessenberg: k >= i - 1)
+    for (int i = tid; i <= j; i += 256) {
+        double y = 0.0;
+        for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) y += H[i + (long)k * ldh] * a[k];
+        const double c = i < j ? (b[i] - y) * inv : ((beta - sab) * inv - y) * inv;
+        g[i] = y * inv + c;
+        pend[i] = c;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        coef[0] = inv;
+        coef[1] = g[j];
+    }
+}
+
+// The update pass of delayed step j: per row, s1 = sum_k V[i,k] a_k and
+// s2 = sum_k V[i,k] g_k (k < j), then v = (u_i - s1) / rho into vout and
+// u'_i = w_i / rho - s2 - v g_j into u (in place). coef = {1/rho, g_j}.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_update_pair(int n, const XT *V, long ldv, int ncols, const double *a,
+                                                     const double *g, const double *coef, XT *u, const XT *w,
+                                                     XT *vout) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double inv = coef[0], gj = coef[1];
+    double s1, s2;
+    vh2_row(V, ldv, ncols, a, g, i, s1, s2);
+    const double v = ((double)ldx(u, i) - s1) * inv;
+    stx(vout, i, (typename Arith<XT>::T)v);
+    const double vs = stored_value(vout, v);
+    stx(u, i, (typename Arith<XT>::T)((double)ldx(w, i) * inv - s2 - vs * gj));
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_reduce(int nblk, const double *partial, int ldp, double *h,
@@ -1186,6 +1462,28 @@ hipError_t launch_dots(int prec, int n, const void *V, long ldv, int ncols, cons
         default:
             return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_dots_pair(int n, const double *V, long ldv, int ncols, const double *u, const double *w,
+                            double *partial, int ldp, hipStream_t st) {
+    const unsigned g = blocks_for(n, kDotRows);
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dots_pair<double>, dim3(g), dim3(256), 0, st, n, V, ldv, ncols, u, w, partial, ldp);
+    return hipGetLastError();
+}
+
+hipError_t launch_dcgs_step(int j, double *dd, double *H, int ldh, double *pend, double *coef, int final_step,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_dcgs_step, dim3(1), dim3(256), 0, st, j, dd, H, ldh, pend, coef, final_step);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_pair(int n, const double *V, long ldv, int ncols, const double *a, const double *g,
+                              const double *coef, double *u, const double *w, double *vout, hipStream_t st) {
+    const unsigned gr = blocks_for(n, 256);
+    if (gr == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_pair<double>, dim3(gr), dim3(256), 0, st, n, V, ldv, ncols, a, g, coef, u, w, vout);
     return hipGetLastError();
 }
 
@@ -1576,7 +1874,7 @@ const char *chain_variant_name(int v) {
                                           "vec8x4",  "vec16x2",  "vec16x4", "vec32x2",   "tilev8x1",
                                           "tilev16x2", "vk2x4x4", "vk4x4x2", "vk8x4x1", "vk16x2x2", "persist8",
                                           "tileb8x1", "tileb16x2", "sell64", "sell64t", "sell64x2", "sell64x4", "sell64d16", "sell64d16x4",
-                                              "dia2",   "dia1"};
+                                              "dia2",   "dia1", "diac"};
     return (v >= 0 && v < CV_COUNT) ? names[v] : "?";
 }
 
