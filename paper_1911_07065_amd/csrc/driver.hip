@@ -1193,8 +1193,10 @@ pp_status setup_arnoldi(pp_matrix A, const double *v0, int d, hipStream_t st, st
             else
                 PP_TRY(spmv_axpby(A, 0, u, 1.0, nullptr, 0.0, w, st));
         }
-        HIP_TRY(launch_dots_pair(n, (const double *)ws.V, ws.ldv, j, u, last ? u : w, A->partial, A->ldp, st));
-        HIP_TRY(launch_reduce(A->nblk_dot, A->partial, A->ldp, 2 * j + 2, dd, nullptr, 0, st));
+        int prow = 0;
+        HIP_TRY(launch_dots_pair(n, (const double *)ws.V, ws.ldv, j, u, last ? u : w, A->partial, A->ldp,
+                                 A->nblk_dot, &prow, st));
+        HIP_TRY(launch_reduce(prow, A->partial, A->ldp, 2 * j + 2, dd, nullptr, 0, st));
         HIP_TRY(launch_dcgs_step(j, dd, Hdev, ld, pend, coef, last ? 1 : 0, st));
         if (!last)
             HIP_TRY(launch_update_pair(n, (const double *)ws.V, ws.ldv, j, dd, dd + 2 * j + 2, coef, u, w,

@@ -54,6 +54,8 @@ const char *chain_variant_name(int v);
 constexpr int kRedBlock = 256;       // threads per reduction workgroup
 constexpr int kDotRows = 1024;       // rows per dot-product workgroup
 constexpr int kDotCols = 16;         // Krylov columns per dot-product pass
+constexpr int kDotsWideCols = 16;    // the setup's dot and update passes switch layout at this width
+constexpr int kDotsWideRows = 1024;  // partial rows of the wide dot pass
 
 // Pointers of one fused chain step (see Step in poly.h).
 struct StepPtrs {
@@ -183,9 +185,10 @@ hipError_t launch_fill(int n, double value, double *x, hipStream_t st);
 // (partial[b*ldp + 0..ncols) = V^T u, [ncols..2 ncols) = V^T w, then u^T u,
 // u^T w), the one-workgroup coefficient step (dd after reduction, H column
 // j-1, pending coefficients, coef = {1/rho, g_j}, g into dd[2j+2..]) and the
-// update pass (v_j into vout, the next pending vector into u).
+// update pass (v_j into vout, the next pending vector into u). The dot pass
+// uses at most max_rows partial rows and returns their number in *rows.
 hipError_t launch_dots_pair(int n, const double *V, long ldv, int ncols, const double *u, const double *w,
-                            double *partial, int ldp, hipStream_t st);
+                            double *partial, int ldp, int max_rows, int *rows, hipStream_t st);
 hipError_t launch_dcgs_step(int j, double *dd, double *H, int ldh, double *pend, double *coef, int final_step,
                             hipStream_t st);
 hipError_t launch_update_pair(int n, const double *V, long ldv, int ncols, const double *a, const double *g,

@@ -1013,40 +1013,6 @@ __device__ __forceinline__ double vh_row(const XT *__restrict__ V, long ldv, int
 // coefficient algebra in one workgroup between them.
 // ---------------------------------------------------------------------------
 
-// s1 = sum_k V[i,k] a_k and s2 = sum_k V[i,k] g_k (k < ncols) from one
-// read of the row: columns 8 at a time (then 4, 2, 1), loads issued together.
-template <typename XT, int KC>
-__device__ __forceinline__ void vh2_chunk(const XT *__restrict__ V, long ldv, int k0, const double *__restrict__ a,
-                                          const double *__restrict__ g, long i, double *s1, double *s2) {
-    double x[KC];
-#pragma unroll
-    for (int u = 0; u < KC; ++u) x[u] = (double)ldx(V, i + (long)(k0 + u) * ldv);
-#pragma unroll
-    for (int u = 0; u < KC; ++u) {
-        s1[u] += x[u] * a[k0 + u];
-        s2[u] += x[u] * g[k0 + u];
-    }
-}
-
-template <typename XT>
-__device__ __forceinline__ void vh2_row(const XT *__restrict__ V, long ldv, int ncols, const double *__restrict__ a,
-                                        const double *__restrict__ g, long i, double &o1, double &o2) {
-    double s1[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, s2[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int k0 = 0;
-    for (; k0 + 8 <= ncols; k0 += 8) vh2_chunk<XT, 8>(V, ldv, k0, a, g, i, s1, s2);
-    if (ncols - k0 >= 4) {
-        vh2_chunk<XT, 4>(V, ldv, k0, a, g, i, s1, s2);
-        k0 += 4;
-    }
-    if (ncols - k0 >= 2) {
-        vh2_chunk<XT, 2>(V, ldv, k0, a, g, i, s1, s2);
-        k0 += 2;
-    }
-    if (ncols - k0 >= 1) vh2_chunk<XT, 1>(V, ldv, k0, a, g, i, s1, s2);
-    o1 = ((s1[0] + s1[1]) + (s1[2] + s1[3])) + ((s1[4] + s1[5]) + (s1[6] + s1[7]));
-    o2 = ((s2[0] + s2[1]) + (s2[2] + s2[3])) + ((s2[4] + s2[5]) + (s2[6] + s2[7]));
-}
-
 // One chunk of KC columns of k_dots_pair: sums V_c u and V_c w.
 template <typename XT, int KC>
 __device__ __forceinline__ void dots2_chunk(const XT *__restrict__ V, long ldv, int c0, int ncols, const long *ii,
@@ -1178,22 +1144,133 @@ __global__ __launch_bounds__(256) void k_dcgs_step(int j, double *dd, double *H,
     }
 }
 
+// The dot pass for a wide basis (ncols >= kDotsWideCols): workgroup (bx, c)
+// sums the columns [8c, 8c + 8) over the row tiles bx, bx + nbx, ... of
+// 256 rows, keeping per-lane sums across its tiles and reducing once at the
+// end into partial row bx (same column layout as k_dots_pair, u^T u and
+// u^T w from the workgroups with c = 0). Column indices past ncols are
+// clamped and their sums dropped. Workgroup ids are ordered so that those
+// on one XCD (id % 8) with consecutive id / 8 share their rows, which lets
+// the re-reads of u and w hit that XCD's L2.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_dots_pair_wide(int n, const XT *__restrict__ V, long ldv, int ncols,
+                                                        const XT *__restrict__ u, const XT *__restrict__ w,
+                                                        double *partial, int ldp, int nbx, int ngroups) {
+    constexpr int KC = 8;
+    __shared__ double sm[4][2 * KC + 2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q = (int)(blockIdx.x >> 3);
+    const int grp = q % ngroups, bx = (q / ngroups) * 8 + (int)(blockIdx.x & 7);
+    if (bx >= nbx) return;
+    const int c0 = grp * KC;
+    long cofs[KC];
+    double au[KC], aw[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        cofs[k] = (long)min(c0 + k, ncols - 1) * ldv;
+        au[k] = 0.0;
+        aw[k] = 0.0;
+    }
+    double uu = 0.0, uw = 0.0;
+    for (long b = (long)bx * 256; b < n; b += (long)nbx * 256) {
+        const long i = b + tid;
+        const long ic = i < n ? i : (long)n - 1;
+        double x[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) x[k] = (double)__builtin_nontemporal_load(V + ic + cofs[k]);
+        const double ut = (double)ldx(u, ic), wt = (double)ldx(w, ic);
+        const double uv = i < n ? ut : 0.0, wv = i < n ? wt : 0.0;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            au[k] += x[k] * uv;
+            aw[k] += x[k] * wv;
+        }
+        uu += uv * uv;
+        uw += uv * wv;
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        au[k] = wave_sum(au[k]);
+        aw[k] = wave_sum(aw[k]);
+    }
+    uu = wave_sum(uu);
+    uw = wave_sum(uw);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            sm[wave][k] = au[k];
+            sm[wave][KC + k] = aw[k];
+        }
+        sm[wave][2 * KC] = uu;
+        sm[wave][2 * KC + 1] = uw;
+    }
+    __syncthreads();
+    double *prow = partial + (long)bx * ldp;
+    if (tid < 2 * KC + 2) {
+        const double t = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
+        if (tid < KC) {
+            if (c0 + tid < ncols) prow[c0 + tid] = t;
+        } else if (tid < 2 * KC) {
+            if (c0 + tid - KC < ncols) prow[ncols + c0 + tid - KC] = t;
+        } else if (grp == 0) {
+            prow[2 * ncols + tid - 2 * KC] = t;
+        }
+    }
+}
+
 // The update pass of delayed step j: per row, s1 = sum_k V[i,k] a_k and
 // s2 = sum_k V[i,k] g_k (k < j), then v = (u_i - s1) / rho into vout and
 // u'_i = w_i / rho - s2 - v g_j into u (in place). coef = {1/rho, g_j}.
-template <typename XT>
-__global__ __launch_bounds__(256) void k_update_pair(int n, const XT *V, long ldv, int ncols, const double *a,
-                                                     const double *g, const double *coef, XT *u, const XT *w,
-                                                     XT *vout) {
-    const long i = (long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
+// RPT rows per lane (256 apart), the basis read KC columns at a time with
+// all RPT * KC loads of a batch issued together (clamped column index, zero
+// coefficient past ncols); NT: non-temporal loads of the basis.
+template <typename XT, int RPT, int KC, bool NT>
+__global__ __launch_bounds__(256) void k_update_pair(int n, const XT *__restrict__ V, long ldv, int ncols,
+                                                     const double *__restrict__ a, const double *__restrict__ g,
+                                                     const double *coef, XT *u, const XT *w, XT *vout) {
+    const long base = (long)blockIdx.x * 256 * RPT + threadIdx.x;
+    long ii[RPT];
+    double s1[RPT], s2[RPT];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+        const long i = base + s * 256;
+        ii[s] = i < n ? i : (long)n - 1;
+        s1[s] = 0.0;
+        s2[s] = 0.0;
+    }
+    for (int k0 = 0; k0 < ncols; k0 += KC) {
+        double x[RPT][KC], ak[KC], gk[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const int c = min(k0 + k, ncols - 1);
+            const bool in = k0 + k < ncols;
+            ak[k] = in ? a[c] : 0.0;
+            gk[k] = in ? g[c] : 0.0;
+#pragma unroll
+            for (int s = 0; s < RPT; ++s)
+                x[s][k] = (double)(NT ? __builtin_nontemporal_load(V + ii[s] + (long)c * ldv)
+                                      : V[ii[s] + (long)c * ldv]);
+        }
+#pragma unroll
+        for (int s = 0; s < RPT; ++s)
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                s1[s] += x[s][k] * ak[k];
+                s2[s] += x[s][k] * gk[k];
+            }
+    }
     const double inv = coef[0], gj = coef[1];
-    double s1, s2;
-    vh2_row(V, ldv, ncols, a, g, i, s1, s2);
-    const double v = ((double)ldx(u, i) - s1) * inv;
-    stx(vout, i, (typename Arith<XT>::T)v);
-    const double vs = stored_value(vout, v);
-    stx(u, i, (typename Arith<XT>::T)((double)ldx(w, i) * inv - s2 - vs * gj));
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+        const long i = base + s * 256;
+        const double uo = (double)ldx(u, ii[s]), wo = (double)ldx(w, ii[s]);
+        if (i < n) {
+            const double v = (uo - s1[s]) * inv;
+            stx(vout, i, (typename Arith<XT>::T)v);
+            const double vs = stored_value(vout, v);
+            stx(u, i, (typename Arith<XT>::T)(wo * inv - s2[s] - vs * gj));
+        }
+    }
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_reduce(int nblk, const double *partial, int ldp, double *h,
@@ -1466,10 +1543,23 @@ hipError_t launch_dots(int prec, int n, const void *V, long ldv, int ncols, cons
 }
 
 hipError_t launch_dots_pair(int n, const double *V, long ldv, int ncols, const double *u, const double *w,
-                            double *partial, int ldp, hipStream_t st) {
-    const unsigned g = blocks_for(n, kDotRows);
-    if (g == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dots_pair<double>, dim3(g), dim3(256), 0, st, n, V, ldv, ncols, u, w, partial, ldp);
+                            double *partial, int ldp, int max_rows, int *rows, hipStream_t st) {
+    *rows = 0;
+    if (n <= 0) return hipSuccess;
+    if (ncols < kDotsWideCols) {
+        const unsigned g = blocks_for(n, kDotRows);
+        if ((int)g > max_rows) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_dots_pair<double>, dim3(g), dim3(256), 0, st, n, V, ldv, ncols, u, w, partial, ldp);
+        *rows = (int)g;
+        return hipGetLastError();
+    }
+    const int nbx = std::min(kDotsWideRows, max_rows);
+    if (nbx < 1) return hipErrorInvalidValue;
+    const int ngroups = (ncols + 7) / 8;
+    const unsigned nwg = 8u * (unsigned)ngroups * (unsigned)((nbx + 7) / 8);
+    hipLaunchKernelGGL(k_dots_pair_wide<double>, dim3(nwg), dim3(256), 0, st, n, V, ldv, ncols, u, w, partial, ldp,
+                       nbx, ngroups);
+    *rows = nbx;
     return hipGetLastError();
 }
 
@@ -1481,9 +1571,15 @@ hipError_t launch_dcgs_step(int j, double *dd, double *H, int ldh, double *pend,
 
 hipError_t launch_update_pair(int n, const double *V, long ldv, int ncols, const double *a, const double *g,
                               const double *coef, double *u, const double *w, double *vout, hipStream_t st) {
-    const unsigned gr = blocks_for(n, 256);
-    if (gr == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update_pair<double>, dim3(gr), dim3(256), 0, st, n, V, ldv, ncols, a, g, coef, u, w, vout);
+    if (n <= 0) return hipSuccess;
+    // narrow bases: 4 rows x 4 columns per batch, cached loads (the recent
+    // columns are still in the MALL); wide: 8 rows x 2 columns, streaming
+    if (ncols < kDotsWideCols)
+        hipLaunchKernelGGL((k_update_pair<double, 4, 4, false>), dim3(blocks_for(n, 1024)), dim3(256), 0, st, n, V,
+                           ldv, ncols, a, g, coef, u, w, vout);
+    else
+        hipLaunchKernelGGL((k_update_pair<double, 8, 2, true>), dim3(blocks_for(n, 2048)), dim3(256), 0, st, n, V,
+                           ldv, ncols, a, g, coef, u, w, vout);
     return hipGetLastError();
 }
 
