@@ -65,6 +65,9 @@ def chain_kernel_name(variant):
         return f"k_chain_sell<float,float,...,short> ({v}: sliced-ELL, 16-bit column offsets, fused chain update)"
     if v.startswith("sell"):
         return f"k_chain_sell<float,float,...,int> ({v}: sliced-ELL SpMV fused with the chain update)"
+    if v == "diap":
+        return ("k_chain_diap<float,float,nd> (diap: diagonal format with one byte per row naming its pattern "
+                "among the matrix's distinct rows, fused chain update)")
     if v.startswith("diac"):
         return (f"k_chain_diac<float,float,nd,rows> ({v}: diagonal format with 1-byte codes into the matrix's "
                 "distinct values, fused chain update)")

@@ -64,6 +64,11 @@ struct pp_matrix_s {
     double *dtab64 = nullptr;
     float *dtab32 = nullptr;
     int ntab = 0;
+    // pattern-coded diagonal copy (few distinct rows; dropped with the value codes)
+    uint32_t *pcode = nullptr;
+    double *ptab64 = nullptr;
+    float *ptab32 = nullptr;
+    int npat = 0;
     // right scaling A diag(s) (composition with a diagonal preconditioner):
     // the chains, the setup and the residual use the scaled values val_own;
     // pp_solve returns x = diag(s) x~
@@ -130,6 +135,10 @@ struct pp_matrix_s {
         d.dtab64 = dtab64;
         d.dtab32 = dtab32;
         d.ntab = ntab;
+        d.pcode = pcode;
+        d.ptab64 = ptab64;
+        d.ptab32 = ptab32;
+        d.npat = npat;
         for (int p = 0; p < 3; ++p) {
             d.tileB8[p] = tileB8[p];
             d.ntileB8[p] = ntileB8[p];
@@ -224,6 +233,9 @@ struct pp_matrix_s {
         dev_free(dcode);
         dev_free(dtab64);
         dev_free(dtab32);
+        dev_free(pcode);
+        dev_free(ptab64);
+        dev_free(ptab32);
         dev_free(val_own);
         dev_free(scale);
         dev_free(sval64);
@@ -366,7 +378,7 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
     for (int v = 0; v < CV_COUNT; ++v) {
         if (v == CV_PERSIST || ((v == CV_SELL || v == CV_SELLT || v == CV_SELL2 || v == CV_SELL4) && A->nslices == 0) ||
             ((v == CV_SELLD || v == CV_SELLD4) && !A->sdel) || ((v == CV_DIA || v == CV_DIA4) && A->h_doff.empty()) ||
-            (v == CV_DIAC && !A->dcode) ||
+            (v == CV_DIAC && !A->dcode) || (v == CV_DIAP && !A->pcode) ||
             (v == CV_TILEB8 && A->ntileB8[prec] == 0) ||
             (v == CV_TILEB16 && A->ntileB16[prec] == 0))
             continue;
@@ -615,6 +627,62 @@ pp_status dev_norm(pp_matrix A, int prec, const void *x, double *out, hipStream_
 }
 
 bool valid_prec(int p) { return p >= 0 && p <= 2; }
+
+// Pattern-coded copy from the value codes (row r's nd codes are
+// codes[r G 8 .. r G 8 + nd)): the distinct code tuples of the rows become
+// patterns when there are at most 256 of them with at most kMaxPatEntries
+// table entries; otherwise the matrix has no pattern-coded copy.
+pp_status build_patterns(pp_matrix A, const std::vector<uint8_t> &codes, int nd, const std::vector<double> &tab,
+                         hipStream_t st) {
+    const int64_t n = A->n;
+    const size_t stride = (size_t)((nd + 7) / 8) * 8;
+    const int maxpat = std::min(256, kMaxPatEntries / nd);
+    std::unordered_map<std::string, int> id_of;
+    std::vector<const uint8_t *> pats;
+    std::vector<uint32_t> words((size_t)((n + 1023) / 1024) * 256, 0u);
+    int prev = -1;
+    const uint8_t *prevc = nullptr;
+    for (int64_t r = 0; r < n; ++r) {
+        const uint8_t *c = codes.data() + (size_t)r * stride;
+        int id = prev;
+        if (!prevc || std::memcmp(c, prevc, nd) != 0) {
+            std::string key((const char *)c, nd);
+            auto it = id_of.find(key);
+            if (it == id_of.end()) {
+                if ((int)pats.size() >= maxpat) return PP_OK;
+                id = (int)pats.size();
+                id_of.emplace(std::move(key), id);
+                pats.push_back(c);
+            } else {
+                id = it->second;
+            }
+            prev = id;
+            prevc = c;
+        }
+        words[(size_t)(r >> 10) * 256 + (size_t)(r & 255)] |= (uint32_t)id << (8 * ((r >> 8) & 3));
+    }
+    const int npat = (int)pats.size();
+    std::vector<double> pt((size_t)npat * nd);
+    std::vector<float> pt32(pt.size());
+    for (int q = 0; q < npat; ++q)
+        for (int d = 0; d < nd; ++d) {
+            pt[(size_t)q * nd + d] = tab[pats[q][d]];
+            pt32[(size_t)q * nd + d] = (float)tab[pats[q][d]];
+        }
+    PP_TRY(dev_alloc(&A->pcode, words.size()));
+    PP_TRY(dev_alloc(&A->ptab64, pt.size()));
+    PP_TRY(dev_alloc(&A->ptab32, pt.size()));
+    if (hipMemcpyAsync(A->pcode, words.data(), sizeof(uint32_t) * words.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(A->ptab64, pt.data(), sizeof(double) * pt.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(A->ptab32, pt32.data(), sizeof(float) * pt.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("pp_matrix_create: pattern-coded upload failed");
+        return PP_EDEVICE;
+    }
+    A->npat = npat;
+    return PP_OK;
+}
 
 }  // namespace
 
@@ -889,6 +957,7 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
                             return fail(PP_EDEVICE);
                         }
                         A->ntab = (int)tab.size();
+                        if ((s = build_patterns(A, codes, nd, tab, st)) != PP_OK) return fail(s);
                     }
                 }
             }
@@ -917,15 +986,19 @@ namespace {
 
 // Point the handle at new FP64 values and refresh the copies derived from them.
 pp_status refresh_values(pp_matrix A, const double *val, hipStream_t st) {
-    if (A->dcode) {
+    if (A->dcode || A->pcode) {
         // the codes describe the old values: drop them (and a tuned pick of them)
         (void)hipStreamSynchronize(st);
         dev_free(A->dcode);
         dev_free(A->dtab64);
         dev_free(A->dtab32);
+        dev_free(A->pcode);
+        dev_free(A->ptab64);
+        dev_free(A->ptab32);
         A->ntab = 0;
+        A->npat = 0;
         for (int p = 0; p < 3; ++p)
-            if (A->variant[p] == CV_DIAC) {
+            if (A->variant[p] == CV_DIAC || A->variant[p] == CV_DIAP) {
                 A->variant[p] = CV_TILE8;
                 A->tuned[p] = 0;
             }
@@ -1065,6 +1138,11 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
         if (variant == CV_DIAC && !A->dcode) {
             set_error("pp_matrix_set_variant: no value-coded diagonal copy (too many diagonals or distinct values, "
                       "or the values changed)");
+            return PP_EINVAL;
+        }
+        if (variant == CV_DIAP && !A->pcode) {
+            set_error("pp_matrix_set_variant: no pattern-coded diagonal copy (no value-coded copy, too many "
+                      "distinct rows, or the values changed)");
             return PP_EINVAL;
         }
         if (variant == CV_TILEB8) PP_TRY(build_round_plan(A, prec, 8, &A->tileB8[prec], &A->ntileB8[prec], 0));

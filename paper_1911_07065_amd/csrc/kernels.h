@@ -41,7 +41,8 @@ enum ChainVariant : int {
     CV_DIA = 24,      // diagonal format (matrices on few diagonals): 2 rows per lane
     CV_DIA4 = 25,     // same, 1 row per lane
     CV_DIAC = 26,     // diagonal format with 1-byte codes into a table of the matrix's distinct values, 4 rows per lane
-    CV_COUNT = 27
+    CV_DIAP = 27,     // diagonal format with one byte per row: the row's pattern in a table of distinct rows
+    CV_COUNT = 28
 };
 
 // A chain step as the persistent kernel reads it from device memory.
@@ -73,6 +74,7 @@ struct StepPtrs {
 
 // Diagonals of the diagonal format, passed by value (uniform per launch).
 constexpr int kMaxDiag = 32;
+constexpr int kMaxPatEntries = 1024;  // rows patterns x diagonals of the pattern-coded format
 struct DiaOffsets {
     int nd;               // number of diagonals (0: no diagonal-format copy)
     int off[kMaxDiag];    // column - row of each diagonal, ascending
@@ -118,6 +120,14 @@ struct DevCSR {
     const double *dtab64;
     const float *dtab32;
     int ntab;
+    // pattern-coded diagonal format (absent if pcode is null): byte q of
+    // word pcode[b * 256 + t] is the pattern of row b * 1024 + q * 256 + t;
+    // the entry of a row with pattern p on diagonal d is ptab[p * nd + d]
+    // (npat * nd <= kMaxPatEntries values)
+    const uint32_t *pcode;
+    const double *ptab64;
+    const float *ptab32;
+    int npat;
     int variant[3];      // chain variant per precision
     int remap[3];        // 1: keep neighbouring workgroups on one XCD
 };

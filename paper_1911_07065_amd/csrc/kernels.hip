@@ -674,6 +674,58 @@ __global__ __launch_bounds__(256) void k_chain_diac(ChainArgs<VT, XT> a, const u
     }
 }
 
+// Pattern-coded diagonal format: the ND entries of a row are one of the
+// matrix's distinct row patterns (a constant-coefficient stencil on a box
+// has one per boundary class), so a row costs one byte. Lane t of block b
+// takes rows b*1024 + q*256 + t (q = 0..3), whose pattern ids are the bytes
+// of pcode[b*256 + t]; the pattern table is staged in LDS. Rows past n read
+// row n - 1 and are not written.
+template <typename VT, typename XT, int ND>
+__global__ __launch_bounds__(256) void k_chain_diap(ChainArgs<VT, XT> a, const uint32_t *__restrict__ pcode,
+                                                    const VT *__restrict__ ptab, int nent, DiaOffsets doff,
+                                                    int nblocks, int remap) {
+    using AT = typename Arith<XT>::T;
+    constexpr int RPT = 4;
+    __shared__ AT tab[kMaxPatEntries];
+    const int blk = remap_tile(blockIdx.x, nblocks, remap);
+    const int base = blk * 256 * RPT + (int)threadIdx.x;
+    const int n = a.n;
+    const uint32_t pw = __builtin_nontemporal_load(pcode + (long)blk * 256 + threadIdx.x);
+    int rr[RPT];
+    AT x[RPT][ND];
+    RowPre<AT> pre[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = base + q * 256;
+        rr[q] = r < n ? r : n - 1;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) x[q][d] = ldx(a.in, min(max(rr[q] + doff.off[d], 0), n - 1));
+        if (r < n) pre[q] = row_prefetch(a, r);
+    }
+    for (int i = (int)threadIdx.x; i < nent; i += 256) tab[i] = (AT)ptab[i];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const AT *t = tab + ((pw >> (8 * q)) & 0xffu) * ND;
+        AT s = AT(0);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) s += t[d] * x[q][d];
+        const int r = base + q * 256;
+        if (r < n) row_finish(a, r, s, pre[q]);
+    }
+}
+
+template <typename VT>
+const VT *diap_tab(const DevCSR &A);
+template <>
+const double *diap_tab<double>(const DevCSR &A) {
+    return A.ptab64;
+}
+template <>
+const float *diap_tab<float>(const DevCSR &A) {
+    return A.ptab32;
+}
+
 template <typename VT>
 const VT *diac_tab(const DevCSR &A);
 template <>
@@ -856,6 +908,34 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int v
                     return hipErrorInvalidValue;  // the coded copy is only built for these counts
             }
 #undef PP_DIAC_ND
+            return hipGetLastError();
+        }
+        case CV_DIAP: {
+            const int nent = A.npat * A.doff.nd;
+            if (A.doff.nd <= 0 || !A.pcode || nent <= 0 || nent > kMaxPatEntries) return hipErrorInvalidValue;
+            const int nb = (int)((A.n + 1023L) / 1024L);
+#define PP_DIAP_ND(K)                                                                                              \
+    case K:                                                                                                        \
+        hipLaunchKernelGGL((k_chain_diap<VT, XT, K>), dim3(nb), dim3(256), 0, st, a, A.pcode, diap_tab<VT>(A), nent, \
+                           A.doff, nb, remap);                                                                     \
+        break;
+            switch (A.doff.nd) {
+                PP_DIAP_ND(1)
+                PP_DIAP_ND(2)
+                PP_DIAP_ND(3)
+                PP_DIAP_ND(4)
+                PP_DIAP_ND(5)
+                PP_DIAP_ND(6)
+                PP_DIAP_ND(7)
+                PP_DIAP_ND(8)
+                PP_DIAP_ND(9)
+                PP_DIAP_ND(13)
+                PP_DIAP_ND(19)
+                PP_DIAP_ND(27)
+                default:
+                    return hipErrorInvalidValue;  // built only with the value-coded copy
+            }
+#undef PP_DIAP_ND
             return hipGetLastError();
         }
         case CV_SELLD:
@@ -1970,7 +2050,7 @@ const char *chain_variant_name(int v) {
                                           "vec8x4",  "vec16x2",  "vec16x4", "vec32x2",   "tilev8x1",
                                           "tilev16x2", "vk2x4x4", "vk4x4x2", "vk8x4x1", "vk16x2x2", "persist8",
                                           "tileb8x1", "tileb16x2", "sell64", "sell64t", "sell64x2", "sell64x4", "sell64d16", "sell64d16x4",
-                                              "dia2",   "dia1", "diac"};
+                                              "dia2",   "dia1", "diac", "diap"};
     return (v >= 0 && v < CV_COUNT) ? names[v] : "?";
 }
 

@@ -150,7 +150,7 @@ def test_bad_arguments_rejected(pp):
         pp.Matrix(np.array([0, 2, 1], dtype=np.int32), np.array([0, 1], dtype=np.int32), np.ones(2))  # rowptr
 
 
-@pytest.mark.parametrize("variant", range(27))
+@pytest.mark.parametrize("variant", range(28))
 def test_every_chain_variant_matches_oracle(pp, variant):
     # each kernel variant the autotuner may pick, with and without the XCD order
     for name in ["ragged_5000", "randsparse_20000", "convdiff3d_20"]:
@@ -172,7 +172,8 @@ def test_every_chain_variant_matches_oracle(pp, variant):
                 # the sliced-ELL copy is only built when its padding is small,
                 # the diagonal format only for matrices on few diagonals
                 assert ("sliced-ELL" in str(exc) and name == "ragged_5000") or \
-                    (("diagonal-format" in str(exc) or "value-coded" in str(exc)) and name != "convdiff3d_20"), exc
+                    (any(k in str(exc) for k in ("diagonal-format", "value-coded", "pattern-coded"))
+                     and name != "convdiff3d_20"), exc
                 continue
             assert relerr(host(pp.apply(poly, M, dev(v), "p")), ref_p) <= 1e-12
             assert relerr(host(pp.apply(poly, M, dev(v), "phi")), ref_phi) <= 1e-12
@@ -204,25 +205,27 @@ def test_diagonal_format_edge_cases(pp, case):
     M = pp.Matrix.from_csr(csr)
     poly = pp.poly_from_roots(P.roots(), keep_order=True)
     v = rhs(csr.n, 5)
-    for variant in (24, 25, 26):
+    for variant in (24, 25, 26, 27):
         for remap in (0, 1):
             say("diagonal format", case, pp.chain_variant_name(variant), remap)
             try:
                 M.set_variant("fp64", variant, remap)
             except Exception as exc:
-                # the value-coded copy needs at most 255 distinct values
-                assert variant == 26 and case == "diagonal_1000" and "value-coded" in str(exc), exc
+                # the value- and pattern-coded copies need at most 255 distinct values
+                assert variant in (26, 27) and case == "diagonal_1000" and \
+                    ("value-coded" in str(exc) or "pattern-coded" in str(exc)), exc
                 continue
             assert relerr(host(pp.apply(poly, M, dev(v), "p")), chains.apply_p(A, P.units, v)) <= 1e-12
             assert relerr(host(pp.apply(poly, M, dev(v), "phi")), chains.apply_phi(A, P.units, v)) <= 1e-12
 
 
-def test_value_coded_copy_dropped_when_values_change(pp):
+@pytest.mark.parametrize("variant", [26, 27])
+def test_value_coded_copy_dropped_when_values_change(pp, variant):
     csr = convdiff3d(20, 10, 10, 10)
     A = csr.to_scipy()
     M = pp.Matrix.from_csr(csr)
-    say("value-coded copy")
-    M.set_variant("fp32", 26, 1)
+    say("coded copy", pp.chain_variant_name(variant))
+    M.set_variant("fp32", variant, 1)
     poly = pp.poly_from_roots([3.0, 7.5], keep_order=True)
     v = rhs(csr.n, 5)
     ref = chains.apply_phi(A, [(chains.REAL, 3.0, 0.0), (chains.REAL, 7.5, 0.0)], v)
@@ -231,10 +234,53 @@ def test_value_coded_copy_dropped_when_values_change(pp):
     assert relerr(got32, ref) <= 1e-5
     M.set_values(dev(2.0 * csr.val))  # the codes no longer describe the values
     assert M.variant("fp32")[0] is None
-    with pytest.raises(Exception, match="value-coded"):
-        M.set_variant("fp32", 26, 1)
+    with pytest.raises(Exception, match="value-coded" if variant == 26 else "pattern-coded"):
+        M.set_variant("fp32", variant, 1)
     ref2 = chains.apply_phi(2.0 * A, [(chains.REAL, 3.0, 0.0), (chains.REAL, 7.5, 0.0)], v)
     assert relerr(host(pp.apply(poly, M, dev(v), "phi")), ref2) <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["fits", "over"])
+def test_pattern_coded_limit(pp, case):
+    # tridiagonal, n = 3000 (three 1024-row blocks, ragged tail): row i has
+    # diagonal 4 + (i mod P)/100, left entry -1 - (floor(i/P) mod Q)/1000 and
+    # right entry -1, so the interior rows take P Q distinct patterns and the
+    # two boundary rows two more. fits: P, Q = 127, 2 gives 256 patterns (the
+    # table's limit); over: 17, 16 gives 274. Both have few distinct values,
+    # so the value-coded copy exists in both cases.
+    import scipy.sparse as sp
+
+    from workloads.generators import CSR
+
+    n = 3000
+    P, Q = (127, 2) if case == "fits" else (17, 16)
+    i = np.arange(n)
+    dg = 4.0 + (i % P) / 100.0
+    left = -1.0 - ((i // P) % Q) / 1000.0
+    T = sp.diags([left[1:], dg, np.full(n - 1, -1.0)], [-1, 0, 1], format="csr")
+    csr = CSR(n=n, rowptr=T.indptr.astype(np.int32), colind=T.indices.astype(np.int32), val=T.data.astype(np.float64))
+    A = csr.to_scipy()
+    rows = {tuple(A[r].toarray()[0, max(r - 1, 0):r + 2]) if 0 < r < n - 1 else (r,) for r in range(n)}
+    assert len(rows) == (256 if case == "fits" else 274)
+    say("pattern limit", case)
+    M = pp.Matrix.from_csr(csr)
+    Pr = oroots.setup(A, start_vector(n, 2), 6)
+    poly = pp.poly_from_roots(Pr.roots(), keep_order=True)
+    v = rhs(n, 5)
+    ref_p = chains.apply_p(A, Pr.units, v)
+    M.set_variant("fp64", 26, 0)
+    assert relerr(host(pp.apply(poly, M, dev(v), "p")), ref_p) <= 1e-12
+    if case == "over":
+        with pytest.raises(Exception, match="pattern-coded"):
+            M.set_variant("fp64", 27, 0)
+        return
+    delta = relerr(apply_p_low(A.astype(np.float32), Pr.units, v.astype(np.float32)), ref_p)
+    for remap in (0, 1):
+        M.set_variant("fp64", 27, remap)
+        M.set_variant("fp32", 27, remap)
+        assert relerr(host(pp.apply(poly, M, dev(v), "p")), ref_p) <= 1e-12
+        assert relerr(host(pp.apply(poly, M, dev(v), "phi")), chains.apply_phi(A, Pr.units, v)) <= 1e-12
+        assert relerr(host(pp.apply(poly, M, dev(v, torch.float32), "p")), ref_p) <= 10 * delta + 1e-6
 
 
 def test_autotuner_picks_a_valid_variant(pp):
@@ -244,7 +290,7 @@ def test_autotuner_picks_a_valid_variant(pp):
     assert M.variant("fp32")[0] is None  # nothing tuned or set yet
     for prec in ("fp64", "fp32", "bf16"):
         name, remap, us = M.tune(prec)
-        assert name in [pp.chain_variant_name(v) for v in range(27)] and remap in (0, 1) and us > 0
+        assert name in [pp.chain_variant_name(v) for v in range(28)] and remap in (0, 1) and us > 0
         assert M.variant(prec) == (name, remap, us)
     M.set_variant("fp32", 3, 0)
     assert M.variant("fp32") == (pp.chain_variant_name(3), 0, 0.0)
