@@ -312,8 +312,21 @@ typedef struct pp_batch_s *pp_batch;
 pp_status pp_batch_create(int nsys, const int64_t *row_off, int64_t nnz, const int32_t *rowptr,
                           const int32_t *colind, const double *val, void *stream, pp_batch *out);
 
-/* New values for the same pattern (device double[nnz]). */
+/* New values for the same pattern (device double[nnz]). Drops the
+ * pattern-coded copy (the batch goes back to format 0). */
 pp_status pp_batch_set_values(pp_batch B, const double *val, void *stream);
+
+/* Storage the batch's sparse products read. 0: sliced-ELL. 1: pattern-coded
+ * diagonals, built by pp_batch_create when every system's entries lie on
+ * the same number of diagonals (3, 5, 7, 9, 13, 19 or 27; the offsets may
+ * differ per system), no row holds two entries of one column, and each
+ * system's rows take at most 256 distinct value tuples: one byte per row
+ * names the row's tuple in its system's table. pp_batch_create selects 1
+ * when that copy exists. Both give the same sums in a different order.
+ * pp_batch_set_format returns PP_EINVAL for a format the batch has no copy
+ * of; pp_batch_format writes the current one (host int). */
+pp_status pp_batch_set_format(pp_batch B, int format);
+pp_status pp_batch_format(pp_batch B, int *format);
 
 void pp_batch_destroy(pp_batch B);
 

@@ -72,6 +72,8 @@ SIGNATURES = {
     "pp_batch_create": (c_int, [c_int, ctypes.POINTER(c_int64), c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                 ctypes.POINTER(c_void_p)]),
     "pp_batch_set_values": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "pp_batch_set_format": (c_int, [c_void_p, c_int]),
+    "pp_batch_format": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
     "pp_batch_destroy": (None, [c_void_p]),
     "pp_batch_setup": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p),
                                ctypes.POINTER(SetupInfo)]),

@@ -545,6 +545,27 @@ class Batch:
             out.append(d)
         return x, out
 
+    BATCH_FORMATS = ("sell", "pattern")
+
+    def format(self) -> str:
+        """Storage the batch's sparse products read: "sell" (sliced-ELL) or
+        "pattern" (one byte per row naming its tuple in its system's table)."""
+        f = ctypes.c_int()
+        check(lib.pp_batch_format(self.handle, ctypes.byref(f)), "pp_batch_format")
+        return self.BATCH_FORMATS[f.value]
+
+    def set_format(self, name: str):
+        check(lib.pp_batch_set_format(self.handle, self.BATCH_FORMATS.index(name)), "pp_batch_set_format")
+
+    def set_values(self, val):
+        """New values (device or host float64[nnz], the concatenated systems'
+        entries in CSR order); drops the pattern-coded copy."""
+        v = _dev_tensor(val, torch.float64, self.device)
+        if v.numel() != self.nnz:
+            raise ValueError("values length")
+        check(lib.pp_batch_set_values(self.handle, _ptr(v), _stream(self.device)), "pp_batch_set_values")
+        torch.cuda.synchronize(self.device)
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is None or not h.value or lib is None:

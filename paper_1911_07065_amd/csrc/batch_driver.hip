@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ppgmres.h"
@@ -55,6 +56,13 @@ struct pp_batch_s {
     float *sval32 = nullptr;
     int nslices = 0;
     long npad = 0;
+    // pattern-coded copy (format 1; see pp_batch_set_format)
+    uint8_t *bpat = nullptr;
+    int32_t *poff = nullptr, *ptoff = nullptr, *sysoff = nullptr;
+    double *ptab64 = nullptr;
+    float *ptab32 = nullptr;
+    int pnd = 0;
+    int format = 0;
     // reduction blocks
     int4 *block = nullptr;
     int32_t *boff = nullptr;
@@ -83,7 +91,25 @@ struct pp_batch_s {
         s.sval64 = sval64;
         s.sval32 = sval32;
         s.nslices = nslices;
+        const bool pat = format == 1;
+        s.bpat = pat ? bpat : nullptr;
+        s.poff = pat ? poff : nullptr;
+        s.ptoff = pat ? ptoff : nullptr;
+        s.sysoff = pat ? sysoff : nullptr;
+        s.ptab64 = pat ? ptab64 : nullptr;
+        s.ptab32 = pat ? ptab32 : nullptr;
+        s.pnd = pat ? pnd : 0;
         return s;
+    }
+    void drop_patterns() {
+        dev_free(bpat);
+        dev_free(poff);
+        dev_free(ptoff);
+        dev_free(sysoff);
+        dev_free(ptab64);
+        dev_free(ptab32);
+        pnd = 0;
+        format = 0;
     }
     BatchBlocks blocks(bool masked = false) const {
         BatchBlocks b;
@@ -170,6 +196,7 @@ struct pp_batch_s {
         dev_free(sperm);
         dev_free(sval64);
         dev_free(sval32);
+        drop_patterns();
         dev_free(block);
         dev_free(boff);
         dev_free(partial);
@@ -281,6 +308,107 @@ pp_status bnorms(pp_batch B, int R, const double *v, std::vector<double> &out, h
     HIP_TRY(hipStreamSynchronize(st));
     out.resize((size_t)B->nsys * R);
     for (size_t p = 0; p < out.size(); ++p) out[p] = std::sqrt(B->hpin[p]);
+    return PP_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// The pattern-coded copy (format 1): every system's entries on the same
+// number nd of diagonals (its own offsets), at most 256 distinct rows per
+// system (a row is the tuple of its nd values, 0 where it has no entry).
+// Leaves the batch without the copy (PP_OK) when it does not qualify.
+pp_status build_batch_patterns(pp_batch B, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                               const double *val, hipStream_t st) {
+    const int nsys = B->nsys;
+    const long n = B->n;
+    if (B->nnz == 0) return PP_OK;
+    int nd = -1;
+    std::vector<int32_t> offs;
+    for (int s = 0; s < nsys; ++s) {
+        std::vector<int32_t> o;
+        for (long r = B->row_off[s]; r < B->row_off[s + 1]; ++r)
+            for (int e = rp[r]; e < rp[r + 1]; ++e) {
+                const int32_t d = ci[e] - (int32_t)r;
+                if (std::find(o.begin(), o.end(), d) == o.end()) {
+                    o.push_back(d);
+                    if ((int)o.size() > kMaxDiag) return PP_OK;
+                }
+            }
+        std::sort(o.begin(), o.end());
+        if (nd < 0) nd = (int)o.size();
+        if ((int)o.size() != nd) return PP_OK;
+        offs.insert(offs.end(), o.begin(), o.end());
+    }
+    if (!(nd == 3 || nd == 5 || nd == 7 || nd == 9 || nd == 13 || nd == 19 || nd == 27)) return PP_OK;
+    std::vector<double> hv(B->nnz);
+    if (hipMemcpyAsync(hv.data(), val, sizeof(double) * B->nnz, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("pp_batch_create: cannot read the values");
+        return PP_EDEVICE;
+    }
+    std::vector<uint8_t> pid((size_t)n, 0);
+    std::vector<double> tab;
+    std::vector<int32_t> toff(nsys), so(nsys + 1);
+    std::vector<double> tup(nd);
+    std::vector<char> seen(nd);
+    for (int s = 0; s < nsys; ++s) {
+        toff[s] = (int32_t)tab.size();
+        so[s] = (int32_t)B->row_off[s];
+        const int32_t *o = offs.data() + (size_t)s * nd;
+        std::unordered_map<std::string, int> id_of;
+        std::string prev;
+        int prev_id = -1;
+        for (long r = B->row_off[s]; r < B->row_off[s + 1]; ++r) {
+            std::fill(tup.begin(), tup.end(), 0.0);
+            std::fill(seen.begin(), seen.end(), 0);
+            for (int e = rp[r]; e < rp[r + 1]; ++e) {
+                const int d = (int)(std::lower_bound(o, o + nd, ci[e] - (int32_t)r) - o);
+                if (seen[d]) return PP_OK;  // two entries of one column
+                seen[d] = 1;
+                tup[d] = hv[e];
+            }
+            std::string key(reinterpret_cast<const char *>(tup.data()), sizeof(double) * nd);
+            int id = prev_id;
+            if (prev_id < 0 || key != prev) {
+                auto it = id_of.find(key);
+                if (it == id_of.end()) {
+                    if (id_of.size() >= 256) return PP_OK;
+                    id = (int)id_of.size();
+                    id_of.emplace(key, id);
+                    tab.insert(tab.end(), tup.begin(), tup.end());
+                } else {
+                    id = it->second;
+                }
+                prev = std::move(key);
+                prev_id = id;
+            }
+            pid[r] = (uint8_t)id;
+        }
+        if (tab.size() >= (size_t)1 << 31) return PP_OK;
+    }
+    so[nsys] = (int32_t)n;
+    std::vector<float> tab32(tab.size());
+    for (size_t q = 0; q < tab.size(); ++q) tab32[q] = (float)tab[q];
+    PP_TRY(dev_alloc(&B->bpat, pid.size()));
+    PP_TRY(dev_alloc(&B->poff, offs.size()));
+    PP_TRY(dev_alloc(&B->ptoff, toff.size()));
+    PP_TRY(dev_alloc(&B->sysoff, so.size()));
+    PP_TRY(dev_alloc(&B->ptab64, tab.size()));
+    PP_TRY(dev_alloc(&B->ptab32, tab.size()));
+    if (hipMemcpyAsync(B->bpat, pid.data(), pid.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(B->poff, offs.data(), sizeof(int32_t) * offs.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(B->ptoff, toff.data(), sizeof(int32_t) * toff.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(B->sysoff, so.data(), sizeof(int32_t) * so.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(B->ptab64, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(B->ptab32, tab32.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("pp_batch_create: pattern-coded upload failed");
+        return PP_EDEVICE;
+    }
+    B->pnd = nd;
+    B->format = 1;
     return PP_OK;
 }
 
@@ -420,6 +548,7 @@ pp_status pp_batch_create(int nsys, const int64_t *row_off, int64_t nnz, const i
     }
     if ((s = upload(d1, &B->desc_spmv, st)) != PP_OK || (s = upload(dr, &B->desc_res, st)) != PP_OK) return fail(s);
     if ((s = dev_alloc(&B->act, (size_t)nsys)) != PP_OK) return fail(s);
+    if ((s = build_batch_patterns(B, rp, ci, val, st)) != PP_OK) return fail(s);
     if (hipHostMalloc((void **)&B->actpin, sizeof(int) * nsys, hipHostMallocDefault) != hipSuccess) {
         B->actpin = nullptr;
         set_error("hipHostMalloc failed");
@@ -436,7 +565,35 @@ pp_status pp_batch_set_values(pp_batch B, const double *val, void *stream) {
         set_error("pp_batch_set_values: bad argument");
         return PP_EINVAL;
     }
+    if (B->bpat) {
+        // the patterns describe the old values
+        (void)hipStreamSynchronize(S(stream));
+        B->drop_patterns();
+    }
     HIP_TRY(launch_sell_values(B->npad, B->sperm, val, B->sval64, B->sval32, S(stream)));
+    return PP_OK;
+}
+
+pp_status pp_batch_set_format(pp_batch B, int format) {
+    if (!B || format < 0 || format > 1) {
+        set_error("pp_batch_set_format: bad argument");
+        return PP_EINVAL;
+    }
+    if (format == 1 && !B->bpat) {
+        set_error("pp_batch_set_format: no pattern-coded copy (the systems' diagonals or row patterns do not "
+                  "qualify, or the values changed)");
+        return PP_EINVAL;
+    }
+    B->format = format;
+    return PP_OK;
+}
+
+pp_status pp_batch_format(pp_batch B, int *format) {
+    if (!B || !format) {
+        set_error("pp_batch_format: bad argument");
+        return PP_EINVAL;
+    }
+    *format = B->format;
     return PP_OK;
 }
 

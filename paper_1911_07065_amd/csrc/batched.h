@@ -25,6 +25,17 @@ struct BatchSell {
     const float *sval32;
     int nslices;
     const int *active;  // per system: 0 = skip its slices (null: all run)
+    // pattern-coded copy (used when bpat is not null): the rows of system s
+    // lie on pnd diagonals with offsets poff[s*pnd + d]; row i of system s
+    // holds ptab[ptoff[s] + bpat[i]*pnd + d] on diagonal d (0 where it has
+    // no entry); system s owns rows sysoff[s] .. sysoff[s+1]-1
+    const uint8_t *bpat;
+    const int32_t *poff;
+    const int32_t *ptoff;
+    const int32_t *sysoff;
+    const double *ptab64;
+    const float *ptab32;
+    int pnd;
 };
 
 // Rows per reduction block; a block never crosses a system boundary.

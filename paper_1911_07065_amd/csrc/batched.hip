@@ -68,6 +68,46 @@ struct BChainArgs {
     XT *bufs[5];
 };
 
+// The chain update of one row after its sparse product s (R right-hand
+// sides): w = a0 s + a1 in (+ a2 aux), then acc and out as in k_chain.
+template <typename XT, int R>
+__device__ __forceinline__ void bchain_finish(const PStep &st, const XT *in, const XT *aux, const XT *vfin, XT *out,
+                                              XT *acc, long row, const typename Arith<XT>::T *s) {
+    using AT = typename Arith<XT>::T;
+    const AT a0 = (AT)st.a0, a1 = (AT)st.a1, a2 = (AT)st.a2, b0 = (AT)st.b0, b1 = (AT)st.b1;
+    AT xin[R], wv[R], t[R];
+    ldr<XT, R>(in, row, xin);
+#pragma unroll
+    for (int r = 0; r < R; ++r) wv[r] = a0 * s[r] + a1 * xin[r];
+    if (aux) {
+        ldr<XT, R>(aux, row, t);
+#pragma unroll
+        for (int r = 0; r < R; ++r) wv[r] += a2 * t[r];
+    }
+    if (acc) {
+        if (st.acc_init) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) t[r] = AT(0);
+        } else {
+            ldr<XT, R>(acc, row, t);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) t[r] = t[r] + b0 * xin[r] + b1 * wv[r];
+        str<XT, R>(acc, row, t);
+    }
+    if (out) {
+        if (vfin) {
+            ldr<XT, R>(vfin, row, t);
+#pragma unroll
+            for (int r = 0; r < R; ++r) t[r] = t[r] - wv[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) t[r] = wv[r];
+        }
+        str<XT, R>(out, row, t);
+    }
+}
+
 template <typename VT, typename XT, int R>
 __global__ __launch_bounds__(256) void k_bchain(BChainArgs<VT, XT> a) {
     using AT = typename Arith<XT>::T;
@@ -117,38 +157,56 @@ __global__ __launch_bounds__(256) void k_bchain(BChainArgs<VT, XT> a) {
         }
     }
     if (!active) return;
-    const AT a0 = (AT)st.a0, a1 = (AT)st.a1, a2 = (AT)st.a2, b0 = (AT)st.b0, b1 = (AT)st.b1;
-    AT xin[R], wv[R], t[R];
-    ldr<XT, R>(in, row, xin);
+    bchain_finish<XT, R>(st, in, aux, vfin, out, acc, row, s);
+}
+
+// The same step on the pattern-coded copy: one wave per 64-row slice; row
+// i of system sys sums ptab[ptoff[sys] + bpat[i] ND + d] x[i + poff[sys ND + d]]
+// over its ND diagonals. Columns are clamped into the system's rows (a
+// diagonal that leaves the system has a zero entry there) and rows past
+// the slice read its last row, so all loads go out unconditionally.
+template <typename VT, typename XT, int R, int ND>
+__global__ __launch_bounds__(256) void k_bchain_pat(BChainArgs<VT, XT> a, const uint8_t *__restrict__ bpat,
+                                                    const int32_t *__restrict__ poff,
+                                                    const int32_t *__restrict__ ptoff,
+                                                    const int32_t *__restrict__ sysoff, const VT *__restrict__ ptab) {
+    using AT = typename Arith<XT>::T;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= a.nslices) return;
+    const int lane = threadIdx.x & 63;
+    const int4 si = a.slice[w];
+    if (a.active && !a.active[si.z]) return;
+    const PStep st = a.desc[(long)si.z * a.K + a.k];
+    if (st.spmv < 0) return;  // this system's program is shorter
+    const bool active = lane < si.y;
+    const long row = (long)si.x + lane;
+    const XT *in = a.bufs[st.in];
+    const XT *aux = st.aux >= 0 ? a.bufs[st.aux] : nullptr;
+    const XT *vfin = st.fin ? a.bufs[0] : nullptr;
+    XT *out = st.out >= 0 ? a.bufs[st.out] : nullptr;
+    XT *acc = st.acc >= 0 ? a.bufs[st.acc] : nullptr;
+    AT s[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) wv[r] = a0 * s[r] + a1 * xin[r];
-    if (aux) {
-        ldr<XT, R>(aux, row, t);
+    for (int r = 0; r < R; ++r) s[r] = AT(0);
+    if (st.spmv) {
+        const int sys = si.z;
+        const int lo = sysoff[sys], hi = sysoff[sys + 1] - 1;
+        const int rc = si.x + min(lane, si.y - 1);
+        const VT *tb = ptab + ptoff[sys] + (int)bpat[rc] * ND;
+        VT v[ND];
+        AT xv[ND][R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) wv[r] += a2 * t[r];
-    }
-    if (acc) {
-        if (st.acc_init) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) t[r] = AT(0);
-        } else {
-            ldr<XT, R>(acc, row, t);
+        for (int d = 0; d < ND; ++d) {
+            v[d] = tb[d];
+            ldr<XT, R>(in, min(max(rc + poff[sys * ND + d], lo), hi), xv[d]);
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) t[r] = t[r] + b0 * xin[r] + b1 * wv[r];
-        str<XT, R>(acc, row, t);
-    }
-    if (out) {
-        if (vfin) {
-            ldr<XT, R>(vfin, row, t);
+        for (int d = 0; d < ND; ++d)
 #pragma unroll
-            for (int r = 0; r < R; ++r) t[r] = t[r] - wv[r];
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) t[r] = wv[r];
-        }
-        str<XT, R>(out, row, t);
+            for (int r = 0; r < R; ++r) s[r] += (AT)v[d] * xv[d][r];
     }
+    if (!active) return;
+    bchain_finish<XT, R>(st, in, aux, vfin, out, acc, row, s);
 }
 
 // One chunk of KC Krylov columns of k_bdots for R interleaved right-hand
@@ -368,9 +426,31 @@ __global__ __launch_bounds__(256) void k_bcombine(const int4 *block, const XT *V
 
 // ---- dispatch helpers -----------------------------------------------------
 
+template <typename VT, typename XT, int R>
+hipError_t bchain_pat_t(const BatchSell &S, const BChainArgs<VT, XT> &a, const VT *ptab, unsigned g, hipStream_t st) {
+#define PP_BPAT_ND(K)                                                                                             \
+    case K:                                                                                                       \
+        hipLaunchKernelGGL((k_bchain_pat<VT, XT, R, K>), dim3(g), dim3(256), 0, st, a, S.bpat, S.poff, S.ptoff,   \
+                           S.sysoff, ptab);                                                                       \
+        break;
+    switch (S.pnd) {
+        PP_BPAT_ND(3)
+        PP_BPAT_ND(5)
+        PP_BPAT_ND(7)
+        PP_BPAT_ND(9)
+        PP_BPAT_ND(13)
+        PP_BPAT_ND(19)
+        PP_BPAT_ND(27)
+        default:
+            return hipErrorInvalidValue;  // the copy is built only for these counts
+    }
+#undef PP_BPAT_ND
+    return hipGetLastError();
+}
+
 template <typename VT, typename XT>
-hipError_t bchain_t(const BatchSell &S, const VT *sval, int R, const PStep *desc, int K, int k, void *const bufs[5],
-                    hipStream_t st) {
+hipError_t bchain_t(const BatchSell &S, const VT *sval, const VT *ptab, int R, const PStep *desc, int K, int k,
+                    void *const bufs[5], hipStream_t st) {
     BChainArgs<VT, XT> a;
     a.slice = S.slice;
     a.sptr = S.sptr;
@@ -384,6 +464,18 @@ hipError_t bchain_t(const BatchSell &S, const VT *sval, int R, const PStep *desc
     for (int i = 0; i < 5; ++i) a.bufs[i] = (XT *)bufs[i];
     const unsigned g = (unsigned)((S.nslices + 3) / 4);
     if (g == 0) return hipSuccess;
+    if (S.bpat) {
+        switch (R) {
+            case 1:
+                return bchain_pat_t<VT, XT, 1>(S, a, ptab, g, st);
+            case 2:
+                return bchain_pat_t<VT, XT, 2>(S, a, ptab, g, st);
+            case 4:
+                return bchain_pat_t<VT, XT, 4>(S, a, ptab, g, st);
+            default:
+                return hipErrorInvalidValue;
+        }
+    }
     switch (R) {
         case 1:
             hipLaunchKernelGGL((k_bchain<VT, XT, 1>), dim3(g), dim3(256), 0, st, a);
@@ -505,11 +597,11 @@ hipError_t launch_bchain(const BatchSell &S, int prec, int R, const PStep *desc,
                          hipStream_t st) {
     switch (prec) {
         case 0:
-            return bchain_t<double, double>(S, S.sval64, R, desc, K, k, bufs, st);
+            return bchain_t<double, double>(S, S.sval64, S.ptab64, R, desc, K, k, bufs, st);
         case 1:
-            return bchain_t<float, float>(S, S.sval32, R, desc, K, k, bufs, st);
+            return bchain_t<float, float>(S, S.sval32, S.ptab32, R, desc, K, k, bufs, st);
         case 2:
-            return bchain_t<float, uint16_t>(S, S.sval32, R, desc, K, k, bufs, st);
+            return bchain_t<float, uint16_t>(S, S.sval32, S.ptab32, R, desc, K, k, bufs, st);
     }
     return hipErrorInvalidValue;
 }

@@ -43,12 +43,15 @@ SMALL = [(16, 3.0, 1000, 5000), (23, 40.0, 1001, 5001), (31, 0.0, 1002, 5002), (
          (9, 7.0, 1004, 5004), (28, 25.0, 1005, 5005)]
 
 
+@pytest.mark.parametrize("fmt", ["pattern", "sell"])
 @pytest.mark.parametrize("inner", ["fp64", "fp32"])
 @pytest.mark.parametrize("R", [1, 4])
-def test_small_batch_matches_single_solves(pp, inner, R):
+def test_small_batch_matches_single_solves(pp, inner, R, fmt):
     csrs = _systems(SMALL)
-    say("batch small", inner, R)
+    say("batch small", inner, R, fmt)
     Bt = pp.Batch(csrs)
+    assert Bt.format() == "pattern"  # every system is a 5-point stencil: 9 row patterns each
+    Bt.set_format(fmt)
     polys = Bt.setup(dev(_v0(SMALL)), 8)
     brs = _rhs_block(SMALL, R)
     bmat = np.concatenate(brs, axis=1)  # (R, n_total)
@@ -74,6 +77,40 @@ def test_small_batch_matches_single_solves(pp, inner, R):
     # the whole block system
     R_all = bmat - (Abig @ X.T).T
     assert np.all(np.linalg.norm(R_all, axis=1) <= 1e-8 * np.linalg.norm(bmat, axis=1) * np.sqrt(len(csrs)))
+
+
+def test_batch_pattern_copy_rules(pp):
+    # a batch whose systems lie on different numbers of diagonals has no
+    # pattern-coded copy; new values drop it, and the sliced-ELL products
+    # then use the new values
+    import scipy.sparse as sp
+
+    from workloads.generators import CSR
+
+    T = sp.diags([np.full(99, -1.0), np.full(100, 2.5), np.full(99, -1.2)], [-1, 0, 1], format="csr")
+    tri = CSR(n=100, rowptr=T.indptr.astype(np.int32), colind=T.indices.astype(np.int32),
+              val=T.data.astype(np.float64))
+    say("batch pattern rules")
+    assert pp.Batch([convdiff2d(12, 3.0), tri]).format() == "sell"
+    with pytest.raises(Exception, match="pattern-coded"):
+        pp.Batch([convdiff2d(12, 3.0), tri]).set_format("pattern")
+    specs = SMALL[:3]
+    csrs = _systems(specs)
+    Bt = pp.Batch(csrs)
+    assert Bt.format() == "pattern"
+    polys = Bt.setup(dev(_v0(specs)), 8)
+    bd = Bt.interleave(np.concatenate(_rhs_block(specs, 1), axis=1))
+    x1, i1 = Bt.solve(polys, bd, 1, tol=1e-10, m=30, inner="fp64")
+    vals = np.concatenate([c.val for c in csrs])
+    Bt.set_values(2.0 * vals)
+    assert Bt.format() == "sell"
+    with pytest.raises(Exception, match="pattern-coded"):
+        Bt.set_format("pattern")
+    # (2A) x = b: x is half the first solution (same roots, scaled problem)
+    polys2 = Bt.setup(dev(_v0(specs)), 8)
+    x2, i2 = Bt.solve(polys2, bd, 1, tol=1e-10, m=30, inner="fp64")
+    assert all(i["converged"] for i in i1 + i2)
+    assert relerr(host(x2), 0.5 * host(x1)) < 1e-8
 
 
 def test_batch_rejects_coupled_blocks(pp):
@@ -147,16 +184,18 @@ def test_batched_config_full_size(pp):
         "s; speed-up", round(t_loop / t_batch, 2))
 
 
+@pytest.mark.parametrize("fmt", ["pattern", "sell"])
 @pytest.mark.parametrize("R", [1, 4])
-def test_batched_graph_replays_equal_eager(pp, R):
+def test_batched_graph_replays_equal_eager(pp, R, fmt):
     # Arnoldi steps captured into HIP graphs and replayed over several cycles
     # (with eager launches, host work and synchronisations between replays)
     # give the eager result bit for bit: x, every pair's counters and the
     # residual history of every cycle
     specs = SMALL
     csrs = _systems(specs)
-    say("batched graphs", R)
+    say("batched graphs", R, fmt)
     Bt = pp.Batch(csrs)
+    Bt.set_format(fmt)
     bd = Bt.interleave(np.concatenate(_rhs_block(specs, R), axis=1))
     polys = Bt.setup(dev(_v0(specs)), 6)
     xe, ie = Bt.solve(polys, bd, R, tol=1e-11, m=8, inner="fp32", graphs=False)
