@@ -288,10 +288,20 @@ pp_status bcgs2(pp_batch B, int prec, int R, const BWork &w, int j, double *Hbas
     void *wv = bcol(w, prec, j + 1);
     HIP_TRY(launch_bdots(bl, prec, R, w.V, w.ldv, ncols, wv, B->partial, B->ldp, st));
     HIP_TRY(launch_bred(bl, R, B->partial, B->ldp, ncols * R, B->h1, B->ldp, Hbase, pstride, 1, st));
-    HIP_TRY(launch_bupdate(bl, prec, R, w.V, w.ldv, ncols, B->h1, B->ldp, wv, nullptr, st));
+    if (ncols <= bupdate_dots_max_cols(prec)) {
+        // w -= V h1 with h2 = V^T w and ||w||^2 from the same read of V; then
+        // H += h2, the norm from ||w||^2 - ||h2||^2, and w = (w - V h2) / norm
+        // in one more read
+        HIP_TRY(launch_bupdate_dots(bl, prec, R, w.V, w.ldv, ncols, B->h1, B->ldp, wv, B->partial, B->ldp, st));
+        HIP_TRY(launch_bred(bl, R, B->partial, B->ldp, ncols * R + R, B->h2, B->ldp, nullptr, 0, 0, st));
+        HIP_TRY(launch_bfinish(bl, R, ncols, B->h2, B->ldp, Hbase, pstride, B->inv, st));
+        HIP_TRY(launch_bupdate(bl, prec, R, w.V, w.ldv, ncols, B->h2, B->ldp, wv, nullptr, B->inv, st));
+        return PP_OK;
+    }
+    HIP_TRY(launch_bupdate(bl, prec, R, w.V, w.ldv, ncols, B->h1, B->ldp, wv, nullptr, nullptr, st));
     HIP_TRY(launch_bdots(bl, prec, R, w.V, w.ldv, ncols, wv, B->partial, B->ldp, st));
     HIP_TRY(launch_bred(bl, R, B->partial, B->ldp, ncols * R, B->h2, B->ldp, Hbase, pstride, 2, st));
-    HIP_TRY(launch_bupdate(bl, prec, R, w.V, w.ldv, ncols, B->h2, B->ldp, wv, B->npart, st));
+    HIP_TRY(launch_bupdate(bl, prec, R, w.V, w.ldv, ncols, B->h2, B->ldp, wv, B->npart, nullptr, st));
     HIP_TRY(launch_bnorm(bl, R, B->npart, Hbase + ncols, pstride, B->inv, st));
     HIP_TRY(launch_bscale(bl, prec, prec, R, wv, B->inv, wv, st));
     return PP_OK;
@@ -618,7 +628,7 @@ pp_status pp_batch_setup(pp_batch B, const double *v0, int d, int add_roots, voi
     // V0 = v0 / ||v0|| per system
     void *v0c = bcol(w, prec, 0);
     HIP_TRY(hipMemcpyAsync(v0c, v0, sizeof(double) * B->n, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(launch_bupdate(bl, prec, R, w.V, w.ldv, 0, B->h1, B->ldp, v0c, B->npart, st));
+    HIP_TRY(launch_bupdate(bl, prec, R, w.V, w.ldv, 0, B->h1, B->ldp, v0c, B->npart, nullptr, st));
     HIP_TRY(launch_bnorm(bl, R, B->npart, nullptr, 0, B->inv, st));
     HIP_TRY(launch_bscale(bl, prec, prec, R, v0c, B->inv, v0c, st));
     const int ld = d + 1;

@@ -64,10 +64,21 @@ hipError_t launch_bdots(const BatchBlocks &B, int prec, int R, const void *V, lo
 // order); if H: H[p*pstride + t/R] (hmode 1: =, 2: +=) for pair p = s*R + t%R.
 hipError_t launch_bred(const BatchBlocks &B, int R, const double *partial, int ldp, int nt, double *h, int ldh,
                        double *H, long pstride, int hmode, hipStream_t st);
-// w[i*R+r] -= sum_c V_c[i*R+r] h[s*ldh + c*R + r]; with npart, per-block sums
-// of the new w^2 in npart[b*R + r].
+// w[i*R+r] -= sum_c V_c[i*R+r] h[s*ldh + c*R + r], then times scale[s*R + r]
+// if scale is not null; with npart, per-block sums of the new w^2 in
+// npart[b*R + r].
 hipError_t launch_bupdate(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols, const double *h,
-                          int ldh, void *w, double *npart, hipStream_t st);
+                          int ldh, void *w, double *npart, const double *scale, hipStream_t st);
+// Fused CGS2 pass (ncols <= bupdate_dots_max_cols(prec)): w -= V h as above,
+// then partial[b*ldp + c*R + r] = block b's sum of V_c w (c < ncols) and
+// partial[b*ldp + ncols*R + r] its sum of w^2.
+int bupdate_dots_max_cols(int prec);
+hipError_t launch_bupdate_dots(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols,
+                               const double *h, int ldh, void *w, double *partial, int ldp, hipStream_t st);
+// per pair p = s*R + r: H[p*pstride + c] += h2[s*ldh + c*R + r] (c < ncols),
+// H[p*pstride + ncols] = sqrt(h2[s*ldh + ncols*R + r] - sum_c h2^2), inv[p] = its inverse (0 if 0)
+hipError_t launch_bfinish(const BatchBlocks &B, int R, int ncols, const double *h2, int ldh, double *H, long pstride,
+                          double *inv, hipStream_t st);
 // per pair: norm = sqrt(sum_b npart[b*R + r]); H[p*pstride] = norm; inv[p] = 1/norm (0 if 0)
 hipError_t launch_bnorm(const BatchBlocks &B, int R, const double *npart, double *H, long pstride, double *inv,
                         hipStream_t st);

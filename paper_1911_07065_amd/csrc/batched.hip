@@ -319,7 +319,8 @@ __global__ __launch_bounds__(256) void k_bred(const int32_t *boff, int R, const 
 
 template <typename XT, int R>
 __global__ __launch_bounds__(256) void k_bupdate(const int4 *block, const int *active, const XT *V, long ldv, int ncols,
-                                                 const double *h, int ldh, XT *w, double *npart) {
+                                                 const double *h, int ldh, XT *w, double *npart,
+                                                 const double *scale) {
     __shared__ double red[4][R];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int4 bi = block[blockIdx.x];
@@ -338,7 +339,8 @@ __global__ __launch_bounds__(256) void k_bupdate(const int4 *block, const int *a
         ldr<XT, R>(w, i, wr);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double wn = (double)wr[r] - acc[r];
+            double wn = (double)wr[r] - acc[r];
+            if (scale) wn *= scale[(long)bi.z * R + r];
             wr[r] = (typename Arith<XT>::T)wn;
             const double stv = stored_value(w, wn);
             sq[r] += stv * stv;
@@ -353,6 +355,87 @@ __global__ __launch_bounds__(256) void k_bupdate(const int4 *block, const int *a
     }
     __syncthreads();
     if (tid < R) npart[(long)blockIdx.x * R + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+}
+
+// Fused pass of batched CGS2 (up to KMAX columns): each thread owns the
+// elements e = i*R + r of its block with a fixed right-hand side r, keeps
+// the element's KMAX basis values in registers, forms w' = w - V h1 (h1 of
+// pair (sys, r)) and adds up V^T w' and ||w'||^2 per r:
+// partial[b*ldp + k*R + r] for k < ncols, partial[b*ldp + ncols*R + r].
+// Columns past ncols re-read the last one with a zero coefficient and
+// their sums are dropped.
+template <typename XT, int KMAX, int R>
+__global__ __launch_bounds__(256) void k_bupdate_dots(const int4 *block, const int *active, const XT *V, long ldv,
+                                                      int ncols, const double *h, int ldh, XT *w, double *partial,
+                                                      int ldp) {
+    using AT = typename Arith<XT>::T;
+    __shared__ double hs[KMAX * R];
+    __shared__ double sm[4][KMAX * R + R];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int4 bi = block[blockIdx.x];
+    if (active && !active[bi.z]) return;
+    for (int t = tid; t < KMAX * R; t += 256) hs[t] = t < ncols * R ? h[(long)bi.z * ldh + t] : 0.0;
+    __syncthreads();
+    const int r = tid % R;
+    const long e0 = (long)bi.x * R, e1 = ((long)bi.x + bi.y) * R;
+    AT acc[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) acc[k] = AT(0);
+    double sq = 0.0;
+    for (long e = e0 + tid; e < e1; e += 256) {
+        AT vr[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) vr[k] = (AT)ldx(V, e + (long)(k < ncols ? k : ncols - 1) * ldv);
+        double wi = (double)ldx(w, e);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) wi -= (double)vr[k] * hs[k * R + r];
+        stx(w, e, (AT)wi);
+        const double wst = stored_value(w, wi);
+        sq += wst * wst;
+        const AT ws = (AT)wst;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) acc[k] += vr[k] * ws;
+    }
+    // sums over the lanes of one r (lanes r, r + R, ...), then over waves
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        double t = (double)acc[k];
+#pragma unroll
+        for (int off = 32; off >= R; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane < R) sm[wave][k * R + lane] = t;
+    }
+#pragma unroll
+    for (int off = 32; off >= R; off >>= 1) sq += __shfl_xor(sq, off, 64);
+    if (lane < R) sm[wave][KMAX * R + lane] = sq;
+    __syncthreads();
+    double *prow = partial + (long)blockIdx.x * ldp;
+    for (int t = tid; t < ncols * R; t += 256) prow[t] = ((sm[0][t] + sm[1][t]) + sm[2][t]) + sm[3][t];
+    if (tid < R) {
+        const int t = KMAX * R + tid;
+        prow[ncols * R + tid] = ((sm[0][t] + sm[1][t]) + sm[2][t]) + sm[3][t];
+    }
+}
+
+// After the fused pass, per pair p = s*R + r: H[p][k] += h2[s][k*R + r]
+// (k < ncols), and the norm of w'' = w' - V h2 from ||w'||^2 - ||h2||^2
+// (h2[s][ncols*R + r] holds ||w'||^2): H[p][ncols] = ||w''||,
+// inv[p] = 1/||w''|| (0 if zero).
+__global__ __launch_bounds__(64) void k_bfinish(int nsys, int R, int ncols, const double *h2, int ldh, double *H,
+                                                long pstride, double *inv) {
+    const int p = blockIdx.x * 64 + threadIdx.x;
+    if (p >= nsys * R) return;
+    const int s = p / R, r = p % R;
+    const double *hp = h2 + (long)s * ldh;
+    double *Hp = H + (long)p * pstride;
+    double ss = 0.0;
+    for (int k = 0; k < ncols; ++k) {
+        const double c = hp[k * R + r];
+        Hp[k] += c;
+        ss += c * c;
+    }
+    const double nrm = sqrt(fmax(hp[ncols * R + r] - ss, 0.0));
+    Hp[ncols] = nrm;
+    inv[p] = nrm > 0.0 ? 1.0 / nrm : 0.0;
 }
 
 __global__ __launch_bounds__(64) void k_bnorm(const int32_t *boff, int nsys, int R, const double *npart, double *H,
@@ -517,25 +600,62 @@ hipError_t bdots_t(const BatchBlocks &B, int R, const XT *V, long ldv, int ncols
 
 template <typename XT>
 hipError_t bupdate_t(const BatchBlocks &B, int R, const XT *V, long ldv, int ncols, const double *h, int ldh, XT *w,
-                     double *npart, hipStream_t st) {
+                     double *npart, const double *scale, hipStream_t st) {
     if (B.nblocks == 0) return hipSuccess;
     switch (R) {
         case 1:
             hipLaunchKernelGGL((k_bupdate<XT, 1>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, h, ldh, w,
-                               npart);
+                               npart, scale);
             break;
         case 2:
             hipLaunchKernelGGL((k_bupdate<XT, 2>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, h, ldh, w,
-                               npart);
+                               npart, scale);
             break;
         case 4:
             hipLaunchKernelGGL((k_bupdate<XT, 4>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, h, ldh, w,
-                               npart);
+                               npart, scale);
             break;
         default:
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename XT, int R>
+hipError_t bupdate_dots_r(const BatchBlocks &B, const XT *V, long ldv, int ncols, const double *h, int ldh, XT *w,
+                          double *partial, int ldp, hipStream_t st) {
+#define PP_BUD(K)                                                                                                  \
+    if (ncols <= K) {                                                                                              \
+        hipLaunchKernelGGL((k_bupdate_dots<XT, K, R>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, \
+                           ncols, h, ldh, w, partial, ldp);                                                        \
+        return hipGetLastError();                                                                                  \
+    }
+    PP_BUD(8)
+    PP_BUD(16)
+    PP_BUD(24)
+    PP_BUD(32)
+    PP_BUD(40)
+    PP_BUD(48)
+    if constexpr (sizeof(XT) < 8) {
+        PP_BUD(64)
+    }
+#undef PP_BUD
+    return hipErrorInvalidValue;
+}
+
+template <typename XT>
+hipError_t bupdate_dots_t(const BatchBlocks &B, int R, const XT *V, long ldv, int ncols, const double *h, int ldh,
+                          XT *w, double *partial, int ldp, hipStream_t st) {
+    if (B.nblocks == 0 || ncols < 1) return hipSuccess;
+    switch (R) {
+        case 1:
+            return bupdate_dots_r<XT, 1>(B, V, ldv, ncols, h, ldh, w, partial, ldp, st);
+        case 2:
+            return bupdate_dots_r<XT, 2>(B, V, ldv, ncols, h, ldh, w, partial, ldp, st);
+        case 4:
+            return bupdate_dots_r<XT, 4>(B, V, ldv, ncols, h, ldh, w, partial, ldp, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename TI, typename TO>
@@ -627,16 +747,40 @@ hipError_t launch_bred(const BatchBlocks &B, int R, const double *partial, int l
 }
 
 hipError_t launch_bupdate(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols, const double *h,
-                          int ldh, void *w, double *npart, hipStream_t st) {
+                          int ldh, void *w, double *npart, const double *scale, hipStream_t st) {
     switch (prec) {
         case 0:
-            return bupdate_t<double>(B, R, (const double *)V, ldv, ncols, h, ldh, (double *)w, npart, st);
+            return bupdate_t<double>(B, R, (const double *)V, ldv, ncols, h, ldh, (double *)w, npart, scale, st);
         case 1:
-            return bupdate_t<float>(B, R, (const float *)V, ldv, ncols, h, ldh, (float *)w, npart, st);
+            return bupdate_t<float>(B, R, (const float *)V, ldv, ncols, h, ldh, (float *)w, npart, scale, st);
         case 2:
-            return bupdate_t<uint16_t>(B, R, (const uint16_t *)V, ldv, ncols, h, ldh, (uint16_t *)w, npart, st);
+            return bupdate_t<uint16_t>(B, R, (const uint16_t *)V, ldv, ncols, h, ldh, (uint16_t *)w, npart, scale, st);
     }
     return hipErrorInvalidValue;
+}
+
+int bupdate_dots_max_cols(int prec) { return prec == 0 ? 48 : 64; }
+
+hipError_t launch_bupdate_dots(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols,
+                               const double *h, int ldh, void *w, double *partial, int ldp, hipStream_t st) {
+    switch (prec) {
+        case 0:
+            return bupdate_dots_t<double>(B, R, (const double *)V, ldv, ncols, h, ldh, (double *)w, partial, ldp, st);
+        case 1:
+            return bupdate_dots_t<float>(B, R, (const float *)V, ldv, ncols, h, ldh, (float *)w, partial, ldp, st);
+        case 2:
+            return bupdate_dots_t<uint16_t>(B, R, (const uint16_t *)V, ldv, ncols, h, ldh, (uint16_t *)w, partial, ldp,
+                                            st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bfinish(const BatchBlocks &B, int R, int ncols, const double *h2, int ldh, double *H, long pstride,
+                          double *inv, hipStream_t st) {
+    const int np = B.nsys * R;
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bfinish, dim3((np + 63) / 64), dim3(64), 0, st, B.nsys, R, ncols, h2, ldh, H, pstride, inv);
+    return hipGetLastError();
 }
 
 hipError_t launch_bnorm(const BatchBlocks &B, int R, const double *npart, double *H, long pstride, double *inv,

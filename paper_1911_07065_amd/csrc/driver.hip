@@ -64,6 +64,16 @@ struct pp_matrix_s {
     double *dtab64 = nullptr;
     float *dtab32 = nullptr;
     int ntab = 0;
+    // column-banded CSR copies (matrices whose entries lie far from the
+    // diagonal): c = 0 two bands, c = 1 four; bperm maps entries to CSR
+    int32_t *brow[2] = {nullptr, nullptr}, *bcol[2] = {nullptr, nullptr}, *bperm[2] = {nullptr, nullptr};
+    double *bval64[2] = {nullptr, nullptr};
+    float *bval32[2] = {nullptr, nullptr};
+    int4 *btile[2] = {nullptr, nullptr};
+    int btoff[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+    int bandK[2] = {0, 0};
+    long bnnz[2] = {0, 0};
+    double *bpart = nullptr;
     // pattern-coded diagonal copy (few distinct rows; dropped with the value codes)
     uint32_t *pcode = nullptr;
     double *ptab64 = nullptr;
@@ -135,6 +145,16 @@ struct pp_matrix_s {
         d.dtab64 = dtab64;
         d.dtab32 = dtab32;
         d.ntab = ntab;
+        for (int c = 0; c < 2; ++c) {
+            d.brow[c] = brow[c];
+            d.bcol[c] = bcol[c];
+            d.bval64[c] = bval64[c];
+            d.bval32[c] = bval32[c];
+            d.btile[c] = btile[c];
+            for (int k = 0; k < 5; ++k) d.btoff[c][k] = btoff[c][k];
+            d.bandK[c] = bandK[c];
+        }
+        d.bpart = bpart;
         d.pcode = pcode;
         d.ptab64 = ptab64;
         d.ptab32 = ptab32;
@@ -236,6 +256,15 @@ struct pp_matrix_s {
         dev_free(pcode);
         dev_free(ptab64);
         dev_free(ptab32);
+        for (int c = 0; c < 2; ++c) {
+            dev_free(brow[c]);
+            dev_free(bcol[c]);
+            dev_free(bperm[c]);
+            dev_free(bval64[c]);
+            dev_free(bval32[c]);
+            dev_free(btile[c]);
+        }
+        dev_free(bpart);
         dev_free(val_own);
         dev_free(scale);
         dev_free(sval64);
@@ -379,6 +408,7 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
         if (v == CV_PERSIST || ((v == CV_SELL || v == CV_SELLT || v == CV_SELL2 || v == CV_SELL4) && A->nslices == 0) ||
             ((v == CV_SELLD || v == CV_SELLD4) && !A->sdel) || ((v == CV_DIA || v == CV_DIA4) && A->h_doff.empty()) ||
             (v == CV_DIAC && !A->dcode) || (v == CV_DIAP && !A->pcode) ||
+            (v == CV_BAND2 && A->bandK[0] == 0) || (v == CV_BAND4 && A->bandK[1] == 0) ||
             (v == CV_TILEB8 && A->ntileB8[prec] == 0) ||
             (v == CV_TILEB16 && A->ntileB16[prec] == 0))
             continue;
@@ -627,6 +657,58 @@ pp_status dev_norm(pp_matrix A, int prec, const void *x, double *out, hipStream_
 }
 
 bool valid_prec(int p) { return p >= 0 && p <= 2; }
+
+// Column-banded CSR copy c with K bands: band k holds the entries whose
+// column lies in [k n / K, (k+1) n / K), in CSR order, with its own row
+// pointers (offsets into the shared entry arrays) and 256-row tiles of at
+// most 2044 entries.
+pp_status build_bands(pp_matrix A, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, const double *val,
+                      int c, int K, hipStream_t st) {
+    const int64_t n = A->n, nnz = A->nnz;
+    std::vector<int32_t> brp((size_t)K * (n + 1)), bc(nnz), bp(nnz);
+    std::vector<int64_t> cnt(K, 0);
+    for (int64_t e = 0; e < nnz; ++e) cnt[(int)((int64_t)ci[e] * K / n)]++;
+    std::vector<int64_t> start(K + 1, 0);
+    for (int k = 0; k < K; ++k) start[k + 1] = start[k] + cnt[k];
+    std::vector<int64_t> pos(start.begin(), start.end() - 1);
+    for (int64_t r = 0; r < n; ++r) {
+        for (int k = 0; k < K; ++k) brp[(size_t)k * (n + 1) + r] = (int32_t)pos[k];
+        for (int e = rp[r]; e < rp[r + 1]; ++e) {
+            const int k = (int)((int64_t)ci[e] * K / n);
+            bc[pos[k]] = ci[e];
+            bp[pos[k]] = e;
+            ++pos[k];
+        }
+    }
+    for (int k = 0; k < K; ++k) brp[(size_t)k * (n + 1) + n] = (int32_t)pos[k];
+    std::vector<int4> tiles, t;
+    A->btoff[c][0] = 0;
+    for (int k = 0; k < K; ++k) {
+        build_tiles(brp.data() + (size_t)k * (n + 1), (int)n, 256, 256 * 8 - 4, t);
+        tiles.insert(tiles.end(), t.begin(), t.end());
+        A->btoff[c][k + 1] = (int)tiles.size();
+    }
+    PP_TRY(dev_alloc(&A->brow[c], brp.size()));
+    PP_TRY(dev_alloc(&A->bcol[c], (size_t)nnz));
+    PP_TRY(dev_alloc(&A->bperm[c], (size_t)nnz));
+    PP_TRY(dev_alloc(&A->bval64[c], (size_t)nnz));
+    PP_TRY(dev_alloc(&A->bval32[c], (size_t)nnz));
+    PP_TRY(dev_alloc(&A->btile[c], tiles.size()));
+    if (!A->bpart) PP_TRY(dev_alloc(&A->bpart, (size_t)n));
+    if (hipMemcpyAsync(A->brow[c], brp.data(), sizeof(int32_t) * brp.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(A->bcol[c], bc.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(A->bperm[c], bp.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(A->btile[c], tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        launch_sell_values(nnz, A->bperm[c], val, A->bval64[c], A->bval32[c], st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("pp_matrix_create: column-banded upload failed");
+        return PP_EDEVICE;
+    }
+    A->bnnz[c] = nnz;
+    A->bandK[c] = K;
+    return PP_OK;
+}
 
 // Pattern-coded copy from the value codes (row r's nd codes are
 // codes[r G 8 .. r G 8 + nd)): the distinct code tuples of the rows become
@@ -963,6 +1045,12 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
             }
         }
     }
+    // column-banded copies for large matrices without a diagonal-format copy
+    // (their gathers reach across the whole input)
+    if (nnz > 0 && n >= 4096 && A->h_doff.empty()) {
+        if ((s = build_bands(A, rp, ci, val, 0, 2, st)) != PP_OK) return fail(s);
+        if ((s = build_bands(A, rp, ci, val, 1, 4, st)) != PP_OK) return fail(s);
+    }
     {
         // tuning program of the persistent kernel: 8 sparse products P0 -> P1 -> P0 ...
         std::vector<PStep> h(8);
@@ -1006,6 +1094,8 @@ pp_status refresh_values(pp_matrix A, const double *val, hipStream_t st) {
     A->val = val;
     HIP_TRY(launch_val_to_f32(A->nnz, val, A->val32, st));
     if (A->nslices > 0) HIP_TRY(launch_sell_values(A->npad, A->sperm, val, A->sval64, A->sval32, st));
+    for (int c = 0; c < 2; ++c)
+        if (A->bandK[c] > 0) HIP_TRY(launch_sell_values(A->bnnz[c], A->bperm[c], val, A->bval64[c], A->bval32[c], st));
     if (!A->h_doff.empty())
         HIP_TRY(launch_sell_values((long)A->h_doff.size() * (((long)A->n + 255) / 256) * 256, A->dperm, val,
                                    A->dval64, A->dval32, st));
@@ -1138,6 +1228,11 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
         if (variant == CV_DIAC && !A->dcode) {
             set_error("pp_matrix_set_variant: no value-coded diagonal copy (too many diagonals or distinct values, "
                       "or the values changed)");
+            return PP_EINVAL;
+        }
+        if ((variant == CV_BAND2 && A->bandK[0] == 0) || (variant == CV_BAND4 && A->bandK[1] == 0)) {
+            set_error("pp_matrix_set_variant: no column-banded copy (built only for matrices of at least 4096 rows "
+                      "whose entries lie far from the diagonal)");
             return PP_EINVAL;
         }
         if (variant == CV_DIAP && !A->pcode) {

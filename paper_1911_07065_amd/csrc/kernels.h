@@ -42,7 +42,9 @@ enum ChainVariant : int {
     CV_DIA4 = 25,     // same, 1 row per lane
     CV_DIAC = 26,     // diagonal format with 1-byte codes into a table of the matrix's distinct values, 4 rows per lane
     CV_DIAP = 27,     // diagonal format with one byte per row: the row's pattern in a table of distinct rows
-    CV_COUNT = 28
+    CV_BAND2 = 28,    // tile8x1 on 2 column bands, one launch per band (partial row sums in between)
+    CV_BAND4 = 29,    // the same with 4 column bands
+    CV_COUNT = 30
 };
 
 // A chain step as the persistent kernel reads it from device memory.
@@ -106,6 +108,20 @@ struct DevCSR {
     const double *sval64;
     const float *sval32;
     int nslices;
+    // column-banded CSR copies (c = 0: 2 bands, c = 1: 4 bands; absent if
+    // bandK[c] == 0): band k holds the entries with columns in
+    // [k n / K, (k+1) n / K); its row pointers are brow[c][k (n + 1) ..]
+    // (offsets into bcol[c] / bval[c]) and its 256-row tiles are
+    // btile[c][btoff[c][k] .. btoff[c][k+1]). bpart: n partial row sums
+    // (8 bytes each) carried from one band to the next.
+    const int32_t *brow[2];
+    const int32_t *bcol[2];
+    const double *bval64[2];
+    const float *bval32[2];
+    const int4 *btile[2];
+    int btoff[2][5];
+    int bandK[2];
+    void *bpart;
     // diagonal-format copy (absent if doff.nd == 0): the entry of row i on
     // diagonal d is dval[((i / 256) nd + d) 256 + i % 256] (0 where the
     // diagonal leaves the matrix or holds no stored entry), its column

@@ -52,6 +52,10 @@ struct ChainArgs {
     typename Arith<XT>::T a0, a1, a2, b0, b1;
     int acc_init;
     int n;
+    // banded products: add pin[r] to the row's sum; with pout, store the sum
+    // there instead of finishing the row
+    const typename Arith<XT>::T *pin;
+    typename Arith<XT>::T *pout;
 };
 
 template <typename AT>
@@ -63,6 +67,10 @@ template <typename VT, typename XT>
 __device__ __forceinline__ RowPre<typename Arith<XT>::T> row_prefetch(const ChainArgs<VT, XT> &a, int r) {
     using AT = typename Arith<XT>::T;
     RowPre<AT> p;
+    if (a.pout) {  // a partial pass reads nothing but its entries
+        p.xin = p.aux = p.vf = p.acc = AT(0);
+        return p;
+    }
     p.xin = ldx(a.in, r);
     p.aux = a.aux ? (AT)ldx(a.aux, r) : AT(0);
     p.vf = a.vfin ? (AT)ldx(a.vfin, r) : AT(0);
@@ -74,6 +82,11 @@ template <typename VT, typename XT>
 __device__ __forceinline__ void row_finish(const ChainArgs<VT, XT> &a, int r, typename Arith<XT>::T s,
                                            const RowPre<typename Arith<XT>::T> &p) {
     using AT = typename Arith<XT>::T;
+    if (a.pin) s += a.pin[r];
+    if (a.pout) {
+        a.pout[r] = s;
+        return;
+    }
     AT w = a.a0 * s + a.a1 * p.xin;
     if (a.aux) w += a.a2 * p.aux;
     if (a.acc) stx(a.acc, r, p.acc + a.b0 * p.xin + a.b1 * w);
@@ -238,6 +251,8 @@ __global__ __launch_bounds__(256) void k_chain_persist(PArgs<VT, XT> p) {
         a.b1 = (AT)st.b1;
         a.acc_init = st.acc_init;
         a.n = p.n;
+        a.pin = nullptr;
+        a.pout = nullptr;
         for (int t = t0; t < t1; ++t) {
             tile_body<VT, XT, EPT, 1>(a, p.tiles[t], st.spmv, buf, red);
             __syncthreads();
@@ -749,6 +764,17 @@ const float *dia_vals<float>(const DevCSR &A) {
 }
 
 template <typename VT>
+const VT *band_vals(const DevCSR &A, int c);
+template <>
+const double *band_vals<double>(const DevCSR &A, int c) {
+    return A.bval64[c];
+}
+template <>
+const float *band_vals<float>(const DevCSR &A, int c) {
+    return A.bval32[c];
+}
+
+template <typename VT>
 const VT *sell_vals(const DevCSR &A);
 template <>
 const double *sell_vals<double>(const DevCSR &A) {
@@ -778,6 +804,8 @@ ChainArgs<VT, XT> chain_args(const DevCSR &A, const VT *val, const StepPtrs &s) 
     a.b1 = (AT)s.b1;
     a.acc_init = s.acc_init;
     a.n = A.n;
+    a.pin = nullptr;
+    a.pout = nullptr;
     return a;
 }
 
@@ -970,6 +998,27 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int v
             else
                 hipLaunchKernelGGL((k_chain_sell<VT, XT, true, 4, int32_t>), dim3(nb), dim3(256), 0, st, a, A.sptr, A.scol,
                                    sell_vals<VT>(A), A.nslices, nb, remap);
+            return hipGetLastError();
+        }
+        case CV_BAND2:
+        case CV_BAND4: {
+            // one launch per column band: at any time the gathers touch one
+            // band of the input, which stays in the XCDs' L2
+            using AT = typename Arith<XT>::T;
+            const int c = variant == CV_BAND2 ? 0 : 1, K = A.bandK[c];
+            if (K == 0 || !A.bpart) return hipErrorInvalidValue;
+            for (int k = 0; k < K; ++k) {
+                ChainArgs<VT, XT> ak = a;
+                ak.rowptr = A.brow[c] + (size_t)k * (A.n + 1);
+                ak.colind = A.bcol[c];
+                ak.val = band_vals<VT>(A, c);
+                ak.pin = k > 0 ? (const AT *)A.bpart : nullptr;
+                ak.pout = k < K - 1 ? (AT *)A.bpart : nullptr;
+                const int t0 = A.btoff[c][k], nt = A.btoff[c][k + 1] - t0;
+                if (nt > 0)
+                    hipLaunchKernelGGL((k_chain_tile<VT, XT, 8, 1>), dim3(nt), dim3(256), 0, st, ak, A.btile[c] + t0,
+                                       nt, remap);
+            }
             return hipGetLastError();
         }
         case CV_TILEB8: {
@@ -2050,7 +2099,7 @@ const char *chain_variant_name(int v) {
                                           "vec8x4",  "vec16x2",  "vec16x4", "vec32x2",   "tilev8x1",
                                           "tilev16x2", "vk2x4x4", "vk4x4x2", "vk8x4x1", "vk16x2x2", "persist8",
                                           "tileb8x1", "tileb16x2", "sell64", "sell64t", "sell64x2", "sell64x4", "sell64d16", "sell64d16x4",
-                                              "dia2",   "dia1", "diac", "diap"};
+                                              "dia2",   "dia1", "diac", "diap", "tile8b2", "tile8b4"};
     return (v >= 0 && v < CV_COUNT) ? names[v] : "?";
 }
 

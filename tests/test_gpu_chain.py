@@ -150,7 +150,7 @@ def test_bad_arguments_rejected(pp):
         pp.Matrix(np.array([0, 2, 1], dtype=np.int32), np.array([0, 1], dtype=np.int32), np.ones(2))  # rowptr
 
 
-@pytest.mark.parametrize("variant", range(28))
+@pytest.mark.parametrize("variant", range(30))
 def test_every_chain_variant_matches_oracle(pp, variant):
     # each kernel variant the autotuner may pick, with and without the XCD order
     for name in ["ragged_5000", "randsparse_20000", "convdiff3d_20"]:
@@ -171,9 +171,11 @@ def test_every_chain_variant_matches_oracle(pp, variant):
             except Exception as exc:
                 # the sliced-ELL copy is only built when its padding is small,
                 # the diagonal format only for matrices on few diagonals
+                # and the column-banded copies only for large matrices without a diagonal format
                 assert ("sliced-ELL" in str(exc) and name == "ragged_5000") or \
                     (any(k in str(exc) for k in ("diagonal-format", "value-coded", "pattern-coded"))
-                     and name != "convdiff3d_20"), exc
+                     and name != "convdiff3d_20") or \
+                    ("column-banded" in str(exc) and name == "convdiff3d_20"), exc
                 continue
             assert relerr(host(pp.apply(poly, M, dev(v), "p")), ref_p) <= 1e-12
             assert relerr(host(pp.apply(poly, M, dev(v), "phi")), ref_phi) <= 1e-12
@@ -283,6 +285,26 @@ def test_pattern_coded_limit(pp, case):
         assert relerr(host(pp.apply(poly, M, dev(v, torch.float32), "p")), ref_p) <= 10 * delta + 1e-6
 
 
+@pytest.mark.parametrize("variant", [28, 29])
+def test_column_banded_copy_follows_new_values(pp, variant):
+    # random sparse n = 20000 (no diagonal format): the banded copies are
+    # built, and new values (pp_matrix_set_values) reach every band
+    csr = randsparse(20000, 16, seed=7)
+    A = csr.to_scipy()
+    M = pp.Matrix.from_csr(csr)
+    say("banded values", pp.chain_variant_name(variant))
+    poly = pp.poly_from_roots([3.0, 7.5], keep_order=True)
+    units = [(chains.REAL, 3.0, 0.0), (chains.REAL, 7.5, 0.0)]
+    v = rhs(csr.n, 5)
+    for scale in (1.0, -0.5):
+        if scale != 1.0:
+            M.set_values(dev(scale * csr.val))
+        for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-5)):
+            M.set_variant(prec, variant, 1)
+            got = host(pp.apply(poly, M, dev(v, dt), "phi")).astype(np.float64)
+            assert relerr(got, chains.apply_phi(scale * A, units, v)) <= tol
+
+
 def test_autotuner_picks_a_valid_variant(pp):
     csr = convdiff3d(48, 10, 10, 10)
     M = pp.Matrix.from_csr(csr)
@@ -290,7 +312,7 @@ def test_autotuner_picks_a_valid_variant(pp):
     assert M.variant("fp32")[0] is None  # nothing tuned or set yet
     for prec in ("fp64", "fp32", "bf16"):
         name, remap, us = M.tune(prec)
-        assert name in [pp.chain_variant_name(v) for v in range(28)] and remap in (0, 1) and us > 0
+        assert name in [pp.chain_variant_name(v) for v in range(30)] and remap in (0, 1) and us > 0
         assert M.variant(prec) == (name, remap, us)
     M.set_variant("fp32", 3, 0)
     assert M.variant("fp32") == (pp.chain_variant_name(3), 0, 0.0)
