@@ -52,8 +52,8 @@ struct ChainArgs {
     typename Arith<XT>::T a0, a1, a2, b0, b1;
     int acc_init;
     int n;
-    // banded products: add pin[r] to the row's sum; with pout, store the sum
-    // there instead of finishing the row
+    // banded products (kernels compiled with BAND): add pin[r] to the row's
+    // sum; with pout, store the sum there instead of finishing the row
     const typename Arith<XT>::T *pin;
     typename Arith<XT>::T *pout;
 };
@@ -63,13 +63,17 @@ struct RowPre {
     AT xin, aux, vf, acc;
 };
 
-template <typename VT, typename XT>
+// BAND: a kernel that may run one band of a column-banded product (pin,
+// pout); the other kernels are compiled without those tests
+template <typename VT, typename XT, bool BAND = false>
 __device__ __forceinline__ RowPre<typename Arith<XT>::T> row_prefetch(const ChainArgs<VT, XT> &a, int r) {
     using AT = typename Arith<XT>::T;
     RowPre<AT> p;
-    if (a.pout) {  // a partial pass reads nothing but its entries
-        p.xin = p.aux = p.vf = p.acc = AT(0);
-        return p;
+    if constexpr (BAND) {
+        if (a.pout) {  // a partial pass reads nothing but its entries
+            p.xin = p.aux = p.vf = p.acc = AT(0);
+            return p;
+        }
     }
     p.xin = ldx(a.in, r);
     p.aux = a.aux ? (AT)ldx(a.aux, r) : AT(0);
@@ -78,14 +82,16 @@ __device__ __forceinline__ RowPre<typename Arith<XT>::T> row_prefetch(const Chai
     return p;
 }
 
-template <typename VT, typename XT>
+template <typename VT, typename XT, bool BAND = false>
 __device__ __forceinline__ void row_finish(const ChainArgs<VT, XT> &a, int r, typename Arith<XT>::T s,
                                            const RowPre<typename Arith<XT>::T> &p) {
     using AT = typename Arith<XT>::T;
-    if (a.pin) s += a.pin[r];
-    if (a.pout) {
-        a.pout[r] = s;
-        return;
+    if constexpr (BAND) {
+        if (a.pin) s += a.pin[r];
+        if (a.pout) {
+            a.pout[r] = s;
+            return;
+        }
     }
     AT w = a.a0 * s + a.a1 * p.xin;
     if (a.aux) w += a.a2 * p.aux;
@@ -105,7 +111,7 @@ __global__ __launch_bounds__(256) void k_chain_elem(ChainArgs<VT, XT> a, const X
 
 // One row tile of a chain step (r0, r1, e0, e1 in ti); buf: LDS of 256*EPT
 // entries, red: LDS of 4. With spmv == 0 only the epilogue runs.
-template <typename VT, typename XT, int EPT, int RPT>
+template <typename VT, typename XT, int EPT, int RPT, bool BAND = false>
 __device__ __forceinline__ void tile_body(const ChainArgs<VT, XT> &a, const int4 ti, int spmv,
                                           typename Arith<XT>::T *buf, typename Arith<XT>::T *red) {
     using AT = typename Arith<XT>::T;
@@ -113,7 +119,7 @@ __device__ __forceinline__ void tile_body(const ChainArgs<VT, XT> &a, const int4
     const int r0 = ti.x, r1 = ti.y, e0 = ti.z, e1 = ti.w;
     const int tid = threadIdx.x;
     if (!spmv) {
-        for (int r = r0 + tid; r < r1; r += 256) row_finish(a, r, AT(0), row_prefetch(a, r));
+        for (int r = r0 + tid; r < r1; r += 256) row_finish<VT, XT, BAND>(a, r, AT(0), row_prefetch<VT, XT, BAND>(a, r));
         return;
     }
     if (e1 - e0 <= TILE) {
@@ -127,7 +133,7 @@ __device__ __forceinline__ void tile_body(const ChainArgs<VT, XT> &a, const int4
             if (r < r1) {
                 rs[q] = a.rowptr[r] - e0;
                 rl[q] = a.rowptr[r + 1] - e0;
-                pre[q] = row_prefetch(a, r);
+                pre[q] = row_prefetch<VT, XT, BAND>(a, r);
             }
         }
         int col[EPT];
@@ -154,7 +160,7 @@ __device__ __forceinline__ void tile_body(const ChainArgs<VT, XT> &a, const int4
             if (r < r1) {
                 AT s = AT(0);
                 for (int k = rs[q]; k < rl[q]; ++k) s += buf[k];
-                row_finish(a, r, s, pre[q]);
+                row_finish<VT, XT, BAND>(a, r, s, pre[q]);
             }
         }
     } else {
@@ -162,18 +168,18 @@ __device__ __forceinline__ void tile_body(const ChainArgs<VT, XT> &a, const int4
         AT s = AT(0);
         for (int e = e0 + tid; e < e1; e += 256) s += (AT)a.val[e] * ldx(a.in, a.colind[e]);
         s = block_sum256(s, red);
-        if (tid == 0) row_finish(a, r0, s, row_prefetch(a, r0));
+        if (tid == 0) row_finish<VT, XT, BAND>(a, r0, s, row_prefetch<VT, XT, BAND>(a, r0));
     }
 }
 
-template <typename VT, typename XT, int EPT, int RPT>
+template <typename VT, typename XT, int EPT, int RPT, bool BAND = false>
 __global__ __launch_bounds__(256) void k_chain_tile(ChainArgs<VT, XT> a, const int4 *__restrict__ tinfo, int ntiles,
                                                     int remap) {
     using AT = typename Arith<XT>::T;
     __shared__ AT buf[256 * EPT];
     __shared__ AT red[4];
     const int t = remap_tile(blockIdx.x, ntiles, remap);
-    tile_body<VT, XT, EPT, RPT>(a, tinfo[t], 1, buf, red);
+    tile_body<VT, XT, EPT, RPT, BAND>(a, tinfo[t], 1, buf, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1016,8 +1022,8 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int v
                 ak.pout = k < K - 1 ? (AT *)A.bpart : nullptr;
                 const int t0 = A.btoff[c][k], nt = A.btoff[c][k + 1] - t0;
                 if (nt > 0)
-                    hipLaunchKernelGGL((k_chain_tile<VT, XT, 8, 1>), dim3(nt), dim3(256), 0, st, ak, A.btile[c] + t0,
-                                       nt, remap);
+                    hipLaunchKernelGGL((k_chain_tile<VT, XT, 8, 1, true>), dim3(nt), dim3(256), 0, st, ak,
+                                       A.btile[c] + t0, nt, remap);
             }
             return hipGetLastError();
         }
