@@ -12,7 +12,9 @@ plain FP64 form is timed beside it. Inputs are resident in HBM before the
 timed region. Prints one JSON line.
 
 More legs are reported beside the headline (skip with --no-extras): the
-random sparse workload (n = 1e6) in FP64/FP32/BF16, differentiation
+random sparse workload (n = 1e6) in FP64/FP32/BF16, the chain step on the
+same stencil at 256^3 (long launches: the kernel's streaming rate),
+differentiation
 through the solve on a 1024^2 2-D system (forward + adjoint), the batched
 solve of 256 systems x 4 right-hand sides against loops of single solves,
 and the paper's own synthetic rows run beside its printed figures.
@@ -123,6 +125,55 @@ def traffic_probe(pp, torch, np, M, n):
                 torch.cuda.synchronize()
                 log("probe", prec, name, f"remap {remap}: 32 launches")
     log("kernel sources sha256", kernel_source_hash())
+
+
+def scale_leg(pp, torch, np, N=256, nroots=16, reps=10):
+    """The chain step on the 3-D convection-diffusion matrix at N^3 = 256^3
+    (n = 16.8 M), where one launch streams long enough that its ramp and
+    drain are small next to the transfer: a phi polynomial of 16 real roots
+    (16 launches of one step each) timed with HIP events, FP32 and FP64,
+    with the autotuner's variant. For the pattern-coded format the step's
+    own bytes are the input read once, the output written once and one
+    pattern byte per row."""
+    from workloads import convdiff3d
+
+    log("scale leg: generating", N)
+    csr = convdiff3d(N, 10.0, 10.0, 10.0)
+    n, nnz = csr.n, csr.nnz
+    M = pp.Matrix.from_csr(csr)
+    del csr
+    poly = pp.poly_from_roots(np.linspace(2.0, 11.0, nroots), keep_order=True)
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"3-D convection-diffusion {N}^3 (n={n}, nnz={nnz}), phi(A)v of {nroots} real roots"}
+    for prec, dt, sx in (("fp32", torch.float32, 4), ("fp64", torch.float64, 8)):
+        M.tune(prec)
+        v = torch.as_tensor(np.random.default_rng(5).standard_normal(n), device="cuda").to(dt)
+        y = torch.empty_like(v)
+        for _ in range(2):
+            pp.apply(poly, M, v, "phi", out=y)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            pp.apply(poly, M, v, "phi", out=y)
+        e1.record(stream)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / (reps * nroots)
+        name = M.variant(prec)[0]
+        fmt = 2 * n * sx + n if name == "diap" else None
+        r = {"variant": name, "step_us": round(us, 3),
+             "csr_GBps": round(step_bytes(n, nnz, sx, sx) / (us * 1e-6) / 1e9, 1)}
+        if fmt is not None:
+            r["format_bytes"] = fmt
+            r["format_GBps"] = round(fmt / (us * 1e-6) / 1e9, 1)
+            r["format_frac"] = round(fmt / (us * 1e-6) / 1e9 / 8000.0, 4)
+        out[prec] = r
+        log("scale leg", prec, name, f"{us:.2f} us/step", r.get("format_GBps"), "GB/s format bytes")
+        del v, y
+    del M
+    torch.cuda.empty_cache()
+    return out
 
 
 def adjoint_leg(pp, torch, np):
@@ -508,6 +559,7 @@ def main():
     extras = {}
     if not args.no_extras:
         extras["random_sparse"] = random_sparse_leg(pp, torch, np)
+        extras["chain_step_256"] = scale_leg(pp, torch, np)
         extras["adjoint"] = adjoint_leg(pp, torch, np)
         extras["batched"] = batched_leg(pp, torch, np)
         extras["paper_context"] = paper_context_leg(pp, torch, np)

@@ -139,7 +139,7 @@ void pp_matrix_destroy(pp_matrix A);
 pp_status pp_matrix_tune(pp_matrix A, int prec, void *stream, int *variant, int *remap,
                          double *us_per_launch);
 
-/* Force a chain-step variant (0 <= variant < 30, remap 0/1; 15 = persistent) for a precision
+/* Force a chain-step variant (0 <= variant < 31, remap 0/1; 15 = persistent) for a precision
  * instead of tuning, e.g. to test every variant. */
 pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap);
 

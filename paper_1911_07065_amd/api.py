@@ -25,7 +25,7 @@ def version() -> str:
     return lib.pp_version().decode()
 
 
-N_CHAIN_VARIANTS = 30
+N_CHAIN_VARIANTS = 31
 
 
 def chain_variant_name(v: int) -> str:
@@ -124,7 +124,7 @@ class Matrix:
         return name, r.value, us.value
 
     def set_variant(self, prec: str, variant: int, remap: int = 1):
-        """Force chain variant `variant` (0..29; 15 = persistent cooperative kernel) for a precision."""
+        """Force chain variant `variant` (0..30; 15 = persistent cooperative kernel) for a precision."""
         check(lib.pp_matrix_set_variant(self.handle, PREC[prec], int(variant), int(remap)), "pp_matrix_set_variant")
 
     def transpose_pattern(self):

@@ -76,6 +76,7 @@ struct pp_matrix_s {
     double *bpart = nullptr;
     // pattern-coded diagonal copy (few distinct rows; dropped with the value codes)
     uint32_t *pcode = nullptr;
+    uint8_t *pbyte = nullptr;
     double *ptab64 = nullptr;
     float *ptab32 = nullptr;
     int npat = 0;
@@ -156,6 +157,7 @@ struct pp_matrix_s {
         }
         d.bpart = bpart;
         d.pcode = pcode;
+        d.pbyte = pbyte;
         d.ptab64 = ptab64;
         d.ptab32 = ptab32;
         d.npat = npat;
@@ -254,6 +256,7 @@ struct pp_matrix_s {
         dev_free(dtab64);
         dev_free(dtab32);
         dev_free(pcode);
+        dev_free(pbyte);
         dev_free(ptab64);
         dev_free(ptab32);
         for (int c = 0; c < 2; ++c) {
@@ -407,7 +410,7 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
     for (int v = 0; v < CV_COUNT; ++v) {
         if (v == CV_PERSIST || ((v == CV_SELL || v == CV_SELLT || v == CV_SELL2 || v == CV_SELL4) && A->nslices == 0) ||
             ((v == CV_SELLD || v == CV_SELLD4) && !A->sdel) || ((v == CV_DIA || v == CV_DIA4) && A->h_doff.empty()) ||
-            (v == CV_DIAC && !A->dcode) || (v == CV_DIAP && !A->pcode) ||
+            (v == CV_DIAC && !A->dcode) || (v == CV_DIAP && !A->pcode) || (v == CV_DIAPV && !A->pbyte) ||
             (v == CV_BAND2 && A->bandK[0] == 0) || (v == CV_BAND4 && A->bandK[1] == 0) ||
             (v == CV_TILEB8 && A->ntileB8[prec] == 0) ||
             (v == CV_TILEB16 && A->ntileB16[prec] == 0))
@@ -722,6 +725,7 @@ pp_status build_patterns(pp_matrix A, const std::vector<uint8_t> &codes, int nd,
     std::unordered_map<std::string, int> id_of;
     std::vector<const uint8_t *> pats;
     std::vector<uint32_t> words((size_t)((n + 1023) / 1024) * 256, 0u);
+    std::vector<uint8_t> bytes((size_t)((n + 1023) / 1024) * 1024, 0);
     int prev = -1;
     const uint8_t *prevc = nullptr;
     for (int64_t r = 0; r < n; ++r) {
@@ -742,6 +746,7 @@ pp_status build_patterns(pp_matrix A, const std::vector<uint8_t> &codes, int nd,
             prevc = c;
         }
         words[(size_t)(r >> 10) * 256 + (size_t)(r & 255)] |= (uint32_t)id << (8 * ((r >> 8) & 3));
+        bytes[(size_t)r] = (uint8_t)id;
     }
     const int npat = (int)pats.size();
     std::vector<double> pt((size_t)npat * nd);
@@ -752,10 +757,12 @@ pp_status build_patterns(pp_matrix A, const std::vector<uint8_t> &codes, int nd,
             pt32[(size_t)q * nd + d] = (float)tab[pats[q][d]];
         }
     PP_TRY(dev_alloc(&A->pcode, words.size()));
+    PP_TRY(dev_alloc(&A->pbyte, bytes.size()));
     PP_TRY(dev_alloc(&A->ptab64, pt.size()));
     PP_TRY(dev_alloc(&A->ptab32, pt.size()));
     if (hipMemcpyAsync(A->pcode, words.data(), sizeof(uint32_t) * words.size(), hipMemcpyHostToDevice, st) !=
             hipSuccess ||
+        hipMemcpyAsync(A->pbyte, bytes.data(), bytes.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(A->ptab64, pt.data(), sizeof(double) * pt.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(A->ptab32, pt32.data(), sizeof(float) * pt.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
@@ -1081,12 +1088,13 @@ pp_status refresh_values(pp_matrix A, const double *val, hipStream_t st) {
         dev_free(A->dtab64);
         dev_free(A->dtab32);
         dev_free(A->pcode);
+        dev_free(A->pbyte);
         dev_free(A->ptab64);
         dev_free(A->ptab32);
         A->ntab = 0;
         A->npat = 0;
         for (int p = 0; p < 3; ++p)
-            if (A->variant[p] == CV_DIAC || A->variant[p] == CV_DIAP) {
+            if (A->variant[p] == CV_DIAC || A->variant[p] == CV_DIAP || A->variant[p] == CV_DIAPV) {
                 A->variant[p] = CV_TILE8;
                 A->tuned[p] = 0;
             }
@@ -1235,7 +1243,7 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
                       "whose entries lie far from the diagonal)");
             return PP_EINVAL;
         }
-        if (variant == CV_DIAP && !A->pcode) {
+        if ((variant == CV_DIAP && !A->pcode) || (variant == CV_DIAPV && !A->pbyte)) {
             set_error("pp_matrix_set_variant: no pattern-coded diagonal copy (no value-coded copy, too many "
                       "distinct rows, or the values changed)");
             return PP_EINVAL;

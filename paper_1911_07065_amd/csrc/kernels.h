@@ -44,7 +44,8 @@ enum ChainVariant : int {
     CV_DIAP = 27,     // diagonal format with one byte per row: the row's pattern in a table of distinct rows
     CV_BAND2 = 28,    // tile8x1 on 2 column bands, one launch per band (partial row sums in between)
     CV_BAND4 = 29,    // the same with 4 column bands
-    CV_COUNT = 30
+    CV_DIAPV = 30,    // pattern-coded diagonals, 4 consecutive rows per lane with vector loads
+    CV_COUNT = 31
 };
 
 // A chain step as the persistent kernel reads it from device memory.
@@ -141,6 +142,7 @@ struct DevCSR {
     // the entry of a row with pattern p on diagonal d is ptab[p * nd + d]
     // (npat * nd <= kMaxPatEntries values)
     const uint32_t *pcode;
+    const uint8_t *pbyte;  // the same patterns one byte per row in row order (ceil(n/1024)*1024 bytes)
     const double *ptab64;
     const float *ptab32;
     int npat;

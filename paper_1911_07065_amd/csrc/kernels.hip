@@ -736,6 +736,104 @@ __global__ __launch_bounds__(256) void k_chain_diap(ChainArgs<VT, XT> a, const u
     }
 }
 
+// Four consecutive elements of a vector as one access; the pointer need only
+// be aligned to its element (dword-aligned vector loads).
+__device__ __forceinline__ double elem_in(double v) { return v; }
+__device__ __forceinline__ float elem_in(float v) { return v; }
+__device__ __forceinline__ float elem_in(uint16_t v) { return __uint_as_float(((uint32_t)v) << 16); }
+__device__ __forceinline__ double elem_out(const double *, double v) { return v; }
+__device__ __forceinline__ float elem_out(const float *, float v) { return v; }
+__device__ __forceinline__ uint16_t elem_out(const uint16_t *, float v) { return f32_to_bf16(v); }
+
+template <typename XT>
+__device__ __forceinline__ void ld4(const XT *__restrict__ p, long i, typename Arith<XT>::T *o) {
+    typedef XT V4 __attribute__((ext_vector_type(4), aligned(sizeof(XT))));
+    const V4 v = *reinterpret_cast<const V4 *>(p + i);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = elem_in(v[k]);
+}
+
+template <typename XT>
+__device__ __forceinline__ void st4(XT *__restrict__ p, long i, const typename Arith<XT>::T *v) {
+    typedef XT V4 __attribute__((ext_vector_type(4), aligned(sizeof(XT))));
+    V4 t;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] = elem_out(p, v[k]);
+    *reinterpret_cast<V4 *>(p + i) = t;
+}
+
+// Pattern-coded diagonal format with 4 consecutive rows per lane: lane t of
+// block b owns rows r .. r+3, r = b*1024 + 4t, whose pattern ids are the
+// bytes pbyte[r .. r+3] (one 4-byte load). In a block whose every window
+// x[r + off .. r + off + 3] lies inside [0, n) (omin <= 0 <= omax bound the
+// offsets), each diagonal's window, the row data and the results move as
+// one vector access each; the blocks at the two ends of the matrix read
+// element by element with clamped indices and write only rows below n.
+template <typename VT, typename XT, int ND>
+__global__ __launch_bounds__(256) void k_chain_diapv(ChainArgs<VT, XT> a, const uint8_t *__restrict__ pbyte,
+                                                     const VT *__restrict__ ptab, int nent, DiaOffsets doff,
+                                                     int omin, int omax, int nblocks, int remap) {
+    using AT = typename Arith<XT>::T;
+    __shared__ AT tab[kMaxPatEntries];
+    const int blk = remap_tile(blockIdx.x, nblocks, remap);
+    const int n = a.n;
+    const long b0 = (long)blk * 1024;
+    const int r = (int)b0 + 4 * (int)threadIdx.x;
+    // (bfloat16 storage always reads element by element: its windows are
+    // only 2-byte aligned)
+    const bool inner = sizeof(XT) >= 4 && b0 + omin >= 0 && b0 + 1023 + omax <= (long)n - 1;
+    const uint32_t pw = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(pbyte) + (r >> 2));
+    AT x[ND][4], xin[4], aux[4], vf[4], acc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) aux[k] = vf[k] = acc[k] = AT(0);
+    if (inner) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) ld4(a.in, (long)r + doff.off[d], x[d]);
+        ld4(a.in, r, xin);
+        if (a.aux) ld4(a.aux, r, aux);
+        if (a.vfin) ld4(a.vfin, r, vf);
+        if (a.acc && !a.acc_init) ld4(a.acc, r, acc);
+    } else {
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[d][k] = ldx(a.in, min(max(r + k + doff.off[d], 0), n - 1));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int rk = min(r + k, n - 1);
+            xin[k] = ldx(a.in, rk);
+            if (a.aux) aux[k] = ldx(a.aux, rk);
+            if (a.vfin) vf[k] = ldx(a.vfin, rk);
+            if (a.acc && !a.acc_init) acc[k] = ldx(a.acc, rk);
+        }
+    }
+    for (int i = (int)threadIdx.x; i < nent; i += 256) tab[i] = (AT)ptab[i];
+    __syncthreads();
+    AT ov[4], av[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const AT *t = tab + ((pw >> (8 * k)) & 0xffu) * ND;
+        AT s = AT(0);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) s += t[d] * x[d][k];
+        AT w = a.a0 * s + a.a1 * xin[k];
+        if (a.aux) w += a.a2 * aux[k];
+        av[k] = acc[k] + a.b0 * xin[k] + a.b1 * w;
+        ov[k] = a.vfin ? vf[k] - w : w;
+    }
+    if (inner) {
+        if (a.acc) st4(a.acc, r, av);
+        if (a.out) st4(a.out, r, ov);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (r + k < n) {
+                if (a.acc) stx(a.acc, r + k, av[k]);
+                if (a.out) stx(a.out, r + k, ov[k]);
+            }
+    }
+}
+
 template <typename VT>
 const VT *diap_tab(const DevCSR &A);
 template <>
@@ -970,6 +1068,39 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int v
                     return hipErrorInvalidValue;  // built only with the value-coded copy
             }
 #undef PP_DIAP_ND
+            return hipGetLastError();
+        }
+        case CV_DIAPV: {
+            const int nent = A.npat * A.doff.nd;
+            if (A.doff.nd <= 0 || !A.pbyte || nent <= 0 || nent > kMaxPatEntries) return hipErrorInvalidValue;
+            int omin = 0, omax = 0;
+            for (int d = 0; d < A.doff.nd; ++d) {
+                omin = std::min(omin, A.doff.off[d]);
+                omax = std::max(omax, A.doff.off[d]);
+            }
+            const int nb = (int)((A.n + 1023L) / 1024L);
+#define PP_DIAPV_ND(K)                                                                                             \
+    case K:                                                                                                        \
+        hipLaunchKernelGGL((k_chain_diapv<VT, XT, K>), dim3(nb), dim3(256), 0, st, a, A.pbyte, diap_tab<VT>(A),    \
+                           nent, A.doff, omin, omax, nb, remap);                                                   \
+        break;
+            switch (A.doff.nd) {
+                PP_DIAPV_ND(1)
+                PP_DIAPV_ND(2)
+                PP_DIAPV_ND(3)
+                PP_DIAPV_ND(4)
+                PP_DIAPV_ND(5)
+                PP_DIAPV_ND(6)
+                PP_DIAPV_ND(7)
+                PP_DIAPV_ND(8)
+                PP_DIAPV_ND(9)
+                PP_DIAPV_ND(13)
+                PP_DIAPV_ND(19)
+                PP_DIAPV_ND(27)
+                default:
+                    return hipErrorInvalidValue;  // built only with the value-coded copy
+            }
+#undef PP_DIAPV_ND
             return hipGetLastError();
         }
         case CV_SELLD:
@@ -2105,7 +2236,7 @@ const char *chain_variant_name(int v) {
                                           "vec8x4",  "vec16x2",  "vec16x4", "vec32x2",   "tilev8x1",
                                           "tilev16x2", "vk2x4x4", "vk4x4x2", "vk8x4x1", "vk16x2x2", "persist8",
                                           "tileb8x1", "tileb16x2", "sell64", "sell64t", "sell64x2", "sell64x4", "sell64d16", "sell64d16x4",
-                                              "dia2",   "dia1", "diac", "diap", "tile8b2", "tile8b4"};
+                                              "dia2",   "dia1", "diac", "diap", "tile8b2", "tile8b4", "diapv"};
     return (v >= 0 && v < CV_COUNT) ? names[v] : "?";
 }
 

@@ -150,7 +150,7 @@ def test_bad_arguments_rejected(pp):
         pp.Matrix(np.array([0, 2, 1], dtype=np.int32), np.array([0, 1], dtype=np.int32), np.ones(2))  # rowptr
 
 
-@pytest.mark.parametrize("variant", range(30))
+@pytest.mark.parametrize("variant", range(31))
 def test_every_chain_variant_matches_oracle(pp, variant):
     # each kernel variant the autotuner may pick, with and without the XCD order
     for name in ["ragged_5000", "randsparse_20000", "convdiff3d_20"]:
@@ -207,21 +207,21 @@ def test_diagonal_format_edge_cases(pp, case):
     M = pp.Matrix.from_csr(csr)
     poly = pp.poly_from_roots(P.roots(), keep_order=True)
     v = rhs(csr.n, 5)
-    for variant in (24, 25, 26, 27):
+    for variant in (24, 25, 26, 27, 30):
         for remap in (0, 1):
             say("diagonal format", case, pp.chain_variant_name(variant), remap)
             try:
                 M.set_variant("fp64", variant, remap)
             except Exception as exc:
                 # the value- and pattern-coded copies need at most 255 distinct values
-                assert variant in (26, 27) and case == "diagonal_1000" and \
+                assert variant in (26, 27, 30) and case == "diagonal_1000" and \
                     ("value-coded" in str(exc) or "pattern-coded" in str(exc)), exc
                 continue
             assert relerr(host(pp.apply(poly, M, dev(v), "p")), chains.apply_p(A, P.units, v)) <= 1e-12
             assert relerr(host(pp.apply(poly, M, dev(v), "phi")), chains.apply_phi(A, P.units, v)) <= 1e-12
 
 
-@pytest.mark.parametrize("variant", [26, 27])
+@pytest.mark.parametrize("variant", [26, 27, 30])
 def test_value_coded_copy_dropped_when_values_change(pp, variant):
     csr = convdiff3d(20, 10, 10, 10)
     A = csr.to_scipy()
@@ -277,9 +277,9 @@ def test_pattern_coded_limit(pp, case):
             M.set_variant("fp64", 27, 0)
         return
     delta = relerr(apply_p_low(A.astype(np.float32), Pr.units, v.astype(np.float32)), ref_p)
-    for remap in (0, 1):
-        M.set_variant("fp64", 27, remap)
-        M.set_variant("fp32", 27, remap)
+    for variant, remap in ((27, 0), (27, 1), (30, 0), (30, 1)):
+        M.set_variant("fp64", variant, remap)
+        M.set_variant("fp32", variant, remap)
         assert relerr(host(pp.apply(poly, M, dev(v), "p")), ref_p) <= 1e-12
         assert relerr(host(pp.apply(poly, M, dev(v), "phi")), chains.apply_phi(A, Pr.units, v)) <= 1e-12
         assert relerr(host(pp.apply(poly, M, dev(v, torch.float32), "p")), ref_p) <= 10 * delta + 1e-6
@@ -312,7 +312,7 @@ def test_autotuner_picks_a_valid_variant(pp):
     assert M.variant("fp32")[0] is None  # nothing tuned or set yet
     for prec in ("fp64", "fp32", "bf16"):
         name, remap, us = M.tune(prec)
-        assert name in [pp.chain_variant_name(v) for v in range(30)] and remap in (0, 1) and us > 0
+        assert name in [pp.chain_variant_name(v) for v in range(31)] and remap in (0, 1) and us > 0
         assert M.variant(prec) == (name, remap, us)
     M.set_variant("fp32", 3, 0)
     assert M.variant("fp32") == (pp.chain_variant_name(3), 0, 0.0)
