@@ -161,7 +161,7 @@ def scale_leg(pp, torch, np, N=256, nroots=16, reps=10):
         e1.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / (reps * nroots)
         name = M.variant(prec)[0]
-        fmt = 2 * n * sx + n if name == "diap" else None
+        fmt = 2 * n * sx + n if name in ("diap", "diapv") else None
         r = {"variant": name, "step_us": round(us, 3),
              "csr_GBps": round(step_bytes(n, nnz, sx, sx) / (us * 1e-6) / 1e9, 1)}
         if fmt is not None:
