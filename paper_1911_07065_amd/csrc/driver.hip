@@ -105,6 +105,7 @@ struct pp_matrix_s {
     unsigned long long bar_host = 0;    // its value after the last launch
     int *err = nullptr;                 // barrier timeout flag (device)
     int *errpin = nullptr;              // pinned mirror
+    bool persist_ran = false;           // a persistent launch happened (the flag can be set)
     PStep *tune_steps = nullptr;        // 8 alternating sparse products
     std::map<std::pair<unsigned long long, int>, PStep *> progs;  // (poly id, kind) -> device table
     std::vector<int32_t> h_rowptr;
@@ -310,6 +311,13 @@ void *buf_ptr(int b, const void *in, void *out, const Workspace &w) {
     }
 }
 
+// Queue the copy of the barrier flag to the host, if a persistent launch
+// ever ran on this handle (no other kernel sets it).
+hipError_t copy_barrier_flag(pp_matrix A, hipStream_t st) {
+    if (!A->persist_ran) return hipSuccess;
+    return hipMemcpyAsync(A->errpin, A->err, sizeof(int), hipMemcpyDeviceToHost, st);
+}
+
 pp_status check_barrier_flag(pp_matrix A) {
     if (A->errpin && *A->errpin) {
         set_error("persistent chain: grid barrier timed out");
@@ -347,6 +355,7 @@ pp_status launch_persist(pp_matrix A, int prec, const PStep *steps, int nsteps, 
                          hipStream_t st) {
     const Workspace &w = A->ws[prec];
     void *bufs[5] = {(void *)in, out, w.P0, w.P1, w.T};
+    A->persist_ran = true;
     HIP_TRY(launch_chain_persist(A->dev(), prec, bufs, steps, nsteps, A->bar, A->bar_host, A->err, A->pgrid, remap,
                                  st));
     A->bar_host += (unsigned long long)(nsteps - 1) * (unsigned long long)A->pgrid;
@@ -450,7 +459,7 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
             HIP_TRY(hipEventSynchronize(e1));
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            HIP_TRY(hipMemcpyAsync(A->errpin, A->err, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(copy_barrier_flag(A, st));
             HIP_TRY(hipStreamSynchronize(st));
             PP_TRY(check_barrier_flag(A));
             const double us = 1e3 * ms / (2 * 8);
@@ -643,7 +652,7 @@ pp_status cgs2_step(pp_matrix A, int prec, const Workspace &ws, int j, hipStream
     }
     if (!to_host) return PP_OK;
     HIP_TRY(hipMemcpyAsync(A->hpin, Hcol, sizeof(double) * (ncols + 1), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(A->errpin, A->err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(copy_barrier_flag(A, st));
     HIP_TRY(hipStreamSynchronize(st));
     return check_barrier_flag(A);
 }
@@ -653,7 +662,7 @@ pp_status dev_norm(pp_matrix A, int prec, const void *x, double *out, hipStream_
     HIP_TRY(launch_dots(prec, A->n, x, 0, 1, x, A->partial, A->ldp, st));
     HIP_TRY(launch_reduce(A->nblk_dot, A->partial, A->ldp, 1, A->h1(), nullptr, 0, st));
     HIP_TRY(hipMemcpyAsync(A->hpin, A->h1(), sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(A->errpin, A->err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(copy_barrier_flag(A, st));
     HIP_TRY(hipStreamSynchronize(st));
     *out = std::sqrt(A->hpin[0]);
     return check_barrier_flag(A);
@@ -1385,7 +1394,7 @@ pp_status setup_arnoldi(pp_matrix A, const double *v0, int d, hipStream_t st, st
     }
     Hbar.assign((size_t)ld * d, 0.0);
     HIP_TRY(hipMemcpyAsync(Hbar.data(), Hdev, sizeof(double) * ld * d, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(A->errpin, A->err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(copy_barrier_flag(A, st));
     HIP_TRY(hipStreamSynchronize(st));
     PP_TRY(check_barrier_flag(A));
     k = d;
