@@ -49,14 +49,28 @@ KERNEL_SOURCES = ("kernels.hip", "kernels.h", "devutil.h")
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written
 
 
+def code_text(src):
+    """C++ source without comments and blank lines, each line stripped, so
+    that the hash below changes with the code and not with its comments."""
+    import re
+
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = []
+    for line in src.splitlines():
+        line = re.sub(r"//.*$", "", line).strip()
+        if line:
+            out.append(line)
+    return "\n".join(out)
+
+
 def kernel_source_hash():
-    """sha256 over the sources the chain kernels are compiled from."""
+    """sha256 over the code (comments dropped) the chain kernels are compiled from."""
     import hashlib
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1911_07065_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1911_07065_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()
 
 

@@ -28,15 +28,22 @@ namespace {
 //     w = a0 (A in)_r + a1 in_r + a2 aux_r
 //     acc_r = (acc_init ? 0 : acc_r) + b0 in_r + b1 w      (if acc)
 //     out_r = fin ? vfin_r - w : w                          (if out)
-// which covers one factor of Algorithm 1 or 3 (see poly.cpp). Two kernel
-// families compute (A in)_r; the autotuner picks one per matrix and
-// precision:
-//  * tile: a workgroup owns a tile of <= 256*RPT rows holding <= 256*EPT
-//    stored entries; the entries are streamed with coalesced loads, the
-//    products staged in LDS and summed per row. Row data of the epilogue is
-//    prefetched before the stream so that it overlaps it.
-//  * vec: LPR lanes per row, U rows in flight per lane group, sums reduced
-//    with cross-lane shuffles; no LDS and no barrier.
+// which covers one factor of Algorithm 1 or 3 (see poly.cpp). Several kernel
+// families compute (A in)_r, each on its own copy of the matrix; the
+// autotuner picks one per matrix and precision:
+//  * tile (CSR): a workgroup owns a tile of <= 256*RPT rows holding
+//    <= 256*EPT stored entries; the entries are streamed with coalesced
+//    loads, the products staged in LDS and summed per row. Row data of the
+//    epilogue is prefetched before the stream so that it overlaps it. The
+//    column-banded variants run it once per band of columns.
+//  * vec (CSR): LPR lanes per row, U rows in flight per lane group, sums
+//    reduced with cross-lane shuffles; no LDS and no barrier.
+//  * sliced-ELL: one lane per row of a 64-row slice, entries stored column
+//    by column (32-bit columns or 16-bit offsets).
+//  * diagonal formats (matrices on few diagonals): stored values per
+//    diagonal, 1-byte codes into the distinct values, or 1 byte per row
+//    naming its pattern among the distinct rows; the gather is x[r + off].
+//  * persistent: a whole chain in one cooperative launch (opt-in).
 // ---------------------------------------------------------------------------
 
 template <typename VT, typename XT>
