@@ -456,6 +456,9 @@ def main():
                          "used to profile the kernel an unprofiled run picks")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the differentiation and batched legs")
+    ap.add_argument("--leg", default=None,
+                    choices=["random_sparse", "chain_step_256", "adjoint", "batched", "paper_context"],
+                    help="run only this side workload and print its JSON (for profiling one workload)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the launch sequence the rocprofv3 counter runs read (no JSON line)")
     args = ap.parse_args()
@@ -471,6 +474,11 @@ def main():
     from workloads import convdiff3d, rhs, start_vector
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    if args.leg:
+        legs = {"random_sparse": random_sparse_leg, "chain_step_256": scale_leg, "adjoint": adjoint_leg,
+                "batched": batched_leg, "paper_context": paper_context_leg}
+        print(json.dumps({args.leg: legs[args.leg](pp, torch, np)}))
+        return
     N, d, m, tol = args.grid, args.degree, args.m, 1e-8
     log("generating workload", N)
     csr = convdiff3d(N, 10.0, 10.0, 10.0)

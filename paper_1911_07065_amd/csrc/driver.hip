@@ -64,6 +64,13 @@ struct pp_matrix_s {
     double *dtab64 = nullptr;
     float *dtab32 = nullptr;
     int ntab = 0;
+    // for new values with the same codes: each entry's code, one entry per
+    // code, each pattern's code tuple, and the check's flag
+    uint8_t *ecode = nullptr;
+    int32_t *crep = nullptr;
+    uint8_t *pcodes = nullptr;
+    int *rflag = nullptr;
+    bool recoded = false;  // the codes were rebuilt once from new values
     // column-banded CSR copies (matrices whose entries lie far from the
     // diagonal): c = 0 two bands, c = 1 four; bperm maps entries to CSR
     int32_t *brow[2] = {nullptr, nullptr}, *bcol[2] = {nullptr, nullptr}, *bperm[2] = {nullptr, nullptr};
@@ -256,6 +263,10 @@ struct pp_matrix_s {
         dev_free(dcode);
         dev_free(dtab64);
         dev_free(dtab32);
+        dev_free(ecode);
+        dev_free(crep);
+        dev_free(pcodes);
+        dev_free(rflag);
         dev_free(pcode);
         dev_free(pbyte);
         dev_free(ptab64);
@@ -760,11 +771,18 @@ pp_status build_patterns(pp_matrix A, const std::vector<uint8_t> &codes, int nd,
     const int npat = (int)pats.size();
     std::vector<double> pt((size_t)npat * nd);
     std::vector<float> pt32(pt.size());
+    std::vector<uint8_t> pc(pt.size());
     for (int q = 0; q < npat; ++q)
         for (int d = 0; d < nd; ++d) {
+            pc[(size_t)q * nd + d] = pats[q][d];
             pt[(size_t)q * nd + d] = tab[pats[q][d]];
             pt32[(size_t)q * nd + d] = (float)tab[pats[q][d]];
         }
+    PP_TRY(dev_alloc(&A->pcodes, pc.size()));
+    if (hipMemcpyAsync(A->pcodes, pc.data(), pc.size(), hipMemcpyHostToDevice, st) != hipSuccess) {
+        set_error("pp_matrix_create: pattern-coded upload failed");
+        return PP_EDEVICE;
+    }
     PP_TRY(dev_alloc(&A->pcode, words.size()));
     PP_TRY(dev_alloc(&A->pbyte, bytes.size()));
     PP_TRY(dev_alloc(&A->ptab64, pt.size()));
@@ -779,6 +797,81 @@ pp_status build_patterns(pp_matrix A, const std::vector<uint8_t> &codes, int nd,
         return PP_EDEVICE;
     }
     A->npat = npat;
+    return PP_OK;
+}
+
+// Value-coded copy of the diagonal format (at most 255 distinct nonzero
+// values; code 0 is zero) and the pattern-coded copy built from it, from
+// the host values hv and the slot -> entry map dp of the diagonal format.
+// Leaves the matrix without the copies (PP_OK) when it does not qualify.
+pp_status build_value_codes(pp_matrix A, const int32_t *dp, const std::vector<double> &hv, hipStream_t st) {
+    const int64_t n = A->n, nnz = A->nnz;
+    const int nd = (int)A->h_doff.size();
+    pp_status s;
+    std::unordered_map<uint64_t, int> code_of;
+    std::vector<double> tab(1, 0.0);
+    code_of[0] = 0;
+    bool few_values = true;
+    for (int64_t q = 0; q < nnz && few_values; ++q) {
+        uint64_t bits;
+        std::memcpy(&bits, &hv[q], sizeof bits);
+        if (code_of.find(bits) == code_of.end()) {
+            if (tab.size() >= 256) {
+                few_values = false;
+                break;
+            }
+            code_of[bits] = (int)tab.size();
+            tab.push_back(hv[q]);
+        }
+    }
+    if (few_values) {
+        const int G = (nd + 7) / 8;
+        std::vector<uint8_t> codes((size_t)n * G * 8, 0);
+        for (int64_t r = 0; r < n; ++r)
+            for (int dd = 0; dd < nd; ++dd) {
+                const int kk = dp[((r >> 8) * (long)nd + dd) * 256 + (r & 255)];
+                if (kk < 0) continue;
+                uint64_t bits;
+                std::memcpy(&bits, &hv[kk], sizeof bits);
+                codes[((size_t)r * G + dd / 8) * 8 + dd % 8] = (uint8_t)code_of[bits];
+            }
+        std::vector<float> tab32(tab.size());
+        for (size_t q = 0; q < tab.size(); ++q) tab32[q] = (float)tab[q];
+        std::vector<uint8_t> ec(nnz);
+        std::vector<int32_t> rep(tab.size(), -1);
+        for (int64_t q = 0; q < nnz; ++q) {
+            uint64_t bits;
+            std::memcpy(&bits, &hv[q], sizeof bits);
+            const int c = code_of[bits];
+            ec[q] = (uint8_t)c;
+            if (rep[c] < 0) rep[c] = (int32_t)q;
+        }
+        if ((s = dev_alloc(&A->ecode, ec.size())) != PP_OK ||
+            (s = dev_alloc(&A->crep, rep.size())) != PP_OK || (s = dev_alloc(&A->rflag, 1)) != PP_OK)
+            return s;
+        if (hipMemcpyAsync(A->ecode, ec.data(), ec.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(A->crep, rep.data(), sizeof(int32_t) * rep.size(), hipMemcpyHostToDevice,
+                           st) != hipSuccess) {
+            set_error("value-coded upload failed");
+            return PP_EDEVICE;
+        }
+        if ((s = dev_alloc(&A->dcode, codes.size())) != PP_OK ||
+            (s = dev_alloc(&A->dtab64, tab.size())) != PP_OK ||
+            (s = dev_alloc(&A->dtab32, tab.size())) != PP_OK)
+            return s;
+        if (hipMemcpyAsync(A->dcode, codes.data(), codes.size(), hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(A->dtab64, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice,
+                           st) != hipSuccess ||
+            hipMemcpyAsync(A->dtab32, tab32.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice,
+                           st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            set_error("value-coded upload failed");
+            return PP_EDEVICE;
+        }
+        A->ntab = (int)tab.size();
+        if ((s = build_patterns(A, codes, nd, tab, st)) != PP_OK) return s;
+    }
     return PP_OK;
 }
 
@@ -1003,61 +1096,14 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
                     return fail(PP_EDEVICE);
                 }
                 A->h_doff = offs;
-                // value-coded copy: at most 255 distinct nonzero values (code 0 is
-                // zero) and a diagonal count the kernel is compiled for
+                // value-coded copy (and the pattern-coded one built from it)
                 const int nd = (int)offs.size();
                 const bool nd_ok = nd <= 9 || nd == 13 || nd == 19 || nd == 27;
                 std::vector<double> hv(nnz);
                 if (nd_ok && hipMemcpyAsync(hv.data(), val, sizeof(double) * nnz, hipMemcpyDeviceToHost, st) ==
                                  hipSuccess &&
-                    hipStreamSynchronize(st) == hipSuccess) {
-                    std::unordered_map<uint64_t, int> code_of;
-                    std::vector<double> tab(1, 0.0);
-                    code_of[0] = 0;
-                    bool few_values = true;
-                    for (int64_t q = 0; q < nnz && few_values; ++q) {
-                        uint64_t bits;
-                        std::memcpy(&bits, &hv[q], sizeof bits);
-                        if (code_of.find(bits) == code_of.end()) {
-                            if (tab.size() >= 256) {
-                                few_values = false;
-                                break;
-                            }
-                            code_of[bits] = (int)tab.size();
-                            tab.push_back(hv[q]);
-                        }
-                    }
-                    if (few_values) {
-                        const int G = (nd + 7) / 8;
-                        std::vector<uint8_t> codes((size_t)n * G * 8, 0);
-                        for (int64_t r = 0; r < n; ++r)
-                            for (int dd = 0; dd < nd; ++dd) {
-                                const int kk = dp[((r >> 8) * (long)nd + dd) * 256 + (r & 255)];
-                                if (kk < 0) continue;
-                                uint64_t bits;
-                                std::memcpy(&bits, &hv[kk], sizeof bits);
-                                codes[((size_t)r * G + dd / 8) * 8 + dd % 8] = (uint8_t)code_of[bits];
-                            }
-                        std::vector<float> tab32(tab.size());
-                        for (size_t q = 0; q < tab.size(); ++q) tab32[q] = (float)tab[q];
-                        if ((s = dev_alloc(&A->dcode, codes.size())) != PP_OK ||
-                            (s = dev_alloc(&A->dtab64, tab.size())) != PP_OK ||
-                            (s = dev_alloc(&A->dtab32, tab.size())) != PP_OK)
-                            return fail(s);
-                        if (hipMemcpyAsync(A->dcode, codes.data(), codes.size(), hipMemcpyHostToDevice, st) !=
-                                hipSuccess ||
-                            hipMemcpyAsync(A->dtab64, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice,
-                                           st) != hipSuccess ||
-                            hipMemcpyAsync(A->dtab32, tab32.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice,
-                                           st) != hipSuccess ||
-                            hipStreamSynchronize(st) != hipSuccess) {
-                            set_error("pp_matrix_create: value-coded upload failed");
-                            return fail(PP_EDEVICE);
-                        }
-                        A->ntab = (int)tab.size();
-                        if ((s = build_patterns(A, codes, nd, tab, st)) != PP_OK) return fail(s);
-                    }
-                }
+                    hipStreamSynchronize(st) == hipSuccess)
+                    if ((s = build_value_codes(A, dp.data(), hv, st)) != PP_OK) return fail(s);
             }
         }
     }
@@ -1090,32 +1136,58 @@ namespace {
 
 // Point the handle at new FP64 values and refresh the copies derived from them.
 pp_status refresh_values(pp_matrix A, const double *val, hipStream_t st) {
-    if (A->dcode || A->pcode) {
-        // the codes describe the old values: drop them (and a tuned pick of them)
-        (void)hipStreamSynchronize(st);
-        dev_free(A->dcode);
-        dev_free(A->dtab64);
-        dev_free(A->dtab32);
-        dev_free(A->pcode);
-        dev_free(A->pbyte);
-        dev_free(A->ptab64);
-        dev_free(A->ptab32);
-        A->ntab = 0;
-        A->npat = 0;
-        for (int p = 0; p < 3; ++p)
-            if (A->variant[p] == CV_DIAC || A->variant[p] == CV_DIAP || A->variant[p] == CV_DIAPV) {
-                A->variant[p] = CV_TILE8;
-                A->tuned[p] = 0;
-            }
-    }
     A->val = val;
     HIP_TRY(launch_val_to_f32(A->nnz, val, A->val32, st));
     if (A->nslices > 0) HIP_TRY(launch_sell_values(A->npad, A->sperm, val, A->sval64, A->sval32, st));
-    for (int c = 0; c < 2; ++c)
-        if (A->bandK[c] > 0) HIP_TRY(launch_sell_values(A->bnnz[c], A->bperm[c], val, A->bval64[c], A->bval32[c], st));
     if (!A->h_doff.empty())
         HIP_TRY(launch_sell_values((long)A->h_doff.size() * (((long)A->n + 255) / 256) * 256, A->dperm, val,
                                    A->dval64, A->dval32, st));
+    for (int c = 0; c < 2; ++c)
+        if (A->bandK[c] > 0) HIP_TRY(launch_sell_values(A->bnnz[c], A->bperm[c], val, A->bval64[c], A->bval32[c], st));
+    if (A->dcode) {
+        // the codes stay when every entry still equals its code's new value
+        // (a constant-coefficient stencil with new coefficients); else drop
+        // them, and a tuned pick of them
+        HIP_TRY(launch_recode(A->nnz, val, A->ecode, A->crep, A->ntab, A->dtab64, A->dtab32,
+                              A->pcode ? A->npat * (int)A->h_doff.size() : 0, A->pcodes, A->ptab64, A->ptab32,
+                              A->rflag, st));
+        int *fl = reinterpret_cast<int *>(A->hpin);
+        HIP_TRY(hipMemcpyAsync(fl, A->rflag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (*fl) {
+            dev_free(A->dcode);
+            dev_free(A->dtab64);
+            dev_free(A->dtab32);
+            dev_free(A->ecode);
+            dev_free(A->crep);
+            dev_free(A->pcodes);
+            dev_free(A->rflag);
+            dev_free(A->pcode);
+            dev_free(A->pbyte);
+            dev_free(A->ptab64);
+            dev_free(A->ptab32);
+            A->ntab = 0;
+            A->npat = 0;
+            for (int p = 0; p < 3; ++p)
+                if (A->variant[p] == CV_DIAC || A->variant[p] == CV_DIAP || A->variant[p] == CV_DIAPV) {
+                    A->variant[p] = CV_TILE8;
+                    A->tuned[p] = 0;
+                }
+            // once per handle, code the new values afresh (classes change
+            // when, e.g., a coefficient that was zero no longer is; later
+            // values of the same classes then keep the codes)
+            if (!A->recoded) {
+                A->recoded = true;
+                const long slots = (long)A->h_doff.size() * (((long)A->n + 255) / 256) * 256;
+                std::vector<int32_t> dp(slots);
+                std::vector<double> hv(A->nnz);
+                HIP_TRY(hipMemcpyAsync(dp.data(), A->dperm, sizeof(int32_t) * slots, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(hv.data(), val, sizeof(double) * A->nnz, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                PP_TRY(build_value_codes(A, dp.data(), hv, st));
+            }
+        }
+    }
     return PP_OK;
 }
 

@@ -233,6 +233,12 @@ hipError_t launch_vmul(int n, double *x, const double *s, hipStream_t st);
 hipError_t launch_convert(int prec_in, int prec_out, int n, const void *in, void *out, hipStream_t st);
 // val32[k] = (float) val64[k]
 hipError_t launch_val_to_f32(int nnz, const double *val64, float *val32, hipStream_t st);
+// New values for the coded copies with their codes kept: tab[c] = val[crep[c]]
+// (tab[0] = 0), ptab[i] = tab[pcodes[i]] (i < nent), and *flag = 1 if some
+// entry k differs from tab[ecode[k]] (the codes are then stale).
+hipError_t launch_recode(long nnz, const double *val, const uint8_t *ecode, const int32_t *crep, int ntab,
+                         double *tab64, float *tab32, int nent, const uint8_t *pcodes, double *ptab64, float *ptab32,
+                         int *flag, hipStream_t st);
 // out[k] = in[perm[k]]
 hipError_t launch_gather(int nnz, const double *in, const int32_t *perm, double *out, hipStream_t st);
 // dval[k] = -lam[row(k)] * x[col(k)]

@@ -1737,6 +1737,38 @@ __global__ __launch_bounds__(256) void k_scale_cols(int nnz, const int32_t *coli
 }
 
 // x[i] *= s[i]
+// New values for the value- and pattern-coded copies, keeping their codes:
+// the table entry of code c is the new value of its representative entry
+// crep[c] (code 0 is zero), the pattern tables follow from their code
+// tuples, and *flag is set when some entry differs from its code's new
+// value (then the codes no longer describe the matrix).
+__global__ __launch_bounds__(256) void k_recode_table(const double *val, const int32_t *crep, int ntab, double *tab64,
+                                                      float *tab32, int *flag) {
+    const int c = threadIdx.x;
+    if (c == 0) *flag = 0;
+    if (c < ntab) {
+        const double t = (c == 0 || crep[c] < 0) ? 0.0 : val[crep[c]];
+        tab64[c] = t;
+        tab32[c] = (float)t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_recode_check(long nnz, const double *val, const uint8_t *ecode,
+                                                      const double *tab64, int *flag) {
+    const long k = (long)blockIdx.x * 256 + threadIdx.x;
+    if (k < nnz && !(val[k] == tab64[ecode[k]])) *flag = 1;
+}
+
+__global__ __launch_bounds__(256) void k_recode_patterns(int nent, const uint8_t *pcodes, const double *tab64,
+                                                         double *ptab64, float *ptab32) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < nent) {
+        const double t = tab64[pcodes[i]];
+        ptab64[i] = t;
+        ptab32[i] = (float)t;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_vmul(int n, double *x, const double *s) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i < n) x[i] *= s[i];
@@ -2020,6 +2052,19 @@ hipError_t launch_scale_cols(int nnz, const int32_t *colind, const double *val, 
     const unsigned g = blocks_for(nnz, 256);
     if (g == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scale_cols, dim3(g), dim3(256), 0, st, nnz, colind, val, s, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_recode(long nnz, const double *val, const uint8_t *ecode, const int32_t *crep, int ntab,
+                         double *tab64, float *tab32, int nent, const uint8_t *pcodes, double *ptab64, float *ptab32,
+                         int *flag, hipStream_t st) {
+    if (ntab < 1 || ntab > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_recode_table, dim3(1), dim3(256), 0, st, val, crep, ntab, tab64, tab32, flag);
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_recode_check, dim3(blocks_for(nnz, 256)), dim3(256), 0, st, nnz, val, ecode, tab64, flag);
+    if (nent > 0 && pcodes)
+        hipLaunchKernelGGL(k_recode_patterns, dim3(blocks_for(nent, 256)), dim3(256), 0, st, nent, pcodes, tab64,
+                           ptab64, ptab32);
     return hipGetLastError();
 }
 

@@ -222,24 +222,46 @@ def test_diagonal_format_edge_cases(pp, case):
 
 
 @pytest.mark.parametrize("variant", [26, 27, 30])
-def test_value_coded_copy_dropped_when_values_change(pp, variant):
+def test_value_coded_copy_follows_new_values(pp, variant):
+    # new values that keep the value classes (every coefficient scaled by
+    # -1.5) keep the codes with new tables; values that split a class drop
+    # the coded copies, and the products then use another format
     csr = convdiff3d(20, 10, 10, 10)
     A = csr.to_scipy()
     M = pp.Matrix.from_csr(csr)
-    say("coded copy", pp.chain_variant_name(variant))
+    name = pp.chain_variant_name(variant)
+    say("coded copy", name)
     M.set_variant("fp32", variant, 1)
+    M.set_variant("fp64", variant, 1)
     poly = pp.poly_from_roots([3.0, 7.5], keep_order=True)
+    units = [(chains.REAL, 3.0, 0.0), (chains.REAL, 7.5, 0.0)]
     v = rhs(csr.n, 5)
-    ref = chains.apply_phi(A, [(chains.REAL, 3.0, 0.0), (chains.REAL, 7.5, 0.0)], v)
-    assert relerr(host(pp.apply(poly, M, dev(v), "phi")).astype(np.float64), ref) <= 1e-12
-    got32 = host(pp.apply(poly, M, dev(v, torch.float32), "phi"))
-    assert relerr(got32, ref) <= 1e-5
-    M.set_values(dev(2.0 * csr.val))  # the codes no longer describe the values
+    ref = chains.apply_phi(A, units, v)
+    assert relerr(host(pp.apply(poly, M, dev(v), "phi")), ref) <= 1e-12
+    assert relerr(host(pp.apply(poly, M, dev(v, torch.float32), "phi")), ref) <= 1e-5
+    M.set_values(dev(-1.5 * csr.val))  # the same classes: the codes stay
+    assert M.variant("fp32")[0] == name and M.variant("fp64")[0] == name
+    ref2 = chains.apply_phi(-1.5 * A, units, v)
+    assert relerr(host(pp.apply(poly, M, dev(v), "phi")), ref2) <= 1e-12
+    assert relerr(host(pp.apply(poly, M, dev(v, torch.float32), "phi")), ref2) <= 1e-5
+    # entries of one class now differ: the first time, the codes are built
+    # afresh from the new values (the tuned pick is reset)
+    val3 = csr.val.copy()
+    val3[::7] *= 1.0 + 1e-3
+    M.set_values(dev(val3))
     assert M.variant("fp32")[0] is None
+    M.set_variant("fp64", variant, 1)
+    ref3 = chains.apply_phi(csr.with_values(val3).to_scipy(), units, v)
+    assert relerr(host(pp.apply(poly, M, dev(v), "phi")), ref3) <= 1e-12
+    # a second split drops the coded copies for good
+    val4 = val3.copy()
+    val4[::5] *= 1.0 - 1e-3
+    M.set_values(dev(val4))
+    assert M.variant("fp64")[0] is None
     with pytest.raises(Exception, match="value-coded" if variant == 26 else "pattern-coded"):
         M.set_variant("fp32", variant, 1)
-    ref2 = chains.apply_phi(2.0 * A, [(chains.REAL, 3.0, 0.0), (chains.REAL, 7.5, 0.0)], v)
-    assert relerr(host(pp.apply(poly, M, dev(v), "phi")), ref2) <= 1e-12
+    ref4 = chains.apply_phi(csr.with_values(val4).to_scipy(), units, v)
+    assert relerr(host(pp.apply(poly, M, dev(v), "phi")), ref4) <= 1e-12
 
 
 @pytest.mark.parametrize("case", ["fits", "over"])
