@@ -168,6 +168,31 @@ pp_status pp_matrix_right_scale(pp_matrix A, const double *s, void *stream);
  * PP_EINVAL if the handle has none. */
 pp_status pp_matrix_scale(pp_matrix A, double *s, void *stream);
 
+/* Composition with block-Jacobi (eqs. (1.3)-(1.4), section 1, and
+ * section 3.1: the polynomial is built for A M^{-1}): M is the block
+ * diagonal of A in blocks of bs consecutive rows (1 <= bs <= 64; the last
+ * block holds the remaining rows). B = A M^{-1} is a new sparse matrix
+ * (row i of B gathers a_ij times row j of M^{-1}, so B holds whole blocks of
+ * columns), built on the host from A's current values:
+ *   pp_block_jacobi_nnz writes B's number of stored entries (host *nnz_b);
+ *   pp_block_jacobi fills caller-allocated device arrays with B's CSR
+ *     (rowptr_b int32[n+1], colind_b int32[nnz_b] ascending in each row,
+ *     val_b double[nnz_b]) and M^{-1}'s blocks (minv double[ceil(n/bs) bs bs],
+ *     block k row-major at minv + k bs bs, entry (r, c) of the block is
+ *     (M^{-1})_{k bs + r, k bs + c});
+ *   pp_matrix_right_blocks attaches minv (copied) to a handle B made from
+ *     those arrays: pp_solve on B then solves phi(B) y = b and returns
+ *     x = M^{-1} p(B) y, the solution of A x = b (after a right scaling of
+ *     B, if any, is undone); pp_gmres_setup and pp_apply work on B.
+ * PP_ESINGULAR if a diagonal block is singular (a zero pivot after partial
+ * pivoting, in double). PP_EINVAL if A already has a right scaling or
+ * right blocks (its solution would then need both undone). A handle with
+ * right blocks has no transpose (pp_matrix_transpose returns PP_EINVAL). */
+pp_status pp_block_jacobi_nnz(pp_matrix A, int bs, void *stream, int64_t *nnz_b);
+pp_status pp_block_jacobi(pp_matrix A, int bs, int32_t *rowptr_b, int32_t *colind_b, double *val_b, double *minv,
+                          void *stream);
+pp_status pp_matrix_right_blocks(pp_matrix B, int bs, const double *minv, void *stream);
+
 /* Name of a chain-step variant ("tile8x1", "vec8x4", ...). */
 const char *pp_chain_variant_name(int variant);
 

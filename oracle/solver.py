@@ -239,6 +239,25 @@ def setup_checked(A, v0: np.ndarray, d: int, b: np.ndarray, tol: float, d_step: 
     return best[0], best[1], True, tried
 
 
+def block_jacobi(A, bs: int):
+    """The operator A M^{-1} for block-Jacobi (eqs. (1.3)-(1.4) with M the
+    block diagonal of A in blocks of bs consecutive rows; the last block
+    holds the remaining rows). Each diagonal block is inverted densely
+    (numpy.linalg.inv); the polynomial is then built on A M^{-1} (section
+    3.1) and x = M^{-1} x~ where x~ solves (A M^{-1}) x~ = b.
+    Returns (A M^{-1} as scipy CSR, M^{-1} as scipy CSR)."""
+    import scipy.sparse as sp
+
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    blocks = []
+    for r0 in range(0, n, bs):
+        r1 = min(r0 + bs, n)
+        blocks.append(np.linalg.inv(A[r0:r1, r0:r1].toarray()))
+    Minv = sp.block_diag(blocks, format="csr")
+    return (A @ Minv).tocsr(), Minv
+
+
 def right_scaled(A, s=None):
     """The operator A M^{-1} for a diagonal right preconditioner M^{-1} =
     diag(s) (eqs. (1.3)-(1.4)); s=None is Jacobi, s_i = 1 / a_ii.

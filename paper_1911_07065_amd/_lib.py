@@ -73,6 +73,9 @@ SIGNATURES = {
                                 ctypes.POINTER(c_void_p)]),
     "pp_batch_set_values": (c_int, [c_void_p, c_void_p, c_void_p]),
     "pp_batch_set_format": (c_int, [c_void_p, c_int]),
+    "pp_block_jacobi_nnz": (c_int, [c_void_p, c_int, c_void_p, ctypes.POINTER(c_int64)]),
+    "pp_block_jacobi": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pp_matrix_right_blocks": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     "pp_batch_format": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
     "pp_batch_destroy": (None, [c_void_p]),
     "pp_batch_setup": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p),

@@ -102,6 +102,27 @@ class Matrix:
             raise
         self.scaling = "jacobi" if s is None else "custom"
 
+    def block_jacobi(self, bs: int) -> "Matrix":
+        """Compose with block-Jacobi (eqs. 1.3-1.4): M is the block diagonal of
+        this matrix's current values in blocks of bs consecutive rows. Returns
+        a new Matrix for B = A M^{-1}; polynomials built on it are polynomials
+        in A M^{-1}, and solve() on it returns the solution of A x = b. The
+        blocks of M^{-1} are in `.minv` (block k row-major at k*bs*bs)."""
+        bs = int(bs)
+        st = _stream(self.device)
+        nnz_b = ctypes.c_int64()
+        check(lib.pp_block_jacobi_nnz(self.handle, bs, st, ctypes.byref(nnz_b)), "pp_block_jacobi_nnz")
+        nb = (self.n + bs - 1) // bs
+        rp = torch.empty(self.n + 1, dtype=torch.int32, device=self.device)
+        ci = torch.empty(max(nnz_b.value, 1), dtype=torch.int32, device=self.device)
+        va = torch.empty(max(nnz_b.value, 1), dtype=torch.float64, device=self.device)
+        mi = torch.empty(nb * bs * bs, dtype=torch.float64, device=self.device)
+        check(lib.pp_block_jacobi(self.handle, bs, _ptr(rp), _ptr(ci), _ptr(va), _ptr(mi), st), "pp_block_jacobi")
+        B = Matrix(rp, ci[: nnz_b.value], va[: nnz_b.value], device=self.device)
+        check(lib.pp_matrix_right_blocks(B.handle, bs, _ptr(mi), st), "pp_matrix_right_blocks")
+        B.minv, B.block_size = mi, bs
+        return B
+
     def scale(self) -> torch.Tensor:
         """The right scaling s of a scaled Matrix."""
         out = torch.empty(self.n, dtype=torch.float64, device=self.device)

@@ -71,6 +71,10 @@ struct pp_matrix_s {
     uint8_t *pcodes = nullptr;
     int *rflag = nullptr;
     bool recoded = false;  // the codes were rebuilt once from new values
+    // block-Jacobi right preconditioner of a handle made for B = A M^{-1}:
+    // pp_solve returns x = M^{-1} x~ (blocks of rbs rows, stride rbs)
+    int rbs = 0;
+    double *rminv = nullptr;
     // column-banded CSR copies (matrices whose entries lie far from the
     // diagonal): c = 0 two bands, c = 1 four; bperm maps entries to CSR
     int32_t *brow[2] = {nullptr, nullptr}, *bcol[2] = {nullptr, nullptr}, *bperm[2] = {nullptr, nullptr};
@@ -267,6 +271,7 @@ struct pp_matrix_s {
         dev_free(crep);
         dev_free(pcodes);
         dev_free(rflag);
+        dev_free(rminv);
         dev_free(pcode);
         dev_free(pbyte);
         dev_free(ptab64);
@@ -1227,6 +1232,121 @@ void drop_scaling(pp_matrix A, hipStream_t st) {
 
 }  // namespace
 
+namespace {
+
+// Inverse of the m x m matrix a (row-major, overwritten) into inv (row
+// stride ld) by Gauss-Jordan elimination with partial pivoting; false if a
+// pivot is exactly zero.
+bool invert_block(int m, std::vector<double> &a, double *inv, int ld) {
+    std::vector<double> b((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) b[(size_t)i * m + i] = 1.0;
+    for (int c = 0; c < m; ++c) {
+        int p = c;
+        for (int r = c + 1; r < m; ++r)
+            if (std::fabs(a[(size_t)r * m + c]) > std::fabs(a[(size_t)p * m + c])) p = r;
+        const double piv = a[(size_t)p * m + c];
+        if (piv == 0.0) return false;
+        if (p != c)
+            for (int k = 0; k < m; ++k) {
+                std::swap(a[(size_t)p * m + k], a[(size_t)c * m + k]);
+                std::swap(b[(size_t)p * m + k], b[(size_t)c * m + k]);
+            }
+        for (int k = 0; k < m; ++k) {
+            a[(size_t)c * m + k] /= piv;
+            b[(size_t)c * m + k] /= piv;
+        }
+        for (int r = 0; r < m; ++r) {
+            if (r == c) continue;
+            const double f = a[(size_t)r * m + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < m; ++k) {
+                a[(size_t)r * m + k] -= f * a[(size_t)c * m + k];
+                b[(size_t)r * m + k] -= f * b[(size_t)c * m + k];
+            }
+        }
+    }
+    for (int r = 0; r < m; ++r)
+        for (int k = 0; k < m; ++k) inv[(size_t)r * ld + k] = b[(size_t)r * m + k];
+    return true;
+}
+
+// B = A M^{-1} for the block-Jacobi M of A's current values (blocks of bs
+// rows): M^{-1}'s blocks into minv (stride bs), B's CSR into brp/bci/bv
+// (built only when bci is not null; nnz_b always). Row i of B: for each
+// block J its columns touch, sum_j a_ij (M^{-1})_{j, J bs + c} over the
+// entries j of that block, in column order, for every column c of J.
+pp_status block_jacobi_build(pp_matrix A, int bs, hipStream_t st, int64_t *nnz_b, std::vector<double> &minv,
+                             std::vector<int32_t> *brp, std::vector<int32_t> *bci, std::vector<double> *bv) {
+    if (A->scale_mode != 0 || A->rbs > 0) {
+        set_error("block-Jacobi: the handle already has a right preconditioner");
+        return PP_EINVAL;
+    }
+    const int64_t n = A->n, nnz = A->nnz;
+    const int64_t nb = (n + bs - 1) / bs;
+    std::vector<int32_t> ci(nnz);
+    std::vector<double> hv(nnz);
+    if (nnz) {
+        HIP_TRY(hipMemcpyAsync(ci.data(), A->colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hv.data(), A->val, sizeof(double) * nnz, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    const auto &rp = A->h_rowptr;
+    minv.assign((size_t)nb * bs * bs, 0.0);
+    std::vector<double> d;
+    for (int64_t k = 0; k < nb; ++k) {
+        const int64_t r0 = k * bs;
+        const int m = (int)std::min<int64_t>(bs, n - r0);
+        d.assign((size_t)m * m, 0.0);
+        for (int64_t r = r0; r < r0 + m; ++r)
+            for (int e = rp[r]; e < rp[r + 1]; ++e)
+                if (ci[e] >= r0 && ci[e] < r0 + m) d[(size_t)(r - r0) * m + (ci[e] - r0)] += hv[e];
+        if (!invert_block(m, d, minv.data() + (size_t)k * bs * bs, bs)) {
+            set_error("block-Jacobi: a diagonal block is singular");
+            return PP_ESINGULAR;
+        }
+    }
+    int64_t tot = 0;
+    std::vector<std::pair<int32_t, double>> row;
+    std::vector<double> acc(bs);
+    if (brp) brp->assign((size_t)n + 1, 0);
+    if (bci) {
+        bci->clear();
+        bv->clear();
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        row.clear();
+        for (int e = rp[i]; e < rp[i + 1]; ++e) row.emplace_back(ci[e], hv[e]);
+        std::stable_sort(row.begin(), row.end(),
+                         [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+                             return a.first < b.first;
+                         });
+        for (size_t q = 0; q < row.size();) {
+            const int64_t J = row[q].first / bs, c0 = J * bs;
+            const int mJ = (int)std::min<int64_t>(bs, n - c0);
+            std::fill(acc.begin(), acc.end(), 0.0);
+            for (; q < row.size() && row[q].first / bs == J; ++q) {
+                const double *mr = minv.data() + (size_t)J * bs * bs + (size_t)(row[q].first - c0) * bs;
+                for (int c = 0; c < mJ; ++c) acc[c] += row[q].second * mr[c];
+            }
+            tot += mJ;
+            if (bci)
+                for (int c = 0; c < mJ; ++c) {
+                    bci->push_back((int32_t)(c0 + c));
+                    bv->push_back(acc[c]);
+                }
+        }
+        if (brp) (*brp)[(size_t)i + 1] = (int32_t)tot;
+        if (tot >= (1LL << 31)) {
+            set_error("block-Jacobi: B = A M^{-1} has too many entries");
+            return PP_EINVAL;
+        }
+    }
+    *nnz_b = tot;
+    return PP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 pp_status pp_matrix_set_values(pp_matrix A, const double *val, void *stream) {
@@ -1275,6 +1395,50 @@ pp_status pp_matrix_scale(pp_matrix A, double *s, void *stream) {
         return PP_EINVAL;
     }
     HIP_TRY(hipMemcpyAsync(s, A->scale, sizeof(double) * A->n, hipMemcpyDeviceToDevice, S(stream)));
+    return PP_OK;
+}
+
+pp_status pp_block_jacobi_nnz(pp_matrix A, int bs, void *stream, int64_t *nnz_b) {
+    if (!A || !nnz_b || bs < 1 || bs > kMaxRightBlock) {
+        set_error("pp_block_jacobi_nnz: bad argument");
+        return PP_EINVAL;
+    }
+    std::vector<double> minv;
+    return block_jacobi_build(A, bs, S(stream), nnz_b, minv, nullptr, nullptr, nullptr);
+}
+
+pp_status pp_block_jacobi(pp_matrix A, int bs, int32_t *rowptr_b, int32_t *colind_b, double *val_b, double *minv,
+                          void *stream) {
+    if (!A || !rowptr_b || !colind_b || !val_b || !minv || bs < 1 || bs > kMaxRightBlock) {
+        set_error("pp_block_jacobi: bad argument");
+        return PP_EINVAL;
+    }
+    hipStream_t st = S(stream);
+    int64_t nb = 0;
+    std::vector<double> mv, bv;
+    std::vector<int32_t> brp, bci;
+    PP_TRY(block_jacobi_build(A, bs, st, &nb, mv, &brp, &bci, &bv));
+    HIP_TRY(hipMemcpyAsync(rowptr_b, brp.data(), sizeof(int32_t) * brp.size(), hipMemcpyHostToDevice, st));
+    if (nb) {
+        HIP_TRY(hipMemcpyAsync(colind_b, bci.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(val_b, bv.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
+    }
+    HIP_TRY(hipMemcpyAsync(minv, mv.data(), sizeof(double) * mv.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return PP_OK;
+}
+
+pp_status pp_matrix_right_blocks(pp_matrix B, int bs, const double *minv, void *stream) {
+    if (!B || !minv || bs < 1 || bs > kMaxRightBlock) {
+        set_error("pp_matrix_right_blocks: bad argument");
+        return PP_EINVAL;
+    }
+    const size_t len = (size_t)((B->n + bs - 1) / bs) * bs * bs;
+    dev_free(B->rminv);
+    B->rbs = 0;
+    PP_TRY(dev_alloc(&B->rminv, len));
+    HIP_TRY(hipMemcpyAsync(B->rminv, minv, sizeof(double) * len, hipMemcpyDeviceToDevice, S(stream)));
+    B->rbs = bs;
     return PP_OK;
 }
 
@@ -1357,6 +1521,10 @@ const char *pp_chain_variant_name(int variant) { return chain_variant_name(varia
 pp_status pp_matrix_transpose(pp_matrix A, int32_t *rowptr_t, int32_t *colind_t, int32_t *perm, void *stream) {
     if (!A || !rowptr_t || (A->nnz > 0 && (!colind_t || !perm))) {
         set_error("pp_matrix_transpose: bad argument");
+        return PP_EINVAL;
+    }
+    if (A->rbs > 0) {
+        set_error("pp_matrix_transpose: the handle has a block-Jacobi right preconditioner");
         return PP_EINVAL;
     }
     hipStream_t st = S(stream);
@@ -1834,6 +2002,8 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
     }
     // composition with a right preconditioner: x = diag(s) x~ (eq. (1.4))
     if (A->scale_mode != 0) HIP_TRY(launch_vmul(n, x, A->scale, st));
+    // composition with block-Jacobi: x = M^{-1} x~
+    if (A->rbs > 0) HIP_TRY(launch_block_apply(n, A->rbs, A->rminv, x, st));
     inf.status = status;
     inf.t_solve_s = now_s() - t0;
     if (info) *info = inf;

@@ -77,7 +77,8 @@ struct StepPtrs {
 
 // Diagonals of the diagonal format, passed by value (uniform per launch).
 constexpr int kMaxDiag = 32;
-constexpr int kMaxPatEntries = 1024;  // rows patterns x diagonals of the pattern-coded format
+constexpr int kMaxPatEntries = 1024;
+constexpr int kMaxRightBlock = 64;    // largest block of a block-Jacobi right preconditioner  // rows patterns x diagonals of the pattern-coded format
 struct DiaOffsets {
     int nd;               // number of diagonals (0: no diagonal-format copy)
     int off[kMaxDiag];    // column - row of each diagonal, ascending
@@ -233,6 +234,9 @@ hipError_t launch_vmul(int n, double *x, const double *s, hipStream_t st);
 hipError_t launch_convert(int prec_in, int prec_out, int n, const void *in, void *out, hipStream_t st);
 // val32[k] = (float) val64[k]
 hipError_t launch_val_to_f32(int nnz, const double *val64, float *val32, hipStream_t st);
+// x = M^{-1} x in place, M^{-1} block diagonal with blocks of bs rows
+// (bs <= kMaxRightBlock; block k row-major with stride bs at minv + k bs bs)
+hipError_t launch_block_apply(int n, int bs, const double *minv, double *x, hipStream_t st);
 // New values for the coded copies with their codes kept: tab[c] = val[crep[c]]
 // (tab[0] = 0), ptab[i] = tab[pcodes[i]] (i < nent), and *flag = 1 if some
 // entry k differs from tab[ecode[k]] (the codes are then stale).

@@ -1769,6 +1769,24 @@ __global__ __launch_bounds__(256) void k_recode_patterns(int nent, const uint8_t
     }
 }
 
+// x = M^{-1} x~ in place for a block-diagonal M^{-1}: one thread per block of
+// bs rows (the last may be shorter), block k row-major with stride bs.
+template <int BS>
+__global__ __launch_bounds__(64) void k_block_apply(int n, int bs, const double *minv, double *x) {
+    const long k = (long)blockIdx.x * 64 + threadIdx.x;
+    const long r0 = k * bs;
+    if (r0 >= n) return;
+    const int m = (int)min((long)bs, (long)n - r0);
+    double t[BS];
+    for (int c = 0; c < m; ++c) t[c] = x[r0 + c];
+    const double *b = minv + k * bs * bs;
+    for (int r = 0; r < m; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < m; ++c) s += b[r * bs + c] * t[c];
+        x[r0 + r] = s;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_vmul(int n, double *x, const double *s) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i < n) x[i] *= s[i];
@@ -2065,6 +2083,20 @@ hipError_t launch_recode(long nnz, const double *val, const uint8_t *ecode, cons
     if (nent > 0 && pcodes)
         hipLaunchKernelGGL(k_recode_patterns, dim3(blocks_for(nent, 256)), dim3(256), 0, st, nent, pcodes, tab64,
                            ptab64, ptab32);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_apply(int n, int bs, const double *minv, double *x, hipStream_t st) {
+    if (bs < 1 || bs > kMaxRightBlock) return hipErrorInvalidValue;
+    const long nb = ((long)n + bs - 1) / bs;
+    const unsigned g = (unsigned)((nb + 63) / 64);
+    if (g == 0) return hipSuccess;
+    if (bs <= 8)
+        hipLaunchKernelGGL(k_block_apply<8>, dim3(g), dim3(64), 0, st, n, bs, minv, x);
+    else if (bs <= 16)
+        hipLaunchKernelGGL(k_block_apply<16>, dim3(g), dim3(64), 0, st, n, bs, minv, x);
+    else
+        hipLaunchKernelGGL(k_block_apply<kMaxRightBlock>, dim3(g), dim3(64), 0, st, n, bs, minv, x);
     return hipGetLastError();
 }
 

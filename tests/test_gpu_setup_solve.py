@@ -2,11 +2,12 @@
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 import scipy.sparse.linalg as sla
 import torch
 
 from oracle import roots as oroots, solver as osolver
-from workloads import convdiff2d, convdiff3d, diag_example7, diagonal, randsparse, rhs, start_vector
+from workloads import convdiff2d, convdiff2d_blockmixed, convdiff3d, diag_example7, diagonal, randsparse, rhs, start_vector
 from gpu_util import say, dev, host, relerr
 
 pytestmark = pytest.mark.gpu
@@ -298,6 +299,94 @@ def test_custom_right_scaling_and_errors(pp):
     ident = pp.poly_from_roots([1.0])
     v = rhs(csr.n, 7)
     assert relerr(host(pp.apply(ident, Mz, dev(v), "phi")), csr.with_values(vals).to_scipy() @ v) <= 1e-14
+
+
+def test_block_jacobi_operator_matches_oracle(pp):
+    # B = A M^{-1} and M^{-1}'s blocks against the oracle (bs = 3 leaves a
+    # one-row last block; bs = 40 takes whole grid lines). Two inversions of
+    # a block D in double differ by about kappa(D) eps |D^{-1}|, so the
+    # columns of block J of B may differ by c kappa(D_J) eps (|A| |M^{-1}|),
+    # c = 4 bs; the mixed case has kappa up to 1e4.
+
+    for csr, bs in ((convdiff2d(20, 5.0), 3), (convdiff2d_blockmixed(24, 5.0, 4, 2.0), 4), (convdiff2d(40, 40.0), 40)):
+        A = csr.to_scipy()
+        say("block jacobi operator", csr.n, bs)
+        M = pp.Matrix.from_csr(csr)
+        B = M.block_jacobi(bs)
+        Bo, Mo = osolver.block_jacobi(A, bs)
+        brp, bci = B.rowptr.cpu().numpy(), B.colind.cpu().numpy()
+        Bg = sp.csr_matrix((host(B.val), bci, brp), shape=A.shape)
+        nblk = (csr.n + bs - 1) // bs
+        kap = np.array([np.linalg.cond(A[k * bs:(k + 1) * bs, k * bs:(k + 1) * bs].toarray()) for k in range(nblk)])
+        bound = 4 * bs * np.finfo(float).eps * kap[np.arange(csr.n) // bs] * (abs(A) @ abs(Mo)).max(axis=0).toarray()
+        assert np.all(np.abs((Bg - Bo).toarray()) <= bound)
+        # every row of B holds whole blocks of columns
+        for i in range(0, csr.n, max(1, csr.n // 37)):
+            cols = bci[brp[i]:brp[i + 1]]
+            assert np.array_equal(cols, np.unique(cols))
+            for c in np.unique(cols // bs):
+                assert np.sum(cols // bs == c) == min(bs, csr.n - c * bs)
+        mi = host(B.minv).reshape(-1, bs, bs)
+        for k in range(0, nblk, 7):
+            m = min(bs, csr.n - k * bs)
+            assert np.max(np.abs(mi[k, :m, :m] - Mo[k * bs:k * bs + m, k * bs:k * bs + m].toarray())) <= \
+                4 * bs * np.finfo(float).eps * kap[k] * np.max(np.abs(mi[k, :m, :m]))
+        v = rhs(csr.n, 7)
+        ident = pp.poly_from_roots([1.0])
+        # the handle's operator is the B it returned
+        assert relerr(host(pp.apply(ident, B, dev(v), "phi")), Bg @ v) <= 1e-13
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_block_jacobi_composed_solve_matches_oracle(pp, inner):
+
+    csr = convdiff2d_blockmixed(40, 5.0, 4, 2.0)
+    A = csr.to_scipy()
+    b, v0 = rhs(csr.n, 1), start_vector(csr.n, 2)
+    say("block jacobi solve", inner)
+    B = pp.Matrix.from_csr(csr).block_jacobi(4)
+    poly = pp.setup(B, dev(v0), 10)
+    Bo, Mo = osolver.block_jacobi(A, 4)
+    P = oroots.setup(Bo, v0, 10, orth="cgs2")
+    assert _multiset_relerr(poly.roots("theta"), P.theta) < 1e-8
+    x, info = pp.solve(poly, B, dev(b), tol=1e-8, m=50, inner=inner)
+    xh = host(x)
+    assert info["converged"] and info["cycles"] <= 3
+    assert np.linalg.norm(b - A @ xh) <= 1e-8 * np.linalg.norm(b)
+    y, _ = osolver.pp_gmres(Bo, b, P.units, m=50, tol=1e-8)
+    say("result block-jacobi", inner, "relres", np.linalg.norm(b - A @ xh) / np.linalg.norm(b), "x_err_vs_oracle",
+        relerr(xh, Mo @ y))
+    assert relerr(xh, Mo @ y) <= 2e-5
+    # the same degree on the mixed matrix itself does not converge
+    M0 = pp.Matrix.from_csr(csr)
+    x0, info0 = pp.solve(pp.setup(M0, dev(v0), 10), M0, dev(b), tol=1e-8, m=50, max_cycles=30, inner=inner)
+    assert not info0["converged"]
+
+
+def test_block_jacobi_errors(pp):
+    csr = convdiff2d(12, 3.0)
+    M = pp.Matrix.from_csr(csr)
+    for bs in (0, 65):
+        with pytest.raises(Exception):
+            M.block_jacobi(bs)
+    # a singular diagonal block: rows 4 and 5 of the block [4, 6) made equal
+    A = csr.to_scipy().tolil()
+    A[5, 4], A[5, 5] = A[4, 4], A[4, 5]
+    A = A.tocsr()
+    A.sort_indices()
+    Ms = pp.Matrix(A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
+    with pytest.raises(Exception, match="singular"):
+        Ms.block_jacobi(2)
+    B = M.block_jacobi(4)
+    with pytest.raises(Exception, match="block-Jacobi"):
+        B.transpose()
+    # a handle that is already right-preconditioned
+    with pytest.raises(Exception, match="right preconditioner"):
+        B.block_jacobi(4)
+    Ms2 = pp.Matrix.from_csr(csr)
+    Ms2.right_scale()
+    with pytest.raises(Exception, match="right preconditioner"):
+        Ms2.block_jacobi(2)
 
 
 def test_jacobi_composed_gradient(pp):

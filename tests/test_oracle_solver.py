@@ -264,6 +264,53 @@ def test_custom_right_scaling_solves():
     assert np.linalg.norm(b - A @ (s * xt)) <= 1e-10 * np.linalg.norm(b)
 
 
+def test_block_jacobi_operator_closed_forms():
+    import scipy.sparse as sp
+
+    from workloads import convdiff2d_blockmixed
+
+    A0 = convdiff2d(20, 5.0).to_scipy()
+    n = A0.shape[0]
+    # bs = 1 is Jacobi: a_ij / a_jj
+    B1, M1 = solver.block_jacobi(A0, 1)
+    AS, s = solver.right_scaled(A0)
+    assert np.array_equal(M1.diagonal(), s)
+    assert np.max(np.abs((B1 - AS).toarray())) <= 2 * np.finfo(float).eps * np.max(np.abs(AS.data))
+    # M^{-1} inverts the diagonal blocks (bs = 3: the last block holds one row)
+    B, Minv = solver.block_jacobi(A0, 3)
+    Mb = sp.block_diag([A0[r:r + 3, r:r + 3].toarray() for r in range(0, n, 3)], format="csr")
+    assert np.max(np.abs((Minv @ Mb - sp.identity(n)).toarray())) <= 1e-14
+    # B (M x) = A x, and B's diagonal blocks are the identity
+    x = np.random.default_rng(3).standard_normal(n)
+    assert np.linalg.norm(B @ (Mb @ x) - A0 @ x) <= 1e-13 * np.linalg.norm(A0 @ x)
+    for r in range(0, n, 3):
+        blk = B[r:r + 3, r:r + 3].toarray()
+        assert np.max(np.abs(blk - np.eye(blk.shape[0]))) <= 1e-14
+    # a block-diagonal mixing R on the right cancels: (A0 R) M^{-1} = A0 M0^{-1}
+    Am = convdiff2d_blockmixed(20, 5.0, 4, 2.0).to_scipy()
+    Bm, _ = solver.block_jacobi(Am, 4)
+    B0, _ = solver.block_jacobi(A0, 4)
+    assert np.max(np.abs((Bm - B0).toarray())) <= 1e-11 * np.max(np.abs(B0.data))
+
+
+def test_block_jacobi_composition_solves_mixed_system():
+    from workloads import convdiff2d_blockmixed
+
+    A = convdiff2d_blockmixed(40, 5.0, 4, 2.0).to_scipy()
+    n = A.shape[0]
+    b, v0 = rhs(n, 1), start_vector(n, 2)
+    B, Minv = solver.block_jacobi(A, 4)
+    PB = roots.setup(B, v0, 10, orth="cgs2")
+    y, inf = solver.pp_gmres(B, b, PB.units, m=50, tol=1e-8, max_cycles=30)
+    x = Minv @ y
+    assert inf.status == solver.OK and inf.cycles <= 2
+    assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
+    assert np.linalg.norm(x - sla.spsolve(A.tocsc(), b)) <= 1e-5 * np.linalg.norm(x)
+    P = roots.setup(A, v0, 10, orth="cgs2")
+    _, inf0 = solver.pp_gmres(A, b, P.units, m=50, tol=1e-8, max_cycles=30)
+    assert inf0.status == solver.NOCONV
+
+
 # ---------------------------------------------------------------------------
 # polynomial changed at every cycle (section 5.2, ChPoly)
 # ---------------------------------------------------------------------------

@@ -9,7 +9,7 @@ from .generators import (  # noqa: F401
     CSR,
     convdiff2d,
     convdiff2d_parts,
-    convdiff2d_colscaled,
+    convdiff2d_colscaled, convdiff2d_blockmixed,
     convdiff3d,
     randsparse,
     biharmonic2d,

@@ -135,6 +135,30 @@ def convdiff2d_colscaled(N: int, alpha: float = 0.0, decades: float = 3.0, seed:
     return base.with_values(base.val * s[base.colind])
 
 
+def convdiff2d_blockmixed(N: int, alpha: float = 0.0, bs: int = 4, decades: float = 2.0, seed: int = 11) -> CSR:
+    """The 2-D convection-diffusion matrix times a block-diagonal matrix R on
+    the right (blocks of bs consecutive columns, the last one shorter): each
+    block is U diag(10^u) V with U, V random orthogonal (QR of N(0,1)
+    draws) and u ~ U(-decades, decades), all from the seed. A badly mixed
+    system for the composition with block-Jacobi; the stored pattern holds
+    whole blocks of columns."""
+    import scipy.sparse as sp
+
+    base = convdiff2d(N, alpha).to_scipy()
+    n = base.shape[0]
+    rng = np.random.default_rng(seed)
+    blocks = []
+    for r0 in range(0, n, bs):
+        m = min(bs, n - r0)
+        U, _ = np.linalg.qr(rng.standard_normal((m, m)))
+        V, _ = np.linalg.qr(rng.standard_normal((m, m)))
+        blocks.append(U @ np.diag(10.0 ** rng.uniform(-decades, decades, m)) @ V)
+    A = (base @ sp.block_diag(blocks, format="csr")).tocsr()
+    A.sort_indices()
+    return CSR(n=n, rowptr=A.indptr.astype(np.int32), colind=A.indices.astype(np.int32),
+               val=A.data.astype(np.float64))
+
+
 def convdiff3d(N: int, cx: float = 0.0, cy: float = 0.0, cz: float = 0.0, gamma: float = 0.0) -> CSR:
     """3-D convection-diffusion, 7-point stencil on an N^3 interior grid."""
     rowptr, colind, val = _stencil(N, 3, (float(cx), float(cy), float(cz)), float(gamma))
