@@ -79,12 +79,13 @@ struct pp_batch_s {
     PStep *desc_spmv = nullptr, *desc_res = nullptr;  // nsys x 1 uniform programs
 
     int *act = nullptr;     // device: per-system active flags of the Arnoldi loop
+    int *ones = nullptr;    // device: all systems active (the unmasked chain's flags)
     int *actpin = nullptr;  // pinned mirror
     int *kdev = nullptr;    // device: columns per pair of the last cycle
     int *kpin = nullptr;
     BatchSell sell(int, bool masked = false) const {
         BatchSell s;
-        s.active = masked ? act : nullptr;
+        s.active = masked ? act : ones;
         s.slice = slice;
         s.sptr = sptr;
         s.scol = scol;
@@ -210,6 +211,7 @@ struct pp_batch_s {
         dev_free(desc_spmv);
         dev_free(desc_res);
         dev_free(act);
+        dev_free(ones);
         dev_free(kdev);
         if (actpin) (void)hipHostFree(actpin);
         if (kpin) (void)hipHostFree(kpin);
@@ -558,6 +560,14 @@ pp_status pp_batch_create(int nsys, const int64_t *row_off, int64_t nnz, const i
     }
     if ((s = upload(d1, &B->desc_spmv, st)) != PP_OK || (s = upload(dr, &B->desc_res, st)) != PP_OK) return fail(s);
     if ((s = dev_alloc(&B->act, (size_t)nsys)) != PP_OK) return fail(s);
+    if ((s = dev_alloc(&B->ones, (size_t)nsys)) != PP_OK) return fail(s);
+    {
+        const std::vector<int> h1(nsys, 1);
+        if (hipMemcpy(B->ones, h1.data(), sizeof(int) * nsys, hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("hipMemcpy failed");
+            return fail(PP_EDEVICE);
+        }
+    }
     if ((s = build_batch_patterns(B, rp, ci, val, st)) != PP_OK) return fail(s);
     if (hipHostMalloc((void **)&B->actpin, sizeof(int) * nsys, hipHostMallocDefault) != hipSuccess) {
         B->actpin = nullptr;

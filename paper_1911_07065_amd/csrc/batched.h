@@ -24,7 +24,7 @@ struct BatchSell {
     const double *sval64;
     const float *sval32;
     int nslices;
-    const int *active;  // per system: 0 = skip its slices (null: all run)
+    const int *active;  // per system: 0 = skip its slices (never null)
     // pattern-coded copy (used when bpat is not null): the rows of system s
     // lie on pnd diagonals with offsets poff[s*pnd + d]; row i of system s
     // holds ptab[ptoff[s] + bpat[i]*pnd + d] on diagonal d (0 where it has

@@ -5,7 +5,9 @@
 // * The chain reads the batch's sliced-ELL copy once per step for all R
 //   right-hand sides (interleaved vectors: the gather of one entry fetches
 //   R consecutive values). Each slice belongs to one system and reads that
-//   system's step descriptor (its own polynomial).
+//   system's step descriptor (its own polynomial). Workgroups are remapped
+//   so that consecutive slices run on one XCD: a row's neighbours a grid
+//   line away are then in that XCD's L2, not fetched again by another.
 // * Gram-Schmidt works on system-aligned row blocks; per-block partial sums
 //   are reduced per system in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
@@ -68,64 +70,106 @@ struct BChainArgs {
     XT *bufs[5];
 };
 
+// Buffers of one chain step for a row. Every load of the row's update goes
+// out unconditionally, before the product's gathers are used: an absent
+// vector is read from `in` again and dropped by a select.
+template <typename XT>
+struct BRow {
+    const XT *in, *aux, *fin, *accr;
+    XT *out, *acc;
+};
+
+template <typename VT, typename XT>
+__device__ __forceinline__ BRow<XT> brow_ptrs(const BChainArgs<VT, XT> &a, const PStep &st) {
+    BRow<XT> p;
+    p.in = a.bufs[st.in];
+    p.aux = st.aux >= 0 ? a.bufs[st.aux] : p.in;
+    p.fin = st.fin ? a.bufs[0] : p.in;
+    p.out = st.out >= 0 ? a.bufs[st.out] : nullptr;
+    p.acc = st.acc >= 0 ? a.bufs[st.acc] : nullptr;
+    p.accr = (st.acc >= 0 && !st.acc_init) ? p.acc : p.in;
+    return p;
+}
+
+template <typename XT, int R>
+struct BRowIn {
+    typename Arith<XT>::T xin[R], aux[R], acc[R], fin[R];
+};
+
+template <typename XT, int R>
+__device__ __forceinline__ void brow_load(const BRow<XT> &p, long i, BRowIn<XT, R> &t) {
+    ldr<XT, R>(p.in, i, t.xin);
+    ldr<XT, R>(p.aux, i, t.aux);
+    ldr<XT, R>(p.accr, i, t.acc);
+    ldr<XT, R>(p.fin, i, t.fin);
+}
+
 // The chain update of one row after its sparse product s (R right-hand
 // sides): w = a0 s + a1 in (+ a2 aux), then acc and out as in k_chain.
 template <typename XT, int R>
-__device__ __forceinline__ void bchain_finish(const PStep &st, const XT *in, const XT *aux, const XT *vfin, XT *out,
-                                              XT *acc, long row, const typename Arith<XT>::T *s) {
+__device__ __forceinline__ void bchain_finish(const PStep &st, const BRow<XT> &p, const BRowIn<XT, R> &t, long row,
+                                              const typename Arith<XT>::T *s) {
     using AT = typename Arith<XT>::T;
     const AT a0 = (AT)st.a0, a1 = (AT)st.a1, a2 = (AT)st.a2, b0 = (AT)st.b0, b1 = (AT)st.b1;
-    AT xin[R], wv[R], t[R];
-    ldr<XT, R>(in, row, xin);
+    const bool has_aux = st.aux >= 0, zero_acc = st.acc_init != 0, fin = st.fin != 0;
+    AT wv[R], o[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) wv[r] = a0 * s[r] + a1 * xin[r];
-    if (aux) {
-        ldr<XT, R>(aux, row, t);
-#pragma unroll
-        for (int r = 0; r < R; ++r) wv[r] += a2 * t[r];
+    for (int r = 0; r < R; ++r) {
+        const AT w = a0 * s[r] + a1 * t.xin[r];
+        const AT wa = w + a2 * t.aux[r];
+        wv[r] = has_aux ? wa : w;
     }
-    if (acc) {
-        if (st.acc_init) {
+    if (p.acc) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) t[r] = AT(0);
-        } else {
-            ldr<XT, R>(acc, row, t);
+        for (int r = 0; r < R; ++r) {
+            const AT c = zero_acc ? AT(0) : t.acc[r];
+            o[r] = c + b0 * t.xin[r] + b1 * wv[r];
         }
-#pragma unroll
-        for (int r = 0; r < R; ++r) t[r] = t[r] + b0 * xin[r] + b1 * wv[r];
-        str<XT, R>(acc, row, t);
+        str<XT, R>(p.acc, row, o);
     }
-    if (out) {
-        if (vfin) {
-            ldr<XT, R>(vfin, row, t);
+    if (p.out) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) t[r] = t[r] - wv[r];
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) t[r] = wv[r];
-        }
-        str<XT, R>(out, row, t);
+        for (int r = 0; r < R; ++r) o[r] = fin ? t.fin[r] - wv[r] : wv[r];
+        str<XT, R>(p.out, row, o);
     }
+}
+
+// The wave's slice index. It is the same on every lane; readfirstlane says
+// so to the compiler, so the slice, its step descriptor and the buffer
+// pointers come through scalar loads.
+__device__ __forceinline__ int bslice_index() {
+    return remap_tile(blockIdx.x, gridDim.x, 1) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// The step descriptor and the active flag of system sys, all fields read
+// before the first is tested: the empty asm takes every field as an input,
+// so the compiler issues all their scalar loads together and waits once.
+template <typename VT, typename XT>
+__device__ __forceinline__ PStep bstep(const BChainArgs<VT, XT> &a, int sys, bool &skip) {
+    const int on = a.active[sys];
+    const PStep st = a.desc[(long)sys * a.K + a.k];
+    asm volatile("" ::"s"(on), "s"(st.spmv), "s"(st.in), "s"(st.aux), "s"(st.out), "s"(st.acc), "s"(st.acc_init),
+                 "s"(st.fin), "s"(st.a0), "s"(st.a1), "s"(st.a2), "s"(st.b0), "s"(st.b1));
+    skip = !on || st.spmv < 0;  // a converged system, or its program is shorter
+    return st;
 }
 
 template <typename VT, typename XT, int R>
 __global__ __launch_bounds__(256) void k_bchain(BChainArgs<VT, XT> a) {
     using AT = typename Arith<XT>::T;
     constexpr int U = 8;
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int w = bslice_index();
     if (w >= a.nslices) return;
     const int lane = threadIdx.x & 63;
     const int4 si = a.slice[w];
-    if (a.active && !a.active[si.z]) return;
-    const PStep st = a.desc[(long)si.z * a.K + a.k];
-    if (st.spmv < 0) return;  // this system's program is shorter
-    const bool active = lane < si.y;
+    bool skip;
+    const PStep st = bstep(a, si.z, skip);
+    if (skip) return;
     const long row = (long)si.x + lane;
-    const XT *in = a.bufs[st.in];
-    const XT *aux = st.aux >= 0 ? a.bufs[st.aux] : nullptr;
-    const XT *vfin = st.fin ? a.bufs[0] : nullptr;
-    XT *out = st.out >= 0 ? a.bufs[st.out] : nullptr;
-    XT *acc = st.acc >= 0 ? a.bufs[st.acc] : nullptr;
+    const long rc = (long)si.x + min(lane, si.y - 1);
+    const BRow<XT> p = brow_ptrs(a, st);
+    BRowIn<XT, R> t;
+    brow_load<XT, R>(p, rc, t);
     AT s[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) s[r] = AT(0);
@@ -146,18 +190,18 @@ __global__ __launch_bounds__(256) void k_bchain(BChainArgs<VT, XT> a) {
             }
             AT xv[U][R];
 #pragma unroll
-            for (int u = 0; u < U; ++u) ldr<XT, R>(in, c[u], xv[u]);
+            for (int u = 0; u < U; ++u) ldr<XT, R>(p.in, c[u], xv[u]);
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const AT t = (AT)v[u] * xv[u][r];
-                    s[r] += (k0 + u < width) ? t : AT(0);
+                    const AT q = (AT)v[u] * xv[u][r];
+                    s[r] += (k0 + u < width) ? q : AT(0);
                 }
         }
     }
-    if (!active) return;
-    bchain_finish<XT, R>(st, in, aux, vfin, out, acc, row, s);
+    if (lane >= si.y) return;
+    bchain_finish<XT, R>(st, p, t, row, s);
 }
 
 // The same step on the pattern-coded copy: one wave per 64-row slice; row
@@ -171,42 +215,43 @@ __global__ __launch_bounds__(256) void k_bchain_pat(BChainArgs<VT, XT> a, const 
                                                     const int32_t *__restrict__ ptoff,
                                                     const int32_t *__restrict__ sysoff, const VT *__restrict__ ptab) {
     using AT = typename Arith<XT>::T;
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int w = bslice_index();
     if (w >= a.nslices) return;
     const int lane = threadIdx.x & 63;
     const int4 si = a.slice[w];
-    if (a.active && !a.active[si.z]) return;
-    const PStep st = a.desc[(long)si.z * a.K + a.k];
-    if (st.spmv < 0) return;  // this system's program is shorter
-    const bool active = lane < si.y;
+    const int sys = si.z;
+    // what depends on the slice alone goes out first: the row's pattern
+    // byte and the system's offsets, beside the step descriptor
+    const int rc = si.x + min(lane, si.y - 1);
+    const int code = bpat[rc];
+    const int lo = sysoff[sys], hi = sysoff[sys + 1] - 1, toff = ptoff[sys];
+    int po[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) po[d] = poff[sys * ND + d];
+    bool skip;
+    const PStep st = bstep(a, sys, skip);
+    if (skip) return;
     const long row = (long)si.x + lane;
-    const XT *in = a.bufs[st.in];
-    const XT *aux = st.aux >= 0 ? a.bufs[st.aux] : nullptr;
-    const XT *vfin = st.fin ? a.bufs[0] : nullptr;
-    XT *out = st.out >= 0 ? a.bufs[st.out] : nullptr;
-    XT *acc = st.acc >= 0 ? a.bufs[st.acc] : nullptr;
+    const BRow<XT> p = brow_ptrs(a, st);
+    BRowIn<XT, R> t;
+    brow_load<XT, R>(p, rc, t);
     AT s[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) s[r] = AT(0);
     if (st.spmv) {
-        const int sys = si.z;
-        const int lo = sysoff[sys], hi = sysoff[sys + 1] - 1;
-        const int rc = si.x + min(lane, si.y - 1);
-        const VT *tb = ptab + ptoff[sys] + (int)bpat[rc] * ND;
-        VT v[ND];
         AT xv[ND][R];
 #pragma unroll
+        for (int d = 0; d < ND; ++d) ldr<XT, R>(p.in, min(max(rc + po[d], lo), hi), xv[d]);
+        const VT *tb = ptab + toff + code * ND;
+#pragma unroll
         for (int d = 0; d < ND; ++d) {
-            v[d] = tb[d];
-            ldr<XT, R>(in, min(max(rc + poff[sys * ND + d], lo), hi), xv[d]);
+            const AT v = (AT)tb[d];
+#pragma unroll
+            for (int r = 0; r < R; ++r) s[r] += v * xv[d][r];
         }
-#pragma unroll
-        for (int d = 0; d < ND; ++d)
-#pragma unroll
-            for (int r = 0; r < R; ++r) s[r] += (AT)v[d] * xv[d][r];
     }
-    if (!active) return;
-    bchain_finish<XT, R>(st, in, aux, vfin, out, acc, row, s);
+    if (lane >= si.y) return;
+    bchain_finish<XT, R>(st, p, t, row, s);
 }
 
 // One chunk of KC Krylov columns of k_bdots for R interleaved right-hand
@@ -534,6 +579,7 @@ hipError_t bchain_pat_t(const BatchSell &S, const BChainArgs<VT, XT> &a, const V
 template <typename VT, typename XT>
 hipError_t bchain_t(const BatchSell &S, const VT *sval, const VT *ptab, int R, const PStep *desc, int K, int k,
                     void *const bufs[5], hipStream_t st) {
+    if (!S.active) return hipErrorInvalidValue;  // the kernels read the flags unconditionally
     BChainArgs<VT, XT> a;
     a.slice = S.slice;
     a.sptr = S.sptr;
