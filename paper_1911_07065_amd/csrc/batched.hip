@@ -255,12 +255,14 @@ __global__ __launch_bounds__(256) void k_bchain_pat(BChainArgs<VT, XT> a, const 
 }
 
 // One chunk of KC Krylov columns of k_bdots for R interleaved right-hand
-// sides: all loads of the chunk are issued before the first is used.
+// sides: all loads of the chunk are issued before the first is used; each
+// wave leaves its sums in sm[wave][(c - g0) R + r], g0 the column group's
+// first column (no barrier here).
 template <typename XT, int R, int KC>
-__device__ __forceinline__ void bdots_chunk(const XT *__restrict__ V, long ldv, int c0, const long *ii,
-                                            const double (*wv)[R], double (*sm)[8], double *prow) {
+__device__ __forceinline__ void bdots_chunk(const XT *__restrict__ V, long ldv, int c0, int g0, const long *ii,
+                                            const double (*wv)[R], double (*sm)[64]) {
     constexpr int RPT = kBatchBlockRows / 256;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     typename Arith<XT>::T x[RPT][KC][R];
 #pragma unroll
     for (int s = 0; s < RPT; ++s)
@@ -274,23 +276,23 @@ __device__ __forceinline__ void bdots_chunk(const XT *__restrict__ V, long ldv, 
 #pragma unroll
             for (int s = 0; s < RPT; ++s) acc += (double)x[s][kc][r] * wv[s][r];
             acc = wave_sum(acc);
-            if (lane == 0) sm[wave][kc * R + r] = acc;
+            if (lane == 0) sm[wave][(c0 - g0 + kc) * R + r] = acc;
         }
-    __syncthreads();
-    if (tid < KC * R) prow[(long)c0 * R + tid] = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
-    __syncthreads();
 }
 
 // Gram-Schmidt projections of one system-aligned block (<= kBatchBlockRows
 // rows, 4 per thread): partial[b*ldp + c*R + r] = sum over the block of
 // V_c[i*R+r] w[i*R+r]. Columns go 8/R at a time, then smaller chunks for the
-// remainder; rows past the block read its last row with weight zero.
+// remainder; rows past the block read its last row with weight zero. The
+// waves meet once per group of 64/R columns, when the group's sums are
+// combined (wave 0 + 1 + 2 + 3, in that order) and written.
 template <typename XT, int R>
 __global__ __launch_bounds__(256) void k_bdots(const int4 *block, const int *active, const XT *V, long ldv, int ncols,
                                                const XT *w, double *partial, int ldp) {
     constexpr int RPT = kBatchBlockRows / 256;
     constexpr int KC = 8 / R;
-    __shared__ double sm[4][8];
+    constexpr int GW = 64 / R;  // a multiple of KC
+    __shared__ double sm[4][64];
     const int4 bi = block[blockIdx.x];
     if (active && !active[bi.z]) return;
     const long r1 = (long)bi.x + bi.y;
@@ -306,17 +308,24 @@ __global__ __launch_bounds__(256) void k_bdots(const int4 *block, const int *act
         for (int r = 0; r < R; ++r) wv[s][r] = i < r1 ? (double)t[r] : 0.0;
     }
     double *prow = partial + (long)blockIdx.x * ldp;
-    int c0 = 0;
-    for (; c0 + KC <= ncols; c0 += KC) bdots_chunk<XT, R, KC>(V, ldv, c0, ii, wv, sm, prow);
-    if (KC >= 8 && ncols - c0 >= 4) {
-        bdots_chunk<XT, R, (KC >= 8 ? 4 : 1)>(V, ldv, c0, ii, wv, sm, prow);
-        c0 += 4;
+    const int tid = threadIdx.x;
+    for (int g0 = 0; g0 < ncols; g0 += GW) {
+        const int g1 = min(ncols, g0 + GW);
+        int c0 = g0;
+        for (; c0 + KC <= g1; c0 += KC) bdots_chunk<XT, R, KC>(V, ldv, c0, g0, ii, wv, sm);
+        if (KC >= 8 && g1 - c0 >= 4) {
+            bdots_chunk<XT, R, (KC >= 8 ? 4 : 1)>(V, ldv, c0, g0, ii, wv, sm);
+            c0 += 4;
+        }
+        if (KC >= 4 && g1 - c0 >= 2) {
+            bdots_chunk<XT, R, (KC >= 4 ? 2 : 1)>(V, ldv, c0, g0, ii, wv, sm);
+            c0 += 2;
+        }
+        if (KC >= 2 && g1 - c0 >= 1) bdots_chunk<XT, R, 1>(V, ldv, c0, g0, ii, wv, sm);
+        __syncthreads();
+        if (tid < (g1 - g0) * R) prow[(long)g0 * R + tid] = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
+        __syncthreads();
     }
-    if (KC >= 4 && ncols - c0 >= 2) {
-        bdots_chunk<XT, R, (KC >= 4 ? 2 : 1)>(V, ldv, c0, ii, wv, sm, prow);
-        c0 += 2;
-    }
-    if (KC >= 2 && ncols - c0 >= 1) bdots_chunk<XT, R, 1>(V, ldv, c0, ii, wv, sm, prow);
 }
 
 // sum over c < ncols of V_c[i*R+r] h[c*R+r] for one row and every r, with
