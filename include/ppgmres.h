@@ -150,6 +150,26 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap);
  * microseconds (0 if the variant was forced). */
 pp_status pp_matrix_variant(pp_matrix A, int prec, int *variant, int *remap, double *us_per_launch);
 
+/* Two chain steps per launch (Algorithms 1 and 3: two consecutive real
+ * roots, each factor one sparse product). On a matrix whose rows are the
+ * points of a gx x gy x gz box with entries only on the diagonals 0, +-1,
+ * +-gx (and +-gx gy), none joining the end of a grid line to the start of
+ * the next (5- and 7-point stencils; detected at pp_matrix_create), one
+ * launch applies both factors: a workgroup stages its tile of the input and
+ * two grid points around it, forms the first factor's result on the tile
+ * and one point around it, and the second factor on the tile. The results
+ * equal two single launches up to the order of rounding. pp_matrix_tune
+ * turns it on for a precision when one launch beats two single steps;
+ * pp_matrix_set_variant turns it off.
+ *   pp_matrix_set_pair_steps: mode 1 on, 0 off, for a tuned (or set)
+ *     precision; PP_EINVAL for mode 1 on a matrix without the box geometry or
+ *     its pattern-coded copy, or for bfloat16 vectors.
+ *   pp_matrix_pair_steps: *mode (host) 1 if in use; box (host int[3], may be
+ *     NULL) the geometry, zeros if none; us_pair (host, may be NULL) the tuned
+ *     time of one two-step launch in microseconds (0 if not timed). */
+pp_status pp_matrix_set_pair_steps(pp_matrix A, int prec, int mode);
+pp_status pp_matrix_pair_steps(pp_matrix A, int prec, int *mode, int *box, double *us_pair);
+
 /* Composition with a diagonal right preconditioner M^{-1} = diag(s)
  * (eqs. (1.3)-(1.4), section 1): from now on the handle's operator is
  * A diag(s). Its chains, pp_gmres_setup (the polynomial is built for

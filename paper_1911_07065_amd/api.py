@@ -144,6 +144,19 @@ class Matrix:
         name = None if v.value < 0 else lib.pp_chain_variant_name(v.value).decode()
         return name, r.value, us.value
 
+    def set_pair_steps(self, on: bool, prec: str = "fp32"):
+        """Run two real-root chain steps per launch (box stencils only), or not."""
+        check(lib.pp_matrix_set_pair_steps(self.handle, PREC[prec], 1 if on else 0), "pp_matrix_set_pair_steps")
+
+    def pair_steps(self, prec: str = "fp32"):
+        """(in use, box dims or None, tuned us per two-step launch)."""
+        mode, us = ctypes.c_int(), ctypes.c_double()
+        box = (ctypes.c_int * 3)()
+        check(lib.pp_matrix_pair_steps(self.handle, PREC[prec], ctypes.byref(mode), box, ctypes.byref(us)),
+              "pp_matrix_pair_steps")
+        dims = tuple(box) if box[0] else None
+        return bool(mode.value), dims, us.value
+
     def set_variant(self, prec: str, variant: int, remap: int = 1):
         """Force chain variant `variant` (0..30; 15 = persistent cooperative kernel) for a precision."""
         check(lib.pp_matrix_set_variant(self.handle, PREC[prec], int(variant), int(remap)), "pp_matrix_set_variant")

@@ -75,6 +75,13 @@ struct pp_matrix_s {
     // pp_solve returns x = M^{-1} x~ (blocks of rbs rows, stride rbs)
     int rbs = 0;
     double *rminv = nullptr;
+    // box geometry of a 5- or 7-point stencil matrix (box_nd == 0: none) and,
+    // per precision, whether chains run two real-root steps per launch and
+    // the tuned time of one such launch
+    int box[3] = {0, 0, 0};
+    int box_nd = 0;
+    int fuse[3] = {0, 0, 0};
+    double pair_us[3] = {0, 0, 0};
     // column-banded CSR copies (matrices whose entries lie far from the
     // diagonal): c = 0 two bands, c = 1 four; bperm maps entries to CSR
     int32_t *brow[2] = {nullptr, nullptr}, *bcol[2] = {nullptr, nullptr}, *bperm[2] = {nullptr, nullptr};
@@ -173,6 +180,8 @@ struct pp_matrix_s {
         d.ptab64 = ptab64;
         d.ptab32 = ptab32;
         d.npat = npat;
+        for (int k = 0; k < 3; ++k) d.box[k] = box[k];
+        d.box_nd = box_nd;
         for (int p = 0; p < 3; ++p) {
             d.tileB8[p] = tileB8[p];
             d.ntileB8[p] = ntileB8[p];
@@ -463,6 +472,31 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
     A->remap[prec] = br;
     A->persist[prec] = 0;
     double best_all = best;
+    // two real-root steps per launch on a box stencil: kept when one such
+    // launch beats two single steps
+    A->fuse[prec] = 0;
+    A->pair_us[prec] = 0.0;
+    if (A->box_nd && A->pbyte && prec != PP_BF16S) {
+        PairPtrs pp;
+        std::memset(&pp, 0, sizeof(pp));
+        pp.in = w.P0;
+        pp.out = w.P1;
+        pp.a01 = pp.a02 = 1.0;
+        const DevCSR d = A->dev();
+        double bp = 1e30;
+        for (int round = 0; round < 2; ++round) {
+            for (int i = 0; i < 2; ++i) HIP_TRY(launch_chain_pair(d, prec, pp, br, st));
+            HIP_TRY(hipEventRecord(e0, st));
+            for (int i = 0; i < reps; ++i) HIP_TRY(launch_chain_pair(d, prec, pp, br, st));
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            bp = std::min(bp, 1e3 * ms / reps);
+        }
+        A->pair_us[prec] = bp;
+        A->fuse[prec] = bp < 2.0 * best ? 1 : 0;
+    }
     // The persistent kernel is only timed on request: its grid barrier must
     // write back and invalidate the per-XCD L2 caches, which costs far more
     // than a kernel boundary on this GPU.
@@ -504,6 +538,26 @@ const std::vector<Step> &prog_of(pp_poly p, int kind) {
 // one launch per step, as tuned for this matrix and precision.
 pp_status run_composite(pp_matrix A, pp_poly poly, int kind, int prec, const void *in, void *out, hipStream_t st);
 
+// Steps i and i+1 of a chain program can run as one fused pair: both one
+// sparse product without an aux vector, the second reading the first's
+// result, which no later step reads before it is written again; at most
+// one accumulator, updated by the second step only when the first's
+// initialisation came before it.
+bool pair_fusable(const std::vector<Step> &prog, size_t i) {
+    const Step &s = prog[i], &t = prog[i + 1];
+    if (s.spmv != 1 || t.spmv != 1 || s.aux != B_NONE || t.aux != B_NONE || s.fin) return false;
+    if (s.out < B_P0 || t.in != s.out || t.out == s.out || t.out == B_IN) return false;
+    if (s.acc != B_NONE && t.acc != B_NONE && (s.acc != t.acc || t.acc_init)) return false;
+    const int acc = s.acc != B_NONE ? s.acc : t.acc;
+    if (acc != B_NONE && (acc == s.in || acc == s.out || acc == t.out)) return false;
+    for (size_t j = i + 2; j < prog.size(); ++j) {
+        const Step &u = prog[j];
+        if (u.in == s.out || u.aux == s.out || (u.acc == s.out && !u.acc_init)) return false;
+        if (u.out == s.out || u.acc == s.out) break;
+    }
+    return true;
+}
+
 pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void *in, void *out, hipStream_t st) {
     if (poly->inner) return run_composite(A, poly, kind, prec, in, out, st);
     PP_TRY(ensure_tuned(A, prec, st));
@@ -524,13 +578,52 @@ pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void 
     }
     const Workspace &w = A->ws[prec];
     const DevCSR d = A->dev();
-    for (const Step &s : prog) {
+    // The temporaries' buffers; a fused pair may swap two of them (below).
+    void *tmp[5] = {nullptr, nullptr, w.P0, w.P1, w.T};
+    auto ptr = [&](int b) -> void * {
+        if (b == B_IN) return (void *)in;
+        if (b == B_OUT) return out;
+        return b >= B_P0 && b <= B_T ? tmp[b] : nullptr;
+    };
+    const bool fuse = A->fuse[prec] && A->box_nd && A->pbyte && prec != PP_BF16S;
+    for (size_t i = 0; i < prog.size(); ++i) {
+        const Step &s = prog[i];
+        if (fuse && i + 1 < prog.size() && pair_fusable(prog, i)) {
+            // Two real-root steps in one launch. The first step's result is
+            // not stored; if the second's output buffer is the first's
+            // input (other workgroups still read it), the pair writes the
+            // first's output buffer instead and the two names swap.
+            const Step &t = prog[i + 1];
+            const bool swap = t.out != B_NONE && ptr(t.out) == ptr(s.in) && s.out >= B_P0 && t.out >= B_P0;
+            PairPtrs pp;
+            pp.in = ptr(s.in);
+            pp.out = swap ? ptr(s.out) : ptr(t.out);
+            pp.acc = ptr(s.acc != B_NONE ? s.acc : t.acc);
+            pp.vfin = t.fin ? in : nullptr;
+            pp.acc1 = s.acc != B_NONE;
+            pp.acc2 = t.acc != B_NONE;
+            pp.init = s.acc != B_NONE ? s.acc_init : t.acc_init;
+            pp.a01 = s.a0;
+            pp.a11 = s.a1;
+            pp.b01 = s.b0;
+            pp.b11 = s.b1;
+            pp.a02 = t.a0;
+            pp.a12 = t.a1;
+            pp.b02 = t.b0;
+            pp.b12 = t.b1;
+            if (pp.out != pp.in && pp.acc != pp.in) {
+                if (swap) std::swap(tmp[s.out], tmp[t.out]);
+                HIP_TRY(launch_chain_pair(d, prec, pp, A->remap[prec], st));
+                ++i;
+                continue;
+            }
+        }
         StepPtrs p;
-        p.in = buf_ptr(s.in, in, out, w);
-        p.aux = buf_ptr(s.aux, in, out, w);
+        p.in = ptr(s.in);
+        p.aux = ptr(s.aux);
         p.vfin = s.fin ? in : nullptr;
-        p.out = buf_ptr(s.out, in, out, w);
-        p.acc = buf_ptr(s.acc, in, out, w);
+        p.out = ptr(s.out);
+        p.acc = ptr(s.acc);
         p.acc_init = s.acc_init;
         p.spmv = s.spmv;
         p.a0 = s.a0;
@@ -880,6 +973,42 @@ pp_status build_value_codes(pp_matrix A, const int32_t *dp, const std::vector<do
     return PP_OK;
 }
 
+// The box geometry of a stencil matrix: diagonals exactly 0, +-1, +-gx
+// (and +-gx gy), n = gx gy gz, and no stored entry joining the last point
+// of a grid line (or plane) to the first of the next. Leaves box_nd = 0
+// when the matrix is not such a stencil.
+void detect_box(pp_matrix A, const std::vector<int32_t> &ci) {
+    const auto &o = A->h_doff;
+    const int nd = (int)o.size();
+    const long n = A->n;
+    long gx = 0, gy = 0, gz = 0;
+    if (nd == 7 && o[0] == -o[6] && o[1] == -o[5] && o[2] == -1 && o[3] == 0 && o[4] == 1 && o[5] >= 2 &&
+        o[6] % o[5] == 0 && n % o[6] == 0) {
+        gx = o[5];
+        gy = o[6] / o[5];
+        gz = n / o[6];
+    } else if (nd == 5 && o[0] == -o[4] && o[1] == -1 && o[2] == 0 && o[3] == 1 && o[4] >= 2 && n % o[4] == 0) {
+        gx = o[4];
+        gy = n / o[4];
+        gz = 1;
+    }
+    if (gx < 2 || gy < 2 || gz < 1) return;
+    const auto &rp = A->h_rowptr;
+    for (long r = 0; r < n; ++r) {
+        const long x = r % gx, y = (r / gx) % gy;
+        for (int k = rp[r]; k < rp[r + 1]; ++k) {
+            const long off = (long)ci[k] - r;
+            if ((off == 1 && x == gx - 1) || (off == -1 && x == 0) || (nd == 7 && off == gx && y == gy - 1) ||
+                (nd == 7 && off == -gx && y == 0))
+                return;
+        }
+    }
+    A->box[0] = (int)gx;
+    A->box[1] = (int)gy;
+    A->box[2] = (int)gz;
+    A->box_nd = nd;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1109,6 +1238,7 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
                                  hipSuccess &&
                     hipStreamSynchronize(st) == hipSuccess)
                     if ((s = build_value_codes(A, dp.data(), hv, st)) != PP_OK) return fail(s);
+                if (A->pbyte) detect_box(A, ci);
             }
         }
     }
@@ -1501,6 +1631,37 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
     }
     A->tuned[prec] = 1;
     A->tuned_us[prec] = 0.0;
+    A->fuse[prec] = 0;  // the forced variant runs every step
+    return PP_OK;
+}
+
+pp_status pp_matrix_set_pair_steps(pp_matrix A, int prec, int mode) {
+    if (!A || !valid_prec(prec) || (mode != 0 && mode != 1)) {
+        set_error("pp_matrix_set_pair_steps: bad argument");
+        return PP_EINVAL;
+    }
+    if (mode == 1 && (!A->box_nd || !A->pbyte || prec == PP_BF16S)) {
+        set_error("pp_matrix_set_pair_steps: two steps per launch need a 5- or 7-point box stencil with a "
+                  "pattern-coded copy, and FP64 or FP32 vectors");
+        return PP_EINVAL;
+    }
+    if (!A->tuned[prec]) {
+        set_error("pp_matrix_set_pair_steps: tune or set the precision's variant first");
+        return PP_EINVAL;
+    }
+    A->fuse[prec] = mode;
+    return PP_OK;
+}
+
+pp_status pp_matrix_pair_steps(pp_matrix A, int prec, int *mode, int *box, double *us_pair) {
+    if (!A || !valid_prec(prec) || !mode) {
+        set_error("pp_matrix_pair_steps: bad argument");
+        return PP_EINVAL;
+    }
+    *mode = A->fuse[prec] && A->box_nd && A->pbyte ? 1 : 0;
+    if (box)
+        for (int k = 0; k < 3; ++k) box[k] = A->box_nd ? A->box[k] : 0;
+    if (us_pair) *us_pair = A->pair_us[prec];
     return PP_OK;
 }
 

@@ -147,6 +147,13 @@ struct DevCSR {
     const double *ptab64;
     const float *ptab32;
     int npat;
+    // box geometry (box_nd == 0: none): the rows are the points of a
+    // box[0] x box[1] x box[2] grid, row x + box[0] (y + box[1] z), with
+    // entries only on the diagonals 0, +-1, +-box[0] (and +-box[0] box[1]
+    // when box_nd == 7) and none joining the end of a grid line to the start
+    // of the next; the diagonal format's d order is that ascending order
+    int box[3];
+    int box_nd;
     int variant[3];      // chain variant per precision
     int remap[3];        // 1: keep neighbouring workgroups on one XCD
 };
@@ -174,6 +181,26 @@ void build_tiles(const int32_t *rowptr, int n, int row_cap, int nnz_cap, std::ve
 size_t elem_size(int prec);
 
 hipError_t launch_chain_step(const DevCSR &A, int prec, const StepPtrs &s, hipStream_t st);
+
+// Two consecutive chain steps, each with one sparse product and no aux
+// vector, the second reading the first's result (two real roots of
+// Algorithm 1 or 3): for each row r
+//     w1 = a01 (A in)_r + a11 in_r,   w2 = a02 (A w1)_r + a12 w1_r
+//     acc_r = (init ? 0 : acc_r) [+ b01 in_r + b11 w1_r if acc1] [+ b02 w1_r + b12 w2_r if acc2]
+//     out_r = vfin ? vfin_r - w2 : w2                       (if out)
+// w1 is not stored. Needs the box geometry and the pattern-coded copy;
+// out and acc must not alias in (other workgroups read in around their
+// tiles). FP64 and FP32 vectors only.
+struct PairPtrs {
+    const void *in;
+    void *out;
+    void *acc;
+    const void *vfin;
+    int acc1, acc2, init;
+    double a01, a11, b01, b11;
+    double a02, a12, b02, b12;
+};
+hipError_t launch_chain_pair(const DevCSR &A, int prec, const PairPtrs &p, int remap, hipStream_t st);
 
 // partial[b * ldp + k] = sum over rows of block b of V[i, k] * w[i], k < ncols.
 int dot_blocks(int n);

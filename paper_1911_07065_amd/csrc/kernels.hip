@@ -896,6 +896,175 @@ const float *sell_vals<float>(const DevCSR &A) {
     return A.sval32;
 }
 
+// Two chain steps in one launch on a box-stencil matrix (see PairPtrs for
+// the arithmetic). A workgroup owns a TX x TY x TZ tile of grid points: it
+// stages the first step's input on the tile and two points around it in
+// LDS (zero outside the box, where the matrix has no entries), computes w1
+// on the tile and one point around it into LDS, then the second step on the
+// tile from w1. Every row's entries come from the pattern-coded copy: one
+// byte per row naming its pattern, whose ND entries (diagonals in ascending
+// offset order) sit in a table staged in LDS.
+template <typename XT>
+struct PairArgs {
+    const XT *in;
+    XT *out;
+    XT *acc;
+    const XT *vfin;
+    typename Arith<XT>::T a01, a11, b01, b11, a02, a12, b02, b12;
+    int acc1, acc2, init;
+    int gx, gy, gz;
+    int ntx, nty, ntiles;
+};
+
+// Offset of diagonal d (ascending order) in a staged region of row length
+// LX and plane size LX * LY.
+template <int ND, int LX, int LY>
+__device__ constexpr int box_off(int d) {
+    if constexpr (ND == 7) {
+        return d == 0 ? -LX * LY : d == 1 ? -LX : d == 2 ? -1 : d == 3 ? 0 : d == 4 ? 1 : d == 5 ? LX : LX * LY;
+    } else {
+        return d == 0 ? -LX : d == 1 ? -1 : d == 2 ? 0 : d == 3 ? 1 : LX;
+    }
+}
+
+template <typename VT, typename XT, int ND, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_chain_pair(PairArgs<XT> a, const uint8_t *__restrict__ pbyte,
+                                                    const VT *__restrict__ ptab, int nent, int remap) {
+    using AT = typename Arith<XT>::T;
+    static_assert(ND == 5 || ND == 7, "5- or 7-point box stencils");
+    constexpr int HZ = ND == 7 ? 1 : 0;  // a 2-D box has one plane
+    static_assert(HZ == 1 || TZ == 1, "one plane per 2-D tile");
+    constexpr int SX = TX + 4, SY = TY + 4, SZ = TZ + 4 * HZ;  // staged input
+    constexpr int WX = TX + 2, WY = TY + 2, WZ = TZ + 2 * HZ;  // w1
+    constexpr int NS = SX * SY * SZ, NW = WX * WY * WZ, NT = TX * TY * TZ;
+    static_assert(NT % 256 == 0, "tiles of whole 256-point rounds");
+    constexpr int CS = (NS + 255) / 256, CW = (NW + 255) / 256, CT = NT / 256;
+    __shared__ AT xs[NS];
+    __shared__ AT ws[NW];
+    __shared__ AT tab[kMaxPatEntries];
+    const int tid = threadIdx.x;
+    const int t = remap_tile(blockIdx.x, a.ntiles, remap);
+    const int x0 = (t % a.ntx) * TX, y0 = ((t / a.ntx) % a.nty) * TY, z0 = (t / (a.ntx * a.nty)) * TZ;
+    const int gx = a.gx, gy = a.gy, gz = a.gz, pxy = gx * gy;
+    // every global load goes out before the first barrier: the staged
+    // input, the patterns of the w1 points, and the tile's patterns and row
+    // data
+    AT v[CS];
+#pragma unroll
+    for (int k = 0; k < CS; ++k) {
+        const int c = tid + k * 256;
+        const int lx = c % SX, ly = (c / SX) % SY, lz = c / (SX * SY);
+        const int px = x0 - 2 + lx, py = y0 - 2 + ly, pz = z0 - 2 * HZ + lz;
+        const bool ok = c < NS && px >= 0 && px < gx && py >= 0 && py < gy && pz >= 0 && pz < gz;
+        v[k] = ok ? (AT)ldx(a.in, px + gx * py + pxy * pz) : AT(0);
+    }
+    int cw[CW];
+#pragma unroll
+    for (int k = 0; k < CW; ++k) {
+        const int c = tid + k * 256;
+        const int lx = c % WX, ly = (c / WX) % WY, lz = c / (WX * WY);
+        const int px = x0 - 1 + lx, py = y0 - 1 + ly, pz = z0 - HZ + lz;
+        const bool ok = c < NW && px >= 0 && px < gx && py >= 0 && py < gy && pz >= 0 && pz < gz;
+        cw[k] = ok ? (int)pbyte[px + gx * py + pxy * pz] : -1;
+    }
+    int ct[CT], rt[CT];
+    AT pa[CT], pf[CT];
+    const bool load_acc = a.acc && !a.init;
+#pragma unroll
+    for (int k = 0; k < CT; ++k) {
+        const int c = tid + k * 256;
+        const int px = x0 + c % TX, py = y0 + (c / TX) % TY, pz = z0 + c / (TX * TY);
+        const bool ok = px < gx && py < gy && pz < gz;
+        const int r = px + gx * py + pxy * pz;
+        rt[k] = ok ? r : -1;
+        ct[k] = ok ? (int)pbyte[r] : 0;
+        pa[k] = ok && load_acc ? (AT)ldx(a.acc, r) : AT(0);
+        pf[k] = ok && a.vfin ? (AT)ldx(a.vfin, r) : AT(0);
+    }
+    for (int i = tid; i < nent; i += 256) tab[i] = (AT)ptab[i];
+#pragma unroll
+    for (int k = 0; k < CS; ++k) {
+        const int c = tid + k * 256;
+        if (c < NS) xs[c] = v[k];
+    }
+    __syncthreads();
+    // the first step on the tile and one point around it (zero outside the box)
+#pragma unroll
+    for (int k = 0; k < CW; ++k) {
+        const int c = tid + k * 256;
+        if (c < NW) {
+            AT w = AT(0);
+            if (cw[k] >= 0) {
+                const int lx = c % WX, ly = (c / WX) % WY, lz = c / (WX * WY);
+                const int q = (lx + 1) + SX * ((ly + 1) + SY * (lz + HZ));
+                const AT *tp = tab + cw[k] * ND;
+                AT sum = AT(0);
+#pragma unroll
+                for (int d = 0; d < ND; ++d) sum += tp[d] * xs[q + box_off<ND, SX, SY>(d)];
+                w = a.a01 * sum + a.a11 * xs[q];
+            }
+            ws[c] = w;
+        }
+    }
+    __syncthreads();
+    // the second step on the tile
+#pragma unroll
+    for (int k = 0; k < CT; ++k) {
+        if (rt[k] < 0) continue;
+        const int c = tid + k * 256;
+        const int lx = c % TX, ly = (c / TX) % TY, lz = c / (TX * TY);
+        const int q = (lx + 1) + WX * ((ly + 1) + WY * (lz + HZ));
+        const int qs = (lx + 2) + SX * ((ly + 2) + SY * (lz + 2 * HZ));
+        const AT *tp = tab + ct[k] * ND;
+        AT sum = AT(0);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) sum += tp[d] * ws[q + box_off<ND, WX, WY>(d)];
+        const AT w1 = ws[q], xin = xs[qs];
+        const AT w2 = a.a02 * sum + a.a12 * w1;
+        if (a.acc) {
+            AT cacc = pa[k];
+            if (a.acc1) cacc = cacc + a.b01 * xin + a.b11 * w1;
+            if (a.acc2) cacc = cacc + a.b02 * w1 + a.b12 * w2;
+            stx(a.acc, rt[k], cacc);
+        }
+        if (a.out) stx(a.out, rt[k], a.vfin ? pf[k] - w2 : w2);
+    }
+}
+
+template <typename VT, typename XT, int ND, int TX, int TY, int TZ>
+hipError_t pair_launch(const DevCSR &A, const VT *ptab, const PairPtrs &p, int remap, hipStream_t st) {
+    using AT = typename Arith<XT>::T;
+    PairArgs<XT> a;
+    a.in = (const XT *)p.in;
+    a.out = (XT *)p.out;
+    a.acc = (XT *)p.acc;
+    a.vfin = (const XT *)p.vfin;
+    a.a01 = (AT)p.a01;
+    a.a11 = (AT)p.a11;
+    a.b01 = (AT)p.b01;
+    a.b11 = (AT)p.b11;
+    a.a02 = (AT)p.a02;
+    a.a12 = (AT)p.a12;
+    a.b02 = (AT)p.b02;
+    a.b12 = (AT)p.b12;
+    a.acc1 = p.acc1;
+    a.acc2 = p.acc2;
+    a.init = p.init;
+    a.gx = A.box[0];
+    a.gy = A.box[1];
+    a.gz = A.box[2];
+    a.ntx = (a.gx + TX - 1) / TX;
+    a.nty = (a.gy + TY - 1) / TY;
+    const long ntz = (a.gz + TZ - 1) / TZ;
+    const long nt = (long)a.ntx * a.nty * ntz;
+    if (nt == 0) return hipSuccess;
+    if (nt >= (1L << 31)) return hipErrorInvalidValue;
+    a.ntiles = (int)nt;
+    hipLaunchKernelGGL((k_chain_pair<VT, XT, ND, TX, TY, TZ>), dim3((unsigned)nt), dim3(256), 0, st, a, A.pbyte, ptab,
+                       A.npat * ND, remap);
+    return hipGetLastError();
+}
+
 template <typename VT, typename XT>
 ChainArgs<VT, XT> chain_args(const DevCSR &A, const VT *val, const StepPtrs &s) {
     using AT = typename Arith<XT>::T;
@@ -1836,6 +2005,21 @@ hipError_t launch_chain_step(const DevCSR &A, int prec, const StepPtrs &s, hipSt
             return chain_launch<float, float>(A, A.val32, s, v, r, st);
         case 2:
             return chain_launch<float, uint16_t>(A, A.val32, s, v, r, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_chain_pair(const DevCSR &A, int prec, const PairPtrs &p, int remap, hipStream_t st) {
+    if (!A.pbyte || !p.in || (A.box_nd != 5 && A.box_nd != 7) || A.npat * A.box_nd > kMaxPatEntries ||
+        (long)A.box[0] * A.box[1] * A.box[2] != A.n || (p.out && p.out == p.in) || (p.acc && p.acc == p.in))
+        return hipErrorInvalidValue;
+    switch (prec) {
+        case 0:
+            return A.box_nd == 7 ? pair_launch<double, double, 7, 32, 8, 4>(A, A.ptab64, p, remap, st)
+                                 : pair_launch<double, double, 5, 64, 32, 1>(A, A.ptab64, p, remap, st);
+        case 1:
+            return A.box_nd == 7 ? pair_launch<float, float, 7, 32, 8, 8>(A, A.ptab32, p, remap, st)
+                                 : pair_launch<float, float, 5, 64, 32, 1>(A, A.ptab32, p, remap, st);
     }
     return hipErrorInvalidValue;
 }

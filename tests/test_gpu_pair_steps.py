@@ -1,0 +1,162 @@
+"""GPU parity of two chain steps per launch (box stencils) against the oracle.
+
+Two consecutive real roots of Algorithm 1 or 3 run as one launch on a
+5- or 7-point stencil matrix. The results must equal the oracle's chains
+(and the single-step launches up to rounding order) for boxes whose sides
+are not multiples of the tile, for polynomials that mix real roots,
+conjugate pairs and added copies, and inside a full solve.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from oracle import chains, roots as oroots
+from oracle.mixed import apply_p_low, apply_phi_low
+from workloads import CSR, convdiff2d, convdiff3d, convdiff3d_box, randsparse, rhs, start_vector
+from gpu_util import say, dev, host, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pp():
+    import paper_1911_07065_amd.api as api
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return api
+
+
+def _wrapped(nx, ny, nz):
+    # 7 full diagonals 0, +-1, +-nx, +-nx ny: entries join the end of every
+    # grid line to the start of the next, so the matrix is not a box stencil
+    n = nx * ny * nz
+    offs = [-nx * ny, -nx, -1, 0, 1, nx, nx * ny]
+    vals = [-0.5, -0.7, -1.1, 6.0, -0.9, -1.3, -0.6]
+    A = sp.diags([np.full(n - abs(o), v) for o, v in zip(offs, vals)], offs, format="csr")
+    A.sort_indices()
+    return CSR(n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
+
+
+def _cases():
+    # box sides that leave partial tiles in every direction (3-D tiles 32 x 8 x 8
+    # and 32 x 8 x 4, 2-D tiles 64 x 32)
+    return {
+        "box3d_37x11x10": (convdiff3d_box(37, 11, 10, 10.0, 5.0, 2.0), (37, 11, 10), 12),
+        "convdiff3d_20": (convdiff3d(20, 10, 10, 10), (20, 20, 20), 12),
+        "convdiff2d_70": (convdiff2d(70, 5.0), (70, 70, 1), 12),
+        "box3d_9x7x33": (convdiff3d_box(9, 7, 33, 1.0, 1.0, 1.0), (9, 7, 33), 6),
+    }
+
+
+def test_box_geometry_detected(pp):
+    for name, (csr, box, _) in _cases().items():
+        M = pp.Matrix.from_csr(csr)
+        say("box", name)
+        assert M.pair_steps("fp64")[1] == box, name
+    for csr in (_wrapped(40, 30, 20), randsparse(5000, 8, seed=3)):
+        M = pp.Matrix.from_csr(csr)
+        assert M.pair_steps("fp64")[1] is None
+        M.set_variant("fp64", 0, 1)
+        with pytest.raises(Exception, match="box stencil"):
+            M.set_pair_steps(True, "fp64")
+    M = pp.Matrix.from_csr(convdiff3d(12, 1, 1, 1))
+    with pytest.raises(Exception, match="tune"):
+        M.set_pair_steps(True, "fp32")
+    M.tune("bf16")
+    with pytest.raises(Exception):
+        M.set_pair_steps(True, "bf16")
+    # forcing a variant runs every step on its own again
+    M.tune("fp64")
+    M.set_pair_steps(True, "fp64")
+    assert M.pair_steps("fp64")[0]
+    M.set_variant("fp64", 0, 1)
+    assert not M.pair_steps("fp64")[0]
+
+
+def _polys(pp, A, n, d):
+    P = oroots.setup(A, start_vector(n, 2), d)
+    th = np.array([7.5, 0.2, 3 + 1j, 3 - 1j, 5 + 0.5j, 5 - 0.5j, 1.0, 0.05, 2.5])
+    Q = oroots.poly_from_roots(th, add_roots=True)
+    return [("setup", P, pp.poly_from_roots(P.roots(), keep_order=True)),
+            ("mixed", Q, pp.poly_from_roots(th, add_roots=True))]
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_pair_steps_match_oracle(pp, name):
+    csr, box, d = _cases()[name]
+    A = csr.to_scipy()
+    A32 = A.astype(np.float32)
+    v = rhs(csr.n, 5)
+    for pname, P, poly in _polys(pp, A, csr.n, d):
+        M = pp.Matrix.from_csr(csr)
+        for prec in ("fp64", "fp32"):
+            M.tune(prec)
+        v32 = v.astype(np.float32)
+        ref_phi = chains.apply_phi(A, P.units, v)
+        for kind, fn in [("p", chains.apply_p), ("phi", chains.apply_phi), ("pi", chains.apply_pi)]:
+            ref = fn(A, P.units, v)
+            # the FP32 bound of the other chain tests: 10x the error of the
+            # chain emulated in float32 (pi through pi = v - phi)
+            flow = apply_p_low if kind == "p" else apply_phi_low
+            delta = relerr(flow(A32, P.units, v32, "fp32"), ref if kind == "p" else ref_phi)
+            say("pair steps", name, pname, kind)
+            got = {}
+            for on in (True, False):
+                M.set_pair_steps(on, "fp64")
+                M.set_pair_steps(on, "fp32")
+                g64 = host(pp.apply(poly, M, dev(v), kind))
+                g32 = host(pp.apply(poly, M, dev(v32, torch.float32), kind))
+                got[on] = g64
+                assert relerr(g64, ref) <= 1e-12, (on, relerr(g64, ref))
+                err32 = relerr(v32 - g32, ref_phi) if kind == "pi" else relerr(g32, ref)
+                assert err32 <= 10 * delta + 1e-6, (on, err32, delta)
+            # the same arithmetic as single launches up to the order of rounding
+            assert relerr(got[True], got[False]) <= 1e-14
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_pair_steps_in_a_solve(pp, inner):
+    # a full PP-GMRES solve with two steps per launch against the oracle's x
+    from oracle import solver as osolver
+
+    csr = convdiff3d_box(40, 36, 30, 10.0, 10.0, 10.0)
+    A = csr.to_scipy()
+    b, v0 = rhs(csr.n, 1), start_vector(csr.n, 2)
+    M = pp.Matrix.from_csr(csr)
+    M.tune(inner)
+    M.set_pair_steps(True, inner)
+    poly = pp.setup(M, dev(v0), 20)
+    P = oroots.setup(A, v0, 20, orth="cgs2")
+    say("pair steps solve", inner, "d_eff", poly.d_eff)
+    x, info = pp.solve(poly, M, dev(b), tol=1e-8, m=50, inner=inner)
+    assert M.pair_steps(inner)[0]
+    xh = host(x)
+    assert info["converged"]
+    assert np.linalg.norm(b - A @ xh) <= 1e-8 * np.linalg.norm(b)
+    y, _ = osolver.pp_gmres(A, b, P.units, m=50, tol=1e-8)
+    assert relerr(xh, y) <= (1e-9 if inner == "fp64" else 2e-5)
+
+
+def test_pair_steps_full_size(pp):
+    # the benchmark's 128^3 workload: phi and p chains with two steps per
+    # launch against the oracle (FP64) and against single launches (FP32)
+    csr = convdiff3d(128, 10, 10, 10)
+    A = csr.to_scipy()
+    P = oroots.setup(A, start_vector(csr.n, 2), 10)
+    M = pp.Matrix.from_csr(csr)
+    M.tune("fp64")
+    M.tune("fp32")
+    poly = pp.poly_from_roots(P.roots(), keep_order=True)
+    v = rhs(csr.n, 5)
+    say("pair steps 128^3")
+    for kind, fn in [("p", chains.apply_p), ("phi", chains.apply_phi)]:
+        M.set_pair_steps(True, "fp64")
+        assert relerr(host(pp.apply(poly, M, dev(v), kind)), fn(A, P.units, v)) <= 1e-12
+        M.set_pair_steps(True, "fp32")
+        got32 = host(pp.apply(poly, M, dev(v, torch.float32), kind))
+        flow = apply_p_low if kind == "p" else apply_phi_low
+        ref = fn(A, P.units, v)
+        delta = relerr(flow(A.astype(np.float32), P.units, v.astype(np.float32), "fp32"), ref)
+        assert relerr(got32, ref) <= 10 * delta + 1e-6

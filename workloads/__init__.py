@@ -11,6 +11,7 @@ from .generators import (  # noqa: F401
     convdiff2d_parts,
     convdiff2d_colscaled, convdiff2d_blockmixed,
     convdiff3d,
+    convdiff3d_box,
     randsparse,
     biharmonic2d,
     diagonal,

@@ -165,6 +165,27 @@ def convdiff3d(N: int, cx: float = 0.0, cy: float = 0.0, cz: float = 0.0, gamma:
     return CSR(N**3, rowptr, colind, val)
 
 
+def convdiff3d_box(nx: int, ny: int, nz: int, cx: float = 0.0, cy: float = 0.0, cz: float = 0.0) -> CSR:
+    """3-D convection-diffusion on an nx x ny x nz interior grid (rows x
+    fastest): the Kronecker sum of the 1-D operators tridiag(-1 - c h/2, 2,
+    -1 + c h/2), h = 1/(m+1) per axis. A 7-point stencil on a box whose
+    sides differ."""
+    import scipy.sparse as sp
+
+    def t1(m, c):
+        h = 1.0 / (m + 1)
+        e = np.ones(m)
+        return sp.diags([(-1.0 - 0.5 * c * h) * e[1:], 2.0 * e, (-1.0 + 0.5 * c * h) * e[1:]], [-1, 0, 1],
+                        format="csr")
+
+    Ix, Iy, Iz = (sp.identity(m, format="csr") for m in (nx, ny, nz))
+    A = (sp.kron(Iz, sp.kron(Iy, t1(nx, cx))) + sp.kron(Iz, sp.kron(t1(ny, cy), Ix)) +
+         sp.kron(t1(nz, cz), sp.kron(Iy, Ix))).tocsr()
+    A.sort_indices()
+    return CSR(n=nx * ny * nz, rowptr=A.indptr.astype(np.int32), colind=A.indices.astype(np.int32),
+               val=A.data.astype(np.float64))
+
+
 def biharmonic2d(N: int = 200) -> CSR:
     """Example 3's matrix: -(u_xxxx + 2 u_xxyy + u_yyyy) + u_xxx on the unit
     square, N x N interior grid, h = 1/(N+1), u = 0 outside the grid (the
