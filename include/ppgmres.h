@@ -205,7 +205,8 @@ pp_status pp_matrix_scale(pp_matrix A, double *s, void *stream);
  *     x = M^{-1} p(B) y, the solution of A x = b (after a right scaling of
  *     B, if any, is undone); pp_gmres_setup and pp_apply work on B.
  * PP_ESINGULAR if a diagonal block is singular (a zero pivot after partial
- * pivoting, in double). PP_EINVAL if A already has a right scaling or
+ * pivoting, in double); PP_ENOMEM if the host copies of B or M^{-1} cannot
+ * be allocated. PP_EINVAL if A already has a right scaling or
  * right blocks (its solution would then need both undone). A handle with
  * right blocks has no transpose (pp_matrix_transpose returns PP_EINVAL). */
 pp_status pp_block_jacobi_nnz(pp_matrix A, int bs, void *stream, int64_t *nnz_b);

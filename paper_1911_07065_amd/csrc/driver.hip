@@ -1534,7 +1534,12 @@ pp_status pp_block_jacobi_nnz(pp_matrix A, int bs, void *stream, int64_t *nnz_b)
         return PP_EINVAL;
     }
     std::vector<double> minv;
-    return block_jacobi_build(A, bs, S(stream), nnz_b, minv, nullptr, nullptr, nullptr);
+    try {
+        return block_jacobi_build(A, bs, S(stream), nnz_b, minv, nullptr, nullptr, nullptr);
+    } catch (const std::bad_alloc &) {
+        set_error("pp_block_jacobi_nnz: out of host memory");
+        return PP_ENOMEM;
+    }
 }
 
 pp_status pp_block_jacobi(pp_matrix A, int bs, int32_t *rowptr_b, int32_t *colind_b, double *val_b, double *minv,
@@ -1547,7 +1552,12 @@ pp_status pp_block_jacobi(pp_matrix A, int bs, int32_t *rowptr_b, int32_t *colin
     int64_t nb = 0;
     std::vector<double> mv, bv;
     std::vector<int32_t> brp, bci;
-    PP_TRY(block_jacobi_build(A, bs, st, &nb, mv, &brp, &bci, &bv));
+    try {
+        PP_TRY(block_jacobi_build(A, bs, st, &nb, mv, &brp, &bci, &bv));
+    } catch (const std::bad_alloc &) {
+        set_error("pp_block_jacobi: out of host memory");
+        return PP_ENOMEM;
+    }
     HIP_TRY(hipMemcpyAsync(rowptr_b, brp.data(), sizeof(int32_t) * brp.size(), hipMemcpyHostToDevice, st));
     if (nb) {
         HIP_TRY(hipMemcpyAsync(colind_b, bci.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
