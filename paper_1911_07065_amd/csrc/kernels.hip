@@ -1614,6 +1614,7 @@ __global__ __launch_bounds__(256) void k_dots_pair_wide(int n, const XT *__restr
         aw[k] = 0.0;
     }
     double uu = 0.0, uw = 0.0;
+#pragma unroll 2
     for (long b = (long)bx * 256; b < n; b += (long)nbx * 256) {
         const long i = b + tid;
         const long ic = i < n ? i : (long)n - 1;
