@@ -151,7 +151,7 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap);
 pp_status pp_matrix_variant(pp_matrix A, int prec, int *variant, int *remap, double *us_per_launch);
 
 /* Two chain steps per launch (Algorithms 1 and 3: two consecutive real
- * roots, each factor one sparse product). On a matrix whose rows are the
+ * roots, or the two sparse products of one conjugate pair). On a matrix whose rows are the
  * points of a gx x gy x gz box with entries only on the diagonals 0, +-1,
  * +-gx (and +-gx gy), none joining the end of a grid line to the start of
  * the next (5- and 7-point stencils; detected at pp_matrix_create), one

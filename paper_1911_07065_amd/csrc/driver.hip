@@ -539,13 +539,14 @@ const std::vector<Step> &prog_of(pp_poly p, int kind) {
 pp_status run_composite(pp_matrix A, pp_poly poly, int kind, int prec, const void *in, void *out, hipStream_t st);
 
 // Steps i and i+1 of a chain program can run as one fused pair: both one
-// sparse product without an aux vector, the second reading the first's
-// result, which no later step reads before it is written again; at most
-// one accumulator, updated by the second step only when the first's
-// initialisation came before it.
+// sparse product, the first without an aux vector, the second reading the
+// first's result and at most the first's input as aux (a conjugate pair's
+// second step); nothing later reads the first's result before it is
+// written again; at most one accumulator, updated by the second step only
+// when the first's initialisation came before it.
 bool pair_fusable(const std::vector<Step> &prog, size_t i) {
     const Step &s = prog[i], &t = prog[i + 1];
-    if (s.spmv != 1 || t.spmv != 1 || s.aux != B_NONE || t.aux != B_NONE || s.fin) return false;
+    if (s.spmv != 1 || t.spmv != 1 || s.aux != B_NONE || (t.aux != B_NONE && t.aux != s.in) || s.fin) return false;
     if (s.out < B_P0 || t.in != s.out || t.out == s.out || t.out == B_IN) return false;
     if (s.acc != B_NONE && t.acc != B_NONE && (s.acc != t.acc || t.acc_init)) return false;
     const int acc = s.acc != B_NONE ? s.acc : t.acc;
@@ -603,6 +604,8 @@ pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void 
             pp.acc1 = s.acc != B_NONE;
             pp.acc2 = t.acc != B_NONE;
             pp.init = s.acc != B_NONE ? s.acc_init : t.acc_init;
+            pp.aux2 = t.aux != B_NONE;
+            pp.a22 = t.a2;
             pp.a01 = s.a0;
             pp.a11 = s.a1;
             pp.b01 = s.b0;

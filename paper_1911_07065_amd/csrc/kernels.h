@@ -182,10 +182,11 @@ size_t elem_size(int prec);
 
 hipError_t launch_chain_step(const DevCSR &A, int prec, const StepPtrs &s, hipStream_t st);
 
-// Two consecutive chain steps, each with one sparse product and no aux
-// vector, the second reading the first's result (two real roots of
-// Algorithm 1 or 3): for each row r
-//     w1 = a01 (A in)_r + a11 in_r,   w2 = a02 (A w1)_r + a12 w1_r
+// Two consecutive chain steps, each with one sparse product, the second
+// reading the first's result and at most the first's input as its aux
+// vector (two real roots of Algorithm 1 or 3, or one conjugate pair):
+// for each row r
+//     w1 = a01 (A in)_r + a11 in_r,   w2 = a02 (A w1)_r + a12 w1_r [+ a22 in_r if aux2]
 //     acc_r = (init ? 0 : acc_r) [+ b01 in_r + b11 w1_r if acc1] [+ b02 w1_r + b12 w2_r if acc2]
 //     out_r = vfin ? vfin_r - w2 : w2                       (if out)
 // w1 is not stored. Needs the box geometry and the pattern-coded copy;
@@ -196,9 +197,9 @@ struct PairPtrs {
     void *out;
     void *acc;
     const void *vfin;
-    int acc1, acc2, init;
+    int acc1, acc2, init, aux2;
     double a01, a11, b01, b11;
-    double a02, a12, b02, b12;
+    double a02, a12, a22, b02, b12;
 };
 hipError_t launch_chain_pair(const DevCSR &A, int prec, const PairPtrs &p, int remap, hipStream_t st);
 

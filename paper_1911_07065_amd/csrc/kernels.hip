@@ -910,8 +910,8 @@ struct PairArgs {
     XT *out;
     XT *acc;
     const XT *vfin;
-    typename Arith<XT>::T a01, a11, b01, b11, a02, a12, b02, b12;
-    int acc1, acc2, init;
+    typename Arith<XT>::T a01, a11, b01, b11, a02, a12, a22, b02, b12;
+    int acc1, acc2, init, aux2;
     int gx, gy, gz;
     int ntx, nty, ntiles;
 };
@@ -1020,7 +1020,8 @@ __global__ __launch_bounds__(256) void k_chain_pair(PairArgs<XT> a, const uint8_
 #pragma unroll
         for (int d = 0; d < ND; ++d) sum += tp[d] * ws[q + box_off<ND, WX, WY>(d)];
         const AT w1 = ws[q], xin = xs[qs];
-        const AT w2 = a.a02 * sum + a.a12 * w1;
+        AT w2 = a.a02 * sum + a.a12 * w1;
+        if (a.aux2) w2 += a.a22 * xin;
         if (a.acc) {
             AT cacc = pa[k];
             if (a.acc1) cacc = cacc + a.b01 * xin + a.b11 * w1;
@@ -1045,6 +1046,8 @@ hipError_t pair_launch(const DevCSR &A, const VT *ptab, const PairPtrs &p, int r
     a.b11 = (AT)p.b11;
     a.a02 = (AT)p.a02;
     a.a12 = (AT)p.a12;
+    a.a22 = (AT)p.a22;
+    a.aux2 = p.aux2;
     a.b02 = (AT)p.b02;
     a.b12 = (AT)p.b12;
     a.acc1 = p.acc1;
