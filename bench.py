@@ -463,8 +463,9 @@ def main():
                     help="only run the launch sequence the rocprofv3 counter runs read (no JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the build has no multi-GPU path; "
-              "see DESIGN.md for how the solver would shard.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this library has no multi-GPU path. "
+              "Across GPUs the rows would split into blocks, with one halo exchange per chain step and one "
+              "small all-reduce per Gram-Schmidt pass.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
