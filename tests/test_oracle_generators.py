@@ -94,3 +94,23 @@ def test_example7_diagonal():
 def test_rhs_normalised():
     b = rhs(1000, 1)
     assert abs(np.linalg.norm(b) - 1) < 1e-14
+
+
+def test_convdiff3d_box_cube_and_structure():
+    from workloads import convdiff3d_box
+
+    # on a cube the Kronecker-sum construction is the 7-point stencil itself
+    for N, c in ((6, (10.0, 10.0, 10.0)), (9, (0.0, 3.0, -2.0))):
+        a = convdiff3d_box(N, N, N, *c).to_scipy()
+        b = convdiff3d(N, *c).to_scipy()
+        assert abs(a - b).max() == 0.0
+    # a box with unequal sides: x fastest, diagonals 0, +-1, +-nx, +-nx ny, and
+    # no entry joining the end of a grid line (or plane) to the start of the next
+    nx, ny, nz = 7, 5, 4
+    A = convdiff3d_box(nx, ny, nz, 1.0, 2.0, 3.0).to_scipy().tocoo()
+    off = A.col - A.row
+    assert set(np.unique(off)) == {0, 1, -1, nx, -nx, nx * ny, -nx * ny}
+    x, y = A.row % nx, (A.row // nx) % ny
+    assert not np.any((off == 1) & (x == nx - 1)) and not np.any((off == -1) & (x == 0))
+    assert not np.any((off == nx) & (y == ny - 1)) and not np.any((off == -nx) & (y == 0))
+    assert A.nnz == 7 * nx * ny * nz - 2 * (ny * nz + nx * nz + nx * ny)
