@@ -474,3 +474,28 @@ def test_chpoly_example12_table5_1(pp, golden_dir):
         assert 0.5 * chp <= ich["mvps"] <= 1.5 * chp
         assert 0.5 * ppg <= mv_pp <= 1.5 * ppg
         assert ich["mvps"] < mv_pp
+
+
+def test_block_jacobi_full_size(pp):
+    # the measured block-Jacobi workload (512^2, 4x4 block mixing): B against
+    # the oracle's on sampled rows, and the composed solve's true residual
+    csr = convdiff2d_blockmixed(512, 5.0, 4, 2.0)
+    A = csr.to_scipy()
+    say("block jacobi full size", csr.n)
+    B = pp.Matrix.from_csr(csr).block_jacobi(4)
+    Bo, Mo = osolver.block_jacobi(A, 4)
+    brp, bci = B.rowptr.cpu().numpy(), B.colind.cpu().numpy()
+    Bg = sp.csr_matrix((host(B.val), bci, brp), shape=A.shape)
+    rows = np.random.default_rng(5).choice(csr.n, 2000, replace=False)
+    C = A.tocoo()
+    inb = C.row // 4 == C.col // 4
+    blocks = np.zeros((csr.n // 4, 4, 4))
+    blocks[C.row[inb] // 4, C.row[inb] % 4, C.col[inb] % 4] = C.data[inb]
+    kap = np.linalg.cond(blocks)
+    scale = (abs(A) @ abs(Mo)).max(axis=0).toarray().ravel()
+    diff = abs(Bg[rows] - Bo[rows]).tocoo()
+    assert np.all(diff.data <= 16 * np.finfo(float).eps * kap[diff.col // 4] * scale[diff.col])
+    b, v0 = rhs(csr.n, 1), start_vector(csr.n, 2)
+    x, info = pp.solve(pp.setup(B, dev(v0), 10), B, dev(b), tol=1e-8, m=50, inner="fp32")
+    assert info["converged"]
+    assert np.linalg.norm(b - A @ host(x)) <= 1e-8 * np.linalg.norm(b)
