@@ -225,9 +225,12 @@ def adjoint_leg(pp, torch, np):
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     log("adjoint", f"{t * 1e3:.1f} ms", "dL/dtheta", g)
+    fused, _, us_pair = M.pair_steps("fp64")
     return {"workload": f"2-D convection-diffusion {N}^2 (n={n}, nnz={A0.nnz}), theta=20 leaf, "
                         "PP(50)-GMRES(50) to 1e-12 FP64, forward + adjoint",
-            "time_s": round(t, 6), "dL_dtheta": g, "norm_dL_db": gb}
+            "time_s": round(t, 6), "dL_dtheta": g, "norm_dL_db": gb,
+            "chain_variant_fp64": M.variant("fp64")[0], "two_steps_per_launch": fused,
+            "two_step_launch_us": round(us_pair, 3)}
 
 
 def random_sparse_leg(pp, torch, np, reps=5):
