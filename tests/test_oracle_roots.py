@@ -314,6 +314,26 @@ def test_insertion_reading_example():
     assert [u[1] for u in out] == [1.0, 2.0, 3.0, 2.0, 4.0, 2.0, 4.0]
 
 
+def test_insertion_copies_shift_later_units():
+    # Units U0 (real, 2 copies), U1 (real, none), U2 (pair, 3 copies), U3
+    # (real, none), worked by hand from the rule "copy j of c goes to
+    # s + 1 + floor(j (L - s - 1) / c)", with s the unit's current index and L
+    # the list length before its copies:
+    #   U0: s = 0, L = 4: j = 2 -> 1 + 3 = 4 (the end), j = 1 -> 1 + 1 = 2
+    #       list U0 U1 U0' U2 U3 U0'
+    #   U2: the copies of U0 moved it: s = 3, L = 6:
+    #       j = 3 -> 4 + 2 = 6 (the end), j = 2 -> 4 + 1 = 5, j = 1 -> 4 + 0 = 4
+    #       list U0 U1 U0' U2 U2' U3 U2' U0' U2'
+    # and the pair keeps its two members together in the root list
+    out = roots.insert_roots([REAL, REAL, PAIR, REAL], [1.0, 2.0, 3.0, 4.0], [0.0, 0.0, 0.5, 0.0], [2, 0, 3, 0])
+    assert [u[1] for u in out] == [1.0, 2.0, 1.0, 3.0, 3.0, 4.0, 3.0, 1.0, 3.0]
+    assert [u[0] for u in out] == [REAL, REAL, REAL, PAIR, PAIR, REAL, PAIR, REAL, PAIR]
+    P = roots.Poly(d=5, theta=np.zeros(5), leja=np.zeros(5), pof=[], n_add=[], units=out)
+    r = P.roots()
+    assert P.d_eff == 13 and P.n_added == 8
+    assert list(r[3:5]) == [3 + 0.5j, 3 - 0.5j] and list(r[11:13]) == [3 + 0.5j, 3 - 0.5j]
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_insertion_properties(seed):
     rng = np.random.default_rng(seed)

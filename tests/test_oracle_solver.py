@@ -51,15 +51,52 @@ def test_degree1_is_textbook_gmres(cycles):
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-12
 
 
+def _mgs_setup_vops(d):
+    # vector operations of a GMRES(d) setup cycle with modified Gram-Schmidt,
+    # counted here independently of the oracle: the start vector's norm and
+    # scaling, then per step j = 1..d, j dots and j axpys, one norm and one
+    # scaling
+    return 2 + sum(2 * j + 2 for j in range(1, d + 1))
+
+
 def test_example5_table3_6_loose():
-    # PP(50)-GMRES(50) matrix-vector products within 30% of Table 3.6
-    for (al, be, ga, _, pp_mvps) in read_table("table3_6_convdiff.txt")[:2]:
+    # PP(50)-GMRES(50): matrix-vector products within 30% of Table 3.6, and
+    # vector operations (setup cycle + solve) within 10% of it
+    for (al, be, ga, _, pp_mvps, _, pp_vops_k) in read_table("table3_6_convdiff.txt")[:2]:
         A = convdiff2d(200, al, be, ga).to_scipy()
         n = A.shape[0]
         P = roots.setup(A, start_vector(n, 2), 50)
         x, info = solver.pp_gmres(A, rhs(n, 1), P.units, m=50, tol=1e-8, setup_mvps=P.d)
         assert info.status == solver.OK
         assert 0.7 * pp_mvps <= info.mvps <= 1.3 * pp_mvps
+        vops = info.vops + _mgs_setup_vops(P.d)
+        assert abs(vops - 1000 * pp_vops_k) <= 0.10 * 1000 * pp_vops_k, (vops, pp_vops_k)
+
+
+@pytest.mark.parametrize("row", range(5))
+def test_counters_per_cycle_table4_1(row):
+    # Table 4.1 (diag(i^2/n), n = 20000, GMRES(50), MGS) prints cycles, mvps,
+    # vops and dots for runs of thousands of full cycles; per cycle they give
+    # the cost of one GMRES(50) cycle of PP(d). Three full cycles of the
+    # oracle (tolerance out of reach) must match: dots within 0.2% (they do
+    # not depend on how the cycle restarts), mvps within 3% and vops within
+    # 1.5% (the paper forms p(A) y once at the end and updates the residual
+    # without a product; the oracle applies p and recomputes b - A x every
+    # cycle: d more mvps and about 2d more vops per cycle)
+    from workloads import diag_squares
+
+    d, cycles, mvps_k, vops_k, dots_k = read_table("table4_1_counts.txt")[row]
+    d = int(d)
+    A = diag_squares(20000).to_scipy()
+    P = roots.setup(A, start_vector(20000, 2), d, add_roots=False)
+    assert P.d == d and P.d_eff == d
+    x, info = solver.pp_gmres(A, rhs(20000, 1), P.units, m=50, tol=1e-30, max_cycles=3, stall_cycles=0)
+    assert info.cycles == 3 and info.iters == 150
+    # the residual norm at the top of every loop pass (4 passes for 3 cycles)
+    per = {"dots": (info.dots - 1) / 3, "vops": (info.vops - 1) / 3, "mvps": info.mvps / 3}
+    paper = {"dots": dots_k * 1e3 / cycles, "vops": vops_k * 1e3 / cycles, "mvps": mvps_k * 1e3 / cycles}
+    for key, tol in (("dots", 0.002), ("mvps", 0.03), ("vops", 0.015)):
+        assert abs(per[key] - paper[key]) <= tol * paper[key], (d, key, per[key], paper[key])
 
 
 def test_richardson_theorem_3_1():
