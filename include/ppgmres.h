@@ -325,6 +325,24 @@ void pp_poly_destroy(pp_poly p);
 pp_status pp_apply(pp_poly p, pp_matrix A, int kind, int prec, const void *v, void *y,
                    void *stream);
 
+/* Device-memory traffic of one pp_apply(p, A, kind, prec) as the library runs
+ * it now (the tuned chain variant and two-step fusion of that precision; the
+ * precision is tuned first if it has not been): the bytes each launch must
+ * move by its definition, summed over the launches of the chain
+ * (Algorithms 1 and 3): the matrix data its storage format holds (values and
+ * column indices, or diagonal values, or 1-byte value codes, or one pattern
+ * byte per row and the pattern table; row pointers or slice offsets; partial
+ * row sums between column bands), one read of the input vector, the aux and
+ * final vectors a step reads, the accumulator of p (read unless the step
+ * initialises it, then written) and one write of the output. A fused pair of
+ * steps reads its input and matrix data once and does not store the first
+ * step's result. This is the byte count a bandwidth figure of the chain is
+ * divided by; it is not a hardware counter.
+ *   bytes (host): the total; launches (host, may be NULL): kernel launches.
+ * PP_EINVAL on a bad argument; tuning errors as pp_matrix_tune. */
+pp_status pp_chain_bytes(pp_poly p, pp_matrix A, int kind, int prec, void *stream, int64_t *bytes,
+                         int64_t *launches);
+
 /* Solve A x = b by PP(d)-GMRES(m) (Algorithm 4 step 2), x_0 = 0.
  * Each cycle starts from the true residual r = b - A x computed in FP64;
  * the cycle runs GMRES(m) on phi(A) in opts->inner precision and adds

@@ -343,6 +343,16 @@ def apply(poly: Poly, A: Matrix, v: torch.Tensor, kind: str = "p", out: torch.Te
     return out
 
 
+def chain_bytes(poly: Poly, A: Matrix, kind: str = "phi", prec: str = "fp32"):
+    """(bytes, launches) of one apply(poly, A, v, kind) in precision prec as the
+    library runs it now (tuned variant, two-step fusion): the device-memory
+    bytes the launches must move by their definition (pp_chain_bytes)."""
+    b, l = ctypes.c_int64(), ctypes.c_int64()
+    check(lib.pp_chain_bytes(poly.handle, A.handle, KIND[kind], PREC[prec], _stream(A.device), ctypes.byref(b),
+                             ctypes.byref(l)), "pp_chain_bytes")
+    return b.value, l.value
+
+
 def solve(poly: Poly | None, A: Matrix, b, tol: float = 1e-8, m: int = 50, max_cycles: int = 1000,
           inner: str = "fp32", stall_cycles: int = 5, x: torch.Tensor | None = None, inner_eta: float = 0.0,
           new_poly_degree: int = 0, new_poly_add: bool = True):

@@ -694,6 +694,100 @@ pp_status run_composite(pp_matrix A, pp_poly poly, int kind, int prec, const voi
     return PP_OK;
 }
 
+// Device-memory bytes of one sparse product's matrix data in the format the
+// chain variant of this precision reads: stored values and indices (or codes,
+// or row patterns and their table), row pointers or slice offsets; for the
+// column-banded copies also the partial row sums passed from one band to the
+// next (written by all bands but the last, read by all but the first).
+int64_t format_bytes(pp_matrix A, int prec) {
+    const int64_t n = A->n, nnz = A->nnz;
+    const int64_t sv = prec == PP_F64 ? 8 : 4;  // matrix values: binary64, else binary32
+    const int64_t nd = (int64_t)A->h_doff.size();
+    switch (A->variant[prec]) {
+        case CV_SELL:
+        case CV_SELLT:
+        case CV_SELL2:
+        case CV_SELL4:
+            return (int64_t)A->npad * (sv + 4) + 4 * ((int64_t)A->nslices + 1);
+        case CV_SELLD:
+        case CV_SELLD4:
+            return (int64_t)A->npad * (sv + 2) + 4 * ((int64_t)A->nslices + 1);
+        case CV_DIA:
+        case CV_DIA4:
+            return (n + 255) / 256 * 256 * nd * sv;
+        case CV_DIAC:
+            return n * ((nd + 7) / 8) * 8 + (int64_t)A->ntab * sv;
+        case CV_DIAP:
+        case CV_DIAPV:
+            return n + (int64_t)A->npat * nd * sv;
+        case CV_BAND2:
+        case CV_BAND4: {
+            const int c = A->variant[prec] == CV_BAND2 ? 0 : 1;
+            const int64_t K = A->bandK[c];
+            return (int64_t)A->bnnz[c] * (sv + 4) + K * 4 * (n + 1) + (K - 1) * 2 * n * sv;
+        }
+        default:  // CSR: row tiles, lanes per row, persistent
+            return nnz * (sv + 4) + 4 * (n + 1);
+    }
+}
+
+// Launches of one sparse product with the chain variant of this precision.
+int64_t product_launches(pp_matrix A, int prec) {
+    const int v = A->variant[prec];
+    if (v == CV_BAND2 || v == CV_BAND4) return A->bandK[v == CV_BAND2 ? 0 : 1];
+    return 1;
+}
+
+// The bytes and launches of one application of a chain program, walked as
+// run_program runs it (the same two-step fusion), without launching: per
+// launch the matrix data of its sparse products, one read of the input, the
+// aux and final vectors, the accumulator (read unless initialised, written)
+// and one write of the output; a fused pair reads its input and matrix data
+// once and never stores the first step's result.
+void program_bytes(pp_matrix A, pp_poly poly, int kind, int prec, int64_t &bytes, int64_t &launches) {
+    const int64_t vec = (int64_t)A->n * (int64_t)elem_size(prec);
+    const int64_t fmt = format_bytes(A, prec);
+    const std::vector<Step> &prog = prog_of(poly, kind);
+    if (poly->inner) {
+        pp_poly in = const_cast<pp_poly>(poly->inner.get());
+        for (const Step &s : prog) {
+            if (s.spmv) program_bytes(A, in, PP_APPLY_PHI, prec, bytes, launches);
+            bytes += vec * (1 + (s.spmv ? 1 : 0) + (s.aux != B_NONE) + (s.fin != 0) + (s.out != B_NONE));
+            if (s.acc != B_NONE) bytes += vec * (s.acc_init ? 1 : 2);
+            launches += 1;
+        }
+        if (kind == PP_APPLY_P) program_bytes(A, in, PP_APPLY_P, prec, bytes, launches);
+        return;
+    }
+    const bool fuse = A->fuse[prec] && A->box_nd && A->pbyte && prec != PP_BF16S && !A->persist[prec];
+    for (size_t i = 0; i < prog.size(); ++i) {
+        const Step &s = prog[i];
+        if (fuse && i + 1 < prog.size() && pair_fusable(prog, i)) {
+            const Step &t = prog[i + 1];
+            const int acc = s.acc != B_NONE ? s.acc : t.acc;
+            const int init = s.acc != B_NONE ? s.acc_init : t.acc_init;
+            const bool out_is_in = t.out != B_NONE && t.out == s.in && !(s.out >= B_P0 && t.out >= B_P0);
+            const bool acc_is_in = acc != B_NONE && acc == s.in;
+            if (!out_is_in && !acc_is_in) {
+                bytes += fmt + vec * (1 + (t.out != B_NONE) + (t.fin != 0));
+                if (acc != B_NONE) bytes += vec * (init ? 1 : 2);
+                launches += 1;
+                ++i;
+                continue;
+            }
+        }
+        if (s.spmv) {
+            bytes += fmt;
+            launches += product_launches(A, prec);
+        } else {
+            launches += 1;
+        }
+        bytes += vec * (1 + (s.aux != B_NONE) + (s.fin != 0) + (s.out != B_NONE));
+        if (s.acc != B_NONE) bytes += vec * (s.acc_init ? 1 : 2);
+    }
+    if (A->persist[prec] && prog.size() >= 2) launches -= (int64_t)prog.size() - 1;  // one cooperative launch
+}
+
 // Sparse products of one application of a polynomial (kind PHI/PI or P).
 int64_t chain_mvps(pp_poly p, int kind) {
     if (!p->inner) return kind == PP_APPLY_P ? p->plan.d_eff - 1 : p->plan.d_eff;
@@ -2005,6 +2099,20 @@ pp_status pp_apply(pp_poly p, pp_matrix A, int kind, int prec, const void *v, vo
     }
     PP_TRY(A->ensure_ws(prec, 0));
     return run_program(A, p, kind, prec, v, y, S(stream));
+}
+
+pp_status pp_chain_bytes(pp_poly p, pp_matrix A, int kind, int prec, void *stream, int64_t *bytes,
+                         int64_t *launches) {
+    if (!p || !A || !bytes || !valid_prec(prec) || kind < 0 || kind > 2) {
+        set_error("pp_chain_bytes: bad argument");
+        return PP_EINVAL;
+    }
+    PP_TRY(ensure_tuned(A, prec, S(stream)));
+    int64_t b = 0, l = 0;
+    program_bytes(A, p, kind, prec, b, l);
+    *bytes = b;
+    if (launches) *launches = l;
+    return PP_OK;
 }
 
 pp_status pp_stability_check(pp_poly p, pp_matrix A, const double *b, void *stream, double *stch) {

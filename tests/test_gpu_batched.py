@@ -1,4 +1,6 @@
-"""GPU parity of the batched solver: every (system, rhs) pair equals its own single solve."""
+"""GPU parity of the batched solver against the FP64 oracle: every system's
+Leja order and added roots bit for bit, and every (system, right-hand side)
+solution against the oracle's PP-GMRES with that system's polynomial."""
 
 import time
 
@@ -7,7 +9,7 @@ import pytest
 import scipy.sparse as sp
 import torch
 
-from oracle import roots as oroots
+from oracle import roots as oroots, solver as osolver
 from workloads import batched_convdiff_specs, convdiff2d, normal_vector, rhs, start_vector
 from gpu_util import say, dev, host, relerr
 
@@ -37,6 +39,49 @@ def _v0(specs):
 
 def _blockdiag(csrs):
     return sp.block_diag([c.to_scipy() for c in csrs]).tocsr()
+
+
+def _inv_norm_bound_2d(N):
+    """1 / lambda_min of the symmetric part of the h^2-scaled 2-D
+    convection-diffusion matrix on an N x N grid (centred convection only
+    changes the skew part, so the symmetric part is the 5-point Laplacian with
+    diagonal 4, smallest eigenvalue 2 (2 - 2 cos(pi h)), h = 1/(N+1)). Since
+    ||A y|| ||y|| >= y^T A y >= lambda_min ||y||^2, this bounds ||A^-1||_2."""
+    h = 1.0 / (N + 1)
+    return 1.0 / (2.0 * (2.0 - 2.0 * np.cos(np.pi * h)))
+
+
+def _check_systems_against_oracle(specs, csrs, polys, brs, X, infos, R, m, systems, tag):
+    """For each system s listed: its Leja order and final root list equal the
+    oracle's rules applied to its own harmonic Ritz values, bit for bit; for
+    each right-hand side r, x equals the oracle's PP-GMRES solution with that
+    polynomial within the bound ||x - x_or|| <= ||A^-1|| (||r|| + ||r_or||),
+    both residuals at most tol ||b||."""
+    off = np.concatenate([[0], np.cumsum([c.n for c in csrs])])
+    worst = 0.0
+    for s in systems:
+        A = csrs[s].to_scipy()
+        theta = polys[s].roots("theta")
+        leja, pof, n_add, units = oroots.order_and_add(theta)
+        assert np.array_equal(polys[s].roots("leja"), leja), s
+        fin = oroots.Poly(polys[s].d, theta, leja, pof, n_add, units).roots()
+        assert np.array_equal(polys[s].roots("final"), fin), s
+        inv_bound = _inv_norm_bound_2d(specs[s][0])
+        for r in range(R):
+            b = brs[s][r]
+            xs = X[r, off[s]:off[s + 1]]
+            xo, io = osolver.pp_gmres(A, b, units, m=m, tol=1e-8, orth="cgs2")
+            res = np.linalg.norm(b - A @ xs)
+            res_o = np.linalg.norm(b - A @ xo)
+            assert infos[s * R + r]["converged"] and res <= 1e-8 * np.linalg.norm(b), (s, r, res)
+            assert io.status == osolver.OK and res_o <= 1e-8 * np.linalg.norm(b)
+            err = relerr(xs, xo)
+            bound = inv_bound * (res + res_o) / np.linalg.norm(xo)
+            worst = max(worst, err)
+            say(f"result batched {tag} system {s} (N={specs[s][0]}) rhs {r}: relres {res / np.linalg.norm(b):.2e}, "
+                f"||x - x_oracle||/||x_oracle|| {err:.2e} (bound {bound:.2e})")
+            assert err <= bound * (1 + 1e-9) + 1e-15, (s, r, err, bound)
+    return worst
 
 
 SMALL = [(16, 3.0, 1000, 5000), (23, 40.0, 1001, 5001), (31, 0.0, 1002, 5002), (40, 12.5, 1003, 5003),
@@ -77,6 +122,22 @@ def test_small_batch_matches_single_solves(pp, inner, R, fmt):
     # the whole block system
     R_all = bmat - (Abig @ X.T).T
     assert np.all(np.linalg.norm(R_all, axis=1) <= 1e-8 * np.linalg.norm(bmat, axis=1) * np.sqrt(len(csrs)))
+
+
+@pytest.mark.parametrize("fmt", ["pattern", "sell"])
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+@pytest.mark.parametrize("R", [1, 4])
+def test_small_batch_matches_oracle(pp, inner, R, fmt):
+    csrs = _systems(SMALL)
+    say("batch small vs oracle", inner, R, fmt)
+    Bt = pp.Batch(csrs)
+    Bt.set_format(fmt)
+    polys = Bt.setup(dev(_v0(SMALL)), 8)
+    brs = _rhs_block(SMALL, R)
+    x, infos = Bt.solve(polys, Bt.interleave(np.concatenate(brs, axis=1)), R, tol=1e-8, m=30, inner=inner)
+    X = host(Bt.deinterleave(x, R))
+    _check_systems_against_oracle(SMALL, csrs, polys, brs, X, infos, R, 30, range(len(SMALL)),
+                                  f"small {inner} R={R} {fmt}")
 
 
 def test_batch_pattern_copy_rules(pp):
@@ -162,6 +223,11 @@ def test_batched_config_full_size(pp):
     say("batched full: time", round(t_batch, 3), "s, worst relres", worst,
         "max iters", max(i["iters"] for i in infos), "max cycles", max(i["cycles"] for i in infos))
     assert all(i["converged"] for i in infos) and worst <= 1e-8
+    # 8 systems of the full batch (every 32nd: sides 70 to 458) against the
+    # oracle, every right-hand side, with the polynomial each system got
+    sample = list(range(0, len(csrs), 32))
+    xw = _check_systems_against_oracle(specs, csrs, polys, _rhs_block(specs, 4), X, infos, 4, 50, sample, "full")
+    say("batched full: worst ||x - x_oracle||/||x_oracle|| over", len(sample), "systems x 4 rhs:", xw)
     # the same work as a loop of single-system solves, timed on every 16th
     # system and scaled to the whole batch
     t_loop = 0.0

@@ -117,16 +117,16 @@ def test_double_rejected_by_batch_and_bad_args(pp, cfg1):
         Bt.solve([p2], Bt.interleave(rhs(csr.n, 1)), 1)
 
 
-def test_example13_table5_2(pp, golden_dir):
+def test_example13_table6_1(pp, golden_dir):
     # Example 13: the biharmonic matrix of Example 3 (n = 40000), GMRES(50).
     # The paper stops on the shortcut residual 1e-10 (its true residuals
     # reach 1.4e-10 or better); here the true residual must reach 2e-10.
-    # Loose comparison with Tables 3.3 and 5.2 (other random vectors, CGS2),
+    # Loose comparison with Tables 3.4 and 6.1 (other random vectors, CGS2),
     # and the section's claim: the composite polynomial needs more than 10x
     # fewer inner products than the best single polynomial.
     single = {int(r[0]): r for r in np.loadtxt(os.path.join(golden_dir, "example3_biharmonic.txt"),
                                                comments="#", ndmin=2)}
-    double = {int(r[0]): r for r in np.loadtxt(os.path.join(golden_dir, "table5_2_double.txt"),
+    double = {int(r[0]): r for r in np.loadtxt(os.path.join(golden_dir, "table6_1_double.txt"),
                                                comments="#", ndmin=2)}
     csr = biharmonic2d(200)
     A = csr.to_scipy()
