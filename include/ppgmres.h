@@ -325,6 +325,23 @@ void pp_poly_destroy(pp_poly p);
 pp_status pp_apply(pp_poly p, pp_matrix A, int kind, int prec, const void *v, void *y,
                    void *stream);
 
+/* pp_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as pp_apply, with the chain's three temporary
+ * vectors in a fixed 48 MiB scratch array that the library holds on each GPU
+ * it runs on until the process ends. It calls no hipMalloc, hipFree or other
+ * allocating routine.
+ *   Limits: 3 vectors of n elements (rounded up to 64) of the precision must
+ *   fit: n <= 2,097,152 in FP64, 4,194,304 in FP32, 8,388,608 in BF16;
+ *   otherwise PP_EINVAL. The precision must already be tuned or set
+ *   (pp_matrix_tune / pp_matrix_set_variant, not the persistent variant),
+ *   and p must not be a double polynomial; otherwise PP_EINVAL.
+ *   Nothing in the scratch needs to start at zero: every temporary is
+ *   written before it is read. All calls on one GPU share its scratch, so
+ *   calls that overlap in time on one GPU (other streams, other threads)
+ *   race; order them on one stream. v, y as for pp_apply. */
+pp_status pp_apply_noalloc(pp_poly p, pp_matrix A, int kind, int prec, const void *v, void *y, void *stream);
+
 /* Device-memory traffic of one pp_apply(p, A, kind, prec) as the library runs
  * it now (the tuned chain variant and two-step fusion of that precision; the
  * precision is tuned first if it has not been): the bytes each launch must

@@ -68,6 +68,7 @@ SIGNATURES = {
     "pp_poly_roots": (c_int, [c_void_p, c_int, c_int, P_double, P_double, P_int, P_int, P_int]),
     "pp_poly_destroy": (None, [c_void_p]),
     "pp_apply": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p]),
+    "pp_apply_noalloc": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "pp_chain_bytes": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_int64),
                                ctypes.POINTER(c_int64)]),
     "pp_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts), c_void_p,

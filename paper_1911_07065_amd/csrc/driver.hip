@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -559,7 +560,10 @@ bool pair_fusable(const std::vector<Step> &prog, size_t i) {
     return true;
 }
 
-pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void *in, void *out, hipStream_t st) {
+// temps: the three temporary vectors (B_P0, B_P1, B_T) of the program; null
+// for the handle's workspace of this precision.
+pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void *in, void *out, hipStream_t st,
+                      void *const *temps = nullptr) {
     if (poly->inner) return run_composite(A, poly, kind, prec, in, out, st);
     PP_TRY(ensure_tuned(A, prec, st));
     const std::vector<Step> &prog = prog_of(poly, kind);
@@ -580,7 +584,7 @@ pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void 
     const Workspace &w = A->ws[prec];
     const DevCSR d = A->dev();
     // The temporaries' buffers; a fused pair may swap two of them (below).
-    void *tmp[5] = {nullptr, nullptr, w.P0, w.P1, w.T};
+    void *tmp[5] = {nullptr, nullptr, temps ? temps[0] : w.P0, temps ? temps[1] : w.P1, temps ? temps[2] : w.T};
     auto ptr = [&](int b) -> void * {
         if (b == B_IN) return (void *)in;
         if (b == B_OUT) return out;
@@ -786,6 +790,40 @@ void program_bytes(pp_matrix A, pp_poly poly, int kind, int prec, int64_t &bytes
         if (s.acc != B_NONE) bytes += vec * (s.acc_init ? 1 : 2);
     }
     if (A->persist[prec] && prog.size() >= 2) launches -= (int64_t)prog.size() - 1;  // one cooperative launch
+}
+
+// Scratch of pp_apply_noalloc: the chain's three temporary vectors, in a
+// file-scope device array that each GPU the library runs on holds until the
+// process ends. Host code must not pass the array's name to a kernel (on the
+// host it is a stand-in, not a device address): its device address is taken
+// once per device with hipGetSymbolAddress and used instead.
+constexpr size_t kNoallocScratchBytes = (size_t)3 * 2097152 * 8;  // 48 MiB: FP64 n <= 2^21
+constexpr int kNoallocMaxDevices = 64;
+__device__ __align__(256) unsigned char noalloc_scratch_mem[kNoallocScratchBytes];
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoallocMaxDevices] = {};
+
+// The scratch array's device address on the current device (looked up on the
+// first call on that device, with the device current).
+pp_status noalloc_scratch(char **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoallocMaxDevices) {
+        set_error("pp_apply_noalloc: device index out of range");
+        return PP_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch_mem));
+        if (e != hipSuccess || !ptr) {
+            set_error(std::string("pp_apply_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
+            return PP_EDEVICE;
+        }
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = (char *)g_noalloc_ptr[dev];
+    return PP_OK;
 }
 
 // Sparse products of one application of a polynomial (kind PHI/PI or P).
@@ -2099,6 +2137,33 @@ pp_status pp_apply(pp_poly p, pp_matrix A, int kind, int prec, const void *v, vo
     }
     PP_TRY(A->ensure_ws(prec, 0));
     return run_program(A, p, kind, prec, v, y, S(stream));
+}
+
+pp_status pp_apply_noalloc(pp_poly p, pp_matrix A, int kind, int prec, const void *v, void *y, void *stream) {
+    if (!p || !A || !v || !y || v == y || !valid_prec(prec) || kind < 0 || kind > 2) {
+        set_error("pp_apply_noalloc: bad argument");
+        return PP_EINVAL;
+    }
+    if (p->inner) {
+        set_error("pp_apply_noalloc: a double polynomial needs more temporaries than the fixed scratch holds");
+        return PP_EINVAL;
+    }
+    if (!A->tuned[prec] || A->persist[prec]) {
+        set_error("pp_apply_noalloc: tune (pp_matrix_tune) or set a single-launch variant for this precision first");
+        return PP_EINVAL;
+    }
+    const size_t ldv = ((size_t)A->n + 63) / 64 * 64;
+    const size_t vec = ldv * elem_size(prec);
+    if (3 * vec > kNoallocScratchBytes) {
+        set_error("pp_apply_noalloc: 3 temporaries of " + std::to_string(vec) + " bytes exceed the " +
+                  std::to_string(kNoallocScratchBytes) + "-byte scratch (n <= " +
+                  std::to_string(kNoallocScratchBytes / 3 / elem_size(prec) / 64 * 64) + " in this precision)");
+        return PP_EINVAL;
+    }
+    char *base = nullptr;
+    PP_TRY(noalloc_scratch(&base));
+    void *const temps[3] = {base, base + vec, base + 2 * vec};
+    return run_program(A, p, kind, prec, v, y, S(stream), temps);
 }
 
 pp_status pp_chain_bytes(pp_poly p, pp_matrix A, int kind, int prec, void *stream, int64_t *bytes,
