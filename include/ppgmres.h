@@ -170,6 +170,34 @@ pp_status pp_matrix_variant(pp_matrix A, int prec, int *variant, int *remap, dou
 pp_status pp_matrix_set_pair_steps(pp_matrix A, int prec, int mode);
 pp_status pp_matrix_pair_steps(pp_matrix A, int prec, int *mode, int *box, double *us_pair);
 
+/* Several chain steps per launch, marching along the grid (Algorithms 1 and
+ * 3): on a box-stencil matrix (as for pp_matrix_set_pair_steps) up to
+ * `steps` consecutive steps that each apply one sparse product without the
+ * accumulator of p (the real-root steps and conjugate-pair steps of a phi or
+ * pi chain) run as one launch. A workgroup owns an x-y tile (an x range in
+ * 2-D) and a chunk of cz planes along z (y in 2-D); it keeps the last three
+ * planes of every intermediate result, on the tile and the points around it
+ * that the later steps read, in LDS, so a launch reads its input and the
+ * pattern bytes and writes its last result once. The results equal single
+ * launches up to the order of rounding. pp_matrix_tune times 2, 3 and 4
+ * steps per launch (and a few chunk sizes) and keeps the count with the
+ * lowest time per step when it beats a single step.
+ *   pp_matrix_set_march: steps 0 (off) or 2..4 (every group of at least two
+ *     fusable steps marches), cz planes per chunk (0: a default that gives
+ *     at least 1024 workgroups), depth 1..3 planes of loads a workgroup keeps
+ *     in flight (0: 1; more than 1 only on constant-coefficient stencils,
+ *     see below); PP_EINVAL for a matrix without the box
+ *     geometry or its pattern-coded copy, bfloat16 vectors, or a precision
+ *     not tuned or set yet. pp_matrix_set_variant turns it off.
+ *   pp_matrix_march: *steps (host) the count in use (0: none), cz and us
+ *     (host, may be NULL) its chunk size and tuned time per launch;
+ *     constant (host, may be NULL) 1 when every row is one interior row's
+ *     stencil truncated at the box (a constant-coefficient stencil): the
+ *     kernel then takes that row's coefficients for every point and reads
+ *     no pattern bytes. */
+pp_status pp_matrix_set_march(pp_matrix A, int prec, int steps, int cz, int depth);
+pp_status pp_matrix_march(pp_matrix A, int prec, int *steps, int *cz, double *us, int *constant);
+
 /* Composition with a diagonal right preconditioner M^{-1} = diag(s)
  * (eqs. (1.3)-(1.4), section 1): from now on the handle's operator is
  * A diag(s). Its chains, pp_gmres_setup (the polynomial is built for

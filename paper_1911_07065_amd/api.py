@@ -157,6 +157,26 @@ class Matrix:
         dims = tuple(box) if box[0] else None
         return bool(mode.value), dims, us.value
 
+    def set_march(self, steps: int, prec: str = "fp32", cz: int = 0, depth: int = 0):
+        """Up to `steps` (2..4) chain steps per launch of the marching kernel
+        on a box stencil (0: off); cz planes per chunk (0: default); depth
+        planes of loads in flight per workgroup (0: 1)."""
+        check(lib.pp_matrix_set_march(self.handle, PREC[prec], int(steps), int(cz), int(depth)),
+              "pp_matrix_set_march")
+
+    def march(self, prec: str = "fp32"):
+        """(steps, cz, us per launch) of the marching kernel in use (steps 0: off)."""
+        g, cz, us, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+        check(lib.pp_matrix_march(self.handle, PREC[prec], ctypes.byref(g), ctypes.byref(cz), ctypes.byref(us),
+                                  ctypes.byref(c)), "pp_matrix_march")
+        return g.value, cz.value, us.value
+
+    def constant_stencil(self) -> bool:
+        """True when every row is one interior row's box stencil truncated at the box."""
+        g, c = ctypes.c_int(), ctypes.c_int()
+        check(lib.pp_matrix_march(self.handle, 0, ctypes.byref(g), None, None, ctypes.byref(c)), "pp_matrix_march")
+        return bool(c.value)
+
     def set_variant(self, prec: str, variant: int, remap: int = 1):
         """Force chain variant `variant` (0..30; 15 = persistent cooperative kernel) for a precision."""
         check(lib.pp_matrix_set_variant(self.handle, PREC[prec], int(variant), int(remap)), "pp_matrix_set_variant")

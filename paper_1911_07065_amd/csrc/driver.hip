@@ -81,8 +81,17 @@ struct pp_matrix_s {
     // the tuned time of one such launch
     int box[3] = {0, 0, 0};
     int box_nd = 0;
+    int box_pint = -1;  // constant-coefficient box stencil: the interior row's pattern (-1: not one)
     int fuse[3] = {0, 0, 0};
     double pair_us[3] = {0, 0, 0};
+    // per precision: chains run up to march[prec] consecutive steps per
+    // launch of the marching kernel (0: off), with chunks of march_cz planes;
+    // march_us[prec][g] is the tuned time of one g-step launch (0: not timed)
+    int march[3] = {0, 0, 0};
+    int march_all[3] = {0, 0, 0};  // set by hand: every group of >= 2 steps marches
+    int march_cz[3][kMarchMax + 1] = {};
+    int march_depth[3][kMarchMax + 1] = {};  // planes of loads in flight (1..3)
+    double march_us[3][kMarchMax + 1] = {};
     // column-banded CSR copies (matrices whose entries lie far from the
     // diagonal): c = 0 two bands, c = 1 four; bperm maps entries to CSR
     int32_t *brow[2] = {nullptr, nullptr}, *bcol[2] = {nullptr, nullptr}, *bperm[2] = {nullptr, nullptr};
@@ -183,6 +192,7 @@ struct pp_matrix_s {
         d.npat = npat;
         for (int k = 0; k < 3; ++k) d.box[k] = box[k];
         d.box_nd = box_nd;
+        d.box_pint = box_nd && pbyte ? box_pint : -1;
         for (int p = 0; p < 3; ++p) {
             d.tileB8[p] = tileB8[p];
             d.ntileB8[p] = ntileB8[p];
@@ -498,6 +508,60 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
         A->pair_us[prec] = bp;
         A->fuse[prec] = bp < 2.0 * best ? 1 : 0;
     }
+    // 2 to kMarchMax steps per launch of the marching kernel: each launch
+    // length is timed over a few plane-chunk sizes; the length with the
+    // lowest time per step is kept when it beats a single step
+    A->march[prec] = 0;
+    A->march_all[prec] = 0;
+    for (int g = 0; g <= kMarchMax; ++g) {
+        A->march_us[prec][g] = 0.0;
+        A->march_cz[prec][g] = 0;
+    }
+    if (A->box_nd && A->pbyte && prec != PP_BF16S) {
+        const DevCSR d = A->dev();
+        MarchPtrs mp;
+        std::memset(&mp, 0, sizeof(mp));
+        mp.in = w.P0;
+        mp.out = w.P1;
+        for (int k = 0; k < kMarchMax; ++k) mp.a0[k] = 1.0;
+        const int cz0 = march_default_cz(d, 1024);
+        const int czs[3] = {cz0, 2 * cz0, std::max(4, cz0 / 2)};
+        const int ndepth = A->box_pint >= 0 ? 3 : 1;  // deeper prefetch: constant-coefficient kernels only
+        double per_step = best;
+        for (int g = 2; g <= kMarchMax; ++g) {
+            mp.nsteps = g;
+            double bg = 1e30;
+            int bcz = cz0, bdepth = 1;
+            for (int c = 0; c < 3; ++c) {
+                if (c > 0 && (czs[c] == czs[0] || (c == 2 && czs[2] == czs[1]))) continue;
+                for (int depth = 1; depth <= ndepth; ++depth) {
+                    mp.depth = depth;
+                    for (int round = 0; round < 2; ++round) {
+                        for (int i = 0; i < 2; ++i) HIP_TRY(launch_chain_march(d, prec, mp, czs[c], br, st));
+                        HIP_TRY(hipEventRecord(e0, st));
+                        for (int i = 0; i < reps; ++i) HIP_TRY(launch_chain_march(d, prec, mp, czs[c], br, st));
+                        HIP_TRY(hipEventRecord(e1, st));
+                        HIP_TRY(hipEventSynchronize(e1));
+                        float ms = 0.f;
+                        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                        const double us = 1e3 * ms / reps;
+                        if (us < bg) {
+                            bg = us;
+                            bcz = czs[c];
+                            bdepth = depth;
+                        }
+                    }
+                }
+            }
+            A->march_us[prec][g] = bg;
+            A->march_cz[prec][g] = bcz;
+            A->march_depth[prec][g] = bdepth;
+            if (bg / g < per_step) {
+                per_step = bg / g;
+                A->march[prec] = g;
+            }
+        }
+    }
     // The persistent kernel is only timed on request: its grid barrier must
     // write back and invalidate the per-XCD L2 caches, which costs far more
     // than a kernel boundary on this GPU.
@@ -560,6 +624,102 @@ bool pair_fusable(const std::vector<Step> &prog, size_t i) {
     return true;
 }
 
+// Steps i .. i+g-1 of a chain program can run as one launch of the
+// marching kernel: each one sparse product without an accumulator; the
+// first without aux; each later one reading the previous step's result and,
+// as aux, at most the previous step's input (a conjugate pair's second
+// step); every result but the last a temporary without a final vector; and
+// no intermediate result read after the group before it is written again.
+bool march_group_ok(const std::vector<Step> &prog, size_t i, int g) {
+    const size_t last = i + g - 1;
+    for (size_t k = i; k < last; ++k) {
+        const int b = prog[k].out;
+        bool rewritten = false;
+        for (size_t m = k + 1; m <= last; ++m)
+            if (prog[m].out == b) {
+                rewritten = true;
+                break;
+            }
+        if (rewritten) continue;
+        for (size_t j = last + 1; j < prog.size(); ++j) {
+            const Step &u = prog[j];
+            if (u.in == b || u.aux == b || (u.acc == b && !u.acc_init)) return false;
+            if (u.out == b || u.acc == b) break;
+        }
+    }
+    return true;
+}
+
+int march_group_len(const std::vector<Step> &prog, size_t i, int smax) {
+    const Step &s0 = prog[i];
+    if (s0.spmv != 1 || s0.acc != B_NONE || s0.aux != B_NONE || s0.out == B_NONE || s0.out == s0.in) return 1;
+    int g = 1;
+    while (g < smax && i + g < prog.size()) {
+        const Step &p = prog[i + g - 1], &t = prog[i + g];
+        if (p.fin || p.out < B_P0) break;
+        if (t.spmv != 1 || t.acc != B_NONE || t.in != p.out || t.out == B_NONE || t.out == t.in) break;
+        if (t.aux != B_NONE && t.aux != p.in) break;
+        ++g;
+    }
+    for (; g >= 2; --g)
+        if (march_group_ok(prog, i, g)) break;
+    return g;
+}
+
+// One launch of a chain program as run_program issues it.
+struct Planned {
+    int kind;   // 0: one step, 1: the two-step pair kernel, 2: the marching kernel
+    int i, g;   // steps i .. i+g-1
+    int write;  // the buffer the launch's last result goes to
+    int swap;   // after the launch the names `write` and the last step's out swap (-1: no swap)
+};
+
+// The launches of a chain program with this matrix's fusion settings for the
+// precision. A fused launch reads its input around its tile while other
+// workgroups write: when its last step's output buffer is the group's input
+// (ping-pong temporaries), the result goes to a temporary whose value is
+// dead after the group and the two names swap for the rest of the program.
+void plan_program(pp_matrix A, const std::vector<Step> &prog, int prec, std::vector<Planned> &out) {
+    out.clear();
+    const bool coded = A->box_nd && A->pbyte && prec != PP_BF16S && !A->persist[prec];
+    const bool pair = coded && A->fuse[prec];
+    const int smax = coded ? A->march[prec] : 0;
+    for (size_t i = 0; i < prog.size();) {
+        const Step &s = prog[i];
+        if (smax >= 2) {
+            int g = march_group_len(prog, i, smax);
+            // a shorter group runs only if that launch length beats single steps
+            while (g >= 2 && g < smax && !A->march_all[prec] &&
+                   !(A->march_us[prec][g] > 0.0 && A->march_us[prec][g] < g * A->tuned_us[prec]))
+                --g;
+            if (g >= 2) {
+                const Step &t = prog[i + g - 1];
+                Planned L{2, (int)i, g, t.out, -1};
+                if (t.out == s.in) {
+                    L.write = s.out;  // step i's result: a temporary, dead after the group
+                    L.swap = s.out;
+                }
+                out.push_back(L);
+                i += g;
+                continue;
+            }
+        }
+        if (pair && i + 1 < prog.size() && pair_fusable(prog, i)) {
+            const Step &t = prog[i + 1];
+            const bool swap = t.out != B_NONE && t.out == s.in && s.out >= B_P0 && t.out >= B_P0;
+            const int write = swap ? s.out : t.out;
+            const int acc = s.acc != B_NONE ? s.acc : t.acc;
+            if (write != s.in && (acc == B_NONE || acc != s.in)) {
+                out.push_back(Planned{1, (int)i, 2, write, swap ? s.out : -1});
+                i += 2;
+                continue;
+            }
+        }
+        out.push_back(Planned{0, (int)i, 1, s.out, -1});
+        ++i;
+    }
+}
+
 // temps: the three temporary vectors (B_P0, B_P1, B_T) of the program; null
 // for the handle's workspace of this precision.
 pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void *in, void *out, hipStream_t st,
@@ -583,26 +743,44 @@ pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void 
     }
     const Workspace &w = A->ws[prec];
     const DevCSR d = A->dev();
-    // The temporaries' buffers; a fused pair may swap two of them (below).
+    // The temporaries' buffers; a fused launch may swap two of them.
     void *tmp[5] = {nullptr, nullptr, temps ? temps[0] : w.P0, temps ? temps[1] : w.P1, temps ? temps[2] : w.T};
     auto ptr = [&](int b) -> void * {
         if (b == B_IN) return (void *)in;
         if (b == B_OUT) return out;
         return b >= B_P0 && b <= B_T ? tmp[b] : nullptr;
     };
-    const bool fuse = A->fuse[prec] && A->box_nd && A->pbyte && prec != PP_BF16S;
-    for (size_t i = 0; i < prog.size(); ++i) {
-        const Step &s = prog[i];
-        if (fuse && i + 1 < prog.size() && pair_fusable(prog, i)) {
+    std::vector<Planned> plan;
+    plan_program(A, prog, prec, plan);
+    for (const Planned &L : plan) {
+        const Step &s = prog[L.i];
+        if (L.kind == 2) {
+            const Step &t = prog[L.i + L.g - 1];
+            MarchPtrs mp;
+            std::memset(&mp, 0, sizeof(mp));
+            mp.in = ptr(s.in);
+            mp.out = ptr(L.write);
+            mp.vfin = t.fin ? in : nullptr;
+            mp.nsteps = L.g;
+            for (int k = 0; k < L.g; ++k) {
+                const Step &u = prog[L.i + k];
+                mp.a0[k] = u.a0;
+                mp.a1[k] = u.a1;
+                mp.a2[k] = u.a2;
+                if (u.aux != B_NONE) mp.aux |= 1 << k;
+            }
+            mp.depth = A->march_depth[prec][L.g];
+            HIP_TRY(launch_chain_march(d, prec, mp, A->march_cz[prec][L.g], A->remap[prec], st));
+            if (L.swap >= 0) std::swap(tmp[L.swap], tmp[t.out]);
+            continue;
+        }
+        if (L.kind == 1) {
             // Two real-root steps in one launch. The first step's result is
-            // not stored; if the second's output buffer is the first's
-            // input (other workgroups still read it), the pair writes the
-            // first's output buffer instead and the two names swap.
-            const Step &t = prog[i + 1];
-            const bool swap = t.out != B_NONE && ptr(t.out) == ptr(s.in) && s.out >= B_P0 && t.out >= B_P0;
+            // not stored.
+            const Step &t = prog[L.i + 1];
             PairPtrs pp;
             pp.in = ptr(s.in);
-            pp.out = swap ? ptr(s.out) : ptr(t.out);
+            pp.out = ptr(L.write);
             pp.acc = ptr(s.acc != B_NONE ? s.acc : t.acc);
             pp.vfin = t.fin ? in : nullptr;
             pp.acc1 = s.acc != B_NONE;
@@ -618,12 +796,9 @@ pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void 
             pp.a12 = t.a1;
             pp.b02 = t.b0;
             pp.b12 = t.b1;
-            if (pp.out != pp.in && pp.acc != pp.in) {
-                if (swap) std::swap(tmp[s.out], tmp[t.out]);
-                HIP_TRY(launch_chain_pair(d, prec, pp, A->remap[prec], st));
-                ++i;
-                continue;
-            }
+            HIP_TRY(launch_chain_pair(d, prec, pp, A->remap[prec], st));
+            if (L.swap >= 0) std::swap(tmp[L.swap], tmp[t.out]);
+            continue;
         }
         StepPtrs p;
         p.in = ptr(s.in);
@@ -763,22 +938,25 @@ void program_bytes(pp_matrix A, pp_poly poly, int kind, int prec, int64_t &bytes
         if (kind == PP_APPLY_P) program_bytes(A, in, PP_APPLY_P, prec, bytes, launches);
         return;
     }
-    const bool fuse = A->fuse[prec] && A->box_nd && A->pbyte && prec != PP_BF16S && !A->persist[prec];
-    for (size_t i = 0; i < prog.size(); ++i) {
-        const Step &s = prog[i];
-        if (fuse && i + 1 < prog.size() && pair_fusable(prog, i)) {
-            const Step &t = prog[i + 1];
+    // fused launches read the pattern-coded copy, whatever the single-step variant
+    const int64_t pat = (int64_t)A->n + (int64_t)A->npat * (int64_t)A->h_doff.size() * (prec == PP_F64 ? 8 : 4);
+    std::vector<Planned> plan;
+    plan_program(A, prog, prec, plan);
+    for (const Planned &L : plan) {
+        const Step &s = prog[L.i], &t = prog[L.i + L.g - 1];
+        if (L.kind == 2) {
+            // the input and the pattern bytes once, the final vector, the output
+            bytes += pat + vec * (1 + (t.fin != 0) + 1);
+            launches += 1;
+            continue;
+        }
+        if (L.kind == 1) {
             const int acc = s.acc != B_NONE ? s.acc : t.acc;
             const int init = s.acc != B_NONE ? s.acc_init : t.acc_init;
-            const bool out_is_in = t.out != B_NONE && t.out == s.in && !(s.out >= B_P0 && t.out >= B_P0);
-            const bool acc_is_in = acc != B_NONE && acc == s.in;
-            if (!out_is_in && !acc_is_in) {
-                bytes += fmt + vec * (1 + (t.out != B_NONE) + (t.fin != 0));
-                if (acc != B_NONE) bytes += vec * (init ? 1 : 2);
-                launches += 1;
-                ++i;
-                continue;
-            }
+            bytes += pat + vec * (1 + (t.out != B_NONE) + (t.fin != 0));
+            if (acc != B_NONE) bytes += vec * (init ? 1 : 2);
+            launches += 1;
+            continue;
         }
         if (s.spmv) {
             bytes += fmt;
@@ -1112,6 +1290,43 @@ pp_status build_value_codes(pp_matrix A, const int32_t *dp, const std::vector<do
 // (and +-gx gy), n = gx gy gz, and no stored entry joining the last point
 // of a grid line (or plane) to the first of the next. Leaves box_nd = 0
 // when the matrix is not such a stencil.
+// A constant-coefficient box stencil: every row's code tuple is the one of
+// an interior row with code 0 (the value zero) wherever the neighbour lies
+// outside the box, so the interior row's coefficients serve every row of a
+// kernel that keeps the points outside the box at zero. The codes stay valid
+// when new values keep them (pp_matrix_set_values), so does this.
+void detect_box_const(pp_matrix A, hipStream_t st) {
+    A->box_pint = -1;
+    if (!A->box_nd || !A->pbyte || !A->pcodes || A->npat <= 0) return;
+    const long n = A->n;
+    const int nd = A->box_nd;
+    const long gx = A->box[0], gy = A->box[1], gz = A->box[2];
+    if (gx < 3 || gy < 3 || (nd == 7 && gz < 3)) return;
+    std::vector<uint8_t> pb((size_t)n), pc((size_t)A->npat * nd);
+    if (hipMemcpyAsync(pb.data(), A->pbyte, (size_t)n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(pc.data(), A->pcodes, pc.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return;
+    const long rc = gx / 2 + gx * (gy / 2 + gy * (nd == 7 ? gz / 2 : 0));
+    const int pint = pb[(size_t)rc];
+    const uint8_t *ci = pc.data() + (size_t)pint * nd;
+    for (long r = 0; r < n; ++r) {
+        const long x = r % gx, y = (r / gx) % gy, z = r / (gx * gy);
+        // neighbours in ascending offset order: (-z) -y -x 0 +x +y (+z)
+        bool in[7];
+        if (nd == 7) {
+            in[0] = z > 0, in[1] = y > 0, in[2] = x > 0, in[3] = true, in[4] = x < gx - 1, in[5] = y < gy - 1,
+            in[6] = z < gz - 1;
+        } else {
+            in[0] = y > 0, in[1] = x > 0, in[2] = true, in[3] = x < gx - 1, in[4] = y < gy - 1;
+        }
+        const uint8_t *cr = pc.data() + (size_t)pb[(size_t)r] * nd;
+        for (int d = 0; d < nd; ++d)
+            if (cr[d] != (in[d] ? ci[d] : 0)) return;
+    }
+    A->box_pint = pint;
+}
+
 void detect_box(pp_matrix A, const std::vector<int32_t> &ci) {
     const auto &o = A->h_doff;
     const int nd = (int)o.size();
@@ -1374,6 +1589,7 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
                     hipStreamSynchronize(st) == hipSuccess)
                     if ((s = build_value_codes(A, dp.data(), hv, st)) != PP_OK) return fail(s);
                 if (A->pbyte) detect_box(A, ci);
+                detect_box_const(A, st);
             }
         }
     }
@@ -1438,6 +1654,7 @@ pp_status refresh_values(pp_matrix A, const double *val, hipStream_t st) {
             dev_free(A->ptab32);
             A->ntab = 0;
             A->npat = 0;
+            A->box_pint = -1;
             for (int p = 0; p < 3; ++p)
                 if (A->variant[p] == CV_DIAC || A->variant[p] == CV_DIAP || A->variant[p] == CV_DIAPV) {
                     A->variant[p] = CV_TILE8;
@@ -1455,6 +1672,7 @@ pp_status refresh_values(pp_matrix A, const double *val, hipStream_t st) {
                 HIP_TRY(hipMemcpyAsync(hv.data(), val, sizeof(double) * A->nnz, hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipStreamSynchronize(st));
                 PP_TRY(build_value_codes(A, dp.data(), hv, st));
+                detect_box_const(A, st);
             }
         }
     }
@@ -1777,6 +1995,8 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
     A->tuned[prec] = 1;
     A->tuned_us[prec] = 0.0;
     A->fuse[prec] = 0;  // the forced variant runs every step
+    A->march[prec] = 0;
+    A->march_all[prec] = 0;
     return PP_OK;
 }
 
@@ -1795,6 +2015,44 @@ pp_status pp_matrix_set_pair_steps(pp_matrix A, int prec, int mode) {
         return PP_EINVAL;
     }
     A->fuse[prec] = mode;
+    return PP_OK;
+}
+
+pp_status pp_matrix_set_march(pp_matrix A, int prec, int steps, int cz, int depth) {
+    if (!A || !valid_prec(prec) || steps < 0 || steps == 1 || steps > kMarchMax || cz < 0 || depth < 0 ||
+        depth > 3) {
+        set_error("pp_matrix_set_march: bad argument");
+        return PP_EINVAL;
+    }
+    if (steps >= 2 && (!A->box_nd || !A->pbyte || prec == PP_BF16S)) {
+        set_error("pp_matrix_set_march: several steps per launch need a 5- or 7-point box stencil with a "
+                  "pattern-coded copy, and FP64 or FP32 vectors");
+        return PP_EINVAL;
+    }
+    if (!A->tuned[prec] || A->persist[prec]) {
+        set_error("pp_matrix_set_march: tune or set a single-launch variant for this precision first");
+        return PP_EINVAL;
+    }
+    A->march[prec] = steps;
+    A->march_all[prec] = steps >= 2;
+    const int c = cz > 0 ? cz : march_default_cz(A->dev(), 1024);
+    for (int g = 2; g <= kMarchMax; ++g) {
+        A->march_cz[prec][g] = c;
+        A->march_depth[prec][g] = depth > 0 ? depth : 1;
+    }
+    return PP_OK;
+}
+
+pp_status pp_matrix_march(pp_matrix A, int prec, int *steps, int *cz, double *us, int *constant) {
+    if (!A || !valid_prec(prec) || !steps) {
+        set_error("pp_matrix_march: bad argument");
+        return PP_EINVAL;
+    }
+    const int g = A->box_nd && A->pbyte && prec != PP_BF16S ? A->march[prec] : 0;
+    *steps = g;
+    if (cz) *cz = g >= 2 ? A->march_cz[prec][g] : 0;
+    if (us) *us = g >= 2 ? A->march_us[prec][g] : 0.0;
+    if (constant) *constant = A->box_nd && A->pbyte && A->box_pint >= 0 ? 1 : 0;
     return PP_OK;
 }
 

@@ -154,6 +154,9 @@ struct DevCSR {
     // of the next; the diagonal format's d order is that ascending order
     int box[3];
     int box_nd;
+    // constant-coefficient box stencil: every row is the stencil of the row
+    // with pattern box_pint (an interior point) truncated at the box; -1: no
+    int box_pint;
     int variant[3];      // chain variant per precision
     int remap[3];        // 1: keep neighbouring workgroups on one XCD
 };
@@ -202,6 +205,31 @@ struct PairPtrs {
     double a02, a12, a22, b02, b12;
 };
 hipError_t launch_chain_pair(const DevCSR &A, int prec, const PairPtrs &p, int remap, hipStream_t st);
+
+// 2 to kMarchMax consecutive chain steps in one launch on a box-stencil
+// matrix, marching along the slowest grid dimension (z in 3-D, y in 2-D).
+// Step k computes w_{k+1} = a0[k] (A w_k) + a1[k] w_k [+ a2[k] w_{k-1} if
+// bit k of aux], w_0 = in (bit 0 must be clear); the last result is stored:
+// out = vfin ? vfin - w_S : w_S. No intermediate result is stored. A
+// workgroup owns an x-y tile (x tile in 2-D) and a chunk of cz planes; it
+// keeps the last three planes of every intermediate result (on the tile and
+// the points around it that later steps need) in LDS. Needs the box
+// geometry and the pattern-coded copy; out must not alias in or vfin; FP64
+// and FP32 vectors only.
+constexpr int kMarchMax = 4;
+struct MarchPtrs {
+    const void *in;
+    void *out;
+    const void *vfin;
+    int nsteps;
+    int aux;
+    int depth;  // planes of loads in flight per workgroup (1..3; constant-coefficient stencils only)
+    double a0[kMarchMax], a1[kMarchMax], a2[kMarchMax];
+};
+hipError_t launch_chain_march(const DevCSR &A, int prec, const MarchPtrs &p, int cz, int remap, hipStream_t st);
+// Planes per chunk that give the grid at least `target` workgroups (at most
+// the marching extent; a multiple of 4 where possible).
+int march_default_cz(const DevCSR &A, int target);
 
 // partial[b * ldp + k] = sum over rows of block b of V[i, k] * w[i], k < ncols.
 int dot_blocks(int n);

@@ -1068,6 +1068,360 @@ hipError_t pair_launch(const DevCSR &A, const VT *ptab, const PairPtrs &p, int r
     return hipGetLastError();
 }
 
+// Several chain steps per launch on a box stencil (see MarchPtrs). The grid
+// is a stack of planes along the marching dimension (z in 3-D, y in 2-D): a
+// plane is gx x gy points (gy = 1 in 2-D), P = gx gy apart. A workgroup
+// owns a TX x TY tile of the plane (TX in 2-D) and the planes [m0, m1).
+// Level l = 0 .. S holds w_l: level 0 the input, level S the output. Level
+// l < S is kept on the tile and S - l points around it (a region of
+// (TX + 2(S - l)) x (TY + 2(S - l)) points), zero outside the box, in a ring
+// of three planes in LDS. At iteration j the workgroup stores input plane
+// m0 - S + j (loaded during iteration j - 1) and then level l computes its
+// plane m0 - S + j - l from the three newest planes of level l - 1 (and,
+// for a conjugate pair's second step, level l - 2's plane, the step's aux).
+// Level S writes plane m0 + j - 2S. Each level's region shrinks by one
+// point per side, so every neighbour it reads exists in the level below;
+// the first 2S iterations fill the rings.
+//
+// Row coefficients: KC (constant coefficients) when every row of the matrix
+// is one interior row's stencil truncated at the box (the points outside
+// the box hold zero in the rings, so the interior coefficients serve every
+// row): the ND coefficients are that row's pattern, read once per
+// workgroup. Otherwise each point's pattern id is loaded with its plane and
+// staged in LDS, and its coefficients come from the pattern table.
+template <typename XT>
+struct MarchArgs {
+    const XT *in;
+    XT *out;
+    const XT *vfin;
+    typename Arith<XT>::T a0[kMarchMax], a1[kMarchMax], a2[kMarchMax];
+    int aux;
+    int gx, gy, gm;
+    int ntx, nty, cz, ntiles;
+    int pint;  // KC: the interior row's pattern
+};
+
+template <int ND, int S, int TX, int TY>
+struct MarchGeom {
+    static constexpr int rx(int l) { return TX + 2 * (S - l); }
+    static constexpr int ry(int l) { return ND == 7 ? TY + 2 * (S - l) : 1; }
+    static constexpr int size(int l) { return rx(l) * ry(l); }
+    static constexpr int chunks(int l) { return (size(l) + 255) / 256; }
+    // LDS ring of levels 0 .. S-1 (three planes each)
+    static constexpr int base(int l) {
+        int b = 0;
+        for (int m = 0; m < l; ++m) b += 3 * size(m);
+        return b;
+    }
+    // pattern ids of levels 1 .. S (one plane each)
+    static constexpr int pbase(int l) {
+        int b = 0;
+        for (int m = 1; m < l; ++m) b += size(m);
+        return b;
+    }
+    // per-thread registers of levels 1 .. S (one per chunk of 256 points)
+    static constexpr int rbase(int l) {
+        int b = 0;
+        for (int m = 1; m < l; ++m) b += chunks(m);
+        return b;
+    }
+};
+
+// sum_d tab[d] x[d] over the stencil of point q of a level region with row
+// length RX, in ascending diagonal order (the pattern table's order): the
+// plane below (lo), the plane's own points (mid) and the plane above (hi)
+template <typename AT, int ND, int RX>
+__device__ __forceinline__ AT march_sum(const AT *tp, const AT *lo, const AT *mid, const AT *hi, int q) {
+    AT s = AT(0);
+    if constexpr (ND == 7) {
+        s += tp[0] * lo[q];
+        s += tp[1] * mid[q - RX];
+        s += tp[2] * mid[q - 1];
+        s += tp[3] * mid[q];
+        s += tp[4] * mid[q + 1];
+        s += tp[5] * mid[q + RX];
+        s += tp[6] * hi[q];
+    } else {
+        s += tp[0] * lo[q];
+        s += tp[1] * mid[q - 1];
+        s += tp[2] * mid[q];
+        s += tp[3] * mid[q + 1];
+        s += tp[4] * hi[q];
+    }
+    return s;
+}
+
+// The per-thread, iteration-invariant part of a level's points: for chunk k
+// (point c = thread + 256 k of the level's region) its index in the source
+// region (the level below, one point wider per side), its index in the aux
+// region (two points wider), and whether it lies in the plane's part of the
+// box (x-y; the plane itself is checked per iteration).
+template <int ND, int S, int TX, int TY>
+struct MarchIdx {
+    using G = MarchGeom<ND, S, TX, TY>;
+    int q[G::rbase(S + 1)], qa[G::rbase(S + 1)];
+    unsigned inb;  // bit rbase(l) + k
+};
+
+// Level L (1 <= L < S) of iteration j into its ring slot j % 3.
+template <typename XT, int ND, int S, int TX, int TY, bool KC, int L>
+__device__ __forceinline__ void march_level(const MarchArgs<XT> &a, typename Arith<XT>::T *ring,
+                                            const typename Arith<XT>::T *tab, const int16_t *pat,
+                                            const MarchIdx<ND, S, TX, TY> &ix, int j, int m0) {
+    using AT = typename Arith<XT>::T;
+    using G = MarchGeom<ND, S, TX, TY>;
+    if constexpr (L < S) {
+        if (j >= 2 * L) {
+            constexpr int RXs = G::rx(L - 1), N = G::size(L), C = G::chunks(L), Ns = G::size(L - 1);
+            const AT *src = ring + G::base(L - 1);
+            const AT *lo = src + ((j + 1) % 3) * Ns, *mid = src + ((j + 2) % 3) * Ns, *hi = src + (j % 3) * Ns;
+            AT *dst = ring + G::base(L) + (j % 3) * N;
+            const int pm = m0 - S + j - L;
+            const bool plane = pm >= 0 && pm < a.gm;
+            const AT c0 = a.a0[L - 1], c1 = a.a1[L - 1], c2 = a.a2[L - 1];
+            bool aux = false;
+            const AT *ax = nullptr;
+            if constexpr (L >= 2) {
+                aux = (a.aux >> (L - 1)) & 1;
+                ax = ring + G::base(L - 2) + ((j + 1) % 3) * G::size(L - 2);
+            }
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                const int c = (int)threadIdx.x + k * 256;
+                if (c < N) {
+                    const int r = G::rbase(L) + k;
+                    AT w = AT(0);
+                    const AT *tp = tab;
+                    bool live;
+                    if constexpr (KC) {
+                        live = plane && ((ix.inb >> r) & 1u);
+                    } else {
+                        const int id = pat[G::pbase(L) + c];
+                        live = id >= 0;
+                        tp = tab + id * ND;
+                    }
+                    if (live) {
+                        const int q = ix.q[r];
+                        w = c0 * march_sum<AT, ND, RXs>(tp, lo, mid, hi, q) + c1 * mid[q];
+                        if (aux) w += c2 * ax[ix.qa[r]];
+                    }
+                    dst[c] = w;
+                }
+            }
+            __syncthreads();
+        }
+        march_level<XT, ND, S, TX, TY, KC, L + 1>(a, ring, tab, pat, ix, j, m0);
+    }
+}
+
+template <typename VT, typename XT, int ND, int S, int TX, int TY, bool KC, int D>
+__global__ __launch_bounds__(256) void k_chain_march(MarchArgs<XT> a, const uint8_t *__restrict__ pbyte,
+                                                     const VT *__restrict__ ptab, int nent, int remap) {
+    using AT = typename Arith<XT>::T;
+    using G = MarchGeom<ND, S, TX, TY>;
+    static_assert(ND == 5 || ND == 7, "5- or 7-point box stencils");
+    static_assert(S >= 2 && S <= kMarchMax, "2 to kMarchMax steps");
+    static_assert(ND == 7 || TY == 1, "a 2-D tile is one line");
+    static_assert(G::rbase(S + 1) <= 32, "validity bits of every level's chunks in one word");
+    constexpr int N0 = G::size(0), C0 = G::chunks(0), RX0 = G::rx(0);
+    constexpr int NO = G::size(S), CO = G::chunks(S);
+    constexpr int RXl = G::rx(S - 1), Nl = G::size(S - 1);
+    constexpr int NP = KC ? 1 : G::pbase(S + 1), CP = G::rbase(S + 1);
+    __shared__ AT ring[G::base(S)];
+    __shared__ AT tab[KC ? ND : kMaxPatEntries];
+    __shared__ int16_t pats[2][NP];  // iteration j uses pats[j % 2] (the last level reads it after the last barrier)
+    const int tid = threadIdx.x;
+    const int t = remap_tile(blockIdx.x, a.ntiles, remap);
+    const int x0 = (t % a.ntx) * TX, y0 = ((t / a.ntx) % a.nty) * TY, m0 = (t / (a.ntx * a.nty)) * a.cz;
+    const int m1 = min(m0 + a.cz, a.gm);
+    const int gx = a.gx, gy = a.gy, gm = a.gm;
+    const long P = (long)gx * gy;
+    const int nit = (m1 - m0) + 2 * S;
+    if constexpr (KC) {
+        if (tid < ND) tab[tid] = (AT)ptab[a.pint * ND + tid];
+    } else {
+        for (int i = tid; i < nent; i += 256) tab[i] = (AT)ptab[i];
+    }
+    // iteration-invariant indices of this thread's points
+    MarchIdx<ND, S, TX, TY> ix;
+    ix.inb = 0u;
+    int off0[C0], offp[CP];
+#pragma unroll
+    for (int k = 0; k < C0; ++k) {
+        const int c = tid + k * 256, lx = c % RX0, ly = c / RX0;
+        const int px = x0 - S + lx, py = ND == 7 ? y0 - S + ly : 0;
+        off0[k] = c < N0 && px >= 0 && px < gx && py >= 0 && py < gy ? px + gx * py : -1;
+    }
+#pragma unroll
+    for (int l = 1; l <= S; ++l) {
+        const int RX = G::rx(l), RXs = G::rx(l - 1), N = G::size(l);
+#pragma unroll
+        for (int k = 0; k < G::chunks(l); ++k) {
+            const int c = tid + k * 256, lx = c % RX, ly = c / RX, r = G::rbase(l) + k;
+            const int px = x0 - (S - l) + lx, py = ND == 7 ? y0 - (S - l) + ly : 0;
+            const bool in = c < N && px >= 0 && px < gx && py >= 0 && py < gy;
+            ix.q[r] = ND == 7 ? (lx + 1) + RXs * (ly + 1) : lx + 1;
+            ix.qa[r] = l >= 2 ? (ND == 7 ? (lx + 2) + G::rx(l - 2) * (ly + 2) : lx + 2) : 0;
+            ix.inb |= (in ? 1u : 0u) << r;
+            offp[r] = in ? px + gx * py : -1;
+        }
+    }
+    // What iteration j reads from global memory (the input plane, the
+    // pattern ids of every level's plane and the final vector on the tile)
+    // is loaded during iteration j - D, into a FIFO of D register sets: with
+    // few workgroups per CU one plane in flight does not cover the latency.
+    AT pre[D][C0], vf[D][CO];
+    int pid[D][KC ? 1 : CP];
+    auto prefetch = [&](int j, AT *pr, int *pi, AT *vv) {
+        const int pm = m0 - S + j;
+        const bool pl0 = j < nit && pm >= 0 && pm < gm;
+#pragma unroll
+        for (int k = 0; k < C0; ++k) pr[k] = pl0 && off0[k] >= 0 ? (AT)ldx(a.in, off0[k] + P * pm) : AT(0);
+        if constexpr (!KC) {
+#pragma unroll
+            for (int l = 1; l <= S; ++l) {
+                const int pml = pm - l;
+                const bool pll = j < nit && pml >= 0 && pml < gm;
+#pragma unroll
+                for (int k = 0; k < G::chunks(l); ++k) {
+                    const int r = G::rbase(l) + k;
+                    pi[r] = pll && offp[r] >= 0 ? (int)pbyte[offp[r] + P * pml] : -1;
+                }
+            }
+        }
+        const int pmo = m0 + j - 2 * S;
+        const bool plo = a.vfin && pmo >= m0 && pmo < m1;
+#pragma unroll
+        for (int k = 0; k < CO; ++k) {
+            const int r = G::rbase(S) + k;
+            vv[k] = plo && offp[r] >= 0 ? (AT)ldx(a.vfin, offp[r] + P * pmo) : AT(0);
+        }
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) prefetch(d, pre[d], pid[d], vf[d]);
+    for (int j = 0; j < nit; ++j) {
+        // with two steps the last one reads level 0 as its aux: the slot
+        // written next must not be overwritten before every wave read it
+        if constexpr (S == 2) __syncthreads();
+        AT *r0 = ring + (j % 3) * N0;
+        int16_t *pat = pats[j % 2];
+#pragma unroll
+        for (int k = 0; k < C0; ++k) {
+            const int c = tid + k * 256;
+            if (c < N0) r0[c] = pre[0][k];
+        }
+        if constexpr (!KC) {
+#pragma unroll
+            for (int l = 1; l <= S; ++l) {
+#pragma unroll
+                for (int k = 0; k < G::chunks(l); ++k) {
+                    const int c = tid + k * 256;
+                    if (c < G::size(l)) pat[G::pbase(l) + c] = (int16_t)pid[0][G::rbase(l) + k];
+                }
+            }
+        }
+        AT vcur[CO];
+#pragma unroll
+        for (int k = 0; k < CO; ++k) vcur[k] = vf[0][k];
+        // advance the FIFO and load what iteration j + D reads
+#pragma unroll
+        for (int d = 0; d + 1 < D; ++d) {
+#pragma unroll
+            for (int k = 0; k < C0; ++k) pre[d][k] = pre[d + 1][k];
+            if constexpr (!KC) {
+#pragma unroll
+                for (int k = 0; k < CP; ++k) pid[d][k] = pid[d + 1][k];
+            }
+#pragma unroll
+            for (int k = 0; k < CO; ++k) vf[d][k] = vf[d + 1][k];
+        }
+        if (j + D < nit) prefetch(j + D, pre[D - 1], pid[D - 1], vf[D - 1]);
+        __syncthreads();
+        march_level<XT, ND, S, TX, TY, KC, 1>(a, ring, tab, pat, ix, j, m0);
+        if (j >= 2 * S) {
+            // the last step on the tile: plane m0 + j - 2S, stored
+            const int pm = m0 + j - 2 * S;
+            const AT *src = ring + G::base(S - 1);
+            const AT *lo = src + ((j + 1) % 3) * Nl, *mid = src + ((j + 2) % 3) * Nl, *hi = src + (j % 3) * Nl;
+            const bool aux = (a.aux >> (S - 1)) & 1;
+            const AT *ax = ring + G::base(S - 2) + ((j + 1) % 3) * G::size(S - 2);
+            const AT c0 = a.a0[S - 1], c1 = a.a1[S - 1], c2 = a.a2[S - 1];
+#pragma unroll
+            for (int k = 0; k < CO; ++k) {
+                const int c = tid + k * 256, r = G::rbase(S) + k;
+                const AT *tp = tab;
+                bool live;
+                if constexpr (KC) {
+                    live = (ix.inb >> r) & 1u;
+                } else {
+                    const int id = c < NO ? (int)pat[G::pbase(S) + c] : -1;
+                    live = id >= 0;
+                    tp = tab + id * ND;
+                }
+                if (live) {
+                    const int q = ix.q[r];
+                    AT w = c0 * march_sum<AT, ND, RXl>(tp, lo, mid, hi, q) + c1 * mid[q];
+                    if (aux) w += c2 * ax[ix.qa[r]];
+                    stx(a.out, offp[r] + P * pm, a.vfin ? vcur[k] - w : w);
+                }
+            }
+        }
+    }
+}
+
+template <typename VT, typename XT, int ND, int S, int TX, int TY>
+hipError_t march_launch(const DevCSR &A, const VT *ptab, const MarchPtrs &p, int cz, int remap, hipStream_t st) {
+    using AT = typename Arith<XT>::T;
+    MarchArgs<XT> a;
+    a.in = (const XT *)p.in;
+    a.out = (XT *)p.out;
+    a.vfin = (const XT *)p.vfin;
+    for (int k = 0; k < kMarchMax; ++k) {
+        a.a0[k] = (AT)p.a0[k];
+        a.a1[k] = (AT)p.a1[k];
+        a.a2[k] = (AT)p.a2[k];
+    }
+    a.aux = p.aux;
+    a.gx = A.box[0];
+    a.gy = ND == 7 ? A.box[1] : 1;
+    a.gm = ND == 7 ? A.box[2] : A.box[1];
+    a.ntx = (a.gx + TX - 1) / TX;
+    a.nty = (a.gy + TY - 1) / TY;
+    a.cz = cz;
+    const long nch = (a.gm + cz - 1) / cz;
+    const long nt = (long)a.ntx * a.nty * nch;
+    if (nt == 0) return hipSuccess;
+    if (nt >= (1L << 31)) return hipErrorInvalidValue;
+    a.ntiles = (int)nt;
+    a.pint = A.box_pint;
+    if (A.box_pint < 0)
+        hipLaunchKernelGGL((k_chain_march<VT, XT, ND, S, TX, TY, false, 1>), dim3((unsigned)nt), dim3(256), 0, st, a,
+                           A.pbyte, ptab, A.npat * ND, remap);
+    else if (p.depth == 3)
+        hipLaunchKernelGGL((k_chain_march<VT, XT, ND, S, TX, TY, true, 3>), dim3((unsigned)nt), dim3(256), 0, st, a,
+                           A.pbyte, ptab, A.npat * ND, remap);
+    else if (p.depth == 2)
+        hipLaunchKernelGGL((k_chain_march<VT, XT, ND, S, TX, TY, true, 2>), dim3((unsigned)nt), dim3(256), 0, st, a,
+                           A.pbyte, ptab, A.npat * ND, remap);
+    else
+        hipLaunchKernelGGL((k_chain_march<VT, XT, ND, S, TX, TY, true, 1>), dim3((unsigned)nt), dim3(256), 0, st, a,
+                           A.pbyte, ptab, A.npat * ND, remap);
+    return hipGetLastError();
+}
+
+template <typename VT, typename XT, int ND, int TX, int TY>
+hipError_t march_dispatch(const DevCSR &A, const VT *ptab, const MarchPtrs &p, int cz, int remap, hipStream_t st) {
+    switch (p.nsteps) {
+        case 2:
+            return march_launch<VT, XT, ND, 2, TX, TY>(A, ptab, p, cz, remap, st);
+        case 3:
+            return march_launch<VT, XT, ND, 3, TX, TY>(A, ptab, p, cz, remap, st);
+        case 4:
+            return march_launch<VT, XT, ND, 4, TX, TY>(A, ptab, p, cz, remap, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename VT, typename XT>
 ChainArgs<VT, XT> chain_args(const DevCSR &A, const VT *val, const StepPtrs &s) {
     using AT = typename Arith<XT>::T;
@@ -2026,6 +2380,36 @@ hipError_t launch_chain_pair(const DevCSR &A, int prec, const PairPtrs &p, int r
                                  : pair_launch<float, float, 5, 64, 32, 1>(A, A.ptab32, p, remap, st);
     }
     return hipErrorInvalidValue;
+}
+
+// x-y tile (x tile in 2-D) of the marching kernel
+constexpr int kMarchTX3 = 64, kMarchTY3 = 4, kMarchTX2 = 256;
+
+hipError_t launch_chain_march(const DevCSR &A, int prec, const MarchPtrs &p, int cz, int remap, hipStream_t st) {
+    if (!A.pbyte || !p.in || !p.out || (A.box_nd != 5 && A.box_nd != 7) || A.npat * A.box_nd > kMaxPatEntries ||
+        (long)A.box[0] * A.box[1] * A.box[2] != A.n || p.out == p.in || p.out == p.vfin || p.nsteps < 2 ||
+        p.nsteps > kMarchMax || (p.aux & 1) || cz < 1 || (A.box_nd == 5 && A.box[2] != 1))
+        return hipErrorInvalidValue;
+    switch (prec) {
+        case 0:
+            return A.box_nd == 7 ? march_dispatch<double, double, 7, kMarchTX3, kMarchTY3>(A, A.ptab64, p, cz, remap, st)
+                                 : march_dispatch<double, double, 5, kMarchTX2, 1>(A, A.ptab64, p, cz, remap, st);
+        case 1:
+            return A.box_nd == 7 ? march_dispatch<float, float, 7, kMarchTX3, kMarchTY3>(A, A.ptab32, p, cz, remap, st)
+                                 : march_dispatch<float, float, 5, kMarchTX2, 1>(A, A.ptab32, p, cz, remap, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+int march_default_cz(const DevCSR &A, int target) {
+    const int nd = A.box_nd;
+    const long gx = A.box[0], gy = nd == 7 ? A.box[1] : 1, gm = nd == 7 ? A.box[2] : A.box[1];
+    const long tiles = nd == 7 ? ((gx + kMarchTX3 - 1) / kMarchTX3) * ((gy + kMarchTY3 - 1) / kMarchTY3)
+                               : (gx + kMarchTX2 - 1) / kMarchTX2;
+    if (gm <= 0 || tiles <= 0) return 1;
+    long cz = gm;
+    while (cz > 4 && tiles * ((gm + cz - 1) / cz) < target) cz = (cz + 1) / 2;
+    return (int)std::max(1L, cz);
 }
 
 int dot_blocks(int n) { return (int)blocks_for(n, kDotRows); }

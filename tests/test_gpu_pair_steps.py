@@ -39,15 +39,28 @@ def _wrapped(nx, ny, nz):
     return CSR(n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
 
 
+def _varcoef(csr, classes=3):
+    # row r's entries scaled by 1 + 0.1 (r mod classes): a box stencil whose
+    # rows are not one interior row truncated at the box (variable coefficients)
+    rows = np.repeat(np.arange(csr.n), np.diff(csr.rowptr))
+    return csr.with_values(csr.val * (1.0 + 0.1 * (rows % classes)))
+
+
 def _cases():
     # box sides that leave partial tiles in every direction (3-D tiles 32 x 8 x 8
-    # and 32 x 8 x 4, 2-D tiles 64 x 32)
+    # and 32 x 8 x 4, 2-D tiles 64 x 32; marching tiles 64 x 4 and 256)
     return {
         "box3d_37x11x10": (convdiff3d_box(37, 11, 10, 10.0, 5.0, 2.0), (37, 11, 10), 12),
         "convdiff3d_20": (convdiff3d(20, 10, 10, 10), (20, 20, 20), 12),
         "convdiff2d_70": (convdiff2d(70, 5.0), (70, 70, 1), 12),
         "box3d_9x7x33": (convdiff3d_box(9, 7, 33, 1.0, 1.0, 1.0), (9, 7, 33), 6),
+        "varcoef3d_21x13x11": (_varcoef(convdiff3d_box(21, 13, 11, 3.0, 2.0, 1.0)), (21, 13, 11), 8),
+        "varcoef2d_300x17": (_varcoef(convdiff3d_box(300, 17, 1, 3.0, 2.0, 0.0)), (300, 17, 1), 8),
     }
+
+
+# constant-coefficient stencils (every row the interior row's stencil truncated at the box)
+CONSTANT = {"box3d_37x11x10", "convdiff3d_20", "convdiff2d_70", "box3d_9x7x33"}
 
 
 def test_box_geometry_detected(pp):
@@ -156,6 +169,22 @@ def test_pair_steps_full_size(pp):
     v = rhs(csr.n, 5)
     say("pair steps 128^3")
     box = (128, 128, 128)
+    for steps in (2, 3, 4):
+        # several steps per marching launch on the full-size grid
+        for kind, fn in [("phi", chains.apply_phi), ("pi", chains.apply_pi)]:
+            ref = fn(A, P.units, v)
+            say("march 128^3", kind, steps)
+            M.set_march(steps, "fp64")
+            assert_close(host(pp.apply(poly, M, dev(v), kind)), ref, 1e-12, f"128^3 {kind} march {steps}", box)
+            M.set_march(steps, "fp32")
+            got32 = host(pp.apply(poly, M, dev(v, torch.float32), kind))
+            emu = apply_phi_low(A.astype(np.float32), P.units, v.astype(np.float32), "fp32")
+            ref_phi = chains.apply_phi(A, P.units, v)
+            for idx in (None, box_face_rows(*box), tail_rows(csr.n)):
+                err = maxerr(v.astype(np.float32) - got32, ref_phi, idx) if kind == "pi" else maxerr(got32, ref, idx)
+                assert err <= 10 * maxerr(emu, ref_phi, idx) + 1e-6
+            M.set_march(0, "fp64")
+            M.set_march(0, "fp32")
     for kind, fn in [("p", chains.apply_p), ("phi", chains.apply_phi)]:
         ref = fn(A, P.units, v)
         M.set_pair_steps(True, "fp64")
@@ -166,3 +195,77 @@ def test_pair_steps_full_size(pp):
         emu = flow(A.astype(np.float32), P.units, v.astype(np.float32), "fp32")
         for idx in (None, box_face_rows(*box), tail_rows(csr.n)):
             assert maxerr(got32, ref, idx) <= 10 * maxerr(emu, ref, idx) + 1e-6
+
+
+# ---------------------------------------------------------------------------
+# several steps per launch, marching along the grid
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("steps", [2, 3, 4])
+@pytest.mark.parametrize("name", list(_cases()))
+def test_march_matches_oracle(pp, name, steps):
+    # phi and pi chains (real roots, conjugate pairs, added copies) with up to
+    # `steps` steps per marching launch, on boxes whose sides leave partial
+    # tiles, with the default chunk of planes and with 5 planes (a ragged
+    # last chunk): element-wise against the oracle, and against single
+    # launches up to rounding order; p chains (their steps carry the
+    # accumulator) run unfused and must be unchanged
+    csr, box, d = _cases()[name]
+    A = csr.to_scipy()
+    A32 = A.astype(np.float32)
+    v = rhs(csr.n, 5)
+    v32 = v.astype(np.float32)
+    for pname, P, poly in _polys(pp, A, csr.n, d):
+        M = pp.Matrix.from_csr(csr)
+        assert M.constant_stencil() == (name in CONSTANT)
+        for prec in ("fp64", "fp32"):
+            M.tune(prec)
+            M.set_pair_steps(False, prec)
+        ref_phi = chains.apply_phi(A, P.units, v)
+        for kind, fn in [("phi", chains.apply_phi), ("pi", chains.apply_pi), ("p", chains.apply_p)]:
+            ref = fn(A, P.units, v)
+            emu = (apply_p_low if kind == "p" else apply_phi_low)(A32, P.units, v32, "fp32")
+            for prec in ("fp64", "fp32"):
+                M.set_march(0, prec)
+            single64 = host(pp.apply(poly, M, dev(v), kind))
+            # default chunk, 5 planes (a ragged last chunk), and 1 to 3 planes
+            # of loads in flight (the deeper prefetch runs on constant stencils)
+            for cz, depth in ((0, 1), (5, 3), (0, 2)):
+                say("march", name, pname, kind, steps, cz, depth)
+                for prec in ("fp64", "fp32"):
+                    M.set_march(steps, prec, cz, depth)
+                assert M.march("fp64")[0] == steps
+                g64 = host(pp.apply(poly, M, dev(v), kind))
+                g32 = host(pp.apply(poly, M, dev(v32, torch.float32), kind))
+                assert_close(g64, ref, 1e-12, f"{name} {pname} {kind} march {steps} cz {cz}", box)
+                assert_close(g64, single64, 1e-14, "march vs single launches", box)
+                for idx in (None, box_face_rows(*box), tail_rows(csr.n)):
+                    delta = maxerr(emu, ref if kind == "p" else ref_phi, idx)
+                    err32 = maxerr(v32 - g32, ref_phi, idx) if kind == "pi" else maxerr(g32, ref, idx)
+                    assert err32 <= 10 * delta + 1e-6, (kind, cz, depth, err32, delta)
+
+
+def test_march_chain_bytes_and_launches(pp):
+    # phi(A)v of 8 real roots, 4 steps per launch: 2 launches, each reading
+    # its input and the pattern bytes once and writing its result; the last
+    # also reads the final vector: 2 F + 5 n s bytes
+    csr = convdiff3d(20, 10, 10, 10)
+    M = pp.Matrix.from_csr(csr)
+    n = csr.n
+    poly = pp.poly_from_roots(np.linspace(2.0, 9.0, 8), keep_order=True)
+    for prec, sv, sx in (("fp64", 8, 8), ("fp32", 4, 4)):
+        M.tune(prec)
+        M.set_pair_steps(False, prec)
+        M.set_march(4, prec)
+        F = n + 27 * 7 * sv
+        say("march bytes", prec)
+        assert pp.chain_bytes(poly, M, "phi", prec) == (2 * F + 5 * n * sx, 2)
+        M.set_march(3, prec)  # groups of 3, 3 and 2
+        assert pp.chain_bytes(poly, M, "phi", prec)[1] == 3
+        M.set_variant(prec, 27, 1)  # a forced variant turns marching off
+        assert M.march(prec)[0] == 0
+        assert pp.chain_bytes(poly, M, "phi", prec)[1] == 8
+    with pytest.raises(Exception, match="box stencil"):
+        Mr = pp.Matrix.from_csr(randsparse(5000, 8, seed=3))
+        Mr.tune("fp64")
+        Mr.set_march(2, "fp64")
