@@ -86,10 +86,16 @@ typedef struct {
                             the current residual, and uses it for that cycle's phi and p; the
                             polynomial argument of pp_solve may then be NULL. 0: off */
     int new_poly_add;    /* ChPoly: add roots for stability (Algorithm 2) */
-    int graphs;          /* pp_batch_solve: 1 = capture each Arnoldi step's device work (chain,
-                            Gram-Schmidt, flag and Hessenberg copies) once per step index and
-                            precision into a HIP graph and replay it in later cycles; 0 = launch
-                            eagerly. Same results either way. Ignored by pp_solve. */
+    int graphs;          /* pp_batch_solve: 1 = capture the device work of a restart cycle (the
+                            Arnoldi steps with their chains, Gram-Schmidt and the Givens updates
+                            of every pair, then the correction and the true residual), per
+                            segment of graph_steps steps and per precision, into HIP graphs and
+                            replay them in later cycles; 0 = launch the same work eagerly. Same
+                            results either way. Ignored by pp_solve. */
+    int graph_steps;     /* pp_batch_solve: the cycle runs in segments of this many Arnoldi steps
+                            (each a graph with opts->graphs); between segments the host reads one
+                            flag and skips the rest of the cycle once every pair has stopped.
+                            0 = the whole cycle as one segment. Ignored by pp_solve. */
 } pp_solve_opts;
 
 /* Result of pp_solve. */
@@ -436,6 +442,26 @@ pp_status pp_batch_set_values(pp_batch B, const double *val, void *stream);
  * of; pp_batch_format writes the current one (host int). */
 pp_status pp_batch_set_format(pp_batch B, int format);
 pp_status pp_batch_format(pp_batch B, int *format);
+
+/* The batched autotuner: one chain step over the whole batch is timed, on
+ * the batch's own matrix, precision (PP_F64/PP_F32/PP_BF16S) and nrhs (1, 2
+ * or 4), for each storage format the batch has (only the one set by
+ * pp_batch_set_format, if it was called), 1 or 2 64-row slices per wave
+ * (pattern-coded format) and the workgroup order (consecutive slices on one
+ * XCD, or not); the fastest is kept for that precision and nrhs. Runs by
+ * itself in the first pp_batch_solve of a (precision, nrhs);
+ * pp_batch_set_values and pp_batch_set_format clear it.
+ *   pp_batch_chain_config: the shape in use (tuned, or the default:
+ *     pp_batch_format's format, 1 slice per wave, XCD order on): *format
+ *     (host) 0 sliced-ELL or 1 pattern-coded; spw, remap, us (host, may be
+ *     NULL) slices per wave, XCD order, tuned microseconds per step (0 if not
+ *     tuned).
+ *   pp_batch_set_chain_config: use this shape for (prec, nrhs) instead of
+ *     tuning (format 0 or 1, spw 1 or 2 with format 1 only, remap 0 or 1);
+ *     PP_EINVAL for a format the batch has no copy of. */
+pp_status pp_batch_tune(pp_batch B, int prec, int nrhs, void *stream);
+pp_status pp_batch_set_chain_config(pp_batch B, int prec, int nrhs, int format, int spw, int remap);
+pp_status pp_batch_chain_config(pp_batch B, int prec, int nrhs, int *format, int *spw, int *remap, double *us);
 
 void pp_batch_destroy(pp_batch B);
 

@@ -33,7 +33,7 @@ class StchOpts(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("m", c_int), ("max_cycles", c_int), ("tol", c_double), ("inner", c_int),
                 ("stall_cycles", c_int), ("inner_eta", c_double), ("history", P_double), ("history_cap", c_int),
-                ("new_poly_degree", c_int), ("new_poly_add", c_int), ("graphs", c_int)]
+                ("new_poly_degree", c_int), ("new_poly_add", c_int), ("graphs", c_int), ("graph_steps", c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -84,6 +84,9 @@ SIGNATURES = {
     "pp_block_jacobi": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pp_matrix_right_blocks": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     "pp_batch_format": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
+    "pp_batch_tune": (c_int, [c_void_p, c_int, c_int, c_void_p]),
+    "pp_batch_set_chain_config": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int]),
+    "pp_batch_chain_config": (c_int, [c_void_p, c_int, c_int, P_int, P_int, P_int, P_double]),
     "pp_batch_destroy": (None, [c_void_p]),
     "pp_batch_setup": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p),
                                ctypes.POINTER(SetupInfo)]),

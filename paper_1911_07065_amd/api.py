@@ -587,9 +587,12 @@ class Batch:
         return out
 
     def solve(self, polys, b, R: int, tol: float = 1e-8, m: int = 50, max_cycles: int = 1000, inner: str = "fp32",
-              stall_cycles: int = 5, inner_eta: float = 0.0, graphs: bool = True):
+              stall_cycles: int = 5, inner_eta: float = 0.0, graphs: bool = True, graph_steps: int = 5):
         """x for every (system, rhs) pair; b interleaved (n*R). Returns (x, list of info dicts per pair).
-        graphs: capture each Arnoldi step into a HIP graph once and replay it in later cycles."""
+        graphs: capture each restart cycle's device work, in segments of graph_steps Arnoldi
+        steps (0: the whole cycle), into HIP graphs once per precision and replay them in
+        later cycles (the same results as eager launches); between segments the host skips
+        the rest of a cycle once every pair has stopped."""
         b = _dev_tensor(b, torch.float64, self.device)
         if b.numel() != self.n * R:
             raise ValueError("right-hand side length")
@@ -597,7 +600,8 @@ class Batch:
         hs = (ctypes.c_void_p * self.nsys)(*[p.handle.value for p in polys])
         hist = np.zeros(max(int(max_cycles), 0) + 2)
         opts = SolveOpts(int(m), int(max_cycles), float(tol), PREC[inner], int(stall_cycles), float(inner_eta),
-                         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hist.size, 0, 1, int(bool(graphs)))
+                         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hist.size, 0, 1, int(bool(graphs)),
+                         int(graph_steps))
         P = self.nsys * R
         infos = (SolveInfo * P)()
         check(lib.pp_batch_solve(self.handle, hs, int(R), _ptr(b), _ptr(x), ctypes.byref(opts), _stream(self.device),
@@ -620,6 +624,23 @@ class Batch:
 
     def set_format(self, name: str):
         check(lib.pp_batch_set_format(self.handle, self.BATCH_FORMATS.index(name)), "pp_batch_set_format")
+
+    def tune(self, R: int, prec: str = "fp32"):
+        """Run the batched autotuner for (prec, R) now; returns chain_config(R, prec)."""
+        check(lib.pp_batch_tune(self.handle, PREC[prec], int(R), _stream(self.device)), "pp_batch_tune")
+        return self.chain_config(R, prec)
+
+    def set_chain_config(self, R: int, prec: str, fmt: str, spw: int = 1, remap: int = 1):
+        """Force the chain kernel's shape for (prec, R) instead of tuning."""
+        check(lib.pp_batch_set_chain_config(self.handle, PREC[prec], int(R), self.BATCH_FORMATS.index(fmt), int(spw),
+                                            int(remap)), "pp_batch_set_chain_config")
+
+    def chain_config(self, R: int, prec: str = "fp32"):
+        """(format name, slices per wave, XCD order, tuned us per step) of the chain kernel in use."""
+        f, spw, rm, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        check(lib.pp_batch_chain_config(self.handle, PREC[prec], int(R), ctypes.byref(f), ctypes.byref(spw),
+                                        ctypes.byref(rm), ctypes.byref(us)), "pp_batch_chain_config")
+        return self.BATCH_FORMATS[f.value], spw.value, rm.value, us.value
 
     def set_values(self, val):
         """New values (device or host float64[nnz], the concatenated systems'

@@ -83,8 +83,94 @@ struct pp_batch_s {
     int *actpin = nullptr;  // pinned mirror
     int *kdev = nullptr;    // device: columns per pair of the last cycle
     int *kpin = nullptr;
-    BatchSell sell(int, bool masked = false) const {
+    // device least squares of every pair (see BGivens), its per-cycle inputs
+    // (beta | target | 1/beta per pair, run flags) and outputs (steps, last
+    // shortcut residual), staged through pinned memory
+    double *gR = nullptr, *gc = nullptr, *gs = nullptr, *gg = nullptr, *gfro = nullptr, *gsc = nullptr;
+    double *gin = nullptr, *ginpin = nullptr, *gscpin = nullptr;
+    int *grun = nullptr, *gsteps = nullptr, *grunpin = nullptr, *gstepspin = nullptr;
+    int *gany = nullptr, *ganypin = nullptr;  // some pair still runs (device, pinned mirror)
+    int gm = -1, gpairs = 0;
+    void free_givens() {
+        dev_free(gR);
+        dev_free(gc);
+        dev_free(gs);
+        dev_free(gg);
+        dev_free(gfro);
+        dev_free(gsc);
+        dev_free(gin);
+        dev_free(grun);
+        dev_free(gsteps);
+        dev_free(gany);
+        if (ganypin) (void)hipHostFree(ganypin);
+        ganypin = nullptr;
+        if (ginpin) (void)hipHostFree(ginpin);
+        if (gscpin) (void)hipHostFree(gscpin);
+        if (grunpin) (void)hipHostFree(grunpin);
+        if (gstepspin) (void)hipHostFree(gstepspin);
+        ginpin = gscpin = nullptr;
+        grunpin = gstepspin = nullptr;
+        gm = -1;
+        gpairs = 0;
+    }
+    pp_status ensure_givens(int m, int R) {
+        const int pairs = nsys * R;
+        if (gm == m && gpairs == pairs) return PP_OK;
+        free_givens();
+        PP_TRY(dev_alloc(&gR, (size_t)pairs * (m + 1) * m));
+        PP_TRY(dev_alloc(&gc, (size_t)pairs * m));
+        PP_TRY(dev_alloc(&gs, (size_t)pairs * m));
+        PP_TRY(dev_alloc(&gg, (size_t)pairs * (m + 1)));
+        PP_TRY(dev_alloc(&gfro, (size_t)pairs));
+        PP_TRY(dev_alloc(&gsc, (size_t)pairs));
+        PP_TRY(dev_alloc(&gin, (size_t)3 * pairs));
+        PP_TRY(dev_alloc(&grun, (size_t)pairs));
+        PP_TRY(dev_alloc(&gsteps, (size_t)pairs));
+        PP_TRY(dev_alloc(&gany, 1));
+        if (hipHostMalloc((void **)&ginpin, sizeof(double) * 3 * pairs, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&ganypin, sizeof(int), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&gscpin, sizeof(double) * pairs, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&grunpin, sizeof(int) * pairs, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&gstepspin, sizeof(int) * pairs, hipHostMallocDefault) != hipSuccess) {
+            set_error("hipHostMalloc failed");
+            return PP_ENOMEM;
+        }
+        gm = m;
+        gpairs = pairs;
+        return PP_OK;
+    }
+    BGivens givens(int R) const {
+        BGivens G;
+        G.Rm = gR;
+        G.c = gc;
+        G.s = gs;
+        G.g = gg;
+        G.fro2 = gfro;
+        G.target = gin + gpairs;
+        G.sc = gsc;
+        G.run = grun;
+        G.k = kdev;
+        G.steps = gsteps;
+        G.act = act;
+        G.m = gm;
+        G.R = R;
+        G.nsys = nsys;
+        return G;
+    }
+    // launch shape of the chain kernels per precision and right-hand-side
+    // count, chosen by tune_bchain (format: 0 sliced-ELL, 1 pattern-coded)
+    struct ChainCfg {
+        int tuned = 0, format = 0, spw = 1, remap = 1;
+        double us = 0.0;
+    };
+    ChainCfg cfg[3][5];
+    bool format_forced = false;  // pp_batch_set_format: the tuner keeps the format
+    BatchSell sell(int prec, bool masked = false, int R = 1) const {
+        const ChainCfg &c = cfg[prec][R];
+        const int fmt = (c.tuned && !format_forced && (c.format == 0 || pnd > 0)) ? c.format : format;
         BatchSell s;
+        s.spw = c.tuned ? c.spw : 1;
+        s.remap = c.tuned ? c.remap : 1;
         s.active = masked ? act : ones;
         s.slice = slice;
         s.sptr = sptr;
@@ -92,7 +178,7 @@ struct pp_batch_s {
         s.sval64 = sval64;
         s.sval32 = sval32;
         s.nslices = nslices;
-        const bool pat = format == 1;
+        const bool pat = fmt == 1 && pnd > 0;
         s.bpat = pat ? bpat : nullptr;
         s.poff = pat ? poff : nullptr;
         s.ptoff = pat ? ptoff : nullptr;
@@ -190,6 +276,7 @@ struct pp_batch_s {
             (void)hipStreamDestroy(gstream);
         }
         if (gevent) (void)hipEventDestroy(gevent);
+        free_givens();
         for (auto &w : ws) free_ws(w);
         dev_free(slice);
         dev_free(sptr);
@@ -275,7 +362,63 @@ pp_status upload_programs(pp_batch B, const pp_poly *polys, int kind, PStep **ds
 pp_status run_bprog(pp_batch B, int prec, int R, const PStep *desc, int K, const void *in, void *out,
                     const BWork &w, hipStream_t st, bool masked = false) {
     void *bufs[5] = {(void *)in, out, w.P(0), w.P(1), w.P(2)};
-    for (int k = 0; k < K; ++k) HIP_TRY(launch_bchain(B->sell(prec, masked), prec, R, desc, K, k, bufs, st));
+    for (int k = 0; k < K; ++k) HIP_TRY(launch_bchain(B->sell(prec, masked, R), prec, R, desc, K, k, bufs, st));
+    return PP_OK;
+}
+
+// The batched autotuner: one sparse product over the whole batch (every
+// system active) is timed for each storage format the batch has (unless the
+// caller fixed it), slices per wave (1 or 2, pattern-coded format) and
+// workgroup order (XCD-aware or not), on the batch's own matrix, precision
+// and right-hand-side count; the fastest is kept for (prec, R).
+pp_status tune_bchain(pp_batch B, int prec, int R, hipStream_t st) {
+    PP_TRY(B->ensure(prec, std::max(B->ws[prec].m, 1), R));
+    const BWork &w = B->ws[prec];
+    HIP_TRY(hipMemsetAsync(w.P(0), 0, (size_t)w.vec, st));
+    void *bufs[5] = {w.P(0), w.P(1), w.P(2), w.P(3), w.P(4)};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    pp_batch_s::ChainCfg &c = B->cfg[prec][R];
+    pp_batch_s::ChainCfg best;
+    best.us = 1e30;
+    const int reps = 5;
+    for (int fmt = 1; fmt >= 0; --fmt) {
+        if (fmt == 1 && B->pnd == 0) continue;
+        if (B->format_forced && fmt != B->format) continue;
+        for (int spw = 1; spw <= (fmt == 1 ? 2 : 1); ++spw)
+            for (int remap = 0; remap <= 1; ++remap) {
+                c.tuned = 1;
+                c.format = fmt;
+                c.spw = spw;
+                c.remap = remap;
+                const BatchSell S = B->sell(prec, false, R);
+                double t = 1e30;
+                for (int round = 0; round < 2; ++round) {
+                    for (int i = 0; i < 2; ++i) HIP_TRY(launch_bchain(S, prec, R, B->desc_spmv, 1, 0, bufs, st));
+                    HIP_TRY(hipEventRecord(e0, st));
+                    for (int i = 0; i < reps; ++i) HIP_TRY(launch_bchain(S, prec, R, B->desc_spmv, 1, 0, bufs, st));
+                    HIP_TRY(hipEventRecord(e1, st));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    t = std::min(t, 1e3 * ms / reps);
+                }
+                if (t < best.us) {
+                    best = c;
+                    best.us = t;
+                }
+            }
+    }
+    c = best;
+    c.tuned = 1;
     return PP_OK;
 }
 
@@ -589,7 +732,10 @@ pp_status pp_batch_set_values(pp_batch B, const double *val, void *stream) {
         // the patterns describe the old values
         (void)hipStreamSynchronize(S(stream));
         B->drop_patterns();
+        B->format_forced = false;
     }
+    for (auto &row : B->cfg)
+        for (auto &c : row) c.tuned = 0;
     HIP_TRY(launch_sell_values(B->npad, B->sperm, val, B->sval64, B->sval32, S(stream)));
     return PP_OK;
 }
@@ -605,6 +751,52 @@ pp_status pp_batch_set_format(pp_batch B, int format) {
         return PP_EINVAL;
     }
     B->format = format;
+    B->format_forced = true;
+    for (auto &row : B->cfg)
+        for (auto &c : row) c.tuned = 0;
+    return PP_OK;
+}
+
+pp_status pp_batch_tune(pp_batch B, int prec, int nrhs, void *stream) {
+    if (!B || prec < 0 || prec > 2 || !(nrhs == 1 || nrhs == 2 || nrhs == 4)) {
+        set_error("pp_batch_tune: bad argument");
+        return PP_EINVAL;
+    }
+    PP_TRY(tune_bchain(B, prec, nrhs, S(stream)));
+    return PP_OK;
+}
+
+pp_status pp_batch_set_chain_config(pp_batch B, int prec, int nrhs, int format, int spw, int remap) {
+    if (!B || prec < 0 || prec > 2 || !(nrhs == 1 || nrhs == 2 || nrhs == 4) || format < 0 || format > 1 ||
+        spw < 1 || spw > 2 || remap < 0 || remap > 1 || (format == 0 && spw != 1)) {
+        set_error("pp_batch_set_chain_config: bad argument (spw 2 only with the pattern-coded format)");
+        return PP_EINVAL;
+    }
+    if (format == 1 && !B->bpat) {
+        set_error("pp_batch_set_chain_config: no pattern-coded copy");
+        return PP_EINVAL;
+    }
+    pp_batch_s::ChainCfg &c = B->cfg[prec][nrhs];
+    c.tuned = 1;
+    c.format = format;
+    c.spw = spw;
+    c.remap = remap;
+    c.us = 0.0;
+    B->format_forced = false;
+    return PP_OK;
+}
+
+pp_status pp_batch_chain_config(pp_batch B, int prec, int nrhs, int *format, int *spw, int *remap, double *us) {
+    if (!B || prec < 0 || prec > 2 || !(nrhs == 1 || nrhs == 2 || nrhs == 4) || !format) {
+        set_error("pp_batch_chain_config: bad argument");
+        return PP_EINVAL;
+    }
+    const pp_batch_s::ChainCfg &c = B->cfg[prec][nrhs];
+    const BatchSell S = B->sell(prec, false, nrhs);
+    *format = S.bpat ? 1 : 0;
+    if (spw) *spw = S.spw;
+    if (remap) *remap = S.remap;
+    if (us) *us = c.tuned ? c.us : 0.0;
     return PP_OK;
 }
 
@@ -756,6 +948,7 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
     const long nR = B->n * R;
     PP_TRY(B->ensure_red(m + 1, R));
     PP_TRY(B->ensure(opts->inner, m, R));
+    if (!B->cfg[opts->inner][R].tuned) PP_TRY(tune_bchain(B, opts->inner, R, st));
     const BatchBlocks bl = B->blocks();
     PStep *dphi = nullptr, *dp = nullptr;
     int Kphi = 0, Kp = 0;
@@ -781,21 +974,88 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
     beta = bnorm;
     std::vector<char> done(P, 0), noconv(P, 0);
     std::vector<std::vector<double>> hist(P);
-    std::vector<GivensLS> ls(P);
-    std::vector<int> kp(P, 0);
     int prec = opts->inner;
     int cycles = 0;
-    // captured Arnoldi steps, per precision and step index (this solve only)
-    struct StepGraphs {
-        int m;
+    PP_TRY(B->ensure_givens(m, R));
+    const BGivens G = B->givens(R);
+    double *gbeta = B->gin, *ginv = B->gin + 2 * P;
+    // The device work of one restart cycle runs in segments of `seg`
+    // Arnoldi steps, with no host synchronisation and no memset inside a
+    // segment: the first segment takes the per-pair inputs in (from pinned
+    // memory, read when the copy runs) and forms V0 = r / beta; every step
+    // runs the phi chain, CGS2 and the Givens update of every running pair
+    // (the masked kernels skip systems whose pairs have all stopped); each
+    // segment ends by copying out whether some pair still runs, and the host
+    // skips the rest of the cycle when none does. The tail forms z, the
+    // correction x += p(A) V z and the true FP64 residual, and copies the
+    // per-pair results out. With opts->graphs each segment and the tail are
+    // captured once per precision into HIP graphs and replayed.
+    const int seg = opts->graph_steps > 0 ? std::min(opts->graph_steps, m) : m;
+    const int nseg = (m + seg - 1) / seg;
+    auto segment_work = [&](int pr, int c) -> pp_status {
+        const BWork &w = B->ws[pr];
+        if (c == 0) {
+            HIP_TRY(hipMemcpyAsync(B->gin, B->ginpin, sizeof(double) * 3 * P, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(B->grun, B->grunpin, sizeof(int) * P, hipMemcpyHostToDevice, st));
+            HIP_TRY(launch_bgivens_init(G, gbeta, st));
+            HIP_TRY(launch_bscale(bl, 0, pr, R, B->r64, ginv, bcol(w, pr, 0), st));
+        }
+        for (int j = c * seg; j < std::min(m, (c + 1) * seg); ++j) {
+            PP_TRY(run_bprog(B, pr, R, dphi, Kphi, bcol(w, pr, j), bcol(w, pr, j + 1), w, st, true));
+            PP_TRY(bcgs2(B, pr, R, w, j, B->Hc, B->ldh, st, true));
+            HIP_TRY(launch_bgivens_step(G, j, B->Hc, B->ldh, kBreakdownTolB, st));
+        }
+        HIP_TRY(launch_bany(B->act, B->nsys, B->gany, st));
+        HIP_TRY(hipMemcpyAsync(B->ganypin, B->gany, sizeof(int), hipMemcpyDeviceToHost, st));
+        return PP_OK;
+    };
+    auto tail_work = [&](int pr) -> pp_status {
+        const BWork &w = B->ws[pr];
+        HIP_TRY(launch_bgivens_solve(G, B->z, B->ldh, st));
+        HIP_TRY(launch_bcombine(bl, pr, R, w.V, w.ldv, B->kdev, B->z, B->ldh, w.P(3), st));
+        PP_TRY(run_bprog(B, pr, R, dp, Kp, w.P(3), w.P(4), w, st));
+        HIP_TRY(launch_axpy_x(pr, (int)nR, 1.0, w.P(4), x, st));
+        {
+            const BWork &w64 = B->ws[0].V ? B->ws[0] : w;
+            void *bufs[5] = {x, B->r64, (void *)b, w64.P(0), w64.P(1)};
+            HIP_TRY(launch_bchain(B->sell(0, false, R), 0, R, B->desc_res, 1, 0, bufs, st));
+        }
+        HIP_TRY(hipMemcpyAsync(B->kpin, B->kdev, sizeof(int) * P, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(B->gstepspin, B->gsteps, sizeof(int) * P, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(B->gscpin, B->gsc, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+        return PP_OK;
+    };
+    // graphs per precision: segments 0 .. nseg-1, then the tail
+    struct CycleGraphs {
         std::vector<hipGraphExec_t> ex;
-        explicit StepGraphs(int m_) : m(m_), ex((size_t)3 * m_, nullptr) {}
-        hipGraphExec_t &at(int p, int j) { return ex[(size_t)p * m + j]; }
-        ~StepGraphs() {
+        ~CycleGraphs() {
             for (auto e : ex)
                 if (e) (void)hipGraphExecDestroy(e);
         }
-    } graphs(m);
+    } graphs;
+    graphs.ex.assign((size_t)3 * (nseg + 1), nullptr);
+    auto run_part = [&](int pr, int part) -> pp_status {
+        auto work = [&]() -> pp_status { return part < nseg ? segment_work(pr, part) : tail_work(pr); };
+        if (!opts->graphs) return work();
+        hipGraphExec_t &ex = graphs.ex[(size_t)pr * (nseg + 1) + part];
+        if (!ex) {
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            const pp_status sw = work();
+            const hipError_t ec = hipStreamEndCapture(st, &g);
+            if (sw != PP_OK) {
+                if (ec == hipSuccess && g) (void)hipGraphDestroy(g);
+                return sw;
+            }
+            HIP_TRY(ec);
+            const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_TRY(ei);
+        }
+        HIP_TRY(hipGraphLaunch(ex, st));
+        return PP_OK;
+    };
+    for (int p = 0; p < P; ++p) B->gscpin[p] = NAN;
     for (;;) {
         int active = 0;
         for (int p = 0; p < P; ++p) {
@@ -817,125 +1077,39 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
         }
         if (active == 0) break;
         ++cycles;
-        if (prec == PP_F64) PP_TRY(B->ensure(0, m, R));
-        const BWork &w = B->ws[prec];
-        // V0 = r / beta for the pairs still running (0 for the others)
+        if (prec == PP_F64) {
+            PP_TRY(B->ensure(0, m, R));
+            if (!B->cfg[0][R].tuned) PP_TRY(tune_bchain(B, 0, R, st));
+        }
+        const double eta = (prec != PP_F64 && opts->inner_eta > 0.0) ? opts->inner_eta : kInnerEtaB[prec];
+        // per-pair inputs of the cycle: beta, the inner target, 1/beta (0 for
+        // pairs that are done) and the run flags
         for (int p = 0; p < P; ++p) {
-            B->zpin[p] = done[p] ? 0.0 : 1.0 / beta[p];
+            B->ginpin[p] = done[p] ? 0.0 : beta[p];
+            B->ginpin[P + p] = std::max(opts->tol * bnorm[p], eta * beta[p]);
+            B->ginpin[2 * P + p] = done[p] ? 0.0 : 1.0 / beta[p];
+            B->grunpin[p] = done[p] ? 0 : 1;
             inf[p].cycles += done[p] ? 0 : 1;
             if (!done[p] && prec == PP_F64) inf[p].fp64_cycles++;
         }
-        HIP_TRY(hipMemcpyAsync(B->inv, B->zpin, sizeof(double) * P, hipMemcpyHostToDevice, st));
-        HIP_TRY(launch_bscale(bl, 0, prec, R, B->r64, B->inv, bcol(w, prec, 0), st));
-        std::vector<char> run(P);
-        for (int p = 0; p < P; ++p) {
-            run[p] = !done[p];
-            kp[p] = 0;
-            if (run[p]) ls[p].reset(m, beta[p]);
-        }
-        const double eta = (prec != PP_F64 && opts->inner_eta > 0.0) ? opts->inner_eta : kInnerEtaB[prec];
-        std::vector<double> fro2(P, 0.0);
-        // systems with no running pair skip the Arnoldi work (their columns
-        // are never combined: z is zero beyond each pair's last step)
-        // the host fills the pinned activity flags; each step copies them to
-        // the device first (read when the copy runs, after the previous
-        // step's synchronisation)
-        auto push_active = [&]() {
-            for (int q = 0; q < B->nsys; ++q) {
-                int a = 0;
-                for (int r = 0; r < R; ++r) a |= run[q * R + r];
-                B->actpin[q] = a;
+        for (int c = 0; c < nseg; ++c) {
+            PP_TRY(run_part(prec, c));
+            if (c + 1 < nseg) {
+                HIP_TRY(hipStreamSynchronize(st));
+                if (!*B->ganypin) break;  // every pair has stopped: the rest of the cycle is skipped
             }
-        };
-        // Device work of Arnoldi step j: flags in, the phi chain, CGS2, the
-        // Hessenberg columns out. With opts->graphs it is captured once per
-        // (precision, j) into a HIP graph and replayed in later cycles; the
-        // work has no synchronisation and no memset, and its arguments
-        // (buffers, programs, column count) are fixed for the solve.
-        auto step_work = [&](int j) -> pp_status {
-            HIP_TRY(hipMemcpyAsync(B->act, B->actpin, sizeof(int) * B->nsys, hipMemcpyHostToDevice, st));
-            PP_TRY(run_bprog(B, prec, R, dphi, Kphi, bcol(w, prec, j), bcol(w, prec, j + 1), w, st, true));
-            PP_TRY(bcgs2(B, prec, R, w, j, B->Hc, B->ldh, st, true));
-            HIP_TRY(hipMemcpyAsync(B->hpin, B->Hc, sizeof(double) * P * B->ldh, hipMemcpyDeviceToHost, st));
-            return PP_OK;
-        };
-        push_active();
-        for (int j = 0; j < m; ++j) {
-            if (opts->graphs) {
-                hipGraphExec_t &ex = graphs.at(prec, j);
-                if (!ex) {
-                    hipGraph_t g = nullptr;
-                    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                    const pp_status sw = step_work(j);
-                    const hipError_t ec = hipStreamEndCapture(st, &g);
-                    if (sw != PP_OK) {
-                        if (ec == hipSuccess && g) (void)hipGraphDestroy(g);
-                        return sw;
-                    }
-                    HIP_TRY(ec);
-                    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-                    (void)hipGraphDestroy(g);
-                    HIP_TRY(ei);
-                }
-                HIP_TRY(hipGraphLaunch(ex, st));
-            } else {
-                PP_TRY(step_work(j));
-            }
-            HIP_TRY(hipStreamSynchronize(st));
-            int still = 0;
-            for (int p = 0; p < P; ++p) {
-                if (!run[p]) continue;
-                const double *h = B->hpin + (size_t)p * B->ldh;
-                bool finite = true;
-                for (int i = 0; i <= j + 1; ++i) {
-                    finite = finite && std::isfinite(h[i]);
-                    fro2[p] += h[i] * h[i];
-                }
-                inf[p].iters++;
-                inf[p].mvps += polys[p / R]->plan.d_eff;
-                inf[p].dots += 2 * (j + 1) + 1;
-                if (!finite) {
-                    run[p] = 0;
-                    continue;
-                }
-                const double sc = ls[p].add_column(h);
-                kp[p] = j + 1;
-                inf[p].relres_shortcut = sc / bnorm[p];
-                const double target = std::max(opts->tol * bnorm[p], eta * beta[p]);
-                if (h[j + 1] <= kBreakdownTolB * std::sqrt(fro2[p]) || sc <= target)
-                    run[p] = 0;
-                else
-                    ++still;
-            }
-            if (still == 0) break;
-            push_active();
         }
-        // z per pair (zero for pairs that did not run)
-        int kmax = 0;
-        for (int p = 0; p < P; ++p) kmax = std::max(kmax, kp[p]);
-        std::vector<double> zp((size_t)P * B->ldh, 0.0);
-        for (int p = 0; p < P; ++p)
-            if (kp[p] > 0) ls[p].solve(zp.data() + (size_t)p * B->ldh);
-        std::memcpy(B->zpin, zp.data(), sizeof(double) * zp.size());
-        for (int p = 0; p < P; ++p) B->kpin[p] = kp[p];
-        HIP_TRY(hipMemcpyAsync(B->z, B->zpin, sizeof(double) * zp.size(), hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(B->kdev, B->kpin, sizeof(int) * P, hipMemcpyHostToDevice, st));
-        if (kmax > 0) {
-            HIP_TRY(launch_bcombine(bl, prec, R, w.V, w.ldv, B->kdev, B->z, B->ldh, w.P(3), st));
-            PP_TRY(run_bprog(B, prec, R, dp, Kp, w.P(3), w.P(4), w, st));
-            HIP_TRY(launch_axpy_x(prec, (int)nR, 1.0, w.P(4), x, st));
-        }
-        // true residual in FP64
-        {
-            const BWork &w64 = B->ws[0].V ? B->ws[0] : w;
-            void *bufs[5] = {x, B->r64, (void *)b, w64.P(0), w64.P(1)};
-            HIP_TRY(launch_bchain(B->sell(0), 0, R, B->desc_res, 1, 0, bufs, st));
-        }
-        PP_TRY(bnorms(B, R, B->r64, beta_new, st));
+        PP_TRY(run_part(prec, nseg));
+        PP_TRY(bnorms(B, R, B->r64, beta_new, st));  // synchronises: the cycle's results are on the host
         bool stalled = false;
         for (int p = 0; p < P; ++p) {
             if (done[p]) continue;
-            inf[p].mvps += polys[p / R]->plan.d_eff;  // p(A) (d_eff - 1) and the residual (1)
+            const int64_t st_p = B->gstepspin[p];
+            const int64_t d_eff = polys[p / R]->plan.d_eff;
+            inf[p].iters += (int)st_p;
+            inf[p].mvps += st_p * d_eff + d_eff;  // the steps' phi chains; p(A) (d_eff - 1) and the residual (1)
+            inf[p].dots += st_p * st_p + 2 * st_p;
+            if (B->kpin[p] > 0) inf[p].relres_shortcut = B->gscpin[p] / bnorm[p];
             if (!(beta_new[p] <= 0.5 * beta[p])) stalled = true;
             beta[p] = beta_new[p];
         }

@@ -36,6 +36,10 @@ struct BatchSell {
     const double *ptab64;
     const float *ptab32;
     int pnd;
+    // launch shape: slices per wave of the pattern-coded kernel (1 or 2) and
+    // the XCD-aware workgroup order (consecutive slices on one XCD) on or off
+    int spw;
+    int remap;
 };
 
 // Rows per reduction block; a block never crosses a system boundary.
@@ -88,5 +92,31 @@ hipError_t launch_bscale(const BatchBlocks &B, int prec_in, int prec_out, int R,
 // out[i*R+r] = sum_j V_j[i*R+r] z[p*ldz + j], j < k[p] (device int per pair)
 hipError_t launch_bcombine(const BatchBlocks &B, int prec, int R, const void *V, long ldv, const int *k,
                            const double *z, int ldz, void *out, hipStream_t st);
+
+// Givens least squares of every (system, rhs) pair on the device, the same
+// arithmetic as the host's GivensLS (no contraction of multiply-adds): pair
+// p's rotated Hessenberg matrix Rm + p (m+1) m (column-major, leading
+// dimension m + 1), its rotations c, s + p m and right-hand side
+// g + p (m+1). Per pair: fro2 (sum of squares of its Hessenberg entries),
+// target (the cycle stops once the shortcut residual |g[j+1]| is at or
+// below it), sc (the last shortcut residual), run (1 while its Arnoldi
+// process runs), k (columns kept), steps (Arnoldi steps taken this cycle).
+// act: per system, 1 while one of its pairs runs (the masked kernels' flags).
+struct BGivens {
+    double *Rm, *c, *s, *g, *fro2, *target, *sc;
+    int *run, *k, *steps, *act;
+    int m, R, nsys;
+};
+// Start of a cycle: g = beta e1, fro2 = 0, k = steps = 0, act from run.
+hipError_t launch_bgivens_init(const BGivens &G, const double *beta, hipStream_t st);
+// Arnoldi step j: for every running pair, its Hessenberg column
+// Hc[p ldh .. p ldh + j + 1] joins its least squares; the pair stops on a
+// non-finite column (the column is dropped), on breakdown
+// (h_{j+1,j} <= tol_brk sqrt(fro2)) or when |g[j+1]| <= target.
+hipError_t launch_bgivens_step(const BGivens &G, int j, const double *Hc, int ldh, double tol_brk, hipStream_t st);
+// flag[0] (device int) = 1 if some system has a running pair (act), else 0.
+hipError_t launch_bany(const int *act, int nsys, int *flag, hipStream_t st);
+// z[p ldz + i] (i < k[p]) solves the pair's triangular system R z = g.
+hipError_t launch_bgivens_solve(const BGivens &G, double *z, int ldz, hipStream_t st);
 
 }  // namespace ppg

@@ -137,8 +137,8 @@ __device__ __forceinline__ void bchain_finish(const PStep &st, const BRow<XT> &p
 // The wave's slice index. It is the same on every lane; readfirstlane says
 // so to the compiler, so the slice, its step descriptor and the buffer
 // pointers come through scalar loads.
-__device__ __forceinline__ int bslice_index() {
-    return remap_tile(blockIdx.x, gridDim.x, 1) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+__device__ __forceinline__ int bslice_index(int remap) {
+    return remap_tile(blockIdx.x, gridDim.x, remap) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
 // The step descriptor and the active flag of system sys, all fields read
@@ -155,10 +155,10 @@ __device__ __forceinline__ PStep bstep(const BChainArgs<VT, XT> &a, int sys, boo
 }
 
 template <typename VT, typename XT, int R>
-__global__ __launch_bounds__(256) void k_bchain(BChainArgs<VT, XT> a) {
+__global__ __launch_bounds__(256) void k_bchain(BChainArgs<VT, XT> a, int remap) {
     using AT = typename Arith<XT>::T;
     constexpr int U = 8;
-    const int w = bslice_index();
+    const int w = bslice_index(remap);
     if (w >= a.nslices) return;
     const int lane = threadIdx.x & 63;
     const int4 si = a.slice[w];
@@ -204,54 +204,76 @@ __global__ __launch_bounds__(256) void k_bchain(BChainArgs<VT, XT> a) {
     bchain_finish<XT, R>(st, p, t, row, s);
 }
 
-// The same step on the pattern-coded copy: one wave per 64-row slice; row
-// i of system sys sums ptab[ptoff[sys] + bpat[i] ND + d] x[i + poff[sys ND + d]]
-// over its ND diagonals. Columns are clamped into the system's rows (a
-// diagonal that leaves the system has a zero entry there) and rows past
-// the slice read its last row, so all loads go out unconditionally.
-template <typename VT, typename XT, int R, int ND>
+// The same step on the pattern-coded copy: a wave takes SPW consecutive
+// 64-row slices (one row of each per lane); row i of system sys sums
+// ptab[ptoff[sys] + bpat[i] ND + d] x[i + poff[sys ND + d]] over its ND
+// diagonals. Columns are clamped into the system's rows (a diagonal that
+// leaves the system has a zero entry there) and rows past the slice read its
+// last row, so all loads go out unconditionally, those of the SPW rows
+// together.
+template <typename VT, typename XT, int R, int ND, int SPW>
 __global__ __launch_bounds__(256) void k_bchain_pat(BChainArgs<VT, XT> a, const uint8_t *__restrict__ bpat,
                                                     const int32_t *__restrict__ poff,
                                                     const int32_t *__restrict__ ptoff,
-                                                    const int32_t *__restrict__ sysoff, const VT *__restrict__ ptab) {
+                                                    const int32_t *__restrict__ sysoff, const VT *__restrict__ ptab,
+                                                    int remap) {
     using AT = typename Arith<XT>::T;
-    const int w = bslice_index();
-    if (w >= a.nslices) return;
+    const int w0 = bslice_index(remap) * SPW;
+    if (w0 >= a.nslices) return;
     const int lane = threadIdx.x & 63;
-    const int4 si = a.slice[w];
-    const int sys = si.z;
-    // what depends on the slice alone goes out first: the row's pattern
-    // byte and the system's offsets, beside the step descriptor
-    const int rc = si.x + min(lane, si.y - 1);
-    const int code = bpat[rc];
-    const int lo = sysoff[sys], hi = sysoff[sys + 1] - 1, toff = ptoff[sys];
-    int po[ND];
+    int4 si[SPW];
+    int rc[SPW], code[SPW], lo[SPW], hi[SPW], toff[SPW], po[SPW][ND];
+    // what depends on the slices alone goes out first: the rows' pattern
+    // bytes and the systems' offsets, beside the step descriptors
 #pragma unroll
-    for (int d = 0; d < ND; ++d) po[d] = poff[sys * ND + d];
-    bool skip;
-    const PStep st = bstep(a, sys, skip);
-    if (skip) return;
-    const long row = (long)si.x + lane;
-    const BRow<XT> p = brow_ptrs(a, st);
-    BRowIn<XT, R> t;
-    brow_load<XT, R>(p, rc, t);
-    AT s[R];
+    for (int q = 0; q < SPW; ++q) {
+        si[q] = a.slice[min(w0 + q, a.nslices - 1)];
+        const int sys = si[q].z;
+        rc[q] = si[q].x + min(lane, si[q].y - 1);
+        code[q] = bpat[rc[q]];
+        lo[q] = sysoff[sys];
+        hi[q] = sysoff[sys + 1] - 1;
+        toff[q] = ptoff[sys];
 #pragma unroll
-    for (int r = 0; r < R; ++r) s[r] = AT(0);
-    if (st.spmv) {
-        AT xv[ND][R];
+        for (int d = 0; d < ND; ++d) po[q][d] = poff[sys * ND + d];
+    }
+    bool skip[SPW];
+    PStep st[SPW];
 #pragma unroll
-        for (int d = 0; d < ND; ++d) ldr<XT, R>(p.in, min(max(rc + po[d], lo), hi), xv[d]);
-        const VT *tb = ptab + toff + code * ND;
+    for (int q = 0; q < SPW; ++q) {
+        st[q] = bstep(a, si[q].z, skip[q]);
+        skip[q] = skip[q] || w0 + q >= a.nslices;
+    }
+    BRow<XT> p[SPW];
+    BRowIn<XT, R> t[SPW];
+    AT xv[SPW][ND][R];
 #pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            const AT v = (AT)tb[d];
+    for (int q = 0; q < SPW; ++q) {
+        if (skip[q]) continue;
+        p[q] = brow_ptrs(a, st[q]);
+        brow_load<XT, R>(p[q], rc[q], t[q]);
+        if (st[q].spmv) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) s[r] += v * xv[d][r];
+            for (int d = 0; d < ND; ++d) ldr<XT, R>(p[q].in, min(max(rc[q] + po[q][d], lo[q]), hi[q]), xv[q][d]);
         }
     }
-    if (lane >= si.y) return;
-    bchain_finish<XT, R>(st, p, t, row, s);
+#pragma unroll
+    for (int q = 0; q < SPW; ++q) {
+        if (skip[q]) continue;
+        AT s[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] = AT(0);
+        if (st[q].spmv) {
+            const VT *tb = ptab + toff[q] + code[q] * ND;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const AT v = (AT)tb[d];
+#pragma unroll
+                for (int r = 0; r < R; ++r) s[r] += v * xv[q][d][r];
+            }
+        }
+        if (lane < si[q].y) bchain_finish<XT, R>(st[q], p[q], t[q], (long)si[q].x + lane, s);
+    }
 }
 
 // One chunk of KC Krylov columns of k_bdots for R interleaved right-hand
@@ -563,12 +585,13 @@ __global__ __launch_bounds__(256) void k_bcombine(const int4 *block, const XT *V
 
 // ---- dispatch helpers -----------------------------------------------------
 
-template <typename VT, typename XT, int R>
-hipError_t bchain_pat_t(const BatchSell &S, const BChainArgs<VT, XT> &a, const VT *ptab, unsigned g, hipStream_t st) {
+template <typename VT, typename XT, int R, int SPW>
+hipError_t bchain_pat_t(const BatchSell &S, const BChainArgs<VT, XT> &a, const VT *ptab, hipStream_t st) {
+    const unsigned g = (unsigned)((S.nslices + 4 * SPW - 1) / (4 * SPW));
 #define PP_BPAT_ND(K)                                                                                             \
     case K:                                                                                                       \
-        hipLaunchKernelGGL((k_bchain_pat<VT, XT, R, K>), dim3(g), dim3(256), 0, st, a, S.bpat, S.poff, S.ptoff,   \
-                           S.sysoff, ptab);                                                                       \
+        hipLaunchKernelGGL((k_bchain_pat<VT, XT, R, K, SPW>), dim3(g), dim3(256), 0, st, a, S.bpat, S.poff,      \
+                           S.ptoff, S.sysoff, ptab, S.remap);                                                     \
         break;
     switch (S.pnd) {
         PP_BPAT_ND(3)
@@ -603,26 +626,27 @@ hipError_t bchain_t(const BatchSell &S, const VT *sval, const VT *ptab, int R, c
     const unsigned g = (unsigned)((S.nslices + 3) / 4);
     if (g == 0) return hipSuccess;
     if (S.bpat) {
+        const bool two = S.spw == 2;
         switch (R) {
             case 1:
-                return bchain_pat_t<VT, XT, 1>(S, a, ptab, g, st);
+                return two ? bchain_pat_t<VT, XT, 1, 2>(S, a, ptab, st) : bchain_pat_t<VT, XT, 1, 1>(S, a, ptab, st);
             case 2:
-                return bchain_pat_t<VT, XT, 2>(S, a, ptab, g, st);
+                return two ? bchain_pat_t<VT, XT, 2, 2>(S, a, ptab, st) : bchain_pat_t<VT, XT, 2, 1>(S, a, ptab, st);
             case 4:
-                return bchain_pat_t<VT, XT, 4>(S, a, ptab, g, st);
+                return two ? bchain_pat_t<VT, XT, 4, 2>(S, a, ptab, st) : bchain_pat_t<VT, XT, 4, 1>(S, a, ptab, st);
             default:
                 return hipErrorInvalidValue;
         }
     }
     switch (R) {
         case 1:
-            hipLaunchKernelGGL((k_bchain<VT, XT, 1>), dim3(g), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_bchain<VT, XT, 1>), dim3(g), dim3(256), 0, st, a, S.remap);
             break;
         case 2:
-            hipLaunchKernelGGL((k_bchain<VT, XT, 2>), dim3(g), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_bchain<VT, XT, 2>), dim3(g), dim3(256), 0, st, a, S.remap);
             break;
         case 4:
-            hipLaunchKernelGGL((k_bchain<VT, XT, 4>), dim3(g), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_bchain<VT, XT, 4>), dim3(g), dim3(256), 0, st, a, S.remap);
             break;
         default:
             return hipErrorInvalidValue;
@@ -870,6 +894,145 @@ hipError_t launch_bcombine(const BatchBlocks &B, int prec, int R, const void *V,
             return bcombine_t<uint16_t>(B, R, (const uint16_t *)V, ldv, k, z, ldz, (uint16_t *)out, st);
     }
     return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Givens least squares of every pair, on the device: one thread per system
+// runs its R pairs in order. The arithmetic is the host's GivensLS step for
+// step (multiply-adds not contracted), so a cycle decides exactly as the
+// host would.
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ __launch_bounds__(256) void k_bgivens_init(BGivens G, const double *beta) {
+    const int s = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (s >= G.nsys) return;
+    int a = 0;
+    for (int r = 0; r < G.R; ++r) {
+        const int p = s * G.R + r;
+        G.g[(size_t)p * (G.m + 1)] = beta[p];
+        G.fro2[p] = 0.0;
+        G.k[p] = 0;
+        G.steps[p] = 0;
+        a |= G.run[p];
+    }
+    G.act[s] = a;
+}
+
+__global__ __launch_bounds__(256) void k_bgivens_step(BGivens G, int j, const double *Hc, int ldh, double tol_brk) {
+#pragma clang fp contract(off)
+    const int s = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (s >= G.nsys) return;
+    const int m = G.m, ld = m + 1;
+    int a = 0;
+    for (int r = 0; r < G.R; ++r) {
+        const int p = s * G.R + r;
+        if (!G.run[p]) continue;
+        const double *h = Hc + (size_t)p * ldh;
+        G.steps[p] += 1;
+        bool finite = true;
+        double f = G.fro2[p];
+        for (int i = 0; i <= j + 1; ++i) {
+            finite = finite && isfinite(h[i]);
+            f += h[i] * h[i];
+        }
+        G.fro2[p] = f;
+        if (!finite) {
+            G.run[p] = 0;
+            continue;
+        }
+        double *col = G.Rm + (size_t)p * ld * m + (size_t)j * ld;
+        double *c = G.c + (size_t)p * m, *sn = G.s + (size_t)p * m, *g = G.g + (size_t)p * ld;
+        for (int i = 0; i <= j + 1; ++i) col[i] = h[i];
+        for (int i = 0; i < j; ++i) {
+            const double t1 = c[i] * col[i] + sn[i] * col[i + 1];
+            const double t2 = -sn[i] * col[i] + c[i] * col[i + 1];
+            col[i] = t1;
+            col[i + 1] = t2;
+        }
+        const double x = col[j], y = col[j + 1];
+        double cj, sj;
+        if (y == 0.0) {
+            cj = 1.0;
+            sj = 0.0;
+        } else if (fabs(y) > fabs(x)) {
+            const double tau = x / y;
+            sj = 1.0 / sqrt(1.0 + tau * tau);
+            cj = sj * tau;
+        } else {
+            const double tau = y / x;
+            cj = 1.0 / sqrt(1.0 + tau * tau);
+            sj = cj * tau;
+        }
+        c[j] = cj;
+        sn[j] = sj;
+        col[j] = cj * x + sj * y;
+        col[j + 1] = 0.0;
+        g[j + 1] = -sj * g[j];
+        g[j] = cj * g[j];
+        G.k[p] = j + 1;
+        const double sc = fabs(g[j + 1]);
+        G.sc[p] = sc;
+        if (h[j + 1] <= tol_brk * sqrt(f) || sc <= G.target[p])
+            G.run[p] = 0;
+        else
+            a = 1;
+    }
+    G.act[s] = a;
+}
+
+__global__ __launch_bounds__(256) void k_bgivens_solve(BGivens G, double *z, int ldz) {
+#pragma clang fp contract(off)
+    const int p = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (p >= G.nsys * G.R) return;
+    const int k = G.k[p], ld = G.m + 1;
+    const double *Rm = G.Rm + (size_t)p * ld * G.m, *g = G.g + (size_t)p * ld;
+    double *zp = z + (size_t)p * ldz;
+    for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int q = i + 1; q < k; ++q) t -= Rm[(size_t)i + (size_t)q * ld] * zp[q];
+        zp[i] = t / Rm[(size_t)i + (size_t)i * ld];
+    }
+}
+
+// flag[0] = 1 if some system still has a running pair, else 0 (one workgroup)
+__global__ __launch_bounds__(256) void k_bany(const int *act, int nsys, int *flag) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    int a = 0;
+    for (int s = (int)threadIdx.x; s < nsys; s += 256) a |= act[s];
+    if (a) any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) flag[0] = any;
+}
+
+}  // namespace
+
+hipError_t launch_bany(const int *act, int nsys, int *flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_bany, dim3(1), dim3(256), 0, st, act, nsys, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_bgivens_init(const BGivens &G, const double *beta, hipStream_t st) {
+    if (G.nsys <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bgivens_init, dim3((G.nsys + 255) / 256), dim3(256), 0, st, G, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_bgivens_step(const BGivens &G, int j, const double *Hc, int ldh, double tol_brk, hipStream_t st) {
+    if (G.nsys <= 0) return hipSuccess;
+    if (j < 0 || j >= G.m || ldh < j + 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bgivens_step, dim3((G.nsys + 255) / 256), dim3(256), 0, st, G, j, Hc, ldh, tol_brk);
+    return hipGetLastError();
+}
+
+hipError_t launch_bgivens_solve(const BGivens &G, double *z, int ldz, hipStream_t st) {
+    const int P = G.nsys * G.R;
+    if (P <= 0) return hipSuccess;
+    if (ldz < G.m) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bgivens_solve, dim3((P + 255) / 256), dim3(256), 0, st, G, z, ldz);
+    return hipGetLastError();
 }
 
 }  // namespace ppg

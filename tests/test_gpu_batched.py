@@ -140,6 +140,39 @@ def test_small_batch_matches_oracle(pp, inner, R, fmt):
                                   f"small {inner} R={R} {fmt}")
 
 
+@pytest.mark.parametrize("R", [1, 4])
+def test_batch_tuner_and_every_launch_shape(pp, R):
+    # the batched autotuner picks a valid shape; every shape (format, slices
+    # per wave, workgroup order) gives each pair's solution within the
+    # oracle bound, and all shapes agree with each other to the solve's
+    # accuracy
+    csrs = _systems(SMALL)
+    say("batch tuner", R)
+    Bt = pp.Batch(csrs)
+    polys = Bt.setup(dev(_v0(SMALL)), 8)
+    brs = _rhs_block(SMALL, R)
+    bd = Bt.interleave(np.concatenate(brs, axis=1))
+    fmt, spw, remap, us = Bt.tune(R, "fp32")
+    assert fmt in ("sell", "pattern") and spw in (1, 2) and remap in (0, 1) and us > 0
+    assert Bt.chain_config(R, "fp32") == (fmt, spw, remap, us)
+    xs = []
+    for shape in [("sell", 1, 0), ("sell", 1, 1), ("pattern", 1, 0), ("pattern", 1, 1), ("pattern", 2, 0),
+                  ("pattern", 2, 1)]:
+        say("batch shape", R, shape)
+        Bt.set_chain_config(R, "fp32", *shape)
+        Bt.set_chain_config(R, "fp64", *shape)
+        assert Bt.chain_config(R, "fp32")[:3] == shape
+        x, infos = Bt.solve(polys, bd, R, tol=1e-8, m=30, inner="fp32")
+        X = host(Bt.deinterleave(x, R))
+        _check_systems_against_oracle(SMALL, csrs, polys, brs, X, infos, R, 30, range(len(SMALL)),
+                                      f"shape {shape} R={R}")
+        xs.append(X)
+    for X in xs[1:]:
+        assert relerr(X, xs[0]) <= 1e-6
+    with pytest.raises(Exception):
+        Bt.set_chain_config(R, "fp32", "sell", 2, 1)  # two slices per wave only on the pattern-coded copy
+
+
 def test_batch_pattern_copy_rules(pp):
     # a batch whose systems lie on different numbers of diagonals has no
     # pattern-coded copy; new values drop it, and the sliced-ELL products
