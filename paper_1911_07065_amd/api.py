@@ -77,7 +77,8 @@ class Matrix:
         if val.numel() != self.nnz:
             raise ValueError("value count does not match the pattern")
         self.val = val
-        self._t = None
+        # a cached transpose (PPSolve.backward) keeps its pattern and tuning:
+        # backward gathers the new values into it
         try:
             check(lib.pp_matrix_set_values(self.handle, _ptr(val), _stream(self.device)), "pp_matrix_set_values")
         except PPError:
