@@ -145,8 +145,12 @@ void pp_matrix_destroy(pp_matrix A);
 pp_status pp_matrix_tune(pp_matrix A, int prec, void *stream, int *variant, int *remap,
                          double *us_per_launch);
 
-/* Force a chain-step variant (0 <= variant < 31, remap 0/1; 15 = persistent) for a precision
- * instead of tuning, e.g. to test every variant. */
+/* Force a chain-step variant (0 <= variant < 32, remap 0/1; 15 = persistent) for a precision
+ * instead of tuning, e.g. to test every variant. Variant 31 (box) applies to a
+ * constant-coefficient 5- or 7-point box stencil (see pp_matrix_march's
+ * `constant`) whose grid lines hold a multiple of 4 points: it reads no
+ * per-row matrix data, only the interior row's coefficients, and sums each
+ * row's terms as the pattern-coded variants do; PP_EINVAL elsewhere. */
 pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap);
 
 /* The chain-step variant in use for a precision, without tuning: variant
@@ -203,6 +207,27 @@ pp_status pp_matrix_pair_steps(pp_matrix A, int prec, int *mode, int *box, doubl
  *     no pattern bytes. */
 pp_status pp_matrix_set_march(pp_matrix A, int prec, int steps, int cz, int depth);
 pp_status pp_matrix_march(pp_matrix A, int prec, int *steps, int *cz, double *us, int *constant);
+
+/* Two chain steps per launch on whole grid lines (the fusion rules of
+ * pp_matrix_set_march with two steps): on a constant-coefficient 7-point box
+ * stencil whose grid lines hold 64, 128 or 256 points, a workgroup owns a
+ * block of whole x-lines (a few in y by a few in z), stages the input on
+ * them and two lines around them in y and z in LDS, forms the first step on
+ * its lines and one line around them, then the second step, which it
+ * stores. There is no halo along the lines and no per-point index
+ * arithmetic, which suits grids too small for marching to fill the GPU.
+ * The results equal single launches up to the order of rounding.
+ * pp_matrix_tune times it beside the marching kernel's two-step launches
+ * and keeps the faster.
+ *   pp_matrix_set_march_shape: shape 1 turns it on (every group of two
+ *     fusable steps runs one such launch; pp_matrix_march then reports
+ *     steps 2), 0 returns two-step groups to the marching kernel; PP_EINVAL
+ *     where it does not apply, for bfloat16 vectors, or for a precision not
+ *     tuned or set yet. pp_matrix_set_variant and pp_matrix_set_march turn it
+ *     off.
+ *   pp_matrix_march_shape: *shape (host) 1 while two-step launches use it. */
+pp_status pp_matrix_set_march_shape(pp_matrix A, int prec, int shape);
+pp_status pp_matrix_march_shape(pp_matrix A, int prec, int *shape);
 
 /* Composition with a diagonal right preconditioner M^{-1} = diag(s)
  * (eqs. (1.3)-(1.4), section 1): from now on the handle's operator is

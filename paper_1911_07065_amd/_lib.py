@@ -54,6 +54,8 @@ SIGNATURES = {
     "pp_matrix_pair_steps": (c_int, [c_void_p, c_int, P_int, P_int, P_double]),
     "pp_matrix_set_march": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
     "pp_matrix_march": (c_int, [c_void_p, c_int, P_int, P_int, P_double, P_int]),
+    "pp_matrix_set_march_shape": (c_int, [c_void_p, c_int, c_int]),
+    "pp_matrix_march_shape": (c_int, [c_void_p, c_int, P_int]),
     "pp_matrix_right_scale": (c_int, [c_void_p, c_void_p, c_void_p]),
     "pp_matrix_scale": (c_int, [c_void_p, c_void_p, c_void_p]),
     "pp_chain_variant_name": (ctypes.c_char_p, [c_int]),

@@ -25,7 +25,7 @@ def version() -> str:
     return lib.pp_version().decode()
 
 
-N_CHAIN_VARIANTS = 31
+N_CHAIN_VARIANTS = 32
 
 
 def chain_variant_name(v: int) -> str:
@@ -171,6 +171,16 @@ class Matrix:
         check(lib.pp_matrix_march(self.handle, PREC[prec], ctypes.byref(g), ctypes.byref(cz), ctypes.byref(us),
                                   ctypes.byref(c)), "pp_matrix_march")
         return g.value, cz.value, us.value
+
+    def set_march_shape(self, shape: int, prec: str = "fp32"):
+        """Two-step launches on whole grid lines (shape 1) or marching planes (0)."""
+        check(lib.pp_matrix_set_march_shape(self.handle, PREC[prec], int(shape)), "pp_matrix_set_march_shape")
+
+    def march_shape(self, prec: str = "fp32") -> int:
+        """1 while two-step launches run on whole grid lines, else 0."""
+        v = ctypes.c_int()
+        check(lib.pp_matrix_march_shape(self.handle, PREC[prec], ctypes.byref(v)), "pp_matrix_march_shape")
+        return v.value
 
     def constant_stencil(self) -> bool:
         """True when every row is one interior row's box stencil truncated at the box."""

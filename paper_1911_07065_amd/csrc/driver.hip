@@ -92,6 +92,10 @@ struct pp_matrix_s {
     int march_cz[3][kMarchMax + 1] = {};
     int march_depth[3][kMarchMax + 1] = {};  // planes of loads in flight (1..3)
     double march_us[3][kMarchMax + 1] = {};
+    // per precision: two-step launches run the whole-line tile kernel
+    // instead of marching planes (constant-coefficient 7-point stencils)
+    int march_tile[3] = {0, 0, 0};
+    int tile_remap[3] = {1, 1, 1};
     // column-banded CSR copies (matrices whose entries lie far from the
     // diagonal): c = 0 two bands, c = 1 four; bperm maps entries to CSR
     int32_t *brow[2] = {nullptr, nullptr}, *bcol[2] = {nullptr, nullptr}, *bperm[2] = {nullptr, nullptr};
@@ -458,7 +462,7 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
             (v == CV_DIAC && !A->dcode) || (v == CV_DIAP && !A->pcode) || (v == CV_DIAPV && !A->pbyte) ||
             (v == CV_BAND2 && A->bandK[0] == 0) || (v == CV_BAND4 && A->bandK[1] == 0) ||
             (v == CV_TILEB8 && A->ntileB8[prec] == 0) ||
-            (v == CV_TILEB16 && A->ntileB16[prec] == 0))
+            (v == CV_TILEB16 && A->ntileB16[prec] == 0) || (v == CV_BOX && !box_step_ok(A->dev())))
             continue;
         for (int r = 0; r < 2; ++r) {
             A->variant[prec] = v;
@@ -513,6 +517,7 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
     // lowest time per step is kept when it beats a single step
     A->march[prec] = 0;
     A->march_all[prec] = 0;
+    A->march_tile[prec] = 0;
     for (int g = 0; g <= kMarchMax; ++g) {
         A->march_us[prec][g] = 0.0;
         A->march_cz[prec][g] = 0;
@@ -551,6 +556,33 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
                             bdepth = depth;
                         }
                     }
+                }
+            }
+            // two steps: whole-line tiles instead of marching planes, where
+            // they apply and are faster
+            if (g == 2 && box_tile_ok(d, prec)) {
+                MarchPtrs tp = mp;
+                tp.shape = 1;
+                tp.depth = 0;
+                double bt = 1e30;
+                for (int round = 0; round < 2; ++round)
+                    for (int r = 0; r < 2; ++r) {
+                        for (int i = 0; i < 2; ++i) HIP_TRY(launch_chain_march(d, prec, tp, 0, r, st));
+                        HIP_TRY(hipEventRecord(e0, st));
+                        for (int i = 0; i < reps; ++i) HIP_TRY(launch_chain_march(d, prec, tp, 0, r, st));
+                        HIP_TRY(hipEventRecord(e1, st));
+                        HIP_TRY(hipEventSynchronize(e1));
+                        float ms = 0.f;
+                        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                        const double us = 1e3 * ms / reps;
+                        if (us < bt) {
+                            bt = us;
+                            A->tile_remap[prec] = r;
+                        }
+                    }
+                if (bt < bg) {
+                    bg = bt;
+                    A->march_tile[prec] = 1;
                 }
             }
             A->march_us[prec][g] = bg;
@@ -770,7 +802,9 @@ pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void 
                 if (u.aux != B_NONE) mp.aux |= 1 << k;
             }
             mp.depth = A->march_depth[prec][L.g];
-            HIP_TRY(launch_chain_march(d, prec, mp, A->march_cz[prec][L.g], A->remap[prec], st));
+            mp.shape = L.g == 2 && A->march_tile[prec] ? 1 : 0;
+            HIP_TRY(launch_chain_march(d, prec, mp, A->march_cz[prec][L.g],
+                                       mp.shape ? A->tile_remap[prec] : A->remap[prec], st));
             if (L.swap >= 0) std::swap(tmp[L.swap], tmp[t.out]);
             continue;
         }
@@ -899,6 +933,8 @@ int64_t format_bytes(pp_matrix A, int prec) {
         case CV_DIAP:
         case CV_DIAPV:
             return n + (int64_t)A->npat * nd * sv;
+        case CV_BOX:  // the interior row's coefficients only
+            return nd * sv;
         case CV_BAND2:
         case CV_BAND4: {
             const int c = A->variant[prec] == CV_BAND2 ? 0 : 1;
@@ -938,8 +974,12 @@ void program_bytes(pp_matrix A, pp_poly poly, int kind, int prec, int64_t &bytes
         if (kind == PP_APPLY_P) program_bytes(A, in, PP_APPLY_P, prec, bytes, launches);
         return;
     }
-    // fused launches read the pattern-coded copy, whatever the single-step variant
-    const int64_t pat = (int64_t)A->n + (int64_t)A->npat * (int64_t)A->h_doff.size() * (prec == PP_F64 ? 8 : 4);
+    // fused launches read the pattern-coded copy, whatever the single-step
+    // variant; on a constant-coefficient stencil only the interior row's
+    // coefficients
+    const int64_t csz = prec == PP_F64 ? 8 : 4;
+    const int64_t pat = A->box_pint >= 0 ? (int64_t)A->h_doff.size() * csz
+                                         : (int64_t)A->n + (int64_t)A->npat * (int64_t)A->h_doff.size() * csz;
     std::vector<Planned> plan;
     plan_program(A, prog, prec, plan);
     for (const Planned &L : plan) {
@@ -1656,7 +1696,8 @@ pp_status refresh_values(pp_matrix A, const double *val, hipStream_t st) {
             A->npat = 0;
             A->box_pint = -1;
             for (int p = 0; p < 3; ++p)
-                if (A->variant[p] == CV_DIAC || A->variant[p] == CV_DIAP || A->variant[p] == CV_DIAPV) {
+                if (A->variant[p] == CV_DIAC || A->variant[p] == CV_DIAP || A->variant[p] == CV_DIAPV ||
+                    A->variant[p] == CV_BOX) {
                     A->variant[p] = CV_TILE8;
                     A->tuned[p] = 0;
                 }
@@ -1986,6 +2027,11 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
                       "distinct rows, or the values changed)");
             return PP_EINVAL;
         }
+        if (variant == CV_BOX && !box_step_ok(A->dev())) {
+            set_error("pp_matrix_set_variant: the box kernel needs a constant-coefficient 5- or 7-point box stencil "
+                      "whose grid lines hold a multiple of 4 points");
+            return PP_EINVAL;
+        }
         if (variant == CV_TILEB8) PP_TRY(build_round_plan(A, prec, 8, &A->tileB8[prec], &A->ntileB8[prec], 0));
         if (variant == CV_TILEB16) PP_TRY(build_round_plan(A, prec, 16, &A->tileB16[prec], &A->ntileB16[prec], 0));
         A->persist[prec] = 0;
@@ -1997,6 +2043,7 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
     A->fuse[prec] = 0;  // the forced variant runs every step
     A->march[prec] = 0;
     A->march_all[prec] = 0;
+    A->march_tile[prec] = 0;
     return PP_OK;
 }
 
@@ -2035,11 +2082,43 @@ pp_status pp_matrix_set_march(pp_matrix A, int prec, int steps, int cz, int dept
     }
     A->march[prec] = steps;
     A->march_all[prec] = steps >= 2;
+    A->march_tile[prec] = 0;
     const int c = cz > 0 ? cz : march_default_cz(A->dev(), 1024);
     for (int g = 2; g <= kMarchMax; ++g) {
         A->march_cz[prec][g] = c;
         A->march_depth[prec][g] = depth > 0 ? depth : 1;
     }
+    return PP_OK;
+}
+
+pp_status pp_matrix_set_march_shape(pp_matrix A, int prec, int shape) {
+    if (!A || !valid_prec(prec) || (shape != 0 && shape != 1)) {
+        set_error("pp_matrix_set_march_shape: bad argument");
+        return PP_EINVAL;
+    }
+    if (!A->tuned[prec] || A->persist[prec]) {
+        set_error("pp_matrix_set_march_shape: tune or set a single-launch variant for this precision first");
+        return PP_EINVAL;
+    }
+    if (shape == 1 && !box_tile_ok(A->dev(), prec)) {
+        set_error("pp_matrix_set_march_shape: whole-line tiles need a constant-coefficient 7-point box stencil "
+                  "whose grid lines hold 64, 128 or 256 points, and FP64 or FP32 vectors");
+        return PP_EINVAL;
+    }
+    A->march_tile[prec] = shape;
+    if (shape == 1) {
+        A->march[prec] = 2;
+        A->march_all[prec] = 1;
+    }
+    return PP_OK;
+}
+
+pp_status pp_matrix_march_shape(pp_matrix A, int prec, int *shape) {
+    if (!A || !valid_prec(prec) || !shape) {
+        set_error("pp_matrix_march_shape: bad argument");
+        return PP_EINVAL;
+    }
+    *shape = A->march[prec] >= 2 && A->march_tile[prec] ? 1 : 0;
     return PP_OK;
 }
 

@@ -45,7 +45,8 @@ enum ChainVariant : int {
     CV_BAND2 = 28,    // tile8x1 on 2 column bands, one launch per band (partial row sums in between)
     CV_BAND4 = 29,    // the same with 4 column bands
     CV_DIAPV = 30,    // pattern-coded diagonals, 4 consecutive rows per lane with vector loads
-    CV_COUNT = 31
+    CV_BOX = 31,      // constant-coefficient box stencil: no per-row matrix data, 4 points of a grid line per lane
+    CV_COUNT = 32
 };
 
 // A chain step as the persistent kernel reads it from device memory.
@@ -224,8 +225,18 @@ struct MarchPtrs {
     int nsteps;
     int aux;
     int depth;  // planes of loads in flight per workgroup (1..3; constant-coefficient stencils only)
+    // 0: the marching kernel; 1: whole-line tiles (k_chain_boxt: two steps,
+    // constant-coefficient 7-point stencil, box_tile_ok)
+    int shape;
     double a0[kMarchMax], a1[kMarchMax], a2[kMarchMax];
 };
+// The single-step box kernel (CV_BOX) applies: a constant-coefficient 5- or
+// 7-point box stencil whose grid lines hold a multiple of 4 points.
+bool box_step_ok(const DevCSR &A);
+// Whole-line tiles (MarchPtrs::shape 1) apply: a constant-coefficient
+// 7-point box stencil whose grid lines hold 64, 128 or 256 points, FP64 or
+// FP32 vectors.
+bool box_tile_ok(const DevCSR &A, int prec);
 hipError_t launch_chain_march(const DevCSR &A, int prec, const MarchPtrs &p, int cz, int remap, hipStream_t st);
 // Planes per chunk that give the grid at least `target` workgroups (at most
 // the marching extent; a multiple of 4 where possible).

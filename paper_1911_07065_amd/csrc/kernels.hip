@@ -841,6 +841,73 @@ __global__ __launch_bounds__(256) void k_chain_diapv(ChainArgs<VT, XT> a, const 
     }
 }
 
+// Constant-coefficient box stencil (every row is the interior row's stencil
+// truncated at the box, DevCSR::box_pint), one chain step with the update of
+// the other chain kernels. The line length gx is a multiple of 4: lane t of
+// block b owns the 4 points r .. r+3 of one grid line, r = 4 (256 b + t).
+// Its own values and each neighbouring line's 4 values move as one vector
+// access, the two neighbours along the line as single loads; no per-row
+// matrix data is read. The ND coefficients (the interior row's pattern, a
+// uniform load) multiply the neighbours in ascending diagonal order; a
+// neighbour outside the box counts as zero, which is what the truncated row
+// holds, so a row's sum has the pattern-coded kernels' terms in their order
+// (the fused update may round differently by an ulp). Addresses of
+// neighbours outside the box are clamped to the point itself and the loaded
+// value is dropped, so every load of a lane goes out at once.
+template <typename VT, typename XT, int ND>
+__global__ __launch_bounds__(256) void k_chain_box(ChainArgs<VT, XT> a, const VT *__restrict__ ptab, int pint,
+                                                   int gx, int gy, int gz, int nblocks, int remap) {
+    using AT = typename Arith<XT>::T;
+    static_assert(ND == 5 || ND == 7, "5- or 7-point box stencils");
+    const int blk = remap_tile(blockIdx.x, nblocks, remap);
+    const int n = a.n;
+    const int r = 4 * (blk * 256 + (int)threadIdx.x);
+    if (r >= n) return;
+    const int P = gx * gy;
+    const int x = r % gx, y = (r / gx) % gy, z = ND == 7 ? r / P : 0;
+    AT c[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) c[d] = (AT)ptab[pint * ND + d];
+    const bool hx0 = x > 0, hx1 = x + 4 < gx, hy0 = y > 0, hy1 = y + 1 < gy;
+    const bool hz0 = ND == 7 && z > 0, hz1 = ND == 7 && z + 1 < gz;
+    AT xc[4], ym[4], yp[4], zm[4], zp[4], aux[4], vf[4], acc[4];
+    ld4(a.in, r, xc);
+    ld4(a.in, hy0 ? r - gx : r, ym);
+    ld4(a.in, hy1 ? r + gx : r, yp);
+    if constexpr (ND == 7) {
+        ld4(a.in, hz0 ? r - P : r, zm);
+        ld4(a.in, hz1 ? r + P : r, zp);
+    }
+    AT xl = ldx(a.in, hx0 ? r - 1 : r), xr = ldx(a.in, hx1 ? r + 4 : r);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) aux[k] = vf[k] = acc[k] = AT(0);
+    if (a.aux) ld4(a.aux, r, aux);
+    if (a.vfin) ld4(a.vfin, r, vf);
+    if (a.acc && !a.acc_init) ld4(a.acc, r, acc);
+    xl = hx0 ? xl : AT(0);
+    xr = hx1 ? xr : AT(0);
+    AT ov[4], av[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const AT left = k == 0 ? xl : xc[k - 1], right = k == 3 ? xr : xc[k + 1];
+        AT s = AT(0);
+        if constexpr (ND == 7) s += c[0] * (hz0 ? zm[k] : AT(0));
+        constexpr int o = ND == 7 ? 1 : 0;
+        s += c[o] * (hy0 ? ym[k] : AT(0));
+        s += c[o + 1] * left;
+        s += c[o + 2] * xc[k];
+        s += c[o + 3] * right;
+        s += c[o + 4] * (hy1 ? yp[k] : AT(0));
+        if constexpr (ND == 7) s += c[6] * (hz1 ? zp[k] : AT(0));
+        AT w = a.a0 * s + a.a1 * xc[k];
+        if (a.aux) w += a.a2 * aux[k];
+        av[k] = acc[k] + a.b0 * xc[k] + a.b1 * w;
+        ov[k] = a.vfin ? vf[k] - w : w;
+    }
+    if (a.acc) st4(a.acc, r, av);
+    if (a.out) st4(a.out, r, ov);
+}
+
 template <typename VT>
 const VT *diap_tab(const DevCSR &A);
 template <>
@@ -1369,6 +1436,156 @@ __global__ __launch_bounds__(256) void k_chain_march(MarchArgs<XT> a, const uint
     }
 }
 
+// Two chain steps per launch on a constant-coefficient 7-point box stencil
+// (DevCSR::box_pint) whose grid lines hold GX points: a workgroup owns TY x
+// TZ whole grid lines (y x z). It stages the input on its lines and two lines
+// around them in y and z (zero outside the box) in LDS, computes the first
+// step on its lines and one line around them into LDS (zero on lines outside
+// the box), then the second step on its lines, which it stores. The steps
+// are those of the marching kernel (MarchArgs): w1 = a0[0] (A in) + a1[0] in,
+// w2 = a0[1] (A w1) + a1[1] w1 [+ a2[1] in if bit 1 of aux], out = vfin ?
+// vfin - w2 : w2. A lane owns 4 consecutive points of a line (GX / 4 lanes
+// per line): the line itself, the lines above and below in y and z are one
+// 4-wide LDS access each, the two neighbours along the line single accesses.
+// Products are summed in ascending diagonal order with the interior row's
+// coefficients, as the other kernels do. There is no x halo and no per-point
+// index arithmetic; the price is the two-line halo in y and z.
+template <typename VT, typename XT, int TY, int TZ, int GX>
+__global__ __launch_bounds__(256) void k_chain_boxt(MarchArgs<XT> a, const VT *__restrict__ ptab, int remap) {
+    using AT = typename Arith<XT>::T;
+    typedef AT AV4 __attribute__((ext_vector_type(4)));
+    static_assert(GX % 4 == 0 && 256 % (GX / 4) == 0, "whole lines of 4-point lanes in a workgroup");
+    constexpr int LPL = GX / 4, LPP = 256 / LPL;  // lanes per line, lines per pass
+    constexpr int RY0 = TY + 4, NL0 = RY0 * (TZ + 4);
+    constexpr int RY1 = TY + 2, NL1 = RY1 * (TZ + 2);
+    constexpr int NT = TY * TZ;
+    constexpr int C0 = (NL0 + LPP - 1) / LPP, C1 = (NL1 + LPP - 1) / LPP, CT = (NT + LPP - 1) / LPP;
+    __shared__ AV4 lev0[NL0 * LPL];
+    __shared__ AV4 lev1[NL1 * LPL];
+    const int tid = threadIdx.x, li = tid / LPL, lx = tid % LPL, x = 4 * lx;
+    const int gy = a.gy, gz = a.gm;
+    const int t = remap_tile(blockIdx.x, a.ntiles, remap);
+    const int y0 = (t % a.nty) * TY, z0 = (t / a.nty) * TZ;
+    const long P = (long)GX * gy;
+    AT c[7];
+#pragma unroll
+    for (int d = 0; d < 7; ++d) c[d] = (AT)ptab[a.pint * 7 + d];
+    // every global load before the first barrier: the staged input (clamped
+    // to a point of the box, dropped outside it) and the final vector
+    AT pre[C0][4];
+#pragma unroll
+    for (int k = 0; k < C0; ++k) {
+        const int L = min(li + k * LPP, NL0 - 1);
+        const int y = y0 - 2 + L % RY0, z = z0 - 2 + L / RY0;
+        const int yc = min(max(y, 0), gy - 1), zc = min(max(z, 0), gz - 1);
+        ld4(a.in, zc * P + (long)yc * GX + x, pre[k]);
+    }
+    AT vf[CT][4];
+    if (a.vfin) {
+#pragma unroll
+        for (int k = 0; k < CT; ++k) {
+            const int L = min(li + k * LPP, NT - 1);
+            const int y = min(y0 + L % TY, gy - 1), z = min(z0 + L / TY, gz - 1);
+            ld4(a.vfin, z * P + (long)y * GX + x, vf[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < C0; ++k) {
+        const int L = li + k * LPP;
+        const int y = y0 - 2 + L % RY0, z = z0 - 2 + L / RY0;
+        const bool in = y >= 0 && y < gy && z >= 0 && z < gz;
+        if (L < NL0) lev0[L * LPL + lx] = in ? AV4{pre[k][0], pre[k][1], pre[k][2], pre[k][3]} : AV4{0, 0, 0, 0};
+    }
+    __syncthreads();
+    // one step on a line of an LDS region with RY lines per z slice
+    auto step = [&](const AV4 *src, int line, int RY, AT a0, AT a1) -> AV4 {
+        const AV4 cc = src[line * LPL + lx];
+        const AV4 ym = src[(line - 1) * LPL + lx], yp = src[(line + 1) * LPL + lx];
+        const AV4 zm = src[(line - RY) * LPL + lx], zp = src[(line + RY) * LPL + lx];
+        const AT *sl = reinterpret_cast<const AT *>(src + line * LPL);
+        const AT xl = x > 0 ? sl[max(x - 1, 0)] : AT(0);
+        const AT xr = x + 4 < GX ? sl[min(x + 4, GX - 1)] : AT(0);
+        const AT xv[6] = {xl, cc[0], cc[1], cc[2], cc[3], xr};
+        AV4 w;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            AT s = AT(0);
+            s += c[0] * zm[i];
+            s += c[1] * ym[i];
+            s += c[2] * xv[i];
+            s += c[3] * xv[i + 1];
+            s += c[4] * xv[i + 2];
+            s += c[5] * yp[i];
+            s += c[6] * zp[i];
+            w[i] = a0 * s + a1 * xv[i + 1];
+        }
+        return w;
+    };
+    // the first step on the tile's lines and one line around them
+#pragma unroll
+    for (int k = 0; k < C1; ++k) {
+        const int L = li + k * LPP;
+        if (L < NL1) {
+            const int ly = L % RY1, lz = L / RY1;
+            const int y = y0 - 1 + ly, z = z0 - 1 + lz;
+            AV4 w = AV4{0, 0, 0, 0};
+            if (y >= 0 && y < gy && z >= 0 && z < gz) w = step(lev0, (ly + 1) + RY0 * (lz + 1), RY0, a.a0[0], a.a1[0]);
+            lev1[L * LPL + lx] = w;
+        }
+    }
+    __syncthreads();
+    // the second step on the tile's lines, stored
+    const bool aux = (a.aux >> 1) & 1;
+#pragma unroll
+    for (int k = 0; k < CT; ++k) {
+        const int L = li + k * LPP;
+        if (L < NT) {
+            const int ly = L % TY, lz = L / TY;
+            const int y = y0 + ly, z = z0 + lz;
+            if (y < gy && z < gz) {
+                AV4 w = step(lev1, (ly + 1) + RY1 * (lz + 1), RY1, a.a0[1], a.a1[1]);
+                if (aux) {
+                    const AV4 xin = lev0[((ly + 2) + RY0 * (lz + 2)) * LPL + lx];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) w[i] += a.a2[1] * xin[i];
+                }
+                AT o[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = a.vfin ? vf[k][i] - w[i] : w[i];
+                st4(a.out, z * P + (long)y * GX + x, o);
+            }
+        }
+    }
+}
+
+template <typename VT, typename XT, int TY, int TZ, int GX>
+hipError_t boxt_launch(const DevCSR &A, const VT *ptab, const MarchPtrs &p, int remap, hipStream_t st) {
+    using AT = typename Arith<XT>::T;
+    MarchArgs<XT> a;
+    a.in = (const XT *)p.in;
+    a.out = (XT *)p.out;
+    a.vfin = (const XT *)p.vfin;
+    for (int k = 0; k < kMarchMax; ++k) {
+        a.a0[k] = (AT)p.a0[k];
+        a.a1[k] = (AT)p.a1[k];
+        a.a2[k] = (AT)p.a2[k];
+    }
+    a.aux = p.aux;
+    a.gx = GX;
+    a.gy = A.box[1];
+    a.gm = A.box[2];
+    a.ntx = 1;
+    a.nty = (a.gy + TY - 1) / TY;
+    a.cz = TZ;
+    const long nt = (long)a.nty * ((a.gm + TZ - 1) / TZ);
+    if (nt == 0) return hipSuccess;
+    if (nt >= (1L << 31)) return hipErrorInvalidValue;
+    a.ntiles = (int)nt;
+    a.pint = A.box_pint;
+    hipLaunchKernelGGL((k_chain_boxt<VT, XT, TY, TZ, GX>), dim3((unsigned)nt), dim3(256), 0, st, a, ptab, remap);
+    return hipGetLastError();
+}
+
 template <typename VT, typename XT, int ND, int S, int TX, int TY>
 hipError_t march_launch(const DevCSR &A, const VT *ptab, const MarchPtrs &p, int cz, int remap, hipStream_t st) {
     using AT = typename Arith<XT>::T;
@@ -1634,6 +1851,17 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int v
                     return hipErrorInvalidValue;  // built only with the value-coded copy
             }
 #undef PP_DIAPV_ND
+            return hipGetLastError();
+        }
+        case CV_BOX: {
+            if (!box_step_ok(A)) return hipErrorInvalidValue;
+            const int nb = (int)((A.n + 1023L) / 1024L);
+            if (A.box_nd == 7)
+                hipLaunchKernelGGL((k_chain_box<VT, XT, 7>), dim3(nb), dim3(256), 0, st, a, diap_tab<VT>(A), A.box_pint,
+                                   A.box[0], A.box[1], A.box[2], nb, remap);
+            else
+                hipLaunchKernelGGL((k_chain_box<VT, XT, 5>), dim3(nb), dim3(256), 0, st, a, diap_tab<VT>(A), A.box_pint,
+                                   A.box[0], A.box[1], 1, nb, remap);
             return hipGetLastError();
         }
         case CV_SELLD:
@@ -2385,7 +2613,46 @@ hipError_t launch_chain_pair(const DevCSR &A, int prec, const PairPtrs &p, int r
 // x-y tile (x tile in 2-D) of the marching kernel
 constexpr int kMarchTX3 = 64, kMarchTY3 = 4, kMarchTX2 = 256;
 
+bool box_step_ok(const DevCSR &A) {
+    return (A.box_nd == 5 || A.box_nd == 7) && A.box_pint >= 0 && A.pbyte && A.ptab64 && A.ptab32 && A.box[0] > 0 &&
+           A.box[0] % 4 == 0 && (long)A.box[0] * A.box[1] * A.box[2] == A.n && A.box_pint < A.npat &&
+           A.npat * A.box_nd <= kMaxPatEntries;
+}
+
+bool box_tile_ok(const DevCSR &A, int prec) {
+    return box_step_ok(A) && A.box_nd == 7 && (prec == 0 || prec == 1) &&
+           (A.box[0] == 64 || A.box[0] == 128 || A.box[0] == 256);
+}
+
+// tiles (y x z lines) of the whole-line kernel: two workgroups per CU where
+// the LDS allows
+hipError_t launch_boxt(const DevCSR &A, int prec, const MarchPtrs &p, int remap, hipStream_t st) {
+    if (!box_tile_ok(A, prec) || p.nsteps != 2 || (p.aux & 1) || !p.in || !p.out || p.out == p.in || p.out == p.vfin)
+        return hipErrorInvalidValue;
+    if (prec == 1) {
+        switch (A.box[0]) {
+            case 64:
+                return boxt_launch<float, float, 8, 8, 64>(A, A.ptab32, p, remap, st);
+            case 128:
+                return boxt_launch<float, float, 8, 4, 128>(A, A.ptab32, p, remap, st);
+            case 256:
+                return boxt_launch<float, float, 4, 4, 256>(A, A.ptab32, p, remap, st);
+        }
+    } else {
+        switch (A.box[0]) {
+            case 64:
+                return boxt_launch<double, double, 8, 4, 64>(A, A.ptab64, p, remap, st);
+            case 128:
+                return boxt_launch<double, double, 4, 4, 128>(A, A.ptab64, p, remap, st);
+            case 256:
+                return boxt_launch<double, double, 4, 2, 256>(A, A.ptab64, p, remap, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_chain_march(const DevCSR &A, int prec, const MarchPtrs &p, int cz, int remap, hipStream_t st) {
+    if (p.shape == 1) return launch_boxt(A, prec, p, remap, st);
     if (!A.pbyte || !p.in || !p.out || (A.box_nd != 5 && A.box_nd != 7) || A.npat * A.box_nd > kMaxPatEntries ||
         (long)A.box[0] * A.box[1] * A.box[2] != A.n || p.out == p.in || p.out == p.vfin || p.nsteps < 2 ||
         p.nsteps > kMarchMax || (p.aux & 1) || cz < 1 || (A.box_nd == 5 && A.box[2] != 1))
@@ -2892,7 +3159,7 @@ const char *chain_variant_name(int v) {
                                           "vec8x4",  "vec16x2",  "vec16x4", "vec32x2",   "tilev8x1",
                                           "tilev16x2", "vk2x4x4", "vk4x4x2", "vk8x4x1", "vk16x2x2", "persist8",
                                           "tileb8x1", "tileb16x2", "sell64", "sell64t", "sell64x2", "sell64x4", "sell64d16", "sell64d16x4",
-                                              "dia2",   "dia1", "diac", "diap", "tile8b2", "tile8b4", "diapv"};
+                                              "dia2",   "dia1", "diac", "diap", "tile8b2", "tile8b4", "diapv", "box"};
     return (v >= 0 && v < CV_COUNT) ? names[v] : "?";
 }
 

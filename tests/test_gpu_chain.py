@@ -144,9 +144,10 @@ def test_cfg2_full_size_p_chain(pp):
     box = (128, 128, 128)
     for prec, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
         # the tuned kernel, and the ones it competes with
-        for variant in (None, "diap", "diapv", "dia1", "sell64"):
+        for variant in (None, "diap", "diapv", "dia1", "sell64", "box"):
             if variant is not None:
-                M.set_variant(prec, [pp.chain_variant_name(k) for k in range(31)].index(variant), 1)
+                names = [pp.chain_variant_name(k) for k in range(pp.N_CHAIN_VARIANTS)]
+                M.set_variant(prec, names.index(variant), 1)
             say("cfg2 full size p chain", prec, variant or "tuned", M.variant(prec)[0])
             got = host(pp.apply(poly, M, dev(v, dt), "p"))
             if prec == "fp64":
@@ -168,7 +169,7 @@ def test_bad_arguments_rejected(pp):
         pp.Matrix(np.array([0, 2, 1], dtype=np.int32), np.array([0, 1], dtype=np.int32), np.ones(2))  # rowptr
 
 
-@pytest.mark.parametrize("variant", range(31))
+@pytest.mark.parametrize("variant", range(32))
 def test_every_chain_variant_matches_oracle(pp, variant):
     # each kernel variant the autotuner may pick, with and without the XCD order
     for name in ["ragged_5000", "randsparse_20000", "convdiff3d_20"]:
@@ -189,8 +190,10 @@ def test_every_chain_variant_matches_oracle(pp, variant):
             except Exception as exc:
                 # the sliced-ELL copy is only built when its padding is small,
                 # the diagonal format only for matrices on few diagonals
-                # and the column-banded copies only for large matrices without a diagonal format
+                # and the column-banded copies only for large matrices without a diagonal format,
+                # the box kernel only for constant-coefficient box stencils
                 assert ("sliced-ELL" in str(exc) and name == "ragged_5000") or \
+                    ("box kernel" in str(exc) and name != "convdiff3d_20") or \
                     (any(k in str(exc) for k in ("diagonal-format", "value-coded", "pattern-coded"))
                      and name != "convdiff3d_20") or \
                     ("column-banded" in str(exc) and name == "convdiff3d_20"), exc
@@ -354,13 +357,13 @@ def test_autotuner_picks_a_valid_variant(pp):
     assert M.variant("fp32")[0] is None  # nothing tuned or set yet
     for prec in ("fp64", "fp32", "bf16"):
         name, remap, us = M.tune(prec)
-        assert name in [pp.chain_variant_name(v) for v in range(31)] and remap in (0, 1) and us > 0
+        assert name in [pp.chain_variant_name(v) for v in range(pp.N_CHAIN_VARIANTS)] and remap in (0, 1) and us > 0
         assert M.variant(prec) == (name, remap, us)
     M.set_variant("fp32", 3, 0)
     assert M.variant("fp32") == (pp.chain_variant_name(3), 0, 0.0)
 
 
-@pytest.mark.parametrize("variant", ["diap", "diapv", "dia1", "sell64", "sell64d16", "tile8x1"])
+@pytest.mark.parametrize("variant", ["diap", "diapv", "dia1", "sell64", "sell64d16", "tile8x1", "box"])
 def test_chain_bytes_hand_count(pp, variant):
     # phi(A)v of two real roots is two launches: pi1 = v - c1 A v (input read,
     # output written) and phi = v - (pi1 - c2 A pi1) (input, final vector v
@@ -374,7 +377,7 @@ def test_chain_bytes_hand_count(pp, variant):
     n, nnz = csr.n, csr.nnz
     A = csr.to_scipy().tocsr()
     M = pp.Matrix.from_csr(csr)
-    names = [pp.chain_variant_name(k) for k in range(31)]
+    names = [pp.chain_variant_name(k) for k in range(pp.N_CHAIN_VARIANTS)]
     offs = [-400, -20, -1, 0, 1, 20, 400]
     dense = np.zeros((n, 7))
     for d, o in enumerate(offs):
@@ -389,6 +392,8 @@ def test_chain_bytes_hand_count(pp, variant):
         M.set_variant(prec, names.index(variant), 1)
         if variant in ("diap", "diapv"):
             F = n + npat * 7 * sv
+        elif variant == "box":
+            F = 7 * sv  # the interior row's coefficients
         elif variant == "dia1":
             F = -(-n // 256) * 256 * 7 * sv
         elif variant.startswith("sell64"):

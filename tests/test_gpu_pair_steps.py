@@ -247,8 +247,10 @@ def test_march_matches_oracle(pp, name, steps):
 
 def test_march_chain_bytes_and_launches(pp):
     # phi(A)v of 8 real roots, 4 steps per launch: 2 launches, each reading
-    # its input and the pattern bytes once and writing its result; the last
-    # also reads the final vector: 2 F + 5 n s bytes
+    # its input and its matrix data once and writing its result; the last
+    # also reads the final vector: 2 F + 5 n s bytes. On this
+    # constant-coefficient stencil the matrix data is the interior row's 7
+    # coefficients (no pattern bytes are read)
     csr = convdiff3d(20, 10, 10, 10)
     M = pp.Matrix.from_csr(csr)
     n = csr.n
@@ -257,7 +259,7 @@ def test_march_chain_bytes_and_launches(pp):
         M.tune(prec)
         M.set_pair_steps(False, prec)
         M.set_march(4, prec)
-        F = n + 27 * 7 * sv
+        F = 7 * sv
         say("march bytes", prec)
         assert pp.chain_bytes(poly, M, "phi", prec) == (2 * F + 5 * n * sx, 2)
         M.set_march(3, prec)  # groups of 3, 3 and 2
