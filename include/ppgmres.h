@@ -96,6 +96,15 @@ typedef struct {
                             (each a graph with opts->graphs); between segments the host reads one
                             flag and skips the rest of the cycle once every pair has stopped.
                             0 = the whole cycle as one segment. Ignored by pp_solve. */
+    int lookahead;       /* pp_solve: 1 = after queueing an Arnoldi step, also queue phi(A) of the
+                            next basis vector before the host waits for the step's Hessenberg
+                            column (the GPU keeps working while the host runs the Givens
+                            update), unless the shortcut residuals so far predict that the step
+                            ends the cycle (its residual times the last step's reduction factor,
+                            within a factor 2 of the target). A wrong guess costs one phi(A)
+                            application, whose result is discarded; the iterates are the same
+                            either way. 0 = wait for the column first. Ignored by
+                            pp_batch_solve. */
 } pp_solve_opts;
 
 /* Result of pp_solve. */
@@ -110,6 +119,8 @@ typedef struct {
     double relres;         /* true ||b - A x|| / ||b|| in FP64 */
     double relres_shortcut;/* last cycle's ||beta e1 - Hbar z|| / ||b|| */
     double t_solve_s;
+    int lookahead_discarded; /* phi(A) applications queued ahead (pp_solve_opts.lookahead) that the
+                                cycle did not need; not counted in mvps */
 } pp_info;
 
 /* ------------------------------------------------------------------ */

@@ -33,13 +33,14 @@ class StchOpts(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("m", c_int), ("max_cycles", c_int), ("tol", c_double), ("inner", c_int),
                 ("stall_cycles", c_int), ("inner_eta", c_double), ("history", P_double), ("history_cap", c_int),
-                ("new_poly_degree", c_int), ("new_poly_add", c_int), ("graphs", c_int), ("graph_steps", c_int)]
+                ("new_poly_degree", c_int), ("new_poly_add", c_int), ("graphs", c_int), ("graph_steps", c_int),
+                ("lookahead", c_int)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", c_int), ("cycles", c_int), ("iters", c_int), ("fp64_cycles", c_int),
                 ("mvps", c_int64), ("vops", c_int64), ("dots", c_int64), ("relres", c_double),
-                ("relres_shortcut", c_double), ("t_solve_s", c_double)]
+                ("relres_shortcut", c_double), ("t_solve_s", c_double), ("lookahead_discarded", c_int)]
 
 
 # name -> (restype, argtypes); must mirror include/ppgmres.h

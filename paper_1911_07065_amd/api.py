@@ -386,11 +386,13 @@ def chain_bytes(poly: Poly, A: Matrix, kind: str = "phi", prec: str = "fp32"):
 
 def solve(poly: Poly | None, A: Matrix, b, tol: float = 1e-8, m: int = 50, max_cycles: int = 1000,
           inner: str = "fp32", stall_cycles: int = 5, x: torch.Tensor | None = None, inner_eta: float = 0.0,
-          new_poly_degree: int = 0, new_poly_add: bool = True):
+          new_poly_degree: int = 0, new_poly_add: bool = True, lookahead: bool = True):
     """x solving A x = b by PP-GMRES(m) with FP64 refinement. Returns (x, info dict);
     info["history"] holds the true relative residual before each cycle and at the end.
     new_poly_degree > 0: a new polynomial of that degree from the current residual
-    at every cycle (section 5.2, ChPoly); poly may then be None."""
+    at every cycle (section 5.2, ChPoly); poly may then be None. lookahead: queue the
+    next Arnoldi step's phi(A) before reading the current step's Hessenberg column
+    (same iterates; see pp_solve_opts)."""
     b = _dev_tensor(b, torch.float64, A.device)
     if b.numel() != A.n:
         raise ValueError("right-hand side length")
@@ -399,7 +401,7 @@ def solve(poly: Poly | None, A: Matrix, b, tol: float = 1e-8, m: int = 50, max_c
     hist = np.zeros(max(int(max_cycles), 0) + 2)
     opts = SolveOpts(int(m), int(max_cycles), float(tol), PREC[inner], int(stall_cycles), float(inner_eta),
                      hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hist.size, int(new_poly_degree),
-                     int(bool(new_poly_add)))
+                     int(bool(new_poly_add)), 0, 0, int(bool(lookahead)))
     info = SolveInfo()
     st = check(lib.pp_solve(poly.handle if poly is not None else None, A.handle, _ptr(b), _ptr(x), ctypes.byref(opts), _stream(A.device),
                             ctypes.byref(info)), "pp_solve")

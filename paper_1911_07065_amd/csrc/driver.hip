@@ -2584,6 +2584,14 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
     // r = b
     HIP_TRY(hipMemcpyAsync(A->r64, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     double beta = bnorm;
+    // marks the arrival of a Hessenberg column in host memory
+    struct Ev {
+        hipEvent_t e = nullptr;
+        ~Ev() {
+            if (e) (void)hipEventDestroy(e);
+        }
+    } col_ready;
+    HIP_TRY(hipEventCreateWithFlags(&col_ready.e, hipEventDisableTiming));
     int prec = opts->inner;
     std::vector<double> hist;
     GivensLS ls;
@@ -2638,9 +2646,23 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
         const double target = std::max(opts->tol * bnorm, eta * beta);
         double fro2 = 0.0;
         int k = 0;
+        // lookahead: phi(A) V[:, j] already queued; the last shortcut
+        // residual and the last step's reduction factor
+        bool ahead = false;
+        double r_last = beta, rate = 1.0;
         for (int j = 0; j < m; ++j) {
-            PP_TRY(run_program(A, p, PP_APPLY_PHI, prec, vcol(ws, prec, j), vcol(ws, prec, j + 1), st));
-            PP_TRY(cgs2_step(A, prec, ws, j, st));
+            if (!ahead) PP_TRY(run_program(A, p, PP_APPLY_PHI, prec, vcol(ws, prec, j), vcol(ws, prec, j + 1), st));
+            PP_TRY(cgs2_step(A, prec, ws, j, st, nullptr, false));
+            HIP_TRY(hipMemcpyAsync(A->hpin, A->H(), sizeof(double) * (j + 2), hipMemcpyDeviceToHost, st));
+            HIP_TRY(copy_barrier_flag(A, st));
+            HIP_TRY(hipEventRecord(col_ready.e, st));
+            // V[:, j+1] is final once the step's kernels ran: queue the next
+            // step's product unless this step is expected to end the cycle
+            ahead = opts->lookahead && j + 1 < m && r_last * rate > 2.0 * target;
+            if (ahead)
+                PP_TRY(run_program(A, p, PP_APPLY_PHI, prec, vcol(ws, prec, j + 1), vcol(ws, prec, j + 2), st));
+            HIP_TRY(hipEventSynchronize(col_ready.e));
+            PP_TRY(check_barrier_flag(A));
             inf.mvps += mv_phi;
             inf.dots += 2 * (j + 1) + 1;
             inf.vops += 4 * (j + 1) + 2 + chain_launches(p, PP_APPLY_PHI);
@@ -2658,12 +2680,17 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
             const double shortcut = ls.add_column(A->hpin);
             k = j + 1;
             inf.relres_shortcut = shortcut / bnorm;
+            rate = r_last > 0.0 ? shortcut / r_last : 1.0;
+            r_last = shortcut;
             const bool lucky = A->hpin[j + 1] <= kBreakdownTol * std::sqrt(fro2);
             if (lucky || shortcut <= target) break;
         }
+        if (ahead) inf.lookahead_discarded++;  // a queued product the cycle did not need
         if (k > 0) {
             ls.solve(zh.data());
-            // stage through pinned memory (the stream is idle here: cgs2_step synchronised)
+            // stage through pinned memory: the host reads the staging slot
+            // below only after the stream passed the column's copy; a queued
+            // product may still run, and the upload is ordered after it
             std::memcpy(A->hpin + A->ldp, zh.data(), sizeof(double) * k);
             HIP_TRY(hipMemcpyAsync(A->z(), A->hpin + A->ldp, sizeof(double) * k, hipMemcpyHostToDevice, st));
             // dy = V_k z (z solves min ||beta e1 - Hbar z||, so it carries beta);

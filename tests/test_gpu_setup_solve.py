@@ -189,6 +189,30 @@ def test_cfg1_solve_matches_oracle(pp, inner):
         assert abs(info["iters"] - io.iters) <= 1
 
 
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16"])
+def test_lookahead_keeps_the_iterates(pp, inner):
+    # queueing the next step's phi(A) before the host reads the Hessenberg
+    # column changes when work is queued, not what is computed: the same x bit
+    # for bit, the same counters; the cycles run to their own stopping points
+    csr = convdiff3d(24, 10, 10, 10)
+    b = rhs(csr.n, 1)
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.setup(M, dev(start_vector(csr.n, 2)), 12)
+    say("lookahead", inner)
+    runs = {}
+    for la in (False, True):
+        x, info = pp.solve(poly, M, dev(b), tol=1e-10, m=20, inner=inner, lookahead=la)
+        runs[la] = (host(x), info)
+    (x0, i0), (x1, i1) = runs[False], runs[True]
+    assert i0["status"] == 0 and i1["status"] == 0
+    assert np.array_equal(x0, x1)
+    for k in ("cycles", "iters", "mvps", "dots", "vops", "fp64_cycles"):
+        assert i0[k] == i1[k], k
+    assert i0["lookahead_discarded"] == 0 and 0 <= i1["lookahead_discarded"] <= i1["cycles"]
+    rel = np.linalg.norm(b - csr.to_scipy() @ x1) / np.linalg.norm(b)
+    assert rel <= 1e-10
+
+
 def test_stability_check_matches_oracle(pp):
     csr = convdiff2d(50, 1.0)
     A = csr.to_scipy()
