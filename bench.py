@@ -91,6 +91,12 @@ def chain_kernel_name(variant):
         return "k_chain_dia_nd<float,float,nd> (dia1: diagonal format, one row per lane, fused chain update)"
     if v.startswith("dia"):
         return f"k_chain_dia<float,float,...> ({v}: diagonal format, fused chain update)"
+    if v == "box":
+        return ("k_chain_box<float,float,7> (box: constant-coefficient box stencil, no per-row matrix data, "
+                "4 points of a grid line per lane, fused chain update)")
+    if v == "box/tile2":
+        return ("k_chain_boxt<float,float,8,4,128> (two chain steps per launch on tiles of 8 x 4 whole grid "
+                "lines, the input and the first step staged in LDS)")
     return f"chain step, variant {v}"
 
 
@@ -106,17 +112,21 @@ def recorded_traffic(prec, variant, remap):
     if rec.get("source_sha256") != kernel_source_hash():
         return None
     for e in rec.get("kernels", []):
-        if e["prec"] == prec and e["variant"] == variant and e["remap"] == remap:
+        # remap -1: launches in the tuned workgroup order (two-step tiles)
+        if e["prec"] == prec and e["variant"] == variant and e["remap"] in (remap, -1):
             return e
     return None
 
 
 def traffic_probe(pp, torch, np, M, n):
     """Launch sequence for the counter runs: a plain copy of COPY_BYTES (to
-    calibrate FETCH_SIZE and WRITE_SIZE), then for each sliced-ELL and
-    diagonal-format variant, precision and XCD order (remap 1, then 0) 4
-    phi applications of an 8-root real polynomial (32 launches of exactly one
-    chain step each: the input read and gathered, the output written)."""
+    calibrate FETCH_SIZE and WRITE_SIZE), then for each sliced-ELL,
+    diagonal-format and box variant, precision and XCD order (remap 1, then
+    0) 4 phi applications of an 8-root real polynomial (32 launches of
+    exactly one chain step each: the input read and gathered, the output
+    written), then, where they apply, the same with two steps per launch on
+    whole grid lines ("box/tile2": 16 launches, each reading its input once
+    and writing its second step's result)."""
     x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     for _ in range(3):
@@ -130,14 +140,28 @@ def traffic_probe(pp, torch, np, M, n):
         v = torch.as_tensor(np.random.default_rng(5).standard_normal(n), device="cuda").to(dt)
         out = torch.empty_like(v)
         for vi, name in enumerate(names):
-            if not (name.startswith("sell") or name.startswith("dia")):
+            if not (name.startswith("sell") or name.startswith("dia") or name == "box"):
                 continue
             for remap in (1, 0):  # the counter summary splits each kernel's dispatches in this order
-                M.set_variant(prec, vi, remap)
+                try:
+                    M.set_variant(prec, vi, remap)
+                except Exception as exc:  # a copy this matrix does not have
+                    log("probe", prec, name, "skipped:", exc)
+                    break
                 for _ in range(4):
                     pp.apply(poly, M, v, "phi", out=out)
                 torch.cuda.synchronize()
                 log("probe", prec, name, f"remap {remap}: 32 launches")
+        try:
+            M.set_variant(prec, names.index("box"), 1)
+            M.set_march_shape(1, prec)
+        except Exception as exc:
+            log("probe", prec, "box/tile2 skipped:", exc)
+            continue
+        for _ in range(4):
+            pp.apply(poly, M, v, "phi", out=out)
+        torch.cuda.synchronize()
+        log("probe", prec, "box/tile2: 16 launches")
     log("kernel sources sha256", kernel_source_hash())
 
 
@@ -165,6 +189,21 @@ def chain_rate(pp, torch, np, M, poly, prec, dt, reps, kind="phi", n=None):
     return {"variant": M.variant(prec)[0], "ms": ms, "launches": launches, "launch_us": ms * 1e3 / launches,
             "bytes": by, "bytes_per_launch": by / launches, "GBps": by / (ms * 1e-3) / 1e9,
             "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+
+
+def launch_floor_us(pp, torch, blocks, reps=200):
+    """Time per launch of back-to-back empty kernels of `blocks` workgroups
+    (pp_launch_floor), HIP events on the stream they run on."""
+    stream = torch.cuda.current_stream()
+    pp.launch_floor(20, blocks)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    pp.launch_floor(reps, blocks)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
 
 
 def scale_leg(pp, torch, np, N=256, nroots=16, reps=10):
@@ -200,7 +239,8 @@ def out_of_mall_leg(pp, torch, np, reps=5, nroots=8):
     """One point per chain-kernel family whose working set is well above the
     256 MB MALL, so each launch streams from HBM: the pattern-coded diagonal
     kernel (diapv) at 384^3 (FP32: input + output + pattern bytes = 509 MB
-    per step), the sliced-ELL kernel (sell64) and the CSR row-tile kernel
+    per step), the constant-coefficient box kernel at 384^3 (input + output =
+    453 MB), the sliced-ELL kernel (sell64) and the CSR row-tile kernel
     (tile8x1) at 256^3 (FP32: 1.08 GB of matrix and vectors per step). Each
     is forced (no tuning), phi(A)v of 8 real roots, HIP events, bytes from
     pp_chain_bytes; FP32 and FP64."""
@@ -209,7 +249,7 @@ def out_of_mall_leg(pp, torch, np, reps=5, nroots=8):
     out = {}
     names = [pp.chain_variant_name(k) for k in range(pp.N_CHAIN_VARIANTS)]
     poly = pp.poly_from_roots(np.linspace(2.0, 11.0, nroots), keep_order=True)
-    for N, variants in ((384, ("diapv",)), (256, ("sell64", "tile8x1"))):
+    for N, variants in ((384, ("diapv", "box")), (256, ("sell64", "tile8x1"))):
         log("out-of-MALL leg: generating", N)
         csr = convdiff3d(N, 10.0, 10.0, 10.0)
         n, nnz = csr.n, csr.nnz
@@ -549,8 +589,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-reps", type=int, default=3, help="oracle runs on the host (median; capped at ~100 s)")
     ap.add_argument("--chain-variant", default=None,
-                    help="pin the chain kernel (e.g. diac) for both precisions instead of autotuning, remap on; "
-                         "used to profile the kernel an unprofiled run picks")
+                    help="pin the chain kernel instead of autotuning, remap on: a variant name for both precisions "
+                         "(e.g. diac) or fp32=<v>,fp64=<w>; <v>/tile2 adds two steps per launch on whole grid "
+                         "lines. Used to profile what an unprofiled run picks (the tracer's launch overhead "
+                         "shifts the tuner's choices)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the differentiation and batched legs")
     ap.add_argument("--leg", default=None,
@@ -605,10 +647,21 @@ def main():
         t_tune = time.perf_counter() - t0
     log("matrix handle", f"create {t_create * 1e3:.1f} ms", f"tune {t_tune * 1e3:.1f} ms")
     if args.chain_variant:
-        vi = [pp.chain_variant_name(k) for k in range(pp.N_CHAIN_VARIANTS)].index(args.chain_variant)
-        for prec in ("fp32", "fp64"):
-            M.set_variant(prec, vi, 1)
-        log("chain variant pinned:", args.chain_variant)
+        # "v" for both precisions, or "fp32=v,fp64=w"; "v/tile2": two steps
+        # per launch on whole grid lines after single steps of v
+        names = [pp.chain_variant_name(k) for k in range(pp.N_CHAIN_VARIANTS)]
+        spec = {}
+        for part in args.chain_variant.split(","):
+            if "=" in part:
+                prec, v = part.split("=", 1)
+                spec[prec] = v
+            else:
+                spec["fp32"] = spec["fp64"] = part
+        for prec, v in spec.items():
+            M.set_variant(prec, names.index(v.split("/")[0]), 1)
+            if v.endswith("/tile2"):
+                M.set_march_shape(1, prec)
+        log("chain variant pinned:", spec)
     bd = torch.as_tensor(b, device="cuda")
     v0d = torch.as_tensor(v0, device="cuda")
     torch.cuda.synchronize()
@@ -660,6 +713,8 @@ def main():
             f"{rf['GBps']:.0f} GB/s own bytes")
 
     k32 = phi["fp32"]
+    if M.march("fp32")[0] == 2 and M.march_shape("fp32") == 1:
+        k32["variant"] = "box/tile2"  # two steps per launch on whole grid lines
     tr = recorded_traffic("fp32", k32["variant"], k32["remap"])
     log("recorded traffic", tr)
     roofline = {
@@ -685,6 +740,20 @@ def main():
                  "bytes_per_launch": int(round(phi["fp64"]["bytes_per_launch"])),
                  "achieved": round(phi["fp64"]["GBps"], 1), "frac": round(phi["fp64"]["frac"], 4)},
     }
+    # the kernel boundary: empty launches of the dominant launch's grid
+    # (two-step tiles: 8 x 4 lines of the 128 x 128 planes; one step: 1024
+    # points per workgroup)
+    blocks = -(-N // 8) * -(-N // 4) if k32["variant"] == "box/tile2" else -(-n // 1024)
+    floor = launch_floor_us(pp, torch, blocks)
+    hbm_us = k32["bytes_per_launch"] / (HBM_PEAK_GBPS * 1e3)
+    roofline["launch_floor"] = {
+        "blocks": blocks, "us": round(floor, 3), "hbm_us": round(hbm_us, 3),
+        "bound_us": round(floor + hbm_us, 3), "frac_of_bound": round((floor + hbm_us) / k32["launch_us"], 4),
+        "note": ("back-to-back empty kernels of the dominant launch's grid (pp_launch_floor, HIP events): the "
+                 "cost of a kernel boundary; bound_us = that floor + the launch's bytes at peak HBM bandwidth, a "
+                 "lower bound on one launch that the HBM fraction alone does not show at this size")}
+    log("launch floor", blocks, "blocks", f"{floor:.2f} us", "bound", f"{floor + hbm_us:.2f} us",
+        "achieved", f"{k32['launch_us']:.2f} us")
 
     extras = {}
     if not args.no_extras:

@@ -99,12 +99,14 @@ typedef struct {
     int lookahead;       /* pp_solve: 1 = after queueing an Arnoldi step, also queue phi(A) of the
                             next basis vector before the host waits for the step's Hessenberg
                             column (the GPU keeps working while the host runs the Givens
-                            update), unless the shortcut residuals so far predict that the step
-                            ends the cycle (its residual times the last step's reduction factor,
-                            within a factor 2 of the target). A wrong guess costs one phi(A)
-                            application, whose result is discarded; the iterates are the same
-                            either way. 0 = wait for the column first. Ignored by
-                            pp_batch_solve. */
+                            update), unless the shortcut residuals so far say the step may end
+                            the cycle: the last residual times the last step's reduction factor
+                            must exceed the target by more than the ratio of one phi(A)
+                            application's time (tuned launch time x launches) to a host round
+                            trip (15 us), at least 2; never on a cycle's first step. A wrong
+                            guess costs one phi(A) application,
+                            whose result is discarded; the iterates are the same either way.
+                            0 = wait for the column first. Ignored by pp_batch_solve. */
 } pp_solve_opts;
 
 /* Result of pp_solve. */
@@ -430,6 +432,14 @@ pp_status pp_apply_noalloc(pp_poly p, pp_matrix A, int kind, int prec, const voi
 pp_status pp_chain_bytes(pp_poly p, pp_matrix A, int kind, int prec, void *stream, int64_t *bytes,
                          int64_t *launches);
 
+/* Launch floor, a measurement aid beside pp_chain_bytes: queue `launches`
+ * back-to-back launches of an empty kernel of `blocks` workgroups of 256
+ * threads on the stream (nothing is read or written). Timing them with
+ * events on the same stream gives the cost of a kernel boundary at that grid
+ * size, which bounds a chain step from below however few bytes it moves.
+ * PP_EINVAL unless 1 <= launches <= 100000 and 1 <= blocks < 2^31. */
+pp_status pp_launch_floor(int launches, int64_t blocks, void *stream);
+
 /* Solve A x = b by PP(d)-GMRES(m) (Algorithm 4 step 2), x_0 = 0.
  * Each cycle starts from the true residual r = b - A x computed in FP64;
  * the cycle runs GMRES(m) on phi(A) in opts->inner precision and adds
@@ -441,6 +451,21 @@ pp_status pp_chain_bytes(pp_poly p, pp_matrix A, int kind, int prec, void *strea
  * Returns PP_OK or PP_NOCONV (x is then the last iterate); info may be NULL. */
 pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_solve_opts *opts,
                    void *stream, pp_info *info);
+
+/* Device memory of pp_solve, for a caller that must bound it beforehand. The
+ * handle owns the solve's workspace and allocates it on first use (then keeps
+ * it for later calls): the Krylov basis of m + 1 columns and 5 work vectors in
+ * the inner precision and in FP64 (rows padded to a multiple of 64), 5 more
+ * per precision for a composite (double) polynomial, the reduction buffers
+ * of the widest Gram-Schmidt pass and, with ChPoly, each cycle's
+ * Hessenberg matrix (see pp_solve_opts).
+ *   total (host, may be NULL): bytes those buffers occupy for these options;
+ *   additional (host, may be NULL): bytes a pp_solve call with these options
+ *     would allocate on this handle now (0 when it already holds them).
+ * The handle's matrix copies (made by pp_matrix_create) are not included.
+ * PP_EINVAL on a bad argument (p may be NULL only with ChPoly). */
+pp_status pp_solve_workspace_bytes(pp_poly p, pp_matrix A, const pp_solve_opts *opts, int64_t *total,
+                                   int64_t *additional);
 
 /* Stability check of section 3.5: StCh = ||(b - A p(A) b) - pi(A) b|| in
  * FP64. b: device double[n]; result to *stch (host). */

@@ -384,6 +384,23 @@ def chain_bytes(poly: Poly, A: Matrix, kind: str = "phi", prec: str = "fp32"):
     return b.value, l.value
 
 
+def solve_workspace_bytes(poly: Poly | None, A: Matrix, m: int = 50, inner: str = "fp32",
+                          new_poly_degree: int = 0):
+    """(total, additional) device bytes of pp_solve's workspace for these options
+    on this handle (pp_solve_workspace_bytes)."""
+    opts = SolveOpts(int(m), 1, 1e-8, PREC[inner], 0, 0.0, None, 0, int(new_poly_degree), 1, 0, 0, 1)
+    t, a = ctypes.c_int64(), ctypes.c_int64()
+    check(lib.pp_solve_workspace_bytes(poly.handle if poly is not None else None, A.handle, ctypes.byref(opts),
+                                       ctypes.byref(t), ctypes.byref(a)), "pp_solve_workspace_bytes")
+    return t.value, a.value
+
+
+def launch_floor(launches: int, blocks: int, device="cuda"):
+    """Queue `launches` empty kernels of `blocks` workgroups on the current stream
+    (time them with events to measure the cost of a kernel boundary)."""
+    check(lib.pp_launch_floor(int(launches), int(blocks), _stream(device)), "pp_launch_floor")
+
+
 def solve(poly: Poly | None, A: Matrix, b, tol: float = 1e-8, m: int = 50, max_cycles: int = 1000,
           inner: str = "fp32", stall_cycles: int = 5, x: torch.Tensor | None = None, inner_eta: float = 0.0,
           new_poly_degree: int = 0, new_poly_add: bool = True, lookahead: bool = True):

@@ -31,6 +31,11 @@ constexpr int kMaxDegree = 4096;
 // relative inner-cycle target of a reduced-precision cycle (the FP64 outer
 // refinement recomputes the true residual after every cycle)
 constexpr double kInnerEta[3] = {0.0, 1e-5, 1e-2};
+// The host's round trip between an Arnoldi step's column and the next
+// launches (what a queued-ahead phi(A) hides), in microseconds; and the time
+// per chain launch assumed when the precision was not tuned.
+constexpr double kLookaheadGapUs = 15.0;
+constexpr double kLaunchGuessUs = 5.0;
 
 }  // namespace
 
@@ -2517,6 +2522,55 @@ pp_status pp_chain_bytes(pp_poly p, pp_matrix A, int kind, int prec, void *strea
     return PP_OK;
 }
 
+pp_status pp_solve_workspace_bytes(pp_poly p, pp_matrix A, const pp_solve_opts *opts, int64_t *total,
+                                   int64_t *additional) {
+    const int d_new = opts ? opts->new_poly_degree : 0;
+    if (!A || !opts || opts->m < 1 || !valid_prec(opts->inner) || d_new < 0 || d_new > std::min(A->n, kMaxDegree) ||
+        (!p && d_new <= 0)) {
+        set_error("pp_solve_workspace_bytes: bad argument");
+        return PP_EINVAL;
+    }
+    const int64_t ldv = ((int64_t)A->n + 63) / 64 * 64;
+    int64_t tot = 0, add = 0;
+    // Krylov basis (m + 1 columns) and 5 work vectors per precision a cycle
+    // may run in (FP64 always: refinement falls back to it; ChPoly's setup
+    // needs d_new + 1 columns of it), plus 5 more for a composite polynomial
+    auto ws = [&](int prec, int cols) {
+        const int64_t b = ldv * (int64_t)elem_size(prec) * (cols + 1 + 5);
+        const int64_t x = (p && p->inner) ? ldv * (int64_t)elem_size(prec) * 5 : 0;
+        tot += b + x;
+        const Workspace &w = A->ws[prec];
+        if (!(w.m >= cols && w.P0)) add += b + (w.X ? 0 : x);
+        else if (x && !w.X) add += x;
+    };
+    ws(0, std::max(opts->m, d_new));
+    if (opts->inner != PP_F64) ws(opts->inner, opts->m);
+    // reduction buffers (device) for the widest Gram-Schmidt pass
+    const int cols = std::max(std::max(opts->m, d_new) + 1, d_new > 0 ? 2 * d_new + 4 : 0);
+    const int64_t want = std::max(cols + 2, 64);
+    const int64_t red = (int64_t)sizeof(double) * want * (std::max(A->nblk_dot, A->nblk_ud) + 5);
+    tot += red;
+    if (cols + 2 > A->ldp) add += red;
+    // ChPoly: each cycle's setup holds its (d+1) x d Hessenberg matrix
+    if (d_new > 0) {
+        const int64_t h = (int64_t)sizeof(double) * (d_new + 1) * d_new;
+        tot += h;
+        add += h;
+    }
+    if (total) *total = tot;
+    if (additional) *additional = add;
+    return PP_OK;
+}
+
+pp_status pp_launch_floor(int launches, int64_t blocks, void *stream) {
+    if (launches < 1 || launches > 100000 || blocks < 1 || blocks >= (1LL << 31)) {
+        set_error("pp_launch_floor: bad argument");
+        return PP_EINVAL;
+    }
+    for (int i = 0; i < launches; ++i) HIP_TRY(launch_empty((long)blocks, S(stream)));
+    return PP_OK;
+}
+
 pp_status pp_stability_check(pp_poly p, pp_matrix A, const double *b, void *stream, double *stch) {
     if (!p || !A || !b || !stch) {
         set_error("pp_stability_check: bad argument");
@@ -2647,9 +2701,15 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
         double fro2 = 0.0;
         int k = 0;
         // lookahead: phi(A) V[:, j] already queued; the last shortcut
-        // residual and the last step's reduction factor
+        // residual and the last step's reduction factor. A wrong guess costs
+        // a whole phi(A) application, a right one saves a host round trip:
+        // queue ahead only while the predicted residual is above the target
+        // by more than that ratio.
         bool ahead = false;
         double r_last = beta, rate = 1.0;
+        const double t_phi = (double)chain_launches(p, PP_APPLY_PHI) *
+                             (A->tuned_us[prec] > 0.0 ? A->tuned_us[prec] : kLaunchGuessUs);
+        const double margin = std::max(2.0, t_phi / kLookaheadGapUs);
         for (int j = 0; j < m; ++j) {
             if (!ahead) PP_TRY(run_program(A, p, PP_APPLY_PHI, prec, vcol(ws, prec, j), vcol(ws, prec, j + 1), st));
             PP_TRY(cgs2_step(A, prec, ws, j, st, nullptr, false));
@@ -2658,7 +2718,9 @@ pp_status pp_solve(pp_poly p, pp_matrix A, const double *b, double *x, const pp_
             HIP_TRY(hipEventRecord(col_ready.e, st));
             // V[:, j+1] is final once the step's kernels ran: queue the next
             // step's product unless this step is expected to end the cycle
-            ahead = opts->lookahead && j + 1 < m && r_last * rate > 2.0 * target;
+            // (not on a cycle's first step: no reduction factor is known yet,
+            // and a strong polynomial may end the cycle there)
+            ahead = opts->lookahead && j >= 1 && j + 1 < m && r_last * rate > margin * target;
             if (ahead)
                 PP_TRY(run_program(A, p, PP_APPLY_PHI, prec, vcol(ws, prec, j + 1), vcol(ws, prec, j + 2), st));
             HIP_TRY(hipEventSynchronize(col_ready.e));

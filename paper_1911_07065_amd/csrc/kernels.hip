@@ -2613,6 +2613,13 @@ hipError_t launch_chain_pair(const DevCSR &A, int prec, const PairPtrs &p, int r
 // x-y tile (x tile in 2-D) of the marching kernel
 constexpr int kMarchTX3 = 64, kMarchTY3 = 4, kMarchTX2 = 256;
 
+__global__ __launch_bounds__(256) void k_empty() {}
+
+hipError_t launch_empty(long blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_empty, dim3((unsigned)blocks), dim3(256), 0, st);
+    return hipGetLastError();
+}
+
 bool box_step_ok(const DevCSR &A) {
     return (A.box_nd == 5 || A.box_nd == 7) && A.box_pint >= 0 && A.pbyte && A.ptab64 && A.ptab32 && A.box[0] > 0 &&
            A.box[0] % 4 == 0 && (long)A.box[0] * A.box[1] * A.box[2] == A.n && A.box_pint < A.npat &&

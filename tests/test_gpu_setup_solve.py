@@ -213,6 +213,33 @@ def test_lookahead_keeps_the_iterates(pp, inner):
     assert rel <= 1e-10
 
 
+def test_solve_workspace_bytes_bounds_the_allocation(pp):
+    # the query's `additional` covers what a solve allocates on the handle
+    # (device memory seen by the driver), and is 0 once the handle holds it
+    csr = convdiff3d(64, 10, 10, 10)
+    b = rhs(csr.n, 1)
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.setup(M, dev(start_vector(csr.n, 2)), 10)
+    M.tune("fp32")
+    say("workspace bytes")
+    for inner, m in (("fp32", 40), ("fp64", 30)):
+        total, add = pp.solve_workspace_bytes(poly, M, m=m, inner=inner)
+        ldv = -(-csr.n // 64) * 64
+        basis = ldv * (4 if inner == "fp32" else 8) * (m + 1 + 5)
+        assert total >= basis and 0 <= add <= total
+        bd = dev(b)
+        x = torch.empty_like(bd)  # the caller's buffers, allocated before the measurement
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        pp.solve(poly, M, bd, tol=1e-8, m=m, inner=inner, x=x)
+        torch.cuda.synchronize()
+        grew = free0 - torch.cuda.mem_get_info()[0]
+        assert grew <= add + (8 << 20), (inner, grew, add)
+        assert pp.solve_workspace_bytes(poly, M, m=m, inner=inner)[1] == 0
+    with pytest.raises(Exception):
+        pp.solve_workspace_bytes(None, M, m=30)  # no polynomial and no ChPoly
+
+
 def test_stability_check_matches_oracle(pp):
     csr = convdiff2d(50, 1.0)
     A = csr.to_scipy()
