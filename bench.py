@@ -95,8 +95,8 @@ def chain_kernel_name(variant):
         return ("k_chain_box<float,float,7> (box: constant-coefficient box stencil, no per-row matrix data, "
                 "4 points of a grid line per lane, fused chain update)")
     if v == "box/tile2":
-        return ("k_chain_boxt<float,float,8,4,128> (two chain steps per launch on tiles of 8 x 4 whole grid "
-                "lines, the input and the first step staged in LDS)")
+        return ("k_chain_boxt<float,float,16,4,128,1024> (two chain steps per launch on tiles of 16 x 4 whole "
+                "grid lines, 1024 threads, the input and the first step staged in LDS)")
     return f"chain step, variant {v}"
 
 
@@ -191,16 +191,17 @@ def chain_rate(pp, torch, np, M, poly, prec, dt, reps, kind="phi", n=None):
             "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
 
 
-def launch_floor_us(pp, torch, blocks, reps=200):
+def launch_floor_us(pp, torch, blocks, threads=256, reps=200):
     """Time per launch of back-to-back empty kernels of `blocks` workgroups
-    (pp_launch_floor), HIP events on the stream they run on."""
+    of `threads` threads (pp_launch_floor), HIP events on the stream they run
+    on."""
     stream = torch.cuda.current_stream()
-    pp.launch_floor(20, blocks)
+    pp.launch_floor(20, blocks, threads)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    pp.launch_floor(reps, blocks)
+    pp.launch_floor(reps, blocks, threads)
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) * 1e3 / reps
@@ -210,9 +211,10 @@ def scale_leg(pp, torch, np, N=256, nroots=16, reps=10):
     """The chain step on the 3-D convection-diffusion matrix at N^3 = 256^3
     (n = 16.8 M), where one launch streams long enough that its ramp and
     drain are small next to the transfer: a phi polynomial of 16 real roots
-    (16 launches of one step each) timed with HIP events, FP32 and FP64,
-    with the autotuner's variant; rates from the bytes the variant must move
-    (pp_chain_bytes)."""
+    timed with HIP events, FP32 and FP64, with the autotuner's choice (one
+    step per launch, or two on whole grid lines); rates from the bytes the
+    launches must move (pp_chain_bytes). step_us is per chain step, launch_us
+    per launch."""
     from workloads import convdiff3d
 
     log("scale leg: generating", N)
@@ -225,11 +227,15 @@ def scale_leg(pp, torch, np, N=256, nroots=16, reps=10):
     for prec, dt, sx in (("fp32", torch.float32, 4), ("fp64", torch.float64, 8)):
         M.tune(prec)
         r = chain_rate(pp, torch, np, M, poly, prec, dt, reps)
-        out[prec] = {"variant": r["variant"], "step_us": round(r["launch_us"], 3),
-                     "bytes_per_step": int(r["bytes_per_launch"]), "GBps": round(r["GBps"], 1),
+        tiles = M.march(prec)[0] == 2 and M.march_shape(prec) == 1
+        step_us = r["ms"] * 1e3 / nroots
+        out[prec] = {"variant": r["variant"] + ("/tile2" if tiles else ""), "step_us": round(step_us, 3),
+                     "launch_us": round(r["launch_us"], 3), "launches": r["launches"],
+                     "bytes_per_launch": int(r["bytes_per_launch"]), "GBps": round(r["GBps"], 1),
                      "frac": round(r["frac"], 4),
-                     "csr_equiv_GBps": round(step_bytes(n, nnz, sx, sx) / (r["launch_us"] * 1e-6) / 1e9, 1)}
-        log("scale leg", prec, r["variant"], f"{r['launch_us']:.2f} us/step", f"{r['GBps']:.0f} GB/s own bytes")
+                     "csr_equiv_GBps": round(step_bytes(n, nnz, sx, sx) / (step_us * 1e-6) / 1e9, 1)}
+        log("scale leg", prec, out[prec]["variant"], f"{step_us:.2f} us/step", f"{r['launch_us']:.2f} us/launch",
+            f"{r['GBps']:.0f} GB/s own bytes")
     del M
     torch.cuda.empty_cache()
     return out
@@ -713,8 +719,9 @@ def main():
             f"{rf['GBps']:.0f} GB/s own bytes")
 
     k32 = phi["fp32"]
-    if M.march("fp32")[0] == 2 and M.march_shape("fp32") == 1:
-        k32["variant"] = "box/tile2"  # two steps per launch on whole grid lines
+    for prec in ("fp32", "fp64"):
+        if M.march(prec)[0] == 2 and M.march_shape(prec) == 1:
+            phi[prec]["variant"] += "/tile2"  # two steps per launch on whole grid lines
     tr = recorded_traffic("fp32", k32["variant"], k32["remap"])
     log("recorded traffic", tr)
     roofline = {
@@ -741,13 +748,14 @@ def main():
                  "achieved": round(phi["fp64"]["GBps"], 1), "frac": round(phi["fp64"]["frac"], 4)},
     }
     # the kernel boundary: empty launches of the dominant launch's grid
-    # (two-step tiles: 8 x 4 lines of the 128 x 128 planes; one step: 1024
-    # points per workgroup)
-    blocks = -(-N // 8) * -(-N // 4) if k32["variant"] == "box/tile2" else -(-n // 1024)
-    floor = launch_floor_us(pp, torch, blocks)
+    # (two-step tiles: 16 x 4 lines of the 128 x 128 planes, 1024 threads;
+    # one step: 1024 points per workgroup of 256 threads)
+    tiles = k32["variant"] == "box/tile2"
+    blocks, threads = ((-(-N // 16) * -(-N // 4), 1024) if tiles else (-(-n // 1024), 256))
+    floor = launch_floor_us(pp, torch, blocks, threads)
     hbm_us = k32["bytes_per_launch"] / (HBM_PEAK_GBPS * 1e3)
     roofline["launch_floor"] = {
-        "blocks": blocks, "us": round(floor, 3), "hbm_us": round(hbm_us, 3),
+        "blocks": blocks, "threads": threads, "us": round(floor, 3), "hbm_us": round(hbm_us, 3),
         "bound_us": round(floor + hbm_us, 3), "frac_of_bound": round((floor + hbm_us) / k32["launch_us"], 4),
         "note": ("back-to-back empty kernels of the dominant launch's grid (pp_launch_floor, HIP events): the "
                  "cost of a kernel boundary; bound_us = that floor + the launch's bytes at peak HBM bandwidth, a "

@@ -433,12 +433,13 @@ pp_status pp_chain_bytes(pp_poly p, pp_matrix A, int kind, int prec, void *strea
                          int64_t *launches);
 
 /* Launch floor, a measurement aid beside pp_chain_bytes: queue `launches`
- * back-to-back launches of an empty kernel of `blocks` workgroups of 256
- * threads on the stream (nothing is read or written). Timing them with
- * events on the same stream gives the cost of a kernel boundary at that grid
- * size, which bounds a chain step from below however few bytes it moves.
- * PP_EINVAL unless 1 <= launches <= 100000 and 1 <= blocks < 2^31. */
-pp_status pp_launch_floor(int launches, int64_t blocks, void *stream);
+ * back-to-back launches of an empty kernel of `blocks` workgroups of
+ * `threads` threads on the stream (nothing is read or written). Timing them
+ * with events on the same stream gives the cost of a kernel boundary at that
+ * grid shape, which bounds a chain launch from below however few bytes it
+ * moves. PP_EINVAL unless 1 <= launches <= 100000, 1 <= blocks < 2^31 and
+ * threads is 64, 128, 256, 512 or 1024. */
+pp_status pp_launch_floor(int launches, int64_t blocks, int threads, void *stream);
 
 /* Solve A x = b by PP(d)-GMRES(m) (Algorithm 4 step 2), x_0 = 0.
  * Each cycle starts from the true residual r = b - A x computed in FP64;

@@ -56,7 +56,7 @@ SIGNATURES = {
     "pp_matrix_set_march": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
     "pp_matrix_march": (c_int, [c_void_p, c_int, P_int, P_int, P_double, P_int]),
     "pp_matrix_set_march_shape": (c_int, [c_void_p, c_int, c_int]),
-    "pp_launch_floor": (c_int, [c_int, c_int64, c_void_p]),
+    "pp_launch_floor": (c_int, [c_int, c_int64, c_int, c_void_p]),
     "pp_solve_workspace_bytes": (c_int, [c_void_p, c_void_p, ctypes.POINTER(SolveOpts), ctypes.POINTER(c_int64),
                                          ctypes.POINTER(c_int64)]),
     "pp_matrix_march_shape": (c_int, [c_void_p, c_int, P_int]),

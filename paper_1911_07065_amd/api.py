@@ -395,10 +395,10 @@ def solve_workspace_bytes(poly: Poly | None, A: Matrix, m: int = 50, inner: str 
     return t.value, a.value
 
 
-def launch_floor(launches: int, blocks: int, device="cuda"):
-    """Queue `launches` empty kernels of `blocks` workgroups on the current stream
-    (time them with events to measure the cost of a kernel boundary)."""
-    check(lib.pp_launch_floor(int(launches), int(blocks), _stream(device)), "pp_launch_floor")
+def launch_floor(launches: int, blocks: int, threads: int = 256, device="cuda"):
+    """Queue `launches` empty kernels of `blocks` workgroups of `threads` threads on
+    the current stream (time them with events to measure a kernel boundary's cost)."""
+    check(lib.pp_launch_floor(int(launches), int(blocks), int(threads), _stream(device)), "pp_launch_floor")
 
 
 def solve(poly: Poly | None, A: Matrix, b, tol: float = 1e-8, m: int = 50, max_cycles: int = 1000,

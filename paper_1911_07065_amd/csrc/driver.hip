@@ -2562,12 +2562,13 @@ pp_status pp_solve_workspace_bytes(pp_poly p, pp_matrix A, const pp_solve_opts *
     return PP_OK;
 }
 
-pp_status pp_launch_floor(int launches, int64_t blocks, void *stream) {
-    if (launches < 1 || launches > 100000 || blocks < 1 || blocks >= (1LL << 31)) {
+pp_status pp_launch_floor(int launches, int64_t blocks, int threads, void *stream) {
+    if (launches < 1 || launches > 100000 || blocks < 1 || blocks >= (1LL << 31) ||
+        (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)) {
         set_error("pp_launch_floor: bad argument");
         return PP_EINVAL;
     }
-    for (int i = 0; i < launches; ++i) HIP_TRY(launch_empty((long)blocks, S(stream)));
+    for (int i = 0; i < launches; ++i) HIP_TRY(launch_empty((long)blocks, threads, S(stream)));
     return PP_OK;
 }
 

@@ -233,8 +233,8 @@ struct MarchPtrs {
 // The single-step box kernel (CV_BOX) applies: a constant-coefficient 5- or
 // 7-point box stencil whose grid lines hold a multiple of 4 points.
 bool box_step_ok(const DevCSR &A);
-// One launch of an empty kernel of `blocks` workgroups (the launch floor).
-hipError_t launch_empty(long blocks, hipStream_t st);
+// One launch of an empty kernel of `blocks` workgroups of `threads` threads (the launch floor).
+hipError_t launch_empty(long blocks, int threads, hipStream_t st);
 // Whole-line tiles (MarchPtrs::shape 1) apply: a constant-coefficient
 // 7-point box stencil whose grid lines hold 64, 128 or 256 points, FP64 or
 // FP32 vectors.
