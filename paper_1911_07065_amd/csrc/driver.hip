@@ -101,6 +101,10 @@ struct pp_matrix_s {
     // instead of marching planes (constant-coefficient 7-point stencils)
     int march_tile[3] = {0, 0, 0};
     int tile_remap[3] = {1, 1, 1};
+    // per precision: two-step pairs (p chains' steps with the accumulator)
+    // run the whole-line tile kernel instead of the cube-tile pair kernel
+    int pair_tile[3] = {0, 0, 0};
+    int pair_remap[3] = {1, 1, 1};
     // column-banded CSR copies (matrices whose entries lie far from the
     // diagonal): c = 0 two bands, c = 1 four; bperm maps entries to CSR
     int32_t *brow[2] = {nullptr, nullptr}, *bcol[2] = {nullptr, nullptr}, *bperm[2] = {nullptr, nullptr};
@@ -492,30 +496,58 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
     A->remap[prec] = br;
     A->persist[prec] = 0;
     double best_all = best;
-    // two real-root steps per launch on a box stencil: kept when one such
-    // launch beats two single steps
+    // two steps per launch on a box stencil (the pairs that chains with an
+    // accumulator use: p chains' steps): one such launch, with the cube-tile
+    // kernel or whole-line tiles where they apply, against two single steps
+    // that also read and write the accumulator; kept when it is faster
     A->fuse[prec] = 0;
     A->pair_us[prec] = 0.0;
+    A->pair_tile[prec] = 0;
     if (A->box_nd && A->pbyte && prec != PP_BF16S) {
+        const DevCSR d = A->dev();
+        auto timed = [&](auto &&launch, double &best_us) -> pp_status {
+            for (int round = 0; round < 2; ++round) {
+                for (int i = 0; i < 2; ++i) HIP_TRY(launch());
+                HIP_TRY(hipEventRecord(e0, st));
+                for (int i = 0; i < reps; ++i) HIP_TRY(launch());
+                HIP_TRY(hipEventRecord(e1, st));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                best_us = std::min(best_us, 1e3 * ms / reps);
+            }
+            return PP_OK;
+        };
+        StepPtrs sa = p;
+        sa.acc = w.T;
+        sa.b0 = sa.b1 = 1.0;
+        double single_acc = 1e30;
+        PP_TRY(timed([&] { return launch_chain_step(d, prec, sa, st); }, single_acc));
         PairPtrs pp;
         std::memset(&pp, 0, sizeof(pp));
         pp.in = w.P0;
         pp.out = w.P1;
+        pp.acc = w.T;
+        pp.acc1 = pp.acc2 = 1;
         pp.a01 = pp.a02 = 1.0;
-        const DevCSR d = A->dev();
+        pp.b01 = pp.b11 = pp.b02 = pp.b12 = 1.0;
         double bp = 1e30;
-        for (int round = 0; round < 2; ++round) {
-            for (int i = 0; i < 2; ++i) HIP_TRY(launch_chain_pair(d, prec, pp, br, st));
-            HIP_TRY(hipEventRecord(e0, st));
-            for (int i = 0; i < reps; ++i) HIP_TRY(launch_chain_pair(d, prec, pp, br, st));
-            HIP_TRY(hipEventRecord(e1, st));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            bp = std::min(bp, 1e3 * ms / reps);
+        PP_TRY(timed([&] { return launch_chain_pair(d, prec, pp, br, st); }, bp));
+        if (box_tile_ok(d, prec)) {
+            PairPtrs tp = pp;
+            tp.shape = 1;
+            for (int r = 0; r < 2; ++r) {
+                double bt = 1e30;
+                PP_TRY(timed([&] { return launch_chain_pair(d, prec, tp, r, st); }, bt));
+                if (bt < bp) {
+                    bp = bt;
+                    A->pair_tile[prec] = 1;
+                    A->pair_remap[prec] = r;
+                }
+            }
         }
         A->pair_us[prec] = bp;
-        A->fuse[prec] = bp < 2.0 * best ? 1 : 0;
+        A->fuse[prec] = bp < 2.0 * single_acc ? 1 : 0;
     }
     // 2 to kMarchMax steps per launch of the marching kernel: each launch
     // length is timed over a few plane-chunk sizes; the length with the
@@ -835,7 +867,8 @@ pp_status run_program(pp_matrix A, pp_poly poly, int kind, int prec, const void 
             pp.a12 = t.a1;
             pp.b02 = t.b0;
             pp.b12 = t.b1;
-            HIP_TRY(launch_chain_pair(d, prec, pp, A->remap[prec], st));
+            pp.shape = A->pair_tile[prec];
+            HIP_TRY(launch_chain_pair(d, prec, pp, pp.shape ? A->pair_remap[prec] : A->remap[prec], st));
             if (L.swap >= 0) std::swap(tmp[L.swap], tmp[t.out]);
             continue;
         }
@@ -983,8 +1016,10 @@ void program_bytes(pp_matrix A, pp_poly poly, int kind, int prec, int64_t &bytes
     // variant; on a constant-coefficient stencil only the interior row's
     // coefficients
     const int64_t csz = prec == PP_F64 ? 8 : 4;
-    const int64_t pat = A->box_pint >= 0 ? (int64_t)A->h_doff.size() * csz
-                                         : (int64_t)A->n + (int64_t)A->npat * (int64_t)A->h_doff.size() * csz;
+    const int64_t coded = (int64_t)A->n + (int64_t)A->npat * (int64_t)A->h_doff.size() * csz;
+    const int64_t pat = A->box_pint >= 0 ? (int64_t)A->h_doff.size() * csz : coded;
+    // the cube-tile pair kernel reads the pattern bytes on any box stencil
+    const int64_t pat_pair = A->pair_tile[prec] ? pat : coded;
     std::vector<Planned> plan;
     plan_program(A, prog, prec, plan);
     for (const Planned &L : plan) {
@@ -998,7 +1033,7 @@ void program_bytes(pp_matrix A, pp_poly poly, int kind, int prec, int64_t &bytes
         if (L.kind == 1) {
             const int acc = s.acc != B_NONE ? s.acc : t.acc;
             const int init = s.acc != B_NONE ? s.acc_init : t.acc_init;
-            bytes += pat + vec * (1 + (t.out != B_NONE) + (t.fin != 0));
+            bytes += pat_pair + vec * (1 + (t.out != B_NONE) + (t.fin != 0));
             if (acc != B_NONE) bytes += vec * (init ? 1 : 2);
             launches += 1;
             continue;
@@ -2049,6 +2084,7 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
     A->march[prec] = 0;
     A->march_all[prec] = 0;
     A->march_tile[prec] = 0;
+    A->pair_tile[prec] = 0;
     return PP_OK;
 }
 
@@ -2111,9 +2147,11 @@ pp_status pp_matrix_set_march_shape(pp_matrix A, int prec, int shape) {
         return PP_EINVAL;
     }
     A->march_tile[prec] = shape;
+    A->pair_tile[prec] = shape;
     if (shape == 1) {
         A->march[prec] = 2;
         A->march_all[prec] = 1;
+        A->fuse[prec] = 1;  // the pairs of p chains too
     }
     return PP_OK;
 }

@@ -204,6 +204,9 @@ struct PairPtrs {
     int acc1, acc2, init, aux2;
     double a01, a11, b01, b11;
     double a02, a12, a22, b02, b12;
+    // 0: the cube-tile kernel (k_chain_pair); 1: whole-line tiles
+    // (k_chain_boxt, constant-coefficient 7-point stencils, box_tile_ok)
+    int shape;
 };
 hipError_t launch_chain_pair(const DevCSR &A, int prec, const PairPtrs &p, int remap, hipStream_t st);
 

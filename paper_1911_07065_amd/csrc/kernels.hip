@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 
 #include "devutil.h"
 #include "kernels.h"
@@ -1441,17 +1442,32 @@ __global__ __launch_bounds__(256) void k_chain_march(MarchArgs<XT> a, const uint
 // TZ whole grid lines (y x z). It stages the input on its lines and two lines
 // around them in y and z (zero outside the box) in LDS, computes the first
 // step on its lines and one line around them into LDS (zero on lines outside
-// the box), then the second step on its lines, which it stores. The steps
-// are those of the marching kernel (MarchArgs): w1 = a0[0] (A in) + a1[0] in,
-// w2 = a0[1] (A w1) + a1[1] w1 [+ a2[1] in if bit 1 of aux], out = vfin ?
-// vfin - w2 : w2. NTH threads; a lane owns 4 consecutive points of a line (GX
-// / 4 lanes per line): the line itself, the lines above and below in y and z are one
-// 4-wide LDS access each, the two neighbours along the line single accesses.
-// Products are summed in ascending diagonal order with the interior row's
-// coefficients, as the other kernels do. There is no x halo and no per-point
-// index arithmetic; the price is the two-line halo in y and z.
+// the box), then the second step on its lines, which it stores. The two
+// steps are those of the pair kernel (PairPtrs), which include the marching
+// kernel's two-step groups (MarchPtrs):
+//     w1 = a01 (A in) + a11 in,   w2 = a02 (A w1) + a12 w1 [+ a22 in if aux2]
+//     acc = (init ? 0 : acc) [+ b01 in + b11 w1 if acc1] [+ b02 w1 + b12 w2 if acc2]
+//     out = vfin ? vfin - w2 : w2                          (if out)
+// so a p chain's pair reads and writes its accumulator once, and w1 never
+// leaves LDS. NTH threads; a lane owns 4 consecutive points of a line (GX / 4
+// lanes per line): the line itself, the lines above and below in y and z are
+// one 4-wide LDS access each, the two neighbours along the line single
+// accesses. Products are summed in ascending diagonal order with the interior
+// row's coefficients, as the other kernels do. There is no x halo and no
+// per-point index arithmetic; the price is the two-line halo in y and z.
+template <typename XT>
+struct BoxtArgs {
+    const XT *in;
+    XT *out;
+    XT *acc;
+    const XT *vfin;
+    typename Arith<XT>::T a01, a11, a02, a12, a22, b01, b11, b02, b12;
+    int aux2, acc1, acc2, init;
+    int gy, gz, nty, ntiles, pint;
+};
+
 template <typename VT, typename XT, int TY, int TZ, int GX, int NTH>
-__global__ __launch_bounds__(NTH) void k_chain_boxt(MarchArgs<XT> a, const VT *__restrict__ ptab, int remap) {
+__global__ __launch_bounds__(NTH) void k_chain_boxt(BoxtArgs<XT> a, const VT *__restrict__ ptab, int remap) {
     using AT = typename Arith<XT>::T;
     typedef AT AV4 __attribute__((ext_vector_type(4)));
     static_assert(GX % 4 == 0 && NTH % (GX / 4) == 0, "whole lines of 4-point lanes in a workgroup");
@@ -1463,7 +1479,7 @@ __global__ __launch_bounds__(NTH) void k_chain_boxt(MarchArgs<XT> a, const VT *_
     __shared__ AV4 lev0[NL0 * LPL];
     __shared__ AV4 lev1[NL1 * LPL];
     const int tid = threadIdx.x, li = tid / LPL, lx = tid % LPL, x = 4 * lx;
-    const int gy = a.gy, gz = a.gm;
+    const int gy = a.gy, gz = a.gz;
     const int t = remap_tile(blockIdx.x, a.ntiles, remap);
     const int y0 = (t % a.nty) * TY, z0 = (t / a.nty) * TZ;
     const long P = (long)GX * gy;
@@ -1471,7 +1487,8 @@ __global__ __launch_bounds__(NTH) void k_chain_boxt(MarchArgs<XT> a, const VT *_
 #pragma unroll
     for (int d = 0; d < 7; ++d) c[d] = (AT)ptab[a.pint * 7 + d];
     // every global load before the first barrier: the staged input (clamped
-    // to a point of the box, dropped outside it) and the final vector
+    // to a point of the box, dropped outside it), the final vector and the
+    // accumulator on the tile's lines
     AT pre[C0][4];
 #pragma unroll
     for (int k = 0; k < C0; ++k) {
@@ -1480,14 +1497,17 @@ __global__ __launch_bounds__(NTH) void k_chain_boxt(MarchArgs<XT> a, const VT *_
         const int yc = min(max(y, 0), gy - 1), zc = min(max(z, 0), gz - 1);
         ld4(a.in, zc * P + (long)yc * GX + x, pre[k]);
     }
-    AT vf[CT][4];
-    if (a.vfin) {
+    const bool load_acc = a.acc && !a.init;
+    AT vf[CT][4], pa[CT][4];
 #pragma unroll
-        for (int k = 0; k < CT; ++k) {
-            const int L = min(li + k * LPP, NT - 1);
-            const int y = min(y0 + L % TY, gy - 1), z = min(z0 + L / TY, gz - 1);
-            ld4(a.vfin, z * P + (long)y * GX + x, vf[k]);
-        }
+    for (int k = 0; k < CT; ++k) {
+        const int L = min(li + k * LPP, NT - 1);
+        const int y = min(y0 + L % TY, gy - 1), z = min(z0 + L / TY, gz - 1);
+        const long r = z * P + (long)y * GX + x;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vf[k][i] = pa[k][i] = AT(0);
+        if (a.vfin) ld4(a.vfin, r, vf[k]);
+        if (load_acc) ld4(a.acc, r, pa[k]);
     }
 #pragma unroll
     for (int k = 0; k < C0; ++k) {
@@ -1529,13 +1549,12 @@ __global__ __launch_bounds__(NTH) void k_chain_boxt(MarchArgs<XT> a, const VT *_
             const int ly = L % RY1, lz = L / RY1;
             const int y = y0 - 1 + ly, z = z0 - 1 + lz;
             AV4 w = AV4{0, 0, 0, 0};
-            if (y >= 0 && y < gy && z >= 0 && z < gz) w = step(lev0, (ly + 1) + RY0 * (lz + 1), RY0, a.a0[0], a.a1[0]);
+            if (y >= 0 && y < gy && z >= 0 && z < gz) w = step(lev0, (ly + 1) + RY0 * (lz + 1), RY0, a.a01, a.a11);
             lev1[L * LPL + lx] = w;
         }
     }
     __syncthreads();
-    // the second step on the tile's lines, stored
-    const bool aux = (a.aux >> 1) & 1;
+    // the second step on the tile's lines, its accumulator update, stored
 #pragma unroll
     for (int k = 0; k < CT; ++k) {
         const int L = li + k * LPP;
@@ -1543,41 +1562,43 @@ __global__ __launch_bounds__(NTH) void k_chain_boxt(MarchArgs<XT> a, const VT *_
             const int ly = L % TY, lz = L / TY;
             const int y = y0 + ly, z = z0 + lz;
             if (y < gy && z < gz) {
-                AV4 w = step(lev1, (ly + 1) + RY1 * (lz + 1), RY1, a.a0[1], a.a1[1]);
-                if (aux) {
-                    const AV4 xin = lev0[((ly + 2) + RY0 * (lz + 2)) * LPL + lx];
+                const int q1 = (ly + 1) + RY1 * (lz + 1);
+                AV4 w2 = step(lev1, q1, RY1, a.a02, a.a12);
+                const AV4 w1 = lev1[q1 * LPL + lx];
+                const AV4 xin = lev0[((ly + 2) + RY0 * (lz + 2)) * LPL + lx];
+                const long r = z * P + (long)y * GX + x;
+                if (a.aux2) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) w[i] += a.a2[1] * xin[i];
+                    for (int i = 0; i < 4; ++i) w2[i] += a.a22 * xin[i];
                 }
-                AT o[4];
+                if (a.acc) {
+                    AT o[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) o[i] = a.vfin ? vf[k][i] - w[i] : w[i];
-                st4(a.out, z * P + (long)y * GX + x, o);
+                    for (int i = 0; i < 4; ++i) {
+                        AT cacc = pa[k][i];
+                        if (a.acc1) cacc = cacc + a.b01 * xin[i] + a.b11 * w1[i];
+                        if (a.acc2) cacc = cacc + a.b02 * w1[i] + a.b12 * w2[i];
+                        o[i] = cacc;
+                    }
+                    st4(a.acc, r, o);
+                }
+                if (a.out) {
+                    AT o[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) o[i] = a.vfin ? vf[k][i] - w2[i] : w2[i];
+                    st4(a.out, r, o);
+                }
             }
         }
     }
 }
 
 template <typename VT, typename XT, int TY, int TZ, int GX, int NTH>
-hipError_t boxt_launch(const DevCSR &A, const VT *ptab, const MarchPtrs &p, int remap, hipStream_t st) {
-    using AT = typename Arith<XT>::T;
-    MarchArgs<XT> a;
-    a.in = (const XT *)p.in;
-    a.out = (XT *)p.out;
-    a.vfin = (const XT *)p.vfin;
-    for (int k = 0; k < kMarchMax; ++k) {
-        a.a0[k] = (AT)p.a0[k];
-        a.a1[k] = (AT)p.a1[k];
-        a.a2[k] = (AT)p.a2[k];
-    }
-    a.aux = p.aux;
-    a.gx = GX;
+hipError_t boxt_launch(const DevCSR &A, const VT *ptab, BoxtArgs<XT> a, int remap, hipStream_t st) {
     a.gy = A.box[1];
-    a.gm = A.box[2];
-    a.ntx = 1;
+    a.gz = A.box[2];
     a.nty = (a.gy + TY - 1) / TY;
-    a.cz = TZ;
-    const long nt = (long)a.nty * ((a.gm + TZ - 1) / TZ);
+    const long nt = (long)a.nty * ((a.gz + TZ - 1) / TZ);
     if (nt == 0) return hipSuccess;
     if (nt >= (1L << 31)) return hipErrorInvalidValue;
     a.ntiles = (int)nt;
@@ -2596,7 +2617,10 @@ hipError_t launch_chain_step(const DevCSR &A, int prec, const StepPtrs &s, hipSt
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_boxt_pair(const DevCSR &A, int prec, const PairPtrs &p, int remap, hipStream_t st);
+
 hipError_t launch_chain_pair(const DevCSR &A, int prec, const PairPtrs &p, int remap, hipStream_t st) {
+    if (p.shape == 1) return launch_boxt_pair(A, prec, p, remap, st);
     if (!A.pbyte || !p.in || (A.box_nd != 5 && A.box_nd != 7) || A.npat * A.box_nd > kMaxPatEntries ||
         (long)A.box[0] * A.box[1] * A.box[2] != A.n || (p.out && p.out == p.in) || (p.acc && p.acc == p.in))
         return hipErrorInvalidValue;
@@ -2637,29 +2661,80 @@ bool box_tile_ok(const DevCSR &A, int prec) {
 // workgroup per CU covers the 128^3 grid in one round (16 x 4 lines of 128
 // points in FP32: 7.0 us per launch, against 8.8 us for 8 x 4 lines with 256
 // threads and two workgroups per CU)
-hipError_t launch_boxt(const DevCSR &A, int prec, const MarchPtrs &p, int remap, hipStream_t st) {
-    if (!box_tile_ok(A, prec) || p.nsteps != 2 || (p.aux & 1) || !p.in || !p.out || p.out == p.in || p.out == p.vfin)
-        return hipErrorInvalidValue;
-    if (prec == 1) {
-        switch (A.box[0]) {
-            case 64:
-                return boxt_launch<float, float, 8, 8, 64, 256>(A, A.ptab32, p, remap, st);
-            case 128:
-                return boxt_launch<float, float, 16, 4, 128, 1024>(A, A.ptab32, p, remap, st);
-            case 256:
-                return boxt_launch<float, float, 8, 4, 256, 1024>(A, A.ptab32, p, remap, st);
-        }
-    } else {
-        switch (A.box[0]) {
-            case 64:
-                return boxt_launch<double, double, 8, 4, 64, 256>(A, A.ptab64, p, remap, st);
-            case 128:
-                return boxt_launch<double, double, 8, 4, 128, 1024>(A, A.ptab64, p, remap, st);
-            case 256:
-                return boxt_launch<double, double, 4, 2, 256, 1024>(A, A.ptab64, p, remap, st);
-        }
+template <typename XT>
+hipError_t boxt_dispatch(const DevCSR &A, int prec, const BoxtArgs<XT> &a, int remap, hipStream_t st);
+template <>
+hipError_t boxt_dispatch<float>(const DevCSR &A, int, const BoxtArgs<float> &a, int remap, hipStream_t st) {
+    switch (A.box[0]) {
+        case 64:
+            return boxt_launch<float, float, 8, 8, 64, 256>(A, A.ptab32, a, remap, st);
+        case 128:
+            return boxt_launch<float, float, 16, 4, 128, 1024>(A, A.ptab32, a, remap, st);
+        case 256:
+            return boxt_launch<float, float, 8, 4, 256, 1024>(A, A.ptab32, a, remap, st);
     }
     return hipErrorInvalidValue;
+}
+template <>
+hipError_t boxt_dispatch<double>(const DevCSR &A, int, const BoxtArgs<double> &a, int remap, hipStream_t st) {
+    switch (A.box[0]) {
+        case 64:
+            return boxt_launch<double, double, 8, 4, 64, 256>(A, A.ptab64, a, remap, st);
+        case 128:
+            return boxt_launch<double, double, 8, 4, 128, 1024>(A, A.ptab64, a, remap, st);
+        case 256:
+            return boxt_launch<double, double, 4, 2, 256, 1024>(A, A.ptab64, a, remap, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename XT>
+BoxtArgs<XT> boxt_args(const PairPtrs &p) {
+    using AT = typename Arith<XT>::T;
+    BoxtArgs<XT> a;
+    std::memset(&a, 0, sizeof(a));
+    a.in = (const XT *)p.in;
+    a.out = (XT *)p.out;
+    a.acc = (XT *)p.acc;
+    a.vfin = (const XT *)p.vfin;
+    a.a01 = (AT)p.a01;
+    a.a11 = (AT)p.a11;
+    a.a02 = (AT)p.a02;
+    a.a12 = (AT)p.a12;
+    a.a22 = (AT)p.a22;
+    a.b01 = (AT)p.b01;
+    a.b11 = (AT)p.b11;
+    a.b02 = (AT)p.b02;
+    a.b12 = (AT)p.b12;
+    a.aux2 = p.aux2;
+    a.acc1 = p.acc1;
+    a.acc2 = p.acc2;
+    a.init = p.init;
+    return a;
+}
+
+hipError_t launch_boxt_pair(const DevCSR &A, int prec, const PairPtrs &p, int remap, hipStream_t st) {
+    if (!box_tile_ok(A, prec) || !p.in || (!p.out && !p.acc) || (p.out && (p.out == p.in || p.out == p.vfin)) ||
+        (p.acc && (p.acc == p.in || p.acc == p.out)))
+        return hipErrorInvalidValue;
+    if (prec == 1) return boxt_dispatch<float>(A, prec, boxt_args<float>(p), remap, st);
+    return boxt_dispatch<double>(A, prec, boxt_args<double>(p), remap, st);
+}
+
+hipError_t launch_boxt(const DevCSR &A, int prec, const MarchPtrs &m, int remap, hipStream_t st) {
+    if (m.nsteps != 2 || (m.aux & 1) || !m.out) return hipErrorInvalidValue;
+    PairPtrs p;
+    std::memset(&p, 0, sizeof(p));
+    p.in = m.in;
+    p.out = m.out;
+    p.vfin = m.vfin;
+    p.a01 = m.a0[0];
+    p.a11 = m.a1[0];
+    p.a02 = m.a0[1];
+    p.a12 = m.a1[1];
+    p.a22 = m.a2[1];
+    p.aux2 = (m.aux >> 1) & 1;
+    return launch_boxt_pair(A, prec, p, remap, st);
 }
 
 hipError_t launch_chain_march(const DevCSR &A, int prec, const MarchPtrs &p, int cz, int remap, hipStream_t st) {

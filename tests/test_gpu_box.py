@@ -204,10 +204,11 @@ def test_box_tile_matches_oracle(pp, name):
                 err = maxerr(v32 - g32, ref_phi, idx) if kind == "pi" else maxerr(g32, ref, idx)
                 assert err <= 10 * delta + 1e-6, (kind, err, delta)
                 assert maxerr(g32, single32, idx) <= 10 * delta + 1e-6
-            # launches: the phi / pi chains fuse their steps two by two
+            # launches: the chains fuse their steps two by two (p chains'
+            # pairs carry the accumulator through the whole-line kernel too)
             by, launches = pp.chain_bytes(poly, M, kind, "fp64")
-            if kind != "p":
-                assert launches < poly.d_eff
+            assert launches < (poly.d_eff if kind != "p" else poly.d_eff - 1)
+            assert M.pair_steps("fp64")[0]
 
 
 def test_box_tile_refused_where_it_does_not_apply(pp):
