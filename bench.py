@@ -227,9 +227,10 @@ def scale_leg(pp, torch, np, N=256, nroots=16, reps=10):
     for prec, dt, sx in (("fp32", torch.float32, 4), ("fp64", torch.float64, 8)):
         M.tune(prec)
         r = chain_rate(pp, torch, np, M, poly, prec, dt, reps)
-        tiles = M.march(prec)[0] == 2 and M.march_shape(prec) == 1
+        g = M.march(prec)[0]
+        fused = "/tile2" if g == 2 and M.march_shape(prec) == 1 else (f"/march{g}" if g >= 2 else "")
         step_us = r["ms"] * 1e3 / nroots
-        out[prec] = {"variant": r["variant"] + ("/tile2" if tiles else ""), "step_us": round(step_us, 3),
+        out[prec] = {"variant": r["variant"] + fused, "step_us": round(step_us, 3),
                      "launch_us": round(r["launch_us"], 3), "launches": r["launches"],
                      "bytes_per_launch": int(r["bytes_per_launch"]), "GBps": round(r["GBps"], 1),
                      "frac": round(r["frac"], 4),
