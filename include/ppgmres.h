@@ -499,9 +499,14 @@ pp_status pp_batch_set_values(pp_batch B, const double *val, void *stream);
  * differ per system), no row holds two entries of one column, and each
  * system's rows take at most 256 distinct value tuples: one byte per row
  * names the row's tuple in its system's table. pp_batch_create selects 1
- * when that copy exists. Both give the same sums in a different order.
- * pp_batch_set_format returns PP_EINVAL for a format the batch has no copy
- * of; pp_batch_format writes the current one (host int). */
+ * when that copy exists. 2: constant-coefficient box stencils, built beside
+ * 1 when every system is a 5-point stencil on a gx x gy grid (offsets -gx,
+ * -1, 0, 1, gx; gx, gy >= 3) whose every row equals the interior row with
+ * the entries that fall outside the grid dropped: each system keeps only
+ * its interior tuple and gx, and a row's coefficients follow from its grid
+ * position. All give the same sums in a different order. pp_batch_set_format
+ * returns PP_EINVAL for a format the batch has no copy of; pp_batch_format
+ * writes the current one (host int). */
 pp_status pp_batch_set_format(pp_batch B, int format);
 pp_status pp_batch_format(pp_batch B, int *format);
 
@@ -509,17 +514,17 @@ pp_status pp_batch_format(pp_batch B, int *format);
  * the batch's own matrix, precision (PP_F64/PP_F32/PP_BF16S) and nrhs (1, 2
  * or 4), for each storage format the batch has (only the one set by
  * pp_batch_set_format, if it was called), 1 or 2 64-row slices per wave
- * (pattern-coded format) and the workgroup order (consecutive slices on one
+ * (pattern-coded and box formats) and the workgroup order (consecutive slices on one
  * XCD, or not); the fastest is kept for that precision and nrhs. Runs by
  * itself in the first pp_batch_solve of a (precision, nrhs);
  * pp_batch_set_values and pp_batch_set_format clear it.
  *   pp_batch_chain_config: the shape in use (tuned, or the default:
  *     pp_batch_format's format, 1 slice per wave, XCD order on): *format
- *     (host) 0 sliced-ELL or 1 pattern-coded; spw, remap, us (host, may be
+ *     (host) 0 sliced-ELL, 1 pattern-coded or 2 box; spw, remap, us (host, may be
  *     NULL) slices per wave, XCD order, tuned microseconds per step (0 if not
  *     tuned).
  *   pp_batch_set_chain_config: use this shape for (prec, nrhs) instead of
- *     tuning (format 0 or 1, spw 1 or 2 with format 1 only, remap 0 or 1);
+ *     tuning (format 0, 1 or 2, spw 2 only with format 1 or 2, remap 0 or 1);
  *     PP_EINVAL for a format the batch has no copy of. */
 pp_status pp_batch_tune(pp_batch B, int prec, int nrhs, void *stream);
 pp_status pp_batch_set_chain_config(pp_batch B, int prec, int nrhs, int format, int spw, int remap);

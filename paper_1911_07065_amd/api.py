@@ -643,11 +643,13 @@ class Batch:
             out.append(d)
         return x, out
 
-    BATCH_FORMATS = ("sell", "pattern")
+    BATCH_FORMATS = ("sell", "pattern", "box")
 
     def format(self) -> str:
-        """Storage the batch's sparse products read: "sell" (sliced-ELL) or
-        "pattern" (one byte per row naming its tuple in its system's table)."""
+        """Storage the batch's sparse products read: "sell" (sliced-ELL),
+        "pattern" (one byte per row naming its tuple in its system's table) or
+        "box" (constant-coefficient 5-point stencils: each system's interior
+        row only)."""
         f = ctypes.c_int()
         check(lib.pp_batch_format(self.handle, ctypes.byref(f)), "pp_batch_format")
         return self.BATCH_FORMATS[f.value]

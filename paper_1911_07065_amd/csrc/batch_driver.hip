@@ -58,6 +58,10 @@ struct pp_batch_s {
     long npad = 0;
     // pattern-coded copy (format 1; see pp_batch_set_format)
     uint8_t *bpat = nullptr;
+    // constant-coefficient box copy (format 2): per system its grid's line
+    // length and its interior row's pattern; set only beside the pattern copy
+    int32_t *bgx = nullptr, *bpint = nullptr;
+    int has_box = 0;
     int32_t *poff = nullptr, *ptoff = nullptr, *sysoff = nullptr;
     double *ptab64 = nullptr;
     float *ptab32 = nullptr;
@@ -165,9 +169,10 @@ struct pp_batch_s {
     };
     ChainCfg cfg[3][5];
     bool format_forced = false;  // pp_batch_set_format: the tuner keeps the format
+    bool format_ok(int f) const { return f == 0 || (f == 1 && pnd > 0) || (f == 2 && has_box && pnd > 0); }
     BatchSell sell(int prec, bool masked = false, int R = 1) const {
         const ChainCfg &c = cfg[prec][R];
-        const int fmt = (c.tuned && !format_forced && (c.format == 0 || pnd > 0)) ? c.format : format;
+        const int fmt = (c.tuned && !format_forced && format_ok(c.format)) ? c.format : format;
         BatchSell s;
         s.spw = c.tuned ? c.spw : 1;
         s.remap = c.tuned ? c.remap : 1;
@@ -178,7 +183,10 @@ struct pp_batch_s {
         s.sval64 = sval64;
         s.sval32 = sval32;
         s.nslices = nslices;
-        const bool pat = fmt == 1 && pnd > 0;
+        const bool pat = (fmt == 1 || fmt == 2) && pnd > 0;
+        const bool box = fmt == 2 && has_box && pnd > 0;
+        s.bgx = box ? bgx : nullptr;
+        s.bpint = box ? bpint : nullptr;
         s.bpat = pat ? bpat : nullptr;
         s.poff = pat ? poff : nullptr;
         s.ptoff = pat ? ptoff : nullptr;
@@ -189,6 +197,9 @@ struct pp_batch_s {
         return s;
     }
     void drop_patterns() {
+        dev_free(bgx);
+        dev_free(bpint);
+        has_box = 0;
         dev_free(bpat);
         dev_free(poff);
         dev_free(ptoff);
@@ -390,10 +401,10 @@ pp_status tune_bchain(pp_batch B, int prec, int R, hipStream_t st) {
     pp_batch_s::ChainCfg best;
     best.us = 1e30;
     const int reps = 5;
-    for (int fmt = 1; fmt >= 0; --fmt) {
-        if (fmt == 1 && B->pnd == 0) continue;
+    for (int fmt = 2; fmt >= 0; --fmt) {
+        if (!B->format_ok(fmt)) continue;
         if (B->format_forced && fmt != B->format) continue;
-        for (int spw = 1; spw <= (fmt == 1 ? 2 : 1); ++spw)
+        for (int spw = 1; spw <= (fmt >= 1 ? 2 : 1); ++spw)
             for (int remap = 0; remap <= 1; ++remap) {
                 c.tuned = 1;
                 c.format = fmt;
@@ -544,6 +555,33 @@ pp_status build_batch_patterns(pp_batch B, const std::vector<int32_t> &rp, const
         if (tab.size() >= (size_t)1 << 31) return PP_OK;
     }
     so[nsys] = (int32_t)n;
+    // constant-coefficient box stencils (5-point): system s's offsets are
+    // -g, -1, 0, 1, g on a g-wide grid of at least 3 x 3 points, and every
+    // row's tuple is its interior row's with the entries outside the grid
+    // zero
+    std::vector<int32_t> bg(nsys, 0), bp(nsys, 0);
+    bool box = nd == 5;
+    for (int s = 0; s < nsys && box; ++s) {
+        const int32_t *o = offs.data() + (size_t)s * nd;
+        const long base = B->row_off[s], ns = B->row_off[s + 1] - base;
+        const long g = o[4];
+        if (!(o[0] == -g && o[1] == -1 && o[2] == 0 && o[3] == 1 && g >= 3 && ns % g == 0 && ns / g >= 3)) {
+            box = false;
+            break;
+        }
+        const long gy = ns / g;
+        const int pint = pid[(size_t)(base + g / 2 + g * (gy / 2))];
+        const double *ci0 = tab.data() + (size_t)toff[s] + (size_t)pint * nd;
+        for (long r = 0; r < ns && box; ++r) {
+            const long x = r % g, y = r / g;
+            const bool in[5] = {y > 0, x > 0, true, x + 1 < g, y + 1 < gy};
+            const double *cr = tab.data() + (size_t)toff[s] + (size_t)pid[(size_t)(base + r)] * nd;
+            for (int d = 0; d < nd; ++d)
+                if (cr[d] != (in[d] ? ci0[d] : 0.0)) box = false;
+        }
+        bg[s] = (int32_t)g;
+        bp[s] = pint;
+    }
     std::vector<float> tab32(tab.size());
     for (size_t q = 0; q < tab.size(); ++q) tab32[q] = (float)tab[q];
     PP_TRY(dev_alloc(&B->bpat, pid.size()));
@@ -564,6 +602,18 @@ pp_status build_batch_patterns(pp_batch B, const std::vector<int32_t> &rp, const
     }
     B->pnd = nd;
     B->format = 1;
+    if (box) {
+        PP_TRY(dev_alloc(&B->bgx, bg.size()));
+        PP_TRY(dev_alloc(&B->bpint, bp.size()));
+        if (hipMemcpyAsync(B->bgx, bg.data(), sizeof(int32_t) * bg.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(B->bpint, bp.data(), sizeof(int32_t) * bp.size(), hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            set_error("pp_batch_create: box-stencil upload failed");
+            return PP_EDEVICE;
+        }
+        B->has_box = 1;
+    }
     return PP_OK;
 }
 
@@ -741,13 +791,18 @@ pp_status pp_batch_set_values(pp_batch B, const double *val, void *stream) {
 }
 
 pp_status pp_batch_set_format(pp_batch B, int format) {
-    if (!B || format < 0 || format > 1) {
+    if (!B || format < 0 || format > 2) {
         set_error("pp_batch_set_format: bad argument");
         return PP_EINVAL;
     }
     if (format == 1 && !B->bpat) {
         set_error("pp_batch_set_format: no pattern-coded copy (the systems' diagonals or row patterns do not "
                   "qualify, or the values changed)");
+        return PP_EINVAL;
+    }
+    if (format == 2 && !B->format_ok(2)) {
+        set_error("pp_batch_set_format: no box-stencil copy (not every system is a constant-coefficient 5-point "
+                  "stencil, or the values changed)");
         return PP_EINVAL;
     }
     B->format = format;
@@ -767,13 +822,17 @@ pp_status pp_batch_tune(pp_batch B, int prec, int nrhs, void *stream) {
 }
 
 pp_status pp_batch_set_chain_config(pp_batch B, int prec, int nrhs, int format, int spw, int remap) {
-    if (!B || prec < 0 || prec > 2 || !(nrhs == 1 || nrhs == 2 || nrhs == 4) || format < 0 || format > 1 ||
+    if (!B || prec < 0 || prec > 2 || !(nrhs == 1 || nrhs == 2 || nrhs == 4) || format < 0 || format > 2 ||
         spw < 1 || spw > 2 || remap < 0 || remap > 1 || (format == 0 && spw != 1)) {
-        set_error("pp_batch_set_chain_config: bad argument (spw 2 only with the pattern-coded format)");
+        set_error("pp_batch_set_chain_config: bad argument (spw 2 only with the pattern-coded or box formats)");
         return PP_EINVAL;
     }
     if (format == 1 && !B->bpat) {
         set_error("pp_batch_set_chain_config: no pattern-coded copy");
+        return PP_EINVAL;
+    }
+    if (format == 2 && !B->format_ok(2)) {
+        set_error("pp_batch_set_chain_config: no box-stencil copy");
         return PP_EINVAL;
     }
     pp_batch_s::ChainCfg &c = B->cfg[prec][nrhs];
@@ -793,7 +852,7 @@ pp_status pp_batch_chain_config(pp_batch B, int prec, int nrhs, int *format, int
     }
     const pp_batch_s::ChainCfg &c = B->cfg[prec][nrhs];
     const BatchSell S = B->sell(prec, false, nrhs);
-    *format = S.bpat ? 1 : 0;
+    *format = S.bgx ? 2 : (S.bpat ? 1 : 0);
     if (spw) *spw = S.spw;
     if (remap) *remap = S.remap;
     if (us) *us = c.tuned ? c.us : 0.0;

@@ -36,6 +36,12 @@ struct BatchSell {
     const double *ptab64;
     const float *ptab32;
     int pnd;
+    // constant-coefficient box copy (used when bgx is not null; pnd == 5 and
+    // the pattern fields above set): system s is a 5-point stencil on a
+    // bgx[s]-wide grid whose every row is its interior row (pattern bpint[s])
+    // truncated at the grid
+    const int32_t *bgx;
+    const int32_t *bpint;
     // launch shape: slices per wave of the pattern-coded kernel (1 or 2) and
     // the XCD-aware workgroup order (consecutive slices on one XCD) on or off
     int spw;

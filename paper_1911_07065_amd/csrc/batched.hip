@@ -276,6 +276,86 @@ __global__ __launch_bounds__(256) void k_bchain_pat(BChainArgs<VT, XT> a, const 
     }
 }
 
+// The same step on constant-coefficient 5-point stencils (every system's
+// rows are its interior row's stencil truncated at its own gx_s x gy_s grid):
+// no per-row matrix data. A wave takes SPW consecutive 64-row slices (a slice
+// lies in one system); the system's line length gx_s, its interior pattern
+// (ptab[ptoff[sys] + pint[sys] 5 + d], d over the offsets -gx_s, -1, 0, +1,
+// +gx_s) come through uniform loads, and a neighbour outside the system's
+// grid counts as zero, which is what its truncated row holds. The terms are
+// summed in the pattern-coded kernel's order. Neighbour indices outside the
+// grid are clamped to the row itself and dropped by a select, so every load
+// goes out unconditionally.
+template <typename VT, typename XT, int R, int SPW>
+__global__ __launch_bounds__(256) void k_bchain_box(BChainArgs<VT, XT> a, const int32_t *__restrict__ bgx,
+                                                    const int32_t *__restrict__ bpint,
+                                                    const int32_t *__restrict__ ptoff,
+                                                    const int32_t *__restrict__ sysoff, const VT *__restrict__ ptab,
+                                                    int remap) {
+    using AT = typename Arith<XT>::T;
+    constexpr int ND = 5;
+    const int w0 = bslice_index(remap) * SPW;
+    if (w0 >= a.nslices) return;
+    const int lane = threadIdx.x & 63;
+    int4 si[SPW];
+    int rc[SPW], gx[SPW], nb[SPW];
+    bool in[SPW][ND];
+    const VT *tb[SPW];
+#pragma unroll
+    for (int q = 0; q < SPW; ++q) {
+        si[q] = a.slice[min(w0 + q, a.nslices - 1)];
+        const int sys = si[q].z;
+        rc[q] = si[q].x + min(lane, si[q].y - 1);
+        const int base = sysoff[sys], ns = sysoff[sys + 1] - base;
+        gx[q] = bgx[sys];
+        tb[q] = ptab + ptoff[sys] + bpint[sys] * ND;
+        const int loc = rc[q] - base, y = loc / gx[q], x = loc - y * gx[q], gy = ns / gx[q];
+        in[q][0] = y > 0;
+        in[q][1] = x > 0;
+        in[q][2] = true;
+        in[q][3] = x + 1 < gx[q];
+        in[q][4] = y + 1 < gy;
+        nb[q] = base;
+    }
+    bool skip[SPW];
+    PStep st[SPW];
+#pragma unroll
+    for (int q = 0; q < SPW; ++q) {
+        st[q] = bstep(a, si[q].z, skip[q]);
+        skip[q] = skip[q] || w0 + q >= a.nslices;
+    }
+    BRow<XT> p[SPW];
+    BRowIn<XT, R> t[SPW];
+    AT xv[SPW][ND][R];
+#pragma unroll
+    for (int q = 0; q < SPW; ++q) {
+        if (skip[q]) continue;
+        p[q] = brow_ptrs(a, st[q]);
+        brow_load<XT, R>(p[q], rc[q], t[q]);
+        if (st[q].spmv) {
+            const int off[ND] = {-gx[q], -1, 0, 1, gx[q]};
+#pragma unroll
+            for (int d = 0; d < ND; ++d) ldr<XT, R>(p[q].in, in[q][d] ? rc[q] + off[d] : rc[q], xv[q][d]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < SPW; ++q) {
+        if (skip[q]) continue;
+        AT s[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] = AT(0);
+        if (st[q].spmv) {
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const AT v = (AT)tb[q][d];
+#pragma unroll
+                for (int r = 0; r < R; ++r) s[r] += v * (in[q][d] ? xv[q][d][r] : AT(0));
+            }
+        }
+        if (lane < si[q].y) bchain_finish<XT, R>(st[q], p[q], t[q], (long)si[q].x + lane, s);
+    }
+}
+
 // One chunk of KC Krylov columns of k_bdots for R interleaved right-hand
 // sides: all loads of the chunk are issued before the first is used; each
 // wave leaves its sums in sm[wave][(c - g0) R + r], g0 the column group's
@@ -586,6 +666,14 @@ __global__ __launch_bounds__(256) void k_bcombine(const int4 *block, const XT *V
 // ---- dispatch helpers -----------------------------------------------------
 
 template <typename VT, typename XT, int R, int SPW>
+hipError_t bchain_box_t(const BatchSell &S, const BChainArgs<VT, XT> &a, const VT *ptab, hipStream_t st) {
+    const unsigned g = (unsigned)((S.nslices + 4 * SPW - 1) / (4 * SPW));
+    hipLaunchKernelGGL((k_bchain_box<VT, XT, R, SPW>), dim3(g), dim3(256), 0, st, a, S.bgx, S.bpint, S.ptoff,
+                       S.sysoff, ptab, S.remap);
+    return hipGetLastError();
+}
+
+template <typename VT, typename XT, int R, int SPW>
 hipError_t bchain_pat_t(const BatchSell &S, const BChainArgs<VT, XT> &a, const VT *ptab, hipStream_t st) {
     const unsigned g = (unsigned)((S.nslices + 4 * SPW - 1) / (4 * SPW));
 #define PP_BPAT_ND(K)                                                                                             \
@@ -625,6 +713,20 @@ hipError_t bchain_t(const BatchSell &S, const VT *sval, const VT *ptab, int R, c
     for (int i = 0; i < 5; ++i) a.bufs[i] = (XT *)bufs[i];
     const unsigned g = (unsigned)((S.nslices + 3) / 4);
     if (g == 0) return hipSuccess;
+    if (S.bgx) {
+        if (!S.bpint || !S.ptoff || !S.sysoff || !ptab) return hipErrorInvalidValue;
+        const bool two = S.spw == 2;
+        switch (R) {
+            case 1:
+                return two ? bchain_box_t<VT, XT, 1, 2>(S, a, ptab, st) : bchain_box_t<VT, XT, 1, 1>(S, a, ptab, st);
+            case 2:
+                return two ? bchain_box_t<VT, XT, 2, 2>(S, a, ptab, st) : bchain_box_t<VT, XT, 2, 1>(S, a, ptab, st);
+            case 4:
+                return two ? bchain_box_t<VT, XT, 4, 2>(S, a, ptab, st) : bchain_box_t<VT, XT, 4, 1>(S, a, ptab, st);
+            default:
+                return hipErrorInvalidValue;
+        }
+    }
     if (S.bpat) {
         const bool two = S.spw == 2;
         switch (R) {

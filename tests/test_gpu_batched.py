@@ -88,7 +88,7 @@ SMALL = [(16, 3.0, 1000, 5000), (23, 40.0, 1001, 5001), (31, 0.0, 1002, 5002), (
          (9, 7.0, 1004, 5004), (28, 25.0, 1005, 5005)]
 
 
-@pytest.mark.parametrize("fmt", ["pattern", "sell"])
+@pytest.mark.parametrize("fmt", ["box", "pattern", "sell"])
 @pytest.mark.parametrize("inner", ["fp64", "fp32"])
 @pytest.mark.parametrize("R", [1, 4])
 def test_small_batch_matches_single_solves(pp, inner, R, fmt):
@@ -124,7 +124,7 @@ def test_small_batch_matches_single_solves(pp, inner, R, fmt):
     assert np.all(np.linalg.norm(R_all, axis=1) <= 1e-8 * np.linalg.norm(bmat, axis=1) * np.sqrt(len(csrs)))
 
 
-@pytest.mark.parametrize("fmt", ["pattern", "sell"])
+@pytest.mark.parametrize("fmt", ["box", "pattern", "sell"])
 @pytest.mark.parametrize("inner", ["fp64", "fp32"])
 @pytest.mark.parametrize("R", [1, 4])
 def test_small_batch_matches_oracle(pp, inner, R, fmt):
@@ -153,11 +153,11 @@ def test_batch_tuner_and_every_launch_shape(pp, R):
     brs = _rhs_block(SMALL, R)
     bd = Bt.interleave(np.concatenate(brs, axis=1))
     fmt, spw, remap, us = Bt.tune(R, "fp32")
-    assert fmt in ("sell", "pattern") and spw in (1, 2) and remap in (0, 1) and us > 0
+    assert fmt in ("sell", "pattern", "box") and spw in (1, 2) and remap in (0, 1) and us > 0
     assert Bt.chain_config(R, "fp32") == (fmt, spw, remap, us)
     xs = []
     for shape in [("sell", 1, 0), ("sell", 1, 1), ("pattern", 1, 0), ("pattern", 1, 1), ("pattern", 2, 0),
-                  ("pattern", 2, 1)]:
+                  ("pattern", 2, 1), ("box", 1, 0), ("box", 1, 1), ("box", 2, 0), ("box", 2, 1)]:
         say("batch shape", R, shape)
         Bt.set_chain_config(R, "fp32", *shape)
         Bt.set_chain_config(R, "fp64", *shape)
@@ -188,6 +188,18 @@ def test_batch_pattern_copy_rules(pp):
     assert pp.Batch([convdiff2d(12, 3.0), tri]).format() == "sell"
     with pytest.raises(Exception, match="pattern-coded"):
         pp.Batch([convdiff2d(12, 3.0), tri]).set_format("pattern")
+    with pytest.raises(Exception, match="box-stencil"):
+        pp.Batch([convdiff2d(12, 3.0), tri]).set_format("box")
+    # a 5-point stencil whose coefficients vary along the grid keeps the
+    # pattern-coded copy but has no box copy
+    var = convdiff2d(12, 3.0)
+    rows = np.repeat(np.arange(var.n), np.diff(var.rowptr))
+    var = CSR(n=var.n, rowptr=var.rowptr, colind=var.colind, val=var.val * (1.0 + 0.01 * (rows % 5)))
+    Bv = pp.Batch([convdiff2d(12, 3.0), var])
+    assert Bv.format() == "pattern"
+    Bv.set_format("pattern")
+    with pytest.raises(Exception, match="box-stencil"):
+        Bv.set_format("box")
     specs = SMALL[:3]
     csrs = _systems(specs)
     Bt = pp.Batch(csrs)
@@ -200,6 +212,8 @@ def test_batch_pattern_copy_rules(pp):
     assert Bt.format() == "sell"
     with pytest.raises(Exception, match="pattern-coded"):
         Bt.set_format("pattern")
+    with pytest.raises(Exception, match="box-stencil"):
+        Bt.set_format("box")
     # (2A) x = b: x is half the first solution (same roots, scaled problem)
     polys2 = Bt.setup(dev(_v0(specs)), 8)
     x2, i2 = Bt.solve(polys2, bd, 1, tol=1e-10, m=30, inner="fp64")
@@ -283,7 +297,7 @@ def test_batched_config_full_size(pp):
         "s; speed-up", round(t_loop / t_batch, 2))
 
 
-@pytest.mark.parametrize("fmt", ["pattern", "sell"])
+@pytest.mark.parametrize("fmt", ["box", "pattern", "sell"])
 @pytest.mark.parametrize("R", [1, 4])
 def test_batched_graph_replays_equal_eager(pp, R, fmt):
     # Arnoldi steps captured into HIP graphs and replayed over several cycles
