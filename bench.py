@@ -540,11 +540,12 @@ def host_cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(csr, b, v0, d, m, reps=3, cap_s=100.0):
+def cpu_baseline(csr, b, v0, d, m, reps=3, cap_s=100.0, gpu_x=None):
     """The FP64 oracle's full time-to-solution on the host (polynomial setup by
     GMRES(d) with modified Gram-Schmidt, Leja order and added roots, then
     PP(d)-GMRES(m) to 1e-8, as the paper times it): the median of up to
-    `reps` runs, fewer when the runs so far took more than cap_s."""
+    `reps` runs, fewer when the runs so far took more than cap_s. gpu_x:
+    {form: x} of the GPU solutions, each compared with the oracle's x."""
     import numpy as np
 
     from oracle import roots, solver
@@ -567,7 +568,9 @@ def cpu_baseline(csr, b, v0, d, m, reps=3, cap_s=100.0):
         if time.perf_counter() - t_all > cap_s:
             break
     rel = float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
+    xerr = {k: float(np.linalg.norm(v - x) / np.linalg.norm(x)) for k, v in (gpu_x or {}).items()}
     return {
+        "x_err_vs_oracle": xerr,
         "value": float(np.median(times)),
         "unit": "s",
         "cores": int(threads),
@@ -693,7 +696,7 @@ def main():
         t = (time.perf_counter() - t0) / args.steps
         A = csr.to_scipy()
         rel = float(np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b))
-        res[inner] = dict(t=t, info=info, poly=poly, relres=rel)
+        res[inner] = dict(t=t, info=info, poly=poly, relres=rel, x=x.cpu().numpy())
         log(inner, f"time-to-solution {t * 1e3:.1f} ms", info, "true relres", rel)
 
     # p(A)v and phi(A)v bandwidth, FP32 and FP64: the bytes the launches must
@@ -776,7 +779,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("timing the oracle on the host (full time-to-solution)")
-        cpu = cpu_baseline(csr, b, v0, d, m, reps=max(1, args.cpu_reps))
+        cpu = cpu_baseline(csr, b, v0, d, m, reps=max(1, args.cpu_reps),
+                           gpu_x={k: res[k]["x"] for k in ("fp32", "fp64")})
 
     r32, r64 = res["fp32"], res["fp64"]
     out = {
@@ -798,6 +802,7 @@ def main():
             "n": n, "nnz": nnz, "d": d, "d_eff": poly.d_eff, "m": m, "tol": tol,
         },
         "relres": r32["relres"],
+        "x_err_vs_oracle": cpu["x_err_vs_oracle"] if cpu else None,
         "iters": r32["info"]["iters"],
         "cycles": r32["info"]["cycles"],
         "fp64_time_to_solution_s": round(r64["t"], 6),
