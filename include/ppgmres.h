@@ -158,12 +158,19 @@ void pp_matrix_destroy(pp_matrix A);
 pp_status pp_matrix_tune(pp_matrix A, int prec, void *stream, int *variant, int *remap,
                          double *us_per_launch);
 
-/* Force a chain-step variant (0 <= variant < 32, remap 0/1; 15 = persistent) for a precision
+/* Force a chain-step variant (0 <= variant < 34, remap 0/1; 15 = persistent) for a precision
  * instead of tuning, e.g. to test every variant. Variant 31 (box) applies to a
  * constant-coefficient 5- or 7-point box stencil (see pp_matrix_march's
  * `constant`) whose grid lines hold a multiple of 4 points: it reads no
  * per-row matrix data, only the interior row's coefficients, and sums each
- * row's terms as the pattern-coded variants do; PP_EINVAL elsewhere. */
+ * row's terms as the pattern-coded variants do; PP_EINVAL elsewhere.
+ * Variants 32 and 33 (csort4, csort2) read the column-sorted copy that
+ * pp_matrix_create builds for matrices of at least 4096 rows without a
+ * diagonal-format copy: rows in blocks of 8192, columns in 16 to 128 bands,
+ * each (block, band) tile's entries sorted by column so that a wave's
+ * gathers share cache lines; a second launch adds, per row, the diagonal
+ * product and the 4 (csort4) or 2 (csort2) partial sums in band order, then
+ * finishes the step. PP_EINVAL when the copy is absent. */
 pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap);
 
 /* The chain-step variant in use for a precision, without tuning: variant

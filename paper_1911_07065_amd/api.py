@@ -25,7 +25,7 @@ def version() -> str:
     return lib.pp_version().decode()
 
 
-N_CHAIN_VARIANTS = 32
+N_CHAIN_VARIANTS = 34
 
 
 def chain_variant_name(v: int) -> str:

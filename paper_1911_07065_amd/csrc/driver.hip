@@ -12,6 +12,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <utility>
 #include <vector>
@@ -115,6 +116,15 @@ struct pp_matrix_s {
     int bandK[2] = {0, 0};
     long bnnz[2] = {0, 0};
     double *bpart = nullptr;
+    // column-sorted tiles (cs_nb == 0: none); cs_perm / cs_dperm map tile
+    // entries and held-apart diagonal entries to CSR positions
+    uint32_t *cs_code = nullptr;
+    int32_t *cs_perm = nullptr, *cs_toff = nullptr, *cs_dperm = nullptr;
+    uint16_t *cs_tptr = nullptr;
+    double *cs_val64 = nullptr, *cs_dg64 = nullptr, *cs_part = nullptr;
+    float *cs_val32 = nullptr, *cs_dg32 = nullptr;
+    int cs_nb = 0, cs_sb = 0, cs_W = 0, cs_maxe = 0;
+    long cs_nnz = 0;
     // pattern-coded diagonal copy (few distinct rows; dropped with the value codes)
     uint32_t *pcode = nullptr;
     uint8_t *pbyte = nullptr;
@@ -198,6 +208,18 @@ struct pp_matrix_s {
             d.bandK[c] = bandK[c];
         }
         d.bpart = bpart;
+        d.cs_code = cs_code;
+        d.cs_val64 = cs_val64;
+        d.cs_val32 = cs_val32;
+        d.cs_toff = cs_toff;
+        d.cs_tptr = cs_tptr;
+        d.cs_dg64 = cs_dperm ? cs_dg64 : nullptr;
+        d.cs_dg32 = cs_dperm ? cs_dg32 : nullptr;
+        d.cs_part = cs_part;
+        d.cs_nb = cs_nb;
+        d.cs_sb = cs_sb;
+        d.cs_W = cs_W;
+        d.cs_maxe = cs_maxe;
         d.pcode = pcode;
         d.pbyte = pbyte;
         d.ptab64 = ptab64;
@@ -318,6 +340,16 @@ struct pp_matrix_s {
             dev_free(btile[c]);
         }
         dev_free(bpart);
+        dev_free(cs_code);
+        dev_free(cs_perm);
+        dev_free(cs_toff);
+        dev_free(cs_dperm);
+        dev_free(cs_tptr);
+        dev_free(cs_val64);
+        dev_free(cs_val32);
+        dev_free(cs_dg64);
+        dev_free(cs_dg32);
+        dev_free(cs_part);
         dev_free(val_own);
         dev_free(scale);
         dev_free(sval64);
@@ -470,6 +502,7 @@ pp_status tune_chain(pp_matrix A, int prec, hipStream_t st) {
             ((v == CV_SELLD || v == CV_SELLD4) && !A->sdel) || ((v == CV_DIA || v == CV_DIA4) && A->h_doff.empty()) ||
             (v == CV_DIAC && !A->dcode) || (v == CV_DIAP && !A->pcode) || (v == CV_DIAPV && !A->pbyte) ||
             (v == CV_BAND2 && A->bandK[0] == 0) || (v == CV_BAND4 && A->bandK[1] == 0) ||
+            ((v == CV_CSORT4 || v == CV_CSORT2) && A->cs_nb == 0) ||
             (v == CV_TILEB8 && A->ntileB8[prec] == 0) ||
             (v == CV_TILEB16 && A->ntileB16[prec] == 0) || (v == CV_BOX && !box_step_ok(A->dev())))
             continue;
@@ -979,6 +1012,15 @@ int64_t format_bytes(pp_matrix A, int prec) {
             const int64_t K = A->bandK[c];
             return (int64_t)A->bnnz[c] * (sv + 4) + K * 4 * (n + 1) + (K - 1) * 2 * n * sv;
         }
+        case CV_CSORT4:
+        case CV_CSORT2: {
+            // tile entries (word + value), tile row pointers and offsets, the
+            // held-apart diagonal, each partial sum written and read
+            const int64_t nsb = A->variant[prec] == CV_CSORT4 ? 4 : 2;
+            const int64_t nt = (n + kCsRows - 1) / kCsRows * A->cs_nb;
+            return (int64_t)A->cs_nnz * (sv + 4) + nt * (kCsRows + 1) * 2 + (nt + 1) * 4 +
+                   (A->cs_dperm ? n * sv : 0) + 2 * nsb * n * sv;
+        }
         default:  // CSR: row tiles, lanes per row, persistent
             return nnz * (sv + 4) + 4 * (n + 1);
     }
@@ -988,6 +1030,7 @@ int64_t format_bytes(pp_matrix A, int prec) {
 int64_t product_launches(pp_matrix A, int prec) {
     const int v = A->variant[prec];
     if (v == CV_BAND2 || v == CV_BAND4) return A->bandK[v == CV_BAND2 ? 0 : 1];
+    if (v == CV_CSORT4 || v == CV_CSORT2) return 2;
     return 1;
 }
 
@@ -1221,6 +1264,131 @@ pp_status build_bands(pp_matrix A, const std::vector<int32_t> &rp, const std::ve
     }
     A->bnnz[c] = nnz;
     A->bandK[c] = K;
+    return PP_OK;
+}
+
+// Column-sorted tiles (the layout is described with DevCSR). The band count
+// is the smallest of 16, 32, 64, 128 for which every band is non-empty and
+// every tile fits: at most 65535 entries, its FP64 products in 80 KB of LDS
+// (two workgroups per CU), column offset and slot in one 32-bit word. When
+// none fits the matrix has no such copy. The diagonal is held apart when
+// every row stores exactly one diagonal entry. Blocks are laid out on
+// several host threads.
+pp_status build_csort(pp_matrix A, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, const double *val,
+                      hipStream_t st) {
+    const int64_t n = A->n;
+    const int nblk = (int)((n + kCsRows - 1) / kCsRows);
+    std::vector<int32_t> dpos((size_t)n, -1);
+    bool split = true;
+    for (int64_t r = 0; r < n && split; ++r)
+        for (int e = rp[r]; e < rp[r + 1]; ++e)
+            if (ci[e] == r) {
+                if (dpos[r] >= 0) split = false;
+                dpos[r] = e;
+            }
+    for (int64_t r = 0; r < n && split; ++r)
+        if (dpos[r] < 0) split = false;
+    int nb = 0, sb = 0;
+    int64_t W = 0, maxe = 0;
+    std::vector<int64_t> cnt;
+    for (int cand : {16, 32, 64, 128}) {
+        const int64_t w = (n + cand - 1) / cand;
+        if ((cand - 1) * w >= n) continue;  // the last band would be empty
+        cnt.assign((size_t)nblk * cand, 0);
+        for (int64_t r = 0; r < n; ++r)
+            for (int e = rp[r]; e < rp[r + 1]; ++e)
+                if (!(split && e == dpos[r])) cnt[(size_t)(r / kCsRows) * cand + ci[e] / w]++;
+        int64_t mx = 1;
+        for (int64_t c : cnt) mx = std::max(mx, c);
+        int bits = 1, cbits = 0;
+        while ((int64_t(1) << bits) < mx) ++bits;
+        while ((int64_t(1) << cbits) < w) ++cbits;
+        if (mx <= 65535 && mx * 8 <= 80 * 1024 && bits + cbits <= 32) {
+            nb = cand;
+            sb = bits;
+            W = w;
+            maxe = mx;
+            break;
+        }
+    }
+    if (nb == 0) return PP_OK;
+    const size_t nt = (size_t)nblk * nb;
+    std::vector<int32_t> toff(nt + 1, 0);
+    for (size_t t = 0; t < nt; ++t) toff[t + 1] = toff[t] + (int32_t)cnt[t];
+    const int64_t ne = toff[nt];
+    std::vector<uint32_t> code((size_t)ne);
+    std::vector<int32_t> perm((size_t)ne);
+    std::vector<uint16_t> tptr(nt * (kCsRows + 1));
+    auto lay_block = [&](int b) {
+        const int64_t r0 = (int64_t)b * kCsRows, r1 = std::min<int64_t>(n, r0 + kCsRows);
+        std::vector<int32_t> run(nb, 0);
+        std::vector<std::vector<std::pair<uint64_t, int32_t>>> ent(nb);  // (column << 20 | slot, CSR index)
+        for (int c = 0; c < nb; ++c) ent[c].reserve((size_t)cnt[(size_t)b * nb + c]);
+        for (int64_t r = r0; r < r1; ++r) {
+            for (int c = 0; c < nb; ++c) tptr[((size_t)b * nb + c) * (kCsRows + 1) + (r - r0)] = (uint16_t)run[c];
+            for (int e = rp[r]; e < rp[r + 1]; ++e) {
+                if (split && e == dpos[r]) continue;
+                const int c = (int)(ci[e] / W);
+                ent[c].push_back({((uint64_t)ci[e] << 20) | (uint64_t)run[c], e});
+                ++run[c];
+            }
+        }
+        for (int c = 0; c < nb; ++c) {
+            const size_t t = (size_t)b * nb + c;
+            for (int64_t rl = r1 - r0; rl <= kCsRows; ++rl) tptr[t * (kCsRows + 1) + rl] = (uint16_t)run[c];
+            std::sort(ent[c].begin(), ent[c].end());
+            for (size_t i = 0; i < ent[c].size(); ++i) {
+                const uint64_t col = ent[c][i].first >> 20, slot = ent[c][i].first & 0xFFFFF;
+                code[toff[t] + i] = (uint32_t)(((col - (uint64_t)c * W) << sb) | slot);
+                perm[toff[t] + i] = ent[c][i].second;
+            }
+        }
+    };
+    {
+        const int nth = std::max(1, std::min<int>(std::min(nblk, 8), (int)std::thread::hardware_concurrency()));
+        std::vector<std::thread> pool;
+        for (int h = 0; h < nth; ++h)
+            pool.emplace_back([&, h]() {
+                for (int b = h; b < nblk; b += nth) lay_block(b);
+            });
+        for (auto &th : pool) th.join();
+    }
+    PP_TRY(dev_alloc(&A->cs_code, (size_t)std::max<int64_t>(ne, 1)));
+    PP_TRY(dev_alloc(&A->cs_perm, (size_t)std::max<int64_t>(ne, 1)));
+    PP_TRY(dev_alloc(&A->cs_val64, (size_t)std::max<int64_t>(ne, 1)));
+    PP_TRY(dev_alloc(&A->cs_val32, (size_t)std::max<int64_t>(ne, 1)));
+    PP_TRY(dev_alloc(&A->cs_toff, toff.size()));
+    PP_TRY(dev_alloc(&A->cs_tptr, tptr.size()));
+    PP_TRY(dev_alloc(&A->cs_part, (size_t)kCsMaxParts * n));
+    if ((ne > 0 && (hipMemcpyAsync(A->cs_code, code.data(), sizeof(uint32_t) * ne, hipMemcpyHostToDevice, st) !=
+                        hipSuccess ||
+                    hipMemcpyAsync(A->cs_perm, perm.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice, st) !=
+                        hipSuccess ||
+                    launch_sell_values(ne, A->cs_perm, val, A->cs_val64, A->cs_val32, st) != hipSuccess)) ||
+        hipMemcpyAsync(A->cs_toff, toff.data(), sizeof(int32_t) * toff.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(A->cs_tptr, tptr.data(), sizeof(uint16_t) * tptr.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("pp_matrix_create: column-sorted upload failed");
+        return PP_EDEVICE;
+    }
+    if (split) {
+        PP_TRY(dev_alloc(&A->cs_dperm, (size_t)n));
+        PP_TRY(dev_alloc(&A->cs_dg64, (size_t)n));
+        PP_TRY(dev_alloc(&A->cs_dg32, (size_t)n));
+        if (hipMemcpyAsync(A->cs_dperm, dpos.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+            launch_sell_values(n, A->cs_dperm, val, A->cs_dg64, A->cs_dg32, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            set_error("pp_matrix_create: column-sorted upload failed");
+            return PP_EDEVICE;
+        }
+    }
+    A->cs_nnz = ne;
+    A->cs_nb = nb;
+    A->cs_sb = sb;
+    A->cs_W = (int)W;
+    A->cs_maxe = (int)maxe;
     return PP_OK;
 }
 
@@ -1678,6 +1846,7 @@ pp_status pp_matrix_create(int64_t n, int64_t nnz, const int32_t *rowptr, const 
     if (nnz > 0 && n >= 4096 && A->h_doff.empty()) {
         if ((s = build_bands(A, rp, ci, val, 0, 2, st)) != PP_OK) return fail(s);
         if ((s = build_bands(A, rp, ci, val, 1, 4, st)) != PP_OK) return fail(s);
+        if ((s = build_csort(A, rp, ci, val, st)) != PP_OK) return fail(s);
     }
     {
         // tuning program of the persistent kernel: 8 sparse products P0 -> P1 -> P0 ...
@@ -1710,6 +1879,10 @@ pp_status refresh_values(pp_matrix A, const double *val, hipStream_t st) {
                                    A->dval64, A->dval32, st));
     for (int c = 0; c < 2; ++c)
         if (A->bandK[c] > 0) HIP_TRY(launch_sell_values(A->bnnz[c], A->bperm[c], val, A->bval64[c], A->bval32[c], st));
+    if (A->cs_nb > 0) {
+        if (A->cs_nnz > 0) HIP_TRY(launch_sell_values(A->cs_nnz, A->cs_perm, val, A->cs_val64, A->cs_val32, st));
+        if (A->cs_dperm) HIP_TRY(launch_sell_values(A->n, A->cs_dperm, val, A->cs_dg64, A->cs_dg32, st));
+    }
     if (A->dcode) {
         // the codes stay when every entry still equals its code's new value
         // (a constant-coefficient stencil with new coefficients); else drop
@@ -2060,6 +2233,11 @@ pp_status pp_matrix_set_variant(pp_matrix A, int prec, int variant, int remap) {
         if ((variant == CV_BAND2 && A->bandK[0] == 0) || (variant == CV_BAND4 && A->bandK[1] == 0)) {
             set_error("pp_matrix_set_variant: no column-banded copy (built only for matrices of at least 4096 rows "
                       "whose entries lie far from the diagonal)");
+            return PP_EINVAL;
+        }
+        if ((variant == CV_CSORT4 || variant == CV_CSORT2) && A->cs_nb == 0) {
+            set_error("pp_matrix_set_variant: no column-sorted copy (built only for matrices of at least 4096 rows "
+                      "whose entries lie far from the diagonal, when every tile fits)");
             return PP_EINVAL;
         }
         if ((variant == CV_DIAP && !A->pcode) || (variant == CV_DIAPV && !A->pbyte)) {

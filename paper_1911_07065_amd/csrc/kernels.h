@@ -46,7 +46,9 @@ enum ChainVariant : int {
     CV_BAND4 = 29,    // the same with 4 column bands
     CV_DIAPV = 30,    // pattern-coded diagonals, 4 consecutive rows per lane with vector loads
     CV_BOX = 31,      // constant-coefficient box stencil: no per-row matrix data, 4 points of a grid line per lane
-    CV_COUNT = 32
+    CV_CSORT4 = 32,   // column-sorted tiles of kCsRows rows x one column band, 4 partial sums per row
+    CV_CSORT2 = 33,   // the same, 2 partial sums per row (twice the bands per workgroup)
+    CV_COUNT = 34
 };
 
 // A chain step as the persistent kernel reads it from device memory.
@@ -75,6 +77,10 @@ struct StepPtrs {
     // spmv == 0: the product term a0 * prod[r] comes from this vector (null: none)
     const void *prod = nullptr;
 };
+
+// Column-sorted tiles: rows per block, and the most partial sums per row.
+constexpr int kCsRows = 8192;
+constexpr int kCsMaxParts = 4;
 
 // Diagonals of the diagonal format, passed by value (uniform per launch).
 constexpr int kMaxDiag = 32;
@@ -148,6 +154,25 @@ struct DevCSR {
     const double *ptab64;
     const float *ptab32;
     int npat;
+    // column-sorted tiles (absent if cs_nb == 0): rows in blocks of kCsRows,
+    // columns in cs_nb bands of cs_W (every band non-empty); tile
+    // t = block * cs_nb + band holds the block's entries in the band, entries
+    // cs_toff[t] .. cs_toff[t+1], sorted by column. Entry e is the word
+    // cs_code[e] = (column - band cs_W) << cs_sb | slot, slot = the entry's
+    // rank in the tile in row-major (CSR) order, and the value cs_val[e];
+    // cs_tptr[t (kCsRows + 1) + rl] is the first slot of the block's row rl.
+    // cs_dg: every row's diagonal entry, held apart from the tiles (null:
+    // the diagonal is in the tiles). cs_part: kCsMaxParts n partial row sums
+    // (8 bytes each). cs_maxe: the largest tile.
+    const uint32_t *cs_code;
+    const double *cs_val64;
+    const float *cs_val32;
+    const int32_t *cs_toff;
+    const uint16_t *cs_tptr;
+    const double *cs_dg64;
+    const float *cs_dg32;
+    void *cs_part;
+    int cs_nb, cs_sb, cs_W, cs_maxe;
     // box geometry (box_nd == 0: none): the rows are the points of a
     // box[0] x box[1] x box[2] grid, row x + box[0] (y + box[1] z), with
     // entries only on the diagonals 0, +-1, +-box[0] (and +-box[0] box[1]

@@ -942,6 +942,148 @@ const float *dia_vals<float>(const DevCSR &A) {
     return A.dval32;
 }
 
+// ---------------------------------------------------------------------------
+// column-sorted tiles (CV_CSORT4 / CV_CSORT2)
+//
+// On a matrix whose entries scatter over all columns, the 64 gathers of one
+// wave of a CSR stream land on 64 different cache lines, and the L2 request
+// rate, not HBM, bounds the product. Here the rows form blocks of kCsRows
+// and the columns cs_nb bands; the entries of a (block, band) tile are
+// stored sorted by column, so 64 consecutive entries of a tile span a narrow
+// column range and share cache lines (a block of 8192 rows with 16 entries
+// each: about 2 columns apart on average). The order of each row's sum
+// stays fixed: a product goes to LDS at its slot (the entry's rank in
+// row-major order) and every row adds its slots in order.
+//
+// k_chain_cs_tiles: a workgroup of 1024 threads takes G consecutive bands
+// of one block, keeps its rows' running sums in registers (kCsRows / 1024
+// rows per thread) and stores them as partial sum k of nsb = cs_nb / G.
+// k_chain_cs_finish: per row, the diagonal product (when held apart), then
+// the partial sums in band order, then the step's vector update.
+// ---------------------------------------------------------------------------
+
+constexpr int kCsThreads = 1024;
+constexpr int kCsRPT = kCsRows / kCsThreads;
+
+template <typename VT, typename XT>
+__global__ __launch_bounds__(kCsThreads, 8) void k_chain_cs_tiles(const uint32_t *__restrict__ code,
+                                                               const VT *__restrict__ val,
+                                                               const int32_t *__restrict__ toff,
+                                                               const uint16_t *__restrict__ tptr, int nb, int sb, int W,
+                                                               int n, int G, const XT *__restrict__ in,
+                                                               typename Arith<XT>::T *__restrict__ part, int remap) {
+    using AT = typename Arith<XT>::T;
+    constexpr int kCsUnroll = sizeof(AT) == 8 ? 4 : 8;  // entries in flight per thread (64 VGPRs)
+    extern __shared__ __align__(16) unsigned char cs_lds[];
+    AT *prod = reinterpret_cast<AT *>(cs_lds);
+    const int nsb = nb / G;
+    const int w = remap_tile(blockIdx.x, gridDim.x, remap);
+    const int b = w / nsb, k = w - b * nsb;
+    const int tid = threadIdx.x;
+    const int r0 = b * kCsRows, rows = min(kCsRows, n - r0);
+    const uint32_t mask = (1u << sb) - 1u;
+    AT acc[kCsRPT];
+#pragma unroll
+    for (int q = 0; q < kCsRPT; ++q) acc[q] = AT(0);
+    for (int g = 0; g < G; ++g) {
+        const int band = k * G + g, t = b * nb + band;
+        const int e0 = toff[t], e1 = toff[t + 1];
+        const XT *xb = in + (long)band * W;
+        for (int e = e0 + tid; e < e1; e += kCsThreads * kCsUnroll) {
+            uint32_t cd[kCsUnroll];
+            VT v[kCsUnroll];
+#pragma unroll
+            for (int u = 0; u < kCsUnroll; ++u) {
+                const int ee = e + u * kCsThreads;
+                cd[u] = ee < e1 ? __builtin_nontemporal_load(code + ee) : 0u;
+                v[u] = ee < e1 ? __builtin_nontemporal_load(val + ee) : VT(0);
+            }
+            AT xv[kCsUnroll];
+#pragma unroll
+            for (int u = 0; u < kCsUnroll; ++u) xv[u] = ldx(xb, (long)(cd[u] >> sb));
+#pragma unroll
+            for (int u = 0; u < kCsUnroll; ++u)
+                if (e + u * kCsThreads < e1) prod[cd[u] & mask] = (AT)v[u] * xv[u];
+        }
+        __syncthreads();
+        const uint16_t *tp = tptr + (size_t)t * (kCsRows + 1);
+#pragma unroll
+        for (int q = 0; q < kCsRPT; ++q) {
+            const int rl = tid + q * kCsThreads;
+            if (rl < rows) {
+                const int p0 = tp[rl], p1 = tp[rl + 1];
+                AT s = acc[q];
+                for (int j = p0; j < p1; ++j) s += prod[j];
+                acc[q] = s;
+            }
+        }
+        __syncthreads();
+    }
+    AT *pk = part + (size_t)k * n + r0;
+#pragma unroll
+    for (int q = 0; q < kCsRPT; ++q) {
+        const int rl = tid + q * kCsThreads;
+        if (rl < rows) pk[rl] = acc[q];
+    }
+}
+
+template <typename VT, typename XT>
+__global__ __launch_bounds__(256) void k_chain_cs_finish(ChainArgs<VT, XT> a, const VT *__restrict__ dg,
+                                                         const typename Arith<XT>::T *__restrict__ part, int nsb) {
+    using AT = typename Arith<XT>::T;
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= a.n) return;
+    const RowPre<AT> p = row_prefetch(a, r);
+    AT s = dg ? (AT)dg[r] * p.xin : AT(0);
+    for (int k = 0; k < nsb; ++k) s += part[(size_t)k * a.n + r];
+    row_finish(a, r, s, p);
+}
+
+template <typename VT>
+const VT *cs_vals(const DevCSR &A);
+template <>
+const double *cs_vals<double>(const DevCSR &A) {
+    return A.cs_val64;
+}
+template <>
+const float *cs_vals<float>(const DevCSR &A) {
+    return A.cs_val32;
+}
+template <typename VT>
+const VT *cs_diag(const DevCSR &A);
+template <>
+const double *cs_diag<double>(const DevCSR &A) {
+    return A.cs_dg64;
+}
+template <>
+const float *cs_diag<float>(const DevCSR &A) {
+    return A.cs_dg32;
+}
+
+// Both launches of one column-sorted product with `nsb` partial sums per row.
+template <typename VT, typename XT>
+hipError_t cs_launch(const DevCSR &A, const ChainArgs<VT, XT> &a, int nsb, int remap, hipStream_t st) {
+    using AT = typename Arith<XT>::T;
+    if (A.cs_nb <= 0 || !A.cs_part || nsb < 1 || nsb > kCsMaxParts || A.cs_nb % nsb != 0) return hipErrorInvalidValue;
+    const size_t lds = (size_t)A.cs_maxe * sizeof(AT);
+    static bool attr_set = false;  // one per instantiation; the call is idempotent
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_chain_cs_tiles<VT, XT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int nblk = (A.n + kCsRows - 1) / kCsRows;
+    AT *part = (AT *)A.cs_part;
+    hipLaunchKernelGGL((k_chain_cs_tiles<VT, XT>), dim3(nblk * nsb), dim3(kCsThreads), lds, st, A.cs_code, cs_vals<VT>(A),
+                       A.cs_toff, A.cs_tptr, A.cs_nb, A.cs_sb, A.cs_W, A.n, A.cs_nb / nsb, a.in, part, remap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_chain_cs_finish<VT, XT>), dim3((A.n + 255) / 256), dim3(256), 0, st, a, cs_diag<VT>(A), part,
+                       nsb);
+    return hipGetLastError();
+}
+
 template <typename VT>
 const VT *band_vals(const DevCSR &A, int c);
 template <>
@@ -1941,6 +2083,10 @@ hipError_t chain_launch(const DevCSR &A, const VT *val, const StepPtrs &s, int v
             }
             return hipGetLastError();
         }
+        case CV_CSORT4:
+            return cs_launch<VT, XT>(A, a, 4, remap, st);
+        case CV_CSORT2:
+            return cs_launch<VT, XT>(A, a, 2, remap, st);
         case CV_TILEB8: {
             const int p = prec_of<XT>();
             if (A.ntileB8[p] == 0) return hipErrorInvalidValue;
@@ -3245,7 +3391,8 @@ const char *chain_variant_name(int v) {
                                           "vec8x4",  "vec16x2",  "vec16x4", "vec32x2",   "tilev8x1",
                                           "tilev16x2", "vk2x4x4", "vk4x4x2", "vk8x4x1", "vk16x2x2", "persist8",
                                           "tileb8x1", "tileb16x2", "sell64", "sell64t", "sell64x2", "sell64x4", "sell64d16", "sell64d16x4",
-                                              "dia2",   "dia1", "diac", "diap", "tile8b2", "tile8b4", "diapv", "box"};
+                                              "dia2",   "dia1", "diac", "diap", "tile8b2", "tile8b4", "diapv", "box",
+                                          "csort4", "csort2"};
     return (v >= 0 && v < CV_COUNT) ? names[v] : "?";
 }
 

@@ -169,7 +169,7 @@ def test_bad_arguments_rejected(pp):
         pp.Matrix(np.array([0, 2, 1], dtype=np.int32), np.array([0, 1], dtype=np.int32), np.ones(2))  # rowptr
 
 
-@pytest.mark.parametrize("variant", range(32))
+@pytest.mark.parametrize("variant", range(34))
 def test_every_chain_variant_matches_oracle(pp, variant):
     # each kernel variant the autotuner may pick, with and without the XCD order
     for name in ["ragged_5000", "randsparse_20000", "convdiff3d_20"]:
@@ -196,13 +196,96 @@ def test_every_chain_variant_matches_oracle(pp, variant):
                     ("box kernel" in str(exc) and name != "convdiff3d_20") or \
                     (any(k in str(exc) for k in ("diagonal-format", "value-coded", "pattern-coded"))
                      and name != "convdiff3d_20") or \
-                    ("column-banded" in str(exc) and name == "convdiff3d_20"), exc
+                    ("column-banded" in str(exc) and name == "convdiff3d_20") or \
+                    ("column-sorted" in str(exc) and name == "convdiff3d_20"), exc
                 continue
             assert_close(host(pp.apply(poly, M, dev(v), "p")), ref_p, 1e-12, "p", BOXES.get(name))
             assert_close(host(pp.apply(poly, M, dev(v), "phi")), ref_phi, 1e-12, "phi", BOXES.get(name))
             got32 = host(pp.apply(poly, M, dev(v, torch.float32), "p"))
             delta = maxerr(apply_p_low(A32, P.units, v.astype(np.float32)), ref_p)
             assert maxerr(got32, ref_p) <= 10 * delta + 1e-6
+
+
+CSORT = (32, 33)  # column-sorted tiles with 4 and 2 partial sums per row
+
+
+def _csort_cases():
+    """Matrices that stress the column-sorted layout: three full row blocks
+    and a ragged one; rows without a diagonal entry (the diagonal stays in
+    the tiles); 40 entries per row (the tiles need 64 bands to fit)."""
+    a = randsparse(3 * 8192 + 77, 16, seed=21)
+    A = a.to_scipy().tolil()
+    for r in range(0, a.n, 7):
+        A[r, r] = 0.0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    A.sort_indices()
+    nodiag = CSR(a.n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
+    return {"blocks_24653": (a, 12), "some_rows_without_diagonal": (nodiag, 10),
+            "dense_rows_20000": (randsparse(20000, 40, seed=5), 8)}
+
+
+@pytest.mark.parametrize("name", list(_csort_cases()))
+def test_column_sorted_tiles_match_oracle(pp, name):
+    # both column-sorted variants, with and without the XCD order, FP64 and
+    # FP32, p and phi chains, element-wise against the oracle
+    csr, d = _csort_cases()[name]
+    A = csr.to_scipy()
+    A32 = A.astype(np.float32)
+    P = oroots.setup(A, start_vector(csr.n, 2), d)
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.poly_from_roots(P.roots(), keep_order=True)
+    v = rhs(csr.n, 5)
+    ref_p = chains.apply_p(A, P.units, v)
+    ref_phi = chains.apply_phi(A, P.units, v)
+    delta = maxerr(apply_p_low(A32, P.units, v.astype(np.float32)), ref_p)
+    for variant in CSORT:
+        for remap in (0, 1):
+            say("column-sorted", name, pp.chain_variant_name(variant), remap)
+            M.set_variant("fp64", variant, remap)
+            M.set_variant("fp32", variant, remap)
+            assert_close(host(pp.apply(poly, M, dev(v), "p")), ref_p, 1e-12, f"{name} p")
+            assert_close(host(pp.apply(poly, M, dev(v), "phi")), ref_phi, 1e-12, f"{name} phi")
+            got32 = host(pp.apply(poly, M, dev(v, torch.float32), "p"))
+            assert maxerr(got32, ref_p) <= 10 * delta + 1e-6
+    # each row's sum has a fixed order: repeated products are identical
+    a = pp.apply(poly, M, dev(v, torch.float32), "phi").clone()
+    b = pp.apply(poly, M, dev(v, torch.float32), "phi").clone()
+    assert torch.equal(a, b)
+
+
+def test_column_sorted_tiles_full_size(pp):
+    # the random sparse workload at its size (n = 1e6, 17 entries per row):
+    # p(A)v of a small polynomial, both variants, element-wise against the
+    # oracle; the bytes by definition count the tile words and values, the
+    # tile row pointers and offsets, the diagonal and the partial sums
+    csr = randsparse(1_000_000, 16, seed=7)
+    A = csr.to_scipy()
+    th = np.array([2.5, 0.7, 1.5 + 0.5j, 1.5 - 0.5j, 3.0])
+    P = oroots.poly_from_roots(th)
+    poly = pp.poly_from_roots(P.roots(), keep_order=True)
+    M = pp.Matrix.from_csr(csr)
+    v = rhs(csr.n, 3)
+    ref = chains.apply_p(A, P.units, v)
+    n = csr.n
+    M.set_variant("fp32", 0, 1)  # tile8x1: CSR bytes, one launch per product
+    b0, l0 = pp.chain_bytes(poly, M, "phi", "fp32")
+    for variant in CSORT:
+        for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 2e-5)):
+            say("column-sorted full size", pp.chain_variant_name(variant), prec)
+            M.set_variant(prec, variant, 1)
+            assert_close(host(pp.apply(poly, M, dev(v, dt), "p")), ref, tol, f"full size {variant} {prec}")
+        # per product, against CSR (8 bytes per entry, 4 (n + 1) row
+        # pointers): the n diagonal entries leave the tiles (8 bytes each)
+        # and come back as a 4-byte diagonal; 16 bands of 123 blocks add
+        # their 8193 2-byte row pointers and 4-byte offsets; each of the nsb
+        # partial sums is written and read once (4 bytes a row)
+        b, launches = pp.chain_bytes(poly, M, "phi", "fp32")
+        products = launches - l0
+        nsb = 4 if variant == 32 else 2
+        nt = -(-n // 8192) * 16
+        per = -8 * n + 4 * n + nt * 8193 * 2 + (nt + 1) * 4 + 2 * nsb * n * 4 - 4 * (n + 1)
+        assert products > 0 and b - b0 == products * per, (b, b0, products, per)
 
 
 @pytest.mark.parametrize("case", ["diagonal_1000", "tridiag_1000", "convdiff2d_37", "convdiff3d_9"])
