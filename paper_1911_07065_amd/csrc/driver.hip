@@ -1303,7 +1303,7 @@ pp_status build_csort(pp_matrix A, const std::vector<int32_t> &rp, const std::ve
         int bits = 1, cbits = 0;
         while ((int64_t(1) << bits) < mx) ++bits;
         while ((int64_t(1) << cbits) < w) ++cbits;
-        if (mx <= 65535 && mx * 8 <= 80 * 1024 && bits + cbits <= 32) {
+        if (mx <= 65535 && mx * 8 <= kCsLdsBytes && bits + cbits <= 32) {
             nb = cand;
             sb = bits;
             W = w;

@@ -78,9 +78,11 @@ struct StepPtrs {
     const void *prod = nullptr;
 };
 
-// Column-sorted tiles: rows per block, and the most partial sums per row.
+// Column-sorted tiles: rows per block, the most partial sums per row, and
+// the LDS bytes a tile's products may take (two workgroups per CU).
 constexpr int kCsRows = 8192;
 constexpr int kCsMaxParts = 4;
+constexpr int kCsLdsBytes = 80 * 1024;
 
 // Diagonals of the diagonal format, passed by value (uniform per launch).
 constexpr int kMaxDiag = 32;

@@ -989,6 +989,15 @@ __global__ __launch_bounds__(kCsThreads, 8) void k_chain_cs_tiles(const uint32_t
         const int band = k * G + g, t = b * nb + band;
         const int e0 = toff[t], e1 = toff[t + 1];
         const XT *xb = in + (long)band * W;
+        // this thread's rows' first and end slots in the tile, two 16-bit
+        // values per word, loaded before the gathers so that they arrive with them
+        const uint16_t *tp = tptr + (size_t)t * (kCsRows + 1);
+        uint32_t span[kCsRPT];
+#pragma unroll
+        for (int q = 0; q < kCsRPT; ++q) {
+            const int rl = tid + q * kCsThreads;
+            span[q] = rl < rows ? (uint32_t)tp[rl] | ((uint32_t)tp[rl + 1] << 16) : 0u;
+        }
         for (int e = e0 + tid; e < e1; e += kCsThreads * kCsUnroll) {
             uint32_t cd[kCsUnroll];
             VT v[kCsUnroll];
@@ -1006,16 +1015,12 @@ __global__ __launch_bounds__(kCsThreads, 8) void k_chain_cs_tiles(const uint32_t
                 if (e + u * kCsThreads < e1) prod[cd[u] & mask] = (AT)v[u] * xv[u];
         }
         __syncthreads();
-        const uint16_t *tp = tptr + (size_t)t * (kCsRows + 1);
 #pragma unroll
         for (int q = 0; q < kCsRPT; ++q) {
-            const int rl = tid + q * kCsThreads;
-            if (rl < rows) {
-                const int p0 = tp[rl], p1 = tp[rl + 1];
-                AT s = acc[q];
-                for (int j = p0; j < p1; ++j) s += prod[j];
-                acc[q] = s;
-            }
+            const int p0 = (int)(span[q] & 0xFFFFu), p1 = (int)(span[q] >> 16);
+            AT s = acc[q];
+            for (int j = p0; j < p1; ++j) s += prod[j];
+            acc[q] = s;
         }
         __syncthreads();
     }
@@ -1066,10 +1071,11 @@ hipError_t cs_launch(const DevCSR &A, const ChainArgs<VT, XT> &a, int nsb, int r
     using AT = typename Arith<XT>::T;
     if (A.cs_nb <= 0 || !A.cs_part || nsb < 1 || nsb > kCsMaxParts || A.cs_nb % nsb != 0) return hipErrorInvalidValue;
     const size_t lds = (size_t)A.cs_maxe * sizeof(AT);
+    if (lds > (size_t)kCsLdsBytes) return hipErrorInvalidValue;  // the copy is built within this bound
     static bool attr_set = false;  // one per instantiation; the call is idempotent
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)k_chain_cs_tiles<VT, XT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kCsLdsBytes);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
