@@ -330,6 +330,19 @@ pp_status pp_adjoint_values(pp_matrix A, const double *lam, const double *x, dou
 pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, void *stream,
                          pp_poly *out, pp_setup_info *info);
 
+/* The same polynomial setup (Algorithm 4 step 1) with the Krylov vectors of
+ * the GMRES(d) cycle stored in `basis` precision: PP_F64 (as pp_gmres_setup)
+ * or PP_F32 (binary32 vectors, half the bytes of the Gram-Schmidt sweeps and
+ * the sparse products; dot products, norms and the Hessenberg matrix are
+ * still accumulated in FP64). The harmonic Ritz values of a PP_F32 basis
+ * differ from the FP64 ones by the rounding of the stored vectors (about
+ * 1e-6 relative on well-separated values); the polynomial is a
+ * preconditioner, so a solve still reaches its tolerance through the FP64
+ * residual and refinement. Arguments and returns as pp_gmres_setup;
+ * PP_EINVAL for another basis. */
+pp_status pp_gmres_setup_basis(pp_matrix A, const double *v0, int d, int add_roots, int basis, void *stream,
+                               pp_poly *out, pp_setup_info *info);
+
 /* Options of the stability check run by pp_gmres_setup_checked (section 3.5). */
 typedef struct {
     const double *b; /* device double[n]: the problem right-hand side the check uses */

@@ -68,6 +68,8 @@ SIGNATURES = {
     "pp_adjoint_values": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pp_gmres_setup": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p),
                                ctypes.POINTER(SetupInfo)]),
+    "pp_gmres_setup_basis": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p),
+                                     ctypes.POINTER(SetupInfo)]),
     "pp_gmres_setup_double": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p),
                                       ctypes.POINTER(SetupInfo)]),
     "pp_gmres_setup_checked": (c_int, [c_void_p, c_void_p, c_int, c_int, ctypes.POINTER(StchOpts), c_void_p,

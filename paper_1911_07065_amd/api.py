@@ -289,15 +289,24 @@ def _poly_from_handle(h, setup_info=None, breakdown=False) -> Poly:
     return Poly(h, do.value, de.value, na.value, breakdown, setup_info)
 
 
-def setup(A: Matrix, v0, d: int, add_roots: bool = True) -> Poly:
-    """Polynomial of degree d from one GMRES(d) cycle on A started at v0 (Algorithm 4 step 1)."""
+def setup(A: Matrix, v0, d: int, add_roots: bool = True, basis: str = "fp64") -> Poly:
+    """Polynomial of degree d from one GMRES(d) cycle on A started at v0
+    (Algorithm 4 step 1). basis: "fp64", or "fp32" to store the cycle's
+    Krylov vectors in binary32 (FP64 dot products and Hessenberg)."""
     v0 = _dev_tensor(v0, torch.float64, A.device)
     if v0.numel() != A.n:
         raise ValueError("start vector length")
     h = ctypes.c_void_p()
     info = SetupInfo()
-    st = check(lib.pp_gmres_setup(A.handle, _ptr(v0), int(d), int(bool(add_roots)), _stream(A.device),
-                                  ctypes.byref(h), ctypes.byref(info)), "pp_gmres_setup")
+    if basis == "fp64":
+        st = check(lib.pp_gmres_setup(A.handle, _ptr(v0), int(d), int(bool(add_roots)), _stream(A.device),
+                                      ctypes.byref(h), ctypes.byref(info)), "pp_gmres_setup")
+    elif basis == "fp32":
+        st = check(lib.pp_gmres_setup_basis(A.handle, _ptr(v0), int(d), int(bool(add_roots)), PREC["fp32"],
+                                            _stream(A.device), ctypes.byref(h), ctypes.byref(info)),
+                   "pp_gmres_setup_basis")
+    else:
+        raise ValueError("basis must be 'fp64' or 'fp32'")
     si = {k: getattr(info, k) for k, _ in SetupInfo._fields_}
     return _poly_from_handle(h, si, breakdown=(st == PP_BREAKDOWN) or bool(info.breakdown))
 

@@ -2450,20 +2450,29 @@ namespace {
 // form the next pending vector from w through the Arnoldi relation
 // A V_j = V_{j+1} Hbar: two sweeps over the basis per step instead of
 // three. A last dot pass finishes column d-1.
+// basis: the precision the Krylov vectors are stored in (0 binary64, 1
+// binary32; dot products, norms and the Hessenberg in FP64 either way).
 pp_status setup_arnoldi(pp_matrix A, const double *v0, int d, hipStream_t st, std::vector<double> &Hbar, int &k,
-                        bool &brk, int64_t &dots, const char *who, pp_poly op = nullptr) {
-    PP_TRY(A->ensure_ws(0, d));
+                        bool &brk, int64_t &dots, const char *who, pp_poly op = nullptr, int basis = 0) {
+    if (basis != 0 && basis != 1) {
+        set_error(std::string(who) + ": basis precision must be FP64 or FP32");
+        return PP_EINVAL;
+    }
+    PP_TRY(A->ensure_ws(basis, d));
     PP_TRY(A->ensure_red(2 * d + 4));
-    const Workspace &ws = A->ws[0];
+    const Workspace &ws = A->ws[basis];
     const int n = A->n;
-    double *u = (double *)ws.D, *w = (double *)ws.ACC;
+    void *u = ws.D, *w = ws.ACC;
     double v0n = 0.0;
     PP_TRY(dev_norm(A, 0, v0, &v0n, st));
     if (!(v0n > 0.0) || !std::isfinite(v0n)) {
         set_error(std::string(who) + ": start vector is zero or not finite");
         return PP_EINVAL;
     }
-    HIP_TRY(hipMemcpyAsync(u, v0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    if (basis == 0)
+        HIP_TRY(hipMemcpyAsync(u, v0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    else
+        HIP_TRY(launch_convert(0, basis, n, v0, u, st));
     // All steps are queued without a host round trip: the Hessenberg columns
     // stay in device memory and the host looks for a breakdown once at the
     // end (columns after a breakdown are discarded).
@@ -2483,18 +2492,18 @@ pp_status setup_arnoldi(pp_matrix A, const double *v0, int d, hipStream_t st, st
         if (!last) {
             // the operator: A, or phi1(A) for the second polynomial of a double one
             if (op)
-                PP_TRY(run_program(A, op, PP_APPLY_PHI, 0, u, w, st));
+                PP_TRY(run_program(A, op, PP_APPLY_PHI, basis, u, w, st));
             else
-                PP_TRY(spmv_axpby(A, 0, u, 1.0, nullptr, 0.0, w, st));
+                PP_TRY(spmv_axpby(A, basis, u, 1.0, nullptr, 0.0, w, st));
         }
         int prow = 0;
-        HIP_TRY(launch_dots_pair(n, (const double *)ws.V, ws.ldv, j, u, last ? u : w, A->partial, A->ldp,
-                                 A->nblk_dot, &prow, st));
+        HIP_TRY(launch_dots_pair(basis, n, ws.V, ws.ldv, j, u, last ? u : w, A->partial, A->ldp, A->nblk_dot, &prow,
+                                 st));
         HIP_TRY(launch_reduce(prow, A->partial, A->ldp, 2 * j + 2, dd, nullptr, 0, st));
         HIP_TRY(launch_dcgs_step(j, dd, Hdev, ld, pend, coef, last ? 1 : 0, st));
         if (!last)
-            HIP_TRY(launch_update_pair(n, (const double *)ws.V, ws.ldv, j, dd, dd + 2 * j + 2, coef, u, w,
-                                       (double *)vcol(ws, 0, j), st));
+            HIP_TRY(launch_update_pair(basis, n, ws.V, ws.ldv, j, dd, dd + 2 * j + 2, coef, u, w,
+                                       vcol(ws, basis, j), st));
     }
     Hbar.assign((size_t)ld * d, 0.0);
     HIP_TRY(hipMemcpyAsync(Hbar.data(), Hdev, sizeof(double) * ld * d, hipMemcpyDeviceToHost, st));
@@ -2573,6 +2582,34 @@ pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, vo
     PP_TRY(setup_arnoldi(A, v0, d, st, Hbar, k, brk, dots, "pp_gmres_setup"));
     pp_poly p = nullptr;
     PP_TRY(poly_from_hbar(Hbar, d + 1, k, brk, add_roots != 0, "pp_gmres_setup", &p));
+    *out = p;
+    if (info) {
+        info->d = k;
+        info->d_eff = p->plan.d_eff;
+        info->n_added = p->plan.n_added;
+        info->breakdown = brk ? 1 : 0;
+        info->mvps = k;
+        info->dots = dots;
+        info->t_setup_s = now_s() - t0;
+    }
+    return (brk && k < d) ? PP_BREAKDOWN : PP_OK;
+}
+
+pp_status pp_gmres_setup_basis(pp_matrix A, const double *v0, int d, int add_roots, int basis, void *stream,
+                               pp_poly *out, pp_setup_info *info) {
+    if (!A || !v0 || !out || d < 1 || d > A->n || d > kMaxDegree || (basis != PP_F64 && basis != PP_F32)) {
+        set_error("pp_gmres_setup_basis: bad argument (need 1 <= d <= min(n, 4096), basis PP_F64 or PP_F32)");
+        return PP_EINVAL;
+    }
+    hipStream_t st = S(stream);
+    const double t0 = now_s();
+    std::vector<double> Hbar;
+    int k = 0;
+    bool brk = false;
+    int64_t dots = 0;
+    PP_TRY(setup_arnoldi(A, v0, d, st, Hbar, k, brk, dots, "pp_gmres_setup_basis", nullptr, basis));
+    pp_poly p = nullptr;
+    PP_TRY(poly_from_hbar(Hbar, d + 1, k, brk, add_roots != 0, "pp_gmres_setup_basis", &p));
     *out = p;
     if (info) {
         info->d = k;

@@ -315,12 +315,13 @@ hipError_t launch_fill(int n, double value, double *x, hipStream_t st);
 // j-1, pending coefficients, coef = {1/rho, g_j}, g into dd[2j+2..]) and the
 // update pass (v_j into vout, the next pending vector into u). The dot pass
 // uses at most max_rows partial rows and returns their number in *rows.
-hipError_t launch_dots_pair(int n, const double *V, long ldv, int ncols, const double *u, const double *w,
+// prec 0: binary64 vectors; prec 1: binary32 vectors (FP64 arithmetic).
+hipError_t launch_dots_pair(int prec, int n, const void *V, long ldv, int ncols, const void *u, const void *w,
                             double *partial, int ldp, int max_rows, int *rows, hipStream_t st);
 hipError_t launch_dcgs_step(int j, double *dd, double *H, int ldh, double *pend, double *coef, int final_step,
                             hipStream_t st);
-hipError_t launch_update_pair(int n, const double *V, long ldv, int ncols, const double *a, const double *g,
-                              const double *coef, double *u, const double *w, double *vout, hipStream_t st);
+hipError_t launch_update_pair(int prec, int n, const void *V, long ldv, int ncols, const double *a, const double *g,
+                              const double *coef, void *u, const void *w, void *vout, hipStream_t st);
 // s[i] = 1/a_ii (0 and *bad = 1 where the diagonal is missing or zero)
 hipError_t launch_jacobi(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double *s, int *bad,
                          hipStream_t st);

@@ -2942,14 +2942,15 @@ hipError_t launch_dots(int prec, int n, const void *V, long ldv, int ncols, cons
     return hipGetLastError();
 }
 
-hipError_t launch_dots_pair(int n, const double *V, long ldv, int ncols, const double *u, const double *w,
-                            double *partial, int ldp, int max_rows, int *rows, hipStream_t st) {
+template <typename XT>
+hipError_t dots_pair_t(int n, const XT *V, long ldv, int ncols, const XT *u, const XT *w, double *partial, int ldp,
+                       int max_rows, int *rows, hipStream_t st) {
     *rows = 0;
     if (n <= 0) return hipSuccess;
     if (ncols < kDotsWideCols) {
         const unsigned g = blocks_for(n, kDotRows);
         if ((int)g > max_rows) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_dots_pair<double>, dim3(g), dim3(256), 0, st, n, V, ldv, ncols, u, w, partial, ldp);
+        hipLaunchKernelGGL(k_dots_pair<XT>, dim3(g), dim3(256), 0, st, n, V, ldv, ncols, u, w, partial, ldp);
         *rows = (int)g;
         return hipGetLastError();
     }
@@ -2957,10 +2958,21 @@ hipError_t launch_dots_pair(int n, const double *V, long ldv, int ncols, const d
     if (nbx < 1) return hipErrorInvalidValue;
     const int ngroups = (ncols + 7) / 8;
     const unsigned nwg = 8u * (unsigned)ngroups * (unsigned)((nbx + 7) / 8);
-    hipLaunchKernelGGL(k_dots_pair_wide<double>, dim3(nwg), dim3(256), 0, st, n, V, ldv, ncols, u, w, partial, ldp,
+    hipLaunchKernelGGL(k_dots_pair_wide<XT>, dim3(nwg), dim3(256), 0, st, n, V, ldv, ncols, u, w, partial, ldp,
                        nbx, ngroups);
     *rows = nbx;
     return hipGetLastError();
+}
+
+hipError_t launch_dots_pair(int prec, int n, const void *V, long ldv, int ncols, const void *u, const void *w,
+                            double *partial, int ldp, int max_rows, int *rows, hipStream_t st) {
+    if (prec == 0)
+        return dots_pair_t<double>(n, (const double *)V, ldv, ncols, (const double *)u, (const double *)w, partial,
+                                   ldp, max_rows, rows, st);
+    if (prec == 1)
+        return dots_pair_t<float>(n, (const float *)V, ldv, ncols, (const float *)u, (const float *)w, partial, ldp,
+                                  max_rows, rows, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_dcgs_step(int j, double *dd, double *H, int ldh, double *pend, double *coef, int final_step,
@@ -2969,18 +2981,30 @@ hipError_t launch_dcgs_step(int j, double *dd, double *H, int ldh, double *pend,
     return hipGetLastError();
 }
 
-hipError_t launch_update_pair(int n, const double *V, long ldv, int ncols, const double *a, const double *g,
-                              const double *coef, double *u, const double *w, double *vout, hipStream_t st) {
+template <typename XT>
+hipError_t update_pair_t(int n, const XT *V, long ldv, int ncols, const double *a, const double *g,
+                         const double *coef, XT *u, const XT *w, XT *vout, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     // narrow bases: 4 rows x 4 columns per batch, cached loads (the recent
     // columns are still in the MALL); wide: 8 rows x 2 columns, streaming
     if (ncols < kDotsWideCols)
-        hipLaunchKernelGGL((k_update_pair<double, 4, 4, false>), dim3(blocks_for(n, 1024)), dim3(256), 0, st, n, V,
+        hipLaunchKernelGGL((k_update_pair<XT, 4, 4, false>), dim3(blocks_for(n, 1024)), dim3(256), 0, st, n, V,
                            ldv, ncols, a, g, coef, u, w, vout);
     else
-        hipLaunchKernelGGL((k_update_pair<double, 8, 2, true>), dim3(blocks_for(n, 2048)), dim3(256), 0, st, n, V,
+        hipLaunchKernelGGL((k_update_pair<XT, 8, 2, true>), dim3(blocks_for(n, 2048)), dim3(256), 0, st, n, V,
                            ldv, ncols, a, g, coef, u, w, vout);
     return hipGetLastError();
+}
+
+hipError_t launch_update_pair(int prec, int n, const void *V, long ldv, int ncols, const double *a, const double *g,
+                              const double *coef, void *u, const void *w, void *vout, hipStream_t st) {
+    if (prec == 0)
+        return update_pair_t<double>(n, (const double *)V, ldv, ncols, a, g, coef, (double *)u, (const double *)w,
+                                     (double *)vout, st);
+    if (prec == 1)
+        return update_pair_t<float>(n, (const float *)V, ldv, ncols, a, g, coef, (float *)u, (const float *)w,
+                                    (float *)vout, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce(int nblk, const double *partial, int ldp, int ncols, double *h, double *H, int hmode,

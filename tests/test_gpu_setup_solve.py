@@ -51,6 +51,53 @@ def test_setup_matches_oracle(pp, N, alpha, d):
     assert poly.d == P.d and poly.n_added == P.n_added
 
 
+@pytest.mark.parametrize("N,alpha,d", [(50, 1.0, 10), (40, 30.0, 20)])
+def test_fp32_basis_setup(pp, N, alpha, d):
+    # the same GMRES(d) cycle with binary32 Krylov vectors (FP64 dots and
+    # Hessenberg): harmonic Ritz values within the rounding of the stored
+    # vectors of the oracle's FP64 ones, the Leja order and added roots of
+    # the library's own theta bit-exact with the oracle's rules, and a solve
+    # with that polynomial reaching the tolerance
+    csr = convdiff2d(N, alpha)
+    A = csr.to_scipy()
+    v0 = start_vector(csr.n, 2)
+    M = pp.Matrix.from_csr(csr)
+    poly = pp.setup(M, dev(v0), d, basis="fp32")
+    P = oroots.setup(A, v0, d, orth="cgs2")
+    theta = poly.roots("theta")
+    err = _multiset_relerr(theta, P.theta)
+    say("setup fp32 basis", N, alpha, d, f"theta vs oracle {err:.2e}")
+    assert err < 1e-4
+    leja, pof, n_add, units = oroots.order_and_add(theta)
+    assert np.array_equal(poly.roots("leja"), leja)
+    assert np.array_equal(poly.roots("final"), oroots.Poly(d, theta, leja, pof, n_add, units).roots())
+    b = rhs(csr.n, 1)
+    x, info = pp.solve(poly, M, dev(b), tol=1e-8, m=50, inner="fp32")
+    rel = np.linalg.norm(b - A @ host(x)) / np.linalg.norm(b)
+    assert info["status"] == 0 and rel <= 1e-8, (info, rel)
+    with pytest.raises(Exception):
+        pp.setup(M, dev(v0), d, basis="bf16")
+
+
+def test_fp32_basis_setup_full_size(pp):
+    # the 128^3 benchmark workload, d = 40: the FP32-basis polynomial solves
+    # to 1e-8 in about as many iterations as the FP64-basis one
+    csr = convdiff3d(128, 10, 10, 10)
+    A = csr.to_scipy()
+    v0 = dev(start_vector(csr.n, 2))
+    b = rhs(csr.n, 1)
+    M = pp.Matrix.from_csr(csr)
+    its = {}
+    for basis in ("fp64", "fp32"):
+        poly = pp.setup(M, v0, 40, basis=basis)
+        x, info = pp.solve(poly, M, dev(b), tol=1e-8, m=50, inner="fp32")
+        rel = np.linalg.norm(b - A @ host(x)) / np.linalg.norm(b)
+        say("full size setup basis", basis, "iters", info["iters"], "relres", rel, "d_eff", poly.d_eff)
+        assert info["status"] == 0 and rel <= 1e-8, (basis, info, rel)
+        its[basis] = info["iters"]
+    assert its["fp32"] <= its["fp64"] + 3
+
+
 def test_setup_example7_adds_two_roots(pp):
     csr = diag_example7()
     say("setup example 7")
