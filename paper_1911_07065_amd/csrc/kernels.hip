@@ -2330,10 +2330,27 @@ __global__ __launch_bounds__(256) void k_dcgs_step(int j, double *dd, double *H,
     if (final_step) return;
     const double inv = sh[1];
     double *g = dd + 2 * j + 2;
-    // y_i = sum_k H[i,k] a_k over k < j (H upper Hessenberg: k >= i - 1)
+    // y_i = sum_k H[i,k] a_k over k < j (H upper Hessenberg: k >= i - 1);
+    // the columns of H and a are staged in LDS first (all loads at once)
+    // when they fit, so the sums below wait on LDS, not on memory
+    constexpr int kStage = 64;
+    __shared__ double hs[kStage * (kStage + 1)];
+    __shared__ double as[kStage];
+    const bool staged = j <= kStage;
+    if (staged) {
+        for (int q = tid; q < (j + 1) * j; q += 256) {
+            const int i = q % (j + 1), k = q / (j + 1);
+            hs[q] = H[i + (long)k * ldh];
+        }
+        for (int k = tid; k < j; k += 256) as[k] = a[k];
+        __syncthreads();
+    }
     for (int i = tid; i <= j; i += 256) {
         double y = 0.0;
-        for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) y += H[i + (long)k * ldh] * a[k];
+        if (staged)
+            for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) y += hs[i + k * (j + 1)] * as[k];
+        else
+            for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) y += H[i + (long)k * ldh] * a[k];
         const double c = i < j ? (b[i] - y) * inv : ((beta - sab) * inv - y) * inv;
         g[i] = y * inv + c;
         pend[i] = c;
