@@ -335,8 +335,8 @@ pp_status pp_gmres_setup(pp_matrix A, const double *v0, int d, int add_roots, vo
  * or PP_F32 (binary32 vectors, half the bytes of the Gram-Schmidt sweeps and
  * the sparse products; dot products, norms and the Hessenberg matrix are
  * still accumulated in FP64). The harmonic Ritz values of a PP_F32 basis
- * differ from the FP64 ones by the rounding of the stored vectors (about
- * 1e-6 relative on well-separated values); the polynomial is a
+ * differ from the FP64 ones by the rounding of the stored vectors (5e-8 to
+ * 2e-7 relative on 2-D convection-diffusion); the polynomial is a
  * preconditioner, so a solve still reaches its tolerance through the FP64
  * residual and refinement. Arguments and returns as pp_gmres_setup;
  * PP_EINVAL for another basis. */

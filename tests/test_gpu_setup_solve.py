@@ -67,7 +67,7 @@ def test_fp32_basis_setup(pp, N, alpha, d):
     theta = poly.roots("theta")
     err = _multiset_relerr(theta, P.theta)
     say("setup fp32 basis", N, alpha, d, f"theta vs oracle {err:.2e}")
-    assert err < 1e-4
+    assert err < 1e-5  # measured 4.5e-8 and 2.3e-7 on these two cases
     leja, pof, n_add, units = oroots.order_and_add(theta)
     assert np.array_equal(poly.roots("leja"), leja)
     assert np.array_equal(poly.roots("final"), oroots.Poly(d, theta, leja, pof, n_add, units).roots())
