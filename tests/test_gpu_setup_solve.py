@@ -355,7 +355,7 @@ def _varah_inv_bound(A):
     return 1.0 / float(np.min(d - off))
 
 
-def _randsparse_vs_oracle(pp, n, inners, xo_cache):
+def _randsparse_vs_oracle(pp, n, inners, xo_cache, basis="fp64"):
     # random sparse, 16 random columns + diagonal, dominance 1.05, degree 100
     # with added roots, GMRES(30), tol 1e-8: x of each inner precision against
     # the FP64 oracle's x (its own polynomial from the same start vector).
@@ -374,9 +374,9 @@ def _randsparse_vs_oracle(pp, n, inners, xo_cache):
     xo = xo_cache[n]
     inv_inf = _varah_inv_bound(A)
     M = pp.Matrix.from_csr(csr)
-    poly = pp.setup(M, dev(v0), 100)
+    poly = pp.setup(M, dev(v0), 100, basis=basis)
     for inner in inners:
-        say("random sparse solve", n, inner)
+        say("random sparse solve", n, inner, "setup basis", basis)
         x, info = pp.solve(poly, M, dev(b), tol=1e-8, m=30, inner=inner)
         xh = host(x)
         r = b - A @ xh
@@ -398,6 +398,12 @@ def randsparse_oracle_x():
 def test_cfg3_shaped_solve_matches_oracle(pp, randsparse_oracle_x):
     # the random sparse workload's shape at n = 1e5
     _randsparse_vs_oracle(pp, 100_000, ("fp64", "fp32", "bf16"), randsparse_oracle_x)
+
+
+def test_cfg3_shaped_fp32_basis_solve(pp, randsparse_oracle_x):
+    # the same with the polynomial from an FP32-basis setup (degree 100): the
+    # FP32 and BF16 forms still land within the bound of the oracle's x
+    _randsparse_vs_oracle(pp, 100_000, ("fp32", "bf16"), randsparse_oracle_x, basis="fp32")
 
 
 def test_cfg3_full_size_solve(pp, randsparse_oracle_x):
