@@ -1345,13 +1345,29 @@ pp_status build_csort(pp_matrix A, const std::vector<int32_t> &rp, const std::ve
         }
     };
     {
+        // a host allocation failure inside a worker is reported, not thrown
+        // across the thread boundary
         const int nth = std::max(1, std::min<int>(std::min(nblk, 8), (int)std::thread::hardware_concurrency()));
+        std::vector<char> failed(nth, 0);
         std::vector<std::thread> pool;
-        for (int h = 0; h < nth; ++h)
-            pool.emplace_back([&, h]() {
-                for (int b = h; b < nblk; b += nth) lay_block(b);
-            });
+        try {
+            for (int h = 0; h < nth; ++h)
+                pool.emplace_back([&, h]() {
+                    try {
+                        for (int b = h; b < nblk; b += nth) lay_block(b);
+                    } catch (...) {
+                        failed[h] = 1;
+                    }
+                });
+        } catch (...) {
+            failed[0] = 1;  // a thread could not be started
+        }
         for (auto &th : pool) th.join();
+        for (char f : failed)
+            if (f) {
+                set_error("pp_matrix_create: out of host memory building the column-sorted copy");
+                return PP_ENOMEM;
+            }
     }
     PP_TRY(dev_alloc(&A->cs_code, (size_t)std::max<int64_t>(ne, 1)));
     PP_TRY(dev_alloc(&A->cs_perm, (size_t)std::max<int64_t>(ne, 1)));

@@ -77,6 +77,13 @@ def test_fp32_basis_setup(pp, N, alpha, d):
     assert info["status"] == 0 and rel <= 1e-8, (info, rel)
     with pytest.raises(Exception):
         pp.setup(M, dev(v0), d, basis="bf16")
+    # the C ABI refuses any other basis precision itself
+    import ctypes
+
+    from paper_1911_07065_amd._lib import lib, SetupInfo
+    h, si, vd = ctypes.c_void_p(), SetupInfo(), dev(v0)
+    st = lib.pp_gmres_setup_basis(M.handle, vd.data_ptr(), d, 1, 2, None, ctypes.byref(h), ctypes.byref(si))
+    assert st == -1 and not h.value  # PP_EINVAL, no polynomial
 
 
 def test_fp32_basis_setup_full_size(pp):
