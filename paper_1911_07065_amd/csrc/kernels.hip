@@ -2964,7 +2964,8 @@ hipError_t dots_pair_t(int n, const XT *V, long ldv, int ncols, const XT *u, con
                        int max_rows, int *rows, hipStream_t st) {
     *rows = 0;
     if (n <= 0) return hipSuccess;
-    if (ncols < kDotsWideCols) {
+    // binary32 bases switch to the wide layout earlier (half the bytes per column)
+    if (ncols < (sizeof(XT) == 4 ? kDotsWideCols / 2 : kDotsWideCols)) {
         const unsigned g = blocks_for(n, kDotRows);
         if ((int)g > max_rows) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_dots_pair<XT>, dim3(g), dim3(256), 0, st, n, V, ldv, ncols, u, w, partial, ldp);
