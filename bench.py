@@ -21,6 +21,7 @@ and the paper's own synthetic rows run beside its printed figures.
 """
 
 import argparse
+import functools
 import json
 import os
 import sys
@@ -477,7 +478,7 @@ def paper_context_leg(pp, torch, np):
             "ours": "one MI355X, FP64, CGS2 (dots count both passes)", "rows": rows}
 
 
-def batched_leg(pp, torch, np, loop_every=16):
+def batched_leg(pp, torch, np, loop_every=16, orth="delayed"):
     """Batched solve: 256 2-D convection-diffusion systems (sides U{64..512},
     coefficient U[0,50)), 4 right-hand sides each, degree 20, GMRES(50),
     FP32 inner / FP64 outer, tol 1e-8 (setup + solve), against a loop of
@@ -488,6 +489,7 @@ def batched_leg(pp, torch, np, loop_every=16):
     specs = batched_convdiff_specs()
     csrs = [convdiff2d(N, a) for (N, a, _, _) in specs]
     B = pp.Batch(csrs)
+    B.set_orth(orth)
     v0 = torch.as_tensor(np.concatenate([start_vector(N * N, s2) for (N, _, _, s2) in specs]), device="cuda")
     brs = [rhs(N * N, s1, count=4) for (N, _, s1, _) in specs]
     bd = B.interleave(np.concatenate(brs, axis=1))
@@ -537,6 +539,7 @@ def batched_leg(pp, torch, np, loop_every=16):
                             for prec, t in tuned.items()},
             "tune_s": round(t_tune, 6),
             "cycle": "device Givens per pair; HIP graphs of 5 Arnoldi steps, one host check between them",
+            "orth": orth,
             "speedup_vs_loop": round(t_loop / t_batch, 3), "speedup_vs_fp64_loop": round(t_loop64 / t_batch, 3)}
 
 
@@ -613,6 +616,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3, help="oracle runs on the host (median; capped at ~100 s)")
     ap.add_argument("--setup-basis", default="fp32", choices=["fp32", "fp64"],
                     help="Krylov vector storage of the FP32 form's polynomial setup (the FP64 form's is fp64)")
+    ap.add_argument("--batch-orth", default="delayed", choices=["delayed", "cgs2"],
+                    help="orthogonalisation of the batched cycles (delayed: two basis sweeps per step)")
     ap.add_argument("--chain-variant", default=None,
                     help="pin the chain kernel instead of autotuning, remap on: a variant name for both precisions "
                          "(e.g. diac) or fp32=<v>,fp64=<w>; <v>/tile2 adds two steps per launch on whole grid "
@@ -644,7 +649,10 @@ def main():
         legs = {"random_sparse": random_sparse_leg, "chain_step_256": scale_leg, "adjoint": adjoint_leg,
                 "batched": batched_leg, "preconditioned": preconditioned_leg, "paper_context": paper_context_leg,
                 "out_of_mall": out_of_mall_leg}
-        print(json.dumps({args.leg: legs[args.leg](pp, torch, np)}))
+        fn = legs[args.leg]
+        if args.leg == "batched":
+            fn = functools.partial(batched_leg, orth=args.batch_orth)
+        print(json.dumps({args.leg: fn(pp, torch, np)}))
         return
     N, d, m, tol = args.grid, args.degree, args.m, 1e-8
     log("generating workload", N)
@@ -787,7 +795,7 @@ def main():
         extras["random_sparse"] = random_sparse_leg(pp, torch, np)
         extras["chain_step_256"] = scale_leg(pp, torch, np)
         extras["adjoint"] = adjoint_leg(pp, torch, np)
-        extras["batched"] = batched_leg(pp, torch, np)
+        extras["batched"] = batched_leg(pp, torch, np, orth=args.batch_orth)
         extras["preconditioned"] = preconditioned_leg(pp, torch, np)
         extras["paper_context"] = paper_context_leg(pp, torch, np)
 

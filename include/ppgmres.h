@@ -547,6 +547,18 @@ pp_status pp_batch_format(pp_batch B, int *format);
  *     tuning (format 0, 1 or 2, spw 2 only with format 1 or 2, remap 0 or 1);
  *     PP_EINVAL for a format the batch has no copy of. */
 pp_status pp_batch_tune(pp_batch B, int prec, int nrhs, void *stream);
+
+/* Orthogonalisation of pp_batch_solve's cycles (Algorithm 4 step 2).
+ * delayed = 1 (default): classical Gram-Schmidt with the second pass and the
+ * normalisation delayed by one step, as in the polynomial setup: two sweeps
+ * of every pair's basis per Arnoldi step; a column of the Hessenberg matrix
+ * is complete one step later, so each pair's least-squares update and
+ * stopping test run one step behind the phi(A) products (a pair that
+ * converges at column k has applied phi(A) k + 1 times in that cycle).
+ * delayed = 0: CGS2, three sweeps per step, no lag. Both give the same
+ * Krylov spaces up to rounding. Cycles longer than 128 steps take CGS2. */
+pp_status pp_batch_set_orth(pp_batch B, int delayed);
+pp_status pp_batch_orth(pp_batch B, int *delayed);
 pp_status pp_batch_set_chain_config(pp_batch B, int prec, int nrhs, int format, int spw, int remap);
 pp_status pp_batch_chain_config(pp_batch B, int prec, int nrhs, int *format, int *spw, int *remap, double *us);
 

@@ -70,6 +70,8 @@ SIGNATURES = {
                                ctypes.POINTER(SetupInfo)]),
     "pp_gmres_setup_basis": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p),
                                      ctypes.POINTER(SetupInfo)]),
+    "pp_batch_set_orth": (c_int, [c_void_p, c_int]),
+    "pp_batch_orth": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
     "pp_gmres_setup_double": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p),
                                       ctypes.POINTER(SetupInfo)]),
     "pp_gmres_setup_checked": (c_int, [c_void_p, c_void_p, c_int, c_int, ctypes.POINTER(StchOpts), c_void_p,

@@ -652,6 +652,18 @@ class Batch:
             out.append(d)
         return x, out
 
+    def set_orth(self, mode: str):
+        """Orthogonalisation of the batched cycles: "delayed" (two basis
+        sweeps per step, the least squares one step behind) or "cgs2"."""
+        if mode not in ("delayed", "cgs2"):
+            raise ValueError("orth must be 'delayed' or 'cgs2'")
+        check(lib.pp_batch_set_orth(self.handle, 1 if mode == "delayed" else 0), "pp_batch_set_orth")
+
+    def orth(self) -> str:
+        f = ctypes.c_int()
+        check(lib.pp_batch_orth(self.handle, ctypes.byref(f)), "pp_batch_orth")
+        return "delayed" if f.value else "cgs2"
+
     BATCH_FORMATS = ("sell", "pattern", "box")
 
     def format(self) -> str:

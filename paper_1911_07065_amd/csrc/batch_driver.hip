@@ -95,7 +95,21 @@ struct pp_batch_s {
     int *grun = nullptr, *gsteps = nullptr, *grunpin = nullptr, *gstepspin = nullptr;
     int *gany = nullptr, *ganypin = nullptr;  // some pair still runs (device, pinned mirror)
     int gm = -1, gpairs = 0;
+    // delayed Gram-Schmidt of the cycle (orth == 1): dot-pass partials and
+    // their per-system sums (ldd = 2 (m + 1) R per row), every pair's
+    // Hessenberg matrix (column c at dH + p*ldhp + c*(m+1)), pending and
+    // next coefficients (m + 1 per pair) and {1/rho, g_j} per pair
+    int orth = 1;
+    int ldd = 0;
+    double *dpart = nullptr, *ddot = nullptr, *dH = nullptr, *dpend = nullptr, *dg = nullptr, *dcoef = nullptr;
     void free_givens() {
+        dev_free(dpart);
+        dev_free(ddot);
+        dev_free(dH);
+        dev_free(dpend);
+        dev_free(dg);
+        dev_free(dcoef);
+        ldd = 0;
         dev_free(gR);
         dev_free(gc);
         dev_free(gs);
@@ -131,6 +145,13 @@ struct pp_batch_s {
         PP_TRY(dev_alloc(&grun, (size_t)pairs));
         PP_TRY(dev_alloc(&gsteps, (size_t)pairs));
         PP_TRY(dev_alloc(&gany, 1));
+        ldd = 2 * (m + 1) * R;
+        PP_TRY(dev_alloc(&dpart, (size_t)nblocks * ldd));
+        PP_TRY(dev_alloc(&ddot, (size_t)nsys * ldd));
+        PP_TRY(dev_alloc(&dH, (size_t)pairs * m * (m + 1)));
+        PP_TRY(dev_alloc(&dpend, (size_t)pairs * (m + 1)));
+        PP_TRY(dev_alloc(&dg, (size_t)pairs * (m + 1)));
+        PP_TRY(dev_alloc(&dcoef, (size_t)pairs * 2));
         if (hipHostMalloc((void **)&ginpin, sizeof(double) * 3 * pairs, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&ganypin, sizeof(int), hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&gscpin, sizeof(double) * pairs, hipHostMallocDefault) != hipSuccess ||
@@ -460,6 +481,27 @@ pp_status bcgs2(pp_batch B, int prec, int R, const BWork &w, int j, double *Hbas
     HIP_TRY(launch_bupdate(bl, prec, R, w.V, w.ldv, ncols, B->h2, B->ldp, wv, B->npart, nullptr, st));
     HIP_TRY(launch_bnorm(bl, R, B->npart, Hbase + ncols, pstride, B->inv, st));
     HIP_TRY(launch_bscale(bl, prec, prec, R, wv, B->inv, wv, st));
+    return PP_OK;
+}
+
+// Step j of the delayed Gram-Schmidt for every pair (masked): the dot pass
+// of the pending vector u (w.P(3)) and w = phi(A) u (column j+1) against
+// columns 0..j-1, the per-system sums, the coefficient step (Hessenberg
+// column j-1 complete) and, unless final, the update pass (column j = v_j,
+// u = the next pending vector). final: the cycle's last call (j = m), which
+// only completes column m-1.
+pp_status bdcgs(pp_batch B, int prec, int R, const BWork &w, int j, bool final, hipStream_t st) {
+    const BatchBlocks bl = B->blocks(true);
+    const int m = B->gm, ldc = m + 1;
+    void *u = w.P(3);
+    const void *wv = final ? u : bcol(w, prec, j + 1);
+    HIP_TRY(launch_bdots2(bl, prec, R, w.V, w.ldv, j, u, wv, B->dpart, B->ldd, st));
+    HIP_TRY(launch_bred(bl, R, B->dpart, B->ldd, 2 * (j + 1) * R, B->ddot, B->ldd, nullptr, 0, 0, st));
+    HIP_TRY(launch_bdcgs_step(bl, R, j, B->ddot, B->ldd, B->dH, (long)m * ldc, ldc, B->dpend, B->dg, B->dcoef,
+                              final ? 1 : 0, st));
+    if (!final)
+        HIP_TRY(launch_bupdate2(bl, prec, R, w.V, w.ldv, j, B->ddot, B->ldd, B->dg, ldc, B->dcoef, u,
+                                bcol(w, prec, j + 1), bcol(w, prec, j), st));
     return PP_OK;
 }
 
@@ -812,6 +854,24 @@ pp_status pp_batch_set_format(pp_batch B, int format) {
     return PP_OK;
 }
 
+pp_status pp_batch_set_orth(pp_batch B, int delayed) {
+    if (!B || (delayed != 0 && delayed != 1)) {
+        set_error("pp_batch_set_orth: bad argument");
+        return PP_EINVAL;
+    }
+    B->orth = delayed;
+    return PP_OK;
+}
+
+pp_status pp_batch_orth(pp_batch B, int *delayed) {
+    if (!B || !delayed) {
+        set_error("pp_batch_orth: bad argument");
+        return PP_EINVAL;
+    }
+    *delayed = B->orth;
+    return PP_OK;
+}
+
 pp_status pp_batch_tune(pp_batch B, int prec, int nrhs, void *stream) {
     if (!B || prec < 0 || prec > 2 || !(nrhs == 1 || nrhs == 2 || nrhs == 4)) {
         set_error("pp_batch_tune: bad argument");
@@ -1050,6 +1110,8 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
     // per-pair results out. With opts->graphs each segment and the tail are
     // captured once per precision into HIP graphs and replayed.
     const int seg = opts->graph_steps > 0 ? std::min(opts->graph_steps, m) : m;
+    // two basis sweeps per step (delayed Gram-Schmidt) or three (CGS2)
+    const bool delayed = B->orth == 1 && m <= bdcgs_max_cols();
     const int nseg = (m + seg - 1) / seg;
     auto segment_work = [&](int pr, int c) -> pp_status {
         const BWork &w = B->ws[pr];
@@ -1057,9 +1119,19 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
             HIP_TRY(hipMemcpyAsync(B->gin, B->ginpin, sizeof(double) * 3 * P, hipMemcpyHostToDevice, st));
             HIP_TRY(hipMemcpyAsync(B->grun, B->grunpin, sizeof(int) * P, hipMemcpyHostToDevice, st));
             HIP_TRY(launch_bgivens_init(G, gbeta, st));
-            HIP_TRY(launch_bscale(bl, 0, pr, R, B->r64, ginv, bcol(w, pr, 0), st));
+            // the first basis vector r / beta: column 0, or the first pending vector
+            HIP_TRY(launch_bscale(bl, 0, pr, R, B->r64, ginv, delayed ? w.P(3) : bcol(w, pr, 0), st));
         }
         for (int j = c * seg; j < std::min(m, (c + 1) * seg); ++j) {
+            if (delayed) {
+                // phi(A) of the pending vector; its column completes one step later
+                PP_TRY(run_bprog(B, pr, R, dphi, Kphi, w.P(3), bcol(w, pr, j + 1), w, st, true));
+                PP_TRY(bdcgs(B, pr, R, w, j, false, st));
+                if (j >= 1)
+                    HIP_TRY(launch_bgivens_step(G, j - 1, B->dH + (size_t)(j - 1) * (m + 1), m * (m + 1),
+                                                kBreakdownTolB, st));
+                continue;
+            }
             PP_TRY(run_bprog(B, pr, R, dphi, Kphi, bcol(w, pr, j), bcol(w, pr, j + 1), w, st, true));
             PP_TRY(bcgs2(B, pr, R, w, j, B->Hc, B->ldh, st, true));
             HIP_TRY(launch_bgivens_step(G, j, B->Hc, B->ldh, kBreakdownTolB, st));
@@ -1070,6 +1142,12 @@ pp_status pp_batch_solve(pp_batch B, const pp_poly *polys, int nrhs, const doubl
     };
     auto tail_work = [&](int pr) -> pp_status {
         const BWork &w = B->ws[pr];
+        if (delayed) {
+            // the last column of the cycle: masked, so a no-op once no pair runs
+            PP_TRY(bdcgs(B, pr, R, w, m, true, st));
+            HIP_TRY(launch_bgivens_step(G, m - 1, B->dH + (size_t)(m - 1) * (m + 1), m * (m + 1), kBreakdownTolB,
+                                        st));
+        }
         HIP_TRY(launch_bgivens_solve(G, B->z, B->ldh, st));
         HIP_TRY(launch_bcombine(bl, pr, R, w.V, w.ldv, B->kdev, B->z, B->ldh, w.P(3), st));
         PP_TRY(run_bprog(B, pr, R, dp, Kp, w.P(3), w.P(4), w, st));

@@ -113,6 +113,25 @@ struct BGivens {
     int *run, *k, *steps, *act;
     int m, R, nsys;
 };
+// The delayed Gram-Schmidt of a cycle (two basis sweeps per step; pair p's
+// pending vector u, w = phi(A) u):
+//  launch_bdots2: partial[b*ldp + c*R + r] = V_c^T u, [(ncols + c)*R + r] =
+//    V_c^T w (c < ncols), [2 ncols R + r] = u^T u, [(2 ncols + 1) R + r] =
+//    u^T w over block b (reduce per system with launch_bred, nt = 2 (ncols+1) R);
+//  launch_bdcgs_step: per pair, completes Hessenberg column j-1 (Hf + p*ldhp
+//    + (j-1)*ldc, rows 0..j) from pend and rho = sqrt(u^T u - |V^T u|^2), and
+//    unless final_step forms the next pending coefficients pend, g (per pair,
+//    stride ldc) and coef[2p] = 1/rho, coef[2p+1] = g_j;
+//  launch_bupdate2: v_j = (u - V a) / rho into vout and u = w / rho - V g -
+//    v_j g_j, one read of V (ncols <= bdcgs_max_cols()).
+hipError_t launch_bdots2(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols, const void *u,
+                         const void *w, double *partial, int ldp, hipStream_t st);
+hipError_t launch_bdcgs_step(const BatchBlocks &B, int R, int j, const double *dd, int ldd, double *Hf, long ldhp,
+                             int ldc, double *pend, double *g, double *coef, int final_step, hipStream_t st);
+hipError_t launch_bupdate2(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols, const double *dd,
+                           int ldd, const double *g, int ldc, const double *coef, void *u, const void *w, void *vout,
+                           hipStream_t st);
+int bdcgs_max_cols();
 // Start of a cycle: g = beta e1, fro2 = 0, k = steps = 0, act from run.
 hipError_t launch_bgivens_init(const BGivens &G, const double *beta, hipStream_t st);
 // Arnoldi step j: for every running pair, its Hessenberg column

@@ -430,6 +430,233 @@ __global__ __launch_bounds__(256) void k_bdots(const int4 *block, const int *act
     }
 }
 
+// ---- delayed Gram-Schmidt of the cycle (two basis sweeps per step) -------
+//
+// Step j of pair p works on its pending vector u (the new column once
+// orthogonalised, not yet normalised) and w = phi(A) u:
+//  dot pass:   V_c^T u and V_c^T w (c < j), u^T u and u^T w per pair;
+//  coefficient step (per pair): rho = sqrt(u^T u - ||V^T u||^2) completes
+//    column j-1 of the Hessenberg matrix, and the first-pass coefficients
+//    of the next column follow from A V = V H (the setup's scheme, per pair);
+//  update pass: v_j = (u - V a) / rho (column j), and the next pending vector
+//    u' = w / rho - V g - v_j g_j, both from one read of V.
+
+// One chunk of KC columns of k_bdots2: the chunk's loads go out together,
+// then per column and rhs the sums against u and w; wave sums land in
+// sm[wave][2 ((c - g0) R + r) + {0, 1}].
+template <typename XT, int R, int KC>
+__device__ __forceinline__ void bdots2_chunk(const XT *__restrict__ V, long ldv, int c0, int g0, const long *ii,
+                                             const double (*uv)[R], const double (*wv)[R], double (*sm)[64]) {
+    constexpr int RPT = kBatchBlockRows / 256;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    typename Arith<XT>::T x[RPT][KC][R];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s)
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) ldr<XT, R>(V + (long)(c0 + kc) * ldv, ii[s], x[s][kc]);
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double au = 0.0, aw = 0.0;
+#pragma unroll
+            for (int s = 0; s < RPT; ++s) {
+                au += (double)x[s][kc][r] * uv[s][r];
+                aw += (double)x[s][kc][r] * wv[s][r];
+            }
+            au = wave_sum(au);
+            aw = wave_sum(aw);
+            if (lane == 0) {
+                sm[wave][2 * ((c0 - g0 + kc) * R + r)] = au;
+                sm[wave][2 * ((c0 - g0 + kc) * R + r) + 1] = aw;
+            }
+        }
+}
+
+// The dot pass of the delayed scheme for one system-aligned block:
+// partial[b*ldp + c*R + r] = sum V_c u, partial[b*ldp + (ncols + c)*R + r] =
+// sum V_c w (c < ncols), partial[b*ldp + 2 ncols R + r] = sum u u and
+// [(2 ncols + 1) R + r] = sum u w. Columns in groups of 32/R (the waves meet
+// once per group); rows past the block read its last row with weight zero.
+template <typename XT, int R>
+__global__ __launch_bounds__(256) void k_bdots2(const int4 *block, const int *active, const XT *V, long ldv, int ncols,
+                                                const XT *u, const XT *w, double *partial, int ldp) {
+    constexpr int RPT = kBatchBlockRows / 256;
+    constexpr int KC = 8 / R > 4 ? 4 : 8 / R;
+    constexpr int GW = 32 / R;  // a multiple of KC
+    __shared__ double sm[4][64];
+    const int4 bi = block[blockIdx.x];
+    if (active && !active[bi.z]) return;
+    const long r1 = (long)bi.x + bi.y;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    long ii[RPT];
+    double uv[RPT][R], wv[RPT][R], suu[R], suw[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) suu[r] = suw[r] = 0.0;
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+        const long i = (long)bi.x + s * 256 + tid;
+        ii[s] = i < r1 ? i : r1 - 1;
+        typename Arith<XT>::T tu[R], tw[R];
+        ldr<XT, R>(u, ii[s], tu);
+        ldr<XT, R>(w, ii[s], tw);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            uv[s][r] = i < r1 ? (double)tu[r] : 0.0;
+            wv[s][r] = i < r1 ? (double)tw[r] : 0.0;
+            suu[r] += uv[s][r] * uv[s][r];
+            suw[r] += uv[s][r] * wv[s][r];
+        }
+    }
+    double *prow = partial + (long)blockIdx.x * ldp;
+    for (int g0 = 0; g0 < ncols; g0 += GW) {
+        const int g1 = min(ncols, g0 + GW);
+        int c0 = g0;
+        for (; c0 + KC <= g1; c0 += KC) bdots2_chunk<XT, R, KC>(V, ldv, c0, g0, ii, uv, wv, sm);
+        for (; c0 < g1; ++c0) bdots2_chunk<XT, R, 1>(V, ldv, c0, g0, ii, uv, wv, sm);
+        __syncthreads();
+        const int nv = (g1 - g0) * R;
+        if (tid < 2 * nv) {
+            const double t = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
+            const int q = tid >> 1, c = g0 + q / R, r = q % R;
+            prow[((tid & 1) ? ncols + c : c) * R + r] = t;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double a = wave_sum(suu[r]), b = wave_sum(suw[r]);
+        if (lane == 0) {
+            sm[wave][2 * r] = a;
+            sm[wave][2 * r + 1] = b;
+        }
+    }
+    __syncthreads();
+    if (tid < 2 * R) {
+        const double t = ((sm[0][tid] + sm[1][tid]) + sm[2][tid]) + sm[3][tid];
+        prow[(2 * ncols + (tid & 1)) * R + (tid >> 1)] = t;
+    }
+}
+
+// The coefficient step of the delayed scheme, one wave per pair p = s R + r
+// (systems with no running pair skipped). dd: the dot pass reduced per system
+// (layout of k_bdots2, row s at dd + s*ldd). Completes column j-1 of the
+// pair's Hessenberg matrix Hf (column c at Hf + p*ldhp + c*ldc, rows 0..c+1)
+// from the pending coefficients pend and rho; then, unless final_step, the
+// next pending coefficients: with y_i = sum_k H[i,k] a_k (k < j),
+// c_i = (b_i - y_i) / rho (i < j), c_j = ((beta - a.b) / rho - y_j) / rho,
+// g_i = y_i / rho + c_i; pend = c, g = g, coef[2p] = 1/rho, coef[2p+1] = g_j.
+__global__ __launch_bounds__(64) void k_bdcgs_step(int j, int R, const double *dd, int ldd, double *Hf, long ldhp,
+                                                   int ldc, double *pend, double *g, double *coef, int final_step,
+                                                   const int *active) {
+    const int p = blockIdx.x, s = p / R, r = p % R;
+    if (active && !active[s]) return;
+    const int lane = threadIdx.x;
+    const double *ds = dd + (long)s * ldd;
+    const double alpha = ds[2 * j * R + r], beta = ds[(2 * j + 1) * R + r];
+    double saa = 0.0, sab = 0.0;
+    for (int k = lane; k < j; k += 64) {
+        const double a = ds[k * R + r], b = ds[(j + k) * R + r];
+        saa += a * a;
+        sab += a * b;
+    }
+    saa = wave_sum(saa);
+    sab = wave_sum(sab);
+    const double rho = sqrt(fmax(alpha - saa, 0.0));
+    const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
+    double *H = Hf + (long)p * ldhp;
+    double *pp = pend + (long)p * ldc, *gg = g + (long)p * ldc;
+    if (j >= 1) {
+        for (int k = lane; k < j; k += 64) H[(long)(j - 1) * ldc + k] = pp[k] + ds[k * R + r];
+        if (lane == 0) H[(long)(j - 1) * ldc + j] = rho;
+    }
+    __syncthreads();
+    if (final_step) {
+        if (lane == 0) {
+            coef[2 * p] = inv;
+            coef[2 * p + 1] = 0.0;
+        }
+        return;
+    }
+    for (int i = lane; i <= j; i += 64) {
+        double y = 0.0;
+        for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) y += H[(long)k * ldc + i] * ds[k * R + r];
+        const double c = i < j ? (ds[(j + i) * R + r] - y) * inv : ((beta - sab) * inv - y) * inv;
+        gg[i] = y * inv + c;
+        pp[i] = c;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        coef[2 * p] = inv;
+        coef[2 * p + 1] = gg[j];
+    }
+}
+
+// The update pass of the delayed scheme for one system-aligned block: per
+// element (row i, rhs r of pair p), s1 = sum_k V_k a_k and s2 = sum_k V_k g_k
+// (k < ncols; a from dd, g per pair), then v = (u - s1) / rho into vout and
+// u = w / rho - s2 - v g_j (in place). Coefficients staged in LDS; at most
+// kBDcgsMaxCols columns.
+constexpr int kBDcgsMaxCols = 128;
+template <typename XT, int R>
+__global__ __launch_bounds__(256) void k_bupdate2(const int4 *block, const int *active, const XT *V, long ldv, int ncols,
+                                                  const double *dd, int ldd, const double *g, int ldc,
+                                                  const double *coef, XT *u, const XT *w, XT *vout) {
+    constexpr int KC = 8 / R > 4 ? 4 : 8 / R;
+    __shared__ double as[kBDcgsMaxCols * R], gs[kBDcgsMaxCols * R], cs[2 * R];
+    const int4 bi = block[blockIdx.x];
+    if (active && !active[bi.z]) return;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < ncols * R; t += 256) {
+        as[t] = dd[(long)bi.z * ldd + t];  // a_k of rhs r at k R + r
+        const int k = t / R, r = t % R;
+        gs[t] = g[((long)bi.z * R + r) * ldc + k];
+    }
+    if (tid < 2 * R) cs[tid] = coef[(long)bi.z * R * 2 + tid];
+    __syncthreads();
+    const long r0 = bi.x, r1 = (long)bi.x + bi.y;
+    for (long i = r0 + tid; i < r1; i += 256) {
+        double s1[R], s2[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) s1[r] = s2[r] = 0.0;
+        int c0 = 0;
+        for (; c0 + KC <= ncols; c0 += KC) {
+            typename Arith<XT>::T x[KC][R];
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) ldr<XT, R>(V + (long)(c0 + kc) * ldv, i, x[kc]);
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    s1[r] += (double)x[kc][r] * as[(c0 + kc) * R + r];
+                    s2[r] += (double)x[kc][r] * gs[(c0 + kc) * R + r];
+                }
+        }
+        for (; c0 < ncols; ++c0) {
+            typename Arith<XT>::T x[R];
+            ldr<XT, R>(V + (long)c0 * ldv, i, x);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                s1[r] += (double)x[r] * as[c0 * R + r];
+                s2[r] += (double)x[r] * gs[c0 * R + r];
+            }
+        }
+        typename Arith<XT>::T uo[R], wo[R], vo[R], un[R];
+        ldr<XT, R>(u, i, uo);
+        ldr<XT, R>(w, i, wo);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double inv = cs[2 * r], gj = cs[2 * r + 1];
+            const double v = ((double)uo[r] - s1[r]) * inv;
+            vo[r] = (typename Arith<XT>::T)v;
+            const double vs = stored_value(vout, v);
+            un[r] = (typename Arith<XT>::T)((double)wo[r] * inv - s2[r] - vs * gj);
+        }
+        str<XT, R>(vout, i, vo);
+        str<XT, R>(u, i, un);
+    }
+}
+
 // sum over c < ncols of V_c[i*R+r] h[c*R+r] for one row and every r, with
 // columns taken KC at a time (all loads of a chunk issued together); KC = 1
 // covers the remainder.
@@ -955,6 +1182,97 @@ hipError_t launch_bupdate_dots(const BatchBlocks &B, int prec, int R, const void
     }
     return hipErrorInvalidValue;
 }
+
+template <typename XT>
+hipError_t bdots2_t(const BatchBlocks &B, int R, const XT *V, long ldv, int ncols, const XT *u, const XT *w,
+                    double *partial, int ldp, hipStream_t st) {
+    if (B.nblocks == 0) return hipSuccess;
+    switch (R) {
+        case 1:
+            hipLaunchKernelGGL((k_bdots2<XT, 1>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, u,
+                               w, partial, ldp);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_bdots2<XT, 2>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, u,
+                               w, partial, ldp);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_bdots2<XT, 4>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols, u,
+                               w, partial, ldp);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename XT>
+hipError_t bupdate2_t(const BatchBlocks &B, int R, const XT *V, long ldv, int ncols, const double *dd, int ldd,
+                      const double *g, int ldc, const double *coef, XT *u, const XT *w, XT *vout, hipStream_t st) {
+    if (B.nblocks == 0) return hipSuccess;
+    switch (R) {
+        case 1:
+            hipLaunchKernelGGL((k_bupdate2<XT, 1>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols,
+                               dd, ldd, g, ldc, coef, u, w, vout);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_bupdate2<XT, 2>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols,
+                               dd, ldd, g, ldc, coef, u, w, vout);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_bupdate2<XT, 4>), dim3(B.nblocks), dim3(256), 0, st, B.block, B.active, V, ldv, ncols,
+                               dd, ldd, g, ldc, coef, u, w, vout);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bdots2(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols, const void *u,
+                         const void *w, double *partial, int ldp, hipStream_t st) {
+    switch (prec) {
+        case 0:
+            return bdots2_t<double>(B, R, (const double *)V, ldv, ncols, (const double *)u, (const double *)w, partial,
+                                    ldp, st);
+        case 1:
+            return bdots2_t<float>(B, R, (const float *)V, ldv, ncols, (const float *)u, (const float *)w, partial, ldp,
+                                   st);
+        case 2:
+            return bdots2_t<uint16_t>(B, R, (const uint16_t *)V, ldv, ncols, (const uint16_t *)u,
+                                      (const uint16_t *)w, partial, ldp, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bdcgs_step(const BatchBlocks &B, int R, int j, const double *dd, int ldd, double *Hf, long ldhp,
+                             int ldc, double *pend, double *g, double *coef, int final_step, hipStream_t st) {
+    const int np = B.nsys * R;
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bdcgs_step, dim3(np), dim3(64), 0, st, j, R, dd, ldd, Hf, ldhp, ldc, pend, g, coef, final_step,
+                       B.active);
+    return hipGetLastError();
+}
+
+hipError_t launch_bupdate2(const BatchBlocks &B, int prec, int R, const void *V, long ldv, int ncols, const double *dd,
+                           int ldd, const double *g, int ldc, const double *coef, void *u, const void *w, void *vout,
+                           hipStream_t st) {
+    if (ncols > kBDcgsMaxCols) return hipErrorInvalidValue;
+    switch (prec) {
+        case 0:
+            return bupdate2_t<double>(B, R, (const double *)V, ldv, ncols, dd, ldd, g, ldc, coef, (double *)u,
+                                      (const double *)w, (double *)vout, st);
+        case 1:
+            return bupdate2_t<float>(B, R, (const float *)V, ldv, ncols, dd, ldd, g, ldc, coef, (float *)u,
+                                     (const float *)w, (float *)vout, st);
+        case 2:
+            return bupdate2_t<uint16_t>(B, R, (const uint16_t *)V, ldv, ncols, dd, ldd, g, ldc, coef, (uint16_t *)u,
+                                        (const uint16_t *)w, (uint16_t *)vout, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+int bdcgs_max_cols() { return kBDcgsMaxCols; }
 
 hipError_t launch_bfinish(const BatchBlocks &B, int R, int ncols, const double *h2, int ldh, double *H, long pstride,
                           double *inv, hipStream_t st) {

@@ -124,13 +124,16 @@ def test_small_batch_matches_single_solves(pp, inner, R, fmt):
     assert np.all(np.linalg.norm(R_all, axis=1) <= 1e-8 * np.linalg.norm(bmat, axis=1) * np.sqrt(len(csrs)))
 
 
+@pytest.mark.parametrize("orth", ["delayed", "cgs2"])
 @pytest.mark.parametrize("fmt", ["box", "pattern", "sell"])
 @pytest.mark.parametrize("inner", ["fp64", "fp32"])
 @pytest.mark.parametrize("R", [1, 4])
-def test_small_batch_matches_oracle(pp, inner, R, fmt):
+def test_small_batch_matches_oracle(pp, inner, R, fmt, orth):
     csrs = _systems(SMALL)
-    say("batch small vs oracle", inner, R, fmt)
+    say("batch small vs oracle", inner, R, fmt, orth)
     Bt = pp.Batch(csrs)
+    assert Bt.orth() == "delayed"  # the default: two basis sweeps per step
+    Bt.set_orth(orth)
     Bt.set_format(fmt)
     polys = Bt.setup(dev(_v0(SMALL)), 8)
     brs = _rhs_block(SMALL, R)
@@ -297,17 +300,19 @@ def test_batched_config_full_size(pp):
         "s; speed-up", round(t_loop / t_batch, 2))
 
 
+@pytest.mark.parametrize("orth", ["delayed", "cgs2"])
 @pytest.mark.parametrize("fmt", ["box", "pattern", "sell"])
 @pytest.mark.parametrize("R", [1, 4])
-def test_batched_graph_replays_equal_eager(pp, R, fmt):
+def test_batched_graph_replays_equal_eager(pp, R, fmt, orth):
     # Arnoldi steps captured into HIP graphs and replayed over several cycles
     # (with eager launches, host work and synchronisations between replays)
     # give the eager result bit for bit: x, every pair's counters and the
     # residual history of every cycle
     specs = SMALL
     csrs = _systems(specs)
-    say("batched graphs", R, fmt)
+    say("batched graphs", R, fmt, orth)
     Bt = pp.Batch(csrs)
+    Bt.set_orth(orth)
     Bt.set_format(fmt)
     bd = Bt.interleave(np.concatenate(_rhs_block(specs, R), axis=1))
     polys = Bt.setup(dev(_v0(specs)), 6)
