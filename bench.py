@@ -478,7 +478,7 @@ def paper_context_leg(pp, torch, np):
             "ours": "one MI355X, FP64, CGS2 (dots count both passes)", "rows": rows}
 
 
-def batched_leg(pp, torch, np, loop_every=16, orth="delayed"):
+def batched_leg(pp, torch, np, loop_every=16, orth="delayed", graph_steps=5):
     """Batched solve: 256 2-D convection-diffusion systems (sides U{64..512},
     coefficient U[0,50)), 4 right-hand sides each, degree 20, GMRES(50),
     FP32 inner / FP64 outer, tol 1e-8 (setup + solve), against a loop of
@@ -503,7 +503,7 @@ def batched_leg(pp, torch, np, loop_every=16, orth="delayed"):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     polys = B.setup(v0, 20)
-    x, infos = B.solve(polys, bd, 4, tol=1e-8, m=50, inner="fp32")
+    x, infos = B.solve(polys, bd, 4, tol=1e-8, m=50, inner="fp32", graph_steps=graph_steps)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     ok = all(i["converged"] for i in infos)
@@ -538,7 +538,7 @@ def batched_leg(pp, torch, np, loop_every=16, orth="delayed"):
             "chain_shape": {prec: {"format": t[0], "slices_per_wave": t[1], "xcd_order": t[2], "step_us": round(t[3], 2)}
                             for prec, t in tuned.items()},
             "tune_s": round(t_tune, 6),
-            "cycle": "device Givens per pair; HIP graphs of 5 Arnoldi steps, one host check between them",
+            "cycle": f"device Givens per pair; HIP graphs of {graph_steps} Arnoldi steps, one host check between them",
             "orth": orth,
             "speedup_vs_loop": round(t_loop / t_batch, 3), "speedup_vs_fp64_loop": round(t_loop64 / t_batch, 3)}
 
@@ -616,6 +616,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3, help="oracle runs on the host (median; capped at ~100 s)")
     ap.add_argument("--setup-basis", default="fp32", choices=["fp32", "fp64"],
                     help="Krylov vector storage of the FP32 form's polynomial setup (the FP64 form's is fp64)")
+    ap.add_argument("--batch-graph-steps", type=int, default=5,
+                    help="Arnoldi steps per captured segment of a batched cycle (one host check per segment)")
     ap.add_argument("--batch-orth", default="delayed", choices=["delayed", "cgs2"],
                     help="orthogonalisation of the batched cycles (delayed: two basis sweeps per step)")
     ap.add_argument("--chain-variant", default=None,
@@ -651,7 +653,7 @@ def main():
                 "out_of_mall": out_of_mall_leg}
         fn = legs[args.leg]
         if args.leg == "batched":
-            fn = functools.partial(batched_leg, orth=args.batch_orth)
+            fn = functools.partial(batched_leg, orth=args.batch_orth, graph_steps=args.batch_graph_steps)
         print(json.dumps({args.leg: fn(pp, torch, np)}))
         return
     N, d, m, tol = args.grid, args.degree, args.m, 1e-8
@@ -795,7 +797,7 @@ def main():
         extras["random_sparse"] = random_sparse_leg(pp, torch, np)
         extras["chain_step_256"] = scale_leg(pp, torch, np)
         extras["adjoint"] = adjoint_leg(pp, torch, np)
-        extras["batched"] = batched_leg(pp, torch, np, orth=args.batch_orth)
+        extras["batched"] = batched_leg(pp, torch, np, orth=args.batch_orth, graph_steps=args.batch_graph_steps)
         extras["preconditioned"] = preconditioned_leg(pp, torch, np)
         extras["paper_context"] = paper_context_leg(pp, torch, np)
 
