@@ -126,7 +126,7 @@ def test_small_batch_matches_single_solves(pp, inner, R, fmt):
 
 @pytest.mark.parametrize("orth", ["delayed", "cgs2"])
 @pytest.mark.parametrize("fmt", ["box", "pattern", "sell"])
-@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("R", [1, 4])
 def test_small_batch_matches_oracle(pp, inner, R, fmt, orth):
     csrs = _systems(SMALL)
