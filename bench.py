@@ -727,7 +727,7 @@ def main():
     # p(A)v and phi(A)v bandwidth, FP32 and FP64: the bytes the launches must
     # move by their definition (pp_chain_bytes: format data, vectors,
     # accumulator) over HIP-event time on the stream the library launches on.
-    # The CSR-equivalent rate (SURVEY's CSR bytes per product) is reported
+    # The CSR-equivalent rate (CSR bytes per product: int32 indices and values) is reported
     # beside it, labelled; it is not a fraction of any kernel's traffic.
     poly = res["fp32"]["poly"]
     pav, phi = {}, {}
