@@ -965,30 +965,77 @@ const float *dia_vals<float>(const DevCSR &A) {
 constexpr int kCsThreads = 1024;
 constexpr int kCsRPT = kCsRows / kCsThreads;
 
+// DB (4-byte sums): two product areas in LDS; while the rows of band g add
+// their slots from one, the gathers of band g+1 fill the other, and the
+// workgroup meets once per band. 8-byte sums keep one area (its products
+// fill the LDS budget): gather, meet, add, meet. Either way the words and
+// values of band g+1 are loaded before band g's slots are added.
 template <typename VT, typename XT>
 __global__ __launch_bounds__(kCsThreads, 8) void k_chain_cs_tiles(const uint32_t *__restrict__ code,
                                                                const VT *__restrict__ val,
                                                                const int32_t *__restrict__ toff,
                                                                const uint16_t *__restrict__ tptr, int nb, int sb, int W,
-                                                               int n, int G, const XT *__restrict__ in,
+                                                               int n, int G, int maxe, const XT *__restrict__ in,
                                                                typename Arith<XT>::T *__restrict__ part, int remap) {
     using AT = typename Arith<XT>::T;
+    constexpr bool DB = sizeof(AT) == 4;
     constexpr int kCsUnroll = sizeof(AT) == 8 ? 4 : 8;  // entries in flight per thread (64 VGPRs)
     extern __shared__ __align__(16) unsigned char cs_lds[];
-    AT *prod = reinterpret_cast<AT *>(cs_lds);
+    AT *prod0 = reinterpret_cast<AT *>(cs_lds);
+    AT *prod1 = DB ? prod0 + maxe : prod0;
     const int nsb = nb / G;
     const int w = remap_tile(blockIdx.x, gridDim.x, remap);
     const int b = w / nsb, k = w - b * nsb;
     const int tid = threadIdx.x;
     const int r0 = b * kCsRows, rows = min(kCsRows, n - r0);
     const uint32_t mask = (1u << sb) - 1u;
-    AT acc[kCsRPT];
+    // first pass of band (k G + g): this thread's words and values
+    auto load = [&](int g, uint32_t (&cd)[kCsUnroll], VT (&v)[kCsUnroll]) {
+        const int t = b * nb + k * G + g;
+        const int e1 = toff[t + 1];
 #pragma unroll
-    for (int q = 0; q < kCsRPT; ++q) acc[q] = AT(0);
-    for (int g = 0; g < G; ++g) {
+        for (int u = 0; u < kCsUnroll; ++u) {
+            const int ee = toff[t] + tid + u * kCsThreads;
+            cd[u] = ee < e1 ? __builtin_nontemporal_load(code + ee) : 0u;
+            v[u] = ee < e1 ? __builtin_nontemporal_load(val + ee) : VT(0);
+        }
+    };
+    // the products of band (k G + g) into dst at their slots, the first
+    // pass from words and values already loaded
+    auto gather = [&](int g, AT *dst, uint32_t (&cd)[kCsUnroll], VT (&v)[kCsUnroll]) {
         const int band = k * G + g, t = b * nb + band;
         const int e0 = toff[t], e1 = toff[t + 1];
         const XT *xb = in + (long)band * W;
+        // an empty tile reads nothing (its band may start past the last column)
+        for (int e = e0 + tid; e < e1;) {
+            AT xv[kCsUnroll];
+#pragma unroll
+            for (int u = 0; u < kCsUnroll; ++u) xv[u] = ldx(xb, (long)(cd[u] >> sb));
+#pragma unroll
+            for (int u = 0; u < kCsUnroll; ++u)
+                if (e + u * kCsThreads < e1) dst[cd[u] & mask] = (AT)v[u] * xv[u];
+            e += kCsThreads * kCsUnroll;
+            if (e >= e1) break;
+#pragma unroll
+            for (int u = 0; u < kCsUnroll; ++u) {
+                const int ee = e + u * kCsThreads;
+                cd[u] = ee < e1 ? __builtin_nontemporal_load(code + ee) : 0u;
+                v[u] = ee < e1 ? __builtin_nontemporal_load(val + ee) : VT(0);
+            }
+        }
+    };
+    AT acc[kCsRPT];
+#pragma unroll
+    for (int q = 0; q < kCsRPT; ++q) acc[q] = AT(0);
+    uint32_t cd[kCsUnroll];
+    VT v[kCsUnroll];
+    load(0, cd, v);
+    if constexpr (DB) {
+        gather(0, prod0, cd, v);
+        __syncthreads();
+    }
+    for (int g = 0; g < G; ++g) {
+        const int t = b * nb + k * G + g;
         // this thread's rows' first and end slots in the tile, two 16-bit
         // values per word, loaded before the gathers so that they arrive with them
         const uint16_t *tp = tptr + (size_t)t * (kCsRows + 1);
@@ -998,29 +1045,22 @@ __global__ __launch_bounds__(kCsThreads, 8) void k_chain_cs_tiles(const uint32_t
             const int rl = tid + q * kCsThreads;
             span[q] = rl < rows ? (uint32_t)tp[rl] | ((uint32_t)tp[rl + 1] << 16) : 0u;
         }
-        for (int e = e0 + tid; e < e1; e += kCsThreads * kCsUnroll) {
-            uint32_t cd[kCsUnroll];
-            VT v[kCsUnroll];
-#pragma unroll
-            for (int u = 0; u < kCsUnroll; ++u) {
-                const int ee = e + u * kCsThreads;
-                cd[u] = ee < e1 ? __builtin_nontemporal_load(code + ee) : 0u;
-                v[u] = ee < e1 ? __builtin_nontemporal_load(val + ee) : VT(0);
-            }
-            AT xv[kCsUnroll];
-#pragma unroll
-            for (int u = 0; u < kCsUnroll; ++u) xv[u] = ldx(xb, (long)(cd[u] >> sb));
-#pragma unroll
-            for (int u = 0; u < kCsUnroll; ++u)
-                if (e + u * kCsThreads < e1) prod[cd[u] & mask] = (AT)v[u] * xv[u];
+        const AT *src = (g & 1) ? prod1 : prod0;
+        if constexpr (!DB) {
+            gather(g, prod0, cd, v);
+            __syncthreads();
         }
-        __syncthreads();
+        // the next band's words travel while this band's slots are added
+        if (g + 1 < G) load(g + 1, cd, v);
 #pragma unroll
         for (int q = 0; q < kCsRPT; ++q) {
             const int p0 = (int)(span[q] & 0xFFFFu), p1 = (int)(span[q] >> 16);
             AT s = acc[q];
-            for (int j = p0; j < p1; ++j) s += prod[j];
+            for (int j = p0; j < p1; ++j) s += src[j];
             acc[q] = s;
+        }
+        if constexpr (DB) {
+            if (g + 1 < G) gather(g + 1, (g & 1) ? prod0 : prod1, cd, v);
         }
         __syncthreads();
     }
@@ -1070,8 +1110,10 @@ template <typename VT, typename XT>
 hipError_t cs_launch(const DevCSR &A, const ChainArgs<VT, XT> &a, int nsb, int remap, hipStream_t st) {
     using AT = typename Arith<XT>::T;
     if (A.cs_nb <= 0 || !A.cs_part || nsb < 1 || nsb > kCsMaxParts || A.cs_nb % nsb != 0) return hipErrorInvalidValue;
-    const size_t lds = (size_t)A.cs_maxe * sizeof(AT);
-    if (lds > (size_t)kCsLdsBytes) return hipErrorInvalidValue;  // the copy is built within this bound
+    // two product areas for 4-byte sums, one for 8-byte: within the bound
+    // the copy is built for (a tile's FP64 products in kCsLdsBytes)
+    const size_t lds = (size_t)A.cs_maxe * sizeof(AT) * (sizeof(AT) == 4 ? 2 : 1);
+    if (lds > (size_t)kCsLdsBytes) return hipErrorInvalidValue;
     static bool attr_set = false;  // one per instantiation; the call is idempotent
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)k_chain_cs_tiles<VT, XT>,
@@ -1082,7 +1124,8 @@ hipError_t cs_launch(const DevCSR &A, const ChainArgs<VT, XT> &a, int nsb, int r
     const int nblk = (A.n + kCsRows - 1) / kCsRows;
     AT *part = (AT *)A.cs_part;
     hipLaunchKernelGGL((k_chain_cs_tiles<VT, XT>), dim3(nblk * nsb), dim3(kCsThreads), lds, st, A.cs_code, cs_vals<VT>(A),
-                       A.cs_toff, A.cs_tptr, A.cs_nb, A.cs_sb, A.cs_W, A.n, A.cs_nb / nsb, a.in, part, remap);
+                       A.cs_toff, A.cs_tptr, A.cs_nb, A.cs_sb, A.cs_W, A.n, A.cs_nb / nsb, A.cs_maxe, a.in, part,
+                       remap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_chain_cs_finish<VT, XT>), dim3((A.n + 255) / 256), dim3(256), 0, st, a, cs_diag<VT>(A), part,
