@@ -970,16 +970,19 @@ constexpr int kCsRPT = kCsRows / kCsThreads;
 // workgroup meets once per band. 8-byte sums keep one area (its products
 // fill the LDS budget): gather, meet, add, meet. Either way the words and
 // values of band g+1 are loaded before band g's slots are added.
-template <typename VT, typename XT>
-__global__ __launch_bounds__(kCsThreads, 8) void k_chain_cs_tiles(const uint32_t *__restrict__ code,
-                                                               const VT *__restrict__ val,
-                                                               const int32_t *__restrict__ toff,
-                                                               const uint16_t *__restrict__ tptr, int nb, int sb, int W,
-                                                               int n, int G, int maxe, const XT *__restrict__ in,
-                                                               typename Arith<XT>::T *__restrict__ part, int remap) {
+//
+// WIDE: one workgroup per CU (up to 128 VGPRs): 8 entries in flight per
+// thread with 8-byte sums too, and the next band's slot ranges loaded with
+// its words.
+template <typename VT, typename XT, bool WIDE>
+__global__ __launch_bounds__(kCsThreads, WIDE ? 4 : 8) void k_chain_cs_tiles(
+    const uint32_t *__restrict__ code, const VT *__restrict__ val, const int32_t *__restrict__ toff,
+    const uint16_t *__restrict__ tptr, int nb, int sb, int W, int n, int G, int maxe, const XT *__restrict__ in,
+    typename Arith<XT>::T *__restrict__ part, int remap) {
     using AT = typename Arith<XT>::T;
     constexpr bool DB = sizeof(AT) == 4;
-    constexpr int kCsUnroll = sizeof(AT) == 8 ? 4 : 8;  // entries in flight per thread (64 VGPRs)
+    // entries in flight per thread (64 VGPRs; 128 when WIDE)
+    constexpr int kCsUnroll = sizeof(AT) == 8 && !WIDE ? 4 : 8;
     extern __shared__ __align__(16) unsigned char cs_lds[];
     AT *prod0 = reinterpret_cast<AT *>(cs_lds);
     AT *prod1 = DB ? prod0 + maxe : prod0;
@@ -1034,24 +1037,33 @@ __global__ __launch_bounds__(kCsThreads, 8) void k_chain_cs_tiles(const uint32_t
         gather(0, prod0, cd, v);
         __syncthreads();
     }
-    for (int g = 0; g < G; ++g) {
-        const int t = b * nb + k * G + g;
-        // this thread's rows' first and end slots in the tile, two 16-bit
-        // values per word, loaded before the gathers so that they arrive with them
-        const uint16_t *tp = tptr + (size_t)t * (kCsRows + 1);
-        uint32_t span[kCsRPT];
+    // this thread's rows' first and end slots in tile (k G + g), two 16-bit
+    // values per word
+    auto load_span = [&](int g, uint32_t (&span)[kCsRPT]) {
+        const uint16_t *tp = tptr + (size_t)(b * nb + k * G + g) * (kCsRows + 1);
 #pragma unroll
         for (int q = 0; q < kCsRPT; ++q) {
             const int rl = tid + q * kCsThreads;
             span[q] = rl < rows ? (uint32_t)tp[rl] | ((uint32_t)tp[rl + 1] << 16) : 0u;
         }
+    };
+    uint32_t span[kCsRPT];
+    if constexpr (WIDE) load_span(0, span);
+    for (int g = 0; g < G; ++g) {
+        // slot ranges: loaded before the gathers so that they arrive with
+        // them (WIDE: one band ahead, with the words)
+        uint32_t span_next[kCsRPT];
+        if constexpr (!WIDE) load_span(g, span);
         const AT *src = (g & 1) ? prod1 : prod0;
         if constexpr (!DB) {
             gather(g, prod0, cd, v);
             __syncthreads();
         }
         // the next band's words travel while this band's slots are added
-        if (g + 1 < G) load(g + 1, cd, v);
+        if (g + 1 < G) {
+            load(g + 1, cd, v);
+            if constexpr (WIDE) load_span(g + 1, span_next);
+        }
 #pragma unroll
         for (int q = 0; q < kCsRPT; ++q) {
             const int p0 = (int)(span[q] & 0xFFFFu), p1 = (int)(span[q] >> 16);
@@ -1063,6 +1075,10 @@ __global__ __launch_bounds__(kCsThreads, 8) void k_chain_cs_tiles(const uint32_t
             if (g + 1 < G) gather(g + 1, (g & 1) ? prod0 : prod1, cd, v);
         }
         __syncthreads();
+        if constexpr (WIDE) {
+#pragma unroll
+            for (int q = 0; q < kCsRPT; ++q) span[q] = span_next[q];
+        }
     }
     AT *pk = part + (size_t)k * n + r0;
 #pragma unroll
@@ -1105,7 +1121,27 @@ const float *cs_diag<float>(const DevCSR &A) {
     return A.cs_dg32;
 }
 
-// Both launches of one column-sorted product with `nsb` partial sums per row.
+// The tile launch of one column-sorted product (lds: its dynamic LDS bytes).
+template <typename VT, typename XT, bool WIDE>
+hipError_t cs_tiles_launch(const DevCSR &A, const ChainArgs<VT, XT> &a, int nsb, size_t lds, int remap,
+                           hipStream_t st) {
+    using AT = typename Arith<XT>::T;
+    static bool attr_set = false;  // one per instantiation; the call is idempotent
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_chain_cs_tiles<VT, XT, WIDE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kCsLdsBytes);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int nblk = (A.n + kCsRows - 1) / kCsRows;
+    hipLaunchKernelGGL((k_chain_cs_tiles<VT, XT, WIDE>), dim3(nblk * nsb), dim3(kCsThreads), lds, st, A.cs_code,
+                       cs_vals<VT>(A), A.cs_toff, A.cs_tptr, A.cs_nb, A.cs_sb, A.cs_W, A.n, A.cs_nb / nsb, A.cs_maxe,
+                       a.in, (AT *)A.cs_part, remap);
+    return hipGetLastError();
+}
+
+// Both launches of one column-sorted product with `nsb` partial sums per
+// row; two partial sums (half the workgroups) take the WIDE tile kernel.
 template <typename VT, typename XT>
 hipError_t cs_launch(const DevCSR &A, const ChainArgs<VT, XT> &a, int nsb, int remap, hipStream_t st) {
     using AT = typename Arith<XT>::T;
@@ -1114,20 +1150,10 @@ hipError_t cs_launch(const DevCSR &A, const ChainArgs<VT, XT> &a, int nsb, int r
     // the copy is built for (a tile's FP64 products in kCsLdsBytes)
     const size_t lds = (size_t)A.cs_maxe * sizeof(AT) * (sizeof(AT) == 4 ? 2 : 1);
     if (lds > (size_t)kCsLdsBytes) return hipErrorInvalidValue;
-    static bool attr_set = false;  // one per instantiation; the call is idempotent
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_chain_cs_tiles<VT, XT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, kCsLdsBytes);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    const int nblk = (A.n + kCsRows - 1) / kCsRows;
-    AT *part = (AT *)A.cs_part;
-    hipLaunchKernelGGL((k_chain_cs_tiles<VT, XT>), dim3(nblk * nsb), dim3(kCsThreads), lds, st, A.cs_code, cs_vals<VT>(A),
-                       A.cs_toff, A.cs_tptr, A.cs_nb, A.cs_sb, A.cs_W, A.n, A.cs_nb / nsb, A.cs_maxe, a.in, part,
-                       remap);
-    hipError_t e = hipGetLastError();
+    hipError_t e = nsb == 2 ? cs_tiles_launch<VT, XT, true>(A, a, nsb, lds, remap, st)
+                            : cs_tiles_launch<VT, XT, false>(A, a, nsb, lds, remap, st);
     if (e != hipSuccess) return e;
+    AT *part = (AT *)A.cs_part;
     hipLaunchKernelGGL((k_chain_cs_finish<VT, XT>), dim3((A.n + 255) / 256), dim3(256), 0, st, a, cs_diag<VT>(A), part,
                        nsb);
     return hipGetLastError();
