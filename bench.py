@@ -99,8 +99,9 @@ def chain_kernel_name(variant):
         return ("k_chain_boxt<float,float,16,4,128,1024> (two chain steps per launch on tiles of 16 x 4 whole "
                 "grid lines, 1024 threads, the input and the first step staged in LDS)")
     if v.startswith("csort"):
-        return (f"k_chain_cs_tiles<float,float> + k_chain_cs_finish ({v}: (8192-row block, column band) tiles "
-                f"whose entries are sorted by column, {v[-1]} partial row sums, then the fused chain update)")
+        wide = "true" if v == "csort2" else "false"
+        return (f"k_chain_cs_tiles<float,float,{wide}> + k_chain_cs_finish ({v}: (8192-row block, column band) "
+                f"tiles whose entries are sorted by column, {v[-1]} partial row sums, then the fused chain update)")
     return f"chain step, variant {v}"
 
 
