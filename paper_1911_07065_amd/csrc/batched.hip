@@ -70,9 +70,9 @@ struct BChainArgs {
     XT *bufs[5];
 };
 
-// Buffers of one chain step for a row. Every load of the row's update goes
-// out unconditionally, before the product's gathers are used: an absent
-// vector is read from `in` again and dropped by a select.
+// Buffers of one chain step for a row. The loads of the row's update go out
+// before the product's gathers are used; an absent vector (a uniform
+// property of the step) is not read and holds zeros.
 template <typename XT>
 struct BRow {
     const XT *in, *aux, *fin, *accr;
@@ -97,11 +97,14 @@ struct BRowIn {
 };
 
 template <typename XT, int R>
-__device__ __forceinline__ void brow_load(const BRow<XT> &p, long i, BRowIn<XT, R> &t) {
+__device__ __forceinline__ void brow_load(const BRow<XT> &p, const PStep &st, long i, BRowIn<XT, R> &t) {
+    using AT = typename Arith<XT>::T;
+#pragma unroll
+    for (int r = 0; r < R; ++r) t.aux[r] = t.acc[r] = t.fin[r] = AT(0);
     ldr<XT, R>(p.in, i, t.xin);
-    ldr<XT, R>(p.aux, i, t.aux);
-    ldr<XT, R>(p.accr, i, t.acc);
-    ldr<XT, R>(p.fin, i, t.fin);
+    if (st.aux >= 0) ldr<XT, R>(p.aux, i, t.aux);
+    if (st.acc >= 0 && !st.acc_init) ldr<XT, R>(p.accr, i, t.acc);
+    if (st.fin) ldr<XT, R>(p.fin, i, t.fin);
 }
 
 // The chain update of one row after its sparse product s (R right-hand
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(256) void k_bchain(BChainArgs<VT, XT> a, int remap)
     const long rc = (long)si.x + min(lane, si.y - 1);
     const BRow<XT> p = brow_ptrs(a, st);
     BRowIn<XT, R> t;
-    brow_load<XT, R>(p, rc, t);
+    brow_load<XT, R>(p, st, rc, t);
     AT s[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) s[r] = AT(0);
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(256) void k_bchain_pat(BChainArgs<VT, XT> a, const 
     for (int q = 0; q < SPW; ++q) {
         if (skip[q]) continue;
         p[q] = brow_ptrs(a, st[q]);
-        brow_load<XT, R>(p[q], rc[q], t[q]);
+        brow_load<XT, R>(p[q], st[q], rc[q], t[q]);
         if (st[q].spmv) {
 #pragma unroll
             for (int d = 0; d < ND; ++d) ldr<XT, R>(p[q].in, min(max(rc[q] + po[q][d], lo[q]), hi[q]), xv[q][d]);
@@ -331,11 +334,18 @@ __global__ __launch_bounds__(256) void k_bchain_box(BChainArgs<VT, XT> a, const 
     for (int q = 0; q < SPW; ++q) {
         if (skip[q]) continue;
         p[q] = brow_ptrs(a, st[q]);
-        brow_load<XT, R>(p[q], rc[q], t[q]);
+        brow_load<XT, R>(p[q], st[q], rc[q], t[q]);
         if (st[q].spmv) {
             const int off[ND] = {-gx[q], -1, 0, 1, gx[q]};
 #pragma unroll
-            for (int d = 0; d < ND; ++d) ldr<XT, R>(p[q].in, in[q][d] ? rc[q] + off[d] : rc[q], xv[q][d]);
+            for (int d = 0; d < ND; ++d) {
+                if (d == 2) {  // the row's own input, already loaded
+#pragma unroll
+                    for (int r = 0; r < R; ++r) xv[q][d][r] = t[q].xin[r];
+                } else {
+                    ldr<XT, R>(p[q].in, in[q][d] ? rc[q] + off[d] : rc[q], xv[q][d]);
+                }
+            }
         }
     }
 #pragma unroll
