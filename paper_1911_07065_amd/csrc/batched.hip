@@ -286,9 +286,11 @@ __global__ __launch_bounds__(256) void k_bchain_pat(BChainArgs<VT, XT> a, const 
 // (ptab[ptoff[sys] + pint[sys] 5 + d], d over the offsets -gx_s, -1, 0, +1,
 // +gx_s) come through uniform loads, and a neighbour outside the system's
 // grid counts as zero, which is what its truncated row holds. The terms are
-// summed in the pattern-coded kernel's order. Neighbour indices outside the
-// grid are clamped to the row itself and dropped by a select, so every load
-// goes out unconditionally.
+// summed in the pattern-coded kernel's order. The rows above and below are
+// loaded (an index outside the grid is clamped to the row itself and dropped
+// by a select); the neighbours along the line are the adjacent lanes' own
+// inputs (a slice is 64 consecutive rows of one system, cut from its first
+// row, so only a full slice's end lanes need rows of another wave).
 template <typename VT, typename XT, int R, int SPW>
 __global__ __launch_bounds__(256) void k_bchain_box(BChainArgs<VT, XT> a, const int32_t *__restrict__ bgx,
                                                     const int32_t *__restrict__ bpint,
@@ -336,15 +338,24 @@ __global__ __launch_bounds__(256) void k_bchain_box(BChainArgs<VT, XT> a, const 
         p[q] = brow_ptrs(a, st[q]);
         brow_load<XT, R>(p[q], st[q], rc[q], t[q]);
         if (st[q].spmv) {
-            const int off[ND] = {-gx[q], -1, 0, 1, gx[q]};
+            // the rows above and below in the grid; the row's own input and
+            // its neighbours along the line come from this lane's and the
+            // adjacent lanes' input (rows rc - 1 and rc + 1), except at the
+            // wave's two ends, which load theirs
+            ldr<XT, R>(p[q].in, in[q][0] ? rc[q] - gx[q] : rc[q], xv[q][0]);
+            ldr<XT, R>(p[q].in, in[q][4] ? rc[q] + gx[q] : rc[q], xv[q][4]);
+            // the end lanes' loads go out with the others, one instruction
+            // for both
+            AT e[R] = {};
+            const bool lo = lane == 0;
+            if (lo || lane == 63)
+                ldr<XT, R>(p[q].in, lo ? (in[q][1] ? rc[q] - 1 : rc[q]) : (in[q][3] ? rc[q] + 1 : rc[q]), e);
 #pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                if (d == 2) {  // the row's own input, already loaded
-#pragma unroll
-                    for (int r = 0; r < R; ++r) xv[q][d][r] = t[q].xin[r];
-                } else {
-                    ldr<XT, R>(p[q].in, in[q][d] ? rc[q] + off[d] : rc[q], xv[q][d]);
-                }
+            for (int r = 0; r < R; ++r) {
+                xv[q][2][r] = t[q].xin[r];
+                const AT up = __shfl_up(t[q].xin[r], 1), dn = __shfl_down(t[q].xin[r], 1);
+                xv[q][1][r] = lo ? e[r] : up;
+                xv[q][3][r] = lane == 63 ? e[r] : dn;
             }
         }
     }
