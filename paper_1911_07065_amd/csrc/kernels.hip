@@ -15,6 +15,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 
 #include "devutil.h"
 #include "kernels.h"
@@ -972,8 +973,8 @@ constexpr int kCsRPT = kCsRows / kCsThreads;
 // values of band g+1 are loaded before band g's slots are added.
 //
 // WIDE: one workgroup per CU (up to 128 VGPRs): 8 entries in flight per
-// thread with 8-byte sums too, and the next band's slot ranges loaded with
-// its words.
+// thread with 8-byte sums too, slot ranges loaded one band ahead, and
+// (FP64, BF16 storage) words two bands ahead.
 template <typename VT, typename XT, bool WIDE>
 __global__ __launch_bounds__(kCsThreads, WIDE ? 4 : 8) void k_chain_cs_tiles(
     const uint32_t *__restrict__ code, const VT *__restrict__ val, const int32_t *__restrict__ toff,
@@ -983,6 +984,8 @@ __global__ __launch_bounds__(kCsThreads, WIDE ? 4 : 8) void k_chain_cs_tiles(
     constexpr bool DB = sizeof(AT) == 4;
     // entries in flight per thread (64 VGPRs; 128 when WIDE)
     constexpr int kCsUnroll = sizeof(AT) == 8 && !WIDE ? 4 : 8;
+    // words two bands ahead (measured: FP32 storage one band ahead is faster)
+    constexpr bool kAhead2 = WIDE && !std::is_same<XT, float>::value;
     extern __shared__ __align__(16) unsigned char cs_lds[];
     AT *prod0 = reinterpret_cast<AT *>(cs_lds);
     AT *prod1 = DB ? prod0 + maxe : prod0;
@@ -1030,13 +1033,6 @@ __global__ __launch_bounds__(kCsThreads, WIDE ? 4 : 8) void k_chain_cs_tiles(
     AT acc[kCsRPT];
 #pragma unroll
     for (int q = 0; q < kCsRPT; ++q) acc[q] = AT(0);
-    uint32_t cd[kCsUnroll];
-    VT v[kCsUnroll];
-    load(0, cd, v);
-    if constexpr (DB) {
-        gather(0, prod0, cd, v);
-        __syncthreads();
-    }
     // this thread's rows' first and end slots in tile (k G + g), two 16-bit
     // values per word
     auto load_span = [&](int g, uint32_t (&span)[kCsRPT]) {
@@ -1047,23 +1043,8 @@ __global__ __launch_bounds__(kCsThreads, WIDE ? 4 : 8) void k_chain_cs_tiles(
             span[q] = rl < rows ? (uint32_t)tp[rl] | ((uint32_t)tp[rl + 1] << 16) : 0u;
         }
     };
-    uint32_t span[kCsRPT];
-    if constexpr (WIDE) load_span(0, span);
-    for (int g = 0; g < G; ++g) {
-        // slot ranges: loaded before the gathers so that they arrive with
-        // them (WIDE: one band ahead, with the words)
-        uint32_t span_next[kCsRPT];
-        if constexpr (!WIDE) load_span(g, span);
-        const AT *src = (g & 1) ? prod1 : prod0;
-        if constexpr (!DB) {
-            gather(g, prod0, cd, v);
-            __syncthreads();
-        }
-        // the next band's words travel while this band's slots are added
-        if (g + 1 < G) {
-            load(g + 1, cd, v);
-            if constexpr (WIDE) load_span(g + 1, span_next);
-        }
+    // each row adds its slots of one band, in slot order
+    auto add_slots = [&](const uint32_t (&span)[kCsRPT], const AT *src) {
 #pragma unroll
         for (int q = 0; q < kCsRPT; ++q) {
             const int p0 = (int)(span[q] & 0xFFFFu), p1 = (int)(span[q] >> 16);
@@ -1071,13 +1052,90 @@ __global__ __launch_bounds__(kCsThreads, WIDE ? 4 : 8) void k_chain_cs_tiles(
             for (int j = p0; j < p1; ++j) s += src[j];
             acc[q] = s;
         }
+    };
+    using Words = uint32_t[kCsUnroll];
+    using Vals = VT[kCsUnroll];
+    using Span = uint32_t[kCsRPT];
+    if constexpr (kAhead2) {
+        // words two bands ahead, in two register sets that trade roles from
+        // one band to the next (the band loop runs two bands per turn, so
+        // no set is copied while its loads are in flight)
+        Words cA, cB;
+        Vals vA, vB;
+        Span sA, sB;
         if constexpr (DB) {
-            if (g + 1 < G) gather(g + 1, (g & 1) ? prod0 : prod1, cd, v);
+            // turn g: the products of band g are in area g & 1, band g+1's
+            // words in (cx, vx), set (cy, vy) free
+            auto turn = [&](int g, Words &cx, Vals &vx, Words &cy, Vals &vy, const Span &sx, Span &sy) {
+                if (g + 2 < G) load(g + 2, cy, vy);
+                if (g + 1 < G) load_span(g + 1, sy);
+                add_slots(sx, (g & 1) ? prod1 : prod0);
+                if (g + 1 < G) gather(g + 1, (g & 1) ? prod0 : prod1, cx, vx);
+                __syncthreads();
+            };
+            load(0, cA, vA);
+            if (G > 1) load(1, cB, vB);
+            load_span(0, sA);
+            gather(0, prod0, cA, vA);
+            __syncthreads();
+            for (int g = 0; g < G; g += 2) {
+                turn(g, cB, vB, cA, vA, sA, sB);
+                if (g + 1 < G) turn(g + 1, cA, vA, cB, vB, sB, sA);
+            }
+        } else {
+            // turn g: band g's words in (cx, vx), band g+1's in (cy, vy)
+            auto turn = [&](int g, Words &cx, Vals &vx, Words &cy, Vals &vy, const Span &sx, Span &sy) {
+                (void)cy;
+                (void)vy;
+                gather(g, prod0, cx, vx);
+                __syncthreads();
+                if (g + 2 < G) load(g + 2, cx, vx);
+                if (g + 1 < G) load_span(g + 1, sy);
+                add_slots(sx, prod0);
+                __syncthreads();
+            };
+            load(0, cA, vA);
+            if (G > 1) load(1, cB, vB);
+            load_span(0, sA);
+            for (int g = 0; g < G; g += 2) {
+                turn(g, cA, vA, cB, vB, sA, sB);
+                if (g + 1 < G) turn(g + 1, cB, vB, cA, vA, sB, sA);
+            }
         }
-        __syncthreads();
-        if constexpr (WIDE) {
+    } else {
+        Words cd;
+        Vals v;
+        load(0, cd, v);
+        if constexpr (DB) {
+            gather(0, prod0, cd, v);
+            __syncthreads();
+        }
+        Span span;
+        if constexpr (WIDE) load_span(0, span);
+        for (int g = 0; g < G; ++g) {
+            // slot ranges: loaded before the gathers so that they arrive
+            // with them (WIDE: one band ahead, with the words)
+            Span span_next;
+            if constexpr (!WIDE) load_span(g, span);
+            const AT *src = (g & 1) ? prod1 : prod0;
+            if constexpr (!DB) {
+                gather(g, prod0, cd, v);
+                __syncthreads();
+            }
+            // the next band's words travel while this band's slots are added
+            if (g + 1 < G) {
+                load(g + 1, cd, v);
+                if constexpr (WIDE) load_span(g + 1, span_next);
+            }
+            add_slots(span, src);
+            if constexpr (DB) {
+                if (g + 1 < G) gather(g + 1, (g & 1) ? prod0 : prod1, cd, v);
+            }
+            __syncthreads();
+            if constexpr (WIDE) {
 #pragma unroll
-            for (int q = 0; q < kCsRPT; ++q) span[q] = span_next[q];
+                for (int q = 0; q < kCsRPT; ++q) span[q] = span_next[q];
+            }
         }
     }
     AT *pk = part + (size_t)k * n + r0;
