@@ -462,26 +462,6 @@ __global__ __launch_bounds__(256) void k_bdots(const int4 *block, const int *act
 //  update pass: v_j = (u - V a) / rho (column j), and the next pending vector
 //    u' = w / rho - V g - v_j g_j, both from one read of V.
 
-// Sum of a double over the wave, valid in every lane: within each row of 16
-// lanes by DPP moves (a VALU operation each: lane ^ 1, lane ^ 2 through
-// quad permutations, then rotations by 4 and 8 lanes), then across the four
-// rows by two lane exchanges. Fixed order, so repeated sums are identical.
-template <int CTRL>
-__device__ __forceinline__ double dpp_double(double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
-                            __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double wave_sum_rows(double v) {
-    v += dpp_double<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-    v += dpp_double<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-    v += dpp_double<0x124>(v);  // row_ror 4
-    v += dpp_double<0x128>(v);  // row_ror 8
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
-}
-
 // One chunk of KC columns of k_bdots2: the chunk's loads go out together,
 // then per column and rhs the sums against u and w; wave sums land in
 // sm[wave][2 ((c - g0) R + r) + {0, 1}].
@@ -505,8 +485,8 @@ __device__ __forceinline__ void bdots2_chunk(const XT *__restrict__ V, long ldv,
                 au += (double)x[s][kc][r] * uv[s][r];
                 aw += (double)x[s][kc][r] * wv[s][r];
             }
-            au = wave_sum_rows(au);
-            aw = wave_sum_rows(aw);
+            au = wave_sum(au);
+            aw = wave_sum(aw);
             if (lane == 0) {
                 sm[wave][2 * ((c0 - g0 + kc) * R + r)] = au;
                 sm[wave][2 * ((c0 - g0 + kc) * R + r) + 1] = aw;

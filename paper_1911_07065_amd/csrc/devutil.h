@@ -60,6 +60,27 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// A double's sum over the wave, valid in every lane: within each row of 16
+// lanes by DPP moves (a VALU operation per half: lane ^ 1 and lane ^ 2
+// through quad permutations, then rotations by 4 and 8 lanes), then across
+// the four rows by two lane exchanges. Fixed order, so repeated sums are
+// identical.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_double<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_double<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_double<0x124>(v);  // row_ror 4
+    v += dpp_double<0x128>(v);  // row_ror 8
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
 // Deterministic sum over a 256-thread block; result valid in thread 0.
 template <typename T>
 __device__ __forceinline__ T block_sum256(T v, T *sm /* [4] */) {
