@@ -722,8 +722,27 @@ def main():
         t = (time.perf_counter() - t0) / args.steps
         A = csr.to_scipy()
         rel = float(np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b))
-        res[inner] = dict(t=t, info=info, poly=poly, relres=rel, x=x.cpu().numpy())
-        log(inner, f"time-to-solution {t * 1e3:.1f} ms", info, "true relres", rel)
+        # the split of a step, outside the timed region: the setup alone, then
+        # the solve alone, each between synchronisations (medians over the
+        # steps, after one untimed split)
+        t_setup, t_solve = [], []
+        for rep in range(args.steps + 1):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            p_ = pp.setup(M, v0d, d, basis=args.setup_basis if inner == "fp32" else "fp64")
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            pp.solve(p_, M, bd, tol=tol, m=m, inner=inner)
+            torch.cuda.synchronize()
+            if rep:
+                t_setup.append(t2 - t1)
+                t_solve.append(time.perf_counter() - t2)
+        res[inner] = dict(t=t, info=info, poly=poly, relres=rel, x=x.cpu().numpy(),
+                          setup_ms=round(float(np.median(t_setup)) * 1e3, 3),
+                          solve_ms=round(float(np.median(t_solve)) * 1e3, 3))
+        log(inner, f"time-to-solution {t * 1e3:.1f} ms", info, "true relres", rel,
+            f"(split: setup {res[inner]['setup_ms']:.2f} ms, solve {res[inner]['solve_ms']:.2f} ms;",
+            "setup runs", [round(v * 1e3, 2) for v in t_setup], "solve runs", [round(v * 1e3, 2) for v in t_solve], ")")
 
     # p(A)v and phi(A)v bandwidth, FP32 and FP64: the bytes the launches must
     # move by their definition (pp_chain_bytes: format data, vectors,
@@ -836,6 +855,10 @@ def main():
         "fp64_relres": r64["relres"],
         "fp64_iters": r64["info"]["iters"],
         "mixed_speedup_vs_fp64": round(r64["t"] / r32["t"], 3),
+        "split_ms": {"note": "one step split into the setup alone and the solve alone, each between synchronisations, "
+                             "measured after the timed steps (medians)",
+                     "fp32": {"setup": r32["setup_ms"], "solve": r32["solve_ms"]},
+                     "fp64": {"setup": r64["setup_ms"], "solve": r64["solve_ms"]}},
         "pAv_GBps": {"fp32": round(pav["fp32"]["GBps"], 1), "fp64": round(pav["fp64"]["GBps"], 1),
                      "bytes": {"fp32": pav["fp32"]["bytes"], "fp64": pav["fp64"]["bytes"]},
                      "note": "bytes the p(A)v launches must move (pp_chain_bytes) / HIP-event time"},
