@@ -327,3 +327,26 @@ def test_batched_graph_replays_equal_eager(pp, R, fmt, orth):
             assert a["relres"] == b["relres"]
         xe2, _ = Bt.solve(polys, bd, R, tol=1e-11, m=8, inner="fp32", graphs=False)
         assert torch.equal(xe2, xe)
+
+
+@pytest.mark.parametrize("orth", ["delayed", "cgs2"])
+def test_batch_repeats_bit_for_bit(pp, orth):
+    # every reduction (wave sums, block partials, per-system passes) has a
+    # fixed order: the same batch solved twice gives the same roots, x and
+    # counters bit for bit
+    csrs = _systems(SMALL)
+    say("batch repeatability", orth)
+    Bt = pp.Batch(csrs)
+    Bt.set_orth(orth)
+    brs = _rhs_block(SMALL, 4)
+    bd = Bt.interleave(np.concatenate(brs, axis=1))
+    runs = []
+    for _ in range(2):
+        polys = Bt.setup(dev(_v0(SMALL)), 8)
+        x, infos = Bt.solve(polys, bd, 4, tol=1e-8, m=30, inner="fp32")
+        runs.append(([p.roots("final") for p in polys], host(x), infos))
+    (r0, x0, i0), (r1, x1, i1) = runs
+    assert all(np.array_equal(a, b) for a, b in zip(r0, r1))
+    assert np.array_equal(x0, x1)
+    for a, b in zip(i0, i1):
+        assert a["cycles"] == b["cycles"] and a["iters"] == b["iters"] and a["relres"] == b["relres"]

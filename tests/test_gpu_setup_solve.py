@@ -243,6 +243,21 @@ def test_cfg1_solve_matches_oracle(pp, inner):
         assert abs(info["iters"] - io.iters) <= 1
 
 
+@pytest.mark.parametrize("basis", ["fp64", "fp32"])
+def test_setup_repeats_bit_for_bit(pp, basis):
+    # the setup's dot passes reduce in a fixed order (wave sums, workgroup
+    # partials, one device pass): the same input gives the same harmonic
+    # Ritz values and roots bit for bit
+    csr = convdiff3d(24, 10, 10, 10)
+    M = pp.Matrix.from_csr(csr)
+    v0 = dev(start_vector(csr.n, 2))
+    say("setup repeatability", basis)
+    p0 = pp.setup(M, v0, 16, basis=basis)
+    p1 = pp.setup(M, v0, 16, basis=basis)
+    for kind in ("theta", "leja", "final"):
+        assert np.array_equal(p0.roots(kind), p1.roots(kind)), kind
+
+
 @pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16"])
 def test_lookahead_keeps_the_iterates(pp, inner):
     # queueing the next step's phi(A) before the host reads the Hessenberg
