@@ -227,8 +227,8 @@ def _csort_cases():
 
 @pytest.mark.parametrize("name", list(_csort_cases()))
 def test_column_sorted_tiles_match_oracle(pp, name):
-    # both column-sorted variants, with and without the XCD order, FP64 and
-    # FP32, p and phi chains, element-wise against the oracle
+    # both column-sorted variants, with and without the XCD order, FP64,
+    # FP32 and BF16 storage, p and phi chains, element-wise against the oracle
     csr, d = _csort_cases()[name]
     A = csr.to_scipy()
     A32 = A.astype(np.float32)
@@ -244,10 +244,16 @@ def test_column_sorted_tiles_match_oracle(pp, name):
             say("column-sorted", name, pp.chain_variant_name(variant), remap)
             M.set_variant("fp64", variant, remap)
             M.set_variant("fp32", variant, remap)
+            M.set_variant("bf16", variant, remap)
             assert_close(host(pp.apply(poly, M, dev(v), "p")), ref_p, 1e-12, f"{name} p")
             assert_close(host(pp.apply(poly, M, dev(v), "phi")), ref_phi, 1e-12, f"{name} phi")
             got32 = host(pp.apply(poly, M, dev(v, torch.float32), "p"))
             assert maxerr(got32, ref_p) <= 10 * delta + 1e-6
+            # BF16 storage (the words of two bands ahead in the two-sum kernel)
+            vb = dev(v, torch.bfloat16)
+            gotb = host(pp.apply(poly, M, vb, "p"))
+            deltab = maxerr(apply_p_low(A32, P.units, host(vb), "bf16"), ref_p)
+            assert maxerr(gotb, ref_p) <= 10 * deltab + 1e-6
     # each row's sum has a fixed order: repeated products are identical
     a = pp.apply(poly, M, dev(v, torch.float32), "phi").clone()
     b = pp.apply(poly, M, dev(v, torch.float32), "phi").clone()
