@@ -281,6 +281,12 @@ def test_column_sorted_tiles_full_size(pp):
             say("column-sorted full size", pp.chain_variant_name(variant), prec)
             M.set_variant(prec, variant, 1)
             assert_close(host(pp.apply(poly, M, dev(v, dt), "p")), ref, tol, f"full size {variant} {prec}")
+        # BF16 storage against the emulated BF16 chain's distance from the oracle
+        say("column-sorted full size", pp.chain_variant_name(variant), "bf16")
+        M.set_variant("bf16", variant, 1)
+        vb = dev(v, torch.bfloat16)
+        deltab = maxerr(apply_p_low(A.astype(np.float32), P.units, host(vb), "bf16"), ref)
+        assert maxerr(host(pp.apply(poly, M, vb, "p")), ref) <= 10 * deltab + 1e-6
         # per product, against CSR (8 bytes per entry, 4 (n + 1) row
         # pointers): the n diagonal entries leave the tiles (8 bytes each)
         # and come back as a 4-byte diagonal; 16 bands of 123 blocks add
